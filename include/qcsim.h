@@ -1,0 +1,187 @@
+/*
+ * qcsim -- single output amplitudes <x|C|0^n> of random 2D-lattice circuits
+ * by sliced tensor-network contraction on one MI355X (gfx950).
+ *
+ * The method (the paper, Sections "Benchmarking and the Experimental Setup"
+ * and "Benchmarking Results"): the circuit is a tensor network whose nodes
+ * hold tensors and whose hyper-edges are running indices; a preprocessing
+ * step splits the contraction of one amplitude into N_s subtasks of equal
+ * cost that share no data, and the subtask results add up to the amplitude.
+ * Here the subtasks are *slices*: k binary indices (wire segments) are fixed
+ * to the bits of a slice id s in [0, 2^k), every slice is contracted along
+ * the same pairwise order, and the amplitude is the FP64 sum over slices.
+ *
+ * Conventions
+ *   - Qubit q of a bitstring x is the byte x[q] in {0, 1}; batches of
+ *     bitstrings are row-major uint8 [n_bs][n_qubits].
+ *   - Gate matrices are indexed U[out][in]; H = (1/sqrt2)[[1,1],[1,-1]],
+ *     sqrt X = 1/2[[1+i,1-i],[1-i,1+i]], sqrt Y = 1/2[[1+i,-1-i],[1+i,1+i]],
+ *     T = diag(1, e^{i pi/4}), CZ = diag(1,1,1,-1) (qc_gate_matrix exports them).
+ *   - A segment (q, o) is the piece of qubit q's wire after its o-th
+ *     non-diagonal gate (H, sqrt X, sqrt Y); o = 0 is the input piece (fixed
+ *     to 0) and the last one is the output piece (fixed to x[q]); neither can
+ *     be sliced.  Slice s gives the j-th sliced segment the bit (s >> j) & 1.
+ *
+ * Errors: every call returns a qc_status; on error the outputs are left
+ * untouched, nothing of the failed call stays enqueued on the stream, and
+ * qc_last_error() (per thread) holds a message.  The library never aborts.
+ *
+ * Threads: a plan is immutable after qc_plan_build except for its caches
+ * (lowered programs and device constants), which are guarded by a mutex.
+ * Concurrent qc_contract_slices calls need separate workspaces.
+ */
+#ifndef QCSIM_H
+#define QCSIM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    QC_OK = 0,
+    QC_ERR_INVALID_ARG = 1,  /* a pointer, size or value is invalid */
+    QC_ERR_RANGE = 2,        /* a slice range or batch is out of bounds */
+    QC_ERR_NOMEM = 3,        /* host or device allocation failed, or ws too small */
+    QC_ERR_DEVICE = 4,       /* a HIP call failed (message in qc_last_error) */
+    QC_ERR_UNSUPPORTED = 5,  /* valid request this build does not handle */
+    QC_ERR_INFEASIBLE = 6    /* the slice count and the size cap cannot both be met */
+} qc_status;
+
+enum {
+    QC_GATE_H = 0,
+    QC_GATE_SQRT_X = 1,
+    QC_GATE_SQRT_Y = 2,
+    QC_GATE_T = 3,
+    QC_GATE_CZ = 4
+};
+
+/* One gate; gates are given in application order.  q1 = -1 for one-qubit
+ * gates.  moment is informational (not used for ordering). */
+typedef struct {
+    int32_t kind;
+    int32_t q0;
+    int32_t q1;
+    int32_t moment;
+} qc_gate;
+
+typedef struct {
+    int32_t n_qubits;        /* 1 .. 4096 */
+    int32_t n_gates;
+    const qc_gate *gates;    /* host pointer, n_gates entries; copied by qc_plan_build */
+} qc_circuit;
+
+/* Arithmetic of the contraction steps.  QC_C64: complex FP32 (interleaved
+ * complex64 tensors, FP32 MFMA).  The split forms store each real operand as
+ * a hi + lo pair of BF16 or FP16 values after a per-tensor power-of-two scale
+ * and accumulate hi*hi + hi*lo + lo*hi in FP32 on MFMA. */
+typedef enum {
+    QC_C64 = 0,
+    QC_SPLIT_BF16 = 1,
+    QC_SPLIT_FP16 = 2
+} qc_precision;
+
+/* How to slice.  The planner picks k segments (in slice-bit order) so that the
+ * largest intermediate of one (slice, bitstring) contraction has at most
+ * 2^log2_max_entries entries and k >= log2_slices. */
+typedef struct {
+    int32_t log2_slices;             /* k wanted; -1 = the smallest k that meets the cap */
+    double log2_max_entries;         /* cap on the largest intermediate; <= 0 = no cap */
+    int32_t n_explicit;              /* number of caller-chosen sliced segments (taken first) */
+    const int32_t *explicit_segments;/* n_explicit (q, ordinal) pairs, host pointer, or NULL */
+    uint64_t seed;                   /* seed of the randomised greedy restarts */
+    int32_t greedy_trials;           /* restarts of the order search (>= 1) */
+} qc_slice_spec;
+
+typedef struct qc_plan qc_plan;
+
+typedef struct {
+    int32_t n_qubits;
+    int32_t log2_slices;        /* k */
+    int32_t n_indices;          /* summed binary indices of the simplified network */
+    int32_t n_leaves;           /* tensors after simplification */
+    int32_t n_steps;            /* pairwise contraction steps (n_leaves - 1) */
+    double log2_max_entries;    /* largest intermediate, one slice and one bitstring */
+    double flops_per_slice;     /* algorithmic real flops, one slice, one bitstring (8 per complex MAC) */
+    double bytes_per_slice;     /* algorithmic bytes, complex64 operands read/written once */
+    double flops_unsliced;      /* same order, no slicing */
+    double peak_live_bytes;     /* peak live complex64 bytes, one slice, one bitstring */
+    double plan_seconds;        /* host time spent in qc_plan_build */
+} qc_plan_info_t;
+
+/* circuit + bitstring + slice set -> contraction plan (host only).
+ *   bitstring: optional default bitstring (n_qubits bytes) or NULL.
+ *   spec: slicing request (NULL = no slicing, one greedy trial).
+ * Builds the hypergraph network (diagonal gates share the wire's index),
+ * simplifies it, searches a greedy pairwise order with randomised restarts,
+ * picks the sliced segments and returns an opaque plan owned by the caller
+ * (free with qc_plan_destroy).  QC_ERR_INFEASIBLE if the cap cannot be met
+ * with the requested k (the message states the achievable size). */
+qc_status qc_plan_build(const qc_circuit *circuit, const uint8_t *bitstring,
+                        const qc_slice_spec *spec, qc_plan **out);
+
+qc_status qc_plan_info(const qc_plan *plan, qc_plan_info_t *info);
+
+/* The k sliced segments as (q, ordinal) pairs in slice-bit order: out_pairs
+ * must hold 2k int32. */
+qc_status qc_plan_sliced_segments(const qc_plan *plan, int32_t *out_pairs);
+
+/* Bit values of slice s: out[j] = (s >> j) & 1 for j < k; QC_ERR_RANGE if
+ * s >= 2^k. */
+qc_status qc_plan_slice_assignment(const qc_plan *plan, uint64_t s, uint8_t *out);
+
+/* JSON description of the program lowered for 2^log2_batch_slices slices and
+ * 2^log2_batch_bs bitstrings in flight: leaves (indices, base values),
+ * steps (operands, index classes, layouts, GEMM shapes, transposes) and
+ * per-step algorithmic flops/bytes.  Writes at most cap bytes to buf (NUL
+ * terminated when it fits) and the full length to *len. */
+qc_status qc_plan_describe(qc_plan *plan, int32_t log2_batch_slices, int32_t log2_batch_bs,
+                           qc_precision prec, char *buf, size_t cap, size_t *len);
+
+/* Device workspace (bytes) that qc_contract_slices needs to keep
+ * chunk_slices slices (rounded up to a power of two) and n_bs bitstrings in
+ * flight.  0 on invalid arguments. */
+size_t qc_workspace_bytes(qc_plan *plan, int64_t chunk_slices, int32_t n_bs, qc_precision prec);
+
+/* plan + slice range -> partial amplitudes, asynchronously on `stream`
+ * (a hipStream_t, or NULL for the null stream) of the current device.
+ *   bitstrings: host uint8 [n_bs][n_qubits], 1 <= n_bs <= 65536; copied.
+ *   ws, ws_bytes: device workspace owned by the caller; the largest
+ *     power-of-two number of slices in flight that fits is used (at least
+ *     one slice must fit, else QC_ERR_NOMEM).
+ *   out_dev: device double [n_bs][2] (re, im); the sum over s in
+ *     [s_begin, s_end) of each slice value is ADDED to it, so consecutive
+ *     ranges compose.  Slices are summed in increasing s within fixed-size
+ *     chunks, in FP64, so the result is bitwise reproducible for the same
+ *     range and workspace size.
+ *   per_slice_dev: optional device double [s_end - s_begin][n_bs][2]
+ *     receiving each slice's value, or NULL.
+ * The call returns once the work is enqueued; synchronise the stream before
+ * reading out_dev. */
+qc_status qc_contract_slices(qc_plan *plan, uint64_t s_begin, uint64_t s_end,
+                             const uint8_t *bitstrings, int32_t n_bs, qc_precision prec,
+                             void *ws, size_t ws_bytes, void *stream,
+                             double *out_dev, double *per_slice_dev);
+
+/* All slices of one amplitude, synchronously; allocates and frees its own
+ * workspace on the current device.  out_host[0..1] = (re, im). */
+qc_status qc_amplitude(qc_plan *plan, const uint8_t *bitstring, qc_precision prec,
+                       double out_host[2]);
+
+/* The library's gate matrix as row-major (re, im) pairs: 2x2 (8 doubles)
+ * for one-qubit kinds, 4x4 (32 doubles) for CZ; out must hold 32 doubles. */
+qc_status qc_gate_matrix(int32_t kind, double *out);
+
+/* Frees the plan and its device constants (NULL-safe). */
+void qc_plan_destroy(qc_plan *plan);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *qc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QCSIM_H */

@@ -1,0 +1,129 @@
+// C ABI: plan construction and inspection (host only).  The device entry
+// points (qc_workspace_bytes, qc_contract_slices, qc_amplitude) live in
+// runtime.hip.
+#include <chrono>
+#include <cstring>
+#include <new>
+
+#include "plan.h"
+
+namespace qc {
+bool search_plan(qc_plan *plan, const qc_slice_spec *spec, std::string &err);
+
+static thread_local std::string g_last_error;
+void set_error(const std::string &msg) { g_last_error = msg; }
+}  // namespace qc
+
+using qc::set_error;
+
+extern "C" const char *qc_last_error(void) { return qc::g_last_error.c_str(); }
+
+extern "C" qc_status qc_plan_build(const qc_circuit *circuit, const uint8_t *bitstring,
+                                   const qc_slice_spec *spec, qc_plan **out) {
+    if (!circuit || !out) { set_error("qc_plan_build: NULL argument"); return QC_ERR_INVALID_ARG; }
+    if (circuit->n_qubits < 1 || circuit->n_qubits > 4096 || circuit->n_gates < 0 ||
+        (circuit->n_gates > 0 && !circuit->gates)) {
+        set_error("qc_plan_build: invalid circuit");
+        return QC_ERR_INVALID_ARG;
+    }
+    if (spec && (spec->log2_slices < -1 || spec->log2_slices > 62 || spec->n_explicit < 0 ||
+                 (spec->n_explicit > 0 && !spec->explicit_segments) || spec->greedy_trials < 0)) {
+        set_error("qc_plan_build: invalid slice spec");
+        return QC_ERR_INVALID_ARG;
+    }
+    if (bitstring)
+        for (int q = 0; q < circuit->n_qubits; ++q)
+            if (bitstring[q] > 1) { set_error("qc_plan_build: bitstring entries must be 0 or 1"); return QC_ERR_INVALID_ARG; }
+    const auto t0 = std::chrono::steady_clock::now();
+    qc_plan *plan = new (std::nothrow) qc_plan();
+    if (!plan) { set_error("qc_plan_build: out of host memory"); return QC_ERR_NOMEM; }
+    std::string err;
+    try {
+        if (!qc::build_network(*circuit, plan->net, err)) {
+            delete plan;
+            set_error("qc_plan_build: " + err);
+            return QC_ERR_INVALID_ARG;
+        }
+        std::vector<int> keep;
+        if (spec)
+            for (int i = 0; i < spec->n_explicit; ++i) {
+                const int e = plan->net.find_segment(spec->explicit_segments[2 * i], spec->explicit_segments[2 * i + 1]);
+                if (e >= 0) keep.push_back(e);
+            }
+        qc::simplify_network(plan->net, keep);
+        plan->prob.n_index = plan->net.n_index();
+        for (const auto &T : plan->net.leaves) {
+            std::vector<int> s;
+            for (int e : T.idx)
+                if (plan->net.out_qubit[e] < 0) s.push_back(e);
+            plan->prob.leaf_idx.push_back(s);
+        }
+        if (!qc::search_plan(plan, spec, err)) {
+            delete plan;
+            set_error("qc_plan_build: " + err);
+            return QC_ERR_INFEASIBLE;
+        }
+    } catch (const std::bad_alloc &) {
+        delete plan;
+        set_error("qc_plan_build: out of host memory");
+        return QC_ERR_NOMEM;
+    }
+    if (bitstring) plan->default_bitstring.assign(bitstring, bitstring + circuit->n_qubits);
+    int n_sum = 0;
+    for (int e = 0; e < plan->net.n_index(); ++e) {
+        bool used = false;
+        for (const auto &li : plan->prob.leaf_idx)
+            for (int f : li) used |= f == e;
+        n_sum += used;
+    }
+    plan->info.n_qubits = circuit->n_qubits;
+    plan->info.n_indices = n_sum;
+    plan->info.n_leaves = (int)plan->net.leaves.size();
+    plan->info.n_steps = (int)plan->tree.size();
+    plan->info.plan_seconds =
+        std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    *out = plan;
+    return QC_OK;
+}
+
+extern "C" qc_status qc_plan_info(const qc_plan *plan, qc_plan_info_t *info) {
+    if (!plan || !info) { set_error("qc_plan_info: NULL argument"); return QC_ERR_INVALID_ARG; }
+    *info = plan->info;
+    return QC_OK;
+}
+
+extern "C" qc_status qc_plan_sliced_segments(const qc_plan *plan, int32_t *out_pairs) {
+    if (!plan || (!out_pairs && !plan->sliced.empty())) { set_error("qc_plan_sliced_segments: NULL argument"); return QC_ERR_INVALID_ARG; }
+    for (size_t j = 0; j < plan->sliced.size(); ++j) {
+        out_pairs[2 * j] = plan->net.seg_q[plan->sliced[j]];
+        out_pairs[2 * j + 1] = plan->net.seg_ord[plan->sliced[j]];
+    }
+    return QC_OK;
+}
+
+extern "C" qc_status qc_plan_slice_assignment(const qc_plan *plan, uint64_t s, uint8_t *out) {
+    if (!plan || (!out && !plan->sliced.empty())) { set_error("qc_plan_slice_assignment: NULL argument"); return QC_ERR_INVALID_ARG; }
+    const int k = (int)plan->sliced.size();
+    if (k < 64 && s >= (uint64_t(1) << k)) { set_error("qc_plan_slice_assignment: slice id out of range"); return QC_ERR_RANGE; }
+    for (int j = 0; j < k; ++j) out[j] = (uint8_t)((s >> j) & 1);
+    return QC_OK;
+}
+
+extern "C" qc_status qc_plan_describe(qc_plan *plan, int32_t log2_batch_slices, int32_t log2_batch_bs,
+                                      qc_precision prec, char *buf, size_t cap, size_t *len) {
+    if (!plan || !len) { set_error("qc_plan_describe: NULL argument"); return QC_ERR_INVALID_ARG; }
+    if (prec != QC_C64 && prec != QC_SPLIT_BF16 && prec != QC_SPLIT_FP16) { set_error("qc_plan_describe: bad precision"); return QC_ERR_INVALID_ARG; }
+    std::string err;
+    qc::Program *prog = qc::get_program(plan, log2_batch_slices, log2_batch_bs, err);
+    if (!prog) { set_error("qc_plan_describe: " + err); return QC_ERR_RANGE; }
+    const std::string s = qc::describe_program(plan, *prog);
+    *len = s.size();
+    if (buf && cap > 0) {
+        const size_t n = std::min(cap - 1, s.size());
+        std::memcpy(buf, s.data(), n);
+        buf[n] = 0;
+    }
+    return QC_OK;
+}
+
+extern "C" void qc_plan_destroy(qc_plan *plan);

@@ -1,0 +1,332 @@
+// Lowering of a contraction tree to a device program for 2^b slices and 2^m
+// bitstrings in flight.
+//
+// In-flight slice bits are the first b sliced segments left open (never
+// summed); bitstring bits are extra open indices carried by every leaf that
+// touches an output segment.  Both then behave like hyper-edges: in a step
+// where both operands hold them they are batch indices, otherwise free
+// indices.  Each step C = A (x) B is classified per index as batch (in both,
+// still needed later), contracted (in both, needed nowhere else), free-A or
+// free-B, and run as a batched GEMM C[b][m][n] = sum_k A[b][m][k] B[b][k][n]
+// after at most one bit-permuting transpose per operand.
+#include <algorithm>
+#include <climits>
+#include <cstring>
+#include <sstream>
+
+#include "plan.h"
+
+namespace qc {
+
+namespace {
+
+enum Cls { CB = 0, CM = 1, CN = 2, CK = 3 };
+
+// True if `layout` is [first-class run][x run][y run] with x, y the two other
+// classes of this operand, each run contiguous (runs may be empty).
+bool groupable(const std::vector<int> &layout, const std::vector<int> &cls, int other_a, int other_b,
+               bool &a_first) {
+    // Sequence of classes with runs collapsed.
+    std::vector<int> runs;
+    for (size_t i = 0; i < layout.size(); ++i)
+        if (runs.empty() || runs.back() != cls[i]) runs.push_back(cls[i]);
+    std::vector<int> seen;
+    for (int r : runs) {
+        if (std::count(seen.begin(), seen.end(), r)) return false;
+        seen.push_back(r);
+    }
+    // Batch must come first if present.
+    size_t pos = 0;
+    if (!runs.empty() && runs[0] == CB) pos = 1;
+    for (size_t i = pos; i < runs.size(); ++i)
+        if (runs[i] == CB) return false;
+    a_first = true;
+    for (size_t i = pos; i < runs.size(); ++i) {
+        if (runs[i] == other_a) { a_first = true; break; }
+        if (runs[i] == other_b) { a_first = false; break; }
+    }
+    return true;
+}
+
+std::vector<int> of_class(const std::vector<int> &layout, const std::vector<int> &cls, int c) {
+    std::vector<int> out;
+    for (size_t i = 0; i < layout.size(); ++i)
+        if (cls[i] == c) out.push_back(layout[i]);
+    return out;
+}
+
+std::vector<int> cat(std::initializer_list<std::vector<int>> parts) {
+    std::vector<int> out;
+    for (auto &p : parts) out.insert(out.end(), p.begin(), p.end());
+    return out;
+}
+
+// Best-fit offset allocator over a growing arena (units: complex64 elements).
+struct Arena {
+    std::vector<std::pair<int64_t, int64_t>> free_;  // (offset, size), sorted by offset
+    int64_t end = 0;
+    static int64_t align(int64_t v) { return (v + 31) & ~int64_t(31); }
+    int64_t alloc(int64_t n) {
+        n = align(std::max<int64_t>(n, 1));
+        int best = -1;
+        for (size_t i = 0; i < free_.size(); ++i)
+            if (free_[i].second >= n && (best < 0 || free_[i].second < free_[best].second)) best = (int)i;
+        if (best >= 0) {
+            const int64_t off = free_[best].first;
+            free_[best].first += n;
+            free_[best].second -= n;
+            if (free_[best].second == 0) free_.erase(free_.begin() + best);
+            return off;
+        }
+        // Extend, absorbing a free block that touches the end.
+        if (!free_.empty() && free_.back().first + free_.back().second == end) {
+            const int64_t off = free_.back().first;
+            free_.pop_back();
+            end = off + n;
+            return off;
+        }
+        const int64_t off = end;
+        end += n;
+        return off;
+    }
+    void release(int64_t off, int64_t n) {
+        n = align(std::max<int64_t>(n, 1));
+        free_.push_back({off, n});
+        std::sort(free_.begin(), free_.end());
+        std::vector<std::pair<int64_t, int64_t>> merged;
+        for (auto &f : free_) {
+            if (!merged.empty() && merged.back().first + merged.back().second == f.first) merged.back().second += f.second;
+            else merged.push_back(f);
+        }
+        free_ = std::move(merged);
+    }
+};
+
+}  // namespace
+
+static bool lower(const qc_plan *plan, int b, int m, Program &prog, std::string &err) {
+    const Network &net = plan->net;
+    const int n_idx = net.n_index();
+    const int L = (int)net.leaves.size();
+    prog.b = b;
+    prog.m = m;
+    const int k = (int)plan->sliced.size();
+    if (b < 0 || b > k) { err = "in-flight slice bits out of range"; return false; }
+    if (m < 0 || m > kMaxBsBits) { err = "in-flight bitstring bits out of range"; return false; }
+    std::vector<char> fixed(n_idx, 0), open(n_idx, 0);
+    for (int j = 0; j < k; ++j) (j < b ? open : fixed)[plan->sliced[j]] = 1;
+
+    std::vector<int> bs_bits;  // major -> minor
+    for (int i = m - 1; i >= 0; --i) bs_bits.push_back(kBsBase + i);
+
+    // Leaf layouts: [bitstring bits][summed indices in base order].
+    std::vector<std::vector<int>> layout;   // per program tensor
+    std::vector<int> total(n_idx, 0);
+    for (int t = 0; t < L; ++t) {
+        const Tensor &T = net.leaves[t];
+        bool has_out = false;
+        std::vector<int> lay;
+        for (int e : T.idx) {
+            if (net.out_qubit[e] >= 0) has_out = true;
+            else if (!fixed[e]) { lay.push_back(e); ++total[e]; }
+        }
+        if (has_out) lay.insert(lay.begin(), bs_bits.begin(), bs_bits.end());
+        if ((int)lay.size() > kMaxRank) { err = "leaf rank exceeds the device limit"; return false; }
+        layout.push_back(lay);
+        prog.leaves.push_back(LeafOp{t, t});
+    }
+    auto is_open = [&](int e) { return e >= kBsBase || open[e]; };
+    // Per tensor: how many of each index's leaves it covers.
+    std::vector<std::vector<std::pair<int, int>>> counts(L);
+    for (int t = 0; t < L; ++t)
+        for (int e : layout[t])
+            if (e < kBsBase) counts[t].push_back({e, 1});
+    for (auto &c : counts) std::sort(c.begin(), c.end());
+
+    std::vector<int> tensor_of(L);  // tree node id -> program tensor id
+    for (int t = 0; t < L; ++t) tensor_of[t] = t;
+    auto new_tensor = [&](std::vector<int> lay) {
+        layout.push_back(std::move(lay));
+        return (int)layout.size() - 1;
+    };
+    auto emit_transpose = [&](int src, std::vector<int> dst_layout) {
+        const int dst = new_tensor(std::move(dst_layout));
+        prog.transposes.push_back(TransposeOp{src, dst});
+        prog.ops.push_back(Op{Op::TRANSPOSE, (int)prog.transposes.size() - 1});
+        prog.transpose_bytes += 16.0 * std::ldexp(1.0, (int)layout[src].size());
+        return dst;
+    };
+
+    for (size_t s = 0; s < plan->tree.size(); ++s) {
+        const int ta = tensor_of[plan->tree[s].a], tb = tensor_of[plan->tree[s].b];
+        const std::vector<int> LA = layout[ta], LB = layout[tb];
+        // Merge counts.
+        const auto &ca = counts[plan->tree[s].a], &cb = counts[plan->tree[s].b];
+        std::vector<std::pair<int, int>> cc;
+        {
+            size_t x = 0, y = 0;
+            while (x < ca.size() || y < cb.size()) {
+                if (y == cb.size() || (x < ca.size() && ca[x].first < cb[y].first)) cc.push_back(ca[x++]);
+                else if (x == ca.size() || cb[y].first < ca[x].first) cc.push_back(cb[y++]);
+                else { cc.push_back({ca[x].first, ca[x].second + cb[y].second}); ++x; ++y; }
+            }
+        }
+        auto count_of = [&](int e) {
+            auto it = std::lower_bound(cc.begin(), cc.end(), std::make_pair(e, INT_MIN));
+            return (it != cc.end() && it->first == e) ? it->second : 0;
+        };
+        auto in = [](const std::vector<int> &v, int e) { return std::find(v.begin(), v.end(), e) != v.end(); };
+        std::vector<int> clsA(LA.size()), clsB(LB.size());
+        for (size_t i = 0; i < LA.size(); ++i) {
+            const int e = LA[i];
+            if (in(LB, e)) clsA[i] = (!is_open(e) && count_of(e) == total[e]) ? CK : CB;
+            else clsA[i] = CM;
+        }
+        for (size_t i = 0; i < LB.size(); ++i) {
+            const int e = LB[i];
+            if (in(LA, e)) clsB[i] = (!is_open(e) && count_of(e) == total[e]) ? CK : CB;
+            else clsB[i] = CN;
+        }
+        bool a_mfirst = true, b_kfirst = true;
+        const bool a_ok = groupable(LA, clsA, CM, CK, a_mfirst);
+        const bool b_ok = groupable(LB, clsB, CK, CN, b_kfirst);
+        std::vector<int> Ab = of_class(LA, clsA, CB), Am = of_class(LA, clsA, CM), Ak = of_class(LA, clsA, CK);
+        std::vector<int> Bb = of_class(LB, clsB, CB), Bk = of_class(LB, clsB, CK), Bn = of_class(LB, clsB, CN);
+        int opA = ta, opB = tb;
+        bool a_km = !a_mfirst, b_nk = !b_kfirst;
+        const int64_t szA = int64_t(1) << LA.size(), szB = int64_t(1) << LB.size();
+        if (a_ok && b_ok && Ab == Bb && Ak == Bk) {
+            // no transposes
+        } else if (a_ok && (!b_ok || szA >= szB)) {
+            opB = emit_transpose(tb, cat({Ab, Ak, Bn}));
+            Bb = Ab; Bk = Ak; b_nk = false;
+        } else if (b_ok) {
+            opA = emit_transpose(ta, cat({Bb, Am, Bk}));
+            Ab = Bb; Ak = Bk; a_km = false;
+        } else {
+            opA = emit_transpose(ta, cat({Ab, Am, Ak}));
+            opB = emit_transpose(tb, cat({Ab, Ak, Bn}));
+            Bb = Ab; Bk = Ak; a_km = false; b_nk = false;
+        }
+        const int tc = new_tensor(cat({Ab, Am, Bn}));
+        GemmOp g;
+        g.a = opA; g.b = opB; g.c = tc;
+        g.cls_b = (int)Ab.size(); g.cls_m = (int)Am.size(); g.cls_n = (int)Bn.size(); g.cls_k = (int)Ak.size();
+        g.nb = int64_t(1) << g.cls_b; g.m = int64_t(1) << g.cls_m; g.n = int64_t(1) << g.cls_n; g.k = int64_t(1) << g.cls_k;
+        g.a_km = a_km && g.m > 1 && g.k > 1;
+        g.b_nk = b_nk && g.n > 1 && g.k > 1;
+        if ((int)layout[tc].size() > kMaxRank) { err = "intermediate rank exceeds the device limit"; return false; }
+        prog.gemms.push_back(g);
+        prog.ops.push_back(Op{Op::GEMM, (int)prog.gemms.size() - 1});
+        prog.flops += 8.0 * double(g.nb) * double(g.m) * double(g.n) * double(g.k);
+        prog.bytes += 8.0 * double(g.nb) * double(g.m * g.k + g.k * g.n + g.m * g.n);
+        // Counts of C: drop contracted indices.
+        std::vector<std::pair<int, int>> keep;
+        for (auto &v : cc)
+            if (in(layout[tc], v.first)) keep.push_back(v);
+        counts.push_back(std::move(keep));
+        tensor_of.push_back(tc);
+    }
+    int root = tensor_of.back();
+    std::vector<int> want;
+    for (int j = b - 1; j >= 0; --j) want.push_back(plan->sliced[j]);
+    want.insert(want.end(), bs_bits.begin(), bs_bits.end());
+    {
+        std::vector<int> a = layout[root], w = want;
+        std::sort(a.begin(), a.end());
+        std::sort(w.begin(), w.end());
+        if (a != w) { err = "internal: root indices are not the open indices"; return false; }
+    }
+    if (layout[root] != want) root = emit_transpose(root, want);
+    prog.root = root;
+
+    // Lifetimes and offsets.  Leaves are born before op 0; each op's output is
+    // allocated before its inputs are released.
+    const int nt = (int)layout.size();
+    std::vector<int> death(nt, -1);
+    for (size_t i = 0; i < prog.ops.size(); ++i) {
+        const Op &op = prog.ops[i];
+        if (op.kind == Op::TRANSPOSE) death[prog.transposes[op.index].src] = (int)i;
+        else { death[prog.gemms[op.index].a] = (int)i; death[prog.gemms[op.index].b] = (int)i; }
+    }
+    prog.tensors.resize(nt);
+    for (int t = 0; t < nt; ++t) prog.tensors[t].layout = layout[t];
+    Arena arena;
+    for (int t = 0; t < L; ++t) prog.tensors[t].offset = arena.alloc(prog.tensors[t].size());
+    for (size_t i = 0; i < prog.ops.size(); ++i) {
+        const Op &op = prog.ops[i];
+        const int out = op.kind == Op::TRANSPOSE ? prog.transposes[op.index].dst : prog.gemms[op.index].c;
+        prog.tensors[out].offset = arena.alloc(prog.tensors[out].size());
+        for (int t = 0; t < nt; ++t)
+            if (death[t] == (int)i) arena.release(prog.tensors[t].offset, prog.tensors[t].size());
+    }
+    prog.tensor_elems = arena.end;
+    return true;
+}
+
+Program *get_program(qc_plan *plan, int b, int m, std::string &err) {
+    std::lock_guard<std::mutex> lk(plan->mu);
+    auto key = std::make_pair(b, m);
+    auto it = plan->programs.find(key);
+    if (it != plan->programs.end()) return it->second.get();
+    auto prog = std::make_unique<Program>();
+    if (!lower(plan, b, m, *prog, err)) return nullptr;
+    Program *raw = prog.get();
+    plan->programs[key] = std::move(prog);
+    return raw;
+}
+
+static void json_ints(std::ostringstream &o, const std::vector<int> &v) {
+    o << '[';
+    for (size_t i = 0; i < v.size(); ++i) o << (i ? "," : "") << v[i];
+    o << ']';
+}
+
+std::string describe_program(const qc_plan *plan, const Program &prog) {
+    const Network &net = plan->net;
+    std::ostringstream o;
+    o.precision(17);
+    o << "{\"b\":" << prog.b << ",\"m\":" << prog.m << ",\"bs_base\":" << kBsBase;
+    o << ",\"n_qubits\":" << net.n_qubits;
+    o << ",\"segments\":[";
+    for (int e = 0; e < net.n_index(); ++e)
+        o << (e ? "," : "") << '[' << net.seg_q[e] << ',' << net.seg_ord[e] << ',' << net.out_qubit[e] << ']';
+    o << "],\"sliced\":";
+    json_ints(o, plan->sliced);
+    o << ",\"leaves\":[";
+    for (size_t t = 0; t < net.leaves.size(); ++t) {
+        const Tensor &T = net.leaves[t];
+        o << (t ? "," : "") << "{\"idx\":";
+        json_ints(o, T.idx);
+        o << ",\"re\":[";
+        for (size_t i = 0; i < T.data.size(); ++i) o << (i ? "," : "") << T.data[i].real();
+        o << "],\"im\":[";
+        for (size_t i = 0; i < T.data.size(); ++i) o << (i ? "," : "") << T.data[i].imag();
+        o << "],\"tensor\":" << prog.leaves[t].tensor << '}';
+    }
+    o << "],\"tensors\":[";
+    for (size_t t = 0; t < prog.tensors.size(); ++t) {
+        o << (t ? "," : "") << "{\"layout\":";
+        json_ints(o, prog.tensors[t].layout);
+        o << ",\"offset\":" << prog.tensors[t].offset << '}';
+    }
+    o << "],\"ops\":[";
+    for (size_t i = 0; i < prog.ops.size(); ++i) {
+        const Op &op = prog.ops[i];
+        o << (i ? "," : "");
+        if (op.kind == Op::TRANSPOSE) {
+            const TransposeOp &t = prog.transposes[op.index];
+            o << "{\"op\":\"transpose\",\"src\":" << t.src << ",\"dst\":" << t.dst << '}';
+        } else {
+            const GemmOp &g = prog.gemms[op.index];
+            o << "{\"op\":\"gemm\",\"a\":" << g.a << ",\"b\":" << g.b << ",\"c\":" << g.c << ",\"nb\":" << g.nb
+              << ",\"m\":" << g.m << ",\"n\":" << g.n << ",\"k\":" << g.k << ",\"a_km\":" << (g.a_km ? 1 : 0)
+              << ",\"b_nk\":" << (g.b_nk ? 1 : 0) << '}';
+        }
+    }
+    o << "],\"root\":" << prog.root << ",\"tensor_elems\":" << prog.tensor_elems << ",\"flops\":" << prog.flops
+      << ",\"bytes\":" << prog.bytes << ",\"transpose_bytes\":" << prog.transpose_bytes << '}';
+    return o.str();
+}
+
+}  // namespace qc

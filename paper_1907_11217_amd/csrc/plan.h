@@ -1,0 +1,141 @@
+// Host-side planner: circuit -> hypergraph tensor network -> simplified
+// leaves -> greedy pairwise order -> sliced segments -> lowered programs.
+//
+// The network follows the paper's refactored form (Section "Benchmarking and
+// the Experimental Setup"): each node holds a tensor and each hyper-edge is a
+// running index.  Running indices are wire segments: a qubit's wire is cut at
+// every non-diagonal gate, and diagonal gates (T, CZ) attach to the segment
+// they act on, so one index can join many tensors.
+#pragma once
+
+#include <complex>
+#include <cstdint>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "qcsim.h"
+
+namespace qc {
+
+using cplx = std::complex<double>;
+
+constexpr int kMaxRank = 40;       // largest tensor rank a program may hold
+constexpr int kMaxBsBits = 16;     // bitstrings in flight <= 65536
+
+// A tensor over binary indices; data is row-major with idx[0] the most
+// significant bit of the flat offset.
+struct Tensor {
+    std::vector<int> idx;
+    std::vector<cplx> data;
+};
+
+struct Network {
+    int n_qubits = 0;
+    std::vector<int> seg_q, seg_ord;    // per index: its segment (q, ordinal)
+    std::vector<int> out_qubit;         // per index: q if it is q's output segment, else -1
+    std::vector<int> n_cut;             // per qubit: non-diagonal gate count
+    std::vector<Tensor> leaves;         // simplified tensors
+    int n_index() const { return (int)seg_q.size(); }
+    int find_segment(int q, int ord) const;
+};
+
+// Builds the hypergraph network of <x|C|0^n> with output segments left as
+// indices (fixed per bitstring at instantiation) and input segments fixed to 0.
+bool build_network(const qc_circuit &c, Network &net, std::string &err);
+void simplify_network(Network &net, const std::vector<int> &keep);
+
+// One pairwise merge: tensors a, b -> a new tensor (ids: leaves first, then
+// merges in order).
+struct Merge { int a, b; };
+
+struct TreeCost {
+    double max_log2 = 0;     // largest intermediate (log2 entries)
+    double flops = 0;        // real flops (8 per complex MAC)
+    double bytes = 0;        // complex64 operand bytes
+    double peak_live = 0;    // peak live complex64 bytes (sequential execution)
+};
+
+// Index sets of all tree nodes given removed (sliced) indices; used by the
+// order search and slicing.
+struct OrderProblem {
+    int n_index = 0;
+    std::vector<std::vector<int>> leaf_idx;   // summed (non-output) indices per leaf
+};
+
+std::vector<Merge> greedy_order(const OrderProblem &p, const std::vector<char> &removed,
+                                uint64_t seed, double temperature);
+TreeCost tree_cost(const OrderProblem &p, const std::vector<Merge> &tree,
+                   const std::vector<char> &removed);
+
+// ------------------------------------------------------------ lowering
+// Index ids inside a program: segment ids, then kBsBase + i for bitstring bit i.
+constexpr int kBsBase = 1 << 20;
+
+struct ProgTensor {
+    std::vector<int> layout;   // major -> minor
+    int64_t offset = 0;        // element offset in the tensor region of ws
+    int64_t size() const { return int64_t(1) << layout.size(); }
+};
+
+struct LeafOp {
+    int leaf;                  // network leaf id
+    int tensor;                // program tensor id
+};
+
+struct TransposeOp {
+    int src, dst;
+};
+
+struct GemmOp {
+    int a, b, c;               // program tensor ids after transposes
+    int64_t nb, m, n, k;       // C[b][m][n] = sum_k A . B
+    bool a_km;                 // A stored [b][k][m] (else [b][m][k])
+    bool b_nk;                 // B stored [b][n][k] (else [b][k][n])
+    int cls_b, cls_m, cls_n, cls_k;  // log2 extents
+};
+
+struct Op {
+    enum Kind { TRANSPOSE, GEMM } kind;
+    int index;                 // into transposes / gemms
+};
+
+struct Program {
+    int b = 0, m = 0;                     // log2 slices / bitstrings in flight
+    std::vector<ProgTensor> tensors;
+    std::vector<LeafOp> leaves;
+    std::vector<TransposeOp> transposes;
+    std::vector<GemmOp> gemms;
+    std::vector<Op> ops;
+    int root = -1;                        // tensor holding [slice bits][bs bits]
+    int64_t tensor_elems = 0;             // tensor region size (complex64 elements)
+    double flops = 0, bytes = 0, transpose_bytes = 0;
+    // Device constants, created lazily on the device current at first use.
+    int device = -1;
+    void *d_leaf_desc = nullptr;
+    void *d_leaf_block = nullptr;
+    void *d_base = nullptr;
+    int n_leaf_blocks = 0;
+};
+
+}  // namespace qc
+
+struct qc_plan {
+    qc::Network net;
+    qc::OrderProblem prob;
+    std::vector<qc::Merge> tree;
+    std::vector<int> sliced;              // index ids in slice-bit order
+    std::vector<uint8_t> default_bitstring;
+    qc_plan_info_t info{};
+    std::mutex mu;
+    std::map<std::pair<int, int>, std::unique_ptr<qc::Program>> programs;
+};
+
+namespace qc {
+// Lowers the plan for 2^b slices and 2^m bitstrings in flight (cached).
+Program *get_program(qc_plan *plan, int b, int m, std::string &err);
+std::string describe_program(const qc_plan *plan, const Program &prog);
+void set_error(const std::string &msg);
+}  // namespace qc

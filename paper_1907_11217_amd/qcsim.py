@@ -1,0 +1,261 @@
+"""Thin ctypes binding of libqcsim.so (argument marshalling only).
+
+Every function here has the name of the C entry point it calls (see
+include/qcsim.h).  Device buffers are torch tensors on the current device
+(``data_ptr()``) and the stream is torch's current stream; all contraction
+work runs in the library's HIP kernels.  If the library is missing, every
+call raises: there is no fallback path.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import json
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libqcsim.so")
+
+QC_OK = 0
+QC_C64, QC_SPLIT_BF16, QC_SPLIT_FP16 = 0, 1, 2
+PRECISIONS = {"c64": QC_C64, "split_bf16": QC_SPLIT_BF16, "split_fp16": QC_SPLIT_FP16}
+STATUS_NAMES = {0: "QC_OK", 1: "QC_ERR_INVALID_ARG", 2: "QC_ERR_RANGE", 3: "QC_ERR_NOMEM",
+                4: "QC_ERR_DEVICE", 5: "QC_ERR_UNSUPPORTED", 6: "QC_ERR_INFEASIBLE"}
+
+EXPORTED = (
+    "qc_plan_build", "qc_plan_info", "qc_plan_sliced_segments", "qc_plan_slice_assignment",
+    "qc_plan_describe", "qc_workspace_bytes", "qc_contract_slices", "qc_amplitude",
+    "qc_gate_matrix", "qc_plan_destroy", "qc_last_error", "qc_kernel_gemm", "qc_kernel_transpose",
+)
+
+
+class QcError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class qc_gate(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("q0", ctypes.c_int32), ("q1", ctypes.c_int32),
+                ("moment", ctypes.c_int32)]
+
+
+class qc_circuit(ctypes.Structure):
+    _fields_ = [("n_qubits", ctypes.c_int32), ("n_gates", ctypes.c_int32),
+                ("gates", ctypes.POINTER(qc_gate))]
+
+
+class qc_slice_spec(ctypes.Structure):
+    _fields_ = [("log2_slices", ctypes.c_int32), ("log2_max_entries", ctypes.c_double),
+                ("n_explicit", ctypes.c_int32), ("explicit_segments", ctypes.POINTER(ctypes.c_int32)),
+                ("seed", ctypes.c_uint64), ("greedy_trials", ctypes.c_int32)]
+
+
+class qc_plan_info_t(ctypes.Structure):
+    _fields_ = [("n_qubits", ctypes.c_int32), ("log2_slices", ctypes.c_int32),
+                ("n_indices", ctypes.c_int32), ("n_leaves", ctypes.c_int32), ("n_steps", ctypes.c_int32),
+                ("log2_max_entries", ctypes.c_double), ("flops_per_slice", ctypes.c_double),
+                ("bytes_per_slice", ctypes.c_double), ("flops_unsliced", ctypes.c_double),
+                ("peak_live_bytes", ctypes.c_double), ("plan_seconds", ctypes.c_double)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+_lib = None
+
+
+def load(path: str | None = None):
+    """Loads libqcsim.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise RuntimeError(f"{p} is missing: build it with __graft_entry__.build()")
+    lib = ctypes.CDLL(p)
+    vp, sz = ctypes.c_void_p, ctypes.c_size_t
+    lib.qc_plan_build.argtypes = [ctypes.POINTER(qc_circuit), vp, ctypes.POINTER(qc_slice_spec), ctypes.POINTER(vp)]
+    lib.qc_plan_info.argtypes = [vp, ctypes.POINTER(qc_plan_info_t)]
+    lib.qc_plan_sliced_segments.argtypes = [vp, vp]
+    lib.qc_plan_slice_assignment.argtypes = [vp, ctypes.c_uint64, vp]
+    lib.qc_plan_describe.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int, vp, sz, ctypes.POINTER(sz)]
+    lib.qc_gate_matrix.argtypes = [ctypes.c_int32, vp]
+    lib.qc_plan_destroy.argtypes = [vp]
+    lib.qc_plan_destroy.restype = None
+    lib.qc_last_error.restype = ctypes.c_char_p
+    for name in ("qc_plan_build", "qc_plan_info", "qc_plan_sliced_segments", "qc_plan_slice_assignment",
+                 "qc_plan_describe", "qc_gate_matrix"):
+        getattr(lib, name).restype = ctypes.c_int
+    if hasattr(lib, "qc_contract_slices"):
+        lib.qc_workspace_bytes.argtypes = [vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_int]
+        lib.qc_workspace_bytes.restype = sz
+        lib.qc_contract_slices.argtypes = [vp, ctypes.c_uint64, ctypes.c_uint64, vp, ctypes.c_int32, ctypes.c_int,
+                                           vp, sz, vp, vp, vp]
+        lib.qc_contract_slices.restype = ctypes.c_int
+        lib.qc_amplitude.argtypes = [vp, vp, ctypes.c_int, vp]
+        lib.qc_amplitude.restype = ctypes.c_int
+        i64 = ctypes.c_int64
+        lib.qc_kernel_gemm.argtypes = [vp, vp, vp, i64, i64, i64, i64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int, vp]
+        lib.qc_kernel_gemm.restype = ctypes.c_int
+        lib.qc_kernel_transpose.argtypes = [vp, vp, ctypes.c_int32, vp, vp]
+        lib.qc_kernel_transpose.restype = ctypes.c_int
+    if path is None:
+        _lib = lib
+    return lib
+
+
+def qc_last_error() -> str:
+    return load().qc_last_error().decode()
+
+
+def _check(status: int, lib=None):
+    if status != QC_OK:
+        raise QcError(status, (lib or load()).qc_last_error().decode())
+
+
+def _prec(p) -> int:
+    return PRECISIONS[p] if isinstance(p, str) else int(p)
+
+
+class Plan:
+    """Owns a qc_plan*; freed by qc_plan_destroy when garbage collected."""
+
+    def __init__(self, handle, lib, n_qubits):
+        self._h = handle
+        self._lib = lib
+        self.n_qubits = n_qubits
+
+    @property
+    def handle(self):
+        return self._h
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            self._lib.qc_plan_destroy(self._h)
+            self._h = None
+
+
+def qc_plan_build(n_qubits: int, circuit, bitstring=None, log2_slices: int = 0,
+                  log2_max_entries: float = 0.0, explicit_segments=None, seed: int = 0,
+                  greedy_trials: int = 1, lib=None) -> Plan:
+    lib = lib or load()
+    circ = np.ascontiguousarray(np.asarray(circuit, dtype=np.int32).reshape(-1, 4))
+    gates = (qc_gate * max(1, len(circ)))()
+    ctypes.memmove(gates, circ.ctypes.data, circ.nbytes)
+    c = qc_circuit(int(n_qubits), len(circ), gates)
+    ex = None
+    n_ex = 0
+    if explicit_segments is not None and len(explicit_segments):
+        ex_arr = np.ascontiguousarray(np.asarray(explicit_segments, dtype=np.int32).reshape(-1, 2))
+        n_ex = len(ex_arr)
+        ex = (ctypes.c_int32 * (2 * n_ex))(*ex_arr.reshape(-1).tolist())
+    spec = qc_slice_spec(int(log2_slices), float(log2_max_entries), n_ex,
+                         ctypes.cast(ex, ctypes.POINTER(ctypes.c_int32)) if ex is not None else None,
+                         int(seed), int(greedy_trials))
+    bsp = None
+    if bitstring is not None:
+        bs = np.ascontiguousarray(np.asarray(bitstring, dtype=np.uint8).reshape(-1))
+        bsp = bs.ctypes.data
+    h = ctypes.c_void_p()
+    _check(lib.qc_plan_build(ctypes.byref(c), bsp, ctypes.byref(spec), ctypes.byref(h)), lib)
+    return Plan(h, lib, int(n_qubits))
+
+
+def qc_plan_info(plan: Plan) -> dict:
+    info = qc_plan_info_t()
+    _check(plan._lib.qc_plan_info(plan.handle, ctypes.byref(info)), plan._lib)
+    return info.as_dict()
+
+
+def qc_plan_sliced_segments(plan: Plan) -> np.ndarray:
+    k = qc_plan_info(plan)["log2_slices"]
+    out = np.zeros((max(k, 1), 2), dtype=np.int32)
+    _check(plan._lib.qc_plan_sliced_segments(plan.handle, out.ctypes.data), plan._lib)
+    return out[:k]
+
+
+def qc_plan_slice_assignment(plan: Plan, s: int) -> np.ndarray:
+    k = qc_plan_info(plan)["log2_slices"]
+    out = np.zeros(max(k, 1), dtype=np.uint8)
+    _check(plan._lib.qc_plan_slice_assignment(plan.handle, ctypes.c_uint64(int(s)), out.ctypes.data), plan._lib)
+    return out[:k]
+
+
+def qc_plan_describe(plan: Plan, log2_batch_slices: int = 0, log2_batch_bs: int = 0, prec="c64") -> dict:
+    n = ctypes.c_size_t()
+    _check(plan._lib.qc_plan_describe(plan.handle, log2_batch_slices, log2_batch_bs, _prec(prec), None, 0,
+                                      ctypes.byref(n)), plan._lib)
+    buf = ctypes.create_string_buffer(n.value + 1)
+    _check(plan._lib.qc_plan_describe(plan.handle, log2_batch_slices, log2_batch_bs, _prec(prec), buf,
+                                      n.value + 1, ctypes.byref(n)), plan._lib)
+    return json.loads(buf.value.decode())
+
+
+def qc_gate_matrix(kind: int, lib=None) -> np.ndarray:
+    lib = lib or load()
+    out = np.zeros(32, dtype=np.float64)
+    _check(lib.qc_gate_matrix(int(kind), out.ctypes.data), lib)
+    c = out[0::2] + 1j * out[1::2]
+    return c.reshape(4, 4) if int(kind) == 4 else c[:4].reshape(2, 2)
+
+
+def qc_workspace_bytes(plan: Plan, chunk_slices: int, n_bs: int, prec="c64") -> int:
+    return int(plan._lib.qc_workspace_bytes(plan.handle, int(chunk_slices), int(n_bs), _prec(prec)))
+
+
+def qc_contract_slices(plan: Plan, s_begin: int, s_end: int, bitstrings, prec, ws, out_dev,
+                       per_slice_dev=None, stream=None):
+    """Enqueues the slice range on ``stream`` (default: torch's current
+    stream); ``ws``, ``out_dev`` and ``per_slice_dev`` are torch device
+    tensors (out_dev float64 [n_bs, 2], accumulated into)."""
+    import torch
+    bs = np.ascontiguousarray(np.atleast_2d(np.asarray(bitstrings, dtype=np.uint8)))
+    if bs.shape[1] != plan.n_qubits:
+        raise ValueError("bitstrings must be [n_bs, n_qubits]")
+    if out_dev.dtype != torch.float64 or out_dev.numel() < 2 * bs.shape[0] or not out_dev.is_contiguous():
+        raise ValueError("out_dev must be a contiguous float64 device tensor of n_bs x 2")
+    if per_slice_dev is not None and (per_slice_dev.dtype != torch.float64 or
+                                      per_slice_dev.numel() < 2 * bs.shape[0] * (s_end - s_begin)):
+        raise ValueError("per_slice_dev must be float64 with (s_end - s_begin) x n_bs x 2 entries")
+    st = stream if stream is not None else torch.cuda.current_stream()
+    _check(plan._lib.qc_contract_slices(
+        plan.handle, ctypes.c_uint64(int(s_begin)), ctypes.c_uint64(int(s_end)), bs.ctypes.data, bs.shape[0],
+        _prec(prec), ws.data_ptr(), ws.numel() * ws.element_size(), st.cuda_stream, out_dev.data_ptr(),
+        per_slice_dev.data_ptr() if per_slice_dev is not None else None), plan._lib)
+
+
+def qc_kernel_gemm(A, B, C, nb: int, m: int, n: int, k: int, a_km: bool = False, b_nk: bool = False,
+                   prec="c64", stream=None):
+    """One batched complex GEMM step on torch complex64 device tensors."""
+    import torch
+    lib = load()
+    for t in (A, B, C):
+        if t.dtype != torch.complex64 or not t.is_contiguous():
+            raise ValueError("operands must be contiguous complex64 device tensors")
+    if A.numel() < nb * m * k or B.numel() < nb * k * n or C.numel() < nb * m * n:
+        raise ValueError("operand too small for the GEMM shape")
+    st = stream if stream is not None else torch.cuda.current_stream()
+    _check(lib.qc_kernel_gemm(A.data_ptr(), B.data_ptr(), C.data_ptr(), nb, m, n, k, int(bool(a_km)),
+                              int(bool(b_nk)), _prec(prec), st.cuda_stream), lib)
+
+
+def qc_kernel_transpose(inp, out, rank: int, perm, stream=None):
+    """Bit-permuting transpose: input bit p goes to output bit perm[p]."""
+    import torch
+    lib = load()
+    if inp.dtype != torch.complex64 or out.dtype != torch.complex64 or inp.numel() < (1 << rank) \
+            or out.numel() < (1 << rank):
+        raise ValueError("operands must be complex64 device tensors of 2^rank entries")
+    p = np.ascontiguousarray(np.asarray(perm, dtype=np.int32))
+    st = stream if stream is not None else torch.cuda.current_stream()
+    _check(lib.qc_kernel_transpose(inp.data_ptr(), out.data_ptr(), int(rank), p.ctypes.data, st.cuda_stream), lib)
+
+
+def qc_amplitude(plan: Plan, bitstring, prec="c64") -> complex:
+    bs = np.ascontiguousarray(np.asarray(bitstring, dtype=np.uint8).reshape(-1))
+    out = np.zeros(2, dtype=np.float64)
+    _check(plan._lib.qc_amplitude(plan.handle, bs.ctypes.data, _prec(prec), out.ctypes.data), plan._lib)
+    return complex(out[0], out[1])

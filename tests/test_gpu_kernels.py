@@ -1,0 +1,73 @@
+"""Step kernels on the GPU against NumPy: the batched complex GEMM (MFMA and
+VALU forms, all four operand layouts) and the bit-permuting transpose."""
+
+import numpy as np
+import pytest
+
+from tests.gpu_util import say
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_1907_11217_amd import qcsim  # noqa: E402
+
+
+def _rand(rng, shape):
+    return (rng.standard_normal(shape) + 1j * rng.standard_normal(shape)).astype(np.complex64)
+
+
+GEMM_SHAPES = [
+    # nb, m, n, k          (MFMA needs m, n >= 32 and k >= 2)
+    (1, 32, 32, 2), (3, 64, 64, 16), (2, 64, 32, 32), (1, 128, 64, 64), (5, 32, 64, 8),
+    (2, 256, 128, 128), (1, 64, 64, 4),
+    (4, 2, 4, 8), (7, 1, 16, 4), (1, 1, 1, 1024), (16, 64, 64, 1), (8, 16, 16, 16), (1, 32, 2, 64),
+]
+
+
+@pytest.mark.parametrize("shape", GEMM_SHAPES)
+@pytest.mark.parametrize("a_km,b_nk", [(0, 0), (1, 0), (0, 1), (1, 1)])
+def test_gemm_c64(shape, a_km, b_nk):
+    nb, m, n, k = shape
+    rng = np.random.default_rng(nb * 1000003 + m * 1009 + n * 31 + k + 7 * a_km + 13 * b_nk)
+    A = _rand(rng, (nb, m, k))
+    B = _rand(rng, (nb, k, n))
+    a_store = A.transpose(0, 2, 1) if a_km else A
+    b_store = B.transpose(0, 2, 1) if b_nk else B
+    dA = torch.from_numpy(np.ascontiguousarray(a_store).reshape(-1)).cuda()
+    dB = torch.from_numpy(np.ascontiguousarray(b_store).reshape(-1)).cuda()
+    dC = torch.zeros(nb * m * n, dtype=torch.complex64, device="cuda")
+    say(f"gemm c64 nb={nb} m={m} n={n} k={k} a_km={a_km} b_nk={b_nk}")
+    qcsim.qc_kernel_gemm(dA, dB, dC, nb, m, n, k, a_km, b_nk)
+    torch.cuda.synchronize()
+    got = dC.cpu().numpy().reshape(nb, m, n)
+    ref = np.matmul(A.astype(np.complex128), B.astype(np.complex128))
+    # FP32 accumulation of k products of unit-variance values.
+    tol = 2e-6 * np.sqrt(k) * 4
+    assert np.abs(got - ref).max() <= tol * max(1.0, np.sqrt(k)), np.abs(got - ref).max()
+
+
+@pytest.mark.parametrize("rank", [0, 1, 3, 5, 8, 10, 11, 14, 18, 22])
+def test_transpose_exact(rank):
+    rng = np.random.default_rng(rank)
+    perm = rng.permutation(rank).astype(np.int32)
+    x = _rand(rng, (1 << rank,))
+    d_in = torch.from_numpy(x).cuda()
+    d_out = torch.zeros(1 << rank, dtype=torch.complex64, device="cuda")
+    say(f"transpose rank={rank}")
+    qcsim.qc_kernel_transpose(d_in, d_out, rank, perm)
+    torch.cuda.synchronize()
+    got = d_out.cpu().numpy()
+    # Reference: bit p of the input offset becomes bit perm[p] of the output.
+    i = np.arange(1 << rank, dtype=np.int64)
+    o = np.zeros_like(i)
+    for p in range(rank):
+        o |= ((i >> p) & 1) << int(perm[p])
+    ref = np.zeros_like(x)
+    ref[o] = x
+    assert np.array_equal(got.view(np.uint64), ref.view(np.uint64))
+
+
+def test_transpose_rejects_bad_perm():
+    d = torch.zeros(8, dtype=torch.complex64, device="cuda")
+    with pytest.raises(qcsim.QcError):
+        qcsim.qc_kernel_transpose(d, d, 3, [0, 0, 1])

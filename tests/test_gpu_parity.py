@@ -1,0 +1,152 @@
+"""End-to-end parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Tolerance for complex FP32 (QC_C64): relative error <= 1e-5 on bitstrings
+with N|a|^2 >= 1e-2, plus batch 2-norm and absolute-vs-RMS bounds (see
+tests/gpu_util.check_amplitudes).  Slice enumeration is checked bit-exactly
+through per-slice values against the oracle's own sliced contraction."""
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.gpu_util import check_amplitudes, say
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_1907_11217_amd import qcsim  # noqa: E402
+
+TOL_C64 = 1e-5
+
+
+def _contract(plan, xs, s_begin, s_end, prec="c64", ws_bytes=None, chunk=None, per_slice=False):
+    n_bs = len(xs)
+    if ws_bytes is None:
+        chunk = chunk or min(s_end - s_begin, 1 << 12)
+        ws_bytes = qcsim.qc_workspace_bytes(plan, chunk, n_bs, prec)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
+    out = torch.zeros(n_bs, 2, dtype=torch.float64, device="cuda")
+    ps = torch.zeros(s_end - s_begin, n_bs, 2, dtype=torch.float64, device="cuda") if per_slice else None
+    qcsim.qc_contract_slices(plan, s_begin, s_end, xs, prec, ws, out, ps)
+    torch.cuda.synchronize()
+    o = out.cpu().numpy()
+    amps = o[:, 0] + 1j * o[:, 1]
+    if per_slice:
+        p = ps.cpu().numpy()
+        return amps, p[..., 0] + 1j * p[..., 1]
+    return amps
+
+
+def test_p2_hadamard_layers_gpu():
+    lat = synth.grid(3, 3)
+    circ = synth.random_circuit(lat, 0, 1)
+    xs = np.array(list(np.ndindex(*([2] * lat.n))), dtype=np.uint8)
+    plan = qcsim.qc_plan_build(lat.n, circ)
+    say("P2 1+0+1 3x3 all bitstrings")
+    got = _contract(plan, xs, 0, 1)
+    ref = np.zeros(len(xs))
+    ref[0] = 1
+    assert np.abs(got - ref).max() <= 1e-7
+
+
+@pytest.mark.parametrize("shape,depth,seed", [((2, 2), 8, 1), ((2, 3), 8, 2), ((3, 3), 8, 3)])
+def test_p6_unitarity_all_amplitudes(shape, depth, seed):
+    lat = synth.grid(*shape)
+    circ = synth.random_circuit(lat, depth, seed)
+    xs = np.array(list(np.ndindex(*([2] * lat.n))), dtype=np.uint8)
+    plan = qcsim.qc_plan_build(lat.n, circ, None, log2_slices=2, greedy_trials=2)
+    say(f"P6 unitarity {shape} d{depth}")
+    got = _contract(plan, xs, 0, 4)
+    assert abs(np.sum(np.abs(got) ** 2) - 1) <= 1e-5
+    psi = oracle.statevector(lat.n, circ)
+    check_amplitudes(got, psi, lat.n, TOL_C64)
+
+
+def test_c1_amplitudes():
+    lat, circ, bs, _ = synth.config("c1")
+    xs = np.concatenate([bs, synth.random_bitstrings(lat.n, 255, 1001)])
+    plan = qcsim.qc_plan_build(lat.n, circ, bs[0])
+    psi = oracle.statevector(lat.n, circ)
+    ref = np.array([psi[oracle.index_of(x)] for x in xs])
+    say("c1 4x4 d10, 256 bitstrings, unsliced")
+    got = _contract(plan, xs, 0, 1)
+    info = check_amplitudes(got, ref, lat.n, TOL_C64)
+    print("c1", info)
+
+
+def test_c1_qc_amplitude():
+    lat, circ, bs, _ = synth.config("c1")
+    x = synth.random_bitstrings(lat.n, 3, 555)[2]
+    plan = qcsim.qc_plan_build(lat.n, circ, x, log2_slices=3)
+    ref = oracle.amplitudes_sv(lat.n, circ, [x])[0]
+    say("c1 qc_amplitude k=3")
+    got = qcsim.qc_amplitude(plan, x)
+    assert abs(got - ref) <= TOL_C64 * max(abs(ref), 2.0 ** (-lat.n / 2))
+
+
+@pytest.fixture(scope="module")
+def c2_setup():
+    lat, circ, bs, spec = synth.config("c2")
+    plan = qcsim.qc_plan_build(lat.n, circ, bs[0], log2_slices=spec["log2_slices"], greedy_trials=8, seed=1)
+    psi = oracle.statevector(lat.n, circ)
+    ref = np.array([psi[oracle.index_of(x)] for x in bs])
+    return lat, circ, bs, plan, ref
+
+
+def test_c2_amplitudes_c64(c2_setup):
+    lat, circ, bs, plan, ref = c2_setup
+    assert qcsim.qc_plan_info(plan)["log2_slices"] == 6
+    say("c2 5x5 d16, 64 bitstrings x 64 slices, c64")
+    got = _contract(plan, bs, 0, 64)
+    info = check_amplitudes(got, ref, lat.n, TOL_C64)
+    print("c2", info)
+
+
+def test_c2_per_slice_values_match_oracle(c2_setup):
+    lat, circ, bs, plan, _ref = c2_setup
+    segs = [tuple(int(v) for v in s) for s in qcsim.qc_plan_sliced_segments(plan)]
+    say("c2 per-slice values")
+    amps, ps = _contract(plan, bs[:8], 0, 64, per_slice=True)
+    assert np.abs(ps.sum(axis=0) - amps).max() <= 1e-15 + 1e-12 * np.abs(amps).max()
+    vals = np.abs(ps).ravel()
+    scale = np.sqrt(np.mean(vals ** 2))
+    for s, j in [(0, 0), (37, 1), (63, 7), (12, 3)]:
+        v = oracle.sliced_value(lat.n, circ, bs[j], segs, s)
+        assert abs(ps[s, j] - v) <= TOL_C64 * max(abs(v), scale), (s, j, ps[s, j], v)
+
+
+def test_c2_ranges_compose_and_repeat(c2_setup):
+    lat, circ, bs, plan, ref = c2_setup
+    ws_bytes = qcsim.qc_workspace_bytes(plan, 16, len(bs))
+    say("c2 ranges [0,64) vs [0,32)+[32,64), chunk 16")
+    whole = _contract(plan, bs, 0, 64, ws_bytes=ws_bytes)
+    again = _contract(plan, bs, 0, 64, ws_bytes=ws_bytes)
+    assert np.array_equal(whole, again)  # bitwise reproducible
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
+    out = torch.zeros(len(bs), 2, dtype=torch.float64, device="cuda")
+    qcsim.qc_contract_slices(plan, 0, 32, bs, "c64", ws, out)
+    qcsim.qc_contract_slices(plan, 32, 64, bs, "c64", ws, out)
+    torch.cuda.synchronize()
+    o = out.cpu().numpy()
+    split = o[:, 0] + 1j * o[:, 1]
+    # Chunk-aligned split: the same per-chunk sums, added in the same order.
+    assert np.array_equal(split, whole)
+    # Unaligned split: equal to rounding.
+    out.zero_()
+    qcsim.qc_contract_slices(plan, 0, 21, bs, "c64", ws, out)
+    qcsim.qc_contract_slices(plan, 21, 64, bs, "c64", ws, out)
+    torch.cuda.synchronize()
+    o = out.cpu().numpy()
+    assert np.abs((o[:, 0] + 1j * o[:, 1]) - whole).max() <= 1e-15
+    check_amplitudes(whole, ref, lat.n, TOL_C64)
+
+
+def test_workspace_too_small(c2_setup):
+    lat, circ, bs, plan, _ref = c2_setup
+    need = qcsim.qc_workspace_bytes(plan, 1, len(bs))
+    ws = torch.empty(max(need // 2, 1), dtype=torch.uint8, device="cuda")
+    out = torch.zeros(len(bs), 2, dtype=torch.float64, device="cuda")
+    with pytest.raises(qcsim.QcError) as e:
+        qcsim.qc_contract_slices(plan, 0, 64, bs, "c64", ws, out)
+    assert e.value.status == 3

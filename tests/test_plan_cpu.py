@@ -1,0 +1,175 @@
+"""Planner and lowering on the CPU: the library's exported program, run by the
+test-only interpreter (tests/plan_interp.py), against the FP64 oracle; slice
+enumeration; gate table; argument errors; exported symbols."""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from paper_1907_11217_amd import qcsim
+from tests.plan_interp import run_program, sliced_amplitudes
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _plan(key_or_lat, circ=None, **kw):
+    if isinstance(key_or_lat, str):
+        lat, circ, bs, spec = synth.config(key_or_lat)
+        return lat, circ, bs, qcsim.qc_plan_build(lat.n, circ, bs[0], **kw)
+    lat = key_or_lat
+    return lat, circ, None, qcsim.qc_plan_build(lat.n, circ, None, **kw)
+
+
+def test_library_exports_every_declared_symbol():
+    declared = set()
+    for h in ("qcsim.h", "qcsim_kernels.h"):
+        hdr = open(os.path.join(ROOT, "include", h)).read()
+        declared |= set(re.findall(r"\b(qc_[a-z_]+)\s*\(", hdr))
+    lib = qcsim.load()
+    missing = [s for s in sorted(declared) if not hasattr(lib, s)]
+    assert not missing, missing
+    assert declared == set(qcsim.EXPORTED)
+
+
+def test_gate_matrices_match_oracle_table():
+    for kind in range(5):
+        assert np.abs(qcsim.qc_gate_matrix(kind) - oracle.gate_matrix(kind)).max() < 1e-15
+
+
+def test_c1_unsliced_program_matches_statevector():
+    lat, circ, _bs, plan = _plan("c1")
+    xs = synth.random_bitstrings(lat.n, 16, 1234)
+    psi = oracle.statevector(lat.n, circ)
+    desc = qcsim.qc_plan_describe(plan, 0, 4)
+    got = run_program(desc, xs)[0]
+    ref = np.array([psi[oracle.index_of(x)] for x in xs])
+    assert np.abs(got - ref).max() < 1e-14
+
+
+@pytest.mark.parametrize("b,m", [(0, 0), (2, 0), (4, 3), (3, 2)])
+def test_c1_sliced_programs_match(b, m):
+    lat, circ, _bs, plan = _plan("c1", log2_slices=4, greedy_trials=2, seed=3)
+    info = qcsim.qc_plan_info(plan)
+    assert info["log2_slices"] == 4
+    xs = synth.random_bitstrings(lat.n, max(1, (1 << m) - 1), 99)
+    psi = oracle.statevector(lat.n, circ)
+    desc = qcsim.qc_plan_describe(plan, b, m)
+    total, per_slice = sliced_amplitudes(desc, xs, 16)
+    ref = np.array([psi[oracle.index_of(x)] for x in xs])
+    assert np.abs(total - ref).max() < 1e-14
+    # Per-slice values equal the oracle's own sliced contraction.
+    segs = [tuple(s) for s in qcsim.qc_plan_sliced_segments(plan)]
+    for s in (0, 5, 15):
+        v = oracle.sliced_value(lat.n, circ, xs[0], segs, s)
+        assert abs(per_slice[s, 0] - v) < 1e-14
+
+
+def test_c2_program_matches_statevector_sample():
+    lat, circ, bs, plan = _plan("c2", log2_slices=6, greedy_trials=4, seed=1)
+    info = qcsim.qc_plan_info(plan)
+    assert info["log2_slices"] == 6 and info["n_steps"] == info["n_leaves"] - 1
+    xs = bs[:3]
+    desc = qcsim.qc_plan_describe(plan, 6, 2)
+    total, per_slice = sliced_amplitudes(desc, xs, 64)
+    ref = np.array([oracle.tn_amplitude(lat.n, circ, x) for x in xs])
+    assert np.abs(total - ref).max() < 1e-14 * max(1.0, np.abs(ref).max() * 1e6)
+    segs = [tuple(s) for s in qcsim.qc_plan_sliced_segments(plan)]
+    v = oracle.sliced_value(lat.n, circ, xs[1], segs, 37)
+    assert abs(per_slice[37, 1] - v) < 1e-15
+
+
+def test_explicit_slices_and_assignment():
+    lat = synth.grid(3, 3)
+    circ = synth.random_circuit(lat, 6, 8)
+    cnt = oracle.segment_counts(lat.n, circ)
+    want = [(q, 1) for q in range(lat.n) if cnt[q] >= 2][:3]
+    plan = qcsim.qc_plan_build(lat.n, circ, None, log2_slices=5, explicit_segments=want)
+    segs = [tuple(int(v) for v in s) for s in qcsim.qc_plan_sliced_segments(plan)]
+    assert segs[:3] == want and len(segs) == 5
+    k = 5
+    for s in range(1 << k):
+        assert list(qcsim.qc_plan_slice_assignment(plan, s)) == [(s >> j) & 1 for j in range(k)]
+    with pytest.raises(qcsim.QcError) as e:
+        qcsim.qc_plan_slice_assignment(plan, 1 << k)
+    assert e.value.status == 2
+    x = synth.random_bitstrings(lat.n, 1, 5)
+    desc = qcsim.qc_plan_describe(plan, 2, 0)
+    total, per_slice = sliced_amplitudes(desc, x, 1 << k)
+    assert abs(total[0] - oracle.amplitudes_sv(lat.n, circ, x)[0]) < 1e-14
+    for s in (0, 7, 31):
+        assert abs(per_slice[s, 0] - oracle.sliced_value(lat.n, circ, x[0], segs, s)) < 1e-15
+
+
+def test_slice_assignment_random_large_k():
+    lat, circ, _bs, plan = _plan("c3", log2_slices=18, log2_max_entries=30)
+    k = qcsim.qc_plan_info(plan)["log2_slices"]
+    assert k >= 18
+    rng = np.random.default_rng(0)
+    for s in rng.integers(0, 1 << k, size=200):
+        assert list(qcsim.qc_plan_slice_assignment(plan, int(s))) == [(int(s) >> j) & 1 for j in range(k)]
+
+
+def test_cap_is_met_and_infeasible_is_reported():
+    lat, circ, _bs, plan = _plan("c3", log2_slices=-1, log2_max_entries=20, greedy_trials=2)
+    info = qcsim.qc_plan_info(plan)
+    assert info["log2_max_entries"] <= 20 and info["log2_slices"] >= 1
+    # Any cap can be met by slicing every summed index ...
+    lat2 = synth.grid(2, 2)
+    circ2 = synth.random_circuit(lat2, 4, 1)
+    p2 = qcsim.qc_plan_build(lat2.n, circ2, None, log2_slices=-1, log2_max_entries=0.5)
+    i2 = qcsim.qc_plan_info(p2)
+    assert i2["log2_max_entries"] == 0 and i2["log2_slices"] == i2["n_indices"]
+    # ... but not more slice bits than there are summed indices.
+    with pytest.raises(qcsim.QcError) as e:
+        qcsim.qc_plan_build(lat2.n, circ2, None, log2_slices=i2["n_indices"] + 1)
+    assert e.value.status == 6
+
+
+def test_invalid_arguments():
+    lat = synth.grid(2, 2)
+    bad = np.array([[9, 0, -1, 0]], dtype=np.int32)
+    with pytest.raises(qcsim.QcError) as e:
+        qcsim.qc_plan_build(lat.n, bad)
+    assert e.value.status == 1
+    bad = np.array([[4, 0, 0, 0]], dtype=np.int32)
+    with pytest.raises(qcsim.QcError):
+        qcsim.qc_plan_build(lat.n, bad)
+    circ = synth.random_circuit(lat, 2, 1)
+    with pytest.raises(qcsim.QcError):
+        qcsim.qc_plan_build(lat.n, circ, np.array([0, 2, 0, 0], dtype=np.uint8))
+    with pytest.raises(qcsim.QcError):
+        qcsim.qc_plan_build(lat.n, circ, explicit_segments=[(0, 0)], log2_slices=1)
+    plan = qcsim.qc_plan_build(lat.n, circ)
+    lib = qcsim.load()
+    assert lib.qc_workspace_bytes(plan.handle, 0, 1, 0) == 0
+    assert lib.qc_workspace_bytes(plan.handle, 1, 0, 0) == 0
+    assert lib.qc_workspace_bytes(plan.handle, 2, 1, 0) == 0  # more slices than the plan has
+    assert lib.qc_workspace_bytes(plan.handle, 1, 4, 0) > 0
+    # Host-side validation of qc_contract_slices happens before any device call.
+    out = ctypes.c_void_p(1)
+    bs = np.zeros(lat.n, dtype=np.uint8)
+    st = lib.qc_contract_slices(plan.handle, 0, 2, bs.ctypes.data, 1, 0, out, 1 << 20, None, out, None)
+    assert st == 2
+    st = lib.qc_contract_slices(plan.handle, 0, 1, bs.ctypes.data, 1, 7, out, 1 << 20, None, out, None)
+    assert st == 1
+    bs[0] = 3
+    st = lib.qc_contract_slices(plan.handle, 0, 1, bs.ctypes.data, 1, 0, out, 1 << 20, None, out, None)
+    assert st == 1
+    assert "0 or 1" in qcsim.qc_last_error()
+
+
+def test_idle_qubit_and_diagonal_only_wires():
+    # A qubit with no gate at all: its amplitude factor is delta(x_q, 0).
+    circ = np.array([[0, 0, -1, 0], [3, 0, -1, 1], [0, 0, -1, 2], [4, 0, 1, 3]], dtype=np.int32)
+    plan = qcsim.qc_plan_build(3, circ)
+    xs = np.array(list(np.ndindex(2, 2, 2)), dtype=np.uint8)
+    desc = qcsim.qc_plan_describe(plan, 0, 3)
+    got = run_program(desc, xs)[0]
+    psi = oracle.statevector(3, circ)
+    ref = np.array([psi[oracle.index_of(x)] for x in xs])
+    assert np.abs(got - ref).max() < 1e-15
