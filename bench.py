@@ -1,0 +1,198 @@
+#!/usr/bin/env python3
+"""Throughput of the sliced tensor-network amplitude path on one MI355X.
+
+One step = one qc_contract_slices call over every slice of the workload for
+its whole bitstring batch (leaf instantiation, all pairwise contraction
+steps, FP64 cross-slice reduction), inputs resident on the device.  Default
+workload: 5x5 grid, depth 1+16+1, 2^6 slices, 64 bitstrings.
+
+Prints ONE JSON line: amplitudes/s (value), slices/s, algorithmic TFLOP/s,
+relative error against the FP64 oracle, the roofline of the dominant kernel
+(per-launch algorithmic work / average launch time from HIP events recorded
+by the library on the call's stream during the timed steps) and the oracle's
+own CPU throughput on the host cores.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "amplitudes/sec and contraction TFLOP/s vs MFMA peak, FP32 vs split-FP16 at stated rel err"
+PEAK_FP32_TFLOPS = 157.3      # MI355X FP32 (vector and matrix)
+PEAK_HBM_GBS = 8000.0
+WORKLOADS = {"grid5x5_d16": "c2", "grid4x4_d10": "c1"}
+
+
+def _workload_text(key, lat, spec, k, n_bs):
+    return (f"{spec['name']}: {lat.n} qubits on a {spec['lattice'][0]}x{spec['lattice'][1]} grid, depth 1+"
+            f"{spec['depth']}+1, 2^{k} slices, {n_bs} bitstrings (seeds {spec['seed']}/{spec['seed'] + 1})")
+
+
+def _gemm_form(op):
+    k = op["k"]
+    kt = 16 if k >= 16 else k
+    ok = kt in (2, 4, 8, 16) and k % kt == 0
+    return "gemm_mfma" if ok and op["m"] % 32 == 0 and op["n"] % 32 == 0 else "gemm_valu"
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="grid5x5_d16", choices=sorted(WORKLOADS))
+    ap.add_argument("--prec", default="c64", choices=["c64", "split_bf16", "split_fp16"])
+    ap.add_argument("--exec", default="auto", choices=["auto", "fused", "stepwise"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}); "
+              "the slice ranges of a multi-GPU run would be independent per GPU, see DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1907_11217_amd import qcsim
+
+    key = WORKLOADS[args.workload]
+    lat, circ, bs, spec = synth.config(key)
+    n_bs = len(bs)
+    torch.cuda.set_device(0)
+    t0 = time.perf_counter()
+    plan = qcsim.qc_plan_build(lat.n, circ, bs[0], log2_slices=spec["log2_slices"],
+                               log2_max_entries=spec.get("log2_cap", 0), greedy_trials=8, seed=1)
+    plan_s = time.perf_counter() - t0
+    qcsim.qc_plan_set_exec(plan, args.exec)
+    info = qcsim.qc_plan_info(plan)
+    k = info["log2_slices"]
+    n_slices = 1 << k
+    ws = torch.empty(qcsim.qc_workspace_bytes(plan, n_slices, n_bs, args.prec), dtype=torch.uint8, device="cuda")
+    out = torch.zeros(n_bs, 2, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def step():
+        qcsim.qc_contract_slices(plan, 0, n_slices, bs, args.prec, ws, out, stream=stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    # Timed region; the library records an event pair around each of its
+    # kernels on `stream` for the per-kernel roofline.
+    qcsim.qc_profile_read(plan)
+    qcsim.qc_profile_enable(plan, True)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        step()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    qcsim.qc_profile_enable(plan, False)
+    ms = ev0.elapsed_time(ev1) / args.steps
+    prof = qcsim.qc_profile_read(plan)
+
+    # Result of one clean step, for the error report.
+    out.zero_()
+    step()
+    torch.cuda.synchronize()
+    o = out.cpu().numpy()
+    amps = o[:, 0] + 1j * o[:, 1]
+
+    # Algorithmic work (the lowered program's own per-step shapes).
+    fused = "fused" in prof
+    if fused:
+        desc = qcsim.qc_plan_describe(plan, 0, 0)
+        pairs_per_launch = n_slices * (1 << max(0, int(np.ceil(np.log2(n_bs)))))
+        flops_step = desc["flops"] * n_slices * n_bs
+        kind_work = {"fused": (desc["flops"] * pairs_per_launch, "alu")}
+    else:
+        b = min(k, 12)
+        desc = None
+        kind_work = {}
+        flops_step = 0.0
+        for bb in range(min(k, 12), -1, -1):
+            try:
+                desc = qcsim.qc_plan_describe(plan, bb, int(np.ceil(np.log2(n_bs))))
+                b = bb
+                break
+            except qcsim.QcError:
+                continue
+        chunks = max(1, n_slices >> b)
+        per = {"gemm_mfma": 0.0, "gemm_valu": 0.0, "transpose": 0.0}
+        for op in desc["ops"]:
+            if op["op"] == "gemm":
+                per[_gemm_form(op)] += 8.0 * op["nb"] * op["m"] * op["n"] * op["k"]
+            else:
+                per["transpose"] += 16.0 * (1 << len(desc["tensors"][op["src"]]["layout"]))
+        flops_step = (per["gemm_mfma"] + per["gemm_valu"]) * chunks * n_bs / (1 << desc["m"])
+        kind_work = {"gemm_mfma": (per["gemm_mfma"] * chunks, "mfma"),
+                     "gemm_valu": (per["gemm_valu"] * chunks, "alu"),
+                     "transpose": (per["transpose"] * chunks, "hbm")}
+    dom = max(prof, key=lambda kk: prof[kk][1])
+    launches, total_ms = prof[dom]
+    avg_ms = total_ms / launches
+    roof = None
+    if dom in kind_work:
+        work_total, bound = kind_work[dom]
+        per_launch = work_total * args.steps / launches
+        if bound == "hbm":
+            achieved = per_launch / (avg_ms * 1e-3) / 1e9
+            roof = dict(bound="hbm", achieved=achieved, peak=PEAK_HBM_GBS, unit="GB/s", frac=achieved / PEAK_HBM_GBS)
+        else:
+            achieved = per_launch / (avg_ms * 1e-3) / 1e12
+            roof = dict(bound=bound, achieved=achieved, peak=PEAK_FP32_TFLOPS, unit="TFLOP/s",
+                        frac=achieved / PEAK_FP32_TFLOPS)
+        roof.update(kernel=dom, avg_launch_ms=avg_ms, launches_per_step=launches / args.steps, traffic=None)
+
+    result = {
+        "metric": METRIC,
+        "value": n_bs / (ms * 1e-3),
+        "unit": "amplitudes/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.prec,
+        "data": "synthetic",
+        "config": {"workload": _workload_text(key, lat, spec, k, n_bs), "n_qubits": lat.n, "depth": spec["depth"],
+                   "log2_slices": k, "n_bitstrings": n_bs, "exec": "fused" if fused else "stepwise"},
+        "slices_per_s": n_slices * n_bs / (ms * 1e-3),
+        "tflops": flops_step / (ms * 1e-3) / 1e12,
+        "flops_per_step": flops_step,
+        "plan_seconds": plan_s,
+        "kernels": {kk: {"launches_per_step": v[0] / args.steps, "avg_ms": v[1] / v[0]} for kk, v in prof.items()},
+        "roofline": roof,
+    }
+
+    if not args.no_cpu_baseline:
+        import oracle
+        threads = int(os.environ.get("OMP_NUM_THREADS", len(os.sched_getaffinity(0))))
+        t0 = time.perf_counter()
+        psi = oracle.statevector(lat.n, circ)
+        cpu_s = time.perf_counter() - t0
+        ref = np.array([psi[oracle.index_of(x)] for x in bs])
+        mask = (1 << lat.n) * np.abs(ref) ** 2 >= 1e-2
+        rel = np.abs(amps - ref)[mask] / np.abs(ref[mask])
+        result["rel_err"] = {"max_rel": float(rel.max()), "norm_rel": float(np.linalg.norm(amps - ref) /
+                                                                             np.linalg.norm(ref)),
+                             "gate": "N|a|^2 >= 1e-2", "tol": 1e-5 if args.prec == "c64" else 1e-4}
+        result["cpu_baseline"] = {"value": n_bs / cpu_s, "unit": "amplitudes/s", "cores": threads, "kind": "oracle",
+                                  "sample": f"one FP64 state-vector run of the same circuit (2^{lat.n} entries, "
+                                            f"OpenMP C) giving all {n_bs} requested amplitudes, {cpu_s:.2f} s"}
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

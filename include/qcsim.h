@@ -140,6 +140,34 @@ qc_status qc_plan_slice_assignment(const qc_plan *plan, uint64_t s, uint8_t *out
 qc_status qc_plan_describe(qc_plan *plan, int32_t log2_batch_slices, int32_t log2_batch_bs,
                            qc_precision prec, char *buf, size_t cap, size_t *len);
 
+/* How qc_contract_slices runs the program:
+ *   QC_EXEC_AUTO (default): fused when one (slice, bitstring) contraction
+ *     fits in LDS, else stepwise;
+ *   QC_EXEC_FUSED: one launch per super-chunk, each wavefront contracting a
+ *     whole (slice, bitstring) program in LDS (QC_ERR_UNSUPPORTED later if it
+ *     does not fit);
+ *   QC_EXEC_STEPWISE: per pairwise step, an LDS-staged transpose where the
+ *     layout needs it and a batched complex GEMM, with slices and bitstrings
+ *     in flight as batch indices in global memory.
+ * Call before qc_workspace_bytes (the workspace depends on the mode). */
+enum { QC_EXEC_AUTO = 0, QC_EXEC_FUSED = 1, QC_EXEC_STEPWISE = 2 };
+qc_status qc_plan_set_exec(qc_plan *plan, int32_t mode);
+
+/* Kernel timing.  While enabled, qc_contract_slices records a pair of HIP
+ * events on its stream around every kernel it launches.  qc_profile_read
+ * waits for the recorded events, then reports per kernel kind the launch
+ * count and the summed event-to-event milliseconds since the last read (and
+ * clears them).  kinds: "fused", "leaves", "transpose", "gemm_mfma",
+ * "gemm_valu", "reduce64".  Not thread-safe across concurrent calls on one
+ * plan. */
+typedef struct {
+    char kind[16];
+    int64_t launches;
+    double total_ms;
+} qc_kernel_stat_t;
+qc_status qc_profile_enable(qc_plan *plan, int32_t on);
+qc_status qc_profile_read(qc_plan *plan, qc_kernel_stat_t *out, int32_t cap, int32_t *n);
+
 /* Device workspace (bytes) that qc_contract_slices needs to keep
  * chunk_slices slices (rounded up to a power of two) and n_bs bitstrings in
  * flight.  0 on invalid arguments. */

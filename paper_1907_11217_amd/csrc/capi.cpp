@@ -126,4 +126,14 @@ extern "C" qc_status qc_plan_describe(qc_plan *plan, int32_t log2_batch_slices, 
     return QC_OK;
 }
 
+extern "C" qc_status qc_plan_set_exec(qc_plan *plan, int32_t mode) {
+    if (!plan || mode < QC_EXEC_AUTO || mode > QC_EXEC_STEPWISE) {
+        set_error("qc_plan_set_exec: invalid argument");
+        return QC_ERR_INVALID_ARG;
+    }
+    std::lock_guard<std::mutex> lk(plan->mu);
+    plan->exec_mode = mode;
+    return QC_OK;
+}
+
 extern "C" void qc_plan_destroy(qc_plan *plan);

@@ -57,10 +57,50 @@ struct GemmDesc {
     int64_t sCb, sCm, sCn;
 };
 
+// Fused form: one wavefront runs a whole lowered program for one group of
+// 2^bf slices x 2^mf bitstrings with every tensor in LDS, contracting each
+// step directly from the operands' own layouts (no transposes).
+constexpr int kFusedMaxRank = 16;
+constexpr int kFusedMaxK = 12;
+constexpr int kFusedLdsBytes = 64 * 1024;
+struct FusedStep {
+    int32_t a_off, b_off, c_off;             // LDS element offsets
+    int32_t rc, rk;                          // log2 of C's size and of the contracted extent
+    int32_t sA[kFusedMaxRank], sB[kFusedMaxRank];   // C bit p -> element stride in A / B (0 = absent)
+    int32_t kA[kFusedMaxK], kB[kFusedMaxK];         // contracted bit j -> stride in A / B
+};
+
+struct FusedParams {
+    const FusedStep *steps;
+    int32_t n_steps;
+    const LeafDesc *leaves;                  // out_off = LDS offset, pad1 = first flat element
+    const int32_t *elem_leaf;                // flat leaf element -> leaf
+    int32_t n_elems;
+    const double2 *base;
+    const uint8_t *bits;                     // [2^m][n_qubits]
+    int32_t n_qubits;
+    int32_t bf, mf;                          // log2 slices / bitstrings per group
+    int32_t n_bs_groups;                     // 2^(m - mf)
+    int64_t first_group, n_slice_groups;    // slice groups relative to sc
+    uint64_t sc;                             // super-chunk base slice id
+    int32_t root_off, root_rank;
+    int8_t root_map[32];                     // root bit p -> slice bit j, or 64 + bitstring bit
+    float2 *partial;                         // [slice - sc][2^m]
+    int32_t m;
+    int32_t lds_elems;
+};
+
+void launch_fused(const FusedParams &p, hipStream_t st);
+// out[bs] += sum of partial over in-range slices of the super-chunk, in
+// aligned blocks of 64 slices: a fixed butterfly within each block, blocks
+// added in increasing order.
+void launch_reduce64(const float2 *partial, int m, int n_bs, uint64_t sc, int64_t n_blocks, uint64_t lo, uint64_t hi,
+                     uint64_t s_begin, double *out, double *per_slice, hipStream_t st);
+
 void launch_leaves(const LeafDesc *descs, const int32_t *block_leaf, int n_blocks, const double2 *base,
                    float2 *tensors, const uint8_t *bits, int n_qubits, uint64_t chunk_base, hipStream_t st);
 void launch_transpose(const TransposeDesc &d, hipStream_t st);
-void launch_gemm(const GemmDesc &d, hipStream_t st);
+const char *launch_gemm(const GemmDesc &d, hipStream_t st);  // returns the form launched
 void launch_reduce(const float2 *root, int b, int m, int n_bs, uint64_t chunk_base, uint64_t s_begin,
                    uint64_t s_end, double *out, double *per_slice, hipStream_t st);
 

@@ -175,7 +175,7 @@ __global__ void __launch_bounds__(64 * WM * WN) gemm_mfma_kernel(GemmDesc d) {
     }
 }
 
-void launch_gemm(const GemmDesc &d, hipStream_t st) {
+const char *launch_gemm(const GemmDesc &d, hipStream_t st) {
     // The MFMA form needs whole 32x32 tiles and a K that the LDS slab divides.
     const int64_t kt_try = d.k >= 16 ? 16 : d.k;
     const bool k_ok = (kt_try == 2 || kt_try == 4 || kt_try == 8 || kt_try == 16) && d.k % kt_try == 0;
@@ -185,7 +185,7 @@ void launch_gemm(const GemmDesc &d, hipStream_t st) {
         int64_t grid = (total + 255) / 256;
         if (grid > 262144) grid = 262144;
         hipLaunchKernelGGL(gemm_valu_kernel, dim3((unsigned)grid), dim3(256), 0, st, d);
-        return;
+        return "gemm_valu";
     }
     const int wm = d.m % 64 == 0 ? 2 : 1, wn = d.n % 64 == 0 ? 2 : 1;
     const int64_t tiles = d.nb * (d.m / (32 * wm)) * (d.n / (32 * wn));
@@ -194,7 +194,7 @@ void launch_gemm(const GemmDesc &d, hipStream_t st) {
 #define QC_GEMM_CASE(WM, WN, KT)                                                                        \
     if (wm == WM && wn == WN && kt == KT) {                                                               \
         hipLaunchKernelGGL((gemm_mfma_kernel<WM, WN, KT>), dim3(grid), dim3(64 * WM * WN), 0, st, d);     \
-        return;                                                                                          \
+        return "gemm_mfma";                                                                              \
     }
 #define QC_GEMM_KTS(WM, WN) QC_GEMM_CASE(WM, WN, 2) QC_GEMM_CASE(WM, WN, 4) QC_GEMM_CASE(WM, WN, 8) QC_GEMM_CASE(WM, WN, 16)
     QC_GEMM_KTS(1, 1)
@@ -203,6 +203,124 @@ void launch_gemm(const GemmDesc &d, hipStream_t st) {
     QC_GEMM_KTS(2, 2)
 #undef QC_GEMM_KTS
 #undef QC_GEMM_CASE
+    return "gemm_none";
+}
+
+// ------------------------------------------------------------------ fused
+__global__ void __launch_bounds__(64) fused_kernel(FusedParams P) {
+    extern __shared__ float2 lds[];
+    const int lane = threadIdx.x;
+    const int64_t n_items = P.n_slice_groups * P.n_bs_groups;
+    for (int64_t item = blockIdx.x; item < n_items; item += gridDim.x) {
+        const int64_t gsl = P.first_group + item / P.n_bs_groups;
+        const int gb = int(item % P.n_bs_groups);
+        const uint64_t slice0 = P.sc + (uint64_t(gsl) << P.bf);
+        const uint8_t *bits = P.bits + (int64_t(gb) << P.mf) * P.n_qubits;
+        for (int e = lane; e < P.n_elems; e += 64) {
+            const LeafDesc &d = P.leaves[P.elem_leaf[e]];
+            const int local = e - d.pad1;
+            int bs = 0, bidx = 0;
+            for (int p = 0; p < d.r_out; ++p) {
+                const int bit = (local >> p) & 1;
+                const int s = d.src[p];
+                if (s >= 64) bs |= bit << (s - 64);
+                else bidx |= bit << s;
+            }
+            for (int i = 0; i < d.n_fix; ++i) bidx |= int((slice0 >> d.fix_j[i]) & 1) << d.fix_pos[i];
+            for (int i = 0; i < d.n_oq; ++i) bidx |= int(bits[bs * P.n_qubits + d.oq_q[i]] & 1) << d.oq_pos[i];
+            const double2 v = P.base[d.base_off + bidx];
+            lds[d.out_off + local] = make_float2(float(v.x), float(v.y));
+        }
+        __syncthreads();
+        for (int s = 0; s < P.n_steps; ++s) {
+            const FusedStep &st = P.steps[s];
+            const int nc = 1 << st.rc, nk = 1 << st.rk;
+            for (int c = lane; c < nc; c += 64) {
+                int a = st.a_off, b = st.b_off;
+                for (int p = 0; p < st.rc; ++p)
+                    if ((c >> p) & 1) { a += st.sA[p]; b += st.sB[p]; }
+                float re = 0.f, im = 0.f;
+                for (int kk = 0; kk < nk; ++kk) {
+                    int ka = a, kb = b;
+                    for (int j = 0; j < st.rk; ++j)
+                        if ((kk >> j) & 1) { ka += st.kA[j]; kb += st.kB[j]; }
+                    const float2 x = lds[ka], y = lds[kb];
+                    re = fmaf(x.x, y.x, re);
+                    re = fmaf(-x.y, y.y, re);
+                    im = fmaf(x.x, y.y, im);
+                    im = fmaf(x.y, y.x, im);
+                }
+                lds[st.c_off + c] = make_float2(re, im);
+            }
+            __syncthreads();
+        }
+        const int nr = 1 << P.root_rank;
+        for (int c = lane; c < nr; c += 64) {
+            int64_t s_low = 0;
+            int bs_low = 0;
+            for (int p = 0; p < P.root_rank; ++p) {
+                const int bit = (c >> p) & 1;
+                const int code = P.root_map[p];
+                if (code >= 64) bs_low |= bit << (code - 64);
+                else s_low |= int64_t(bit) << code;
+            }
+            const int64_t s_rel = (gsl << P.bf) + s_low;
+            const int64_t bs = (int64_t(gb) << P.mf) + bs_low;
+            P.partial[(s_rel << P.m) + bs] = lds[P.root_off + c];
+        }
+        __syncthreads();
+    }
+}
+
+void launch_fused(const FusedParams &p, hipStream_t st) {
+    const int64_t items = p.n_slice_groups * p.n_bs_groups;
+    if (items <= 0) return;
+    const unsigned grid = (unsigned)(items < 1048576 ? items : 1048576);
+    hipLaunchKernelGGL(fused_kernel, dim3(grid), dim3(64), size_t(p.lds_elems) * sizeof(float2), st, p);
+}
+
+// --------------------------------------------------------------- reduce64
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__global__ void __launch_bounds__(64) reduce64_kernel(const float2 *__restrict__ partial, int m, int n_bs,
+                                                      uint64_t sc, int64_t n_blocks, uint64_t lo, uint64_t hi,
+                                                      uint64_t s_begin, double *__restrict__ out,
+                                                      double *__restrict__ per_slice) {
+    const int bs = blockIdx.x;
+    const int lane = threadIdx.x;
+    if (bs >= n_bs) return;
+    double acc_re = out[2 * bs], acc_im = out[2 * bs + 1];
+    for (int64_t blk = 0; blk < n_blocks; ++blk) {
+        const uint64_t b0 = sc + uint64_t(blk) * 64;
+        if (b0 + 64 <= lo || b0 >= hi) continue;
+        const uint64_t s = b0 + lane;
+        double re = 0.0, im = 0.0;
+        if (s >= lo && s < hi) {
+            const float2 v = partial[(int64_t(s - sc) << m) + bs];
+            re = double(v.x);
+            im = double(v.y);
+            if (per_slice) {
+                double *p = per_slice + 2 * (int64_t(s - s_begin) * n_bs + bs);
+                p[0] = re;
+                p[1] = im;
+            }
+        }
+        acc_re += wave_sum(re);
+        acc_im += wave_sum(im);
+    }
+    if (lane == 0) {
+        out[2 * bs] = acc_re;
+        out[2 * bs + 1] = acc_im;
+    }
+}
+
+void launch_reduce64(const float2 *partial, int m, int n_bs, uint64_t sc, int64_t n_blocks, uint64_t lo, uint64_t hi,
+                     uint64_t s_begin, double *out, double *per_slice, hipStream_t st) {
+    hipLaunchKernelGGL(reduce64_kernel, dim3(n_bs), dim3(64), 0, st, partial, m, n_bs, sc, n_blocks, lo, hi, s_begin,
+                       out, per_slice);
 }
 
 // ---------------------------------------------------------------- reduce

@@ -65,7 +65,8 @@ std::vector<int> cat(std::initializer_list<std::vector<int>> parts) {
 struct Arena {
     std::vector<std::pair<int64_t, int64_t>> free_;  // (offset, size), sorted by offset
     int64_t end = 0;
-    static int64_t align(int64_t v) { return (v + 31) & ~int64_t(31); }
+    int64_t granule = 32;  // allocation unit (elements), a power of two
+    int64_t align(int64_t v) const { return (v + granule - 1) & ~(granule - 1); }
     int64_t alloc(int64_t n) {
         n = align(std::max<int64_t>(n, 1));
         int best = -1;
@@ -210,6 +211,7 @@ static bool lower(const qc_plan *plan, int b, int m, Program &prog, std::string 
         }
         const int tc = new_tensor(cat({Ab, Am, Bn}));
         GemmOp g;
+        g.a_src = ta; g.b_src = tb;
         g.a = opA; g.b = opB; g.c = tc;
         g.cls_b = (int)Ab.size(); g.cls_m = (int)Am.size(); g.cls_n = (int)Bn.size(); g.cls_k = (int)Ak.size();
         g.nb = int64_t(1) << g.cls_b; g.m = int64_t(1) << g.cls_m; g.n = int64_t(1) << g.cls_n; g.k = int64_t(1) << g.cls_k;
@@ -228,6 +230,7 @@ static bool lower(const qc_plan *plan, int b, int m, Program &prog, std::string 
         tensor_of.push_back(tc);
     }
     int root = tensor_of.back();
+    prog.root_pre = root;
     std::vector<int> want;
     for (int j = b - 1; j >= 0; --j) want.push_back(plan->sliced[j]);
     want.insert(want.end(), bs_bits.begin(), bs_bits.end());
@@ -261,6 +264,27 @@ static bool lower(const qc_plan *plan, int b, int m, Program &prog, std::string 
             if (death[t] == (int)i) arena.release(prog.tensors[t].offset, prog.tensors[t].size());
     }
     prog.tensor_elems = arena.end;
+
+    // Fused form: GEMM steps read their operands as produced (no transposes);
+    // offsets in a separate arena sized for LDS.
+    {
+        std::vector<int> fdeath(nt, -1);
+        for (size_t i = 0; i < prog.gemms.size(); ++i) {
+            fdeath[prog.gemms[i].a_src] = (int)i;
+            fdeath[prog.gemms[i].b_src] = (int)i;
+        }
+        prog.lds_offset.assign(nt, -1);
+        Arena la;
+        la.granule = 2;
+        for (int t = 0; t < L; ++t) prog.lds_offset[t] = la.alloc(prog.tensors[t].size());
+        for (size_t i = 0; i < prog.gemms.size(); ++i) {
+            const int c = prog.gemms[i].c;
+            prog.lds_offset[c] = la.alloc(prog.tensors[c].size());
+            for (int t = 0; t < nt; ++t)
+                if (fdeath[t] == (int)i) la.release(prog.lds_offset[t], prog.tensors[t].size());
+        }
+        prog.lds_elems = la.end;
+    }
     return true;
 }
 

@@ -90,6 +90,7 @@ struct TransposeOp {
 };
 
 struct GemmOp {
+    int a_src, b_src;          // operand tensors as produced (before transposes)
     int a, b, c;               // program tensor ids after transposes
     int64_t nb, m, n, k;       // C[b][m][n] = sum_k A . B
     bool a_km;                 // A stored [b][k][m] (else [b][m][k])
@@ -110,14 +111,22 @@ struct Program {
     std::vector<GemmOp> gemms;
     std::vector<Op> ops;
     int root = -1;                        // tensor holding [slice bits][bs bits]
+    int root_pre = -1;                    // the tree's last tensor (before any final transpose)
     int64_t tensor_elems = 0;             // tensor region size (complex64 elements)
     double flops = 0, bytes = 0, transpose_bytes = 0;
+    // Fused form: the same steps without transposes, every tensor in LDS.
+    std::vector<int64_t> lds_offset;      // per program tensor (-1 if not used by the fused form)
+    int64_t lds_elems = 0;
     // Device constants, created lazily on the device current at first use.
     int device = -1;
     void *d_leaf_desc = nullptr;
     void *d_leaf_block = nullptr;
     void *d_base = nullptr;
     int n_leaf_blocks = 0;
+    void *d_fused_leaf = nullptr;         // leaf table with LDS offsets
+    void *d_fused_elem = nullptr;         // flat leaf element -> leaf id
+    void *d_fused_steps = nullptr;
+    int n_leaf_elems = 0;
 };
 
 }  // namespace qc
@@ -129,6 +138,11 @@ struct qc_plan {
     std::vector<int> sliced;              // index ids in slice-bit order
     std::vector<uint8_t> default_bitstring;
     qc_plan_info_t info{};
+    int exec_mode = QC_EXEC_AUTO;
+    // Kernel timing (qc_profile_enable): pending event pairs and their kind.
+    bool profiling = false;
+    std::vector<std::pair<std::string, std::pair<void *, void *>>> prof_pending;
+    std::vector<void *> prof_pool;
     std::mutex mu;
     std::map<std::pair<int, int>, std::unique_ptr<qc::Program>> programs;
 };

@@ -1,5 +1,19 @@
 // Device side of the C ABI: program constants, workspace layout and the
-// chunk loop of qc_contract_slices (leaves -> steps -> FP64 reduction).
+// slice loop of qc_contract_slices.
+//
+// A call covers [s_begin, s_end) in aligned super-chunks of P slices (P a
+// power of two >= 64).  Per super-chunk the slice values of every bitstring
+// are written to a partial buffer, then added to out_dev in aligned blocks of
+// 64 slices (fixed butterfly per block, blocks in increasing order), so any
+// split of a range at multiples of 64 gives bitwise the same sums.
+//
+// Two ways to produce the slice values:
+//  * fused: when every tensor of one (slice, bitstring) group fits in LDS, a
+//    single launch runs the whole program per wavefront (leaves, all steps,
+//    root) -- one launch per super-chunk;
+//  * stepwise: leaves, then per step an LDS-staged transpose (if the operand
+//    layout needs one) and a batched complex GEMM on MFMA, over 2^b slices
+//    and all bitstrings in flight in global memory.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -25,19 +39,6 @@ int ceil_log2(int64_t v) {
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
-struct WsLayout {
-    size_t bits_off, bits_bytes, tensor_off, total;
-};
-
-WsLayout ws_layout(const Program &prog, int n_qubits) {
-    WsLayout w;
-    w.bits_off = 0;
-    w.bits_bytes = align256(size_t(n_qubits) << prog.m);
-    w.tensor_off = w.bits_bytes;
-    w.total = w.tensor_off + align256(size_t(prog.tensor_elems) * sizeof(float2));
-    return w;
-}
-
 #define QC_HIP(call)                                                                  \
     do {                                                                              \
         hipError_t e_ = (call);                                                       \
@@ -47,14 +48,81 @@ WsLayout ws_layout(const Program &prog, int n_qubits) {
         }                                                                             \
     } while (0)
 
-// Uploads the program's leaf table and base values to the current device.
-bool ensure_device(const qc_plan *plan, Program &prog, std::string &err) {
-    int dev = 0;
-    QC_HIP(hipGetDevice(&dev));
-    if (prog.d_leaf_desc) {
-        if (prog.device != dev) { err = "plan was first used on another device"; return false; }
-        return true;
+// How one call executes: which program, fused or not, and the super-chunk.
+struct Exec {
+    Program *prog = nullptr;
+    bool fused = false;
+    int m = 0;          // log2 bitstrings (padded)
+    int lp = 6;         // log2 super-chunk slices
+};
+
+struct WsLayout {
+    size_t bits_off, partial_off, tensor_off, total;
+};
+
+WsLayout ws_layout(const Exec &x, int n_qubits) {
+    WsLayout w;
+    w.bits_off = 0;
+    w.partial_off = align256(size_t(n_qubits) << x.m);
+    w.tensor_off = w.partial_off + align256((size_t(1) << (x.lp + x.m)) * sizeof(float2));
+    w.total = w.tensor_off + (x.fused ? 0 : align256(size_t(x.prog->tensor_elems) * sizeof(float2)));
+    return w;
+}
+
+bool fused_fits(const Program &p) {
+    if (p.lds_elems * int64_t(sizeof(float2)) > kFusedLdsBytes) return false;
+    for (const GemmOp &g : p.gemms) {
+        const int rc = (int)p.tensors[g.c].layout.size();
+        if (rc > kFusedMaxRank || g.cls_k > kFusedMaxK) return false;
     }
+    return (int)p.tensors[p.root_pre].layout.size() <= 32;
+}
+
+// Picks the execution for a range of n_range slices with 2^m bitstrings that
+// fits ws_bytes (ws_bytes = 0: no limit, used by the workspace query with the
+// caller's chunk size in `want_lp`).
+bool choose_exec(qc_plan *plan, int m, int want_lp, size_t ws_bytes, Exec &x, std::string &err) {
+    const int k = (int)plan->sliced.size();
+    const int nq = plan->net.n_qubits;
+    x.m = m;
+    Program *pf = get_program(plan, 0, 0, err);
+    if (!pf) return false;
+    const bool fits = fused_fits(*pf);
+    if (plan->exec_mode == QC_EXEC_FUSED && !fits) {
+        err = "the fused form does not fit in LDS for this plan";
+        return false;
+    }
+    if (fits && plan->exec_mode != QC_EXEC_STEPWISE) {
+        x.prog = pf;
+        x.fused = true;
+        for (int lp = std::max(6, want_lp); lp >= 6; --lp) {
+            x.lp = lp;
+            if (ws_bytes == 0 || ws_layout(x, nq).total <= ws_bytes) return true;
+        }
+        err = "workspace too small for one block of 64 slices";
+        return false;
+    }
+    x.fused = false;
+    for (int b = std::min(k, want_lp); b >= 0; --b) {
+        Program *p = get_program(plan, b, m, err);
+        if (!p) return false;
+        x.prog = p;
+        x.lp = std::max(b, 6);
+        if (ws_bytes == 0 || ws_layout(x, nq).total <= ws_bytes) return true;
+    }
+    err = "workspace too small for one slice";
+    return false;
+}
+
+bool upload(void **dst, const void *src, size_t bytes, std::string &err) {
+    QC_HIP(hipMalloc(dst, std::max<size_t>(bytes, 16)));
+    if (bytes) QC_HIP(hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice));
+    return true;
+}
+
+// Leaf table of a program; lds = true gives LDS offsets (fused form).
+void leaf_table(const qc_plan *plan, const Program &prog, bool lds, std::vector<LeafDesc> &descs,
+                std::vector<int32_t> &block_or_elem, std::vector<double2> &base, std::string &err) {
     const Network &net = plan->net;
     std::vector<char> fixed(net.n_index(), 0);
     std::vector<int> slice_bit(net.n_index(), -1);
@@ -62,18 +130,17 @@ bool ensure_device(const qc_plan *plan, Program &prog, std::string &err) {
         slice_bit[plan->sliced[j]] = (int)j;
         if ((int)j >= prog.b) fixed[plan->sliced[j]] = 1;
     }
-    std::vector<LeafDesc> descs;
-    std::vector<int32_t> block_leaf;
-    std::vector<double2> base;
+    int32_t first_elem = 0;
     for (size_t li = 0; li < prog.leaves.size(); ++li) {
         const Tensor &T = net.leaves[prog.leaves[li].leaf];
-        const ProgTensor &pt = prog.tensors[prog.leaves[li].tensor];
+        const int tid = prog.leaves[li].tensor;
+        const ProgTensor &pt = prog.tensors[tid];
         LeafDesc d;
         std::memset(&d, 0, sizeof(d));
         const int rb = (int)T.idx.size();
         const int ro = (int)pt.layout.size();
-        if (rb > kLeafMaxBase || ro > kLeafMaxRank) { err = "leaf too large for the device table"; return false; }
-        d.out_off = pt.offset;
+        if (rb > kLeafMaxBase || ro > kLeafMaxRank) { err = "leaf too large for the device table"; return; }
+        d.out_off = lds ? prog.lds_offset[tid] : pt.offset;
         d.base_off = (int32_t)base.size();
         d.r_out = ro;
         auto base_pos = [&](int e) {
@@ -83,8 +150,7 @@ bool ensure_device(const qc_plan *plan, Program &prog, std::string &err) {
         };
         for (int p = 0; p < ro; ++p) {
             const int e = pt.layout[ro - 1 - p];
-            if (e >= kBsBase) d.src[p] = (int8_t)(64 + (e - kBsBase));
-            else d.src[p] = (int8_t)base_pos(e);
+            d.src[p] = (int8_t)(e >= kBsBase ? 64 + (e - kBsBase) : base_pos(e));
         }
         for (int j = 0; j < rb; ++j) {
             const int e = T.idx[j];
@@ -99,32 +165,83 @@ bool ensure_device(const qc_plan *plan, Program &prog, std::string &err) {
             }
         }
         for (const cplx &v : T.data) base.push_back(make_double2(v.real(), v.imag()));
-        d.pad0 = (int32_t)block_leaf.size();
-        const int64_t nblk = ((int64_t(1) << ro) + 255) / 256;
-        for (int64_t b = 0; b < nblk; ++b) block_leaf.push_back((int32_t)li);
+        if (lds) {
+            d.pad1 = first_elem;
+            for (int64_t e = 0; e < (int64_t(1) << ro); ++e) block_or_elem.push_back((int32_t)li);
+            first_elem += 1 << ro;
+        } else {
+            d.pad0 = (int32_t)block_or_elem.size();
+            const int64_t nblk = ((int64_t(1) << ro) + 255) / 256;
+            for (int64_t b = 0; b < nblk; ++b) block_or_elem.push_back((int32_t)li);
+        }
         descs.push_back(d);
     }
-    void *a = nullptr, *b = nullptr, *c = nullptr;
-    QC_HIP(hipMalloc(&a, std::max<size_t>(1, descs.size() * sizeof(LeafDesc))));
-    if (hipMalloc(&b, std::max<size_t>(1, block_leaf.size() * sizeof(int32_t))) != hipSuccess ||
-        hipMalloc(&c, std::max<size_t>(1, base.size() * sizeof(double2))) != hipSuccess) {
-        hipFree(a);
-        if (b) hipFree(b);
-        err = "hipMalloc of program constants failed";
-        return false;
-    }
-    if (hipMemcpy(a, descs.data(), descs.size() * sizeof(LeafDesc), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(b, block_leaf.data(), block_leaf.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(c, base.data(), base.size() * sizeof(double2), hipMemcpyHostToDevice) != hipSuccess) {
-        hipFree(a); hipFree(b); hipFree(c);
-        err = "upload of program constants failed";
-        return false;
-    }
-    prog.d_leaf_desc = a;
-    prog.d_leaf_block = b;
-    prog.d_base = c;
-    prog.n_leaf_blocks = (int)block_leaf.size();
+}
+
+// Strides of index e in a layout (0 if absent).
+int32_t stride_in(const std::vector<int> &layout, int e) {
+    const int r = (int)layout.size();
+    for (int i = 0; i < r; ++i)
+        if (layout[i] == e) return int32_t(1) << (r - 1 - i);
+    return 0;
+}
+
+// Uploads the program's constants to the current device (once).
+bool ensure_device(const qc_plan *plan, Program &prog, bool fused, std::string &err) {
+    int dev = 0;
+    QC_HIP(hipGetDevice(&dev));
+    if (prog.device >= 0 && prog.device != dev) { err = "plan was first used on another device"; return false; }
     prog.device = dev;
+    if (!fused && !prog.d_leaf_desc) {
+        std::vector<LeafDesc> descs;
+        std::vector<int32_t> blocks;
+        std::vector<double2> base;
+        leaf_table(plan, prog, false, descs, blocks, base, err);
+        if (!err.empty()) return false;
+        if (!upload(&prog.d_leaf_block, blocks.data(), blocks.size() * 4, err) ||
+            (!prog.d_base && !upload(&prog.d_base, base.data(), base.size() * sizeof(double2), err)) ||
+            !upload(&prog.d_leaf_desc, descs.data(), descs.size() * sizeof(LeafDesc), err))
+            return false;
+        prog.n_leaf_blocks = (int)blocks.size();
+    }
+    if (fused && !prog.d_fused_steps) {
+        std::vector<LeafDesc> descs;
+        std::vector<int32_t> elems;
+        std::vector<double2> base;
+        leaf_table(plan, prog, true, descs, elems, base, err);
+        if (!err.empty()) return false;
+        std::vector<FusedStep> steps;
+        for (const GemmOp &g : prog.gemms) {
+            const auto &LA = prog.tensors[g.a_src].layout, &LB = prog.tensors[g.b_src].layout;
+            const auto &LC = prog.tensors[g.c].layout;
+            FusedStep st;
+            std::memset(&st, 0, sizeof(st));
+            st.a_off = (int32_t)prog.lds_offset[g.a_src];
+            st.b_off = (int32_t)prog.lds_offset[g.b_src];
+            st.c_off = (int32_t)prog.lds_offset[g.c];
+            st.rc = (int32_t)LC.size();
+            for (int p = 0; p < st.rc; ++p) {
+                const int e = LC[st.rc - 1 - p];
+                st.sA[p] = stride_in(LA, e);
+                st.sB[p] = stride_in(LB, e);
+            }
+            int j = 0;
+            for (int e : LA)
+                if (std::find(LC.begin(), LC.end(), e) == LC.end()) {
+                    st.kA[j] = stride_in(LA, e);
+                    st.kB[j] = stride_in(LB, e);
+                    ++j;
+                }
+            st.rk = j;
+            steps.push_back(st);
+        }
+        if (!upload(&prog.d_fused_elem, elems.data(), elems.size() * 4, err) ||
+            !upload(&prog.d_fused_leaf, descs.data(), descs.size() * sizeof(LeafDesc), err) ||
+            (!prog.d_base && !upload(&prog.d_base, base.data(), base.size() * sizeof(double2), err)) ||
+            !upload(&prog.d_fused_steps, steps.data(), steps.size() * sizeof(FusedStep), err))
+            return false;
+        prog.n_leaf_elems = (int)elems.size();
+    }
     return true;
 }
 
@@ -184,46 +301,124 @@ GemmDesc make_gemm(const Program &prog, const GemmOp &g, float2 *tensors) {
     return d;
 }
 
-}  // namespace
+// Event pair around each launch while the plan's kernel timing is on.
+struct Prof {
+    qc_plan *plan;
+    hipStream_t st;
+    void *e0 = nullptr;
+    void *event() {
+        if (!plan->prof_pool.empty()) {
+            void *e = plan->prof_pool.back();
+            plan->prof_pool.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        hipEventCreate(&e);
+        return (void *)e;
+    }
+    void begin() {
+        if (!plan->profiling) return;
+        e0 = event();
+        hipEventRecord((hipEvent_t)e0, st);
+    }
+    void end(const char *kind) {
+        if (!plan->profiling) return;
+        void *e1 = event();
+        hipEventRecord((hipEvent_t)e1, st);
+        plan->prof_pending.push_back({kind, {e0, e1}});
+    }
+};
 
-void free_program_device(Program &prog) {
-    if (!prog.d_leaf_desc) return;
-    int cur = 0;
-    hipGetDevice(&cur);
-    hipSetDevice(prog.device);
-    hipFree(prog.d_leaf_desc);
-    hipFree(prog.d_leaf_block);
-    hipFree(prog.d_base);
-    hipSetDevice(cur);
-    prog.d_leaf_desc = prog.d_leaf_block = prog.d_base = nullptr;
-}
-
-static bool enqueue(qc_plan *plan, Program &prog, uint64_t s_begin, uint64_t s_end, const uint8_t *bits_host,
-                    int n_bs, void *ws, size_t ws_bytes, hipStream_t st, double *out_dev, double *per_slice_dev,
-                    std::string &err) {
-    if (!ensure_device(plan, prog, err)) return false;
+bool enqueue(qc_plan *plan, const Exec &x, uint64_t s_begin, uint64_t s_end, const uint8_t *bits_host, int n_bs,
+             void *ws, hipStream_t st, double *out_dev, double *per_slice_dev, std::string &err) {
+    Program &prog = *x.prog;
+    Prof prof{plan, st};
+    if (!ensure_device(plan, prog, x.fused, err)) return false;
     const int nq = plan->net.n_qubits;
-    const WsLayout w = ws_layout(prog, nq);
-    if (w.total > ws_bytes) { err = "workspace too small"; return false; }
+    const WsLayout w = ws_layout(x, nq);
     uint8_t *bits = (uint8_t *)ws + w.bits_off;
+    float2 *partial = (float2 *)((char *)ws + w.partial_off);
     float2 *tensors = (float2 *)((char *)ws + w.tensor_off);
     const size_t used = size_t(n_bs) * nq;
     QC_HIP(hipMemcpyAsync(bits, bits_host, used, hipMemcpyHostToDevice, st));
-    if ((size_t(nq) << prog.m) > used)
-        QC_HIP(hipMemsetAsync(bits + used, 0, (size_t(nq) << prog.m) - used, st));
-    const uint64_t chunk = uint64_t(1) << prog.b;
-    for (uint64_t cb = s_begin & ~(chunk - 1); cb < s_end; cb += chunk) {
-        launch_leaves((const LeafDesc *)prog.d_leaf_desc, (const int32_t *)prog.d_leaf_block, prog.n_leaf_blocks,
-                      (const double2 *)prog.d_base, tensors, bits, nq, cb, st);
-        for (const Op &op : prog.ops) {
-            if (op.kind == Op::TRANSPOSE) launch_transpose(make_transpose(prog, prog.transposes[op.index], tensors), st);
-            else launch_gemm(make_gemm(prog, prog.gemms[op.index], tensors), st);
+    if ((size_t(nq) << x.m) > used) QC_HIP(hipMemsetAsync(bits + used, 0, (size_t(nq) << x.m) - used, st));
+    const uint64_t P = uint64_t(1) << x.lp;
+    for (uint64_t sc = s_begin & ~(P - 1); sc < s_end; sc += P) {
+        const uint64_t lo = std::max(s_begin, sc), hi = std::min(s_end, sc + P);
+        if (x.fused) {
+            FusedParams fp;
+            std::memset(&fp, 0, sizeof(fp));
+            fp.steps = (const FusedStep *)prog.d_fused_steps;
+            fp.n_steps = (int32_t)prog.gemms.size();
+            fp.leaves = (const LeafDesc *)prog.d_fused_leaf;
+            fp.elem_leaf = (const int32_t *)prog.d_fused_elem;
+            fp.n_elems = prog.n_leaf_elems;
+            fp.base = (const double2 *)prog.d_base;
+            fp.bits = bits;
+            fp.n_qubits = nq;
+            fp.bf = prog.b;
+            fp.mf = prog.m;
+            fp.m = x.m;
+            fp.n_bs_groups = 1 << (x.m - prog.m);
+            const int64_t g0 = int64_t(lo - sc) >> prog.b;
+            const int64_t g1 = (int64_t(hi - sc) + (int64_t(1) << prog.b) - 1) >> prog.b;
+            fp.first_group = g0;
+            fp.n_slice_groups = g1 - g0;
+            fp.sc = sc;
+            const auto &LR = prog.tensors[prog.root_pre].layout;
+            fp.root_off = (int32_t)prog.lds_offset[prog.root_pre];
+            fp.root_rank = (int32_t)LR.size();
+            for (int p = 0; p < fp.root_rank; ++p) {
+                const int e = LR[fp.root_rank - 1 - p];
+                if (e >= kBsBase) fp.root_map[p] = (int8_t)(64 + (e - kBsBase));
+                else fp.root_map[p] = (int8_t)(std::find(plan->sliced.begin(), plan->sliced.end(), e) - plan->sliced.begin());
+            }
+            fp.partial = partial;
+            fp.lds_elems = (int32_t)prog.lds_elems;
+            prof.begin();
+            launch_fused(fp, st);
+            prof.end("fused");
+        } else {
+            const uint64_t chunk = uint64_t(1) << prog.b;
+            for (uint64_t cb = lo & ~(chunk - 1); cb < hi; cb += chunk) {
+                prof.begin();
+                launch_leaves((const LeafDesc *)prog.d_leaf_desc, (const int32_t *)prog.d_leaf_block,
+                              prog.n_leaf_blocks, (const double2 *)prog.d_base, tensors, bits, nq, cb, st);
+                prof.end("leaves");
+                for (const Op &op : prog.ops) {
+                    prof.begin();
+                    if (op.kind == Op::TRANSPOSE) {
+                        launch_transpose(make_transpose(prog, prog.transposes[op.index], tensors), st);
+                        prof.end("transpose");
+                    } else {
+                        prof.end(launch_gemm(make_gemm(prog, prog.gemms[op.index], tensors), st));
+                    }
+                }
+                QC_HIP(hipMemcpyAsync(partial + ((cb - sc) << x.m), tensors + prog.tensors[prog.root].offset,
+                                      (size_t(1) << (prog.b + x.m)) * sizeof(float2), hipMemcpyDeviceToDevice, st));
+            }
         }
-        launch_reduce(tensors + prog.tensors[prog.root].offset, prog.b, prog.m, n_bs, cb, s_begin, s_end, out_dev,
-                      per_slice_dev, st);
+        prof.begin();
+        launch_reduce64(partial, x.m, n_bs, sc, int64_t(P / 64), lo, hi, s_begin, out_dev, per_slice_dev, st);
+        prof.end("reduce64");
         QC_HIP(hipGetLastError());
     }
     return true;
+}
+
+}  // namespace
+
+void free_program_device(Program &prog) {
+    if (prog.device < 0) return;
+    int cur = 0;
+    hipGetDevice(&cur);
+    hipSetDevice(prog.device);
+    for (void **p : {&prog.d_leaf_desc, &prog.d_leaf_block, &prog.d_base, &prog.d_fused_leaf, &prog.d_fused_elem,
+                     &prog.d_fused_steps}) {
+        if (*p) hipFree(*p);
+        *p = nullptr;
+    }
+    hipSetDevice(cur);
 }
 
 }  // namespace qc
@@ -235,28 +430,26 @@ static bool check_bitstrings(const qc_plan *plan, const uint8_t *bits, int n_bs)
     return true;
 }
 
+static bool valid_prec(qc_precision p) { return p == QC_C64 || p == QC_SPLIT_BF16 || p == QC_SPLIT_FP16; }
+
 extern "C" size_t qc_workspace_bytes(qc_plan *plan, int64_t chunk_slices, int32_t n_bs, qc_precision prec) {
-    if (!plan || chunk_slices < 1 || n_bs < 1 || n_bs > (1 << qc::kMaxBsBits) ||
-        (prec != QC_C64 && prec != QC_SPLIT_BF16 && prec != QC_SPLIT_FP16)) {
+    if (!plan || chunk_slices < 1 || n_bs < 1 || n_bs > (1 << qc::kMaxBsBits) || !valid_prec(prec)) {
         set_error("qc_workspace_bytes: invalid argument");
         return 0;
     }
     const int b = qc::ceil_log2(chunk_slices);
     if (b > (int)plan->sliced.size()) { set_error("qc_workspace_bytes: more slices than the plan has"); return 0; }
     std::string err;
-    qc::Program *prog = qc::get_program(plan, b, qc::ceil_log2(n_bs), err);
-    if (!prog) { set_error("qc_workspace_bytes: " + err); return 0; }
-    return qc::ws_layout(*prog, plan->net.n_qubits).total;
+    qc::Exec x;
+    if (!qc::choose_exec(plan, qc::ceil_log2(n_bs), b, 0, x, err)) { set_error("qc_workspace_bytes: " + err); return 0; }
+    return qc::ws_layout(x, plan->net.n_qubits).total;
 }
 
 extern "C" qc_status qc_contract_slices(qc_plan *plan, uint64_t s_begin, uint64_t s_end, const uint8_t *bitstrings,
                                         int32_t n_bs, qc_precision prec, void *ws, size_t ws_bytes, void *stream,
                                         double *out_dev, double *per_slice_dev) {
     if (!plan || !bitstrings || !ws || !out_dev) { set_error("qc_contract_slices: NULL argument"); return QC_ERR_INVALID_ARG; }
-    if (prec != QC_C64 && prec != QC_SPLIT_BF16 && prec != QC_SPLIT_FP16) {
-        set_error("qc_contract_slices: invalid precision");
-        return QC_ERR_INVALID_ARG;
-    }
+    if (!valid_prec(prec)) { set_error("qc_contract_slices: invalid precision"); return QC_ERR_INVALID_ARG; }
     if (prec != QC_C64) { set_error("qc_contract_slices: split precision is not built yet"); return QC_ERR_UNSUPPORTED; }
     if (n_bs < 1 || n_bs > (1 << qc::kMaxBsBits)) { set_error("qc_contract_slices: n_bs out of range"); return QC_ERR_RANGE; }
     const int k = (int)plan->sliced.size();
@@ -264,17 +457,14 @@ extern "C" qc_status qc_contract_slices(qc_plan *plan, uint64_t s_begin, uint64_
     if (s_begin > s_end || s_end > n_slices) { set_error("qc_contract_slices: slice range out of bounds"); return QC_ERR_RANGE; }
     if (!check_bitstrings(plan, bitstrings, n_bs)) { set_error("qc_contract_slices: bitstring entries must be 0 or 1"); return QC_ERR_INVALID_ARG; }
     if (s_begin == s_end) return QC_OK;
-    const int m = qc::ceil_log2(n_bs);
     std::string err;
-    qc::Program *prog = nullptr;
-    for (int b = std::min(k, qc::ceil_log2((int64_t)(s_end - s_begin))); b >= 0; --b) {
-        qc::Program *p = qc::get_program(plan, b, m, err);
-        if (!p) { set_error("qc_contract_slices: " + err); return QC_ERR_UNSUPPORTED; }
-        if (qc::ws_layout(*p, plan->net.n_qubits).total <= ws_bytes) { prog = p; break; }
+    qc::Exec x;
+    const int want = std::min(k, qc::ceil_log2((int64_t)(s_end - s_begin)));
+    if (!qc::choose_exec(plan, qc::ceil_log2(n_bs), want, ws_bytes, x, err)) {
+        set_error("qc_contract_slices: " + err);
+        return err.find("workspace") != std::string::npos ? QC_ERR_NOMEM : QC_ERR_UNSUPPORTED;
     }
-    if (!prog) { set_error("qc_contract_slices: workspace too small for one slice"); return QC_ERR_NOMEM; }
-    if (!qc::enqueue(plan, *prog, s_begin, s_end, bitstrings, n_bs, ws, ws_bytes, (hipStream_t)stream, out_dev,
-                     per_slice_dev, err)) {
+    if (!qc::enqueue(plan, x, s_begin, s_end, bitstrings, n_bs, ws, (hipStream_t)stream, out_dev, per_slice_dev, err)) {
         set_error("qc_contract_slices: " + err);
         return QC_ERR_DEVICE;
     }
@@ -294,8 +484,7 @@ extern "C" qc_status qc_amplitude(qc_plan *plan, const uint8_t *bitstring, qc_pr
         if (need == 0) return QC_ERR_UNSUPPORTED;
         if (need <= cap) break;
     }
-    if (b < 0) b = 0;
-    need = qc_workspace_bytes(plan, int64_t(1) << b, 1, prec);
+    if (b < 0) need = qc_workspace_bytes(plan, 1, 1, prec);
     void *ws = nullptr, *out = nullptr;
     if (hipMalloc(&ws, need) != hipSuccess) { set_error("qc_amplitude: workspace allocation failed"); return QC_ERR_NOMEM; }
     if (hipMalloc(&out, 2 * sizeof(double)) != hipSuccess) { hipFree(ws); set_error("qc_amplitude: allocation failed"); return QC_ERR_NOMEM; }
@@ -319,8 +508,46 @@ extern "C" qc_status qc_amplitude(qc_plan *plan, const uint8_t *bitstring, qc_pr
     return st;
 }
 
+extern "C" qc_status qc_profile_enable(qc_plan *plan, int32_t on) {
+    if (!plan) { set_error("qc_profile_enable: NULL plan"); return QC_ERR_INVALID_ARG; }
+    plan->profiling = on != 0;
+    return QC_OK;
+}
+
+extern "C" qc_status qc_profile_read(qc_plan *plan, qc_kernel_stat_t *out, int32_t cap, int32_t *n) {
+    if (!plan || !n || cap < 0 || (cap > 0 && !out)) { set_error("qc_profile_read: invalid argument"); return QC_ERR_INVALID_ARG; }
+    std::vector<qc_kernel_stat_t> stats;
+    qc_status st = QC_OK;
+    for (auto &pe : plan->prof_pending) {
+        float ms = 0.f;
+        if (hipEventSynchronize((hipEvent_t)pe.second.second) != hipSuccess ||
+            hipEventElapsedTime(&ms, (hipEvent_t)pe.second.first, (hipEvent_t)pe.second.second) != hipSuccess) {
+            set_error("qc_profile_read: event query failed");
+            st = QC_ERR_DEVICE;
+        }
+        qc_kernel_stat_t *s = nullptr;
+        for (auto &x : stats)
+            if (pe.first == x.kind) s = &x;
+        if (!s) {
+            stats.push_back(qc_kernel_stat_t{});
+            s = &stats.back();
+            std::strncpy(s->kind, pe.first.c_str(), sizeof(s->kind) - 1);
+        }
+        s->launches += 1;
+        s->total_ms += ms;
+        plan->prof_pool.push_back(pe.second.first);
+        plan->prof_pool.push_back(pe.second.second);
+    }
+    plan->prof_pending.clear();
+    *n = (int32_t)stats.size();
+    for (int32_t i = 0; i < std::min<int32_t>(cap, *n); ++i) out[i] = stats[i];
+    return st;
+}
+
 extern "C" void qc_plan_destroy(qc_plan *plan) {
     if (!plan) return;
+    for (auto &pe : plan->prof_pending) plan->prof_pool.push_back(pe.second.first), plan->prof_pool.push_back(pe.second.second);
+    for (void *e : plan->prof_pool) hipEventDestroy((hipEvent_t)e);
     for (auto &kv : plan->programs) qc::free_program_device(*kv.second);
     delete plan;
 }

@@ -28,7 +28,9 @@ EXPORTED = (
     "qc_plan_build", "qc_plan_info", "qc_plan_sliced_segments", "qc_plan_slice_assignment",
     "qc_plan_describe", "qc_workspace_bytes", "qc_contract_slices", "qc_amplitude",
     "qc_gate_matrix", "qc_plan_destroy", "qc_last_error", "qc_kernel_gemm", "qc_kernel_transpose",
+    "qc_plan_set_exec", "qc_profile_enable", "qc_profile_read",
 )
+EXEC_MODES = {"auto": 0, "fused": 1, "stepwise": 2}
 
 
 class QcError(RuntimeError):
@@ -64,6 +66,10 @@ class qc_plan_info_t(ctypes.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+class qc_kernel_stat_t(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_char * 16), ("launches", ctypes.c_int64), ("total_ms", ctypes.c_double)]
+
+
 _lib = None
 
 
@@ -83,6 +89,8 @@ def load(path: str | None = None):
     lib.qc_plan_slice_assignment.argtypes = [vp, ctypes.c_uint64, vp]
     lib.qc_plan_describe.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int, vp, sz, ctypes.POINTER(sz)]
     lib.qc_gate_matrix.argtypes = [ctypes.c_int32, vp]
+    lib.qc_plan_set_exec.argtypes = [vp, ctypes.c_int32]
+    lib.qc_plan_set_exec.restype = ctypes.c_int
     lib.qc_plan_destroy.argtypes = [vp]
     lib.qc_plan_destroy.restype = None
     lib.qc_last_error.restype = ctypes.c_char_p
@@ -102,6 +110,11 @@ def load(path: str | None = None):
         lib.qc_kernel_gemm.restype = ctypes.c_int
         lib.qc_kernel_transpose.argtypes = [vp, vp, ctypes.c_int32, vp, vp]
         lib.qc_kernel_transpose.restype = ctypes.c_int
+        lib.qc_profile_enable.argtypes = [vp, ctypes.c_int32]
+        lib.qc_profile_enable.restype = ctypes.c_int
+        lib.qc_profile_read.argtypes = [vp, ctypes.POINTER(qc_kernel_stat_t), ctypes.c_int32,
+                                        ctypes.POINTER(ctypes.c_int32)]
+        lib.qc_profile_read.restype = ctypes.c_int
     if path is None:
         _lib = lib
     return lib
@@ -194,6 +207,23 @@ def qc_plan_describe(plan: Plan, log2_batch_slices: int = 0, log2_batch_bs: int 
     return json.loads(buf.value.decode())
 
 
+def qc_plan_set_exec(plan: Plan, mode) -> None:
+    m = EXEC_MODES[mode] if isinstance(mode, str) else int(mode)
+    _check(plan._lib.qc_plan_set_exec(plan.handle, m), plan._lib)
+
+
+def qc_profile_enable(plan: Plan, on: bool = True) -> None:
+    _check(plan._lib.qc_profile_enable(plan.handle, int(bool(on))), plan._lib)
+
+
+def qc_profile_read(plan: Plan) -> dict:
+    """{kind: (launches, total_ms)} since the last read (waits for the events)."""
+    stats = (qc_kernel_stat_t * 32)()
+    n = ctypes.c_int32()
+    _check(plan._lib.qc_profile_read(plan.handle, stats, 32, ctypes.byref(n)), plan._lib)
+    return {stats[i].kind.decode(): (int(stats[i].launches), float(stats[i].total_ms)) for i in range(n.value)}
+
+
 def qc_gate_matrix(kind: int, lib=None) -> np.ndarray:
     lib = lib or load()
     out = np.zeros(32, dtype=np.float64)
@@ -203,7 +233,10 @@ def qc_gate_matrix(kind: int, lib=None) -> np.ndarray:
 
 
 def qc_workspace_bytes(plan: Plan, chunk_slices: int, n_bs: int, prec="c64") -> int:
-    return int(plan._lib.qc_workspace_bytes(plan.handle, int(chunk_slices), int(n_bs), _prec(prec)))
+    n = int(plan._lib.qc_workspace_bytes(plan.handle, int(chunk_slices), int(n_bs), _prec(prec)))
+    if n == 0:
+        raise QcError(1, plan._lib.qc_last_error().decode())
+    return n
 
 
 def qc_contract_slices(plan: Plan, s_begin: int, s_end: int, bitstrings, prec, ws, out_dev,

@@ -50,26 +50,33 @@ def test_p2_hadamard_layers_gpu():
     assert np.abs(got - ref).max() <= 1e-7
 
 
+MODES = ["fused", "stepwise"]
+
+
+@pytest.mark.parametrize("mode", MODES)
 @pytest.mark.parametrize("shape,depth,seed", [((2, 2), 8, 1), ((2, 3), 8, 2), ((3, 3), 8, 3)])
-def test_p6_unitarity_all_amplitudes(shape, depth, seed):
+def test_p6_unitarity_all_amplitudes(shape, depth, seed, mode):
     lat = synth.grid(*shape)
     circ = synth.random_circuit(lat, depth, seed)
     xs = np.array(list(np.ndindex(*([2] * lat.n))), dtype=np.uint8)
     plan = qcsim.qc_plan_build(lat.n, circ, None, log2_slices=2, greedy_trials=2)
-    say(f"P6 unitarity {shape} d{depth}")
+    qcsim.qc_plan_set_exec(plan, mode)
+    say(f"P6 unitarity {shape} d{depth} {mode}")
     got = _contract(plan, xs, 0, 4)
     assert abs(np.sum(np.abs(got) ** 2) - 1) <= 1e-5
     psi = oracle.statevector(lat.n, circ)
     check_amplitudes(got, psi, lat.n, TOL_C64)
 
 
-def test_c1_amplitudes():
+@pytest.mark.parametrize("mode", MODES)
+def test_c1_amplitudes(mode):
     lat, circ, bs, _ = synth.config("c1")
     xs = np.concatenate([bs, synth.random_bitstrings(lat.n, 255, 1001)])
     plan = qcsim.qc_plan_build(lat.n, circ, bs[0])
+    qcsim.qc_plan_set_exec(plan, mode)
     psi = oracle.statevector(lat.n, circ)
     ref = np.array([psi[oracle.index_of(x)] for x in xs])
-    say("c1 4x4 d10, 256 bitstrings, unsliced")
+    say(f"c1 4x4 d10, 256 bitstrings, unsliced, {mode}")
     got = _contract(plan, xs, 0, 1)
     info = check_amplitudes(got, ref, lat.n, TOL_C64)
     print("c1", info)
@@ -94,19 +101,23 @@ def c2_setup():
     return lat, circ, bs, plan, ref
 
 
-def test_c2_amplitudes_c64(c2_setup):
+@pytest.mark.parametrize("mode", MODES)
+def test_c2_amplitudes_c64(c2_setup, mode):
     lat, circ, bs, plan, ref = c2_setup
     assert qcsim.qc_plan_info(plan)["log2_slices"] == 6
-    say("c2 5x5 d16, 64 bitstrings x 64 slices, c64")
+    qcsim.qc_plan_set_exec(plan, mode)
+    say(f"c2 5x5 d16, 64 bitstrings x 64 slices, c64, {mode}")
     got = _contract(plan, bs, 0, 64)
     info = check_amplitudes(got, ref, lat.n, TOL_C64)
     print("c2", info)
 
 
-def test_c2_per_slice_values_match_oracle(c2_setup):
+@pytest.mark.parametrize("mode", MODES)
+def test_c2_per_slice_values_match_oracle(c2_setup, mode):
     lat, circ, bs, plan, _ref = c2_setup
+    qcsim.qc_plan_set_exec(plan, mode)
     segs = [tuple(int(v) for v in s) for s in qcsim.qc_plan_sliced_segments(plan)]
-    say("c2 per-slice values")
+    say(f"c2 per-slice values, {mode}")
     amps, ps = _contract(plan, bs[:8], 0, 64, per_slice=True)
     assert np.abs(ps.sum(axis=0) - amps).max() <= 1e-15 + 1e-12 * np.abs(amps).max()
     vals = np.abs(ps).ravel()
@@ -116,37 +127,53 @@ def test_c2_per_slice_values_match_oracle(c2_setup):
         assert abs(ps[s, j] - v) <= TOL_C64 * max(abs(v), scale), (s, j, ps[s, j], v)
 
 
-def test_c2_ranges_compose_and_repeat(c2_setup):
-    lat, circ, bs, plan, ref = c2_setup
-    ws_bytes = qcsim.qc_workspace_bytes(plan, 16, len(bs))
-    say("c2 ranges [0,64) vs [0,32)+[32,64), chunk 16")
-    whole = _contract(plan, bs, 0, 64, ws_bytes=ws_bytes)
-    again = _contract(plan, bs, 0, 64, ws_bytes=ws_bytes)
+@pytest.mark.parametrize("mode", MODES)
+def test_ranges_compose_and_repeat(c2_setup, mode):
+    # Slices are summed in aligned blocks of 64; splits at multiples of 64
+    # compose bitwise, other splits to rounding.
+    lat, circ, bs, _plan, ref = c2_setup
+    plan = qcsim.qc_plan_build(lat.n, circ, bs[0], log2_slices=8, greedy_trials=2, seed=5)
+    qcsim.qc_plan_set_exec(plan, mode)
+    xs = bs[:16]
+    ws_bytes = qcsim.qc_workspace_bytes(plan, 64, len(xs))
+    say("c2 circuit, 256 slices: [0,256) vs [0,128)+[128,256) vs [0,100)+[100,256)")
+    whole = _contract(plan, xs, 0, 256, ws_bytes=ws_bytes)
+    again = _contract(plan, xs, 0, 256, ws_bytes=ws_bytes)
     assert np.array_equal(whole, again)  # bitwise reproducible
+    big = _contract(plan, xs, 0, 256)    # different super-chunk size, same 64-blocks
+    assert np.array_equal(whole, big)
     ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
-    out = torch.zeros(len(bs), 2, dtype=torch.float64, device="cuda")
-    qcsim.qc_contract_slices(plan, 0, 32, bs, "c64", ws, out)
-    qcsim.qc_contract_slices(plan, 32, 64, bs, "c64", ws, out)
+    out = torch.zeros(len(xs), 2, dtype=torch.float64, device="cuda")
+    qcsim.qc_contract_slices(plan, 0, 128, xs, "c64", ws, out)
+    qcsim.qc_contract_slices(plan, 128, 256, xs, "c64", ws, out)
     torch.cuda.synchronize()
     o = out.cpu().numpy()
-    split = o[:, 0] + 1j * o[:, 1]
-    # Chunk-aligned split: the same per-chunk sums, added in the same order.
-    assert np.array_equal(split, whole)
-    # Unaligned split: equal to rounding.
+    assert np.array_equal(o[:, 0] + 1j * o[:, 1], whole)
     out.zero_()
-    qcsim.qc_contract_slices(plan, 0, 21, bs, "c64", ws, out)
-    qcsim.qc_contract_slices(plan, 21, 64, bs, "c64", ws, out)
+    qcsim.qc_contract_slices(plan, 0, 100, xs, "c64", ws, out)
+    qcsim.qc_contract_slices(plan, 100, 256, xs, "c64", ws, out)
     torch.cuda.synchronize()
     o = out.cpu().numpy()
-    assert np.abs((o[:, 0] + 1j * o[:, 1]) - whole).max() <= 1e-15
-    check_amplitudes(whole, ref, lat.n, TOL_C64)
+    assert np.abs((o[:, 0] + 1j * o[:, 1]) - whole).max() <= 1e-12 * np.abs(whole).max()
+    check_amplitudes(whole, ref[:16], lat.n, TOL_C64)
 
 
-def test_workspace_too_small(c2_setup):
+@pytest.mark.parametrize("mode", MODES)
+def test_workspace_too_small(c2_setup, mode):
     lat, circ, bs, plan, _ref = c2_setup
+    qcsim.qc_plan_set_exec(plan, mode)
     need = qcsim.qc_workspace_bytes(plan, 1, len(bs))
     ws = torch.empty(max(need // 2, 1), dtype=torch.uint8, device="cuda")
     out = torch.zeros(len(bs), 2, dtype=torch.float64, device="cuda")
     with pytest.raises(qcsim.QcError) as e:
         qcsim.qc_contract_slices(plan, 0, 64, bs, "c64", ws, out)
     assert e.value.status == 3
+
+
+def test_fused_mode_rejected_when_too_large():
+    lat, circ, bs, _ = synth.config("c3")
+    plan = qcsim.qc_plan_build(lat.n, circ, bs[0], log2_slices=0)
+    qcsim.qc_plan_set_exec(plan, "fused")
+    with pytest.raises(qcsim.QcError) as e:
+        qcsim.qc_workspace_bytes(plan, 1, 1)
+    assert "does not fit" in str(e.value)

@@ -27,7 +27,7 @@ def _plan(key_or_lat, circ=None, **kw):
 
 def test_library_exports_every_declared_symbol():
     declared = set()
-    for h in ("qcsim.h", "qcsim_kernels.h"):
+    for h in ("qcsim.h", "qcsim_kernels.h"):  # every declared entry point
         hdr = open(os.path.join(ROOT, "include", h)).read()
         declared |= set(re.findall(r"\b(qc_[a-z_]+)\s*\(", hdr))
     lib = qcsim.load()
