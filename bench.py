@@ -109,8 +109,10 @@ def main():
 
     # Algorithmic work (the lowered program's own per-step shapes).
     fused = "fused" in prof
+    result_extra = {}
     if fused:
         desc = qcsim.qc_plan_describe(plan, 0, 0)
+        result_extra = {"fused_pairs_per_wave": desc["fused_pairs"], "fused_tuning_ms": desc["fused_tuning"]}
         pairs_per_launch = n_slices * (1 << max(0, int(np.ceil(np.log2(n_bs)))))
         flops_step = desc["flops"] * n_slices * n_bs
         kind_work = {"fused": (desc["flops"] * pairs_per_launch, "alu")}
@@ -175,6 +177,7 @@ def main():
         "kernels": {kk: {"launches_per_step": v[0] / args.steps, "avg_ms": v[1] / v[0]} for kk, v in prof.items()},
         "roofline": roof,
     }
+    result.update(result_extra)
 
     if not args.no_cpu_baseline:
         import oracle

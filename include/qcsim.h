@@ -109,6 +109,10 @@ typedef struct {
     double flops_unsliced;      /* same order, no slicing */
     double peak_live_bytes;     /* peak live complex64 bytes, one slice, one bitstring */
     double plan_seconds;        /* host time spent in qc_plan_build */
+    int32_t n_folded_steps;     /* steps whose value is the same for every slice and bitstring,
+                                   computed once in qc_plan_build (not counted in n_steps or
+                                   flops_per_slice) */
+    int32_t reserved;
 } qc_plan_info_t;
 
 /* circuit + bitstring + slice set -> contraction plan (host only).

@@ -57,40 +57,54 @@ struct GemmDesc {
     int64_t sCb, sCm, sCn;
 };
 
-// Fused form: one wavefront runs a whole lowered program for one group of
-// 2^bf slices x 2^mf bitstrings with every tensor in LDS, contracting each
-// step directly from the operands' own layouts (no transposes).
-constexpr int kFusedMaxRank = 16;
-constexpr int kFusedMaxK = 12;
-constexpr int kFusedLdsBytes = 64 * 1024;
+// Fused form: one wavefront runs the whole program of one (slice, bitstring)
+// pair with every tensor in LDS, contracting each step directly from the
+// operands' own layouts (no transposes).  Operand addressing is table-driven:
+// per step, pool[tab + c] packs the LDS offsets of A and B for output c
+// (low/high 16 bits) and pool[tab + 2^rc + j] the offsets added for the j-th
+// value of the contracted indices.
+constexpr int kFusedLdsBytes = 64 * 1024;     // LDS offsets then fit in 16 bits
 struct FusedStep {
-    int32_t a_off, b_off, c_off;             // LDS element offsets
+    int32_t c_off;                           // LDS offset of C (within one pair's region)
     int32_t rc, rk;                          // log2 of C's size and of the contracted extent
-    int32_t sA[kFusedMaxRank], sB[kFusedMaxRank];   // C bit p -> element stride in A / B (0 = absent)
-    int32_t kA[kFusedMaxK], kB[kFusedMaxK];         // contracted bit j -> stride in A / B
+    int32_t tab;                             // start of this step's entries in the pool
+    int32_t k[4];                            // the first 4 contracted offsets (also in the pool)
 };
 
 struct FusedParams {
     const FusedStep *steps;
     int32_t n_steps;
-    const LeafDesc *leaves;                  // out_off = LDS offset, pad1 = first flat element
-    const int32_t *elem_leaf;                // flat leaf element -> leaf
+    const int32_t *pool;                     // padded with 8 zeros at the end
+    const float2 *leaf_image;                // LDS [0, n_image): leaf values that do not depend on the pair
+    int32_t n_image;
+    const int4 *elems;                       // run-time leaf elements: (LDS slot, base index, dyn0, dyn1)
     int32_t n_elems;
     const double2 *base;
     const uint8_t *bits;                     // [2^m][n_qubits]
     int32_t n_qubits;
-    int32_t bf, mf;                          // log2 slices / bitstrings per group
-    int32_t n_bs_groups;                     // 2^(m - mf)
-    int64_t first_group, n_slice_groups;    // slice groups relative to sc
+    int32_t m;                               // log2 bitstrings (rows of bits / partial)
+    int64_t first_slice, n_slices;           // slices relative to sc
     uint64_t sc;                             // super-chunk base slice id
-    int32_t root_off, root_rank;
-    int8_t root_map[32];                     // root bit p -> slice bit j, or 64 + bitstring bit
+    int32_t root_off;
     float2 *partial;                         // [slice - sc][2^m]
-    int32_t m;
     int32_t lds_elems;
 };
 
-void launch_fused(const FusedParams &p, hipStream_t st);
+// The scalar part of FusedParams, passed by value next to the tables (which
+// go as separate read-only kernel arguments so that uniform reads of them
+// become scalar loads).
+struct FusedScalars {
+    int32_t n_steps, n_pool, n_image, n_elems, n_qubits, m, root_off, pair_elems;
+    int64_t first_slice, n_slices;
+    uint64_t sc;
+};
+
+// Pairs per wavefront the fused kernel is built for; the runtime times them
+// on first use of a program and keeps the fastest.
+constexpr int kFusedPairsOptions[] = {1, 2, 4, 8};
+size_t fused_lds_bytes(int pairs, int pair_elems, int n_pool);
+void launch_fused_pairs(const FusedParams &p, int pairs, int pair_elems, int n_pool, hipStream_t st);
+
 // out[bs] += sum of partial over in-range slices of the super-chunk, in
 // aligned blocks of 64 slices: a fixed butterfly within each block, blocks
 // added in increasing order.

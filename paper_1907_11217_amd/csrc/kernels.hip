@@ -207,76 +207,173 @@ const char *launch_gemm(const GemmDesc &d, hipStream_t st) {
 }
 
 // ------------------------------------------------------------------ fused
-__global__ void __launch_bounds__(64) fused_kernel(FusedParams P) {
+// One work item = one (slice, bitstring) pair, one wavefront.  Leaves are
+// written into LDS from the base table (each element picks its base entry from
+// its own index plus at most two bits taken from the slice id or the
+// bitstring), then every step computes its outputs from table-driven LDS
+// offsets, and lane 0 stores the rank-0 root.
+// A run-time bit of a leaf element, 16-bit code: base bit position in the low
+// 3 bits, source above it (slice bit j < 64, or 64 + qubit of the bitstring);
+// 0xffff = none.  Two codes per 32-bit word.
+__device__ __forceinline__ int dyn_bit(uint32_t code, uint64_t slice, const uint8_t *row) {
+    if (code == 0xffffu) return 0;
+    const int src = int(code >> 3);
+    const int bit = src < 64 ? int((slice >> src) & 1) : int(row[src - 64] & 1);
+    return bit << (code & 7u);
+}
+
+__device__ __forceinline__ int dyn_bits(int z, int w, uint64_t slice, const uint8_t *row) {
+    return dyn_bit(uint32_t(z) & 0xffffu, slice, row) + dyn_bit(uint32_t(z) >> 16, slice, row) +
+           dyn_bit(uint32_t(w) & 0xffffu, slice, row) + dyn_bit(uint32_t(w) >> 16, slice, row);
+}
+
+__device__ __forceinline__ float2 contract_one(const float2 *lds, int a, int b, const int32_t *kt, int nk) {
+    float re = 0.f, im = 0.f;
+    for (int kk = 0; kk < nk; ++kk) {
+        const uint32_t kab = uint32_t(kt[kk]);
+        const float2 x = lds[a + int(kab & 0xffffu)];
+        const float2 y = lds[b + int(kab >> 16)];
+        re = fmaf(x.x, y.x, re);
+        re = fmaf(-x.y, y.y, re);
+        im = fmaf(x.x, y.y, im);
+        im = fmaf(x.y, y.x, im);
+    }
+    return make_float2(re, im);
+}
+
+// Same for a compile-time contracted extent: all LDS reads are issued before
+// the multiply-adds.
+template <int NK>
+__device__ __forceinline__ float2 contract_fixed(const float2 *lds, int a, int b, const int32_t *__restrict__ kt) {
+    float2 x[NK], y[NK];
+#pragma unroll
+    for (int i = 0; i < NK; ++i) {
+        const uint32_t u = uint32_t(kt[i]);
+        x[i] = lds[a + int(u & 0xffffu)];
+        y[i] = lds[b + int(u >> 16)];
+    }
+    float re = 0.f, im = 0.f;
+#pragma unroll
+    for (int i = 0; i < NK; ++i) {
+        re = fmaf(x[i].x, y[i].x, re);
+        re = fmaf(-x[i].y, y[i].y, re);
+        im = fmaf(x[i].x, y[i].y, im);
+        im = fmaf(x[i].y, y[i].x, im);
+    }
+    return make_float2(re, im);
+}
+
+// The fused kernel's workgroup is a single wavefront, whose LDS accesses are
+// performed in issue order.  Between steps it is therefore enough that the
+// compiler keeps LDS accesses on their side of the boundary (a wavefront-scope
+// fence); a workgroup barrier would also wait for the global loads that
+// prefetch the next step's tables.
+__device__ __forceinline__ void wave_step_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// One wavefront runs PAIRS (slice, bitstring) pairs through the same step
+// stream, each pair in its own LDS region of pair_elems values; the step
+// headers (one scalar load each) and the LDS-resident offset table are shared,
+// so their scalar work is paid once per PAIRS pairs.  For a step with 2^rc
+// outputs, lane l works on pair l >> rc, output l & (2^rc - 1).
+template <int PAIRS>
+__global__ void __launch_bounds__(64)
+fused_kernel(const FusedStep *__restrict__ steps, const int32_t *__restrict__ pool,
+             const float2 *__restrict__ image, const int4 *__restrict__ elems, const double2 *__restrict__ base,
+             const uint8_t *__restrict__ bits, float2 *__restrict__ partial, FusedScalars S) {
     extern __shared__ float2 lds[];
+    int32_t *tab = reinterpret_cast<int32_t *>(lds + PAIRS * S.pair_elems);
     const int lane = threadIdx.x;
-    const int64_t n_items = P.n_slice_groups * P.n_bs_groups;
-    for (int64_t item = blockIdx.x; item < n_items; item += gridDim.x) {
-        const int64_t gsl = P.first_group + item / P.n_bs_groups;
-        const int gb = int(item % P.n_bs_groups);
-        const uint64_t slice0 = P.sc + (uint64_t(gsl) << P.bf);
-        const uint8_t *bits = P.bits + (int64_t(gb) << P.mf) * P.n_qubits;
-        for (int e = lane; e < P.n_elems; e += 64) {
-            const LeafDesc &d = P.leaves[P.elem_leaf[e]];
-            const int local = e - d.pad1;
-            int bs = 0, bidx = 0;
-            for (int p = 0; p < d.r_out; ++p) {
-                const int bit = (local >> p) & 1;
-                const int s = d.src[p];
-                if (s >= 64) bs |= bit << (s - 64);
-                else bidx |= bit << s;
-            }
-            for (int i = 0; i < d.n_fix; ++i) bidx |= int((slice0 >> d.fix_j[i]) & 1) << d.fix_pos[i];
-            for (int i = 0; i < d.n_oq; ++i) bidx |= int(bits[bs * P.n_qubits + d.oq_q[i]] & 1) << d.oq_pos[i];
-            const double2 v = P.base[d.base_off + bidx];
-            lds[d.out_off + local] = make_float2(float(v.x), float(v.y));
+    for (int i = lane; i < S.n_pool; i += 64) tab[i] = pool[i];
+    const int n_bs = 1 << S.m;
+    const int64_t n_pairs = S.n_slices << S.m;
+    const int64_t n_groups = (n_pairs + PAIRS - 1) / PAIRS;
+    for (int64_t g = blockIdx.x; g < n_groups; g += gridDim.x) {
+        // Leaves of every pair: the pair-independent values in one coalesced
+        // copy, then the elements whose base entry depends on slice or
+        // bitstring bits.  A group past the last pair repeats the last pair.
+        for (int p = 0; p < PAIRS; ++p) {
+            float2 *L = lds + p * S.pair_elems;
+            for (int e = lane; e < S.n_image; e += 64) L[e] = image[e];
         }
-        __syncthreads();
-        for (int s = 0; s < P.n_steps; ++s) {
-            const FusedStep &st = P.steps[s];
-            const int nc = 1 << st.rc, nk = 1 << st.rk;
-            for (int c = lane; c < nc; c += 64) {
-                int a = st.a_off, b = st.b_off;
-                for (int p = 0; p < st.rc; ++p)
-                    if ((c >> p) & 1) { a += st.sA[p]; b += st.sB[p]; }
-                float re = 0.f, im = 0.f;
-                for (int kk = 0; kk < nk; ++kk) {
-                    int ka = a, kb = b;
-                    for (int j = 0; j < st.rk; ++j)
-                        if ((kk >> j) & 1) { ka += st.kA[j]; kb += st.kB[j]; }
-                    const float2 x = lds[ka], y = lds[kb];
-                    re = fmaf(x.x, y.x, re);
-                    re = fmaf(-x.y, y.y, re);
-                    im = fmaf(x.x, y.y, im);
-                    im = fmaf(x.y, y.x, im);
+        wave_step_sync();
+        for (int p = 0; p < PAIRS; ++p) {
+            const int64_t pair = min(g * PAIRS + p, n_pairs - 1);
+            const uint64_t slice = S.sc + uint64_t(S.first_slice + (pair >> S.m));
+            const uint8_t *row = bits + int64_t(pair & (n_bs - 1)) * S.n_qubits;
+            float2 *L = lds + p * S.pair_elems;
+            for (int e = lane; e < S.n_elems; e += 64) {
+                const int4 t = elems[e];
+                const double2 v = base[t.y + dyn_bits(t.z, t.w, slice, row)];
+                L[t.x] = make_float2(float(v.x), float(v.y));
+            }
+        }
+        wave_step_sync();
+        for (int s = 0; s < S.n_steps; ++s) {
+            const FusedStep h = steps[s];
+            const int nc = 1 << h.rc;
+            for (int pc = lane; pc < (PAIRS << h.rc); pc += 64) {
+                const int p = pc >> h.rc, c = pc & (nc - 1);
+                const uint32_t u = uint32_t(tab[h.tab + c]);
+                const int po = p * S.pair_elems;
+                const int a = po + int(u & 0xffffu), b = po + int(u >> 16);
+                float2 v;
+                switch (h.rk) {
+                case 0: v = contract_fixed<1>(lds, a, b, h.k); break;
+                case 1: v = contract_fixed<2>(lds, a, b, h.k); break;
+                case 2: v = contract_fixed<4>(lds, a, b, h.k); break;
+                default: v = contract_one(lds, a, b, tab + h.tab + nc, 1 << h.rk);
                 }
-                lds[st.c_off + c] = make_float2(re, im);
+                lds[po + h.c_off + c] = v;
             }
-            __syncthreads();
+            wave_step_sync();
         }
-        const int nr = 1 << P.root_rank;
-        for (int c = lane; c < nr; c += 64) {
-            int64_t s_low = 0;
-            int bs_low = 0;
-            for (int p = 0; p < P.root_rank; ++p) {
-                const int bit = (c >> p) & 1;
-                const int code = P.root_map[p];
-                if (code >= 64) bs_low |= bit << (code - 64);
-                else s_low |= int64_t(bit) << code;
-            }
-            const int64_t s_rel = (gsl << P.bf) + s_low;
-            const int64_t bs = (int64_t(gb) << P.mf) + bs_low;
-            P.partial[(s_rel << P.m) + bs] = lds[P.root_off + c];
+        if (lane < PAIRS && g * PAIRS + lane < n_pairs) {
+            const int64_t pair = g * PAIRS + lane;
+            const int64_t s_rel = S.first_slice + (pair >> S.m);
+            partial[(s_rel << S.m) + (pair & (n_bs - 1))] = lds[lane * S.pair_elems + S.root_off];
         }
-        __syncthreads();
+        wave_step_sync();
     }
 }
 
-void launch_fused(const FusedParams &p, hipStream_t st) {
-    const int64_t items = p.n_slice_groups * p.n_bs_groups;
-    if (items <= 0) return;
-    const unsigned grid = (unsigned)(items < 1048576 ? items : 1048576);
-    hipLaunchKernelGGL(fused_kernel, dim3(grid), dim3(64), size_t(p.lds_elems) * sizeof(float2), st, p);
+size_t fused_lds_bytes(int pairs, int pair_elems, int n_pool) {
+    return size_t(pairs) * pair_elems * sizeof(float2) + size_t(n_pool) * sizeof(int32_t);
+}
+
+void launch_fused_pairs(const FusedParams &p, int pairs, int pair_elems, int n_pool, hipStream_t st) {
+    const int64_t n_pairs = p.n_slices << p.m;
+    if (n_pairs <= 0) return;
+    const int64_t groups = (n_pairs + pairs - 1) / pairs;
+    const unsigned grid = (unsigned)(groups < 1048576 ? groups : 1048576);
+    FusedScalars S;
+    S.n_steps = p.n_steps;
+    S.n_pool = n_pool;
+    S.n_image = p.n_image;
+    S.n_elems = p.n_elems;
+    S.n_qubits = p.n_qubits;
+    S.m = p.m;
+    S.root_off = p.root_off;
+    S.pair_elems = pair_elems;
+    S.first_slice = p.first_slice;
+    S.n_slices = p.n_slices;
+    S.sc = p.sc;
+    const size_t lds = fused_lds_bytes(pairs, pair_elems, n_pool);
+#define QC_FUSED_CASE(N)                                                                                      \
+    case N:                                                                                                   \
+        hipLaunchKernelGGL(fused_kernel<N>, dim3(grid), dim3(64), lds, st, p.steps, p.pool, p.leaf_image,      \
+                           p.elems, p.base, p.bits, p.partial, S);                                            \
+        break;
+    switch (pairs) {
+        QC_FUSED_CASE(1)
+        QC_FUSED_CASE(2)
+        QC_FUSED_CASE(4)
+        QC_FUSED_CASE(8)
+    default: break;
+    }
+#undef QC_FUSED_CASE
 }
 
 // --------------------------------------------------------------- reduce64

@@ -343,12 +343,17 @@ std::string describe_program(const qc_plan *plan, const Program &prog) {
             o << "{\"op\":\"transpose\",\"src\":" << t.src << ",\"dst\":" << t.dst << '}';
         } else {
             const GemmOp &g = prog.gemms[op.index];
-            o << "{\"op\":\"gemm\",\"a\":" << g.a << ",\"b\":" << g.b << ",\"c\":" << g.c << ",\"nb\":" << g.nb
+            o << "{\"op\":\"gemm\",\"a\":" << g.a << ",\"b\":" << g.b << ",\"a_src\":" << g.a_src
+              << ",\"b_src\":" << g.b_src << ",\"c\":" << g.c << ",\"nb\":" << g.nb
               << ",\"m\":" << g.m << ",\"n\":" << g.n << ",\"k\":" << g.k << ",\"a_km\":" << (g.a_km ? 1 : 0)
               << ",\"b_nk\":" << (g.b_nk ? 1 : 0) << '}';
         }
     }
-    o << "],\"root\":" << prog.root << ",\"tensor_elems\":" << prog.tensor_elems << ",\"flops\":" << prog.flops
+    o << "],\"fused_pairs\":" << prog.fused_pairs << ",\"fused_tuning\":[";
+    for (size_t i = 0; i < prog.fused_tuning.size(); ++i)
+        o << (i ? "," : "") << '[' << prog.fused_tuning[i].first << ',' << prog.fused_tuning[i].second << ']';
+    o << "],\"root\":" << prog.root << ",\"tensor_elems\":" << prog.tensor_elems << ",\"lds_elems\":" << prog.lds_elems
+      << ",\"flops\":" << prog.flops
       << ",\"bytes\":" << prog.bytes << ",\"transpose_bytes\":" << prog.transpose_bytes << '}';
     return o.str();
 }

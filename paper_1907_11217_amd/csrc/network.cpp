@@ -87,7 +87,7 @@ bool build_network(const qc_circuit &c, Network &net, std::string &err) {
 }
 
 // C = sum over `contracted` of A * B, with C's indices in the order given.
-static Tensor contract_host(const Tensor &A, const Tensor &B, const std::vector<int> &c_idx,
+Tensor contract_host(const Tensor &A, const Tensor &B, const std::vector<int> &c_idx,
                             const std::vector<int> &contracted) {
     std::vector<int> all = c_idx;
     all.insert(all.end(), contracted.begin(), contracted.end());
@@ -120,8 +120,15 @@ static Tensor contract_host(const Tensor &A, const Tensor &B, const std::vector<
 // than the larger of the two (this absorbs vectors, collapses chains of 2x2
 // tensors and folds tensors whose indices are a subset of a neighbour's).
 // Output segments and the indices in `keep` (caller-chosen slices) are never
-// summed here.  Exact in FP64.
+// summed here.  Sizes are counted without output segments, which are fixed per
+// bitstring when leaves are instantiated; a merged tensor keeps at most
+// kMaxLeafBase indices in all.  Exact in FP64.
 void simplify_network(Network &net, const std::vector<int> &keep) {
+    auto eff = [&](const std::vector<int> &idx) {
+        int r = 0;
+        for (int f : idx) r += net.out_qubit[f] < 0;
+        return r;
+    };
     std::vector<Tensor> &T = net.leaves;
     std::vector<char> alive(T.size(), 1);
     std::vector<std::set<int>> holders(net.n_index());
@@ -147,7 +154,8 @@ void simplify_network(Network &net, const std::vector<int> &keep) {
                                                 std::find(keep.begin(), keep.end(), f) == keep.end();
                             (closes ? contracted : c_idx).push_back(f);
                         }
-                    if (c_idx.size() > std::max(T[a].idx.size(), T[b].idx.size())) continue;
+                    if (eff(c_idx) > std::max(eff(T[a].idx), eff(T[b].idx)) || (int)c_idx.size() > kMaxLeafBase)
+                        continue;
                     Tensor C = contract_host(T[a], T[b], c_idx, contracted);
                     for (int f : T[a].idx) holders[f].erase((int)a);
                     for (int f : T[b].idx) holders[f].erase(b);

@@ -44,6 +44,15 @@ std::vector<int> sorted_union(const std::vector<int> &a, const std::vector<int> 
 
 std::vector<Merge> greedy_order(const OrderProblem &p, const std::vector<char> &removed,
                                 uint64_t seed, double temperature) {
+    return greedy_order_phased(p, removed, seed, temperature, nullptr, 0);
+}
+
+// With `dynamic` set: a first phase merges only pairs of tensors that are both
+// free of dynamic leaves (sliced or output indices) while the result keeps at
+// most `const_cap` indices, so that the pair-invariant part of the network
+// ends up in subtrees of its own; then the plain greedy finishes.
+std::vector<Merge> greedy_order_phased(const OrderProblem &p, const std::vector<char> &removed, uint64_t seed,
+                                       double temperature, const std::vector<char> *dynamic, int const_cap) {
     const int L = (int)p.leaf_idx.size();
     std::vector<std::vector<int>> sets;
     sets.reserve(2 * L);
@@ -79,16 +88,25 @@ std::vector<Merge> greedy_order(const OrderProblem &p, const std::vector<char> &
         }
         return r;
     };
+    std::vector<char> is_dyn(L, 0);
+    if (dynamic)
+        for (int t = 0; t < L; ++t) is_dyn[t] = (*dynamic)[t];
+    bool phase1 = dynamic != nullptr;
     auto push = [&](int a, int b) {
         if (a > b) std::swap(a, b);
+        const int rc = result_rank(a, b);
+        if (phase1 && (is_dyn[a] || is_dyn[b] || rc > const_cap)) return;
         const double sa = std::ldexp(1.0, (int)sets[a].size()), sb = std::ldexp(1.0, (int)sets[b].size());
-        double key = std::ldexp(1.0, result_rank(a, b)) - sa - sb;
+        double key = std::ldexp(1.0, rc) - sa - sb;
         if (temperature > 0) key -= temperature * (sa + sb) * rng.gumbel();
         heap.push(Cand{key, a, b});
     };
-    for (int e = 0; e < p.n_index; ++e)
-        for (size_t i = 0; i < holders[e].size(); ++i)
-            for (size_t j = i + 1; j < holders[e].size(); ++j) push(holders[e][i], holders[e][j]);
+    auto push_all = [&]() {
+        for (int e = 0; e < p.n_index; ++e)
+            for (size_t i = 0; i < holders[e].size(); ++i)
+                for (size_t j = i + 1; j < holders[e].size(); ++j) push(holders[e][i], holders[e][j]);
+    };
+    push_all();
 
     std::vector<Merge> tree;
     int n_alive = L;
@@ -109,22 +127,28 @@ std::vector<Merge> greedy_order(const OrderProblem &p, const std::vector<char> &
         sets.push_back(std::move(c));
         alive[a] = alive[b] = 0;
         alive.push_back(1);
+        is_dyn.push_back(is_dyn[a] || is_dyn[b]);
         tree.push_back(Merge{a, b});
         --n_alive;
         return id;
     };
-    while (!heap.empty()) {
-        Cand cd = heap.top();
-        heap.pop();
-        if (!alive[cd.a] || !alive[cd.b]) continue;
-        const int id = do_merge(cd.a, cd.b);
-        std::vector<int> nbr;
-        for (int e : sets[id])
-            for (int d : holders[e])
-                if (d != id) nbr.push_back(d);
-        std::sort(nbr.begin(), nbr.end());
-        nbr.erase(std::unique(nbr.begin(), nbr.end()), nbr.end());
-        for (int d : nbr) push(id, d);
+    for (;;) {
+        while (!heap.empty()) {
+            Cand cd = heap.top();
+            heap.pop();
+            if (!alive[cd.a] || !alive[cd.b]) continue;
+            const int id = do_merge(cd.a, cd.b);
+            std::vector<int> nbr;
+            for (int e : sets[id])
+                for (int d : holders[e])
+                    if (d != id) nbr.push_back(d);
+            std::sort(nbr.begin(), nbr.end());
+            nbr.erase(std::unique(nbr.begin(), nbr.end()), nbr.end());
+            for (int d : nbr) push(id, d);
+        }
+        if (!phase1) break;
+        phase1 = false;
+        push_all();
     }
     // Disconnected pieces: fold the two smallest until one tensor is left.
     while (n_alive > 1) {
@@ -244,6 +268,108 @@ static bool choose_slices(const OrderProblem &p, const std::vector<Merge> &tree,
     }
 }
 
+// Largest pair-invariant intermediate folded on the host (log2 entries).
+constexpr int kFoldMaxLog2 = 14;
+
+// Per-(slice, bitstring) flops of a tree once its foldable pair-invariant
+// subtrees are precomputed.
+static double per_pair_flops(const OrderProblem &p, const std::vector<Merge> &tree,
+                             const std::vector<char> &removed, const std::vector<char> &dyn_leaf) {
+    std::vector<std::vector<int>> sets, unions;
+    node_sets(p, tree, removed, sets, unions);
+    const int L = (int)p.leaf_idx.size();
+    std::vector<char> dyn(dyn_leaf.begin(), dyn_leaf.end());
+    double f = 0;
+    for (size_t i = 0; i < tree.size(); ++i) {
+        const bool d = dyn[tree[i].a] || dyn[tree[i].b];
+        dyn.push_back(d);
+        if (d || (int)sets[L + i].size() > kFoldMaxLog2) f += 8.0 * std::ldexp(1.0, (int)unions[i].size());
+    }
+    return f;
+}
+
+// Replaces every maximal pair-invariant subtree (no dynamic leaf, result of
+// at most 2^kFoldMaxLog2 entries) by one leaf computed here in FP64 -- the
+// paper's preprocessing, done once per circuit for all slices and bitstrings.
+static void fold_invariant_subtrees(qc_plan *plan, const std::vector<char> &dyn_leaf) {
+    OrderProblem &p = plan->prob;
+    const int L = (int)p.leaf_idx.size();
+    const int M = (int)plan->tree.size();
+    std::vector<char> removed(p.n_index, 0);
+    for (int e : plan->sliced) removed[e] = 1;
+    std::vector<std::vector<int>> sets, unions;
+    node_sets(p, plan->tree, removed, sets, unions);
+    std::vector<char> foldable(L + M, 0), cst(L + M, 0);
+    for (int t = 0; t < L; ++t) cst[t] = !dyn_leaf[t];
+    std::vector<int> parent(L + M, -1);
+    for (int i = 0; i < M; ++i) {
+        const int n = L + i;
+        const int a = plan->tree[i].a, b = plan->tree[i].b;
+        cst[n] = cst[a] && cst[b];
+        // Every node of a folded subtree must be small, so the host work stays
+        // bounded (2^|union| products per step).
+        foldable[n] = cst[n] && (int)sets[n].size() <= kFoldMaxLog2 && (int)unions[i].size() <= kFoldMaxLog2 + 4 &&
+                      (a < L || foldable[a]) && (b < L || foldable[b]);
+        parent[plan->tree[i].a] = parent[plan->tree[i].b] = n;
+    }
+    std::vector<char> top(L + M, 0), inside(L + M, 0);
+    for (int n = L + M - 1; n >= L; --n) {
+        if (!foldable[n]) continue;
+        if (parent[n] >= 0 && (foldable[parent[n]] || inside[parent[n]])) inside[n] = 1;
+        else top[n] = 1;
+    }
+    // Children of folded nodes are inside as well.
+    for (int n = L + M - 1; n >= L; --n)
+        if (top[n] || inside[n]) inside[plan->tree[n - L].a] = inside[plan->tree[n - L].b] = 1;
+    bool any = false;
+    for (int n = L; n < L + M; ++n) any |= top[n];
+    if (!any) return;
+    // Host values of the folded nodes (post-order).
+    std::vector<Tensor> val(L + M);
+    std::vector<char> have(L + M, 0);
+    for (int t = 0; t < L; ++t)
+        if (inside[t]) { val[t] = plan->net.leaves[t]; have[t] = 1; }
+    for (int i = 0; i < M; ++i) {
+        const int n = L + i;
+        if (!(inside[n] || top[n])) continue;
+        const int a = plan->tree[i].a, b = plan->tree[i].b;
+        std::vector<int> contracted;
+        for (int e : unions[i])
+            if (!std::binary_search(sets[n].begin(), sets[n].end(), e)) contracted.push_back(e);
+        val[n] = contract_host(val[a], val[b], sets[n], contracted);
+        have[n] = 1;
+        val[a] = Tensor();
+        val[b] = Tensor();
+    }
+    std::vector<Tensor> leaves;
+    std::vector<std::vector<int>> leaf_idx;
+    std::vector<int> new_id(L + M, -1);
+    for (int t = 0; t < L; ++t)
+        if (!inside[t]) {
+            new_id[t] = (int)leaves.size();
+            leaves.push_back(plan->net.leaves[t]);
+            leaf_idx.push_back(p.leaf_idx[t]);
+        }
+    for (int n = L; n < L + M; ++n)
+        if (top[n]) {
+            new_id[n] = (int)leaves.size();
+            leaves.push_back(std::move(val[n]));
+            leaf_idx.push_back(sets[n]);
+        }
+    const int L2 = (int)leaves.size();
+    std::vector<Merge> tree;
+    for (int i = 0; i < M; ++i) {
+        const int n = L + i;
+        if (inside[n] || top[n]) continue;
+        tree.push_back(Merge{new_id[plan->tree[i].a], new_id[plan->tree[i].b]});
+        new_id[n] = L2 + (int)tree.size() - 1;
+    }
+    plan->info.n_folded_steps = M - (int)tree.size();
+    plan->net.leaves = std::move(leaves);
+    p.leaf_idx = std::move(leaf_idx);
+    plan->tree = std::move(tree);
+}
+
 bool search_plan(qc_plan *plan, const qc_slice_spec *spec, std::string &err) {
     const OrderProblem &p = plan->prob;
     const int k_target = spec ? spec->log2_slices : 0;
@@ -291,8 +417,14 @@ bool search_plan(qc_plan *plan, const qc_slice_spec *spec, std::string &err) {
         }
     }
     if (!have) {
-        err = "cannot meet a cap of 2^" + std::to_string(cap) + " entries; smallest largest-intermediate found 2^" +
-              std::to_string(best_ach);
+        int n_sliceable = 0;
+        for (char c : sliceable) n_sliceable += c;
+        if (kt > n_sliceable)
+            err = "asked for " + std::to_string(kt) + " slice bits but the simplified network has only " +
+                  std::to_string(n_sliceable) + " sliceable indices";
+        else
+            err = "cannot meet a cap of 2^" + std::to_string(cap) + " entries; smallest largest-intermediate found 2^" +
+                  std::to_string(best_ach);
         return false;
     }
     // Re-search the order on the sliced network; keep it if it is cheaper
@@ -305,15 +437,39 @@ bool search_plan(qc_plan *plan, const qc_slice_spec *spec, std::string &err) {
         const TreeCost c = tree_cost(p, tree, rm);
         if ((cap <= 0 || c.max_log2 <= cap) && c.flops < bc.flops) { bc = c; best_tree = tree; }
     }
+    const TreeCost c0 = tree_cost(p, best_tree, std::vector<char>(p.n_index, 0));
+    plan->info.flops_unsliced = c0.flops;
+
+    // Pair-invariant work: a leaf is dynamic if it holds a sliced or an output
+    // segment; every other subtree has the same value for all (slice,
+    // bitstring) pairs.  Try constant-first orders and keep the one with the
+    // least per-pair work, then fold its invariant subtrees on the host.
+    std::vector<char> dyn_leaf(p.leaf_idx.size(), 0);
+    for (size_t t = 0; t < p.leaf_idx.size(); ++t) {
+        for (int e : plan->net.leaves[t].idx)
+            if (plan->net.out_qubit[e] >= 0 || rm[e]) dyn_leaf[t] = 1;
+    }
+    double best_dev = per_pair_flops(p, best_tree, rm, dyn_leaf);
+    const int const_cap = std::max(4, (int)bc.max_log2);
+    for (int t = 0; t < trials; ++t) {
+        std::vector<Merge> tree = greedy_order_phased(p, rm, seed + 0x5000 + 0x1000 * t,
+                                                      t == 0 ? 0.0 : 0.1 + 0.05 * (t % 8), &dyn_leaf, const_cap);
+        const TreeCost c = tree_cost(p, tree, rm);
+        if (cap > 0 && c.max_log2 > cap) continue;
+        const double dev = per_pair_flops(p, tree, rm, dyn_leaf);
+        if (dev < best_dev) { best_dev = dev; best_tree = tree; }
+    }
     plan->tree = best_tree;
     plan->sliced = best_sliced;
-    const TreeCost c0 = tree_cost(p, best_tree, std::vector<char>(p.n_index, 0));
+    fold_invariant_subtrees(plan, dyn_leaf);
+    std::vector<char> rm2(plan->prob.n_index, 0);
+    for (int e : plan->sliced) rm2[e] = 1;
+    const TreeCost cf = tree_cost(plan->prob, plan->tree, rm2);
     plan->info.log2_slices = (int)best_sliced.size();
-    plan->info.log2_max_entries = bc.max_log2;
-    plan->info.flops_per_slice = bc.flops;
-    plan->info.bytes_per_slice = bc.bytes;
-    plan->info.flops_unsliced = c0.flops;
-    plan->info.peak_live_bytes = bc.peak_live;
+    plan->info.log2_max_entries = cf.max_log2;
+    plan->info.flops_per_slice = cf.flops;
+    plan->info.bytes_per_slice = cf.bytes;
+    plan->info.peak_live_bytes = cf.peak_live;
     (void)last_ach;
     return true;
 }

@@ -23,6 +23,7 @@ namespace qc {
 using cplx = std::complex<double>;
 
 constexpr int kMaxRank = 40;       // largest tensor rank a program may hold
+constexpr int kMaxLeafBase = 4;    // indices of a simplified leaf, output segments included
 constexpr int kMaxBsBits = 16;     // bitstrings in flight <= 65536
 
 // A tensor over binary indices; data is row-major with idx[0] the most
@@ -46,6 +47,9 @@ struct Network {
 // indices (fixed per bitstring at instantiation) and input segments fixed to 0.
 bool build_network(const qc_circuit &c, Network &net, std::string &err);
 void simplify_network(Network &net, const std::vector<int> &keep);
+// C = sum over `contracted` of A * B, with C's indices in the order c_idx (FP64, host).
+Tensor contract_host(const Tensor &A, const Tensor &B, const std::vector<int> &c_idx,
+                     const std::vector<int> &contracted);
 
 // One pairwise merge: tensors a, b -> a new tensor (ids: leaves first, then
 // merges in order).
@@ -67,6 +71,8 @@ struct OrderProblem {
 
 std::vector<Merge> greedy_order(const OrderProblem &p, const std::vector<char> &removed,
                                 uint64_t seed, double temperature);
+std::vector<Merge> greedy_order_phased(const OrderProblem &p, const std::vector<char> &removed, uint64_t seed,
+                                       double temperature, const std::vector<char> *dynamic, int const_cap);
 TreeCost tree_cost(const OrderProblem &p, const std::vector<Merge> &tree,
                    const std::vector<char> &removed);
 
@@ -123,10 +129,15 @@ struct Program {
     void *d_leaf_block = nullptr;
     void *d_base = nullptr;
     int n_leaf_blocks = 0;
-    void *d_fused_leaf = nullptr;         // leaf table with LDS offsets
-    void *d_fused_elem = nullptr;         // flat leaf element -> leaf id
-    void *d_fused_steps = nullptr;
+    void *d_fused_image = nullptr;        // leaf values that do not depend on the (slice, bitstring) pair
+    int n_image = 0;
+    void *d_fused_elems = nullptr;        // run-time leaf elements: LDS slot, base index, dynamic bits
+    void *d_fused_pool = nullptr;         // per step: operand offsets per output, then per contracted value
+    void *d_fused_steps = nullptr;        // per step header
     int n_leaf_elems = 0;
+    int n_pool = 0;                       // pool entries (including the padding)
+    int fused_pairs = 0;                  // pairs per wavefront chosen by timing (0 = not tuned yet)
+    std::vector<std::pair<int, float>> fused_tuning;  // (pairs, ms) measured when tuning
 };
 
 }  // namespace qc

@@ -69,13 +69,21 @@ WsLayout ws_layout(const Exec &x, int n_qubits) {
     return w;
 }
 
-bool fused_fits(const Program &p) {
+// The fused form runs the (0 slices, 0 bitstring bits) program: every tensor
+// of one pair in LDS (offsets then fit in 16 bits) and a rank-0 root; each
+// leaf may take at most four bits from the slice id and the bitstring.
+bool fused_fits(const qc_plan *plan, const Program &p) {
+    if (p.b != 0 || p.m != 0) return false;
     if (p.lds_elems * int64_t(sizeof(float2)) > kFusedLdsBytes) return false;
-    for (const GemmOp &g : p.gemms) {
-        const int rc = (int)p.tensors[g.c].layout.size();
-        if (rc > kFusedMaxRank || g.cls_k > kFusedMaxK) return false;
+    if (!p.tensors[p.root_pre].layout.empty()) return false;
+    std::vector<char> sliced(plan->net.n_index(), 0);
+    for (int e : plan->sliced) sliced[e] = 1;
+    for (const LeafOp &lo : p.leaves) {
+        int dyn = 0;
+        for (int e : plan->net.leaves[lo.leaf].idx) dyn += sliced[e] || plan->net.out_qubit[e] >= 0;
+        if (dyn > 4) return false;
     }
-    return (int)p.tensors[p.root_pre].layout.size() <= 32;
+    return true;
 }
 
 // Picks the execution for a range of n_range slices with 2^m bitstrings that
@@ -87,7 +95,7 @@ bool choose_exec(qc_plan *plan, int m, int want_lp, size_t ws_bytes, Exec &x, st
     x.m = m;
     Program *pf = get_program(plan, 0, 0, err);
     if (!pf) return false;
-    const bool fits = fused_fits(*pf);
+    const bool fits = fused_fits(plan, *pf);
     if (plan->exec_mode == QC_EXEC_FUSED && !fits) {
         err = "the fused form does not fit in LDS for this plan";
         return false;
@@ -206,42 +214,114 @@ bool ensure_device(const qc_plan *plan, Program &prog, bool fused, std::string &
     }
     if (fused && !prog.d_fused_steps) {
         std::vector<LeafDesc> descs;
-        std::vector<int32_t> elems;
+        std::vector<int32_t> unused;
         std::vector<double2> base;
-        leaf_table(plan, prog, true, descs, elems, base, err);
+        leaf_table(plan, prog, true, descs, unused, base, err);
         if (!err.empty()) return false;
+        // Leaf elements: LDS slot, base index from the element's own bits,
+        // and up to four bits taken at run time from the slice id (16-bit
+        // code pos | j << 3) or the bitstring (pos | (64 + q) << 3).
+        // Elements without run-time bits go into the LDS image instead.
+        std::vector<int4> elems;
+        std::vector<float2> image;
+        for (const LeafDesc &d : descs) {
+            std::vector<uint32_t> dyn;
+            for (int i = 0; i < d.n_fix; ++i) dyn.push_back(uint32_t(d.fix_pos[i]) | (uint32_t(d.fix_j[i]) << 3));
+            for (int i = 0; i < d.n_oq; ++i) dyn.push_back(uint32_t(d.oq_pos[i]) | (uint32_t(64 + d.oq_q[i]) << 3));
+            if (dyn.size() > 4) { err = "a leaf has more than four run-time bits"; return false; }
+            while (dyn.size() < 4) dyn.push_back(0xffffu);
+            const bool is_dyn = dyn[0] != 0xffffu;
+            const int z = int(dyn[0] | (dyn[1] << 16)), w = int(dyn[2] | (dyn[3] << 16));
+            for (int64_t e = 0; e < (int64_t(1) << d.r_out); ++e) {
+                int idx = d.base_off;
+                for (int p = 0; p < d.r_out; ++p)
+                    if ((e >> p) & 1) idx += 1 << d.src[p];
+                const int64_t slot = d.out_off + e;
+                if ((int64_t)image.size() <= slot) image.resize(slot + 1, make_float2(0.f, 0.f));
+                if (!is_dyn) image[slot] = make_float2(float(base[idx].x), float(base[idx].y));
+                else elems.push_back(make_int4(int(slot), idx, z, w));
+            }
+        }
         std::vector<FusedStep> steps;
+        std::vector<int32_t> pool;
         for (const GemmOp &g : prog.gemms) {
             const auto &LA = prog.tensors[g.a_src].layout, &LB = prog.tensors[g.b_src].layout;
             const auto &LC = prog.tensors[g.c].layout;
             FusedStep st;
             std::memset(&st, 0, sizeof(st));
-            st.a_off = (int32_t)prog.lds_offset[g.a_src];
-            st.b_off = (int32_t)prog.lds_offset[g.b_src];
             st.c_off = (int32_t)prog.lds_offset[g.c];
             st.rc = (int32_t)LC.size();
+            st.tab = (int32_t)pool.size();
+            std::vector<int32_t> sA, sB, kA, kB;
             for (int p = 0; p < st.rc; ++p) {
                 const int e = LC[st.rc - 1 - p];
-                st.sA[p] = stride_in(LA, e);
-                st.sB[p] = stride_in(LB, e);
+                sA.push_back(stride_in(LA, e));
+                sB.push_back(stride_in(LB, e));
             }
-            int j = 0;
             for (int e : LA)
                 if (std::find(LC.begin(), LC.end(), e) == LC.end()) {
-                    st.kA[j] = stride_in(LA, e);
-                    st.kB[j] = stride_in(LB, e);
-                    ++j;
+                    kA.push_back(stride_in(LA, e));
+                    kB.push_back(stride_in(LB, e));
                 }
-            st.rk = j;
+            st.rk = (int32_t)kA.size();
+            const int64_t a0 = prog.lds_offset[g.a_src], b0 = prog.lds_offset[g.b_src];
+            for (int64_t c = 0; c < (int64_t(1) << st.rc); ++c) {
+                int64_t a = a0, b = b0;
+                for (int p = 0; p < st.rc; ++p)
+                    if ((c >> p) & 1) { a += sA[p]; b += sB[p]; }
+                pool.push_back(int32_t(uint32_t(a) | (uint32_t(b) << 16)));
+            }
+            for (int64_t kk = 0; kk < (int64_t(1) << st.rk); ++kk) {
+                int64_t a = 0, b = 0;
+                for (int j = 0; j < st.rk; ++j)
+                    if ((kk >> j) & 1) { a += kA[j]; b += kB[j]; }
+                const int32_t packed = int32_t(uint32_t(a) | (uint32_t(b) << 16));
+                pool.push_back(packed);
+                if (kk < 4) st.k[kk] = packed;
+            }
             steps.push_back(st);
         }
-        if (!upload(&prog.d_fused_elem, elems.data(), elems.size() * 4, err) ||
-            !upload(&prog.d_fused_leaf, descs.data(), descs.size() * sizeof(LeafDesc), err) ||
+        pool.insert(pool.end(), 8, 0);
+        if (!upload(&prog.d_fused_image, image.data(), image.size() * sizeof(float2), err) ||
+            !upload(&prog.d_fused_elems, elems.data(), elems.size() * sizeof(int4), err) ||
+            !upload(&prog.d_fused_pool, pool.data(), pool.size() * 4, err) ||
             (!prog.d_base && !upload(&prog.d_base, base.data(), base.size() * sizeof(double2), err)) ||
             !upload(&prog.d_fused_steps, steps.data(), steps.size() * sizeof(FusedStep), err))
             return false;
         prog.n_leaf_elems = (int)elems.size();
+        prog.n_image = (int)image.size();
+        prog.n_pool = (int)pool.size();
     }
+    return true;
+}
+
+int pair_elems_of(const Program &prog) { return int((prog.lds_elems + 1) & ~int64_t(1)); }
+
+// Times each pairs-per-wavefront option once on the caller's stream (the
+// launches write the same partial values the real launch then overwrites)
+// and keeps the fastest.  Runs once per program.
+bool tune_fused(Program &prog, const FusedParams &fp, hipStream_t st, std::string &err) {
+    const int pe = pair_elems_of(prog);
+    hipEvent_t e0, e1;
+    QC_HIP(hipEventCreate(&e0));
+    QC_HIP(hipEventCreate(&e1));
+    float best = 0.f;
+    for (int pairs : kFusedPairsOptions) {
+        if (fused_lds_bytes(pairs, pe, prog.n_pool) > size_t(kFusedLdsBytes)) continue;
+        launch_fused_pairs(fp, pairs, pe, prog.n_pool, st);  // warm-up
+        QC_HIP(hipEventRecord(e0, st));
+        for (int r = 0; r < 3; ++r) launch_fused_pairs(fp, pairs, pe, prog.n_pool, st);
+        QC_HIP(hipEventRecord(e1, st));
+        QC_HIP(hipEventSynchronize(e1));
+        float ms = 0.f;
+        QC_HIP(hipEventElapsedTime(&ms, e0, e1));
+        prog.fused_tuning.push_back({pairs, ms / 3});
+        if (prog.fused_pairs == 0 || ms < best) { best = ms; prog.fused_pairs = pairs; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    QC_HIP(hipGetLastError());
+    if (prog.fused_pairs == 0) { err = "no fused form fits in LDS"; return false; }
     return true;
 }
 
@@ -350,33 +430,24 @@ bool enqueue(qc_plan *plan, const Exec &x, uint64_t s_begin, uint64_t s_end, con
             std::memset(&fp, 0, sizeof(fp));
             fp.steps = (const FusedStep *)prog.d_fused_steps;
             fp.n_steps = (int32_t)prog.gemms.size();
-            fp.leaves = (const LeafDesc *)prog.d_fused_leaf;
-            fp.elem_leaf = (const int32_t *)prog.d_fused_elem;
+            fp.pool = (const int32_t *)prog.d_fused_pool;
+            fp.leaf_image = (const float2 *)prog.d_fused_image;
+            fp.n_image = prog.n_image;
+            fp.elems = (const int4 *)prog.d_fused_elems;
             fp.n_elems = prog.n_leaf_elems;
             fp.base = (const double2 *)prog.d_base;
             fp.bits = bits;
             fp.n_qubits = nq;
-            fp.bf = prog.b;
-            fp.mf = prog.m;
             fp.m = x.m;
-            fp.n_bs_groups = 1 << (x.m - prog.m);
-            const int64_t g0 = int64_t(lo - sc) >> prog.b;
-            const int64_t g1 = (int64_t(hi - sc) + (int64_t(1) << prog.b) - 1) >> prog.b;
-            fp.first_group = g0;
-            fp.n_slice_groups = g1 - g0;
+            fp.first_slice = int64_t(lo - sc);
+            fp.n_slices = int64_t(hi - lo);
             fp.sc = sc;
-            const auto &LR = prog.tensors[prog.root_pre].layout;
             fp.root_off = (int32_t)prog.lds_offset[prog.root_pre];
-            fp.root_rank = (int32_t)LR.size();
-            for (int p = 0; p < fp.root_rank; ++p) {
-                const int e = LR[fp.root_rank - 1 - p];
-                if (e >= kBsBase) fp.root_map[p] = (int8_t)(64 + (e - kBsBase));
-                else fp.root_map[p] = (int8_t)(std::find(plan->sliced.begin(), plan->sliced.end(), e) - plan->sliced.begin());
-            }
             fp.partial = partial;
             fp.lds_elems = (int32_t)prog.lds_elems;
+            if (prog.fused_pairs == 0 && !tune_fused(prog, fp, st, err)) return false;
             prof.begin();
-            launch_fused(fp, st);
+            launch_fused_pairs(fp, prog.fused_pairs, pair_elems_of(prog), prog.n_pool, st);
             prof.end("fused");
         } else {
             const uint64_t chunk = uint64_t(1) << prog.b;
@@ -413,7 +484,8 @@ void free_program_device(Program &prog) {
     int cur = 0;
     hipGetDevice(&cur);
     hipSetDevice(prog.device);
-    for (void **p : {&prog.d_leaf_desc, &prog.d_leaf_block, &prog.d_base, &prog.d_fused_leaf, &prog.d_fused_elem,
+    for (void **p : {&prog.d_leaf_desc, &prog.d_leaf_block, &prog.d_base, &prog.d_fused_image, &prog.d_fused_elems,
+                     &prog.d_fused_pool,
                      &prog.d_fused_steps}) {
         if (*p) hipFree(*p);
         *p = nullptr;

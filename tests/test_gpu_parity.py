@@ -59,10 +59,13 @@ def test_p6_unitarity_all_amplitudes(shape, depth, seed, mode):
     lat = synth.grid(*shape)
     circ = synth.random_circuit(lat, depth, seed)
     xs = np.array(list(np.ndindex(*([2] * lat.n))), dtype=np.uint8)
-    plan = qcsim.qc_plan_build(lat.n, circ, None, log2_slices=2, greedy_trials=2)
+    # As many slice bits as the simplified network has, up to 2.
+    n_idx = qcsim.qc_plan_info(qcsim.qc_plan_build(lat.n, circ))["n_indices"]
+    k = min(2, n_idx)
+    plan = qcsim.qc_plan_build(lat.n, circ, None, log2_slices=k, greedy_trials=2)
     qcsim.qc_plan_set_exec(plan, mode)
-    say(f"P6 unitarity {shape} d{depth} {mode}")
-    got = _contract(plan, xs, 0, 4)
+    say(f"P6 unitarity {shape} d{depth} {mode} k={k}")
+    got = _contract(plan, xs, 0, 1 << k)
     assert abs(np.sum(np.abs(got) ** 2) - 1) <= 1e-5
     psi = oracle.statevector(lat.n, circ)
     check_amplitudes(got, psi, lat.n, TOL_C64)
