@@ -197,6 +197,16 @@ qc_status qc_contract_slices(qc_plan *plan, uint64_t s_begin, uint64_t s_end,
                              void *ws, size_t ws_bytes, void *stream,
                              double *out_dev, double *per_slice_dev);
 
+/* qc_contract_slices with the bitstrings already resident in device memory:
+ * bitstrings_dev is a device uint8 [n_bs][n_qubits] array owned by the
+ * caller, entries 0 or 1 (not checked), read by the kernels of this call, so
+ * it must stay unchanged until the stream reaches them.  Nothing is copied
+ * from the host; otherwise identical semantics and errors. */
+qc_status qc_contract_slices_dev(qc_plan *plan, uint64_t s_begin, uint64_t s_end,
+                                 const uint8_t *bitstrings_dev, int32_t n_bs, qc_precision prec,
+                                 void *ws, size_t ws_bytes, void *stream,
+                                 double *out_dev, double *per_slice_dev);
+
 /* All slices of one amplitude, synchronously; allocates and frees its own
  * workspace on the current device.  out_host[0..1] = (re, im). */
 qc_status qc_amplitude(qc_plan *plan, const uint8_t *bitstring, qc_precision prec,

@@ -57,32 +57,33 @@ struct GemmDesc {
     int64_t sCb, sCm, sCn;
 };
 
-// Fused form: one wavefront runs the whole program of one (slice, bitstring)
-// pair with every tensor in LDS, contracting each step directly from the
-// operands' own layouts (no transposes).  Operand addressing is table-driven:
-// per step, pool[tab + c] packs the LDS offsets of A and B for output c
-// (low/high 16 bits) and pool[tab + 2^rc + j] the offsets added for the j-th
-// value of the contracted indices.
-constexpr int kFusedLdsBytes = 64 * 1024;     // LDS offsets then fit in 16 bits
-struct FusedStep {
-    int32_t c_off;                           // LDS offset of C (within one pair's region)
-    int32_t rc, rk;                          // log2 of C's size and of the contracted extent
-    int32_t tab;                             // start of this step's entries in the pool
-    int32_t k[4];                            // the first 4 contracted offsets (also in the pool)
-};
+// Fused form: one wavefront runs the whole program of (slice, bitstring)
+// pairs with every tensor in LDS, contracting each step directly from the
+// operands' own layouts (no transposes).  Steps are grouped into levels of
+// the contraction tree (a step's level is one more than its operands'), and
+// all outputs of one level are computed together, one per lane, with one
+// wavefront-scope fence per level.  Each output is an item (int4):
+//   x = out slot | nk << 16  (nk = number of contracted values)
+//   y = a0 | b0 << 16        (operand slots of the first contracted value)
+//   z = a1 | b1 << 16        (second value; the pair's zero slot when nk = 1)
+//   w = pool index of the remaining (nk - 2) slot pairs, or -1
+// Slots are offsets inside one pair's LDS region (below 2^16).
+constexpr int kFusedLdsBytes = 64 * 1024;
 
 struct FusedParams {
-    const FusedStep *steps;
-    int32_t n_steps;
-    const int32_t *pool;                     // padded with 8 zeros at the end
+    const int32_t *level_start;              // n_levels + 1 item offsets
+    int32_t n_levels;
+    const int4 *items;
+    const int32_t *pool;
     const float2 *leaf_image;                // LDS [0, n_image): leaf values that do not depend on the pair
     int32_t n_image;
     const int4 *elems;                       // run-time leaf elements: (LDS slot, base index, dyn0, dyn1)
     int32_t n_elems;
     const double2 *base;
-    const uint8_t *bits;                     // [2^m][n_qubits]
+    const uint8_t *bits;                     // [n_bs][n_qubits]
     int32_t n_qubits;
-    int32_t m;                               // log2 bitstrings (rows of bits / partial)
+    int32_t n_bs;
+    int32_t m;                               // log2 padded bitstrings (rows of partial)
     int64_t first_slice, n_slices;           // slices relative to sc
     uint64_t sc;                             // super-chunk base slice id
     int32_t root_off;
@@ -94,16 +95,17 @@ struct FusedParams {
 // go as separate read-only kernel arguments so that uniform reads of them
 // become scalar loads).
 struct FusedScalars {
-    int32_t n_steps, n_pool, n_image, n_elems, n_qubits, m, root_off, pair_elems;
+    int32_t n_levels, n_image, n_elems, n_qubits, m, root_off, pair_elems, zero_slot;
+    int32_t n_bs, pad;                       // rows of bits; padded bitstrings reuse the last row
     int64_t first_slice, n_slices;
     uint64_t sc;
 };
 
 // Pairs per wavefront the fused kernel is built for; the runtime times them
 // on first use of a program and keeps the fastest.
-constexpr int kFusedPairsOptions[] = {1, 2, 4, 8};
-size_t fused_lds_bytes(int pairs, int pair_elems, int n_pool);
-void launch_fused_pairs(const FusedParams &p, int pairs, int pair_elems, int n_pool, hipStream_t st);
+constexpr int kFusedPairsOptions[] = {1, 2, 4};
+size_t fused_lds_bytes(int pairs, int pair_elems);
+void launch_fused_pairs(const FusedParams &p, int pairs, int pair_elems, int zero_slot, hipStream_t st);
 
 // out[bs] += sum of partial over in-range slices of the super-chunk, in
 // aligned blocks of 64 slices: a fixed butterfly within each block, blocks
@@ -112,10 +114,9 @@ void launch_reduce64(const float2 *partial, int m, int n_bs, uint64_t sc, int64_
                      uint64_t s_begin, double *out, double *per_slice, hipStream_t st);
 
 void launch_leaves(const LeafDesc *descs, const int32_t *block_leaf, int n_blocks, const double2 *base,
-                   float2 *tensors, const uint8_t *bits, int n_qubits, uint64_t chunk_base, hipStream_t st);
+                   float2 *tensors, const uint8_t *bits, int n_qubits, int n_bs, uint64_t chunk_base,
+                   hipStream_t st);
 void launch_transpose(const TransposeDesc &d, hipStream_t st);
 const char *launch_gemm(const GemmDesc &d, hipStream_t st);  // returns the form launched
-void launch_reduce(const float2 *root, int b, int m, int n_bs, uint64_t chunk_base, uint64_t s_begin,
-                   uint64_t s_end, double *out, double *per_slice, hipStream_t st);
 
 }  // namespace qc

@@ -16,7 +16,7 @@ namespace qc {
 __global__ void __launch_bounds__(256) leaf_kernel(const LeafDesc *__restrict__ descs,
                                                    const int32_t *__restrict__ block_leaf,
                                                    const double2 *__restrict__ base, float2 *__restrict__ tensors,
-                                                   const uint8_t *__restrict__ bits, int n_qubits,
+                                                   const uint8_t *__restrict__ bits, int n_qubits, int n_bs,
                                                    uint64_t chunk_base) {
     const int leaf = block_leaf[blockIdx.x];
     const LeafDesc &d = descs[leaf];
@@ -29,6 +29,7 @@ __global__ void __launch_bounds__(256) leaf_kernel(const LeafDesc *__restrict__ 
         if (s >= 64) bs |= bit << (s - 64);
         else bidx |= bit << s;
     }
+    bs = min(bs, n_bs - 1);  // padded bitstrings repeat the last one (their results are dropped)
     for (int i = 0; i < d.n_fix; ++i) bidx |= int((chunk_base >> d.fix_j[i]) & 1) << d.fix_pos[i];
     for (int i = 0; i < d.n_oq; ++i) bidx |= int(bits[int64_t(bs) * n_qubits + d.oq_q[i]] & 1) << d.oq_pos[i];
     const double2 v = base[d.base_off + bidx];
@@ -36,10 +37,11 @@ __global__ void __launch_bounds__(256) leaf_kernel(const LeafDesc *__restrict__ 
 }
 
 void launch_leaves(const LeafDesc *descs, const int32_t *block_leaf, int n_blocks, const double2 *base,
-                   float2 *tensors, const uint8_t *bits, int n_qubits, uint64_t chunk_base, hipStream_t st) {
+                   float2 *tensors, const uint8_t *bits, int n_qubits, int n_bs, uint64_t chunk_base,
+                   hipStream_t st) {
     if (n_blocks <= 0) return;
     hipLaunchKernelGGL(leaf_kernel, dim3(n_blocks), dim3(256), 0, st, descs, block_leaf, base, tensors, bits,
-                       n_qubits, chunk_base);
+                       n_qubits, n_bs, chunk_base);
 }
 
 // --------------------------------------------------------------- transpose
@@ -227,66 +229,27 @@ __device__ __forceinline__ int dyn_bits(int z, int w, uint64_t slice, const uint
            dyn_bit(uint32_t(w) & 0xffffu, slice, row) + dyn_bit(uint32_t(w) >> 16, slice, row);
 }
 
-__device__ __forceinline__ float2 contract_one(const float2 *lds, int a, int b, const int32_t *kt, int nk) {
-    float re = 0.f, im = 0.f;
-    for (int kk = 0; kk < nk; ++kk) {
-        const uint32_t kab = uint32_t(kt[kk]);
-        const float2 x = lds[a + int(kab & 0xffffu)];
-        const float2 y = lds[b + int(kab >> 16)];
-        re = fmaf(x.x, y.x, re);
-        re = fmaf(-x.y, y.y, re);
-        im = fmaf(x.x, y.y, im);
-        im = fmaf(x.y, y.x, im);
-    }
-    return make_float2(re, im);
-}
-
-// Same for a compile-time contracted extent: all LDS reads are issued before
-// the multiply-adds.
-template <int NK>
-__device__ __forceinline__ float2 contract_fixed(const float2 *lds, int a, int b, const int32_t *__restrict__ kt) {
-    float2 x[NK], y[NK];
-#pragma unroll
-    for (int i = 0; i < NK; ++i) {
-        const uint32_t u = uint32_t(kt[i]);
-        x[i] = lds[a + int(u & 0xffffu)];
-        y[i] = lds[b + int(u >> 16)];
-    }
-    float re = 0.f, im = 0.f;
-#pragma unroll
-    for (int i = 0; i < NK; ++i) {
-        re = fmaf(x[i].x, y[i].x, re);
-        re = fmaf(-x[i].y, y[i].y, re);
-        im = fmaf(x[i].x, y[i].y, im);
-        im = fmaf(x[i].y, y[i].x, im);
-    }
-    return make_float2(re, im);
-}
-
 // The fused kernel's workgroup is a single wavefront, whose LDS accesses are
-// performed in issue order.  Between steps it is therefore enough that the
+// performed in issue order.  Between levels it is therefore enough that the
 // compiler keeps LDS accesses on their side of the boundary (a wavefront-scope
-// fence); a workgroup barrier would also wait for the global loads that
-// prefetch the next step's tables.
+// fence); a workgroup barrier would also wait for outstanding global loads.
 __device__ __forceinline__ void wave_step_sync() {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
 }
 
-// One wavefront runs PAIRS (slice, bitstring) pairs through the same step
-// stream, each pair in its own LDS region of pair_elems values; the step
-// headers (one scalar load each) and the LDS-resident offset table are shared,
-// so their scalar work is paid once per PAIRS pairs.  For a step with 2^rc
-// outputs, lane l works on pair l >> rc, output l & (2^rc - 1).
+// One wavefront runs PAIRS (slice, bitstring) pairs, each in its own LDS
+// region of pair_elems values (the last one, zero_slot, holds 0), level by
+// level: every item of a level reads only tensors of lower levels, so a level
+// needs no synchronisation inside it.
 template <int PAIRS>
 __global__ void __launch_bounds__(64)
-fused_kernel(const FusedStep *__restrict__ steps, const int32_t *__restrict__ pool,
-             const float2 *__restrict__ image, const int4 *__restrict__ elems, const double2 *__restrict__ base,
-             const uint8_t *__restrict__ bits, float2 *__restrict__ partial, FusedScalars S) {
+fused_kernel(const int32_t *__restrict__ level_start, const int4 *__restrict__ items,
+             const int32_t *__restrict__ pool, const float2 *__restrict__ image, const int4 *__restrict__ elems,
+             const double2 *__restrict__ base, const uint8_t *__restrict__ bits, float2 *__restrict__ partial,
+             FusedScalars S) {
     extern __shared__ float2 lds[];
-    int32_t *tab = reinterpret_cast<int32_t *>(lds + PAIRS * S.pair_elems);
     const int lane = threadIdx.x;
-    for (int i = lane; i < S.n_pool; i += 64) tab[i] = pool[i];
     const int n_bs = 1 << S.m;
     const int64_t n_pairs = S.n_slices << S.m;
     const int64_t n_groups = (n_pairs + PAIRS - 1) / PAIRS;
@@ -297,12 +260,13 @@ fused_kernel(const FusedStep *__restrict__ steps, const int32_t *__restrict__ po
         for (int p = 0; p < PAIRS; ++p) {
             float2 *L = lds + p * S.pair_elems;
             for (int e = lane; e < S.n_image; e += 64) L[e] = image[e];
+            if (lane == 0) L[S.zero_slot] = make_float2(0.f, 0.f);
         }
         wave_step_sync();
         for (int p = 0; p < PAIRS; ++p) {
             const int64_t pair = min(g * PAIRS + p, n_pairs - 1);
             const uint64_t slice = S.sc + uint64_t(S.first_slice + (pair >> S.m));
-            const uint8_t *row = bits + int64_t(pair & (n_bs - 1)) * S.n_qubits;
+            const uint8_t *row = bits + int64_t(min(int(pair & (n_bs - 1)), S.n_bs - 1)) * S.n_qubits;
             float2 *L = lds + p * S.pair_elems;
             for (int e = lane; e < S.n_elems; e += 64) {
                 const int4 t = elems[e];
@@ -311,22 +275,37 @@ fused_kernel(const FusedStep *__restrict__ steps, const int32_t *__restrict__ po
             }
         }
         wave_step_sync();
-        for (int s = 0; s < S.n_steps; ++s) {
-            const FusedStep h = steps[s];
-            const int nc = 1 << h.rc;
-            for (int pc = lane; pc < (PAIRS << h.rc); pc += 64) {
-                const int p = pc >> h.rc, c = pc & (nc - 1);
-                const uint32_t u = uint32_t(tab[h.tab + c]);
-                const int po = p * S.pair_elems;
-                const int a = po + int(u & 0xffffu), b = po + int(u >> 16);
-                float2 v;
-                switch (h.rk) {
-                case 0: v = contract_fixed<1>(lds, a, b, h.k); break;
-                case 1: v = contract_fixed<2>(lds, a, b, h.k); break;
-                case 2: v = contract_fixed<4>(lds, a, b, h.k); break;
-                default: v = contract_one(lds, a, b, tab + h.tab + nc, 1 << h.rk);
+        for (int lv = 0; lv < S.n_levels; ++lv) {
+            const int i0 = level_start[lv], i1 = level_start[lv + 1];
+            for (int i = i0 + lane; i < i1; i += 64) {
+                const int4 it = items[i];
+                const uint32_t y = uint32_t(it.y), z = uint32_t(it.z);
+#pragma unroll
+                for (int p = 0; p < PAIRS; ++p) {
+                    const float2 *L = lds + p * S.pair_elems;
+                    const float2 x0 = L[y & 0xffffu], y0 = L[y >> 16];
+                    const float2 x1 = L[z & 0xffffu], y1 = L[z >> 16];
+                    float re = x0.x * y0.x;
+                    re = fmaf(-x0.y, y0.y, re);
+                    float im = x0.x * y0.y;
+                    im = fmaf(x0.y, y0.x, im);
+                    re = fmaf(x1.x, y1.x, re);
+                    re = fmaf(-x1.y, y1.y, re);
+                    im = fmaf(x1.x, y1.y, im);
+                    im = fmaf(x1.y, y1.x, im);
+                    if (it.w >= 0) {  // more than two contracted values
+                        const int extra = pool[it.w];
+                        for (int j = 1; j <= extra; ++j) {
+                            const uint32_t u = uint32_t(pool[it.w + j]);
+                            const float2 xa = L[u & 0xffffu], yb = L[u >> 16];
+                            re = fmaf(xa.x, yb.x, re);
+                            re = fmaf(-xa.y, yb.y, re);
+                            im = fmaf(xa.x, yb.y, im);
+                            im = fmaf(xa.y, yb.x, im);
+                        }
+                    }
+                    lds[p * S.pair_elems + (it.x & 0xffff)] = make_float2(re, im);
                 }
-                lds[po + h.c_off + c] = v;
             }
             wave_step_sync();
         }
@@ -339,38 +318,37 @@ fused_kernel(const FusedStep *__restrict__ steps, const int32_t *__restrict__ po
     }
 }
 
-size_t fused_lds_bytes(int pairs, int pair_elems, int n_pool) {
-    return size_t(pairs) * pair_elems * sizeof(float2) + size_t(n_pool) * sizeof(int32_t);
-}
+size_t fused_lds_bytes(int pairs, int pair_elems) { return size_t(pairs) * pair_elems * sizeof(float2); }
 
-void launch_fused_pairs(const FusedParams &p, int pairs, int pair_elems, int n_pool, hipStream_t st) {
+void launch_fused_pairs(const FusedParams &p, int pairs, int pair_elems, int zero_slot, hipStream_t st) {
     const int64_t n_pairs = p.n_slices << p.m;
     if (n_pairs <= 0) return;
     const int64_t groups = (n_pairs + pairs - 1) / pairs;
     const unsigned grid = (unsigned)(groups < 1048576 ? groups : 1048576);
     FusedScalars S;
-    S.n_steps = p.n_steps;
-    S.n_pool = n_pool;
+    S.n_levels = p.n_levels;
+    S.zero_slot = zero_slot;
     S.n_image = p.n_image;
     S.n_elems = p.n_elems;
     S.n_qubits = p.n_qubits;
     S.m = p.m;
     S.root_off = p.root_off;
     S.pair_elems = pair_elems;
+    S.n_bs = p.n_bs;
+    S.pad = 0;
     S.first_slice = p.first_slice;
     S.n_slices = p.n_slices;
     S.sc = p.sc;
-    const size_t lds = fused_lds_bytes(pairs, pair_elems, n_pool);
+    const size_t lds = fused_lds_bytes(pairs, pair_elems);
 #define QC_FUSED_CASE(N)                                                                                      \
     case N:                                                                                                   \
-        hipLaunchKernelGGL(fused_kernel<N>, dim3(grid), dim3(64), lds, st, p.steps, p.pool, p.leaf_image,      \
-                           p.elems, p.base, p.bits, p.partial, S);                                            \
+        hipLaunchKernelGGL(fused_kernel<N>, dim3(grid), dim3(64), lds, st, p.level_start, p.items, p.pool,     \
+                           p.leaf_image, p.elems, p.base, p.bits, p.partial, S);                              \
         break;
     switch (pairs) {
         QC_FUSED_CASE(1)
         QC_FUSED_CASE(2)
         QC_FUSED_CASE(4)
-        QC_FUSED_CASE(8)
     default: break;
     }
 #undef QC_FUSED_CASE
@@ -417,53 +395,6 @@ __global__ void __launch_bounds__(64) reduce64_kernel(const float2 *__restrict__
 void launch_reduce64(const float2 *partial, int m, int n_bs, uint64_t sc, int64_t n_blocks, uint64_t lo, uint64_t hi,
                      uint64_t s_begin, double *out, double *per_slice, hipStream_t st) {
     hipLaunchKernelGGL(reduce64_kernel, dim3(n_bs), dim3(64), 0, st, partial, m, n_bs, sc, n_blocks, lo, hi, s_begin,
-                       out, per_slice);
-}
-
-// ---------------------------------------------------------------- reduce
-// out[bs] += sum over in-range slices of root[s_low][bs], in FP64.  One block
-// per bitstring; thread t sums s_low = t, t + 256, ... in order, then a fixed
-// LDS tree combines the 256 partial sums, so the result does not depend on
-// timing.
-__global__ void __launch_bounds__(256) reduce_kernel(const float2 *__restrict__ root, int b, int m, int n_bs,
-                                                     uint64_t chunk_base, uint64_t s_begin, uint64_t s_end,
-                                                     double *__restrict__ out, double *__restrict__ per_slice) {
-    __shared__ double sre[256], sim[256];
-    const int bs = blockIdx.x;
-    if (bs >= n_bs) return;
-    double re = 0, im = 0;
-    const int64_t ns = int64_t(1) << b;
-    for (int64_t sl = threadIdx.x; sl < ns; sl += blockDim.x) {
-        const uint64_t s = chunk_base + uint64_t(sl);
-        if (s < s_begin || s >= s_end) continue;
-        const float2 v = root[(sl << m) + bs];
-        re += double(v.x);
-        im += double(v.y);
-        if (per_slice) {
-            double *p = per_slice + 2 * (int64_t(s - s_begin) * n_bs + bs);
-            p[0] = double(v.x);
-            p[1] = double(v.y);
-        }
-    }
-    sre[threadIdx.x] = re;
-    sim[threadIdx.x] = im;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if (threadIdx.x < w) {
-            sre[threadIdx.x] += sre[threadIdx.x + w];
-            sim[threadIdx.x] += sim[threadIdx.x + w];
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        out[2 * bs] += sre[0];
-        out[2 * bs + 1] += sim[0];
-    }
-}
-
-void launch_reduce(const float2 *root, int b, int m, int n_bs, uint64_t chunk_base, uint64_t s_begin,
-                   uint64_t s_end, double *out, double *per_slice, hipStream_t st) {
-    hipLaunchKernelGGL(reduce_kernel, dim3(n_bs), dim3(256), 0, st, root, b, m, n_bs, chunk_base, s_begin, s_end,
                        out, per_slice);
 }
 

@@ -265,23 +265,35 @@ static bool lower(const qc_plan *plan, int b, int m, Program &prog, std::string 
     }
     prog.tensor_elems = arena.end;
 
-    // Fused form: GEMM steps read their operands as produced (no transposes);
-    // offsets in a separate arena sized for LDS.
+    // Fused form: GEMM steps read their operands as produced (no transposes)
+    // and run level by level (a step's level is one more than its operands'),
+    // all steps of a level at once.  Offsets come from a separate arena sized
+    // for LDS, filled in level order: the outputs of level l are placed
+    // first, and only then are the operands read at level l released, so a
+    // slot is reused only by a later level.
     {
-        std::vector<int> fdeath(nt, -1);
-        for (size_t i = 0; i < prog.gemms.size(); ++i) {
-            fdeath[prog.gemms[i].a_src] = (int)i;
-            fdeath[prog.gemms[i].b_src] = (int)i;
+        const int ng = (int)prog.gemms.size();
+        std::vector<int> level(nt, 0);
+        int n_levels = 0;
+        for (const GemmOp &g : prog.gemms) {
+            level[g.c] = 1 + std::max(level[g.a_src], level[g.b_src]);
+            n_levels = std::max(n_levels, level[g.c]);
         }
         prog.lds_offset.assign(nt, -1);
         Arena la;
         la.granule = 2;
         for (int t = 0; t < L; ++t) prog.lds_offset[t] = la.alloc(prog.tensors[t].size());
-        for (size_t i = 0; i < prog.gemms.size(); ++i) {
-            const int c = prog.gemms[i].c;
-            prog.lds_offset[c] = la.alloc(prog.tensors[c].size());
-            for (int t = 0; t < nt; ++t)
-                if (fdeath[t] == (int)i) la.release(prog.lds_offset[t], prog.tensors[t].size());
+        for (int lv = 1; lv <= n_levels; ++lv) {
+            for (int i = 0; i < ng; ++i) {
+                const int c = prog.gemms[i].c;
+                if (level[c] == lv) prog.lds_offset[c] = la.alloc(prog.tensors[c].size());
+            }
+            for (int i = 0; i < ng; ++i) {
+                const GemmOp &g = prog.gemms[i];
+                if (level[g.c] != lv) continue;
+                la.release(prog.lds_offset[g.a_src], prog.tensors[g.a_src].size());
+                la.release(prog.lds_offset[g.b_src], prog.tensors[g.b_src].size());
+            }
         }
         prog.lds_elems = la.end;
     }
@@ -332,7 +344,9 @@ std::string describe_program(const qc_plan *plan, const Program &prog) {
     for (size_t t = 0; t < prog.tensors.size(); ++t) {
         o << (t ? "," : "") << "{\"layout\":";
         json_ints(o, prog.tensors[t].layout);
-        o << ",\"offset\":" << prog.tensors[t].offset << '}';
+        o << ",\"offset\":" << prog.tensors[t].offset;
+        if (t < prog.lds_offset.size()) o << ",\"lds\":" << prog.lds_offset[t];
+        o << '}';
     }
     o << "],\"ops\":[";
     for (size_t i = 0; i < prog.ops.size(); ++i) {

@@ -132,10 +132,12 @@ struct Program {
     void *d_fused_image = nullptr;        // leaf values that do not depend on the (slice, bitstring) pair
     int n_image = 0;
     void *d_fused_elems = nullptr;        // run-time leaf elements: LDS slot, base index, dynamic bits
-    void *d_fused_pool = nullptr;         // per step: operand offsets per output, then per contracted value
-    void *d_fused_steps = nullptr;        // per step header
+    void *d_fused_items = nullptr;        // one item per output of every step, grouped by tree level
+    void *d_fused_levels = nullptr;       // item offsets of the levels
+    void *d_fused_pool = nullptr;         // operand slots of items with more than two contracted values
     int n_leaf_elems = 0;
-    int n_pool = 0;                       // pool entries (including the padding)
+    int n_levels = 0;
+    int n_pool = 0;
     int fused_pairs = 0;                  // pairs per wavefront chosen by timing (0 = not tuned yet)
     std::vector<std::pair<int, float>> fused_tuning;  // (pairs, ms) measured when tuning
 };

@@ -72,9 +72,14 @@ WsLayout ws_layout(const Exec &x, int n_qubits) {
 // The fused form runs the (0 slices, 0 bitstring bits) program: every tensor
 // of one pair in LDS (offsets then fit in 16 bits) and a rank-0 root; each
 // leaf may take at most four bits from the slice id and the bitstring.
+// A pair's LDS region: the program's tensors, then one slot holding zero.
+int64_t pair_elems64(const Program &prog) { return (prog.lds_elems + 2) & ~int64_t(1); }
+int zero_slot_of(const Program &prog) { return int(prog.lds_elems); }
+int pair_elems_of(const Program &prog) { return int(pair_elems64(prog)); }  // only once fused_fits holds
+
 bool fused_fits(const qc_plan *plan, const Program &p) {
     if (p.b != 0 || p.m != 0) return false;
-    if (p.lds_elems * int64_t(sizeof(float2)) > kFusedLdsBytes) return false;
+    if (pair_elems64(p) * int64_t(sizeof(float2)) > kFusedLdsBytes) return false;
     if (!p.tensors[p.root_pre].layout.empty()) return false;
     std::vector<char> sliced(plan->net.n_index(), 0);
     for (int e : plan->sliced) sliced[e] = 1;
@@ -212,7 +217,7 @@ bool ensure_device(const qc_plan *plan, Program &prog, bool fused, std::string &
             return false;
         prog.n_leaf_blocks = (int)blocks.size();
     }
-    if (fused && !prog.d_fused_steps) {
+    if (fused && !prog.d_fused_items) {
         std::vector<LeafDesc> descs;
         std::vector<int32_t> unused;
         std::vector<double2> base;
@@ -242,19 +247,25 @@ bool ensure_device(const qc_plan *plan, Program &prog, bool fused, std::string &
                 else elems.push_back(make_int4(int(slot), idx, z, w));
             }
         }
-        std::vector<FusedStep> steps;
+        // Items: one per output of every step, grouped by tree level (a
+        // step's level is one more than its operands'; leaves are level 0).
+        const int zero = zero_slot_of(prog);
+        std::vector<int> level(prog.tensors.size(), 0);
+        int n_levels = 0;
+        for (const GemmOp &g : prog.gemms) {
+            level[g.c] = 1 + std::max(level[g.a_src], level[g.b_src]);
+            n_levels = std::max(n_levels, level[g.c]);
+        }
+        std::vector<std::vector<int4>> by_level(n_levels);
         std::vector<int32_t> pool;
+        auto pack = [](int64_t a, int64_t b) { return int32_t(uint32_t(a) | (uint32_t(b) << 16)); };
         for (const GemmOp &g : prog.gemms) {
             const auto &LA = prog.tensors[g.a_src].layout, &LB = prog.tensors[g.b_src].layout;
             const auto &LC = prog.tensors[g.c].layout;
-            FusedStep st;
-            std::memset(&st, 0, sizeof(st));
-            st.c_off = (int32_t)prog.lds_offset[g.c];
-            st.rc = (int32_t)LC.size();
-            st.tab = (int32_t)pool.size();
+            const int rc = (int)LC.size();
             std::vector<int32_t> sA, sB, kA, kB;
-            for (int p = 0; p < st.rc; ++p) {
-                const int e = LC[st.rc - 1 - p];
+            for (int p = 0; p < rc; ++p) {
+                const int e = LC[rc - 1 - p];
                 sA.push_back(stride_in(LA, e));
                 sB.push_back(stride_in(LB, e));
             }
@@ -263,54 +274,65 @@ bool ensure_device(const qc_plan *plan, Program &prog, bool fused, std::string &
                     kA.push_back(stride_in(LA, e));
                     kB.push_back(stride_in(LB, e));
                 }
-            st.rk = (int32_t)kA.size();
+            const int rk = (int)kA.size();
+            const int64_t nk = int64_t(1) << rk;
+            std::vector<int64_t> ka(nk, 0), kb(nk, 0);
+            for (int64_t kk = 0; kk < nk; ++kk)
+                for (int j = 0; j < rk; ++j)
+                    if ((kk >> j) & 1) { ka[kk] += kA[j]; kb[kk] += kB[j]; }
             const int64_t a0 = prog.lds_offset[g.a_src], b0 = prog.lds_offset[g.b_src];
-            for (int64_t c = 0; c < (int64_t(1) << st.rc); ++c) {
+            for (int64_t c = 0; c < (int64_t(1) << rc); ++c) {
                 int64_t a = a0, b = b0;
-                for (int p = 0; p < st.rc; ++p)
+                for (int p = 0; p < rc; ++p)
                     if ((c >> p) & 1) { a += sA[p]; b += sB[p]; }
-                pool.push_back(int32_t(uint32_t(a) | (uint32_t(b) << 16)));
+                int4 it;
+                it.x = int(uint32_t(prog.lds_offset[g.c] + c) | (uint32_t(nk) << 16));
+                it.y = pack(a, b);
+                it.z = nk > 1 ? pack(a + ka[1], b + kb[1]) : pack(zero, zero);
+                it.w = -1;
+                if (nk > 2) {
+                    it.w = (int)pool.size();
+                    pool.push_back(int32_t(nk - 2));
+                    for (int64_t kk = 2; kk < nk; ++kk) pool.push_back(pack(a + ka[kk], b + kb[kk]));
+                }
+                by_level[level[g.c] - 1].push_back(it);
             }
-            for (int64_t kk = 0; kk < (int64_t(1) << st.rk); ++kk) {
-                int64_t a = 0, b = 0;
-                for (int j = 0; j < st.rk; ++j)
-                    if ((kk >> j) & 1) { a += kA[j]; b += kB[j]; }
-                const int32_t packed = int32_t(uint32_t(a) | (uint32_t(b) << 16));
-                pool.push_back(packed);
-                if (kk < 4) st.k[kk] = packed;
-            }
-            steps.push_back(st);
         }
-        pool.insert(pool.end(), 8, 0);
+        std::vector<int4> items;
+        std::vector<int32_t> level_start(1, 0);
+        for (auto &lv : by_level) {
+            items.insert(items.end(), lv.begin(), lv.end());
+            level_start.push_back((int32_t)items.size());
+        }
         if (!upload(&prog.d_fused_image, image.data(), image.size() * sizeof(float2), err) ||
             !upload(&prog.d_fused_elems, elems.data(), elems.size() * sizeof(int4), err) ||
             !upload(&prog.d_fused_pool, pool.data(), pool.size() * 4, err) ||
             (!prog.d_base && !upload(&prog.d_base, base.data(), base.size() * sizeof(double2), err)) ||
-            !upload(&prog.d_fused_steps, steps.data(), steps.size() * sizeof(FusedStep), err))
+            !upload(&prog.d_fused_items, items.data(), items.size() * sizeof(int4), err) ||
+            !upload(&prog.d_fused_levels, level_start.data(), level_start.size() * 4, err))
             return false;
         prog.n_leaf_elems = (int)elems.size();
         prog.n_image = (int)image.size();
         prog.n_pool = (int)pool.size();
+        prog.n_levels = n_levels;
     }
     return true;
 }
-
-int pair_elems_of(const Program &prog) { return int((prog.lds_elems + 1) & ~int64_t(1)); }
 
 // Times each pairs-per-wavefront option once on the caller's stream (the
 // launches write the same partial values the real launch then overwrites)
 // and keeps the fastest.  Runs once per program.
 bool tune_fused(Program &prog, const FusedParams &fp, hipStream_t st, std::string &err) {
-    const int pe = pair_elems_of(prog);
+    const int pe = pair_elems_of(prog), zero = zero_slot_of(prog);
     hipEvent_t e0, e1;
     QC_HIP(hipEventCreate(&e0));
     QC_HIP(hipEventCreate(&e1));
     float best = 0.f;
     for (int pairs : kFusedPairsOptions) {
-        if (fused_lds_bytes(pairs, pe, prog.n_pool) > size_t(kFusedLdsBytes)) continue;
-        launch_fused_pairs(fp, pairs, pe, prog.n_pool, st);  // warm-up
+        if (fused_lds_bytes(pairs, pe) > size_t(kFusedLdsBytes)) continue;
+        launch_fused_pairs(fp, pairs, pe, zero, st);  // warm-up
         QC_HIP(hipEventRecord(e0, st));
-        for (int r = 0; r < 3; ++r) launch_fused_pairs(fp, pairs, pe, prog.n_pool, st);
+        for (int r = 0; r < 3; ++r) launch_fused_pairs(fp, pairs, pe, zero, st);
         QC_HIP(hipEventRecord(e1, st));
         QC_HIP(hipEventSynchronize(e1));
         float ms = 0.f;
@@ -409,27 +431,33 @@ struct Prof {
     }
 };
 
-bool enqueue(qc_plan *plan, const Exec &x, uint64_t s_begin, uint64_t s_end, const uint8_t *bits_host, int n_bs,
-             void *ws, hipStream_t st, double *out_dev, double *per_slice_dev, std::string &err) {
+// bits_in: host bitstrings (copied into the workspace) or, with bits_on_device,
+// the caller's device array (read in place).
+bool enqueue(qc_plan *plan, const Exec &x, uint64_t s_begin, uint64_t s_end, const uint8_t *bits_in,
+             bool bits_on_device, int n_bs, void *ws, hipStream_t st, double *out_dev, double *per_slice_dev,
+             std::string &err) {
     Program &prog = *x.prog;
     Prof prof{plan, st};
     if (!ensure_device(plan, prog, x.fused, err)) return false;
     const int nq = plan->net.n_qubits;
     const WsLayout w = ws_layout(x, nq);
-    uint8_t *bits = (uint8_t *)ws + w.bits_off;
+    const uint8_t *bits = bits_in;
     float2 *partial = (float2 *)((char *)ws + w.partial_off);
     float2 *tensors = (float2 *)((char *)ws + w.tensor_off);
-    const size_t used = size_t(n_bs) * nq;
-    QC_HIP(hipMemcpyAsync(bits, bits_host, used, hipMemcpyHostToDevice, st));
-    if ((size_t(nq) << x.m) > used) QC_HIP(hipMemsetAsync(bits + used, 0, (size_t(nq) << x.m) - used, st));
+    if (!bits_on_device) {
+        uint8_t *dst = (uint8_t *)ws + w.bits_off;
+        QC_HIP(hipMemcpyAsync(dst, bits_in, size_t(n_bs) * nq, hipMemcpyHostToDevice, st));
+        bits = dst;
+    }
     const uint64_t P = uint64_t(1) << x.lp;
     for (uint64_t sc = s_begin & ~(P - 1); sc < s_end; sc += P) {
         const uint64_t lo = std::max(s_begin, sc), hi = std::min(s_end, sc + P);
         if (x.fused) {
             FusedParams fp;
             std::memset(&fp, 0, sizeof(fp));
-            fp.steps = (const FusedStep *)prog.d_fused_steps;
-            fp.n_steps = (int32_t)prog.gemms.size();
+            fp.level_start = (const int32_t *)prog.d_fused_levels;
+            fp.n_levels = prog.n_levels;
+            fp.items = (const int4 *)prog.d_fused_items;
             fp.pool = (const int32_t *)prog.d_fused_pool;
             fp.leaf_image = (const float2 *)prog.d_fused_image;
             fp.n_image = prog.n_image;
@@ -438,6 +466,7 @@ bool enqueue(qc_plan *plan, const Exec &x, uint64_t s_begin, uint64_t s_end, con
             fp.base = (const double2 *)prog.d_base;
             fp.bits = bits;
             fp.n_qubits = nq;
+            fp.n_bs = n_bs;
             fp.m = x.m;
             fp.first_slice = int64_t(lo - sc);
             fp.n_slices = int64_t(hi - lo);
@@ -447,14 +476,14 @@ bool enqueue(qc_plan *plan, const Exec &x, uint64_t s_begin, uint64_t s_end, con
             fp.lds_elems = (int32_t)prog.lds_elems;
             if (prog.fused_pairs == 0 && !tune_fused(prog, fp, st, err)) return false;
             prof.begin();
-            launch_fused_pairs(fp, prog.fused_pairs, pair_elems_of(prog), prog.n_pool, st);
+            launch_fused_pairs(fp, prog.fused_pairs, pair_elems_of(prog), zero_slot_of(prog), st);
             prof.end("fused");
         } else {
             const uint64_t chunk = uint64_t(1) << prog.b;
             for (uint64_t cb = lo & ~(chunk - 1); cb < hi; cb += chunk) {
                 prof.begin();
                 launch_leaves((const LeafDesc *)prog.d_leaf_desc, (const int32_t *)prog.d_leaf_block,
-                              prog.n_leaf_blocks, (const double2 *)prog.d_base, tensors, bits, nq, cb, st);
+                              prog.n_leaf_blocks, (const double2 *)prog.d_base, tensors, bits, nq, n_bs, cb, st);
                 prof.end("leaves");
                 for (const Op &op : prog.ops) {
                     prof.begin();
@@ -482,15 +511,14 @@ bool enqueue(qc_plan *plan, const Exec &x, uint64_t s_begin, uint64_t s_end, con
 void free_program_device(Program &prog) {
     if (prog.device < 0) return;
     int cur = 0;
-    hipGetDevice(&cur);
-    hipSetDevice(prog.device);
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(prog.device);
     for (void **p : {&prog.d_leaf_desc, &prog.d_leaf_block, &prog.d_base, &prog.d_fused_image, &prog.d_fused_elems,
-                     &prog.d_fused_pool,
-                     &prog.d_fused_steps}) {
-        if (*p) hipFree(*p);
+                     &prog.d_fused_pool, &prog.d_fused_items, &prog.d_fused_levels}) {
+        if (*p) (void)hipFree(*p);
         *p = nullptr;
     }
-    hipSetDevice(cur);
+    (void)hipSetDevice(cur);
 }
 
 }  // namespace qc
@@ -517,30 +545,49 @@ extern "C" size_t qc_workspace_bytes(qc_plan *plan, int64_t chunk_slices, int32_
     return qc::ws_layout(x, plan->net.n_qubits).total;
 }
 
-extern "C" qc_status qc_contract_slices(qc_plan *plan, uint64_t s_begin, uint64_t s_end, const uint8_t *bitstrings,
-                                        int32_t n_bs, qc_precision prec, void *ws, size_t ws_bytes, void *stream,
-                                        double *out_dev, double *per_slice_dev) {
-    if (!plan || !bitstrings || !ws || !out_dev) { set_error("qc_contract_slices: NULL argument"); return QC_ERR_INVALID_ARG; }
-    if (!valid_prec(prec)) { set_error("qc_contract_slices: invalid precision"); return QC_ERR_INVALID_ARG; }
-    if (prec != QC_C64) { set_error("qc_contract_slices: split precision is not built yet"); return QC_ERR_UNSUPPORTED; }
-    if (n_bs < 1 || n_bs > (1 << qc::kMaxBsBits)) { set_error("qc_contract_slices: n_bs out of range"); return QC_ERR_RANGE; }
+static qc_status contract_common(const char *fn, qc_plan *plan, uint64_t s_begin, uint64_t s_end,
+                                 const uint8_t *bitstrings, bool bits_on_device, int32_t n_bs, qc_precision prec,
+                                 void *ws, size_t ws_bytes, void *stream, double *out_dev, double *per_slice_dev) {
+    const std::string f(fn);
+    if (!plan || !bitstrings || !ws || !out_dev) { set_error(f + ": NULL argument"); return QC_ERR_INVALID_ARG; }
+    if (!valid_prec(prec)) { set_error(f + ": invalid precision"); return QC_ERR_INVALID_ARG; }
+    if (prec != QC_C64) { set_error(f + ": split precision is not built yet"); return QC_ERR_UNSUPPORTED; }
+    if (n_bs < 1 || n_bs > (1 << qc::kMaxBsBits)) { set_error(f + ": n_bs out of range"); return QC_ERR_RANGE; }
     const int k = (int)plan->sliced.size();
     const uint64_t n_slices = k >= 64 ? ~uint64_t(0) : (uint64_t(1) << k);
-    if (s_begin > s_end || s_end > n_slices) { set_error("qc_contract_slices: slice range out of bounds"); return QC_ERR_RANGE; }
-    if (!check_bitstrings(plan, bitstrings, n_bs)) { set_error("qc_contract_slices: bitstring entries must be 0 or 1"); return QC_ERR_INVALID_ARG; }
+    if (s_begin > s_end || s_end > n_slices) { set_error(f + ": slice range out of bounds"); return QC_ERR_RANGE; }
+    if (!bits_on_device && !check_bitstrings(plan, bitstrings, n_bs)) {
+        set_error(f + ": bitstring entries must be 0 or 1");
+        return QC_ERR_INVALID_ARG;
+    }
     if (s_begin == s_end) return QC_OK;
     std::string err;
     qc::Exec x;
     const int want = std::min(k, qc::ceil_log2((int64_t)(s_end - s_begin)));
     if (!qc::choose_exec(plan, qc::ceil_log2(n_bs), want, ws_bytes, x, err)) {
-        set_error("qc_contract_slices: " + err);
+        set_error(f + ": " + err);
         return err.find("workspace") != std::string::npos ? QC_ERR_NOMEM : QC_ERR_UNSUPPORTED;
     }
-    if (!qc::enqueue(plan, x, s_begin, s_end, bitstrings, n_bs, ws, (hipStream_t)stream, out_dev, per_slice_dev, err)) {
-        set_error("qc_contract_slices: " + err);
+    if (!qc::enqueue(plan, x, s_begin, s_end, bitstrings, bits_on_device, n_bs, ws, (hipStream_t)stream, out_dev,
+                     per_slice_dev, err)) {
+        set_error(f + ": " + err);
         return QC_ERR_DEVICE;
     }
     return QC_OK;
+}
+
+extern "C" qc_status qc_contract_slices(qc_plan *plan, uint64_t s_begin, uint64_t s_end, const uint8_t *bitstrings,
+                                        int32_t n_bs, qc_precision prec, void *ws, size_t ws_bytes, void *stream,
+                                        double *out_dev, double *per_slice_dev) {
+    return contract_common("qc_contract_slices", plan, s_begin, s_end, bitstrings, false, n_bs, prec, ws, ws_bytes,
+                           stream, out_dev, per_slice_dev);
+}
+
+extern "C" qc_status qc_contract_slices_dev(qc_plan *plan, uint64_t s_begin, uint64_t s_end,
+                                            const uint8_t *bitstrings_dev, int32_t n_bs, qc_precision prec, void *ws,
+                                            size_t ws_bytes, void *stream, double *out_dev, double *per_slice_dev) {
+    return contract_common("qc_contract_slices_dev", plan, s_begin, s_end, bitstrings_dev, true, n_bs, prec, ws,
+                           ws_bytes, stream, out_dev, per_slice_dev);
 }
 
 extern "C" qc_status qc_amplitude(qc_plan *plan, const uint8_t *bitstring, qc_precision prec, double out_host[2]) {

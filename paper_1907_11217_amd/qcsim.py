@@ -28,7 +28,7 @@ EXPORTED = (
     "qc_plan_build", "qc_plan_info", "qc_plan_sliced_segments", "qc_plan_slice_assignment",
     "qc_plan_describe", "qc_workspace_bytes", "qc_contract_slices", "qc_amplitude",
     "qc_gate_matrix", "qc_plan_destroy", "qc_last_error", "qc_kernel_gemm", "qc_kernel_transpose",
-    "qc_plan_set_exec", "qc_profile_enable", "qc_profile_read",
+    "qc_plan_set_exec", "qc_profile_enable", "qc_profile_read", "qc_contract_slices_dev",
 )
 EXEC_MODES = {"auto": 0, "fused": 1, "stepwise": 2}
 
@@ -104,6 +104,8 @@ def load(path: str | None = None):
         lib.qc_contract_slices.argtypes = [vp, ctypes.c_uint64, ctypes.c_uint64, vp, ctypes.c_int32, ctypes.c_int,
                                            vp, sz, vp, vp, vp]
         lib.qc_contract_slices.restype = ctypes.c_int
+        lib.qc_contract_slices_dev.argtypes = lib.qc_contract_slices.argtypes
+        lib.qc_contract_slices_dev.restype = ctypes.c_int
         lib.qc_amplitude.argtypes = [vp, vp, ctypes.c_int, vp]
         lib.qc_amplitude.restype = ctypes.c_int
         i64 = ctypes.c_int64
@@ -257,6 +259,27 @@ def qc_contract_slices(plan: Plan, s_begin: int, s_end: int, bitstrings, prec, w
     st = stream if stream is not None else torch.cuda.current_stream()
     _check(plan._lib.qc_contract_slices(
         plan.handle, ctypes.c_uint64(int(s_begin)), ctypes.c_uint64(int(s_end)), bs.ctypes.data, bs.shape[0],
+        _prec(prec), ws.data_ptr(), ws.numel() * ws.element_size(), st.cuda_stream, out_dev.data_ptr(),
+        per_slice_dev.data_ptr() if per_slice_dev is not None else None), plan._lib)
+
+
+def qc_contract_slices_dev(plan: Plan, s_begin: int, s_end: int, bits_dev, prec, ws, out_dev, per_slice_dev=None,
+                           stream=None):
+    """As qc_contract_slices, with ``bits_dev`` a contiguous uint8 device
+    tensor [n_bs, n_qubits] already on the GPU (entries 0/1, not checked)."""
+    import torch
+    if bits_dev.dtype != torch.uint8 or bits_dev.dim() != 2 or bits_dev.shape[1] != plan.n_qubits \
+            or not bits_dev.is_contiguous() or not bits_dev.is_cuda:
+        raise ValueError("bits_dev must be a contiguous uint8 device tensor [n_bs, n_qubits]")
+    n_bs = bits_dev.shape[0]
+    if out_dev.dtype != torch.float64 or out_dev.numel() < 2 * n_bs or not out_dev.is_contiguous():
+        raise ValueError("out_dev must be a contiguous float64 device tensor of n_bs x 2")
+    if per_slice_dev is not None and (per_slice_dev.dtype != torch.float64 or
+                                      per_slice_dev.numel() < 2 * n_bs * (s_end - s_begin)):
+        raise ValueError("per_slice_dev must be float64 with (s_end - s_begin) x n_bs x 2 entries")
+    st = stream if stream is not None else torch.cuda.current_stream()
+    _check(plan._lib.qc_contract_slices_dev(
+        plan.handle, ctypes.c_uint64(int(s_begin)), ctypes.c_uint64(int(s_end)), bits_dev.data_ptr(), n_bs,
         _prec(prec), ws.data_ptr(), ws.numel() * ws.element_size(), st.cuda_stream, out_dev.data_ptr(),
         per_slice_dev.data_ptr() if per_slice_dev is not None else None), plan._lib)
 

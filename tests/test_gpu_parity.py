@@ -180,3 +180,22 @@ def test_fused_mode_rejected_when_too_large():
     with pytest.raises(qcsim.QcError) as e:
         qcsim.qc_workspace_bytes(plan, 1, 1)
     assert "does not fit" in str(e.value)
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_device_resident_bitstrings_match_host(c2_setup, mode):
+    # 37 bitstrings: the padded rows of the batch reuse the last row.
+    lat, circ, bs, plan, ref = c2_setup
+    qcsim.qc_plan_set_exec(plan, mode)
+    xs = bs[:37]
+    ws = torch.empty(qcsim.qc_workspace_bytes(plan, 64, len(xs)), dtype=torch.uint8, device="cuda")
+    out_h = torch.zeros(len(xs), 2, dtype=torch.float64, device="cuda")
+    out_d = torch.zeros(len(xs), 2, dtype=torch.float64, device="cuda")
+    say(f"c2 device-resident bitstrings, 37 rows, {mode}")
+    qcsim.qc_contract_slices(plan, 0, 64, xs, "c64", ws, out_h)
+    bits_dev = torch.from_numpy(np.ascontiguousarray(xs)).cuda()
+    qcsim.qc_contract_slices_dev(plan, 0, 64, bits_dev, "c64", ws, out_d)
+    torch.cuda.synchronize()
+    assert torch.equal(out_h, out_d)
+    o = out_d.cpu().numpy()
+    check_amplitudes(o[:, 0] + 1j * o[:, 1], ref[:37], lat.n, TOL_C64)

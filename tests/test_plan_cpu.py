@@ -163,6 +163,36 @@ def test_invalid_arguments():
     assert "0 or 1" in qcsim.qc_last_error()
 
 
+@pytest.mark.parametrize("key,k", [("c1", 0), ("c2", 6), ("c3", 16)])
+def test_fused_lds_arena_has_no_live_overlap(key, k):
+    # The fused form runs all steps of a tree level together; two tensors
+    # that coexist at some level (written at or before it, last read at or
+    # after it) must not share LDS slots.
+    lat, circ, bs, spec = synth.config(key)
+    plan = qcsim.qc_plan_build(lat.n, circ, bs[0], log2_slices=k, log2_max_entries=spec.get("log2_cap", 0),
+                               greedy_trials=4, seed=1)
+    d = qcsim.qc_plan_describe(plan, 0, 0)
+    tens = d["tensors"]
+    level = {l["tensor"]: 0 for l in d["leaves"]}
+    death = {}
+    gemms = [op for op in d["ops"] if op["op"] == "gemm"]
+    for op in gemms:
+        level[op["c"]] = 1 + max(level[op["a_src"]], level[op["b_src"]])
+        death[op["a_src"]] = level[op["c"]]
+        death[op["b_src"]] = level[op["c"]]
+    n_levels = max(level.values())
+    used = sorted(level)
+    for t in used:
+        death.setdefault(t, n_levels + 1)  # the root is read after the last level
+    spans = {t: (tens[t]["lds"], tens[t]["lds"] + (1 << len(tens[t]["layout"]))) for t in used}
+    for t in used:
+        assert 0 <= spans[t][0] and spans[t][1] <= d["lds_elems"]
+    for i, t in enumerate(used):
+        for u in used[i + 1:]:
+            if max(level[t], level[u]) <= min(death[t], death[u]):
+                assert spans[t][1] <= spans[u][0] or spans[u][1] <= spans[t][0], (t, u)
+
+
 def test_idle_qubit_and_diagonal_only_wires():
     # A qubit with no gate at all: its amplitude factor is delta(x_q, 0).
     circ = np.array([[0, 0, -1, 0], [3, 0, -1, 1], [0, 0, -1, 2], [4, 0, 1, 3]], dtype=np.int32)
