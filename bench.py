@@ -34,6 +34,22 @@ def _workload_text(key, lat, spec, k, n_bs):
             f"{spec['depth']}+1, 2^{k} slices, {n_bs} bitstrings (seeds {spec['seed']}/{spec['seed'] + 1})")
 
 
+def _traffic(kind, workload):
+    """HBM bytes per launch of `kind` from the committed counter runs
+    (profiles/traffic.json: FETCH_SIZE and WRITE_SIZE, each scaled by the same
+    counter on a plain copy), or None if they were taken on another workload
+    or before the kernel source last changed."""
+    import hashlib
+    try:
+        rec = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))[kind]
+    except (OSError, KeyError, ValueError):
+        return None
+    src = open(os.path.join(ROOT, "paper_1907_11217_amd", "csrc", "kernels.hip"), "rb").read()
+    if rec.get("workload") != workload or hashlib.sha256(src).hexdigest()[:16] != rec.get("kernels_hip_sha256_16"):
+        return None
+    return 1024.0 * (rec["fetch_kib"] * rec["fetch_scale"] + rec["write_kib"] * rec["write_scale"])
+
+
 def _gemm_form(op):
     k = op["k"]
     kt = 16 if k >= 16 else k
@@ -167,7 +183,8 @@ def main():
             achieved = per_launch / (avg_ms * 1e-3) / 1e12
             roof = dict(bound=bound, achieved=achieved, peak=PEAK_FP32_TFLOPS, unit="TFLOP/s",
                         frac=achieved / PEAK_FP32_TFLOPS)
-        roof.update(kernel=dom, avg_launch_ms=avg_ms, launches_per_step=launches / args.steps, traffic=None)
+        roof.update(kernel=dom, avg_launch_ms=avg_ms, launches_per_step=launches / args.steps,
+                    traffic=_traffic(dom, args.workload))
 
     result = {
         "metric": METRIC,
