@@ -73,10 +73,16 @@ typedef struct {
     const qc_gate *gates;    /* host pointer, n_gates entries; copied by qc_plan_build */
 } qc_circuit;
 
-/* Arithmetic of the contraction steps.  QC_C64: complex FP32 (interleaved
- * complex64 tensors, FP32 MFMA).  The split forms store each real operand as
- * a hi + lo pair of BF16 or FP16 values after a per-tensor power-of-two scale
- * and accumulate hi*hi + hi*lo + lo*hi in FP32 on MFMA. */
+/* Arithmetic of the contraction steps.  Tensors are always stored as
+ * interleaved complex64.  QC_C64: complex FP32 steps (FP32 MFMA or vector ALU).
+ * QC_SPLIT_BF16 / QC_SPLIT_FP16: GEMM steps with m and n multiples of 32 read
+ * each real operand value x as x 2^-d = hi + lo in BF16 or FP16 (round to
+ * nearest even) and accumulate hi*hi + hi*lo + lo*hi in FP32 on MFMA; the
+ * power-of-two scale d is 0 for BF16 and, for FP16, floor(log2 max|x|) - 14
+ * over the tensor instance of the current chunk, with max|x| recorded by the
+ * kernel that wrote the tensor.  Smaller steps stay complex FP32.  The split
+ * forms always run stepwise (see qc_plan_set_exec).  The cross-slice sum is
+ * FP64 in every case. */
 typedef enum {
     QC_C64 = 0,
     QC_SPLIT_BF16 = 1,
@@ -146,10 +152,10 @@ qc_status qc_plan_describe(qc_plan *plan, int32_t log2_batch_slices, int32_t log
 
 /* How qc_contract_slices runs the program:
  *   QC_EXEC_AUTO (default): fused when one (slice, bitstring) contraction
- *     fits in LDS, else stepwise;
+ *     fits in LDS and prec is QC_C64, else stepwise;
  *   QC_EXEC_FUSED: one launch per super-chunk, each wavefront contracting a
- *     whole (slice, bitstring) program in LDS (QC_ERR_UNSUPPORTED later if it
- *     does not fit);
+ *     whole (slice, bitstring) program in LDS in complex FP32
+ *     (QC_ERR_UNSUPPORTED later if it does not fit or prec is split);
  *   QC_EXEC_STEPWISE: per pairwise step, an LDS-staged transpose where the
  *     layout needs it and a batched complex GEMM, with slices and bitstrings
  *     in flight as batch indices in global memory.
@@ -162,8 +168,8 @@ qc_status qc_plan_set_exec(qc_plan *plan, int32_t mode);
  * waits for the recorded events, then reports per kernel kind the launch
  * count and the summed event-to-event milliseconds since the last read (and
  * clears them).  kinds: "fused", "leaves", "transpose", "gemm_mfma",
- * "gemm_valu", "reduce64".  Not thread-safe across concurrent calls on one
- * plan. */
+ * "gemm_split_bf16", "gemm_split_fp16", "gemm_valu", "reduce64".  Not
+ * thread-safe across concurrent calls on one plan. */
 typedef struct {
     char kind[16];
     int64_t launches;

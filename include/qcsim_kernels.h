@@ -21,11 +21,24 @@ extern "C" {
  * contracted indices):
  *   C[b][i][j] = sum_l A[b][i][l] * B[b][l][j],  0 <= b < nb, i < m, j < n, l < k.
  * A is stored [nb][m][k] (a_km = 0) or [nb][k][m] (a_km = 1); B is stored
- * [nb][k][n] (b_nk = 0) or [nb][n][k] (b_nk = 1); C is [nb][m][n].  All
- * extents >= 1.  prec selects complex FP32 or a split form (hi/lo BF16 or
- * FP16 operands with FP32 accumulation, per-call power-of-two scaling). */
+ * [nb][k][n] (b_nk = 0) or [nb][n][k] (b_nk = 1); C is [nb][m][n]; all are
+ * caller-owned device buffers, extents >= 1.
+ *
+ * prec = QC_C64: complex FP32 (MFMA when m and n are multiples of 32 and k is
+ * 2, 4, 8 or a multiple of 16; else the vector ALU).  prec = QC_SPLIT_BF16 or
+ * QC_SPLIT_FP16: when m and n are multiples of 32 and k >= 2, each real
+ * operand value x is written as x 2^-d = h + l (h = rn(x 2^-d), l = rn(x 2^-d
+ * - h) in the 16-bit type), each real product is h h' + h l' + l h' with FP32
+ * accumulation on MFMA, and C is complex FP32 scaled back by 2^(d_A + d_B);
+ * d = 0 for BF16, d = floor(log2 max|x|) - 14 over the whole operand for FP16
+ * (max over real and imaginary parts; d = 0 for a zero operand).  Other
+ * shapes use the FP32 vector-ALU form.
+ *
+ * scale_ws: device buffer of 3 uint32, required for QC_SPLIT_FP16, optional
+ * otherwise (NULL).  When given, the call overwrites it with the float bits
+ * of max(|re|, |im|) over A, over B, and over the C it writes. */
 qc_status qc_kernel_gemm(const void *A, const void *B, void *C, int64_t nb, int64_t m, int64_t n, int64_t k,
-                         int32_t a_km, int32_t b_nk, qc_precision prec, void *stream);
+                         int32_t a_km, int32_t b_nk, qc_precision prec, void *scale_ws, void *stream);
 
 /* Bit-permuting transpose of a rank-r tensor (2^r complex64 values): the
  * value at input offset i goes to the output offset whose bit perm[p] equals

@@ -17,7 +17,8 @@ struct LeafDesc {
     int32_t r_out;               // output rank
     int32_t n_fix;               // base bits fixed by the chunk's slice id
     int32_t n_oq;                // base bits fixed by a qubit of the bitstring
-    int32_t pad0, pad1;
+    int32_t first_block;         // stepwise form: first block of this leaf in the launch
+    int32_t amax_slot;           // stepwise form: max|x| slot of this leaf's tensor
     int8_t src[kLeafMaxRank];    // output bit p -> base bit, or 64 + bitstring bit
     int8_t fix_pos[kLeafMaxBase];
     int8_t fix_j[kLeafMaxBase];  // slice bit j (< 64)
@@ -47,6 +48,17 @@ struct TransposeDesc {
 
 // Batched complex GEMM C[b][m][n] = sum_k A[b][m][k] B[b][k][n] (element
 // strides, complex64 interleaved).
+//
+// Split precision (prec = 1 BF16, 2 FP16): every real operand value x is
+// scaled by 2^-d of its tensor and split as h = rn(x 2^-d), l = rn(x 2^-d - h)
+// in the 16-bit type; each real product is accumulated in FP32 as
+// h h' + h l' + l h' and the result scaled back by 2^(d_A + d_B).  d = 0 for
+// BF16 (FP32's exponent range); for FP16 d = floor(log2 max|x|) - 14, so the
+// largest |x| 2^-d lies in [2^14, 2^15).  max|x| of each tensor comes from
+// amax_* (the float bits of max(|re|, |im|) over the tensor, kept by the
+// kernel that wrote it); a kernel that writes C with amax_c set folds its
+// outputs in with atomicMax.
+enum GemmPrec { kPrecC64 = 0, kPrecBF16 = 1, kPrecFP16 = 2 };
 struct GemmDesc {
     const float2 *A;
     const float2 *B;
@@ -55,7 +67,15 @@ struct GemmDesc {
     int64_t sAb, sAm, sAk;
     int64_t sBb, sBk, sBn;
     int64_t sCb, sCm, sCn;
+    int32_t prec;
+    const uint32_t *amax_a, *amax_b;
+    uint32_t *amax_c;
 };
+
+// Records max(|re|, |im|) of n values into *amax (atomicMax on float bits).
+void launch_absmax(const float2 *x, int64_t n, uint32_t *amax, hipStream_t st);
+// Sets n uint32 to zero (a fill kernel, so the op can sit in a captured graph).
+void launch_zero_u32(uint32_t *p, int64_t n, hipStream_t st);
 
 // Fused form: one wavefront runs the whole program of (slice, bitstring)
 // pairs with every tensor in LDS, contracting each step directly from the
@@ -113,9 +133,10 @@ void launch_fused_pairs(const FusedParams &p, int pairs, int pair_elems, int zer
 void launch_reduce64(const float2 *partial, int m, int n_bs, uint64_t sc, int64_t n_blocks, uint64_t lo, uint64_t hi,
                      uint64_t s_begin, double *out, double *per_slice, hipStream_t st);
 
+// amax: per program tensor slots (indexed by leaf tensor id), or null.
 void launch_leaves(const LeafDesc *descs, const int32_t *block_leaf, int n_blocks, const double2 *base,
                    float2 *tensors, const uint8_t *bits, int n_qubits, int n_bs, uint64_t chunk_base,
-                   hipStream_t st);
+                   uint32_t *amax, hipStream_t st);
 void launch_transpose(const TransposeDesc &d, hipStream_t st);
 const char *launch_gemm(const GemmDesc &d, hipStream_t st);  // returns the form launched
 

@@ -1,6 +1,6 @@
 // Step kernels for gfx950: leaf instantiation, LDS-staged bit-permuting
-// transpose, complex batched GEMM (FP32 MFMA and a VALU form for shapes below
-// the MFMA tile), and the FP64 cross-slice reduction.
+// transpose, complex batched GEMM (FP32 MFMA, split BF16/FP16 MFMA, and a VALU
+// form for shapes below the MFMA tile), and the FP64 cross-slice reduction.
 #include <hip/hip_runtime.h>
 
 #include "kernels.h"
@@ -13,35 +13,76 @@ namespace qc {
 // the chunk's slice id (sliced segments not in flight), or fixed by the
 // bitstring (output segments); the bitstring bits of the batch become extra
 // output bits.  One thread per output element.
+// max(|re|, |im|) of the wavefront's values folded into *amax (uint32 order
+// of non-negative floats is their numeric order).  Every lane must call it.
+__device__ __forceinline__ void wave_amax(float v, uint32_t *amax) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+    if ((threadIdx.x & 63) == 0) atomicMax(amax, __float_as_uint(v));
+}
+
 __global__ void __launch_bounds__(256) leaf_kernel(const LeafDesc *__restrict__ descs,
                                                    const int32_t *__restrict__ block_leaf,
                                                    const double2 *__restrict__ base, float2 *__restrict__ tensors,
                                                    const uint8_t *__restrict__ bits, int n_qubits, int n_bs,
-                                                   uint64_t chunk_base) {
+                                                   uint64_t chunk_base, uint32_t *__restrict__ amax) {
     const int leaf = block_leaf[blockIdx.x];
     const LeafDesc &d = descs[leaf];
-    const int64_t e = int64_t(blockIdx.x - d.pad0) * blockDim.x + threadIdx.x;
-    if (e >= (int64_t(1) << d.r_out)) return;
-    int bs = 0, bidx = 0;
-    for (int p = 0; p < d.r_out; ++p) {
-        const int bit = int((e >> p) & 1);
-        const int s = d.src[p];
-        if (s >= 64) bs |= bit << (s - 64);
-        else bidx |= bit << s;
+    const int64_t e = int64_t(blockIdx.x - d.first_block) * blockDim.x + threadIdx.x;
+    float mx = 0.f;
+    if (e < (int64_t(1) << d.r_out)) {
+        int bs = 0, bidx = 0;
+        for (int p = 0; p < d.r_out; ++p) {
+            const int bit = int((e >> p) & 1);
+            const int s = d.src[p];
+            if (s >= 64) bs |= bit << (s - 64);
+            else bidx |= bit << s;
+        }
+        bs = min(bs, n_bs - 1);  // padded bitstrings repeat the last one (their results are dropped)
+        for (int i = 0; i < d.n_fix; ++i) bidx |= int((chunk_base >> d.fix_j[i]) & 1) << d.fix_pos[i];
+        for (int i = 0; i < d.n_oq; ++i) bidx |= int(bits[int64_t(bs) * n_qubits + d.oq_q[i]] & 1) << d.oq_pos[i];
+        const double2 v = base[d.base_off + bidx];
+        const float2 f = make_float2(float(v.x), float(v.y));
+        tensors[d.out_off + e] = f;
+        mx = fmaxf(fabsf(f.x), fabsf(f.y));
     }
-    bs = min(bs, n_bs - 1);  // padded bitstrings repeat the last one (their results are dropped)
-    for (int i = 0; i < d.n_fix; ++i) bidx |= int((chunk_base >> d.fix_j[i]) & 1) << d.fix_pos[i];
-    for (int i = 0; i < d.n_oq; ++i) bidx |= int(bits[int64_t(bs) * n_qubits + d.oq_q[i]] & 1) << d.oq_pos[i];
-    const double2 v = base[d.base_off + bidx];
-    tensors[d.out_off + e] = make_float2(float(v.x), float(v.y));
+    if (amax) wave_amax(mx, amax + d.amax_slot);
 }
 
 void launch_leaves(const LeafDesc *descs, const int32_t *block_leaf, int n_blocks, const double2 *base,
                    float2 *tensors, const uint8_t *bits, int n_qubits, int n_bs, uint64_t chunk_base,
-                   hipStream_t st) {
+                   uint32_t *amax, hipStream_t st) {
     if (n_blocks <= 0) return;
     hipLaunchKernelGGL(leaf_kernel, dim3(n_blocks), dim3(256), 0, st, descs, block_leaf, base, tensors, bits,
-                       n_qubits, n_bs, chunk_base);
+                       n_qubits, n_bs, chunk_base, amax);
+}
+
+// ------------------------------------------------------------ scale slots
+__global__ void __launch_bounds__(256) absmax_kernel(const float2 *__restrict__ x, int64_t n, uint32_t *amax) {
+    float mx = 0.f;
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) {
+        const float2 v = x[i];
+        mx = fmaxf(mx, fmaxf(fabsf(v.x), fabsf(v.y)));
+    }
+    wave_amax(mx, amax);
+}
+
+void launch_absmax(const float2 *x, int64_t n, uint32_t *amax, hipStream_t st) {
+    int64_t grid = (n + 255) / 256;
+    grid = grid < 1 ? 1 : (grid > 1024 ? 1024 : grid);
+    hipLaunchKernelGGL(absmax_kernel, dim3((unsigned)grid), dim3(256), 0, st, x, n, amax);
+}
+
+__global__ void __launch_bounds__(256) zero_u32_kernel(uint32_t *p, int64_t n) {
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+        p[i] = 0u;
+}
+
+void launch_zero_u32(uint32_t *p, int64_t n, hipStream_t st) {
+    if (n <= 0) return;
+    int64_t grid = (n + 255) / 256;
+    grid = grid > 1024 ? 1024 : grid;
+    hipLaunchKernelGGL(zero_u32_kernel, dim3((unsigned)grid), dim3(256), 0, st, p, n);
 }
 
 // --------------------------------------------------------------- transpose
@@ -84,9 +125,11 @@ void launch_transpose(const TransposeDesc &d, hipStream_t st) {
 
 // -------------------------------------------------------------- VALU GEMM
 // One thread per output element; used when m or n is below the MFMA tile or
-// k is 1.  FP32 complex accumulation in k order.
+// k is 1.  FP32 complex accumulation in k order (also for the split
+// precisions: these shapes gain nothing from 16-bit operands).
 __global__ void __launch_bounds__(256) gemm_valu_kernel(GemmDesc d) {
     const int64_t total = d.nb * d.m * d.n;
+    float mx = 0.f;
     for (int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; idx < total;
          idx += int64_t(gridDim.x) * blockDim.x) {
         const int64_t ni = idx % d.n;
@@ -105,7 +148,9 @@ __global__ void __launch_bounds__(256) gemm_valu_kernel(GemmDesc d) {
             im = fmaf(x.y, y.x, im);
         }
         d.C[bi * d.sCb + mi * d.sCm + ni * d.sCn] = make_float2(re, im);
+        mx = fmaxf(mx, fmaxf(fabsf(re), fabsf(im)));
     }
+    if (d.amax_c) wave_amax(mx, d.amax_c);
 }
 
 // -------------------------------------------------------------- MFMA GEMM
@@ -177,21 +222,156 @@ __global__ void __launch_bounds__(64 * WM * WN) gemm_mfma_kernel(GemmDesc d) {
     }
 }
 
-const char *launch_gemm(const GemmDesc &d, hipStream_t st) {
-    // The MFMA form needs whole 32x32 tiles and a K that the LDS slab divides.
-    const int64_t kt_try = d.k >= 16 ? 16 : d.k;
-    const bool k_ok = (kt_try == 2 || kt_try == 4 || kt_try == 8 || kt_try == 16) && d.k % kt_try == 0;
-    const bool mfma = k_ok && d.m % 32 == 0 && d.n % 32 == 0;
-    if (!mfma) {
-        const int64_t total = d.nb * d.m * d.n;
-        int64_t grid = (total + 255) / 256;
-        if (grid > 262144) grid = 262144;
-        hipLaunchKernelGGL(gemm_valu_kernel, dim3((unsigned)grid), dim3(256), 0, st, d);
-        return "gemm_valu";
+// ------------------------------------------------ split-precision MFMA GEMM
+// Operands stay complex64 in memory.  While a K slab of 16 complex values is
+// staged into LDS, each real part x becomes x 2^-d = h + l (h, l in the 16-bit
+// type, round to nearest even), stored in four planes per operand: hi re,
+// hi im, lo re, lo im, each [row][16] so that one lane's MFMA operand (8
+// consecutive k of one row) is a single 16-byte LDS read.  Each real product
+// X Y is accumulated as Xh Yh + Xh Yl + Xl Yh on v_mfma_f32_32x32x16_{f16,bf16};
+// the complex product takes four of them (4M), so 12 MFMAs per slab and wave.
+// The product -Ai Bi uses Ai with flipped sign bits (exact).  K need not be a
+// multiple of 16: the last slab is padded with zeros.
+typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ floatx16 mfma16(half8 a, half8 b, floatx16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ floatx16 mfma16(bf16x8 a, bf16x8 b, floatx16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+}
+template <typename V> __device__ __forceinline__ V negate16(V v) {
+    return __builtin_bit_cast(V, __builtin_bit_cast(u32x4, v) ^ 0x80008000u);
+}
+
+// Scale exponent of a tensor from its recorded max|x|: FP16 puts the largest
+// magnitude in [2^14, 2^15); BF16 (FP32's exponent range) and zero, infinite
+// or missing maxima use 0.
+template <typename T> __device__ __forceinline__ int split_exp(const uint32_t *amax);
+template <> __device__ __forceinline__ int split_exp<__bf16>(const uint32_t *) { return 0; }
+template <> __device__ __forceinline__ int split_exp<_Float16>(const uint32_t *amax) {
+    if (!amax) return 0;
+    const float m = __uint_as_float(*amax);
+    if (!(m > 0.f) || !(m <= 3.4028235e38f)) return 0;
+    return ilogbf(m) - 14;
+}
+
+template <typename T, int WM, int WN>
+__global__ void __launch_bounds__(64 * WM * WN) gemm_split_kernel(GemmDesc d) {
+    typedef T V __attribute__((ext_vector_type(8)));
+    constexpr int TM = 32 * WM, TN = 32 * WN, NT = 64 * WM * WN, KT = 16;
+    __shared__ __attribute__((aligned(16))) T As[4][TM][KT];
+    __shared__ __attribute__((aligned(16))) T Bs[4][TN][KT];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int wm = wave / WN, wn = wave % WN;
+    const int64_t tiles_m = d.m / TM, tiles_n = d.n / TN;
+    const int64_t n_tiles = d.nb * tiles_m * tiles_n;
+    const bool a_k_fast = d.sAk == 1;
+    const bool b_n_fast = d.sBn == 1;
+    const int ea = split_exp<T>(d.amax_a), eb = split_exp<T>(d.amax_b);
+    float mx = 0.f;
+    for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+        const int64_t tn = tile % tiles_n;
+        const int64_t tm = (tile / tiles_n) % tiles_m;
+        const int64_t bi = tile / (tiles_n * tiles_m);
+        const float2 *Ab = d.A + bi * d.sAb + tm * TM * d.sAm;
+        const float2 *Bb = d.B + bi * d.sBb + tn * TN * d.sBn;
+        floatx16 acc_re, acc_im;
+        for (int v = 0; v < 16; ++v) { acc_re[v] = 0.f; acc_im[v] = 0.f; }
+        for (int64_t k0 = 0; k0 < d.k; k0 += KT) {
+            for (int e = threadIdx.x; e < TM * KT; e += NT) {
+                int i, kk;
+                if (a_k_fast) { i = e / KT; kk = e % KT; } else { i = e % TM; kk = e / TM; }
+                float2 v = make_float2(0.f, 0.f);
+                if (k0 + kk < d.k) v = Ab[i * d.sAm + (k0 + kk) * d.sAk];
+                const float xr = ldexpf(v.x, -ea), xi = ldexpf(v.y, -ea);
+                const T hr = T(xr), hi = T(xi);
+                As[0][i][kk] = hr;
+                As[1][i][kk] = hi;
+                As[2][i][kk] = T(xr - float(hr));
+                As[3][i][kk] = T(xi - float(hi));
+            }
+            for (int e = threadIdx.x; e < TN * KT; e += NT) {
+                int j, kk;
+                if (b_n_fast) { j = e % TN; kk = e / TN; } else { j = e / KT; kk = e % KT; }
+                float2 v = make_float2(0.f, 0.f);
+                if (k0 + kk < d.k) v = Bb[(k0 + kk) * d.sBk + j * d.sBn];
+                const float xr = ldexpf(v.x, -eb), xi = ldexpf(v.y, -eb);
+                const T hr = T(xr), hi = T(xi);
+                Bs[0][j][kk] = hr;
+                Bs[1][j][kk] = hi;
+                Bs[2][j][kk] = T(xr - float(hr));
+                Bs[3][j][kk] = T(xi - float(hi));
+            }
+            __syncthreads();
+            const int ra = wm * 32 + (lane & 31), rb = wn * 32 + (lane & 31), kq = (lane >> 5) * 8;
+            const V arh = *(const V *)&As[0][ra][kq], aih = *(const V *)&As[1][ra][kq];
+            const V arl = *(const V *)&As[2][ra][kq], ail = *(const V *)&As[3][ra][kq];
+            const V brh = *(const V *)&Bs[0][rb][kq], bih = *(const V *)&Bs[1][rb][kq];
+            const V brl = *(const V *)&Bs[2][rb][kq], bil = *(const V *)&Bs[3][rb][kq];
+            const V naih = negate16(aih), nail = negate16(ail);
+            acc_re = mfma16(arh, brh, acc_re);
+            acc_re = mfma16(arh, brl, acc_re);
+            acc_re = mfma16(arl, brh, acc_re);
+            acc_re = mfma16(naih, bih, acc_re);
+            acc_re = mfma16(naih, bil, acc_re);
+            acc_re = mfma16(nail, bih, acc_re);
+            acc_im = mfma16(arh, bih, acc_im);
+            acc_im = mfma16(arh, bil, acc_im);
+            acc_im = mfma16(arl, bih, acc_im);
+            acc_im = mfma16(aih, brh, acc_im);
+            acc_im = mfma16(aih, brl, acc_im);
+            acc_im = mfma16(ail, brh, acc_im);
+            __syncthreads();
+        }
+        float2 *Cb = d.C + bi * d.sCb + (tm * TM + wm * 32) * d.sCm + (tn * TN + wn * 32) * d.sCn;
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            const int row = (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
+            const int col = lane & 31;
+            const float re = ldexpf(acc_re[v], ea + eb), im = ldexpf(acc_im[v], ea + eb);
+            Cb[row * d.sCm + col * d.sCn] = make_float2(re, im);
+            mx = fmaxf(mx, fmaxf(fabsf(re), fabsf(im)));
+        }
     }
+    if (d.amax_c) wave_amax(mx, d.amax_c);
+}
+
+const char *launch_gemm(const GemmDesc &d, hipStream_t st) {
+    const bool tiles32 = d.m % 32 == 0 && d.n % 32 == 0;
     const int wm = d.m % 64 == 0 ? 2 : 1, wn = d.n % 64 == 0 ? 2 : 1;
     const int64_t tiles = d.nb * (d.m / (32 * wm)) * (d.n / (32 * wn));
     const unsigned grid = (unsigned)(tiles < 1048576 ? tiles : 1048576);
+    // The split forms need whole 32x32 tiles (K is zero-padded to the slab).
+    if (d.prec != kPrecC64 && tiles32 && d.k >= 2) {
+#define QC_SPLIT_CASE(T, WM, WN)                                                                       \
+    if (wm == WM && wn == WN) {                                                                        \
+        hipLaunchKernelGGL((gemm_split_kernel<T, WM, WN>), dim3(grid), dim3(64 * WM * WN), 0, st, d);    \
+        return d.prec == kPrecFP16 ? "gemm_split_fp16" : "gemm_split_bf16";                            \
+    }
+        if (d.prec == kPrecFP16) {
+            QC_SPLIT_CASE(_Float16, 1, 1) QC_SPLIT_CASE(_Float16, 1, 2) QC_SPLIT_CASE(_Float16, 2, 1)
+            QC_SPLIT_CASE(_Float16, 2, 2)
+        } else {
+            QC_SPLIT_CASE(__bf16, 1, 1) QC_SPLIT_CASE(__bf16, 1, 2) QC_SPLIT_CASE(__bf16, 2, 1)
+            QC_SPLIT_CASE(__bf16, 2, 2)
+        }
+#undef QC_SPLIT_CASE
+    }
+    // The FP32 MFMA form needs whole 32x32 tiles and a K that the LDS slab
+    // divides; it records no max|x| (the split forms never route here).
+    const int64_t kt_try = d.k >= 16 ? 16 : d.k;
+    const bool k_ok = (kt_try == 2 || kt_try == 4 || kt_try == 8 || kt_try == 16) && d.k % kt_try == 0;
+    if (d.prec != kPrecC64 || !k_ok || !tiles32) {
+        const int64_t total = d.nb * d.m * d.n;
+        int64_t g = (total + 255) / 256;
+        if (g > 262144) g = 262144;
+        hipLaunchKernelGGL(gemm_valu_kernel, dim3((unsigned)g), dim3(256), 0, st, d);
+        return "gemm_valu";
+    }
     const int kt = d.k >= 16 ? 16 : (int)d.k;
 #define QC_GEMM_CASE(WM, WN, KT)                                                                        \
     if (wm == WM && wn == WN && kt == KT) {                                                               \

@@ -54,17 +54,22 @@ struct Exec {
     bool fused = false;
     int m = 0;          // log2 bitstrings (padded)
     int lp = 6;         // log2 super-chunk slices
+    int prec = kPrecC64;
 };
 
+// Workspace: bitstrings (when handed over from the host), the super-chunk's
+// slice values, per-tensor max|x| slots (split FP16 scale bookkeeping), and
+// the stepwise program's tensor region.
 struct WsLayout {
-    size_t bits_off, partial_off, tensor_off, total;
+    size_t bits_off, partial_off, amax_off, tensor_off, total;
 };
 
 WsLayout ws_layout(const Exec &x, int n_qubits) {
     WsLayout w;
     w.bits_off = 0;
     w.partial_off = align256(size_t(n_qubits) << x.m);
-    w.tensor_off = w.partial_off + align256((size_t(1) << (x.lp + x.m)) * sizeof(float2));
+    w.amax_off = w.partial_off + align256((size_t(1) << (x.lp + x.m)) * sizeof(float2));
+    w.tensor_off = w.amax_off + (x.fused ? 0 : align256(x.prog->tensors.size() * sizeof(uint32_t)));
     w.total = w.tensor_off + (x.fused ? 0 : align256(size_t(x.prog->tensor_elems) * sizeof(float2)));
     return w;
 }
@@ -94,15 +99,19 @@ bool fused_fits(const qc_plan *plan, const Program &p) {
 // Picks the execution for a range of n_range slices with 2^m bitstrings that
 // fits ws_bytes (ws_bytes = 0: no limit, used by the workspace query with the
 // caller's chunk size in `want_lp`).
-bool choose_exec(qc_plan *plan, int m, int want_lp, size_t ws_bytes, Exec &x, std::string &err) {
+// The split precisions run stepwise: the fused form computes its small dot
+// products on the vector ALU in FP32.
+bool choose_exec(qc_plan *plan, int m, int want_lp, int prec, size_t ws_bytes, Exec &x, std::string &err) {
     const int k = (int)plan->sliced.size();
     const int nq = plan->net.n_qubits;
     x.m = m;
+    x.prec = prec;
     Program *pf = get_program(plan, 0, 0, err);
     if (!pf) return false;
-    const bool fits = fused_fits(plan, *pf);
+    const bool fits = prec == kPrecC64 && fused_fits(plan, *pf);
     if (plan->exec_mode == QC_EXEC_FUSED && !fits) {
-        err = "the fused form does not fit in LDS for this plan";
+        err = prec == kPrecC64 ? "the fused form does not fit in LDS for this plan"
+                               : "the fused form runs complex FP32 only";
         return false;
     }
     if (fits && plan->exec_mode != QC_EXEC_STEPWISE) {
@@ -143,7 +152,6 @@ void leaf_table(const qc_plan *plan, const Program &prog, bool lds, std::vector<
         slice_bit[plan->sliced[j]] = (int)j;
         if ((int)j >= prog.b) fixed[plan->sliced[j]] = 1;
     }
-    int32_t first_elem = 0;
     for (size_t li = 0; li < prog.leaves.size(); ++li) {
         const Tensor &T = net.leaves[prog.leaves[li].leaf];
         const int tid = prog.leaves[li].tensor;
@@ -179,11 +187,10 @@ void leaf_table(const qc_plan *plan, const Program &prog, bool lds, std::vector<
         }
         for (const cplx &v : T.data) base.push_back(make_double2(v.real(), v.imag()));
         if (lds) {
-            d.pad1 = first_elem;
             for (int64_t e = 0; e < (int64_t(1) << ro); ++e) block_or_elem.push_back((int32_t)li);
-            first_elem += 1 << ro;
         } else {
-            d.pad0 = (int32_t)block_or_elem.size();
+            d.first_block = (int32_t)block_or_elem.size();
+            d.amax_slot = tid;
             const int64_t nblk = ((int64_t(1) << ro) + 255) / 256;
             for (int64_t b = 0; b < nblk; ++b) block_or_elem.push_back((int32_t)li);
         }
@@ -389,8 +396,15 @@ TransposeDesc make_transpose(const Program &prog, const TransposeOp &t, float2 *
     return make_transpose_desc(tensors + prog.tensors[t.src].offset, tensors + prog.tensors[t.dst].offset, r, perm);
 }
 
-GemmDesc make_gemm(const Program &prog, const GemmOp &g, float2 *tensors) {
+// amax: per-tensor max|x| slots (split FP16) or null; slot[t] maps a
+// transposed tensor to the slot of the tensor it was copied from.
+GemmDesc make_gemm(const Program &prog, const GemmOp &g, float2 *tensors, int prec, uint32_t *amax,
+                   const std::vector<int> &slot) {
     GemmDesc d;
+    d.prec = prec;
+    d.amax_a = amax ? amax + slot[g.a] : nullptr;
+    d.amax_b = amax ? amax + slot[g.b] : nullptr;
+    d.amax_c = amax ? amax + slot[g.c] : nullptr;
     d.A = tensors + prog.tensors[g.a].offset;
     d.B = tensors + prog.tensors[g.b].offset;
     d.C = tensors + prog.tensors[g.c].offset;
@@ -444,6 +458,12 @@ bool enqueue(qc_plan *plan, const Exec &x, uint64_t s_begin, uint64_t s_end, con
     const uint8_t *bits = bits_in;
     float2 *partial = (float2 *)((char *)ws + w.partial_off);
     float2 *tensors = (float2 *)((char *)ws + w.tensor_off);
+    // Scale bookkeeping only where a scale is derived from it (FP16).
+    uint32_t *amax = (!x.fused && x.prec == kPrecFP16) ? (uint32_t *)((char *)ws + w.amax_off) : nullptr;
+    std::vector<int> slot(prog.tensors.size());
+    for (size_t t = 0; t < slot.size(); ++t) slot[t] = (int)t;
+    for (const Op &op : prog.ops)
+        if (op.kind == Op::TRANSPOSE) slot[prog.transposes[op.index].dst] = slot[prog.transposes[op.index].src];
     if (!bits_on_device) {
         uint8_t *dst = (uint8_t *)ws + w.bits_off;
         QC_HIP(hipMemcpyAsync(dst, bits_in, size_t(n_bs) * nq, hipMemcpyHostToDevice, st));
@@ -482,8 +502,10 @@ bool enqueue(qc_plan *plan, const Exec &x, uint64_t s_begin, uint64_t s_end, con
             const uint64_t chunk = uint64_t(1) << prog.b;
             for (uint64_t cb = lo & ~(chunk - 1); cb < hi; cb += chunk) {
                 prof.begin();
+                if (amax) launch_zero_u32(amax, (int64_t)slot.size(), st);
                 launch_leaves((const LeafDesc *)prog.d_leaf_desc, (const int32_t *)prog.d_leaf_block,
-                              prog.n_leaf_blocks, (const double2 *)prog.d_base, tensors, bits, nq, n_bs, cb, st);
+                              prog.n_leaf_blocks, (const double2 *)prog.d_base, tensors, bits, nq, n_bs, cb, amax,
+                              st);
                 prof.end("leaves");
                 for (const Op &op : prog.ops) {
                     prof.begin();
@@ -491,7 +513,7 @@ bool enqueue(qc_plan *plan, const Exec &x, uint64_t s_begin, uint64_t s_end, con
                         launch_transpose(make_transpose(prog, prog.transposes[op.index], tensors), st);
                         prof.end("transpose");
                     } else {
-                        prof.end(launch_gemm(make_gemm(prog, prog.gemms[op.index], tensors), st));
+                        prof.end(launch_gemm(make_gemm(prog, prog.gemms[op.index], tensors, x.prec, amax, slot), st));
                     }
                 }
                 QC_HIP(hipMemcpyAsync(partial + ((cb - sc) << x.m), tensors + prog.tensors[prog.root].offset,
@@ -532,6 +554,10 @@ static bool check_bitstrings(const qc_plan *plan, const uint8_t *bits, int n_bs)
 
 static bool valid_prec(qc_precision p) { return p == QC_C64 || p == QC_SPLIT_BF16 || p == QC_SPLIT_FP16; }
 
+namespace qc {
+int prec_code(qc_precision p) { return p == QC_SPLIT_FP16 ? kPrecFP16 : (p == QC_SPLIT_BF16 ? kPrecBF16 : kPrecC64); }
+}  // namespace qc
+
 extern "C" size_t qc_workspace_bytes(qc_plan *plan, int64_t chunk_slices, int32_t n_bs, qc_precision prec) {
     if (!plan || chunk_slices < 1 || n_bs < 1 || n_bs > (1 << qc::kMaxBsBits) || !valid_prec(prec)) {
         set_error("qc_workspace_bytes: invalid argument");
@@ -541,7 +567,10 @@ extern "C" size_t qc_workspace_bytes(qc_plan *plan, int64_t chunk_slices, int32_
     if (b > (int)plan->sliced.size()) { set_error("qc_workspace_bytes: more slices than the plan has"); return 0; }
     std::string err;
     qc::Exec x;
-    if (!qc::choose_exec(plan, qc::ceil_log2(n_bs), b, 0, x, err)) { set_error("qc_workspace_bytes: " + err); return 0; }
+    if (!qc::choose_exec(plan, qc::ceil_log2(n_bs), b, qc::prec_code(prec), 0, x, err)) {
+        set_error("qc_workspace_bytes: " + err);
+        return 0;
+    }
     return qc::ws_layout(x, plan->net.n_qubits).total;
 }
 
@@ -551,7 +580,6 @@ static qc_status contract_common(const char *fn, qc_plan *plan, uint64_t s_begin
     const std::string f(fn);
     if (!plan || !bitstrings || !ws || !out_dev) { set_error(f + ": NULL argument"); return QC_ERR_INVALID_ARG; }
     if (!valid_prec(prec)) { set_error(f + ": invalid precision"); return QC_ERR_INVALID_ARG; }
-    if (prec != QC_C64) { set_error(f + ": split precision is not built yet"); return QC_ERR_UNSUPPORTED; }
     if (n_bs < 1 || n_bs > (1 << qc::kMaxBsBits)) { set_error(f + ": n_bs out of range"); return QC_ERR_RANGE; }
     const int k = (int)plan->sliced.size();
     const uint64_t n_slices = k >= 64 ? ~uint64_t(0) : (uint64_t(1) << k);
@@ -564,7 +592,7 @@ static qc_status contract_common(const char *fn, qc_plan *plan, uint64_t s_begin
     std::string err;
     qc::Exec x;
     const int want = std::min(k, qc::ceil_log2((int64_t)(s_end - s_begin)));
-    if (!qc::choose_exec(plan, qc::ceil_log2(n_bs), want, ws_bytes, x, err)) {
+    if (!qc::choose_exec(plan, qc::ceil_log2(n_bs), want, qc::prec_code(prec), ws_bytes, x, err)) {
         set_error(f + ": " + err);
         return err.find("workspace") != std::string::npos ? QC_ERR_NOMEM : QC_ERR_UNSUPPORTED;
     }
@@ -672,9 +700,17 @@ extern "C" void qc_plan_destroy(qc_plan *plan) {
 }
 
 extern "C" qc_status qc_kernel_gemm(const void *A, const void *B, void *C, int64_t nb, int64_t m, int64_t n, int64_t k,
-                                    int32_t a_km, int32_t b_nk, qc_precision prec, void *stream) {
-    if (!A || !B || !C || nb < 1 || m < 1 || n < 1 || k < 1) { set_error("qc_kernel_gemm: invalid argument"); return QC_ERR_INVALID_ARG; }
-    if (prec != QC_C64) { set_error("qc_kernel_gemm: split precision is not built yet"); return QC_ERR_UNSUPPORTED; }
+                                    int32_t a_km, int32_t b_nk, qc_precision prec, void *scale_ws, void *stream) {
+    if (!A || !B || !C || nb < 1 || m < 1 || n < 1 || k < 1 || !valid_prec(prec)) {
+        set_error("qc_kernel_gemm: invalid argument");
+        return QC_ERR_INVALID_ARG;
+    }
+    if (prec == QC_SPLIT_FP16 && !scale_ws) {
+        set_error("qc_kernel_gemm: split FP16 needs scale_ws");
+        return QC_ERR_INVALID_ARG;
+    }
+    const hipStream_t st = (hipStream_t)stream;
+    uint32_t *amax = (uint32_t *)scale_ws;
     qc::GemmDesc d;
     d.A = (const float2 *)A; d.B = (const float2 *)B; d.C = (float2 *)C;
     d.nb = nb; d.m = m; d.n = n; d.k = k;
@@ -683,7 +719,16 @@ extern "C" qc_status qc_kernel_gemm(const void *A, const void *B, void *C, int64
     d.sBb = k * n;
     if (b_nk) { d.sBn = k; d.sBk = 1; } else { d.sBk = n; d.sBn = 1; }
     d.sCb = m * n; d.sCm = n; d.sCn = 1;
-    qc::launch_gemm(d, (hipStream_t)stream);
+    d.prec = qc::prec_code(prec);
+    d.amax_a = amax;
+    d.amax_b = amax ? amax + 1 : nullptr;
+    d.amax_c = amax ? amax + 2 : nullptr;
+    if (amax) {
+        qc::launch_zero_u32(amax, 3, st);
+        qc::launch_absmax(d.A, nb * m * k, amax, st);
+        qc::launch_absmax(d.B, nb * k * n, amax + 1, st);
+    }
+    qc::launch_gemm(d, st);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) { set_error(std::string("qc_kernel_gemm: ") + hipGetErrorString(e)); return QC_ERR_DEVICE; }
     return QC_OK;

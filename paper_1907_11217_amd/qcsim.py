@@ -109,7 +109,8 @@ def load(path: str | None = None):
         lib.qc_amplitude.argtypes = [vp, vp, ctypes.c_int, vp]
         lib.qc_amplitude.restype = ctypes.c_int
         i64 = ctypes.c_int64
-        lib.qc_kernel_gemm.argtypes = [vp, vp, vp, i64, i64, i64, i64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int, vp]
+        lib.qc_kernel_gemm.argtypes = [vp, vp, vp, i64, i64, i64, i64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int, vp,
+                                       vp]
         lib.qc_kernel_gemm.restype = ctypes.c_int
         lib.qc_kernel_transpose.argtypes = [vp, vp, ctypes.c_int32, vp, vp]
         lib.qc_kernel_transpose.restype = ctypes.c_int
@@ -285,8 +286,11 @@ def qc_contract_slices_dev(plan: Plan, s_begin: int, s_end: int, bits_dev, prec,
 
 
 def qc_kernel_gemm(A, B, C, nb: int, m: int, n: int, k: int, a_km: bool = False, b_nk: bool = False,
-                   prec="c64", stream=None):
-    """One batched complex GEMM step on torch complex64 device tensors."""
+                   prec="c64", scale_ws=None, stream=None):
+    """One batched complex GEMM step on torch complex64 device tensors.
+    scale_ws: optional int32 device tensor of >= 3 entries (required for
+    split_fp16); afterwards it holds the float bits of max(|re|,|im|) of A, B
+    and C."""
     import torch
     lib = load()
     for t in (A, B, C):
@@ -294,9 +298,14 @@ def qc_kernel_gemm(A, B, C, nb: int, m: int, n: int, k: int, a_km: bool = False,
             raise ValueError("operands must be contiguous complex64 device tensors")
     if A.numel() < nb * m * k or B.numel() < nb * k * n or C.numel() < nb * m * n:
         raise ValueError("operand too small for the GEMM shape")
+    if scale_ws is not None and (scale_ws.numel() < 3 or scale_ws.element_size() != 4):
+        raise ValueError("scale_ws must hold at least 3 32-bit entries")
+    if scale_ws is None and _prec(prec) == PRECISIONS["split_fp16"]:
+        scale_ws = torch.zeros(3, dtype=torch.int32, device=A.device)
     st = stream if stream is not None else torch.cuda.current_stream()
     _check(lib.qc_kernel_gemm(A.data_ptr(), B.data_ptr(), C.data_ptr(), nb, m, n, k, int(bool(a_km)),
-                              int(bool(b_nk)), _prec(prec), st.cuda_stream), lib)
+                              int(bool(b_nk)), _prec(prec), None if scale_ws is None else scale_ws.data_ptr(),
+                              st.cuda_stream), lib)
 
 
 def qc_kernel_transpose(inp, out, rank: int, perm, stream=None):

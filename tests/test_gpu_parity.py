@@ -199,3 +199,41 @@ def test_device_resident_bitstrings_match_host(c2_setup, mode):
     assert torch.equal(out_h, out_d)
     o = out_d.cpu().numpy()
     check_amplitudes(o[:, 0] + 1j * o[:, 1], ref[:37], lat.n, TOL_C64)
+
+
+# Split precisions: relative error <= 1e-4 for split FP16; split BF16 has no
+# target of its own and is held to 1e-3.  They always run stepwise.
+TOL_SPLIT = {"split_fp16": 1e-4, "split_bf16": 1e-3}
+
+
+@pytest.mark.parametrize("prec", sorted(TOL_SPLIT))
+def test_p6_unitarity_split(prec):
+    lat = synth.grid(3, 3)
+    circ = synth.random_circuit(lat, 8, 3)
+    xs = np.array(list(np.ndindex(*([2] * lat.n))), dtype=np.uint8)
+    plan = qcsim.qc_plan_build(lat.n, circ, None, log2_slices=2, greedy_trials=2)
+    say(f"P6 unitarity 3x3 d8 {prec}")
+    got = _contract(plan, xs, 0, 4, prec=prec)
+    assert abs(np.sum(np.abs(got) ** 2) - 1) <= TOL_SPLIT[prec]
+    check_amplitudes(got, oracle.statevector(lat.n, circ), lat.n, TOL_SPLIT[prec])
+
+
+@pytest.mark.parametrize("prec", sorted(TOL_SPLIT))
+def test_c2_amplitudes_split(c2_setup, prec):
+    lat, circ, bs, plan, ref = c2_setup
+    qcsim.qc_plan_set_exec(plan, "auto")
+    say(f"c2 5x5 d16, 64 bitstrings x 64 slices, {prec}")
+    got = _contract(plan, bs, 0, 64, prec=prec)
+    info = check_amplitudes(got, ref, lat.n, TOL_SPLIT[prec])
+    print("c2", prec, info)
+
+
+def test_split_needs_stepwise(c2_setup):
+    _lat, _circ, bs, plan, _ref = c2_setup
+    qcsim.qc_plan_set_exec(plan, "fused")
+    try:
+        with pytest.raises(qcsim.QcError) as e:
+            qcsim.qc_workspace_bytes(plan, 64, len(bs), "split_fp16")
+        assert "complex FP32" in str(e.value)
+    finally:
+        qcsim.qc_plan_set_exec(plan, "auto")
