@@ -340,12 +340,183 @@ __global__ void __launch_bounds__(64 * WM * WN) gemm_split_kernel(GemmDesc d) {
     if (d.amax_c) wave_amax(mx, d.amax_c);
 }
 
+// Large-tile form for m, n multiples of 128: a 128x128 block tile, four
+// waves each owning 64x64 (2x2 MFMA tiles, 8 accumulators), K slabs of 16
+// double-buffered in LDS with one barrier per slab; the next slab's complex64
+// operands are loaded into registers while the current slab is multiplied,
+// then scaled, split and stored into the other buffer.  Each thread stages
+// 8 consecutive k of one row of A and of B (one 16-byte LDS write per plane);
+// the two 16-byte halves of a row swap places on every other group of 8 rows
+// to spread the fragment reads over the LDS banks.  Tiles are numbered with n
+// fastest and dealt to the eight XCDs in contiguous ranges, so the blocks of
+// one XCD share A panels in that XCD's L2.
+__device__ __forceinline__ int swz(int row, int half) { return (half ^ ((row >> 3) & 1)) * 8; }
+
+template <typename T>
+__device__ __forceinline__ void split_store(T (*plane)[128][16], int row, int half, const float2 (&v)[8], int e) {
+    typedef T V __attribute__((ext_vector_type(8)));
+    V hr, hi, lr, li;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const float xr = ldexpf(v[q].x, -e), xi = ldexpf(v[q].y, -e);
+        const T a = T(xr), b = T(xi);
+        hr[q] = a;
+        hi[q] = b;
+        lr[q] = T(xr - float(a));
+        li[q] = T(xi - float(b));
+    }
+    const int c = swz(row, half);
+    *(V *)&plane[0][row][c] = hr;
+    *(V *)&plane[1][row][c] = hi;
+    *(V *)&plane[2][row][c] = lr;
+    *(V *)&plane[3][row][c] = li;
+}
+
+// 8 consecutive k (from k0 + 8 half) of row `row` of an operand whose element
+// (row, kk) sits at base[row * s_row + kk * s_k]; zero beyond k.  vec: k is
+// the fast axis and every row start is 16-byte aligned (16-byte loads).
+__device__ __forceinline__ void load8(float2 (&v)[8], const float2 *base, int64_t s_row, int64_t s_k, bool vec,
+                                      int row, int64_t kk0, int64_t k) {
+    const float2 *p = base + row * s_row + kk0 * s_k;
+    if (vec && kk0 + 8 <= k) {
+        const float4 *p4 = (const float4 *)p;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const float4 w = p4[q];
+            v[2 * q] = make_float2(w.x, w.y);
+            v[2 * q + 1] = make_float2(w.z, w.w);
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v[q] = kk0 + q < k ? p[q * s_k] : make_float2(0.f, 0.f);
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) gemm_split_big_kernel(GemmDesc d) {
+    typedef T V __attribute__((ext_vector_type(8)));
+    constexpr int TM = 128, TN = 128, KT = 16;
+    __shared__ __attribute__((aligned(16))) T As[2][4][TM][KT];
+    __shared__ __attribute__((aligned(16))) T Bs[2][4][TN][KT];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int64_t tiles_m = d.m / TM, tiles_n = d.n / TN;
+    const int64_t n_tiles = d.nb * tiles_m * tiles_n;
+    // Staging roles: along k when k is the fast axis (64 contiguous bytes per
+    // thread), else along the row (coalesced across the wavefront).
+    const bool a_kc = d.sAk == 1, b_kc = d.sBk == 1;
+    const int ar = a_kc ? (t >> 1) : (t & 127), ah = a_kc ? (t & 1) : (t >> 7);
+    const int br = b_kc ? (t >> 1) : (t & 127), bh = b_kc ? (t & 1) : (t >> 7);
+    const bool a_vec = a_kc && d.sAm % 2 == 0 && d.sAb % 2 == 0 && (uintptr_t)d.A % 16 == 0;
+    const bool b_vec = b_kc && d.sBn % 2 == 0 && d.sBb % 2 == 0 && (uintptr_t)d.B % 16 == 0;
+    const int ea = split_exp<T>(d.amax_a), eb = split_exp<T>(d.amax_b);
+    const int n_slabs = int((d.k + KT - 1) / KT);
+    float mx = 0.f;
+    // XCD-aware numbering (a permutation of the grid when it divides by 8).
+    int64_t first = blockIdx.x;
+    if (gridDim.x % 8 == 0) first = int64_t(blockIdx.x % 8) * (gridDim.x / 8) + blockIdx.x / 8;
+    for (int64_t tile = first; tile < n_tiles; tile += gridDim.x) {
+        const int64_t tn = tile % tiles_n;
+        const int64_t tm = (tile / tiles_n) % tiles_m;
+        const int64_t bi = tile / (tiles_n * tiles_m);
+        const float2 *Ab = d.A + bi * d.sAb + tm * TM * d.sAm;
+        const float2 *Bb = d.B + bi * d.sBb + tn * TN * d.sBn;
+        floatx16 acc[2][2][2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int v = 0; v < 16; ++v) { acc[i][j][0][v] = 0.f; acc[i][j][1][v] = 0.f; }
+        float2 ra[8], rb[8];
+        load8(ra, Ab, d.sAm, d.sAk, a_vec, ar, 8 * ah, d.k);
+        load8(rb, Bb, d.sBn, d.sBk, b_vec, br, 8 * bh, d.k);
+        split_store<T>(As[0], ar, ah, ra, ea);
+        split_store<T>(Bs[0], br, bh, rb, eb);
+        __syncthreads();
+        for (int s = 0; s < n_slabs; ++s) {
+            const int buf = s & 1;
+            const bool more = s + 1 < n_slabs;
+            if (more) {
+                const int64_t k1 = int64_t(s + 1) * KT;
+                load8(ra, Ab, d.sAm, d.sAk, a_vec, ar, k1 + 8 * ah, d.k);
+                load8(rb, Bb, d.sBn, d.sBk, b_vec, br, k1 + 8 * bh, d.k);
+            }
+            V a[2][4], b[2][4], na[2][2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                const int row = wm * 64 + i * 32 + (lane & 31);
+                const int c = swz(row, lane >> 5);
+#pragma unroll
+                for (int p = 0; p < 4; ++p) a[i][p] = *(const V *)&As[buf][p][row][c];
+                na[i][0] = negate16(a[i][1]);
+                na[i][1] = negate16(a[i][3]);
+            }
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const int row = wn * 64 + j * 32 + (lane & 31);
+                const int c = swz(row, lane >> 5);
+#pragma unroll
+                for (int p = 0; p < 4; ++p) b[j][p] = *(const V *)&Bs[buf][p][row][c];
+            }
+            // Planes: 0 hi re, 1 hi im, 2 lo re, 3 lo im.  Consecutive MFMAs
+            // go to different accumulators.
+#define QC_MFMA_ALL(ROW_A, COL_B, RI)                                                    \
+    _Pragma("unroll") for (int i = 0; i < 2; ++i) _Pragma("unroll") for (int j = 0; j < 2; ++j) \
+        acc[i][j][RI] = mfma16(ROW_A, COL_B, acc[i][j][RI]);
+            QC_MFMA_ALL(a[i][0], b[j][0], 0)
+            QC_MFMA_ALL(a[i][0], b[j][1], 1)
+            QC_MFMA_ALL(a[i][0], b[j][2], 0)
+            QC_MFMA_ALL(a[i][0], b[j][3], 1)
+            QC_MFMA_ALL(a[i][2], b[j][0], 0)
+            QC_MFMA_ALL(a[i][2], b[j][1], 1)
+            QC_MFMA_ALL(na[i][0], b[j][1], 0)
+            QC_MFMA_ALL(a[i][1], b[j][0], 1)
+            QC_MFMA_ALL(na[i][0], b[j][3], 0)
+            QC_MFMA_ALL(a[i][1], b[j][2], 1)
+            QC_MFMA_ALL(na[i][1], b[j][1], 0)
+            QC_MFMA_ALL(a[i][3], b[j][0], 1)
+#undef QC_MFMA_ALL
+            if (more) {
+                split_store<T>(As[buf ^ 1], ar, ah, ra, ea);
+                split_store<T>(Bs[buf ^ 1], br, bh, rb, eb);
+            }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                float2 *Cb = d.C + bi * d.sCb + (tm * TM + wm * 64 + i * 32) * d.sCm + (tn * TN + wn * 64 + j * 32) * d.sCn;
+#pragma unroll
+                for (int v = 0; v < 16; ++v) {
+                    const int row = (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
+                    const int col = lane & 31;
+                    const float re = ldexpf(acc[i][j][0][v], ea + eb), im = ldexpf(acc[i][j][1][v], ea + eb);
+                    Cb[row * d.sCm + col * d.sCn] = make_float2(re, im);
+                    mx = fmaxf(mx, fmaxf(fabsf(re), fabsf(im)));
+                }
+            }
+    }
+    if (d.amax_c) wave_amax(mx, d.amax_c);
+}
+
 const char *launch_gemm(const GemmDesc &d, hipStream_t st) {
     const bool tiles32 = d.m % 32 == 0 && d.n % 32 == 0;
     const int wm = d.m % 64 == 0 ? 2 : 1, wn = d.n % 64 == 0 ? 2 : 1;
     const int64_t tiles = d.nb * (d.m / (32 * wm)) * (d.n / (32 * wn));
     const unsigned grid = (unsigned)(tiles < 1048576 ? tiles : 1048576);
     // The split forms need whole 32x32 tiles (K is zero-padded to the slab).
+    if (d.prec != kPrecC64 && d.m % 128 == 0 && d.n % 128 == 0 && d.k >= 2) {
+        const int64_t t128 = d.nb * (d.m / 128) * (d.n / 128);
+        const unsigned g = (unsigned)(t128 < 1048576 ? t128 : 1048576);
+        if (d.prec == kPrecFP16) {
+            hipLaunchKernelGGL(gemm_split_big_kernel<_Float16>, dim3(g), dim3(256), 0, st, d);
+            return "gemm_split_fp16";
+        }
+        hipLaunchKernelGGL(gemm_split_big_kernel<__bf16>, dim3(g), dim3(256), 0, st, d);
+        return "gemm_split_bf16";
+    }
     if (d.prec != kPrecC64 && tiles32 && d.k >= 2) {
 #define QC_SPLIT_CASE(T, WM, WN)                                                                       \
     if (wm == WM && wn == WN) {                                                                        \

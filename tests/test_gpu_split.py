@@ -58,7 +58,9 @@ def _exact_operands(rng, nb, m, n, k, sa, sb):
     return A, B
 
 
-EXACT_SHAPES = [(1, 32, 32, 16), (2, 64, 64, 64), (3, 64, 32, 17), (1, 128, 128, 256), (4, 32, 64, 3)]
+# 32-multiples take the 32/64-tile form, 128-multiples the large-tile form.
+EXACT_SHAPES = [(1, 32, 32, 16), (2, 64, 64, 64), (3, 64, 32, 17), (4, 32, 64, 3), (1, 128, 128, 256), (2, 256, 128, 40),
+                (1, 128, 384, 9)]
 
 
 @pytest.mark.parametrize("prec", PRECS)
@@ -74,7 +76,8 @@ def test_split_gemm_exact(prec, shape, a_km, b_nk, scale):
     assert np.array_equal(got.astype(np.complex128), ref), np.abs(got - ref).max()
 
 
-SHAPES = [(1, 32, 32, 16), (2, 64, 64, 128), (1, 128, 64, 1000), (8, 32, 32, 2), (1, 64, 128, 4096)]
+SHAPES = [(1, 32, 32, 16), (2, 64, 64, 128), (1, 128, 64, 1000), (8, 32, 32, 2), (1, 64, 128, 4096), (1, 256, 256, 1000),
+          (3, 128, 128, 33), (1, 128, 256, 4096)]
 
 
 @pytest.mark.parametrize("prec", PRECS)
@@ -111,8 +114,9 @@ def test_split_gemm_small_shapes_use_fp32(prec):
 
 
 @pytest.mark.parametrize("prec", PRECS + ["c64"])
-def test_scale_slots(prec):
-    nb, m, n, k = 2, 64, 32, 48
+@pytest.mark.parametrize("shape", [(2, 64, 32, 48), (1, 128, 256, 48)])
+def test_scale_slots(prec, shape):
+    nb, m, n, k = shape
     rng = np.random.default_rng(9)
     A = ((rng.standard_normal((nb, m, k)) + 1j * rng.standard_normal((nb, m, k))) * 2.0 ** -25).astype(np.complex64)
     B = ((rng.standard_normal((nb, k, n)) + 1j * rng.standard_normal((nb, k, n))) * 3.0).astype(np.complex64)
