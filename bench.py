@@ -50,11 +50,147 @@ def _traffic(kind, workload):
     return 1024.0 * (rec["fetch_kib"] * rec["fetch_scale"] + rec["write_kib"] * rec["write_scale"])
 
 
-def _gemm_form(op):
-    k = op["k"]
+def _gemm_form(op, prec="c64"):
+    """Kernel kind the library launches for a GEMM step (its dispatch rule)."""
+    k, m, n = op["k"], op["m"], op["n"]
+    if prec != "c64":
+        return f"gemm_{prec}" if m % 32 == 0 and n % 32 == 0 and k >= 2 else "gemm_valu"
     kt = 16 if k >= 16 else k
     ok = kt in (2, 4, 8, 16) and k % kt == 0
-    return "gemm_mfma" if ok and op["m"] % 32 == 0 and op["n"] % 32 == 0 else "gemm_valu"
+    return "gemm_mfma" if ok and m % 32 == 0 and n % 32 == 0 else "gemm_valu"
+
+
+PEAK_MFMA_TFLOPS = {"c64": PEAK_FP32_TFLOPS, "split_bf16": 2500.0, "split_fp16": 2500.0}
+HW_PER_ALG = {"c64": 1.0, "split_bf16": 3.0, "split_fp16": 3.0}   # hardware flops per algorithmic flop
+
+
+def _events_ms(stream, fn, reps):
+    import torch
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(reps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def first_nonzero_slice(key, candidates):
+    """The first candidate slice of the 70-qubit plan whose value is not exactly
+    zero (found with one split-BF16 contraction each)."""
+    import torch
+
+    import synth
+    from paper_1907_11217_amd import qcsim
+
+    lat, circ, bs, spec = synth.config(key)
+    plan = qcsim.qc_plan_build(lat.n, circ, bs[0], log2_slices=spec["log2_slices"],
+                               log2_max_entries=spec.get("log2_cap", 0), greedy_trials=8, seed=1)
+    k = qcsim.qc_plan_info(plan)["log2_slices"]
+    ws = torch.empty(qcsim.qc_workspace_bytes(plan, 1, 1, "split_bf16"), dtype=torch.uint8, device="cuda")
+    out = torch.zeros(1, 2, dtype=torch.float64, device="cuda")
+    tried = []
+    for s in candidates(k):
+        out.zero_()
+        qcsim.qc_contract_slices(plan, s, s + 1, bs[:1], "split_bf16", ws, out)
+        torch.cuda.synchronize()
+        tried.append(s)
+        if out.abs().max().item() > 0:
+            return s, tried
+    return tried[-1], tried
+
+
+def big_leg(key, precs, reps, s_range, oracle_slices=()):
+    """One large configuration on the stepwise path: every precision runs the
+    same slice range for one bitstring; reports time, algorithmic TFLOP/s,
+    the GEMM kernels' achieved MFMA rate against their dtype's peak, and the
+    agreement with the complex FP32 result (and with the oracle on sampled
+    slices, when asked)."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1907_11217_amd import qcsim
+
+    lat, circ, bs, spec = synth.config(key)
+    t0 = time.perf_counter()
+    plan = qcsim.qc_plan_build(lat.n, circ, bs[0], log2_slices=spec["log2_slices"],
+                               log2_max_entries=spec.get("log2_cap", 0), greedy_trials=8, seed=1)
+    plan_s = time.perf_counter() - t0
+    info = qcsim.qc_plan_info(plan)
+    k = info["log2_slices"]
+    s0, s1 = s_range(k)
+    n_sl = s1 - s0
+    x = bs[:1]
+    stream = torch.cuda.current_stream()
+    out = torch.zeros(1, 2, dtype=torch.float64, device="cuda")
+    b = (n_sl - 1).bit_length()
+    desc = qcsim.qc_plan_describe(plan, b, 0)
+    chunks = max(1, n_sl >> b)
+    leg = {"workload": (f"{spec['name']}: {lat.n} qubits, depth 1+{spec['depth']}+1, 2^{k} slices (cap 2^"
+                        f"{spec.get('log2_cap', 0)} entries), slices [{s0}, {s1}) for bitstring seed "
+                        f"{spec['seed'] + 1}"),
+           "log2_slices": k, "slices_per_step": n_sl, "plan_seconds": plan_s,
+           "flops_per_slice_b0": info["flops_per_slice"], "per_prec": {}}
+    ref = None
+    per_slice_ref = None
+    for prec in precs:
+        ws = torch.empty(qcsim.qc_workspace_bytes(plan, n_sl, 1, prec), dtype=torch.uint8, device="cuda")
+        ps = torch.zeros(n_sl, 1, 2, dtype=torch.float64, device="cuda")
+
+        def step():
+            qcsim.qc_contract_slices(plan, s0, s1, x, prec, ws, out, stream=stream)
+
+        out.zero_()
+        qcsim.qc_contract_slices(plan, s0, s1, x, prec, ws, out, ps, stream=stream)
+        torch.cuda.synchronize()
+        val = complex(*out.cpu().numpy()[0])
+        psv = ps.cpu().numpy()[:, 0, 0] + 1j * ps.cpu().numpy()[:, 0, 1]
+        ms = _events_ms(stream, step, reps)
+        qcsim.qc_profile_read(plan)
+        qcsim.qc_profile_enable(plan, True)
+        step()
+        torch.cuda.synchronize()
+        qcsim.qc_profile_enable(plan, False)
+        prof = qcsim.qc_profile_read(plan)
+        # Algorithmic flops of the step's GEMMs, per kernel kind.
+        per_kind = {}
+        for op in desc["ops"]:
+            if op["op"] == "gemm":
+                f = _gemm_form(op, prec)
+                per_kind[f] = per_kind.get(f, 0.0) + 8.0 * op["nb"] * op["m"] * op["n"] * op["k"] * chunks
+        flops = sum(per_kind.values())
+        r = {"ms_per_step": ms, "value": val.real, "value_im": val.imag, "tflops": flops / (ms * 1e-3) / 1e12,
+             "kernels": {kk: {"launches": v[0], "ms": v[1]} for kk, v in prof.items()}}
+        mf = "gemm_mfma" if prec == "c64" else f"gemm_{prec}"
+        if mf in prof and mf in per_kind:
+            ach = per_kind[mf] / (prof[mf][1] * 1e-3) / 1e12
+            r["mfma_gemm"] = {"kernel": mf, "achieved_tflops_alg": ach,
+                              "achieved_tflops_hw": ach * HW_PER_ALG[prec], "peak_tflops": PEAK_MFMA_TFLOPS[prec],
+                              "frac": ach * HW_PER_ALG[prec] / PEAK_MFMA_TFLOPS[prec],
+                              "flop_share": per_kind[mf] / flops}
+        if ref is None:
+            ref, per_slice_ref = val, psv
+        else:
+            r["rel_diff_vs_c64"] = abs(val - ref) / abs(ref) if ref != 0 else None
+            scale = np.sqrt(np.mean(np.abs(per_slice_ref) ** 2))
+            r["per_slice_max_diff_vs_c64_over_rms"] = float(np.abs(psv - per_slice_ref).max() / scale)
+        leg["per_prec"][prec] = r
+        del ws
+    if "c64" in leg["per_prec"] and n_sl < (1 << k):
+        leg["projected_s_per_amplitude_c64"] = leg["per_prec"]["c64"]["ms_per_step"] * 1e-3 * (1 << k) / n_sl
+    for p in precs[1:]:
+        leg[f"speedup_{p}_over_c64"] = leg["per_prec"]["c64"]["ms_per_step"] / leg["per_prec"][p]["ms_per_step"]
+    if oracle_slices:
+        import oracle
+        segs = [tuple(int(v) for v in sg) for sg in qcsim.qc_plan_sliced_segments(plan)]
+        errs = []
+        for s in oracle_slices:
+            v = oracle.sliced_value(lat.n, circ, x[0], segs, s0 + s)
+            errs.append(abs(per_slice_ref[s] - v) / abs(v))
+        leg["oracle_per_slice_rel_err_c64"] = {"slices": [s0 + s for s in oracle_slices], "max": float(max(errs))}
+    return leg
 
 
 def main():
@@ -66,6 +202,8 @@ def main():
     ap.add_argument("--prec", default="c64", choices=["c64", "split_bf16", "split_fp16"])
     ap.add_argument("--exec", default="auto", choices=["auto", "fused", "stepwise"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip the 7x7 depth-24 and 70-qubit depth-32 reports")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -211,6 +349,19 @@ def main():
         "roofline": roof,
     }
     result.update(result_extra)
+
+    if not args.no_large:
+        precs = ["c64", "split_fp16", "split_bf16"]
+        # 7x7 depth 24: every slice of one amplitude per step.
+        result["grid7x7_d24"] = big_leg("c3", precs, 5, lambda k: (0, 1 << k), oracle_slices=(0,))
+        # 70 qubits depth 32: one slice per step; the amplitude is projected
+        # as slice time x 2^k.  Many slices of this plan are exactly zero (a
+        # leaf or an intermediate vanishes for their sliced values); the
+        # precisions are compared on the first nonzero one counting down from
+        # the last slice (the time per slice does not depend on the values).
+        s4, tried = first_nonzero_slice("c4", lambda k: [(1 << k) - 1 - j for j in range(16)])
+        result["diamond70_d32"] = big_leg("c4", precs, 2, lambda k: (s4, s4 + 1))
+        result["diamond70_d32"]["zero_slices_skipped"] = len(tried) - 1
 
     if not args.no_cpu_baseline:
         import oracle

@@ -8,7 +8,7 @@
 namespace qc {
 
 constexpr int kLeafMaxRank = 40;
-constexpr int kLeafMaxBase = 8;
+constexpr int kLeafMaxBase = 16;  // folded leaves carry up to 14 indices
 
 // One leaf tensor to instantiate for a chunk of slices and bitstrings.
 struct LeafDesc {

@@ -13,12 +13,20 @@ namespace qc {
 // the chunk's slice id (sliced segments not in flight), or fixed by the
 // bitstring (output segments); the bitstring bits of the batch become extra
 // output bits.  One thread per output element.
-// max(|re|, |im|) of the wavefront's values folded into *amax (uint32 order
-// of non-negative floats is their numeric order).  Every lane must call it.
-__device__ __forceinline__ void wave_amax(float v, uint32_t *amax) {
+// max(|re|, |im|) of the workgroup's values folded into *amax with one
+// atomic per workgroup (uint32 order of non-negative floats is their numeric
+// order).  Every thread of the workgroup must call it.
+__device__ __forceinline__ void block_amax(float v, uint32_t *amax) {
+    __shared__ float part[16];
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
-    if ((threadIdx.x & 63) == 0) atomicMax(amax, __float_as_uint(v));
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < int(blockDim.x + 63) / 64; ++w) v = fmaxf(v, part[w]);
+        atomicMax(amax, __float_as_uint(v));
+    }
 }
 
 __global__ void __launch_bounds__(256) leaf_kernel(const LeafDesc *__restrict__ descs,
@@ -46,7 +54,7 @@ __global__ void __launch_bounds__(256) leaf_kernel(const LeafDesc *__restrict__ 
         tensors[d.out_off + e] = f;
         mx = fmaxf(fabsf(f.x), fabsf(f.y));
     }
-    if (amax) wave_amax(mx, amax + d.amax_slot);
+    if (amax) block_amax(mx, amax + d.amax_slot);
 }
 
 void launch_leaves(const LeafDesc *descs, const int32_t *block_leaf, int n_blocks, const double2 *base,
@@ -64,7 +72,7 @@ __global__ void __launch_bounds__(256) absmax_kernel(const float2 *__restrict__ 
         const float2 v = x[i];
         mx = fmaxf(mx, fmaxf(fabsf(v.x), fabsf(v.y)));
     }
-    wave_amax(mx, amax);
+    block_amax(mx, amax);
 }
 
 void launch_absmax(const float2 *x, int64_t n, uint32_t *amax, hipStream_t st) {
@@ -150,7 +158,7 @@ __global__ void __launch_bounds__(256) gemm_valu_kernel(GemmDesc d) {
         d.C[bi * d.sCb + mi * d.sCm + ni * d.sCn] = make_float2(re, im);
         mx = fmaxf(mx, fmaxf(fabsf(re), fabsf(im)));
     }
-    if (d.amax_c) wave_amax(mx, d.amax_c);
+    if (d.amax_c) block_amax(mx, d.amax_c);
 }
 
 // -------------------------------------------------------------- MFMA GEMM
@@ -337,7 +345,7 @@ __global__ void __launch_bounds__(64 * WM * WN) gemm_split_kernel(GemmDesc d) {
             mx = fmaxf(mx, fmaxf(fabsf(re), fabsf(im)));
         }
     }
-    if (d.amax_c) wave_amax(mx, d.amax_c);
+    if (d.amax_c) block_amax(mx, d.amax_c);
 }
 
 // Large-tile form for m, n multiples of 128: a 128x128 block tile, four
@@ -498,7 +506,7 @@ __global__ void __launch_bounds__(256) gemm_split_big_kernel(GemmDesc d) {
                 }
             }
     }
-    if (d.amax_c) wave_amax(mx, d.amax_c);
+    if (d.amax_c) block_amax(mx, d.amax_c);
 }
 
 const char *launch_gemm(const GemmDesc &d, hipStream_t st) {
@@ -539,7 +547,7 @@ const char *launch_gemm(const GemmDesc &d, hipStream_t st) {
     if (d.prec != kPrecC64 || !k_ok || !tiles32) {
         const int64_t total = d.nb * d.m * d.n;
         int64_t g = (total + 255) / 256;
-        if (g > 262144) g = 262144;
+        if (g > 8192) g = 8192;
         hipLaunchKernelGGL(gemm_valu_kernel, dim3((unsigned)g), dim3(256), 0, st, d);
         return "gemm_valu";
     }
@@ -711,33 +719,53 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
-__global__ void __launch_bounds__(64) reduce64_kernel(const float2 *__restrict__ partial, int m, int n_bs,
-                                                      uint64_t sc, int64_t n_blocks, uint64_t lo, uint64_t hi,
-                                                      uint64_t s_begin, double *__restrict__ out,
-                                                      double *__restrict__ per_slice) {
+// One workgroup per bitstring.  Its four waves form the 64-slice block sums
+// (fixed butterfly) of up to 256 blocks at a time into LDS; then one thread
+// adds them to the running total in increasing block order, so the result is
+// bitwise the same as adding the blocks one after another.
+constexpr int kReduceBatch = 256;
+
+__global__ void __launch_bounds__(256) reduce64_kernel(const float2 *__restrict__ partial, int m, int n_bs,
+                                                       uint64_t sc, int64_t n_blocks, uint64_t lo, uint64_t hi,
+                                                       uint64_t s_begin, double *__restrict__ out,
+                                                       double *__restrict__ per_slice) {
+    __shared__ double2 bsum[kReduceBatch];
+    __shared__ int valid[kReduceBatch];
     const int bs = blockIdx.x;
-    const int lane = threadIdx.x;
-    if (bs >= n_bs) return;
-    double acc_re = out[2 * bs], acc_im = out[2 * bs + 1];
-    for (int64_t blk = 0; blk < n_blocks; ++blk) {
-        const uint64_t b0 = sc + uint64_t(blk) * 64;
-        if (b0 + 64 <= lo || b0 >= hi) continue;
-        const uint64_t s = b0 + lane;
-        double re = 0.0, im = 0.0;
-        if (s >= lo && s < hi) {
-            const float2 v = partial[(int64_t(s - sc) << m) + bs];
-            re = double(v.x);
-            im = double(v.y);
-            if (per_slice) {
-                double *p = per_slice + 2 * (int64_t(s - s_begin) * n_bs + bs);
-                p[0] = re;
-                p[1] = im;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    double acc_re = 0.0, acc_im = 0.0;
+    if (threadIdx.x == 0) { acc_re = out[2 * bs]; acc_im = out[2 * bs + 1]; }
+    for (int64_t first = 0; first < n_blocks; first += kReduceBatch) {
+        const int nb = int(n_blocks - first < kReduceBatch ? n_blocks - first : kReduceBatch);
+        for (int j = wave; j < nb; j += 4) {
+            const uint64_t b0 = sc + uint64_t(first + j) * 64;
+            const bool in = !(b0 + 64 <= lo || b0 >= hi);
+            double re = 0.0, im = 0.0;
+            const uint64_t s = b0 + lane;
+            if (in && s >= lo && s < hi) {
+                const float2 v = partial[(int64_t(s - sc) << m) + bs];
+                re = double(v.x);
+                im = double(v.y);
+                if (per_slice) {
+                    double *p = per_slice + 2 * (int64_t(s - s_begin) * n_bs + bs);
+                    p[0] = re;
+                    p[1] = im;
+                }
+            }
+            re = wave_sum(re);
+            im = wave_sum(im);
+            if (lane == 0) {
+                bsum[j] = make_double2(re, im);
+                valid[j] = in;
             }
         }
-        acc_re += wave_sum(re);
-        acc_im += wave_sum(im);
+        __syncthreads();
+        if (threadIdx.x == 0)
+            for (int j = 0; j < nb; ++j)
+                if (valid[j]) { acc_re += bsum[j].x; acc_im += bsum[j].y; }
+        __syncthreads();
     }
-    if (lane == 0) {
+    if (threadIdx.x == 0) {
         out[2 * bs] = acc_re;
         out[2 * bs + 1] = acc_im;
     }
@@ -745,7 +773,7 @@ __global__ void __launch_bounds__(64) reduce64_kernel(const float2 *__restrict__
 
 void launch_reduce64(const float2 *partial, int m, int n_bs, uint64_t sc, int64_t n_blocks, uint64_t lo, uint64_t hi,
                      uint64_t s_begin, double *out, double *per_slice, hipStream_t st) {
-    hipLaunchKernelGGL(reduce64_kernel, dim3(n_bs), dim3(64), 0, st, partial, m, n_bs, sc, n_blocks, lo, hi, s_begin,
+    hipLaunchKernelGGL(reduce64_kernel, dim3(n_bs), dim3(256), 0, st, partial, m, n_bs, sc, n_blocks, lo, hi, s_begin,
                        out, per_slice);
 }
 
