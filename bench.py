@@ -53,11 +53,15 @@ def _traffic(kind, workload):
 def _gemm_form(op, prec="c64"):
     """Kernel kind the library launches for a GEMM step (its dispatch rule)."""
     k, m, n = op["k"], op["m"], op["n"]
-    if prec != "c64":
-        return f"gemm_{prec}" if m % 32 == 0 and n % 32 == 0 and k >= 2 else "gemm_valu"
+    if prec != "c64" and m % 32 == 0 and n % 32 == 0 and k >= 2:
+        return f"gemm_{prec}"
     kt = 16 if k >= 16 else k
     ok = kt in (2, 4, 8, 16) and k % kt == 0
-    return "gemm_mfma" if ok and m % 32 == 0 and n % 32 == 0 else "gemm_valu"
+    if prec == "c64" and ok and m % 32 == 0 and n % 32 == 0:
+        return "gemm_mfma"
+    if k >= 4096 and op["nb"] * m * n <= 4096:
+        return "gemm_dot"
+    return "gemm_skinny" if n >= 256 and m in (1, 2, 4, 8, 16) else "gemm_valu"
 
 
 PEAK_MFMA_TFLOPS = {"c64": PEAK_FP32_TFLOPS, "split_bf16": 2500.0, "split_fp16": 2500.0}
@@ -297,15 +301,18 @@ def main():
             except qcsim.QcError:
                 continue
         chunks = max(1, n_slices >> b)
-        per = {"gemm_mfma": 0.0, "gemm_valu": 0.0, "transpose": 0.0}
+        per = {"gemm_mfma": 0.0, "gemm_valu": 0.0, "gemm_skinny": 0.0, "gemm_dot": 0.0, "transpose": 0.0}
         for op in desc["ops"]:
             if op["op"] == "gemm":
                 per[_gemm_form(op)] += 8.0 * op["nb"] * op["m"] * op["n"] * op["k"]
             else:
                 per["transpose"] += 16.0 * (1 << len(desc["tensors"][op["src"]]["layout"]))
-        flops_step = (per["gemm_mfma"] + per["gemm_valu"]) * chunks * n_bs / (1 << desc["m"])
+        flops_step = (per["gemm_mfma"] + per["gemm_valu"] + per["gemm_skinny"] + per["gemm_dot"]) * chunks * n_bs / \
+            (1 << desc["m"])
         kind_work = {"gemm_mfma": (per["gemm_mfma"] * chunks, "mfma"),
                      "gemm_valu": (per["gemm_valu"] * chunks, "alu"),
+                     "gemm_skinny": (per["gemm_skinny"] * chunks, "alu"),
+                     "gemm_dot": (per["gemm_dot"] * chunks, "alu"),
                      "transpose": (per["transpose"] * chunks, "hbm")}
     dom = max(prof, key=lambda kk: prof[kk][1])
     launches, total_ms = prof[dom]

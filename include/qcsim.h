@@ -163,12 +163,24 @@ qc_status qc_plan_describe(qc_plan *plan, int32_t log2_batch_slices, int32_t log
 enum { QC_EXEC_AUTO = 0, QC_EXEC_FUSED = 1, QC_EXEC_STEPWISE = 2 };
 qc_status qc_plan_set_exec(qc_plan *plan, int32_t mode);
 
+/* Graph replay of the stepwise form (on by default).  The first
+ * qc_contract_slices call with a given configuration (precision, workspace,
+ * bitstring and output buffers, slice range, batch size) captures its launch
+ * sequence as a HIP graph on a private stream, and every call with the same
+ * configuration replays it on the caller's stream; graphs hold no memset
+ * nodes.  Up to 8 graphs are kept per lowered program; evicting one waits for
+ * the device to drain.  Calls with kernel timing on, and the fused form (two
+ * launches per super-chunk), launch directly.  on = 0 launches every kernel
+ * directly. */
+qc_status qc_plan_set_graphs(qc_plan *plan, int32_t on);
+
 /* Kernel timing.  While enabled, qc_contract_slices records a pair of HIP
  * events on its stream around every kernel it launches.  qc_profile_read
  * waits for the recorded events, then reports per kernel kind the launch
  * count and the summed event-to-event milliseconds since the last read (and
  * clears them).  kinds: "fused", "leaves", "transpose", "gemm_mfma",
- * "gemm_split_bf16", "gemm_split_fp16", "gemm_valu", "reduce64".  Not
+ * "gemm_split_bf16", "gemm_split_fp16", "gemm_skinny", "gemm_dot",
+ * "gemm_valu", "reduce64".  Not
  * thread-safe across concurrent calls on one plan. */
 typedef struct {
     char kind[16];

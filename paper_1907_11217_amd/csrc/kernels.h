@@ -76,6 +76,8 @@ struct GemmDesc {
 void launch_absmax(const float2 *x, int64_t n, uint32_t *amax, hipStream_t st);
 // Sets n uint32 to zero (a fill kernel, so the op can sit in a captured graph).
 void launch_zero_u32(uint32_t *p, int64_t n, hipStream_t st);
+// dst[i] = src[i] for n complex64 values (a kernel, for the same reason).
+void launch_copy(float2 *dst, const float2 *src, int64_t n, hipStream_t st);
 
 // Fused form: one wavefront runs the whole program of (slice, bitstring)
 // pairs with every tensor in LDS, contracting each step directly from the

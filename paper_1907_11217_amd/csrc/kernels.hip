@@ -86,6 +86,18 @@ __global__ void __launch_bounds__(256) zero_u32_kernel(uint32_t *p, int64_t n) {
         p[i] = 0u;
 }
 
+__global__ void __launch_bounds__(256) copy_kernel(float2 *__restrict__ dst, const float2 *__restrict__ src, int64_t n) {
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+        dst[i] = src[i];
+}
+
+void launch_copy(float2 *dst, const float2 *src, int64_t n, hipStream_t st) {
+    if (n <= 0) return;
+    int64_t grid = (n + 255) / 256;
+    grid = grid > 4096 ? 4096 : grid;
+    hipLaunchKernelGGL(copy_kernel, dim3((unsigned)grid), dim3(256), 0, st, dst, src, n);
+}
+
 void launch_zero_u32(uint32_t *p, int64_t n, hipStream_t st) {
     if (n <= 0) return;
     int64_t grid = (n + 255) / 256;
@@ -98,36 +110,52 @@ void launch_zero_u32(uint32_t *p, int64_t n, hipStream_t st) {
 // input's fastest bits), stored in LDS, then written in output order
 // (coalesced along the output's fastest bits).  LDS rows of 32 complex values
 // are padded by one entry to spread the strided phase-2 reads over banks.
+// Every tile has the same shape, so each thread's element offsets inside a
+// tile (at most four per thread) are computed once; per tile only the base
+// offsets change, summed over the set bits of the tile id.
 __device__ __forceinline__ int lds_pad(int t) { return t + (t >> 5); }
 
 __global__ void __launch_bounds__(256) transpose_kernel(TransposeDesc d) {
     __shared__ float2 tile[(1 << kTransMaxTile) + (1 << kTransMaxTile) / 32];
     const int tsize = 1 << d.n_tile;
+    constexpr int E = 4;  // (1 << kTransMaxTile) / 256, and 128 / 64 for the small form
+    int64_t ioff[E], ooff[E];
+    int ilds[E], olds[E];
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+        const int t = threadIdx.x + j * blockDim.x;
+        int64_t io = 0, oo = 0;
+        int l = 0;
+        for (int i = 0; i < d.n_tile; ++i)
+            if ((t >> i) & 1) { io += d.tin_in[i]; oo += d.tout_out[i]; l += d.tout_lds[i]; }
+        ioff[j] = io;
+        ilds[j] = lds_pad(t);
+        ooff[j] = oo;
+        olds[j] = lds_pad(l);
+    }
     for (int64_t t_id = blockIdx.x; t_id < d.n_tiles; t_id += gridDim.x) {
         int64_t in_base = 0, out_base = 0;
-        for (int j = 0; j < d.n_rest; ++j)
-            if ((t_id >> j) & 1) { in_base += d.rest_in[j]; out_base += d.rest_out[j]; }
-        for (int t = threadIdx.x; t < tsize; t += blockDim.x) {
-            int64_t off = in_base;
-            for (int i = 0; i < d.n_tile; ++i)
-                if ((t >> i) & 1) off += d.tin_in[i];
-            tile[lds_pad(t)] = d.in[off];
+        for (uint64_t rest = uint64_t(t_id); rest; rest &= rest - 1) {
+            const int j = __builtin_ctzll(rest);
+            in_base += d.rest_in[j];
+            out_base += d.rest_out[j];
         }
+#pragma unroll
+        for (int j = 0; j < E; ++j)
+            if (threadIdx.x + j * blockDim.x < tsize) tile[ilds[j]] = d.in[in_base + ioff[j]];
         __syncthreads();
-        for (int t = threadIdx.x; t < tsize; t += blockDim.x) {
-            int64_t off = out_base;
-            int l = 0;
-            for (int i = 0; i < d.n_tile; ++i)
-                if ((t >> i) & 1) { off += d.tout_out[i]; l += d.tout_lds[i]; }
-            d.out[off] = tile[lds_pad(l)];
-        }
+#pragma unroll
+        for (int j = 0; j < E; ++j)
+            if (threadIdx.x + j * blockDim.x < tsize) d.out[out_base + ooff[j]] = tile[olds[j]];
         __syncthreads();
     }
 }
 
 void launch_transpose(const TransposeDesc &d, hipStream_t st) {
     const int64_t grid = d.n_tiles < 65536 ? d.n_tiles : 65536;
-    const int threads = d.n_tile >= 8 ? 256 : (d.n_tile >= 6 ? 64 : 64);
+    // 256 threads for tiles of 256..1024 elements, 64 for smaller ones (at
+    // most four elements per thread either way).
+    const int threads = d.n_tile >= 8 ? 256 : 64;
     hipLaunchKernelGGL(transpose_kernel, dim3((unsigned)grid), dim3(threads), 0, st, d);
 }
 
@@ -157,6 +185,86 @@ __global__ void __launch_bounds__(256) gemm_valu_kernel(GemmDesc d) {
         }
         d.C[bi * d.sCb + mi * d.sCm + ni * d.sCn] = make_float2(re, im);
         mx = fmaxf(mx, fmaxf(fabsf(re), fabsf(im)));
+    }
+    if (d.amax_c) block_amax(mx, d.amax_c);
+}
+
+// Skinny form for m <= 16 with a wide n (a small tensor applied to a large
+// one, HBM-bound): one thread per column j of C reads B[b][:, j] once
+// (coalesced when n is B's fast axis) and keeps all m outputs of the column
+// in registers; A's m x k values are the same for every thread of the block.
+template <int M>
+__global__ void __launch_bounds__(256) gemm_skinny_kernel(GemmDesc d) {
+    const int64_t chunks = (d.n + 255) / 256;
+    const int64_t total = d.nb * chunks;
+    float mx = 0.f;
+    for (int64_t blk = blockIdx.x; blk < total; blk += gridDim.x) {
+        const int64_t bi = blk / chunks;
+        const int64_t j = (blk % chunks) * 256 + threadIdx.x;
+        const bool ok = j < d.n;
+        const float2 *Ab = d.A + bi * d.sAb;
+        const float2 *Bb = d.B + bi * d.sBb + (ok ? j : 0) * d.sBn;
+        float re[M], im[M];
+#pragma unroll
+        for (int i = 0; i < M; ++i) { re[i] = 0.f; im[i] = 0.f; }
+        for (int64_t l = 0; l < d.k; ++l) {
+            const float2 y = ok ? Bb[l * d.sBk] : make_float2(0.f, 0.f);
+#pragma unroll
+            for (int i = 0; i < M; ++i) {
+                const float2 x = Ab[i * d.sAm + l * d.sAk];
+                re[i] = fmaf(x.x, y.x, re[i]);
+                re[i] = fmaf(-x.y, y.y, re[i]);
+                im[i] = fmaf(x.x, y.y, im[i]);
+                im[i] = fmaf(x.y, y.x, im[i]);
+            }
+        }
+        if (ok) {
+            float2 *Cb = d.C + bi * d.sCb + j * d.sCn;
+#pragma unroll
+            for (int i = 0; i < M; ++i) {
+                Cb[i * d.sCm] = make_float2(re[i], im[i]);
+                mx = fmaxf(mx, fmaxf(fabsf(re[i]), fabsf(im[i])));
+            }
+        }
+    }
+    if (d.amax_c) block_amax(mx, d.amax_c);
+}
+
+// Dot form for a few outputs with a long k (the last steps of a tree often
+// contract two large tensors to a handful of values): one workgroup of 1024
+// threads per output, k strided over the threads (coalesced), then a fixed
+// LDS tree, so the result does not depend on the launch.
+__global__ void __launch_bounds__(1024) gemm_dot_kernel(GemmDesc d) {
+    __shared__ float2 part[1024];
+    const int64_t total = d.nb * d.m * d.n;
+    float mx = 0.f;
+    for (int64_t o = blockIdx.x; o < total; o += gridDim.x) {
+        const int64_t j = o % d.n, i = (o / d.n) % d.m, bi = o / (d.n * d.m);
+        const float2 *a = d.A + bi * d.sAb + i * d.sAm;
+        const float2 *b = d.B + bi * d.sBb + j * d.sBn;
+        float re = 0.f, im = 0.f;
+        for (int64_t l = threadIdx.x; l < d.k; l += blockDim.x) {
+            const float2 x = a[l * d.sAk], y = b[l * d.sBk];
+            re = fmaf(x.x, y.x, re);
+            re = fmaf(-x.y, y.y, re);
+            im = fmaf(x.x, y.y, im);
+            im = fmaf(x.y, y.x, im);
+        }
+        part[threadIdx.x] = make_float2(re, im);
+        __syncthreads();
+        for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+            if (int(threadIdx.x) < w) {
+                const float2 u = part[threadIdx.x], v = part[threadIdx.x + w];
+                part[threadIdx.x] = make_float2(u.x + v.x, u.y + v.y);
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            const float2 r = part[0];
+            d.C[bi * d.sCb + i * d.sCm + j * d.sCn] = r;
+            mx = fmaxf(mx, fmaxf(fabsf(r.x), fabsf(r.y)));
+        }
+        __syncthreads();
     }
     if (d.amax_c) block_amax(mx, d.amax_c);
 }
@@ -545,6 +653,23 @@ const char *launch_gemm(const GemmDesc &d, hipStream_t st) {
     const int64_t kt_try = d.k >= 16 ? 16 : d.k;
     const bool k_ok = (kt_try == 2 || kt_try == 4 || kt_try == 8 || kt_try == 16) && d.k % kt_try == 0;
     if (d.prec != kPrecC64 || !k_ok || !tiles32) {
+        if (d.k >= 4096 && d.nb * d.m * d.n <= 4096) {
+            const int64_t outs = d.nb * d.m * d.n;
+            hipLaunchKernelGGL(gemm_dot_kernel, dim3((unsigned)outs), dim3(1024), 0, st, d);
+            return "gemm_dot";
+        }
+        if (d.n >= 256 && (d.m == 1 || d.m == 2 || d.m == 4 || d.m == 8 || d.m == 16)) {
+            const int64_t blocks = d.nb * ((d.n + 255) / 256);
+            const unsigned g = (unsigned)(blocks < 8192 ? blocks : 8192);
+            switch (d.m) {
+                case 1: hipLaunchKernelGGL(gemm_skinny_kernel<1>, dim3(g), dim3(256), 0, st, d); break;
+                case 2: hipLaunchKernelGGL(gemm_skinny_kernel<2>, dim3(g), dim3(256), 0, st, d); break;
+                case 4: hipLaunchKernelGGL(gemm_skinny_kernel<4>, dim3(g), dim3(256), 0, st, d); break;
+                case 8: hipLaunchKernelGGL(gemm_skinny_kernel<8>, dim3(g), dim3(256), 0, st, d); break;
+                default: hipLaunchKernelGGL(gemm_skinny_kernel<16>, dim3(g), dim3(256), 0, st, d); break;
+            }
+            return "gemm_skinny";
+        }
         const int64_t total = d.nb * d.m * d.n;
         int64_t g = (total + 255) / 256;
         if (g > 8192) g = 8192;

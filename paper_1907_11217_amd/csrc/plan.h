@@ -140,6 +140,9 @@ struct Program {
     int n_pool = 0;
     int fused_pairs = 0;                  // pairs per wavefront chosen by timing (0 = not tuned yet)
     std::vector<std::pair<int, float>> fused_tuning;  // (pairs, ms) measured when tuning
+    // Launch sequences captured as HIP graphs, keyed by everything the
+    // captured kernel arguments depend on (buffers, range, batch, precision).
+    std::vector<std::pair<std::vector<uint64_t>, void *>> graphs;  // (key, hipGraphExec_t)
 };
 
 }  // namespace qc
@@ -158,6 +161,11 @@ struct qc_plan {
     std::vector<void *> prof_pool;
     std::mutex mu;
     std::map<std::pair<int, int>, std::unique_ptr<qc::Program>> programs;
+    // Device-side state of the contraction calls (constants, tuning, graphs,
+    // profiling events) is updated under dev_mu.
+    std::mutex dev_mu;
+    bool use_graphs = true;
+    void *capture_stream = nullptr;       // hipStream_t used only to capture graphs
 };
 
 namespace qc {

@@ -360,12 +360,21 @@ TransposeDesc make_transpose_desc(const float2 *in, float2 *out, int r, const st
     std::memset(&d, 0, sizeof(d));
     d.in = in;
     d.out = out;
-    const int a = std::min(r, 5), c = std::min(r, 5);
-    std::vector<int> tile, rest;  // input bit positions
-    for (int p = 0; p < r; ++p) {
-        if (r <= kTransMaxTile || p < a || perm[p] < c) tile.push_back(p);
-        else rest.push_back(p);
+    // Tile bits: the input's lowest bits and the output's lowest bits, taken
+    // alternately until the tile has kTransMaxTile bits (all bits of a small
+    // tensor), so reads and writes both run along contiguous stretches.
+    std::vector<char> in_tile(r, r <= kTransMaxTile ? 1 : 0);
+    if (r > kTransMaxTile) {
+        std::vector<int> inv(r);
+        for (int p = 0; p < r; ++p) inv[perm[p]] = p;
+        int a = 0, c = 0, n = 0;
+        while (n < kTransMaxTile) {
+            const int p = a <= c ? a++ : inv[c++];
+            if (!in_tile[p]) { in_tile[p] = 1; ++n; }
+        }
     }
+    std::vector<int> tile, rest;  // input bit positions
+    for (int p = 0; p < r; ++p) (in_tile[p] ? tile : rest).push_back(p);
     std::vector<int> tin = tile, tout = tile;
     std::sort(tin.begin(), tin.end());
     std::sort(tout.begin(), tout.end(), [&](int x, int y) { return perm[x] < perm[y]; });
@@ -445,17 +454,19 @@ struct Prof {
     }
 };
 
-// bits_in: host bitstrings (copied into the workspace) or, with bits_on_device,
-// the caller's device array (read in place).
-bool enqueue(qc_plan *plan, const Exec &x, uint64_t s_begin, uint64_t s_end, const uint8_t *bits_in,
-             bool bits_on_device, int n_bs, void *ws, hipStream_t st, double *out_dev, double *per_slice_dev,
-             std::string &err) {
+// The launches of one call, on stream st, bitstrings already in device
+// memory: for each super-chunk either the fused kernel or the stepwise
+// sequence (scale-slot reset, leaves, transposes and GEMMs per chunk, root
+// copy), then the FP64 reduction.  Only kernel launches (and, with prof,
+// event records), so the sequence can be captured as a graph.
+bool launch_all(qc_plan *plan, const Exec &x, uint64_t s_begin, uint64_t s_end, const uint8_t *bits, int n_bs,
+                void *ws, hipStream_t st, double *out_dev, double *per_slice_dev, bool profile, std::string &err) {
     Program &prog = *x.prog;
     Prof prof{plan, st};
-    if (!ensure_device(plan, prog, x.fused, err)) return false;
+    const bool saved = plan->profiling;
+    plan->profiling = profile;
     const int nq = plan->net.n_qubits;
     const WsLayout w = ws_layout(x, nq);
-    const uint8_t *bits = bits_in;
     float2 *partial = (float2 *)((char *)ws + w.partial_off);
     float2 *tensors = (float2 *)((char *)ws + w.tensor_off);
     // Scale bookkeeping only where a scale is derived from it (FP16).
@@ -464,11 +475,6 @@ bool enqueue(qc_plan *plan, const Exec &x, uint64_t s_begin, uint64_t s_end, con
     for (size_t t = 0; t < slot.size(); ++t) slot[t] = (int)t;
     for (const Op &op : prog.ops)
         if (op.kind == Op::TRANSPOSE) slot[prog.transposes[op.index].dst] = slot[prog.transposes[op.index].src];
-    if (!bits_on_device) {
-        uint8_t *dst = (uint8_t *)ws + w.bits_off;
-        QC_HIP(hipMemcpyAsync(dst, bits_in, size_t(n_bs) * nq, hipMemcpyHostToDevice, st));
-        bits = dst;
-    }
     const uint64_t P = uint64_t(1) << x.lp;
     for (uint64_t sc = s_begin & ~(P - 1); sc < s_end; sc += P) {
         const uint64_t lo = std::max(s_begin, sc), hi = std::min(s_end, sc + P);
@@ -494,7 +500,7 @@ bool enqueue(qc_plan *plan, const Exec &x, uint64_t s_begin, uint64_t s_end, con
             fp.root_off = (int32_t)prog.lds_offset[prog.root_pre];
             fp.partial = partial;
             fp.lds_elems = (int32_t)prog.lds_elems;
-            if (prog.fused_pairs == 0 && !tune_fused(prog, fp, st, err)) return false;
+            if (prog.fused_pairs == 0 && !tune_fused(prog, fp, st, err)) { plan->profiling = saved; return false; }
             prof.begin();
             launch_fused_pairs(fp, prog.fused_pairs, pair_elems_of(prog), zero_slot_of(prog), st);
             prof.end("fused");
@@ -516,16 +522,91 @@ bool enqueue(qc_plan *plan, const Exec &x, uint64_t s_begin, uint64_t s_end, con
                         prof.end(launch_gemm(make_gemm(prog, prog.gemms[op.index], tensors, x.prec, amax, slot), st));
                     }
                 }
-                QC_HIP(hipMemcpyAsync(partial + ((cb - sc) << x.m), tensors + prog.tensors[prog.root].offset,
-                                      (size_t(1) << (prog.b + x.m)) * sizeof(float2), hipMemcpyDeviceToDevice, st));
+                launch_copy(partial + ((cb - sc) << x.m), tensors + prog.tensors[prog.root].offset,
+                            int64_t(1) << (prog.b + x.m), st);
             }
         }
         prof.begin();
         launch_reduce64(partial, x.m, n_bs, sc, int64_t(P / 64), lo, hi, s_begin, out_dev, per_slice_dev, st);
         prof.end("reduce64");
-        QC_HIP(hipGetLastError());
     }
+    plan->profiling = saved;
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) { err = std::string("kernel launch: ") + hipGetErrorString(e); return false; }
     return true;
+}
+
+// Replays the cached graph of this exact call configuration, or captures the
+// launch sequence on the plan's capture stream, instantiates it and replays
+// it (at most 8 graphs per program; the oldest is dropped after the device
+// has drained).  Returns false with err empty if capture is not possible, so
+// the caller launches directly.
+bool launch_graph(qc_plan *plan, const Exec &x, uint64_t s_begin, uint64_t s_end, const uint8_t *bits, int n_bs,
+                  void *ws, hipStream_t st, double *out_dev, double *per_slice_dev, std::string &err) {
+    Program &prog = *x.prog;
+    const std::vector<uint64_t> key = {uint64_t(x.fused), uint64_t(x.prec), uint64_t(x.lp), uint64_t(x.m),
+                                       uint64_t(uintptr_t(ws)), uint64_t(uintptr_t(bits)), uint64_t(n_bs),
+                                       uint64_t(uintptr_t(out_dev)), uint64_t(uintptr_t(per_slice_dev)), s_begin,
+                                       s_end, uint64_t(prog.fused_pairs)};
+    for (auto &g : prog.graphs)
+        if (g.first == key) {
+            QC_HIP(hipGraphLaunch((hipGraphExec_t)g.second, st));
+            return true;
+        }
+    if (!plan->capture_stream) {
+        hipStream_t cs = nullptr;
+        QC_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+        plan->capture_stream = (void *)cs;
+    }
+    hipStream_t cs = (hipStream_t)plan->capture_stream;
+    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    std::string lerr;
+    const bool ok = launch_all(plan, x, s_begin, s_end, bits, n_bs, ws, cs, out_dev, per_slice_dev, false, lerr);
+    hipGraph_t graph = nullptr;
+    const hipError_t ec = hipStreamEndCapture(cs, &graph);
+    hipGraphExec_t exec = nullptr;
+    const bool inst = ok && ec == hipSuccess && graph &&
+                      hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess;
+    if (graph) (void)hipGraphDestroy(graph);
+    if (!inst) {
+        (void)hipGetLastError();
+        return false;
+    }
+    if (prog.graphs.size() >= 8) {
+        QC_HIP(hipDeviceSynchronize());
+        (void)hipGraphExecDestroy((hipGraphExec_t)prog.graphs.front().second);
+        prog.graphs.erase(prog.graphs.begin());
+    }
+    prog.graphs.push_back({key, (void *)exec});
+    QC_HIP(hipGraphLaunch(exec, st));
+    return true;
+}
+
+// bits_in: host bitstrings (copied into the workspace) or, with bits_on_device,
+// the caller's device array (read in place).
+bool enqueue(qc_plan *plan, const Exec &x, uint64_t s_begin, uint64_t s_end, const uint8_t *bits_in,
+             bool bits_on_device, int n_bs, void *ws, hipStream_t st, double *out_dev, double *per_slice_dev,
+             std::string &err) {
+    std::lock_guard<std::mutex> lk(plan->dev_mu);
+    Program &prog = *x.prog;
+    if (!ensure_device(plan, prog, x.fused, err)) return false;
+    const WsLayout w = ws_layout(x, plan->net.n_qubits);
+    const uint8_t *bits = bits_in;
+    if (!bits_on_device) {
+        uint8_t *dst = (uint8_t *)ws + w.bits_off;
+        QC_HIP(hipMemcpyAsync(dst, bits_in, size_t(n_bs) * plan->net.n_qubits, hipMemcpyHostToDevice, st));
+        bits = dst;
+    }
+    // Graphs pay off for the stepwise form's long launch sequences; the fused
+    // form is two launches per super-chunk, which replay no faster.
+    if (plan->use_graphs && !plan->profiling && !x.fused) {
+        if (launch_graph(plan, x, s_begin, s_end, bits, n_bs, ws, st, out_dev, per_slice_dev, err)) return true;
+        if (!err.empty()) return false;
+    }
+    return launch_all(plan, x, s_begin, s_end, bits, n_bs, ws, st, out_dev, per_slice_dev, plan->profiling, err);
 }
 
 }  // namespace
@@ -535,6 +616,8 @@ void free_program_device(Program &prog) {
     int cur = 0;
     (void)hipGetDevice(&cur);
     (void)hipSetDevice(prog.device);
+    for (auto &g : prog.graphs) (void)hipGraphExecDestroy((hipGraphExec_t)g.second);
+    prog.graphs.clear();
     for (void **p : {&prog.d_leaf_desc, &prog.d_leaf_block, &prog.d_base, &prog.d_fused_image, &prog.d_fused_elems,
                      &prog.d_fused_pool, &prog.d_fused_items, &prog.d_fused_levels}) {
         if (*p) (void)hipFree(*p);
@@ -655,6 +738,13 @@ extern "C" qc_status qc_amplitude(qc_plan *plan, const uint8_t *bitstring, qc_pr
     return st;
 }
 
+extern "C" qc_status qc_plan_set_graphs(qc_plan *plan, int32_t on) {
+    if (!plan) { set_error("qc_plan_set_graphs: NULL plan"); return QC_ERR_INVALID_ARG; }
+    std::lock_guard<std::mutex> lk(plan->dev_mu);
+    plan->use_graphs = on != 0;
+    return QC_OK;
+}
+
 extern "C" qc_status qc_profile_enable(qc_plan *plan, int32_t on) {
     if (!plan) { set_error("qc_profile_enable: NULL plan"); return QC_ERR_INVALID_ARG; }
     plan->profiling = on != 0;
@@ -696,6 +786,7 @@ extern "C" void qc_plan_destroy(qc_plan *plan) {
     for (auto &pe : plan->prof_pending) plan->prof_pool.push_back(pe.second.first), plan->prof_pool.push_back(pe.second.second);
     for (void *e : plan->prof_pool) hipEventDestroy((hipEvent_t)e);
     for (auto &kv : plan->programs) qc::free_program_device(*kv.second);
+    if (plan->capture_stream) (void)hipStreamDestroy((hipStream_t)plan->capture_stream);
     delete plan;
 }
 

@@ -28,7 +28,7 @@ EXPORTED = (
     "qc_plan_build", "qc_plan_info", "qc_plan_sliced_segments", "qc_plan_slice_assignment",
     "qc_plan_describe", "qc_workspace_bytes", "qc_contract_slices", "qc_amplitude",
     "qc_gate_matrix", "qc_plan_destroy", "qc_last_error", "qc_kernel_gemm", "qc_kernel_transpose",
-    "qc_plan_set_exec", "qc_profile_enable", "qc_profile_read", "qc_contract_slices_dev",
+    "qc_plan_set_exec", "qc_profile_enable", "qc_profile_read", "qc_contract_slices_dev", "qc_plan_set_graphs",
 )
 EXEC_MODES = {"auto": 0, "fused": 1, "stepwise": 2}
 
@@ -114,6 +114,8 @@ def load(path: str | None = None):
         lib.qc_kernel_gemm.restype = ctypes.c_int
         lib.qc_kernel_transpose.argtypes = [vp, vp, ctypes.c_int32, vp, vp]
         lib.qc_kernel_transpose.restype = ctypes.c_int
+        lib.qc_plan_set_graphs.argtypes = [vp, ctypes.c_int32]
+        lib.qc_plan_set_graphs.restype = ctypes.c_int
         lib.qc_profile_enable.argtypes = [vp, ctypes.c_int32]
         lib.qc_profile_enable.restype = ctypes.c_int
         lib.qc_profile_read.argtypes = [vp, ctypes.POINTER(qc_kernel_stat_t), ctypes.c_int32,
@@ -214,6 +216,11 @@ def qc_plan_describe(plan: Plan, log2_batch_slices: int = 0, log2_batch_bs: int 
 def qc_plan_set_exec(plan: Plan, mode) -> None:
     m = EXEC_MODES[mode] if isinstance(mode, str) else int(mode)
     _check(plan._lib.qc_plan_set_exec(plan.handle, m), plan._lib)
+
+
+def qc_plan_set_graphs(plan: Plan, on: bool = True) -> None:
+    """Replay captured HIP graphs for repeated call configurations (default on)."""
+    _check(plan._lib.qc_plan_set_graphs(plan.handle, int(bool(on))), plan._lib)
 
 
 def qc_profile_enable(plan: Plan, on: bool = True) -> None:

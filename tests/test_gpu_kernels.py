@@ -21,6 +21,10 @@ GEMM_SHAPES = [
     (1, 32, 32, 2), (3, 64, 64, 16), (2, 64, 32, 32), (1, 128, 64, 64), (5, 32, 64, 8),
     (2, 256, 128, 128), (1, 64, 64, 4),
     (4, 2, 4, 8), (7, 1, 16, 4), (1, 1, 1, 1024), (16, 64, 64, 1), (8, 16, 16, 16), (1, 32, 2, 64),
+    # m <= 16 with n >= 256: the skinny form (one thread per column of C)
+    (2, 1, 1024, 4), (1, 4, 4096, 64), (3, 16, 300, 7), (5, 8, 256, 1), (1, 2, 65536, 2),
+    # a few outputs with k >= 4096: the dot form (one workgroup per output)
+    (1, 1, 1, 1 << 20), (2, 2, 2, 5000), (1, 1, 3, 4096),
 ]
 
 
@@ -46,7 +50,7 @@ def test_gemm_c64(shape, a_km, b_nk):
     assert np.abs(got - ref).max() <= tol * max(1.0, np.sqrt(k)), np.abs(got - ref).max()
 
 
-@pytest.mark.parametrize("rank", [0, 1, 3, 5, 8, 10, 11, 14, 18, 22])
+@pytest.mark.parametrize("rank", [0, 1, 3, 5, 8, 10, 11, 14, 18, 22, 24])
 def test_transpose_exact(rank):
     rng = np.random.default_rng(rank)
     perm = rng.permutation(rank).astype(np.int32)
@@ -71,3 +75,33 @@ def test_transpose_rejects_bad_perm():
     d = torch.zeros(8, dtype=torch.complex64, device="cuda")
     with pytest.raises(qcsim.QcError):
         qcsim.qc_kernel_transpose(d, d, 3, [0, 0, 1])
+
+
+@pytest.mark.parametrize("kind", ["identity", "reverse", "low_fixed", "rotate"])
+def test_transpose_structured(kind):
+    # Permutations whose input-low and output-low bits overlap (the tile then
+    # grows along both) or coincide entirely.
+    rank = 20
+    if kind == "identity":
+        perm = np.arange(rank)
+    elif kind == "reverse":
+        perm = np.arange(rank)[::-1]
+    elif kind == "low_fixed":
+        perm = np.concatenate([np.arange(7), np.random.default_rng(3).permutation(np.arange(7, rank))])
+    else:
+        perm = (np.arange(rank) + 3) % rank
+    perm = perm.astype(np.int32)
+    rng = np.random.default_rng(11)
+    x = _rand(rng, (1 << rank,))
+    d_in = torch.from_numpy(x).cuda()
+    d_out = torch.zeros(1 << rank, dtype=torch.complex64, device="cuda")
+    say(f"transpose rank={rank} {kind}")
+    qcsim.qc_kernel_transpose(d_in, d_out, rank, perm)
+    torch.cuda.synchronize()
+    i = np.arange(1 << rank, dtype=np.int64)
+    o = np.zeros_like(i)
+    for p in range(rank):
+        o |= ((i >> p) & 1) << int(perm[p])
+    ref = np.zeros_like(x)
+    ref[o] = x
+    assert np.array_equal(d_out.cpu().numpy().view(np.uint64), ref.view(np.uint64))

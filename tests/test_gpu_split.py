@@ -105,7 +105,7 @@ def test_split_gemm_error_bound(prec, shape, a_km, b_nk):
 def test_split_gemm_small_shapes_use_fp32(prec):
     # Shapes below the 32x32 tile (or k = 1) take the FP32 vector-ALU form.
     rng = np.random.default_rng(5)
-    for nb, m, n, k in [(4, 2, 4, 8), (16, 64, 64, 1), (1, 32, 2, 64)]:
+    for nb, m, n, k in [(4, 2, 4, 8), (16, 64, 64, 1), (1, 32, 2, 64), (2, 8, 512, 16)]:
         A = rng.standard_normal((nb, m, k)) + 1j * rng.standard_normal((nb, m, k))
         B = rng.standard_normal((nb, k, n)) + 1j * rng.standard_normal((nb, k, n))
         got = _run(A, B, nb, m, n, k, 0, 0, prec)
