@@ -844,10 +844,11 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
-// One workgroup per bitstring.  Its four waves form the 64-slice block sums
-// (fixed butterfly) of up to 256 blocks at a time into LDS; then one thread
-// adds them to the running total in increasing block order, so the result is
-// bitwise the same as adding the blocks one after another.
+// One workgroup per bitstring.  Its waves (one, or four when there are many
+// blocks) form the 64-slice block sums (fixed butterfly) of up to 256 blocks
+// at a time into LDS; then one thread adds them to the running total in
+// increasing block order, so the result is bitwise the same as adding the
+// blocks one after another.
 constexpr int kReduceBatch = 256;
 
 __global__ void __launch_bounds__(256) reduce64_kernel(const float2 *__restrict__ partial, int m, int n_bs,
@@ -862,7 +863,7 @@ __global__ void __launch_bounds__(256) reduce64_kernel(const float2 *__restrict_
     if (threadIdx.x == 0) { acc_re = out[2 * bs]; acc_im = out[2 * bs + 1]; }
     for (int64_t first = 0; first < n_blocks; first += kReduceBatch) {
         const int nb = int(n_blocks - first < kReduceBatch ? n_blocks - first : kReduceBatch);
-        for (int j = wave; j < nb; j += 4) {
+        for (int j = wave; j < nb; j += int(blockDim.x) / 64) {
             const uint64_t b0 = sc + uint64_t(first + j) * 64;
             const bool in = !(b0 + 64 <= lo || b0 >= hi);
             double re = 0.0, im = 0.0;
@@ -898,8 +899,9 @@ __global__ void __launch_bounds__(256) reduce64_kernel(const float2 *__restrict_
 
 void launch_reduce64(const float2 *partial, int m, int n_bs, uint64_t sc, int64_t n_blocks, uint64_t lo, uint64_t hi,
                      uint64_t s_begin, double *out, double *per_slice, hipStream_t st) {
-    hipLaunchKernelGGL(reduce64_kernel, dim3(n_bs), dim3(256), 0, st, partial, m, n_bs, sc, n_blocks, lo, hi, s_begin,
-                       out, per_slice);
+    const int threads = n_blocks >= 16 ? 256 : 64;
+    hipLaunchKernelGGL(reduce64_kernel, dim3(n_bs), dim3(threads), 0, st, partial, m, n_bs, sc, n_blocks, lo, hi,
+                       s_begin, out, per_slice);
 }
 
 }  // namespace qc
