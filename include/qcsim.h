@@ -174,6 +174,21 @@ qc_status qc_plan_set_exec(qc_plan *plan, int32_t mode);
  * directly. */
 qc_status qc_plan_set_graphs(qc_plan *plan, int32_t on);
 
+/* Autotuning (untimed preparation, like qc_plan_build).  Lowers the plan
+ * for chunk_slices slices and n_bs bitstrings in flight (as
+ * qc_contract_slices would with this workspace) and, for every GEMM step of
+ * the stepwise program, times each applicable kernel form (MFMA tile shapes,
+ * the split 128 x 128 tile, the skinny, dot and vector-ALU forms) on the
+ * caller's workspace (contents are overwritten) and stream, and keeps the
+ * fastest for this plan and precision.  Choices are shared process-wide per
+ * (device architecture, precision, shape, operand layout); cache_path (or
+ * NULL) names a text file that is read first, so known shapes are not timed
+ * again, and rewritten afterwards.  *n_timed (optional) receives the number
+ * of shapes timed.  Synchronous.  Fused programs time their own launch forms
+ * on first use and are left alone here. */
+qc_status qc_tune(qc_plan *plan, int64_t chunk_slices, int32_t n_bs, qc_precision prec, void *ws,
+                  size_t ws_bytes, void *stream, const char *cache_path, int32_t *n_timed);
+
 /* Kernel timing.  While enabled, qc_contract_slices records a pair of HIP
  * events on its stream around every kernel it launches.  qc_profile_read
  * waits for the recorded events, then reports per kernel kind the launch

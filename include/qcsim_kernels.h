@@ -40,6 +40,18 @@ extern "C" {
 qc_status qc_kernel_gemm(const void *A, const void *B, void *C, int64_t nb, int64_t m, int64_t n, int64_t k,
                          int32_t a_km, int32_t b_nk, qc_precision prec, void *scale_ws, void *stream);
 
+/* qc_kernel_gemm with the kernel form fixed (the choices qc_tune times):
+ *   0 vector ALU (any shape), 1 skinny (m in {1,2,4,8,16}, n >= 64),
+ *   2 dot (k >= 256, nb m n <= 65536), 3..6 complex FP32 MFMA with block
+ *   tiles 32x32, 32x64, 64x32, 64x64 (QC_C64; k in {2,4,8} or a multiple of
+ *   16), 7 split 128x128, 8..11 split 32x32, 32x64, 64x32, 64x64 (split
+ *   precisions, k >= 2); form -1 is the default choice.  Forms 0..2 compute
+ *   in FP32 for every precision.  QC_ERR_UNSUPPORTED if the form does not
+ *   apply to the shape and precision. */
+qc_status qc_kernel_gemm_form(const void *A, const void *B, void *C, int64_t nb, int64_t m, int64_t n, int64_t k,
+                              int32_t a_km, int32_t b_nk, qc_precision prec, int32_t form, void *scale_ws,
+                              void *stream);
+
 /* Bit-permuting transpose of a rank-r tensor (2^r complex64 values): the
  * value at input offset i goes to the output offset whose bit perm[p] equals
  * bit p of i, for p = 0..r-1 (bit 0 = least significant).  perm is a host

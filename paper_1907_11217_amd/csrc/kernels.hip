@@ -617,48 +617,98 @@ __global__ void __launch_bounds__(256) gemm_split_big_kernel(GemmDesc d) {
     if (d.amax_c) block_amax(mx, d.amax_c);
 }
 
-const char *launch_gemm(const GemmDesc &d, hipStream_t st) {
-    const bool tiles32 = d.m % 32 == 0 && d.n % 32 == 0;
+// ----------------------------------------------------------- GEMM variants
+// Every kernel form a GEMM step can run as.  gemm_variant_ok says whether a
+// form applies to a shape (tile divisibility, k, precision); the default
+// choice follows fixed rules, the autotuner may pick another applicable one.
+bool gemm_variant_ok(const GemmDesc &d, int v) {
+    const bool split = d.prec != kPrecC64;
+    const int64_t kt = d.k >= 16 ? 16 : d.k;
+    const bool k_fp32 = (kt == 2 || kt == 4 || kt == 8 || kt == 16) && d.k % kt == 0;
+    const bool m_pow2_16 = d.m == 1 || d.m == 2 || d.m == 4 || d.m == 8 || d.m == 16;
+    switch (v) {
+        case kVarValu: return true;
+        case kVarSkinny: return d.n >= 64 && m_pow2_16;
+        case kVarDot: return d.k >= 256 && d.nb * d.m * d.n <= 65536;
+        case kVarMfma11: case kVarMfma12: case kVarMfma21: case kVarMfma22: {
+            const int wm = (v == kVarMfma21 || v == kVarMfma22) ? 2 : 1, wn = (v == kVarMfma12 || v == kVarMfma22) ? 2 : 1;
+            return !split && k_fp32 && d.m % (32 * wm) == 0 && d.n % (32 * wn) == 0;
+        }
+        case kVarSplitBig: return split && d.k >= 2 && d.m % 128 == 0 && d.n % 128 == 0;
+        case kVarSplit11: case kVarSplit12: case kVarSplit21: case kVarSplit22: {
+            const int wm = (v == kVarSplit21 || v == kVarSplit22) ? 2 : 1, wn = (v == kVarSplit12 || v == kVarSplit22) ? 2 : 1;
+            return split && d.k >= 2 && d.m % (32 * wm) == 0 && d.n % (32 * wn) == 0;
+        }
+        default: return false;
+    }
+}
+
+int gemm_default_variant(const GemmDesc &d) {
+    if (d.prec != kPrecC64 && gemm_variant_ok(d, kVarSplitBig)) return kVarSplitBig;
     const int wm = d.m % 64 == 0 ? 2 : 1, wn = d.n % 64 == 0 ? 2 : 1;
-    const int64_t tiles = d.nb * (d.m / (32 * wm)) * (d.n / (32 * wn));
+    if (d.prec != kPrecC64) {
+        const int v = wm == 2 ? (wn == 2 ? kVarSplit22 : kVarSplit21) : (wn == 2 ? kVarSplit12 : kVarSplit11);
+        if (gemm_variant_ok(d, v)) return v;
+    } else {
+        const int v = wm == 2 ? (wn == 2 ? kVarMfma22 : kVarMfma21) : (wn == 2 ? kVarMfma12 : kVarMfma11);
+        if (gemm_variant_ok(d, v)) return v;
+    }
+    if (d.k >= 4096 && d.nb * d.m * d.n <= 4096) return kVarDot;
+    if (d.n >= 256 && gemm_variant_ok(d, kVarSkinny)) return kVarSkinny;
+    return kVarValu;
+}
+
+namespace {
+template <int WM, int WN>
+void launch_mfma(const GemmDesc &d, hipStream_t st) {
+    const int64_t tiles = d.nb * (d.m / (32 * WM)) * (d.n / (32 * WN));
     const unsigned grid = (unsigned)(tiles < 1048576 ? tiles : 1048576);
-    // The split forms need whole 32x32 tiles (K is zero-padded to the slab).
-    if (d.prec != kPrecC64 && d.m % 128 == 0 && d.n % 128 == 0 && d.k >= 2) {
-        const int64_t t128 = d.nb * (d.m / 128) * (d.n / 128);
-        const unsigned g = (unsigned)(t128 < 1048576 ? t128 : 1048576);
-        if (d.prec == kPrecFP16) {
-            hipLaunchKernelGGL(gemm_split_big_kernel<_Float16>, dim3(g), dim3(256), 0, st, d);
-            return "gemm_split_fp16";
+    switch (d.k >= 16 ? 16 : int(d.k)) {
+        case 2: hipLaunchKernelGGL((gemm_mfma_kernel<WM, WN, 2>), dim3(grid), dim3(64 * WM * WN), 0, st, d); break;
+        case 4: hipLaunchKernelGGL((gemm_mfma_kernel<WM, WN, 4>), dim3(grid), dim3(64 * WM * WN), 0, st, d); break;
+        case 8: hipLaunchKernelGGL((gemm_mfma_kernel<WM, WN, 8>), dim3(grid), dim3(64 * WM * WN), 0, st, d); break;
+        default: hipLaunchKernelGGL((gemm_mfma_kernel<WM, WN, 16>), dim3(grid), dim3(64 * WM * WN), 0, st, d); break;
+    }
+}
+
+template <int WM, int WN>
+void launch_split(const GemmDesc &d, hipStream_t st) {
+    const int64_t tiles = d.nb * (d.m / (32 * WM)) * (d.n / (32 * WN));
+    const unsigned grid = (unsigned)(tiles < 1048576 ? tiles : 1048576);
+    if (d.prec == kPrecFP16)
+        hipLaunchKernelGGL((gemm_split_kernel<_Float16, WM, WN>), dim3(grid), dim3(64 * WM * WN), 0, st, d);
+    else
+        hipLaunchKernelGGL((gemm_split_kernel<__bf16, WM, WN>), dim3(grid), dim3(64 * WM * WN), 0, st, d);
+}
+}  // namespace
+
+const char *launch_gemm_variant(const GemmDesc &d, int v, hipStream_t st) {
+    const char *split_name = d.prec == kPrecFP16 ? "gemm_split_fp16" : "gemm_split_bf16";
+    switch (v) {
+        case kVarMfma11: launch_mfma<1, 1>(d, st); return "gemm_mfma";
+        case kVarMfma12: launch_mfma<1, 2>(d, st); return "gemm_mfma";
+        case kVarMfma21: launch_mfma<2, 1>(d, st); return "gemm_mfma";
+        case kVarMfma22: launch_mfma<2, 2>(d, st); return "gemm_mfma";
+        case kVarSplit11: launch_split<1, 1>(d, st); return split_name;
+        case kVarSplit12: launch_split<1, 2>(d, st); return split_name;
+        case kVarSplit21: launch_split<2, 1>(d, st); return split_name;
+        case kVarSplit22: launch_split<2, 2>(d, st); return split_name;
+        case kVarSplitBig: {
+            const int64_t t128 = d.nb * (d.m / 128) * (d.n / 128);
+            const unsigned g = (unsigned)(t128 < 1048576 ? t128 : 1048576);
+            if (d.prec == kPrecFP16)
+                hipLaunchKernelGGL(gemm_split_big_kernel<_Float16>, dim3(g), dim3(256), 0, st, d);
+            else
+                hipLaunchKernelGGL(gemm_split_big_kernel<__bf16>, dim3(g), dim3(256), 0, st, d);
+            return split_name;
         }
-        hipLaunchKernelGGL(gemm_split_big_kernel<__bf16>, dim3(g), dim3(256), 0, st, d);
-        return "gemm_split_bf16";
-    }
-    if (d.prec != kPrecC64 && tiles32 && d.k >= 2) {
-#define QC_SPLIT_CASE(T, WM, WN)                                                                       \
-    if (wm == WM && wn == WN) {                                                                        \
-        hipLaunchKernelGGL((gemm_split_kernel<T, WM, WN>), dim3(grid), dim3(64 * WM * WN), 0, st, d);    \
-        return d.prec == kPrecFP16 ? "gemm_split_fp16" : "gemm_split_bf16";                            \
-    }
-        if (d.prec == kPrecFP16) {
-            QC_SPLIT_CASE(_Float16, 1, 1) QC_SPLIT_CASE(_Float16, 1, 2) QC_SPLIT_CASE(_Float16, 2, 1)
-            QC_SPLIT_CASE(_Float16, 2, 2)
-        } else {
-            QC_SPLIT_CASE(__bf16, 1, 1) QC_SPLIT_CASE(__bf16, 1, 2) QC_SPLIT_CASE(__bf16, 2, 1)
-            QC_SPLIT_CASE(__bf16, 2, 2)
-        }
-#undef QC_SPLIT_CASE
-    }
-    // The FP32 MFMA form needs whole 32x32 tiles and a K that the LDS slab
-    // divides; it records no max|x| (the split forms never route here).
-    const int64_t kt_try = d.k >= 16 ? 16 : d.k;
-    const bool k_ok = (kt_try == 2 || kt_try == 4 || kt_try == 8 || kt_try == 16) && d.k % kt_try == 0;
-    if (d.prec != kPrecC64 || !k_ok || !tiles32) {
-        if (d.k >= 4096 && d.nb * d.m * d.n <= 4096) {
+        case kVarDot: {
             const int64_t outs = d.nb * d.m * d.n;
-            hipLaunchKernelGGL(gemm_dot_kernel, dim3((unsigned)outs), dim3(1024), 0, st, d);
+            const unsigned g = (unsigned)(outs < 65536 ? outs : 65536);
+            hipLaunchKernelGGL(gemm_dot_kernel, dim3(g), dim3(1024), 0, st, d);
             return "gemm_dot";
         }
-        if (d.n >= 256 && (d.m == 1 || d.m == 2 || d.m == 4 || d.m == 8 || d.m == 16)) {
+        case kVarSkinny: {
             const int64_t blocks = d.nb * ((d.n + 255) / 256);
             const unsigned g = (unsigned)(blocks < 8192 ? blocks : 8192);
             switch (d.m) {
@@ -670,27 +720,17 @@ const char *launch_gemm(const GemmDesc &d, hipStream_t st) {
             }
             return "gemm_skinny";
         }
-        const int64_t total = d.nb * d.m * d.n;
-        int64_t g = (total + 255) / 256;
-        if (g > 8192) g = 8192;
-        hipLaunchKernelGGL(gemm_valu_kernel, dim3((unsigned)g), dim3(256), 0, st, d);
-        return "gemm_valu";
+        default: {
+            const int64_t total = d.nb * d.m * d.n;
+            int64_t g = (total + 255) / 256;
+            if (g > 8192) g = 8192;
+            hipLaunchKernelGGL(gemm_valu_kernel, dim3((unsigned)g), dim3(256), 0, st, d);
+            return "gemm_valu";
+        }
     }
-    const int kt = d.k >= 16 ? 16 : (int)d.k;
-#define QC_GEMM_CASE(WM, WN, KT)                                                                        \
-    if (wm == WM && wn == WN && kt == KT) {                                                               \
-        hipLaunchKernelGGL((gemm_mfma_kernel<WM, WN, KT>), dim3(grid), dim3(64 * WM * WN), 0, st, d);     \
-        return "gemm_mfma";                                                                              \
-    }
-#define QC_GEMM_KTS(WM, WN) QC_GEMM_CASE(WM, WN, 2) QC_GEMM_CASE(WM, WN, 4) QC_GEMM_CASE(WM, WN, 8) QC_GEMM_CASE(WM, WN, 16)
-    QC_GEMM_KTS(1, 1)
-    QC_GEMM_KTS(1, 2)
-    QC_GEMM_KTS(2, 1)
-    QC_GEMM_KTS(2, 2)
-#undef QC_GEMM_KTS
-#undef QC_GEMM_CASE
-    return "gemm_none";
 }
+
+const char *launch_gemm(const GemmDesc &d, hipStream_t st) { return launch_gemm_variant(d, gemm_default_variant(d), st); }
 
 // ------------------------------------------------------------------ fused
 // One work item = one (slice, bitstring) pair, one wavefront.  Leaves are

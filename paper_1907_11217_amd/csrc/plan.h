@@ -102,6 +102,7 @@ struct GemmOp {
     bool a_km;                 // A stored [b][k][m] (else [b][m][k])
     bool b_nk;                 // B stored [b][n][k] (else [b][k][n])
     int cls_b, cls_m, cls_n, cls_k;  // log2 extents
+    int variant[3] = {-1, -1, -1};   // GEMM kernel form per precision chosen by qc_tune (-1: default rules)
 };
 
 struct Op {

@@ -17,6 +17,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdio>
+#include <map>
+#include <mutex>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -519,7 +522,10 @@ bool launch_all(qc_plan *plan, const Exec &x, uint64_t s_begin, uint64_t s_end, 
                         launch_transpose(make_transpose(prog, prog.transposes[op.index], tensors), st);
                         prof.end("transpose");
                     } else {
-                        prof.end(launch_gemm(make_gemm(prog, prog.gemms[op.index], tensors, x.prec, amax, slot), st));
+                        const GemmOp &g = prog.gemms[op.index];
+                        const GemmDesc gd = make_gemm(prog, g, tensors, x.prec, amax, slot);
+                        const int v = g.variant[x.prec];
+                        prof.end(v >= 0 && gemm_variant_ok(gd, v) ? launch_gemm_variant(gd, v, st) : launch_gemm(gd, st));
                     }
                 }
                 launch_copy(partial + ((cb - sc) << x.m), tensors + prog.tensors[prog.root].offset,
@@ -607,6 +613,46 @@ bool enqueue(qc_plan *plan, const Exec &x, uint64_t s_begin, uint64_t s_end, con
         if (!err.empty()) return false;
     }
     return launch_all(plan, x, s_begin, s_end, bits, n_bs, ws, st, out_dev, per_slice_dev, plan->profiling, err);
+}
+
+// ------------------------------------------------------------------ tuning
+// Process-wide choice of GEMM kernel form per (device architecture,
+// precision, shape, operand layouts), filled by qc_tune from timings or a
+// cache file of lines "arch prec nb m n k a_km b_nk variant ms".
+std::mutex g_tune_mu;
+std::map<std::string, std::pair<int, float>> g_tune;
+
+std::string tune_key(const std::string &arch, const GemmDesc &d, bool a_km, bool b_nk) {
+    return arch + " " + std::to_string(d.prec) + " " + std::to_string(d.nb) + " " + std::to_string(d.m) + " " +
+           std::to_string(d.n) + " " + std::to_string(d.k) + " " + std::to_string(int(a_km)) + " " +
+           std::to_string(int(b_nk));
+}
+
+void tune_load(const char *path) {
+    if (!path) return;
+    FILE *f = std::fopen(path, "r");
+    if (!f) return;
+    char arch[64];
+    int prec, a_km, b_nk, v;
+    long long nb, m, n, k;
+    float ms;
+    while (std::fscanf(f, "%63s %d %lld %lld %lld %lld %d %d %d %f", arch, &prec, &nb, &m, &n, &k, &a_km, &b_nk, &v,
+                       &ms) == 10) {
+        if (v < 0 || v >= kVarCount) continue;
+        GemmDesc d{};
+        d.prec = prec; d.nb = nb; d.m = m; d.n = n; d.k = k;
+        g_tune[tune_key(arch, d, a_km, b_nk)] = {v, ms};
+    }
+    std::fclose(f);
+}
+
+bool tune_save(const char *path, std::string &err) {
+    if (!path) return true;
+    FILE *f = std::fopen(path, "w");
+    if (!f) { err = std::string("cannot write ") + path; return false; }
+    for (auto &kv : g_tune) std::fprintf(f, "%s %d %.6f\n", kv.first.c_str(), kv.second.first, kv.second.second);
+    std::fclose(f);
+    return true;
 }
 
 }  // namespace
@@ -745,6 +791,100 @@ extern "C" qc_status qc_plan_set_graphs(qc_plan *plan, int32_t on) {
     return QC_OK;
 }
 
+extern "C" qc_status qc_tune(qc_plan *plan, int64_t chunk_slices, int32_t n_bs, qc_precision prec, void *ws,
+                             size_t ws_bytes, void *stream, const char *cache_path, int32_t *n_timed) {
+    if (!plan || !ws || chunk_slices < 1 || n_bs < 1 || n_bs > (1 << qc::kMaxBsBits) || !valid_prec(prec)) {
+        set_error("qc_tune: invalid argument");
+        return QC_ERR_INVALID_ARG;
+    }
+    const int k = (int)plan->sliced.size();
+    const int b = qc::ceil_log2(chunk_slices);
+    if (b > k) { set_error("qc_tune: more slices than the plan has"); return QC_ERR_RANGE; }
+    std::string err;
+    qc::Exec x;
+    if (!qc::choose_exec(plan, qc::ceil_log2(n_bs), b, qc::prec_code(prec), ws_bytes, x, err)) {
+        set_error("qc_tune: " + err);
+        return err.find("workspace") != std::string::npos ? QC_ERR_NOMEM : QC_ERR_UNSUPPORTED;
+    }
+    int32_t timed = 0;
+    if (!x.fused) {
+        std::lock_guard<std::mutex> lk(plan->dev_mu);
+        qc::Program &prog = *x.prog;
+        const hipStream_t st = (hipStream_t)stream;
+        if (!qc::ensure_device(plan, prog, false, err)) { set_error("qc_tune: " + err); return QC_ERR_DEVICE; }
+        int dev = 0;
+        hipDeviceProp_t props;
+        if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&props, dev) != hipSuccess) {
+            set_error("qc_tune: device query failed");
+            return QC_ERR_DEVICE;
+        }
+        const std::string arch = std::string(props.gcnArchName).substr(0, std::string(props.gcnArchName).find(':'));
+        std::lock_guard<std::mutex> tl(qc::g_tune_mu);
+        qc::tune_load(cache_path);
+        const qc::WsLayout w = qc::ws_layout(x, plan->net.n_qubits);
+        float2 *tensors = (float2 *)((char *)ws + w.tensor_off);
+        uint32_t *amax = x.prec == qc::kPrecFP16 ? (uint32_t *)((char *)ws + w.amax_off) : nullptr;
+        std::vector<int> slot(prog.tensors.size());
+        for (size_t t = 0; t < slot.size(); ++t) slot[t] = (int)t;
+        for (const qc::Op &op : prog.ops)
+            if (op.kind == qc::Op::TRANSPOSE) slot[prog.transposes[op.index].dst] = slot[prog.transposes[op.index].src];
+        if (amax) qc::launch_zero_u32(amax, (int64_t)slot.size(), st);
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+            set_error("qc_tune: event creation failed");
+            return QC_ERR_DEVICE;
+        }
+        qc_status status = QC_OK;
+        // Operands are the program's own workspace regions: their contents do
+        // not matter for timing, and every access stays inside the tensors.
+        for (qc::GemmOp &g : prog.gemms) {
+            const qc::GemmDesc d = qc::make_gemm(prog, g, tensors, x.prec, amax, slot);
+            const std::string key = qc::tune_key(arch, d, g.a_km, g.b_nk);
+            auto it = qc::g_tune.find(key);
+            if (it == qc::g_tune.end()) {
+                int best = -1;
+                float best_ms = 0.f;
+                // Forms without matrix cores are not timed on large steps that
+                // an MFMA form can take.
+                bool mfma_ok = false;
+                for (int v = qc::kVarMfma11; v < qc::kVarCount; ++v) mfma_ok |= qc::gemm_variant_ok(d, v);
+                const double flops = 8.0 * double(d.nb) * double(d.m) * double(d.n) * double(d.k);
+                for (int v = 0; v < qc::kVarCount; ++v) {
+                    if (!qc::gemm_variant_ok(d, v)) continue;
+                    if (mfma_ok && flops > 1e8 && v < qc::kVarMfma11) continue;
+                    qc::launch_gemm_variant(d, v, st);  // warm-up
+                    float ms = 0.f;
+                    if (hipEventRecord(e0, st) != hipSuccess) { status = QC_ERR_DEVICE; break; }
+                    for (int r = 0; r < 3; ++r) qc::launch_gemm_variant(d, v, st);
+                    if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                        hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                        status = QC_ERR_DEVICE;
+                        break;
+                    }
+                    if (best < 0 || ms < best_ms) { best = v; best_ms = ms; }
+                }
+                if (status != QC_OK || best < 0) break;
+                it = qc::g_tune.insert({key, {best, best_ms / 3}}).first;
+                ++timed;
+            }
+            g.variant[x.prec] = it->second.first;
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (status == QC_OK && hipGetLastError() != hipSuccess) status = QC_ERR_DEVICE;
+        if (status != QC_OK) { set_error("qc_tune: a timing launch failed"); return status; }
+        // Captured graphs hold the previous forms.
+        if (!prog.graphs.empty()) {
+            if (hipDeviceSynchronize() != hipSuccess) { set_error("qc_tune: synchronize failed"); return QC_ERR_DEVICE; }
+            for (auto &gr : prog.graphs) (void)hipGraphExecDestroy((hipGraphExec_t)gr.second);
+            prog.graphs.clear();
+        }
+        if (!qc::tune_save(cache_path, err)) { set_error("qc_tune: " + err); return QC_ERR_INVALID_ARG; }
+    }
+    if (n_timed) *n_timed = timed;
+    return QC_OK;
+}
+
 extern "C" qc_status qc_profile_enable(qc_plan *plan, int32_t on) {
     if (!plan) { set_error("qc_profile_enable: NULL plan"); return QC_ERR_INVALID_ARG; }
     plan->profiling = on != 0;
@@ -790,9 +930,11 @@ extern "C" void qc_plan_destroy(qc_plan *plan) {
     delete plan;
 }
 
-extern "C" qc_status qc_kernel_gemm(const void *A, const void *B, void *C, int64_t nb, int64_t m, int64_t n, int64_t k,
-                                    int32_t a_km, int32_t b_nk, qc_precision prec, void *scale_ws, void *stream) {
-    if (!A || !B || !C || nb < 1 || m < 1 || n < 1 || k < 1 || !valid_prec(prec)) {
+extern "C" qc_status qc_kernel_gemm_form(const void *A, const void *B, void *C, int64_t nb, int64_t m, int64_t n,
+                                         int64_t k, int32_t a_km, int32_t b_nk, qc_precision prec, int32_t form,
+                                         void *scale_ws, void *stream) {
+    if (!A || !B || !C || nb < 1 || m < 1 || n < 1 || k < 1 || !valid_prec(prec) || form < -1 ||
+        form >= qc::kVarCount) {
         set_error("qc_kernel_gemm: invalid argument");
         return QC_ERR_INVALID_ARG;
     }
@@ -814,15 +956,24 @@ extern "C" qc_status qc_kernel_gemm(const void *A, const void *B, void *C, int64
     d.amax_a = amax;
     d.amax_b = amax ? amax + 1 : nullptr;
     d.amax_c = amax ? amax + 2 : nullptr;
+    if (form >= 0 && !qc::gemm_variant_ok(d, form)) {
+        set_error("qc_kernel_gemm_form: the form does not apply to this shape and precision");
+        return QC_ERR_UNSUPPORTED;
+    }
     if (amax) {
         qc::launch_zero_u32(amax, 3, st);
         qc::launch_absmax(d.A, nb * m * k, amax, st);
         qc::launch_absmax(d.B, nb * k * n, amax + 1, st);
     }
-    qc::launch_gemm(d, st);
+    qc::launch_gemm_variant(d, form >= 0 ? form : qc::gemm_default_variant(d), st);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) { set_error(std::string("qc_kernel_gemm: ") + hipGetErrorString(e)); return QC_ERR_DEVICE; }
     return QC_OK;
+}
+
+extern "C" qc_status qc_kernel_gemm(const void *A, const void *B, void *C, int64_t nb, int64_t m, int64_t n, int64_t k,
+                                    int32_t a_km, int32_t b_nk, qc_precision prec, void *scale_ws, void *stream) {
+    return qc_kernel_gemm_form(A, B, C, nb, m, n, k, a_km, b_nk, prec, -1, scale_ws, stream);
 }
 
 extern "C" qc_status qc_kernel_transpose(const void *in, void *out, int32_t rank, const int32_t *perm, void *stream) {

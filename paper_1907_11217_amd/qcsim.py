@@ -29,6 +29,7 @@ EXPORTED = (
     "qc_plan_describe", "qc_workspace_bytes", "qc_contract_slices", "qc_amplitude",
     "qc_gate_matrix", "qc_plan_destroy", "qc_last_error", "qc_kernel_gemm", "qc_kernel_transpose",
     "qc_plan_set_exec", "qc_profile_enable", "qc_profile_read", "qc_contract_slices_dev", "qc_plan_set_graphs",
+    "qc_tune", "qc_kernel_gemm_form",
 )
 EXEC_MODES = {"auto": 0, "fused": 1, "stepwise": 2}
 
@@ -112,8 +113,14 @@ def load(path: str | None = None):
         lib.qc_kernel_gemm.argtypes = [vp, vp, vp, i64, i64, i64, i64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int, vp,
                                        vp]
         lib.qc_kernel_gemm.restype = ctypes.c_int
+        lib.qc_kernel_gemm_form.argtypes = [vp, vp, vp, i64, i64, i64, i64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int,
+                                            ctypes.c_int32, vp, vp]
+        lib.qc_kernel_gemm_form.restype = ctypes.c_int
         lib.qc_kernel_transpose.argtypes = [vp, vp, ctypes.c_int32, vp, vp]
         lib.qc_kernel_transpose.restype = ctypes.c_int
+        lib.qc_tune.argtypes = [vp, i64, ctypes.c_int32, ctypes.c_int, vp, ctypes.c_size_t, vp, ctypes.c_char_p,
+                                ctypes.POINTER(ctypes.c_int32)]
+        lib.qc_tune.restype = ctypes.c_int
         lib.qc_plan_set_graphs.argtypes = [vp, ctypes.c_int32]
         lib.qc_plan_set_graphs.restype = ctypes.c_int
         lib.qc_profile_enable.argtypes = [vp, ctypes.c_int32]
@@ -218,6 +225,19 @@ def qc_plan_set_exec(plan: Plan, mode) -> None:
     _check(plan._lib.qc_plan_set_exec(plan.handle, m), plan._lib)
 
 
+def qc_tune(plan: Plan, chunk_slices: int, n_bs: int, prec, ws, cache_path=None, stream=None) -> int:
+    """Times the GEMM kernel forms of the stepwise program for this chunk and
+    keeps the fastest; returns the number of shapes timed (0 when the cache
+    file already held them all)."""
+    import torch
+    st = stream if stream is not None else torch.cuda.current_stream()
+    n = ctypes.c_int32(0)
+    _check(plan._lib.qc_tune(plan.handle, int(chunk_slices), int(n_bs), _prec(prec), ws.data_ptr(),
+                             ws.numel() * ws.element_size(), st.cuda_stream,
+                             None if cache_path is None else str(cache_path).encode(), ctypes.byref(n)), plan._lib)
+    return n.value
+
+
 def qc_plan_set_graphs(plan: Plan, on: bool = True) -> None:
     """Replay captured HIP graphs for repeated call configurations (default on)."""
     _check(plan._lib.qc_plan_set_graphs(plan.handle, int(bool(on))), plan._lib)
@@ -292,12 +312,16 @@ def qc_contract_slices_dev(plan: Plan, s_begin: int, s_end: int, bits_dev, prec,
         per_slice_dev.data_ptr() if per_slice_dev is not None else None), plan._lib)
 
 
+GEMM_FORMS = {"valu": 0, "skinny": 1, "dot": 2, "mfma11": 3, "mfma12": 4, "mfma21": 5, "mfma22": 6,
+              "split_big": 7, "split11": 8, "split12": 9, "split21": 10, "split22": 11}
+
+
 def qc_kernel_gemm(A, B, C, nb: int, m: int, n: int, k: int, a_km: bool = False, b_nk: bool = False,
-                   prec="c64", scale_ws=None, stream=None):
+                   prec="c64", scale_ws=None, stream=None, form=-1):
     """One batched complex GEMM step on torch complex64 device tensors.
     scale_ws: optional int32 device tensor of >= 3 entries (required for
     split_fp16); afterwards it holds the float bits of max(|re|,|im|) of A, B
-    and C."""
+    and C.  form: a GEMM_FORMS value fixes the kernel form (-1: default)."""
     import torch
     lib = load()
     for t in (A, B, C):
@@ -310,9 +334,9 @@ def qc_kernel_gemm(A, B, C, nb: int, m: int, n: int, k: int, a_km: bool = False,
     if scale_ws is None and _prec(prec) == PRECISIONS["split_fp16"]:
         scale_ws = torch.zeros(3, dtype=torch.int32, device=A.device)
     st = stream if stream is not None else torch.cuda.current_stream()
-    _check(lib.qc_kernel_gemm(A.data_ptr(), B.data_ptr(), C.data_ptr(), nb, m, n, k, int(bool(a_km)),
-                              int(bool(b_nk)), _prec(prec), None if scale_ws is None else scale_ws.data_ptr(),
-                              st.cuda_stream), lib)
+    _check(lib.qc_kernel_gemm_form(A.data_ptr(), B.data_ptr(), C.data_ptr(), nb, m, n, k, int(bool(a_km)),
+                                   int(bool(b_nk)), _prec(prec), int(form),
+                                   None if scale_ws is None else scale_ws.data_ptr(), st.cuda_stream), lib)
 
 
 def qc_kernel_transpose(inp, out, rank: int, perm, stream=None):
