@@ -245,6 +245,26 @@ qc_status qc_contract_slices_dev(qc_plan *plan, uint64_t s_begin, uint64_t s_end
 qc_status qc_amplitude(qc_plan *plan, const uint8_t *bitstring, qc_precision prec,
                        double out_host[2]);
 
+/* Many amplitude requests, each with its own plan, bitstring and slice
+ * range, in one call (asynchronous on `stream`).  Requests whose plan runs
+ * fused (complex FP32, the program fits in LDS) share one launch whose
+ * wavefronts take (request, slice) pairs in turn; the others run stepwise on
+ * four internal streams that start after the caller's earlier work and that
+ * the caller's stream waits for.  Per request r: out_dev[2 r .. 2 r + 1] +=
+ * its sum over slices [s_begin, s_end) (same fixed-order FP64 sum as
+ * qc_contract_slices); t_done_dev[r] = device wall-clock time (see
+ * hipDeviceAttributeWallClockRate) at which its last slice value was
+ * written (fused) or its sum was formed (stepwise); t_done_dev[n] = the
+ * time the batch started.  ws: at least qc_batch_workspace_bytes. */
+typedef struct {
+    qc_plan *plan;
+    const uint8_t *bitstring;    /* host uint8 [n_qubits] of this plan's circuit, copied */
+    uint64_t s_begin, s_end;     /* slice range of this request */
+} qc_request;
+size_t qc_batch_workspace_bytes(const qc_request *reqs, int32_t n, qc_precision prec);
+qc_status qc_contract_batch(const qc_request *reqs, int32_t n, qc_precision prec, void *ws, size_t ws_bytes,
+                            void *stream, double *out_dev, uint64_t *t_done_dev);
+
 /* The library's gate matrix as row-major (re, im) pairs: 2x2 (8 doubles)
  * for one-qubit kinds, 4x4 (32 doubles) for CZ; out must hold 32 doubles. */
 qc_status qc_gate_matrix(int32_t kind, double *out);

@@ -129,6 +129,27 @@ constexpr int kFusedPairsOptions[] = {1, 2, 4};
 size_t fused_lds_bytes(int pairs, int pair_elems);
 void launch_fused_pairs(const FusedParams &p, int pairs, int pair_elems, int zero_slot, hipStream_t st);
 
+// Device descriptor of one request of a fused batch (one bitstring).  Its
+// slice values go to partial[partial_off + (s - s_base)], s_base = s_begin
+// rounded down to a multiple of 64.
+struct BatchReq {
+    const int32_t *level_start;
+    const int4 *items;
+    const int32_t *pool;
+    const float2 *image;
+    const int4 *elems;
+    const double2 *base;
+    const uint8_t *bits;                     // device copy of the bitstring
+    int32_t n_levels, n_image, n_elems, root_off, zero_slot, out_index;  // out_index: position in the caller's array
+    uint64_t s_begin, s_base;
+    int64_t n_slices, item_off, partial_off;
+};
+void launch_fused_batch(const BatchReq *reqs, int n_reqs, int64_t n_items, int max_pair_elems, float2 *partial,
+                        uint32_t *done, uint64_t *t_done, hipStream_t st);
+void launch_reduce_batch(const BatchReq *reqs, int n_reqs, const float2 *partial, double *out, hipStream_t st);
+// t[0] = the device wall clock (constant rate, hipDeviceAttributeWallClockRate kHz).
+void launch_stamp(uint64_t *t, hipStream_t st);
+
 // out[bs] += sum of partial over in-range slices of the super-chunk, in
 // aligned blocks of 64 slices: a fixed butterfly within each block, blocks
 // added in increasing order.

@@ -842,6 +842,129 @@ fused_kernel(const int32_t *__restrict__ level_start, const int4 *__restrict__ i
     }
 }
 
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// ---------------------------------------------------------- fused batches
+// Many independent requests (each its own plan and bitstring) in one
+// launch: a work item is one (request, slice) pair, taken by one wavefront
+// in grid-stride order; the request is found by binary search over the
+// requests' first items.  Each request keeps its own tables; the workgroup
+// allocates the largest pair region among them.  The wavefront that writes
+// a request's last slice value stamps the request's completion time
+// (done[] counts finished slices per request, in batch order; t_done[] is
+// indexed by the request's position in the caller's array).
+__global__ void __launch_bounds__(64) fused_batch_kernel(const BatchReq *__restrict__ reqs, int n_reqs,
+                                                         int64_t n_items, float2 *__restrict__ partial,
+                                                         uint32_t *__restrict__ done, uint64_t *__restrict__ t_done) {
+    extern __shared__ float2 lds[];
+    const int lane = threadIdx.x;
+    for (int64_t item = blockIdx.x; item < n_items; item += gridDim.x) {
+        int lo = 0, hi = n_reqs - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (reqs[mid].item_off <= item) lo = mid;
+            else hi = mid - 1;
+        }
+        const BatchReq &R = reqs[lo];
+        const int64_t sl = item - R.item_off;
+        const uint64_t slice = R.s_begin + uint64_t(sl);
+        for (int e = lane; e < R.n_image; e += 64) lds[e] = R.image[e];
+        if (lane == 0) lds[R.zero_slot] = make_float2(0.f, 0.f);
+        wave_step_sync();
+        for (int e = lane; e < R.n_elems; e += 64) {
+            const int4 t = R.elems[e];
+            const double2 v = R.base[t.y + dyn_bits(t.z, t.w, slice, R.bits)];
+            lds[t.x] = make_float2(float(v.x), float(v.y));
+        }
+        wave_step_sync();
+        for (int lv = 0; lv < R.n_levels; ++lv) {
+            const int i0 = R.level_start[lv], i1 = R.level_start[lv + 1];
+            for (int i = i0 + lane; i < i1; i += 64) {
+                const int4 it = R.items[i];
+                const uint32_t y = uint32_t(it.y), z = uint32_t(it.z);
+                const float2 x0 = lds[y & 0xffffu], y0 = lds[y >> 16];
+                const float2 x1 = lds[z & 0xffffu], y1 = lds[z >> 16];
+                float re = x0.x * y0.x;
+                re = fmaf(-x0.y, y0.y, re);
+                float im = x0.x * y0.y;
+                im = fmaf(x0.y, y0.x, im);
+                re = fmaf(x1.x, y1.x, re);
+                re = fmaf(-x1.y, y1.y, re);
+                im = fmaf(x1.x, y1.y, im);
+                im = fmaf(x1.y, y1.x, im);
+                if (it.w >= 0) {
+                    const int extra = R.pool[it.w];
+                    for (int j = 1; j <= extra; ++j) {
+                        const uint32_t u = uint32_t(R.pool[it.w + j]);
+                        const float2 xa = lds[u & 0xffffu], yb = lds[u >> 16];
+                        re = fmaf(xa.x, yb.x, re);
+                        re = fmaf(-xa.y, yb.y, re);
+                        im = fmaf(xa.x, yb.y, im);
+                        im = fmaf(xa.y, yb.x, im);
+                    }
+                }
+                lds[it.x & 0xffff] = make_float2(re, im);
+            }
+            wave_step_sync();
+        }
+        if (lane == 0) {
+            partial[R.partial_off + (int64_t(slice) - int64_t(R.s_base))] = lds[R.root_off];
+            __threadfence();
+            if (atomicAdd(&done[lo], 1u) + 1u == uint32_t(R.n_slices)) t_done[R.out_index] = wall_clock64();
+        }
+        wave_step_sync();
+    }
+}
+
+void launch_fused_batch(const BatchReq *reqs, int n_reqs, int64_t n_items, int max_pair_elems, float2 *partial,
+                        uint32_t *done, uint64_t *t_done, hipStream_t st) {
+    if (n_items <= 0) return;
+    const unsigned grid = (unsigned)(n_items < 1048576 ? n_items : 1048576);
+    hipLaunchKernelGGL(fused_batch_kernel, dim3(grid), dim3(64), size_t(max_pair_elems) * sizeof(float2), st, reqs,
+                       n_reqs, n_items, partial, done, t_done);
+}
+
+// One workgroup per request: its slice values summed as the single-request
+// reduction does (aligned 64-slice blocks, fixed butterfly, blocks in order)
+// and added to out[2 r].
+__global__ void __launch_bounds__(64) reduce_batch_kernel(const BatchReq *__restrict__ reqs,
+                                                          const float2 *__restrict__ partial,
+                                                          double *__restrict__ out) {
+    const BatchReq &R = reqs[blockIdx.x];
+    const int lane = threadIdx.x;
+    double acc_re = out[2 * R.out_index], acc_im = out[2 * R.out_index + 1];
+    const uint64_t lo = R.s_begin, hi = R.s_begin + uint64_t(R.n_slices);
+    for (uint64_t b0 = R.s_base; b0 < hi; b0 += 64) {
+        const uint64_t s = b0 + lane;
+        double re = 0.0, im = 0.0;
+        if (s >= lo && s < hi) {
+            const float2 v = partial[R.partial_off + int64_t(s - R.s_base)];
+            re = double(v.x);
+            im = double(v.y);
+        }
+        acc_re += wave_sum(re);
+        acc_im += wave_sum(im);
+    }
+    if (lane == 0) {
+        out[2 * R.out_index] = acc_re;
+        out[2 * R.out_index + 1] = acc_im;
+    }
+}
+
+void launch_reduce_batch(const BatchReq *reqs, int n_reqs, const float2 *partial, double *out, hipStream_t st) {
+    if (n_reqs <= 0) return;
+    hipLaunchKernelGGL(reduce_batch_kernel, dim3(n_reqs), dim3(64), 0, st, reqs, partial, out);
+}
+
+__global__ void stamp_kernel(uint64_t *t) {
+    if (threadIdx.x == 0) t[0] = wall_clock64();
+}
+
+void launch_stamp(uint64_t *t, hipStream_t st) { hipLaunchKernelGGL(stamp_kernel, dim3(1), dim3(64), 0, st, t); }
+
 size_t fused_lds_bytes(int pairs, int pair_elems) { return size_t(pairs) * pair_elems * sizeof(float2); }
 
 void launch_fused_pairs(const FusedParams &p, int pairs, int pair_elems, int zero_slot, hipStream_t st) {
@@ -879,10 +1002,6 @@ void launch_fused_pairs(const FusedParams &p, int pairs, int pair_elems, int zer
 }
 
 // --------------------------------------------------------------- reduce64
-__device__ __forceinline__ double wave_sum(double v) {
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
 
 // One workgroup per bitstring.  Its waves (one, or four when there are many
 // blocks) form the 64-slice block sums (fixed butterfly) of up to 256 blocks

@@ -784,6 +784,217 @@ extern "C" qc_status qc_amplitude(qc_plan *plan, const uint8_t *bitstring, qc_pr
     return st;
 }
 
+// ------------------------------------------------------------------ batches
+namespace qc {
+namespace {
+constexpr int kBatchStreams = 4;
+
+struct BatchLayout {
+    size_t desc_off, bits_off, done_off, partial_off, steps_off, part_bytes, total;
+    std::vector<int> fused;                   // request indices run by the fused batch kernel
+    std::vector<int> stepwise;                // the others
+    std::vector<Exec> exec;                   // per request
+    std::vector<int> want;                    // per request: log2 slices wanted in flight
+    int64_t n_items = 0, partial_elems = 0;
+    int max_pair_elems = 0, bits_stride = 16;
+};
+
+bool batch_layout(const qc_request *reqs, int n, int prec, size_t ws_bytes, BatchLayout &L, std::string &err) {
+    L.exec.assign(n, Exec());
+    L.want.assign(n, 0);
+    L.part_bytes = 0;
+    for (int r = 0; r < n; ++r) {
+        const qc_request &q = reqs[r];
+        const int k = (int)q.plan->sliced.size();
+        const uint64_t range = q.s_end - q.s_begin;
+        L.bits_stride = std::max(L.bits_stride, (q.plan->net.n_qubits + 15) & ~15);
+        const int want = std::min({k, 12, ceil_log2((int64_t)std::max<uint64_t>(range, 1))});
+        Exec x;
+        if (!choose_exec(q.plan, 0, want, prec, 0, x, err)) return false;
+        L.exec[r] = x;
+        L.want[r] = want;
+        if (range == 0) continue;
+        if (x.fused) {
+            L.fused.push_back(r);
+            L.n_items += int64_t(range);
+            const uint64_t base = q.s_begin & ~uint64_t(63);
+            L.partial_elems += int64_t((q.s_end - base + 63) & ~uint64_t(63));
+            L.max_pair_elems = std::max(L.max_pair_elems, pair_elems_of(*x.prog));
+        } else {
+            L.stepwise.push_back(r);
+            L.part_bytes = std::max(L.part_bytes, ws_layout(x, q.plan->net.n_qubits).total);
+        }
+    }
+    const size_t nf = L.fused.size();
+    L.desc_off = 0;
+    L.bits_off = align256(nf * sizeof(BatchReq));
+    L.done_off = L.bits_off + align256(nf * size_t(L.bits_stride));
+    L.partial_off = L.done_off + align256(nf * sizeof(uint32_t));
+    L.steps_off = L.partial_off + align256(size_t(L.partial_elems) * sizeof(float2));
+    const int streams = std::min<int>(kBatchStreams, (int)L.stepwise.size());
+    L.total = L.steps_off + size_t(streams) * align256(L.part_bytes);
+    if (ws_bytes && L.total > ws_bytes) { err = "workspace too small for the batch"; return false; }
+    return true;
+}
+
+std::mutex g_stream_mu;
+std::map<int, std::vector<hipStream_t>> g_streams;
+
+bool batch_streams(int dev, std::vector<hipStream_t> &out, std::string &err) {
+    std::lock_guard<std::mutex> lk(g_stream_mu);
+    auto &v = g_streams[dev];
+    while ((int)v.size() < kBatchStreams) {
+        hipStream_t s = nullptr;
+        QC_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+        v.push_back(s);
+    }
+    out = v;
+    return true;
+}
+}  // namespace
+}  // namespace qc
+
+static qc_status check_requests(const char *fn, const qc_request *reqs, int32_t n, qc_precision prec) {
+    const std::string f(fn);
+    if (!reqs || n < 1 || !valid_prec(prec)) { set_error(f + ": invalid argument"); return QC_ERR_INVALID_ARG; }
+    for (int32_t r = 0; r < n; ++r) {
+        const qc_request &q = reqs[r];
+        if (!q.plan || !q.bitstring) { set_error(f + ": request with NULL plan or bitstring"); return QC_ERR_INVALID_ARG; }
+        const int k = (int)q.plan->sliced.size();
+        const uint64_t n_slices = k >= 64 ? ~uint64_t(0) : (uint64_t(1) << k);
+        if (q.s_begin > q.s_end || q.s_end > n_slices) {
+            set_error(f + ": request slice range out of bounds");
+            return QC_ERR_RANGE;
+        }
+        if (!check_bitstrings(q.plan, q.bitstring, 1)) {
+            set_error(f + ": bitstring entries must be 0 or 1");
+            return QC_ERR_INVALID_ARG;
+        }
+    }
+    return QC_OK;
+}
+
+extern "C" size_t qc_batch_workspace_bytes(const qc_request *reqs, int32_t n, qc_precision prec) {
+    if (check_requests("qc_batch_workspace_bytes", reqs, n, prec) != QC_OK) return 0;
+    qc::BatchLayout L;
+    std::string err;
+    if (!qc::batch_layout(reqs, n, qc::prec_code(prec), 0, L, err)) {
+        set_error("qc_batch_workspace_bytes: " + err);
+        return 0;
+    }
+    return std::max<size_t>(L.total, 256);
+}
+
+extern "C" qc_status qc_contract_batch(const qc_request *reqs, int32_t n, qc_precision prec, void *ws, size_t ws_bytes,
+                                       void *stream, double *out_dev, uint64_t *t_done_dev) {
+    const qc_status cs = check_requests("qc_contract_batch", reqs, n, prec);
+    if (cs != QC_OK) return cs;
+    if (!ws || !out_dev || !t_done_dev) { set_error("qc_contract_batch: NULL argument"); return QC_ERR_INVALID_ARG; }
+    qc::BatchLayout L;
+    std::string err;
+    if (!qc::batch_layout(reqs, n, qc::prec_code(prec), ws_bytes, L, err)) {
+        set_error("qc_contract_batch: " + err);
+        return err.find("workspace") != std::string::npos ? QC_ERR_NOMEM : QC_ERR_UNSUPPORTED;
+    }
+    const hipStream_t st = (hipStream_t)stream;
+    char *w = (char *)ws;
+    auto fail = [&](const std::string &m) {
+        set_error("qc_contract_batch: " + m);
+        return QC_ERR_DEVICE;
+    };
+    // Batch start, and requests with an empty range complete at once.
+    qc::launch_stamp(t_done_dev + n, st);
+    for (int32_t r = 0; r < n; ++r)
+        if (reqs[r].s_begin == reqs[r].s_end) qc::launch_stamp(t_done_dev + r, st);
+    // Stepwise requests: round-robin over internal streams (each with its own
+    // workspace part) that start after the caller's prior work and that the
+    // caller's stream waits for at the end.
+    std::vector<hipStream_t> streams;
+    std::vector<hipEvent_t> events;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return fail("no device");
+    if (!L.stepwise.empty()) {
+        if (!qc::batch_streams(dev, streams, err)) return fail(err);
+        hipEvent_t fork = nullptr;
+        if (hipEventCreateWithFlags(&fork, hipEventDisableTiming) != hipSuccess || hipEventRecord(fork, st) != hipSuccess)
+            return fail("event");
+        const int used = std::min<int>(qc::kBatchStreams, (int)L.stepwise.size());
+        for (int i = 0; i < used; ++i)
+            if (hipStreamWaitEvent(streams[i], fork, 0) != hipSuccess) return fail("stream wait");
+        (void)hipEventDestroy(fork);
+        for (size_t j = 0; j < L.stepwise.size(); ++j) {
+            const int r = L.stepwise[j];
+            const int i = int(j % used);
+            void *part = w + L.steps_off + size_t(i) * qc::align256(L.part_bytes);
+            qc::Exec x;
+            if (!qc::choose_exec(reqs[r].plan, 0, L.want[r], qc::prec_code(prec), L.part_bytes, x, err)) return fail(err);
+            if (!qc::enqueue(reqs[r].plan, x, reqs[r].s_begin, reqs[r].s_end, reqs[r].bitstring, false, 1, part,
+                             streams[i], out_dev + 2 * r, nullptr, err))
+                return fail(err);
+            qc::launch_stamp(t_done_dev + r, streams[i]);
+        }
+        for (int i = 0; i < used; ++i) {
+            hipEvent_t join = nullptr;
+            if (hipEventCreateWithFlags(&join, hipEventDisableTiming) != hipSuccess ||
+                hipEventRecord(join, streams[i]) != hipSuccess || hipStreamWaitEvent(st, join, 0) != hipSuccess)
+                return fail("event");
+            events.push_back(join);
+        }
+    }
+    // Fused requests: one launch over every (request, slice) pair.
+    if (!L.fused.empty()) {
+        std::vector<qc::BatchReq> desc(L.fused.size());
+        std::vector<uint8_t> bits(L.fused.size() * size_t(L.bits_stride), 0);
+        int64_t item = 0, poff = 0;
+        for (size_t j = 0; j < L.fused.size(); ++j) {
+            const int r = L.fused[j];
+            const qc_request &q = reqs[r];
+            qc::Program &prog = *L.exec[r].prog;
+            {
+                std::lock_guard<std::mutex> lk(q.plan->dev_mu);
+                if (!qc::ensure_device(q.plan, prog, true, err)) return fail(err);
+            }
+            std::memcpy(bits.data() + j * L.bits_stride, q.bitstring, q.plan->net.n_qubits);
+            qc::BatchReq &d = desc[j];
+            std::memset(&d, 0, sizeof(d));
+            d.level_start = (const int32_t *)prog.d_fused_levels;
+            d.items = (const int4 *)prog.d_fused_items;
+            d.pool = (const int32_t *)prog.d_fused_pool;
+            d.image = (const float2 *)prog.d_fused_image;
+            d.elems = (const int4 *)prog.d_fused_elems;
+            d.base = (const double2 *)prog.d_base;
+            d.bits = (const uint8_t *)(w + L.bits_off) + j * L.bits_stride;
+            d.n_levels = prog.n_levels;
+            d.n_image = prog.n_image;
+            d.n_elems = prog.n_leaf_elems;
+            d.root_off = (int32_t)prog.lds_offset[prog.root_pre];
+            d.zero_slot = qc::zero_slot_of(prog);
+            d.out_index = r;
+            d.s_begin = q.s_begin;
+            d.s_base = q.s_begin & ~uint64_t(63);
+            d.n_slices = int64_t(q.s_end - q.s_begin);
+            d.item_off = item;
+            d.partial_off = poff;
+            item += d.n_slices;
+            poff += int64_t((q.s_end - d.s_base + 63) & ~uint64_t(63));
+        }
+        if (hipMemcpyAsync(w + L.desc_off, desc.data(), desc.size() * sizeof(qc::BatchReq), hipMemcpyHostToDevice, st) !=
+                hipSuccess ||
+            hipMemcpyAsync(w + L.bits_off, bits.data(), bits.size(), hipMemcpyHostToDevice, st) != hipSuccess)
+            return fail("copy");
+        uint32_t *done = (uint32_t *)(w + L.done_off);
+        float2 *partial = (float2 *)(w + L.partial_off);
+        qc::launch_zero_u32(done, (int64_t)L.fused.size(), st);
+        qc::launch_fused_batch((const qc::BatchReq *)(w + L.desc_off), (int)L.fused.size(), L.n_items,
+                               L.max_pair_elems, partial, done, t_done_dev, st);
+        qc::launch_reduce_batch((const qc::BatchReq *)(w + L.desc_off), (int)L.fused.size(), partial, out_dev, st);
+    }
+    for (hipEvent_t e : events) (void)hipEventDestroy(e);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(hipGetErrorString(e));
+    return QC_OK;
+}
+
 extern "C" qc_status qc_plan_set_graphs(qc_plan *plan, int32_t on) {
     if (!plan) { set_error("qc_plan_set_graphs: NULL plan"); return QC_ERR_INVALID_ARG; }
     std::lock_guard<std::mutex> lk(plan->dev_mu);

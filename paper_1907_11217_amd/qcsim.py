@@ -29,7 +29,7 @@ EXPORTED = (
     "qc_plan_describe", "qc_workspace_bytes", "qc_contract_slices", "qc_amplitude",
     "qc_gate_matrix", "qc_plan_destroy", "qc_last_error", "qc_kernel_gemm", "qc_kernel_transpose",
     "qc_plan_set_exec", "qc_profile_enable", "qc_profile_read", "qc_contract_slices_dev", "qc_plan_set_graphs",
-    "qc_tune", "qc_kernel_gemm_form",
+    "qc_tune", "qc_kernel_gemm_form", "qc_batch_workspace_bytes", "qc_contract_batch",
 )
 EXEC_MODES = {"auto": 0, "fused": 1, "stepwise": 2}
 
@@ -48,6 +48,11 @@ class qc_gate(ctypes.Structure):
 class qc_circuit(ctypes.Structure):
     _fields_ = [("n_qubits", ctypes.c_int32), ("n_gates", ctypes.c_int32),
                 ("gates", ctypes.POINTER(qc_gate))]
+
+
+class qc_request(ctypes.Structure):
+    _fields_ = [("plan", ctypes.c_void_p), ("bitstring", ctypes.POINTER(ctypes.c_uint8)),
+                ("s_begin", ctypes.c_uint64), ("s_end", ctypes.c_uint64)]
 
 
 class qc_slice_spec(ctypes.Structure):
@@ -121,6 +126,11 @@ def load(path: str | None = None):
         lib.qc_tune.argtypes = [vp, i64, ctypes.c_int32, ctypes.c_int, vp, ctypes.c_size_t, vp, ctypes.c_char_p,
                                 ctypes.POINTER(ctypes.c_int32)]
         lib.qc_tune.restype = ctypes.c_int
+        lib.qc_batch_workspace_bytes.argtypes = [ctypes.POINTER(qc_request), ctypes.c_int32, ctypes.c_int]
+        lib.qc_batch_workspace_bytes.restype = ctypes.c_size_t
+        lib.qc_contract_batch.argtypes = [ctypes.POINTER(qc_request), ctypes.c_int32, ctypes.c_int, vp, ctypes.c_size_t,
+                                          vp, vp, vp]
+        lib.qc_contract_batch.restype = ctypes.c_int
         lib.qc_plan_set_graphs.argtypes = [vp, ctypes.c_int32]
         lib.qc_plan_set_graphs.restype = ctypes.c_int
         lib.qc_profile_enable.argtypes = [vp, ctypes.c_int32]
@@ -236,6 +246,41 @@ def qc_tune(plan: Plan, chunk_slices: int, n_bs: int, prec, ws, cache_path=None,
                              ws.numel() * ws.element_size(), st.cuda_stream,
                              None if cache_path is None else str(cache_path).encode(), ctypes.byref(n)), plan._lib)
     return n.value
+
+
+class Batch:
+    """A request array for qc_contract_batch: (plan, bitstring, s_begin, s_end)
+    tuples; keeps the plans and bitstrings alive."""
+
+    def __init__(self, requests):
+        self.plans = [r[0] for r in requests]
+        self.bits = [np.ascontiguousarray(np.asarray(r[1], dtype=np.uint8)) for r in requests]
+        self.array = (qc_request * len(requests))()
+        for i, (p, b, r) in enumerate(zip(self.plans, self.bits, requests)):
+            s0 = r[2] if len(r) > 2 else 0
+            s1 = r[3] if len(r) > 3 else (1 << qc_plan_info(p)["log2_slices"])
+            self.array[i] = qc_request(p.handle, b.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), s0, s1)
+        self.lib = self.plans[0]._lib
+
+    def __len__(self):
+        return len(self.plans)
+
+
+def qc_batch_workspace_bytes(batch: Batch, prec="c64") -> int:
+    n = int(batch.lib.qc_batch_workspace_bytes(batch.array, len(batch), _prec(prec)))
+    if n == 0:
+        raise QcError(1, batch.lib.qc_last_error().decode())
+    return n
+
+
+def qc_contract_batch(batch: Batch, prec, ws, out_dev, t_done_dev, stream=None):
+    """Enqueues every request; out_dev float64 [n, 2] (accumulated into),
+    t_done_dev int64 [n + 1] (completion wall-clock stamps, then the start)."""
+    import torch
+    st = stream if stream is not None else torch.cuda.current_stream()
+    _check(batch.lib.qc_contract_batch(batch.array, len(batch), _prec(prec), ws.data_ptr(),
+                                       ws.numel() * ws.element_size(), st.cuda_stream, out_dev.data_ptr(),
+                                       t_done_dev.data_ptr()), batch.lib)
 
 
 def qc_plan_set_graphs(plan: Plan, on: bool = True) -> None:
