@@ -80,6 +80,78 @@ def _events_ms(stream, fn, reps):
     return e0.elapsed_time(e1) / reps
 
 
+def batch_leg(n_req=256, seed=501, cap=24, reps=3, n_oracle=6, trials=32, precs=("c64", "split_fp16")):
+    """Uneven batch of requests (4x4 d12, 5x5 d16, 6x6 d20, 7x7 d24 drawn
+    uniformly), each with its own plan (the smallest slice count meeting a
+    2^cap-entry cap) and bitstring, in one qc_contract_batch call per step."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1907_11217_amd import qcsim
+
+    reqs = synth.request_mix(n_req, seed)
+    t0 = time.perf_counter()
+    items, ks = [], []
+    for r in reqs:
+        lat = r["lattice"]
+        plan = qcsim.qc_plan_build(lat.n, r["circuit"], r["bitstring"], log2_slices=-1, log2_max_entries=cap,
+                                   greedy_trials=trials, seed=1)
+        ks.append(qcsim.qc_plan_info(plan)["log2_slices"])
+        items.append((plan, r["bitstring"]))
+    plan_s = time.perf_counter() - t0
+    batch = qcsim.Batch(items)
+    stream = torch.cuda.current_stream()
+    khz = qcsim.qc_wall_clock_khz()
+    leg = {"workload": (f"{n_req} requests drawn uniformly from 4x4 d12 / 5x5 d16 / 6x6 d20 / 7x7 d24 "
+                        f"(seed {seed}), one bitstring each, plans capped at 2^{cap} entries"),
+           "plan_seconds": plan_s, "per_prec": {}}
+    fam_of = ["%dx%d_d%d" % r["family"] for r in reqs]
+    leg["families"] = {f: {"count": fam_of.count(f), "k": sorted({k for g, k in zip(fam_of, ks) if g == f})}
+                       for f in sorted(set(fam_of))}
+    ref = None
+    for prec in precs:
+        ws = torch.empty(qcsim.qc_batch_workspace_bytes(batch, prec), dtype=torch.uint8, device="cuda")
+        out = torch.zeros(n_req, 2, dtype=torch.float64, device="cuda")
+        tdone = torch.zeros(n_req + 1, dtype=torch.int64, device="cuda")
+        qcsim.qc_contract_batch(batch, prec, ws, out, tdone, stream=stream)  # first call: graphs
+        torch.cuda.synchronize()
+        o = out.cpu().numpy().copy()
+        amps = o[:, 0] + 1j * o[:, 1]
+
+        def step():
+            qcsim.qc_contract_batch(batch, prec, ws, out, tdone, stream=stream)
+
+        ms = _events_ms(stream, step, reps)
+        step()
+        torch.cuda.synchronize()
+        t = tdone.cpu().numpy()
+        done_ms = (t[:-1] - t[-1]) / khz
+        r = {"ms_per_batch": ms, "amplitudes_per_s": n_req / (ms * 1e-3),
+             "completion_ms": {"p50": float(np.percentile(done_ms, 50)), "p99": float(np.percentile(done_ms, 99)),
+                               "max": float(done_ms.max())},
+             "family_max_completion_ms": {f: float(max(d for g, d in zip(fam_of, done_ms) if g == f))
+                                          for f in sorted(set(fam_of))}}
+        if ref is None:
+            ref = amps
+            import oracle
+            errs = []
+            for i, q in enumerate(reqs):
+                if len(errs) >= n_oracle:
+                    break
+                if q["family"][0] <= 5:
+                    a = oracle.amplitudes_sv(q["lattice"].n, q["circuit"], [q["bitstring"]])[0]
+                    errs.append(abs(amps[i] - a) / abs(a))
+            r["oracle_rel_err_small_requests"] = {"n": len(errs), "max": float(max(errs))}
+        else:
+            n_q = np.array([q["lattice"].n for q in reqs], dtype=float)
+            gate = np.exp2(n_q) * np.abs(ref) ** 2 >= 1e-2
+            r["max_rel_diff_vs_c64"] = float((np.abs(amps - ref)[gate] / np.abs(ref[gate])).max())
+        leg["per_prec"][prec] = r
+        del ws
+    return leg
+
+
 def first_nonzero_slice(key, candidates):
     """The first candidate slice of the 70-qubit plan whose value is not exactly
     zero (found with one split-BF16 contraction each)."""
@@ -105,7 +177,7 @@ def first_nonzero_slice(key, candidates):
     return tried[-1], tried
 
 
-def big_leg(key, precs, reps, s_range, oracle_slices=()):
+def big_leg(key, precs, reps, s_range, oracle_slices=(), tune=False):
     """One large configuration on the stepwise path: every precision runs the
     same slice range for one bitstring; reports time, algorithmic TFLOP/s,
     the GEMM kernels' achieved MFMA rate against their dtype's peak, and the
@@ -146,6 +218,13 @@ def big_leg(key, precs, reps, s_range, oracle_slices=()):
         def step():
             qcsim.qc_contract_slices(plan, s0, s1, x, prec, ws, out, stream=stream)
 
+        tune_s = None
+        if tune:
+            # Untimed preparation, like the plan build.
+            t1 = time.perf_counter()
+            qcsim.qc_tune(plan, n_sl, 1, prec, ws, stream=stream)
+            tune_s = time.perf_counter() - t1
+
         out.zero_()
         qcsim.qc_contract_slices(plan, s0, s1, x, prec, ws, out, ps, stream=stream)
         torch.cuda.synchronize()
@@ -166,6 +245,7 @@ def big_leg(key, precs, reps, s_range, oracle_slices=()):
                 per_kind[f] = per_kind.get(f, 0.0) + 8.0 * op["nb"] * op["m"] * op["n"] * op["k"] * chunks
         flops = sum(per_kind.values())
         r = {"ms_per_step": ms, "value": val.real, "value_im": val.imag, "tflops": flops / (ms * 1e-3) / 1e12,
+             "tune_seconds": tune_s,
              "kernels": {kk: {"launches": v[0], "ms": v[1]} for kk, v in prof.items()}}
         mf = "gemm_mfma" if prec == "c64" else f"gemm_{prec}"
         if mf in prof and mf in per_kind:
@@ -360,7 +440,7 @@ def main():
     if not args.no_large:
         precs = ["c64", "split_fp16", "split_bf16"]
         # 7x7 depth 24: every slice of one amplitude per step.
-        result["grid7x7_d24"] = big_leg("c3", precs, 5, lambda k: (0, 1 << k), oracle_slices=(0,))
+        result["grid7x7_d24"] = big_leg("c3", precs, 5, lambda k: (0, 1 << k), oracle_slices=(0,), tune=True)
         # 70 qubits depth 32: one slice per step; the amplitude is projected
         # as slice time x 2^k.  Many slices of this plan are exactly zero (a
         # leaf or an intermediate vanishes for their sliced values); the
@@ -369,6 +449,7 @@ def main():
         s4, tried = first_nonzero_slice("c4", lambda k: [(1 << k) - 1 - j for j in range(16)])
         result["diamond70_d32"] = big_leg("c4", precs, 2, lambda k: (s4, s4 + 1))
         result["diamond70_d32"]["zero_slices_skipped"] = len(tried) - 1
+        result["request_batch"] = batch_leg()
 
     if not args.no_cpu_baseline:
         import oracle

@@ -249,8 +249,8 @@ qc_status qc_amplitude(qc_plan *plan, const uint8_t *bitstring, qc_precision pre
  * range, in one call (asynchronous on `stream`).  Requests whose plan runs
  * fused (complex FP32, the program fits in LDS) share one launch whose
  * wavefronts take (request, slice) pairs in turn; the others run stepwise on
- * four internal streams that start after the caller's earlier work and that
- * the caller's stream waits for.  Per request r: out_dev[2 r .. 2 r + 1] +=
+ * eight internal streams (default priority) that start after the caller's
+ * earlier work and that the caller's stream waits for.  Per request r: out_dev[2 r .. 2 r + 1] +=
  * its sum over slices [s_begin, s_end) (same fixed-order FP64 sum as
  * qc_contract_slices); t_done_dev[r] = device wall-clock time (see
  * hipDeviceAttributeWallClockRate) at which its last slice value was
@@ -262,6 +262,8 @@ typedef struct {
     uint64_t s_begin, s_end;     /* slice range of this request */
 } qc_request;
 size_t qc_batch_workspace_bytes(const qc_request *reqs, int32_t n, qc_precision prec);
+/* Rate of the device wall clock used by the completion stamps (kHz). */
+qc_status qc_wall_clock_khz(int32_t *khz);
 qc_status qc_contract_batch(const qc_request *reqs, int32_t n, qc_precision prec, void *ws, size_t ws_bytes,
                             void *stream, double *out_dev, uint64_t *t_done_dev);
 

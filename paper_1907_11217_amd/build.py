@@ -18,7 +18,7 @@ INCLUDES = ["-I" + os.path.join(ROOT, "include"), "-I" + CSRC]
 HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
              # No packed FP32 instructions in device code.
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
-HOST_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-Wall", "-Wno-sign-compare"]
+HOST_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-pthread", "-Wall", "-Wno-sign-compare"]
 
 
 def _run(cmd):
@@ -41,7 +41,7 @@ def build(verbose: bool = False) -> str:
         _run(["hipcc", *HIP_FLAGS, *INCLUDES, "-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
     tmp = OUT + ".tmp"
-    _run(["hipcc", "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp])
+    _run(["hipcc", "-shared", "-fPIC", "-pthread", f"--offload-arch={ARCH}", *objs, "-o", tmp])
     os.replace(tmp, OUT)
     if verbose:
         print("built", OUT)

@@ -8,8 +8,10 @@
 // at a time, the index whose removal most reduces the largest intermediate
 // and, as a tie-break, the flops of one slice.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <queue>
+#include <thread>
 
 #include "plan.h"
 
@@ -370,6 +372,26 @@ static void fold_invariant_subtrees(qc_plan *plan, const std::vector<char> &dyn_
     plan->tree = std::move(tree);
 }
 
+// Runs f(0..n-1) on up to 16 host threads.  Each trial writes only its own
+// result slot and the caller scans the slots in index order, so the plan does
+// not depend on the thread count or scheduling.
+template <class F>
+static void parallel_trials(int n, F f) {
+    const int hw = (int)std::thread::hardware_concurrency();
+    const int nt = std::max(1, std::min({n, hw > 0 ? hw : 1, 16}));
+    if (nt == 1) {
+        for (int t = 0; t < n; ++t) f(t);
+        return;
+    }
+    std::atomic<int> next(0);
+    std::vector<std::thread> pool;
+    for (int w = 0; w < nt; ++w)
+        pool.emplace_back([&]() {
+            for (int t = next++; t < n; t = next++) f(t);
+        });
+    for (auto &th : pool) th.join();
+}
+
 bool search_plan(qc_plan *plan, const qc_slice_spec *spec, std::string &err) {
     const OrderProblem &p = plan->prob;
     const int k_target = spec ? spec->log2_slices : 0;
@@ -401,19 +423,29 @@ bool search_plan(qc_plan *plan, const qc_slice_spec *spec, std::string &err) {
     double last_ach = 0;
     std::vector<char> none(p.n_index, 0);
     for (int e : explicit_s) none[e] = 1;
-    for (int t = 0; t < trials; ++t) {
-        std::vector<Merge> tree = greedy_order(p, none, seed + 0x1000 * t, t == 0 ? 0.0 : 0.1 + 0.05 * (t % 8));
-        std::vector<int> sl = explicit_s;
-        double ach = 0;
-        const bool ok = choose_slices(p, tree, kt, cap, sl, sliceable, ach);
-        last_ach = std::min(last_ach == 0 ? ach : last_ach, ach);
-        if (!ok) { best_ach = std::min(best_ach, ach); continue; }
-        std::vector<char> rm(p.n_index, 0);
-        for (int e : sl) rm[e] = 1;
-        const TreeCost c = tree_cost(p, tree, rm);
-        const double total = c.flops * std::ldexp(1.0, (int)sl.size());
-        if (!have || sl.size() < best_sliced.size() || (sl.size() == best_sliced.size() && total < best_total)) {
-            have = true; best_total = total; best_tree = tree; best_sliced = sl;
+    struct Trial {
+        std::vector<Merge> tree;
+        std::vector<int> sl;
+        double ach = 0, total = 0;
+        bool ok = false;
+    };
+    std::vector<Trial> tr(trials);
+    parallel_trials(trials, [&](int t) {
+        Trial &r = tr[t];
+        r.tree = greedy_order(p, none, seed + 0x1000 * t, t == 0 ? 0.0 : 0.1 + 0.05 * (t % 8));
+        r.sl = explicit_s;
+        r.ok = choose_slices(p, r.tree, kt, cap, r.sl, sliceable, r.ach);
+        if (r.ok) {
+            std::vector<char> rm(p.n_index, 0);
+            for (int e : r.sl) rm[e] = 1;
+            r.total = tree_cost(p, r.tree, rm).flops * std::ldexp(1.0, (int)r.sl.size());
+        }
+    });
+    for (Trial &r : tr) {
+        last_ach = std::min(last_ach == 0 ? r.ach : last_ach, r.ach);
+        if (!r.ok) { best_ach = std::min(best_ach, r.ach); continue; }
+        if (!have || r.sl.size() < best_sliced.size() || (r.sl.size() == best_sliced.size() && r.total < best_total)) {
+            have = true; best_total = r.total; best_tree = r.tree; best_sliced = r.sl;
         }
     }
     if (!have) {
@@ -432,11 +464,13 @@ bool search_plan(qc_plan *plan, const qc_slice_spec *spec, std::string &err) {
     std::vector<char> rm(p.n_index, 0);
     for (int e : best_sliced) rm[e] = 1;
     TreeCost bc = tree_cost(p, best_tree, rm);
-    for (int t = 0; t < trials; ++t) {
-        std::vector<Merge> tree = greedy_order(p, rm, seed + 0x9000 + 0x1000 * t, t == 0 ? 0.0 : 0.1 + 0.05 * (t % 8));
-        const TreeCost c = tree_cost(p, tree, rm);
-        if ((cap <= 0 || c.max_log2 <= cap) && c.flops < bc.flops) { bc = c; best_tree = tree; }
-    }
+    std::vector<std::pair<std::vector<Merge>, TreeCost>> re(trials);
+    parallel_trials(trials, [&](int t) {
+        re[t].first = greedy_order(p, rm, seed + 0x9000 + 0x1000 * t, t == 0 ? 0.0 : 0.1 + 0.05 * (t % 8));
+        re[t].second = tree_cost(p, re[t].first, rm);
+    });
+    for (auto &r : re)
+        if ((cap <= 0 || r.second.max_log2 <= cap) && r.second.flops < bc.flops) { bc = r.second; best_tree = r.first; }
     const TreeCost c0 = tree_cost(p, best_tree, std::vector<char>(p.n_index, 0));
     plan->info.flops_unsliced = c0.flops;
 
@@ -451,14 +485,15 @@ bool search_plan(qc_plan *plan, const qc_slice_spec *spec, std::string &err) {
     }
     double best_dev = per_pair_flops(p, best_tree, rm, dyn_leaf);
     const int const_cap = std::max(4, (int)bc.max_log2);
-    for (int t = 0; t < trials; ++t) {
-        std::vector<Merge> tree = greedy_order_phased(p, rm, seed + 0x5000 + 0x1000 * t,
-                                                      t == 0 ? 0.0 : 0.1 + 0.05 * (t % 8), &dyn_leaf, const_cap);
-        const TreeCost c = tree_cost(p, tree, rm);
-        if (cap > 0 && c.max_log2 > cap) continue;
-        const double dev = per_pair_flops(p, tree, rm, dyn_leaf);
-        if (dev < best_dev) { best_dev = dev; best_tree = tree; }
-    }
+    std::vector<std::pair<std::vector<Merge>, double>> ph(trials);
+    parallel_trials(trials, [&](int t) {
+        ph[t].first = greedy_order_phased(p, rm, seed + 0x5000 + 0x1000 * t, t == 0 ? 0.0 : 0.1 + 0.05 * (t % 8),
+                                          &dyn_leaf, const_cap);
+        const TreeCost c = tree_cost(p, ph[t].first, rm);
+        ph[t].second = (cap > 0 && c.max_log2 > cap) ? -1.0 : per_pair_flops(p, ph[t].first, rm, dyn_leaf);
+    });
+    for (auto &r : ph)
+        if (r.second >= 0 && r.second < best_dev) { best_dev = r.second; best_tree = r.first; }
     plan->tree = best_tree;
     plan->sliced = best_sliced;
     fold_invariant_subtrees(plan, dyn_leaf);

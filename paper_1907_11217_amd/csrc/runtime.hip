@@ -787,7 +787,7 @@ extern "C" qc_status qc_amplitude(qc_plan *plan, const uint8_t *bitstring, qc_pr
 // ------------------------------------------------------------------ batches
 namespace qc {
 namespace {
-constexpr int kBatchStreams = 4;
+constexpr int kBatchStreams = 8;
 
 struct BatchLayout {
     size_t desc_off, bits_off, done_off, partial_off, steps_off, part_bytes, total;
@@ -933,13 +933,6 @@ extern "C" qc_status qc_contract_batch(const qc_request *reqs, int32_t n, qc_pre
                 return fail(err);
             qc::launch_stamp(t_done_dev + r, streams[i]);
         }
-        for (int i = 0; i < used; ++i) {
-            hipEvent_t join = nullptr;
-            if (hipEventCreateWithFlags(&join, hipEventDisableTiming) != hipSuccess ||
-                hipEventRecord(join, streams[i]) != hipSuccess || hipStreamWaitEvent(st, join, 0) != hipSuccess)
-                return fail("event");
-            events.push_back(join);
-        }
     }
     // Fused requests: one launch over every (request, slice) pair.
     if (!L.fused.empty()) {
@@ -989,9 +982,29 @@ extern "C" qc_status qc_contract_batch(const qc_request *reqs, int32_t n, qc_pre
                                L.max_pair_elems, partial, done, t_done_dev, st);
         qc::launch_reduce_batch((const qc::BatchReq *)(w + L.desc_off), (int)L.fused.size(), partial, out_dev, st);
     }
+    // The caller's stream waits for the internal streams (after its own
+    // fused work, which thus overlaps them).
+    const int used = std::min<int>(qc::kBatchStreams, (int)L.stepwise.size());
+    for (int i = 0; i < used; ++i) {
+        hipEvent_t join = nullptr;
+        if (hipEventCreateWithFlags(&join, hipEventDisableTiming) != hipSuccess ||
+            hipEventRecord(join, streams[i]) != hipSuccess || hipStreamWaitEvent(st, join, 0) != hipSuccess)
+            return fail("event");
+        events.push_back(join);
+    }
     for (hipEvent_t e : events) (void)hipEventDestroy(e);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(hipGetErrorString(e));
+    return QC_OK;
+}
+
+extern "C" qc_status qc_wall_clock_khz(int32_t *khz) {
+    int dev = 0;
+    if (!khz) { set_error("qc_wall_clock_khz: NULL argument"); return QC_ERR_INVALID_ARG; }
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess) {
+        set_error("qc_wall_clock_khz: device query failed");
+        return QC_ERR_DEVICE;
+    }
     return QC_OK;
 }
 

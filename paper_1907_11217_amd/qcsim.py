@@ -29,7 +29,7 @@ EXPORTED = (
     "qc_plan_describe", "qc_workspace_bytes", "qc_contract_slices", "qc_amplitude",
     "qc_gate_matrix", "qc_plan_destroy", "qc_last_error", "qc_kernel_gemm", "qc_kernel_transpose",
     "qc_plan_set_exec", "qc_profile_enable", "qc_profile_read", "qc_contract_slices_dev", "qc_plan_set_graphs",
-    "qc_tune", "qc_kernel_gemm_form", "qc_batch_workspace_bytes", "qc_contract_batch",
+    "qc_tune", "qc_kernel_gemm_form", "qc_batch_workspace_bytes", "qc_contract_batch", "qc_wall_clock_khz",
 )
 EXEC_MODES = {"auto": 0, "fused": 1, "stepwise": 2}
 
@@ -131,6 +131,8 @@ def load(path: str | None = None):
         lib.qc_contract_batch.argtypes = [ctypes.POINTER(qc_request), ctypes.c_int32, ctypes.c_int, vp, ctypes.c_size_t,
                                           vp, vp, vp]
         lib.qc_contract_batch.restype = ctypes.c_int
+        lib.qc_wall_clock_khz.argtypes = [ctypes.POINTER(ctypes.c_int32)]
+        lib.qc_wall_clock_khz.restype = ctypes.c_int
         lib.qc_plan_set_graphs.argtypes = [vp, ctypes.c_int32]
         lib.qc_plan_set_graphs.restype = ctypes.c_int
         lib.qc_profile_enable.argtypes = [vp, ctypes.c_int32]
@@ -281,6 +283,13 @@ def qc_contract_batch(batch: Batch, prec, ws, out_dev, t_done_dev, stream=None):
     _check(batch.lib.qc_contract_batch(batch.array, len(batch), _prec(prec), ws.data_ptr(),
                                        ws.numel() * ws.element_size(), st.cuda_stream, out_dev.data_ptr(),
                                        t_done_dev.data_ptr()), batch.lib)
+
+
+def qc_wall_clock_khz() -> int:
+    lib = load()
+    k = ctypes.c_int32(0)
+    _check(lib.qc_wall_clock_khz(ctypes.byref(k)), lib)
+    return k.value
 
 
 def qc_plan_set_graphs(plan: Plan, on: bool = True) -> None:
