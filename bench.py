@@ -287,13 +287,40 @@ def main():
     ap.add_argument("--exec", default="auto", choices=["auto", "fused", "stepwise"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-large", action="store_true",
-                    help="skip the 7x7 depth-24 and 70-qubit depth-32 reports")
+                    help="skip the 7x7 depth-24, 70-qubit depth-32 and request-batch reports")
+    ap.add_argument("--leg", choices=["grid7x7_d24", "diamond70_d32", "request_batch"],
+                    help="run only this report and print its JSON (for profiling runs)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only copy 256 MiB device to device 5 times (the plain-copy reference of the "
+                         "FETCH_SIZE / WRITE_SIZE counter runs)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}); "
               "the slice ranges of a multi-GPU run would be independent per GPU, see DESIGN.md", file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration:
+        import torch
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_per_launch": src.numel() * 4}), flush=True)
+        return
+    if args.leg:
+        import torch
+        torch.cuda.set_device(0)
+        precs = ["c64", "split_fp16", "split_bf16"]
+        if args.leg == "grid7x7_d24":
+            leg = big_leg("c3", precs, 5, lambda k: (0, 1 << k), oracle_slices=(), tune=True)
+        elif args.leg == "diamond70_d32":
+            s4, _ = first_nonzero_slice("c4", lambda k: [(1 << k) - 1 - j for j in range(16)])
+            leg = big_leg("c4", precs, 2, lambda k: (s4, s4 + 1))
+        else:
+            leg = batch_leg()
+        print(json.dumps(leg), flush=True)
+        return
 
     import numpy as np
     import torch
