@@ -45,7 +45,8 @@ qc_status qc_kernel_gemm(const void *A, const void *B, void *C, int64_t nb, int6
  *   2 dot (k >= 256, nb m n <= 65536), 3..6 complex FP32 MFMA with block
  *   tiles 32x32, 32x64, 64x32, 64x64 (QC_C64; k in {2,4,8} or a multiple of
  *   16), 7 split 128x128, 8..11 split 32x32, 32x64, 64x32, 64x64 (split
- *   precisions, k >= 2); form -1 is the default choice.  Forms 0..2 compute
+ *   precisions, k >= 2), 12 complex FP32 MFMA 128x128 (QC_C64, k >= 2, m and n
+ *   multiples of 128); form -1 is the default choice.  Forms 0..2 compute
  *   in FP32 for every precision.  QC_ERR_UNSUPPORTED if the form does not
  *   apply to the shape and precision. */
 qc_status qc_kernel_gemm_form(const void *A, const void *B, void *C, int64_t nb, int64_t m, int64_t n, int64_t k,

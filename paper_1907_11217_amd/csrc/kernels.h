@@ -164,11 +164,11 @@ void launch_transpose(const TransposeDesc &d, hipStream_t st);
 const char *launch_gemm(const GemmDesc &d, hipStream_t st);  // returns the form launched
 
 // GEMM kernel forms (tuning choices).  Mfma/Split WM WN: complex FP32 or
-// split 16-bit MFMA with a (32 WM) x (32 WN) block tile; SplitBig: the
-// 128 x 128 split tile; Skinny: m <= 16; Dot: few outputs, long k; Valu: any.
+// split 16-bit MFMA with a (32 WM) x (32 WN) block tile; SplitBig, MfmaBig:
+// the 128 x 128 tiles; Skinny: m <= 16; Dot: few outputs, long k; Valu: any.
 enum GemmVariant {
     kVarValu = 0, kVarSkinny, kVarDot, kVarMfma11, kVarMfma12, kVarMfma21, kVarMfma22,
-    kVarSplitBig, kVarSplit11, kVarSplit12, kVarSplit21, kVarSplit22, kVarCount
+    kVarSplitBig, kVarSplit11, kVarSplit12, kVarSplit21, kVarSplit22, kVarMfmaBig, kVarCount
 };
 bool gemm_variant_ok(const GemmDesc &d, int v);
 int gemm_default_variant(const GemmDesc &d);

@@ -617,6 +617,103 @@ __global__ void __launch_bounds__(256) gemm_split_big_kernel(GemmDesc d) {
     if (d.amax_c) block_amax(mx, d.amax_c);
 }
 
+// Large-tile complex FP32 form for m, n multiples of 128: the split form's
+// block structure (128x128 tile, four waves of 64x64, K slabs of 16 double
+// buffered in LDS, next slab prefetched in registers, XCD-contiguous tile
+// order) with FP32 operands stored [k][row] as (re, im) pairs, so one
+// 8-byte LDS read gives a lane both parts of its v_mfma_f32_32x32x2_f32
+// operand.  4M form: Cr += Ar Br - Ai Bi, Ci += Ar Bi + Ai Br.
+__device__ __forceinline__ void store8_kmajor(float2 (*plane)[128], int row, int half, const float2 (&v)[8]) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) plane[8 * half + q][row] = v[q];
+}
+
+__global__ void __launch_bounds__(256) gemm_mfma_big_kernel(GemmDesc d) {
+    constexpr int TM = 128, TN = 128, KT = 16;
+    __shared__ __attribute__((aligned(16))) float2 As[2][KT][TM];
+    __shared__ __attribute__((aligned(16))) float2 Bs[2][KT][TN];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int64_t tiles_m = d.m / TM, tiles_n = d.n / TN;
+    const int64_t n_tiles = d.nb * tiles_m * tiles_n;
+    const bool a_kc = d.sAk == 1, b_kc = d.sBk == 1;
+    const int ar = a_kc ? (t >> 1) : (t & 127), ah = a_kc ? (t & 1) : (t >> 7);
+    const int br = b_kc ? (t >> 1) : (t & 127), bh = b_kc ? (t & 1) : (t >> 7);
+    const bool a_vec = a_kc && d.sAm % 2 == 0 && d.sAb % 2 == 0 && (uintptr_t)d.A % 16 == 0;
+    const bool b_vec = b_kc && d.sBn % 2 == 0 && d.sBb % 2 == 0 && (uintptr_t)d.B % 16 == 0;
+    const int n_slabs = int((d.k + KT - 1) / KT);
+    int64_t first = blockIdx.x;
+    if (gridDim.x % 8 == 0) first = int64_t(blockIdx.x % 8) * (gridDim.x / 8) + blockIdx.x / 8;
+    for (int64_t tile = first; tile < n_tiles; tile += gridDim.x) {
+        const int64_t tn = tile % tiles_n;
+        const int64_t tm = (tile / tiles_n) % tiles_m;
+        const int64_t bi = tile / (tiles_n * tiles_m);
+        const float2 *Ab = d.A + bi * d.sAb + tm * TM * d.sAm;
+        const float2 *Bb = d.B + bi * d.sBb + tn * TN * d.sBn;
+        floatx16 acc[2][2][2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int v = 0; v < 16; ++v) { acc[i][j][0][v] = 0.f; acc[i][j][1][v] = 0.f; }
+        float2 ra[8], rb[8];
+        load8(ra, Ab, d.sAm, d.sAk, a_vec, ar, 8 * ah, d.k);
+        load8(rb, Bb, d.sBn, d.sBk, b_vec, br, 8 * bh, d.k);
+        store8_kmajor(As[0], ar, ah, ra);
+        store8_kmajor(Bs[0], br, bh, rb);
+        __syncthreads();
+        for (int s = 0; s < n_slabs; ++s) {
+            const int buf = s & 1;
+            const bool more = s + 1 < n_slabs;
+            if (more) {
+                const int64_t k1 = int64_t(s + 1) * KT;
+                load8(ra, Ab, d.sAm, d.sAk, a_vec, ar, k1 + 8 * ah, d.k);
+                load8(rb, Bb, d.sBn, d.sBk, b_vec, br, k1 + 8 * bh, d.k);
+            }
+#pragma unroll
+            for (int kk = 0; kk < KT; kk += 2) {
+                const int kr = kk + (lane >> 5);
+                float2 a[2], b[2];
+#pragma unroll
+                for (int i = 0; i < 2; ++i) a[i] = As[buf][kr][wm * 64 + i * 32 + (lane & 31)];
+#pragma unroll
+                for (int j = 0; j < 2; ++j) b[j] = Bs[buf][kr][wn * 64 + j * 32 + (lane & 31)];
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+#pragma unroll
+                    for (int j = 0; j < 2; ++j) {
+                        acc[i][j][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i].x, b[j].x, acc[i][j][0], 0, 0, 0);
+                        acc[i][j][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i].x, b[j].y, acc[i][j][1], 0, 0, 0);
+                    }
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+#pragma unroll
+                    for (int j = 0; j < 2; ++j) {
+                        acc[i][j][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(-a[i].y, b[j].y, acc[i][j][0], 0, 0, 0);
+                        acc[i][j][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i].y, b[j].x, acc[i][j][1], 0, 0, 0);
+                    }
+            }
+            if (more) {
+                store8_kmajor(As[buf ^ 1], ar, ah, ra);
+                store8_kmajor(Bs[buf ^ 1], br, bh, rb);
+            }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                float2 *Cb = d.C + bi * d.sCb + (tm * TM + wm * 64 + i * 32) * d.sCm + (tn * TN + wn * 64 + j * 32) * d.sCn;
+#pragma unroll
+                for (int v = 0; v < 16; ++v) {
+                    const int row = (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
+                    Cb[row * d.sCm + (lane & 31) * d.sCn] = make_float2(acc[i][j][0][v], acc[i][j][1][v]);
+                }
+            }
+    }
+}
+
 // ----------------------------------------------------------- GEMM variants
 // Every kernel form a GEMM step can run as.  gemm_variant_ok says whether a
 // form applies to a shape (tile divisibility, k, precision); the default
@@ -635,6 +732,7 @@ bool gemm_variant_ok(const GemmDesc &d, int v) {
             return !split && k_fp32 && d.m % (32 * wm) == 0 && d.n % (32 * wn) == 0;
         }
         case kVarSplitBig: return split && d.k >= 2 && d.m % 128 == 0 && d.n % 128 == 0;
+        case kVarMfmaBig: return !split && d.k >= 2 && d.m % 128 == 0 && d.n % 128 == 0;
         case kVarSplit11: case kVarSplit12: case kVarSplit21: case kVarSplit22: {
             const int wm = (v == kVarSplit21 || v == kVarSplit22) ? 2 : 1, wn = (v == kVarSplit12 || v == kVarSplit22) ? 2 : 1;
             return split && d.k >= 2 && d.m % (32 * wm) == 0 && d.n % (32 * wn) == 0;
@@ -645,6 +743,7 @@ bool gemm_variant_ok(const GemmDesc &d, int v) {
 
 int gemm_default_variant(const GemmDesc &d) {
     if (d.prec != kPrecC64 && gemm_variant_ok(d, kVarSplitBig)) return kVarSplitBig;
+    if (d.prec == kPrecC64 && gemm_variant_ok(d, kVarMfmaBig)) return kVarMfmaBig;
     const int wm = d.m % 64 == 0 ? 2 : 1, wn = d.n % 64 == 0 ? 2 : 1;
     if (d.prec != kPrecC64) {
         const int v = wm == 2 ? (wn == 2 ? kVarSplit22 : kVarSplit21) : (wn == 2 ? kVarSplit12 : kVarSplit11);
@@ -693,6 +792,12 @@ const char *launch_gemm_variant(const GemmDesc &d, int v, hipStream_t st) {
         case kVarSplit12: launch_split<1, 2>(d, st); return split_name;
         case kVarSplit21: launch_split<2, 1>(d, st); return split_name;
         case kVarSplit22: launch_split<2, 2>(d, st); return split_name;
+        case kVarMfmaBig: {
+            const int64_t t128 = d.nb * (d.m / 128) * (d.n / 128);
+            const unsigned g = (unsigned)(t128 < 1048576 ? t128 : 1048576);
+            hipLaunchKernelGGL(gemm_mfma_big_kernel, dim3(g), dim3(256), 0, st, d);
+            return "gemm_mfma";
+        }
         case kVarSplitBig: {
             const int64_t t128 = d.nb * (d.m / 128) * (d.n / 128);
             const unsigned g = (unsigned)(t128 < 1048576 ? t128 : 1048576);

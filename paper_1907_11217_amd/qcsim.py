@@ -367,7 +367,7 @@ def qc_contract_slices_dev(plan: Plan, s_begin: int, s_end: int, bits_dev, prec,
 
 
 GEMM_FORMS = {"valu": 0, "skinny": 1, "dot": 2, "mfma11": 3, "mfma12": 4, "mfma21": 5, "mfma22": 6,
-              "split_big": 7, "split11": 8, "split12": 9, "split21": 10, "split22": 11}
+              "split_big": 7, "split11": 8, "split12": 9, "split21": 10, "split22": 11, "mfma_big": 12}
 
 
 def qc_kernel_gemm(A, B, C, nb: int, m: int, n: int, k: int, a_km: bool = False, b_nk: bool = False,
