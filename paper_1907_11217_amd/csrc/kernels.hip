@@ -552,7 +552,11 @@ __global__ void __launch_bounds__(256) gemm_split_big_kernel(GemmDesc d) {
         __syncthreads();
         for (int s = 0; s < n_slabs; ++s) {
             const int buf = s & 1;
-            const bool more = s + 1 < n_slabs;
+            // The next slab.  BF16 stages it unconditionally (zeros past the
+            // end, into the buffer nobody reads again) so that the staging
+            // shares the MFMAs' basic block and can be interleaved with them.
+            constexpr bool kInterleave = __is_same(T, __bf16);
+            const bool more = kInterleave || s + 1 < n_slabs;
             if (more) {
                 const int64_t k1 = int64_t(s + 1) * KT;
                 load8(ra, Ab, d.sAm, d.sAk, a_vec, ar, k1 + 8 * ah, d.k);
@@ -596,6 +600,21 @@ __global__ void __launch_bounds__(256) gemm_split_big_kernel(GemmDesc d) {
             if (more) {
                 split_store<T>(As[buf ^ 1], ar, ah, ra, ea);
                 split_store<T>(Bs[buf ^ 1], br, bh, rb, eb);
+            }
+            // BF16: the fragment reads, then each of the 48 MFMAs with four
+            // VALU instructions of the next slab's conversion and an LDS write
+            // after every sixth, so the conversion hides under the matrix
+            // pipe (measured faster).  FP16's conversion also scales and is
+            // about twice as long; it is left to the compiler's order, which
+            // measured faster for it.
+            if constexpr (kInterleave) {
+                __builtin_amdgcn_sched_group_barrier(0x100, 16, 0);
+#pragma unroll
+                for (int g = 0; g < 48; ++g) {
+                    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+                    __builtin_amdgcn_sched_group_barrier(0x002, 4, 0);
+                    if (g % 6 == 5) __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);
+                }
             }
             __syncthreads();
         }
