@@ -150,6 +150,24 @@ qc_status qc_plan_slice_assignment(const qc_plan *plan, uint64_t s, uint8_t *out
 qc_status qc_plan_describe(qc_plan *plan, int32_t log2_batch_slices, int32_t log2_batch_bs,
                            qc_precision prec, char *buf, size_t cap, size_t *len);
 
+/* The same lowered program's operations as a table, in execution order.
+ * kind 0 = bit-permuting transpose (a = source tensor, c = destination,
+ * m = its number of complex64 elements); kind 1 = GEMM step (a, b = operand
+ * tensors as stored after any transpose, c = result; C[nb][m][n] =
+ * sum_k A B with A stored [nb][k][m] if a_km else [nb][m][k], B stored
+ * [nb][n][k] if b_nk else [nb][k][n]).  Tensor ids match qc_plan_describe.
+ * Writes min(cap, count) rows to out (out may be NULL when cap is 0) and
+ * the count to *n; QC_ERR_RANGE if the batch sizes exceed the plan. */
+typedef struct {
+    int32_t kind;
+    int32_t a, b, c;                 /* b = -1 for a transpose */
+    int64_t nb, m, n, k;
+    int32_t a_km, b_nk;
+    double flops;                    /* 8 nb m n k for a GEMM step, 0 for a transpose */
+} qc_step_t;
+qc_status qc_plan_export_steps(qc_plan *plan, int32_t log2_batch_slices, int32_t log2_batch_bs, qc_step_t *out,
+                               int32_t cap, int32_t *n);
+
 /* How qc_contract_slices runs the program:
  *   QC_EXEC_AUTO (default): fused when one (slice, bitstring) contraction
  *     fits in LDS and prec is QC_C64, else stepwise;

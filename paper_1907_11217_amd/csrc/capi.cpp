@@ -126,6 +126,42 @@ extern "C" qc_status qc_plan_describe(qc_plan *plan, int32_t log2_batch_slices, 
     return QC_OK;
 }
 
+extern "C" qc_status qc_plan_export_steps(qc_plan *plan, int32_t log2_batch_slices, int32_t log2_batch_bs,
+                                          qc_step_t *out, int32_t cap, int32_t *n) {
+    if (!plan || !n || cap < 0 || (cap > 0 && !out)) {
+        set_error("qc_plan_export_steps: invalid argument");
+        return QC_ERR_INVALID_ARG;
+    }
+    std::string err;
+    qc::Program *prog = qc::get_program(plan, log2_batch_slices, log2_batch_bs, err);
+    if (!prog) { set_error("qc_plan_export_steps: " + err); return QC_ERR_RANGE; }
+    *n = (int32_t)prog->ops.size();
+    for (int32_t i = 0; i < std::min<int32_t>(cap, *n); ++i) {
+        const qc::Op &op = prog->ops[i];
+        qc_step_t r{};
+        if (op.kind == qc::Op::TRANSPOSE) {
+            const qc::TransposeOp &t = prog->transposes[op.index];
+            r.kind = 0;
+            r.a = t.src;
+            r.b = -1;
+            r.c = t.dst;
+            r.m = prog->tensors[t.src].size();
+        } else {
+            const qc::GemmOp &g = prog->gemms[op.index];
+            r.kind = 1;
+            r.a = g.a;
+            r.b = g.b;
+            r.c = g.c;
+            r.nb = g.nb; r.m = g.m; r.n = g.n; r.k = g.k;
+            r.a_km = g.a_km;
+            r.b_nk = g.b_nk;
+            r.flops = 8.0 * double(g.nb) * double(g.m) * double(g.n) * double(g.k);
+        }
+        out[i] = r;
+    }
+    return QC_OK;
+}
+
 extern "C" qc_status qc_plan_set_exec(qc_plan *plan, int32_t mode) {
     if (!plan || mode < QC_EXEC_AUTO || mode > QC_EXEC_STEPWISE) {
         set_error("qc_plan_set_exec: invalid argument");

@@ -30,6 +30,7 @@ EXPORTED = (
     "qc_gate_matrix", "qc_plan_destroy", "qc_last_error", "qc_kernel_gemm", "qc_kernel_transpose",
     "qc_plan_set_exec", "qc_profile_enable", "qc_profile_read", "qc_contract_slices_dev", "qc_plan_set_graphs",
     "qc_tune", "qc_kernel_gemm_form", "qc_batch_workspace_bytes", "qc_contract_batch", "qc_wall_clock_khz",
+    "qc_plan_export_steps",
 )
 EXEC_MODES = {"auto": 0, "fused": 1, "stepwise": 2}
 
@@ -48,6 +49,12 @@ class qc_gate(ctypes.Structure):
 class qc_circuit(ctypes.Structure):
     _fields_ = [("n_qubits", ctypes.c_int32), ("n_gates", ctypes.c_int32),
                 ("gates", ctypes.POINTER(qc_gate))]
+
+
+class qc_step_t(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("a", ctypes.c_int32), ("b", ctypes.c_int32), ("c", ctypes.c_int32),
+                ("nb", ctypes.c_int64), ("m", ctypes.c_int64), ("n", ctypes.c_int64), ("k", ctypes.c_int64),
+                ("a_km", ctypes.c_int32), ("b_nk", ctypes.c_int32), ("flops", ctypes.c_double)]
 
 
 class qc_request(ctypes.Structure):
@@ -131,6 +138,9 @@ def load(path: str | None = None):
         lib.qc_contract_batch.argtypes = [ctypes.POINTER(qc_request), ctypes.c_int32, ctypes.c_int, vp, ctypes.c_size_t,
                                           vp, vp, vp]
         lib.qc_contract_batch.restype = ctypes.c_int
+        lib.qc_plan_export_steps.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(qc_step_t),
+                                             ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
+        lib.qc_plan_export_steps.restype = ctypes.c_int
         lib.qc_wall_clock_khz.argtypes = [ctypes.POINTER(ctypes.c_int32)]
         lib.qc_wall_clock_khz.restype = ctypes.c_int
         lib.qc_plan_set_graphs.argtypes = [vp, ctypes.c_int32]
@@ -283,6 +293,17 @@ def qc_contract_batch(batch: Batch, prec, ws, out_dev, t_done_dev, stream=None):
     _check(batch.lib.qc_contract_batch(batch.array, len(batch), _prec(prec), ws.data_ptr(),
                                        ws.numel() * ws.element_size(), st.cuda_stream, out_dev.data_ptr(),
                                        t_done_dev.data_ptr()), batch.lib)
+
+
+def qc_plan_export_steps(plan: Plan, log2_batch_slices: int = 0, log2_batch_bs: int = 0):
+    """The lowered program's operations as a list of dicts (execution order)."""
+    n = ctypes.c_int32(0)
+    _check(plan._lib.qc_plan_export_steps(plan.handle, log2_batch_slices, log2_batch_bs, None, 0, ctypes.byref(n)),
+           plan._lib)
+    rows = (qc_step_t * max(1, n.value))()
+    _check(plan._lib.qc_plan_export_steps(plan.handle, log2_batch_slices, log2_batch_bs, rows, n.value,
+                                          ctypes.byref(n)), plan._lib)
+    return [{f: getattr(rows[i], f) for f, _ in qc_step_t._fields_} for i in range(n.value)]
 
 
 def qc_wall_clock_khz() -> int:

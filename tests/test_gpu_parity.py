@@ -237,3 +237,25 @@ def test_split_needs_stepwise(c2_setup):
         assert "complex FP32" in str(e.value)
     finally:
         qcsim.qc_plan_set_exec(plan, "auto")
+
+
+@pytest.mark.parametrize("prec", ["c64", "split_fp16"])
+def test_c3_sampled_slices_match_oracle(prec):
+    # 7x7 depth 24: beyond the state vector, so slice values are compared
+    # with the oracle's own sliced contraction (O3, slice list of the plan read
+    # as data) on slices drawn from the seed + 2 stream; each oracle slice
+    # takes ~16 s on the host, so two slices.  All 2^16 slices run in one
+    # call (the measured configuration), per-slice values kept.
+    lat, circ, bs, spec = synth.config("c3")
+    plan = qcsim.qc_plan_build(lat.n, circ, bs[0], log2_slices=16, log2_max_entries=30, greedy_trials=8, seed=1)
+    k = qcsim.qc_plan_info(plan)["log2_slices"]
+    segs = [tuple(int(v) for v in s) for s in qcsim.qc_plan_sliced_segments(plan)]
+    picks = [int(s) for s in synth.random_slices(k, 2, spec["seed"] + 2)]
+    say(f"c3 7x7 d24 all 2^{k} slices {prec}, oracle on slices {picks}")
+    amp, ps = _contract(plan, bs[:1], 0, 1 << k, prec=prec, chunk=1 << k, per_slice=True)
+    assert abs(ps[:, 0].sum() - amp[0]) <= 1e-12 * np.abs(ps).sum()
+    scale = np.sqrt(np.mean(np.abs(ps[:, 0]) ** 2))
+    tol = TOL_C64 if prec == "c64" else TOL_SPLIT[prec]
+    for s in picks:
+        v = oracle.sliced_value(lat.n, circ, bs[0], segs, s)
+        assert abs(ps[s, 0] - v) <= tol * max(abs(v), scale), (s, ps[s, 0], v)

@@ -203,3 +203,21 @@ def test_idle_qubit_and_diagonal_only_wires():
     psi = oracle.statevector(3, circ)
     ref = np.array([psi[oracle.index_of(x)] for x in xs])
     assert np.abs(got - ref).max() < 1e-15
+
+
+def test_export_steps_matches_description():
+    lat, circ, bs, plan = _plan("c2", log2_slices=6, greedy_trials=2, seed=1)
+    for b, m in [(0, 0), (6, 6), (3, 2)]:
+        steps = qcsim.qc_plan_export_steps(plan, b, m)
+        ops = qcsim.qc_plan_describe(plan, b, m)["ops"]
+        assert len(steps) == len(ops)
+        for st, op in zip(steps, ops):
+            if op["op"] == "gemm":
+                assert st["kind"] == 1 and (st["a"], st["b"], st["c"]) == (op["a"], op["b"], op["c"])
+                assert (st["nb"], st["m"], st["n"], st["k"]) == (op["nb"], op["m"], op["n"], op["k"])
+                assert (st["a_km"], st["b_nk"]) == (int(op["a_km"]), int(op["b_nk"]))
+                assert st["flops"] == 8.0 * op["nb"] * op["m"] * op["n"] * op["k"]
+            else:
+                assert st["kind"] == 0 and (st["a"], st["c"]) == (op["src"], op["dst"]) and st["b"] == -1
+    with pytest.raises(qcsim.QcError):
+        qcsim.qc_plan_export_steps(plan, 7, 0)
