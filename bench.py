@@ -57,7 +57,7 @@ def _gemm_form(op, prec="c64"):
         return f"gemm_{prec}"
     kt = 16 if k >= 16 else k
     ok = kt in (2, 4, 8, 16) and k % kt == 0
-    if prec == "c64" and ok and m % 32 == 0 and n % 32 == 0:
+    if prec == "c64" and ((ok and m % 32 == 0 and n % 32 == 0) or (k >= 2 and m % 128 == 0 and n % 128 == 0)):
         return "gemm_mfma"
     if k >= 4096 and op["nb"] * m * n <= 4096:
         return "gemm_dot"
@@ -202,7 +202,7 @@ def big_leg(key, precs, reps, s_range, oracle_slices=(), tune=False):
     stream = torch.cuda.current_stream()
     out = torch.zeros(1, 2, dtype=torch.float64, device="cuda")
     b = (n_sl - 1).bit_length()
-    desc = qcsim.qc_plan_describe(plan, b, 0)
+    steps = qcsim.qc_plan_export_steps(plan, b, 0)
     chunks = max(1, n_sl >> b)
     leg = {"workload": (f"{spec['name']}: {lat.n} qubits, depth 1+{spec['depth']}+1, 2^{k} slices (cap 2^"
                         f"{spec.get('log2_cap', 0)} entries), slices [{s0}, {s1}) for bitstring seed "
@@ -239,10 +239,10 @@ def big_leg(key, precs, reps, s_range, oracle_slices=(), tune=False):
         prof = qcsim.qc_profile_read(plan)
         # Algorithmic flops of the step's GEMMs, per kernel kind.
         per_kind = {}
-        for op in desc["ops"]:
-            if op["op"] == "gemm":
-                f = _gemm_form(op, prec)
-                per_kind[f] = per_kind.get(f, 0.0) + 8.0 * op["nb"] * op["m"] * op["n"] * op["k"] * chunks
+        for op in steps:
+            if op["kind"] == 1:
+                f = "micro" if op["micro"] else _gemm_form(op, prec)
+                per_kind[f] = per_kind.get(f, 0.0) + op["flops"] * chunks
         flops = sum(per_kind.values())
         r = {"ms_per_step": ms, "value": val.real, "value_im": val.imag, "tflops": flops / (ms * 1e-3) / 1e12,
              "tune_seconds": tune_s,
@@ -408,18 +408,20 @@ def main():
             except qcsim.QcError:
                 continue
         chunks = max(1, n_slices >> b)
-        per = {"gemm_mfma": 0.0, "gemm_valu": 0.0, "gemm_skinny": 0.0, "gemm_dot": 0.0, "transpose": 0.0}
+        per = {"gemm_mfma": 0.0, "gemm_valu": 0.0, "gemm_skinny": 0.0, "gemm_dot": 0.0, "micro": 0.0,
+               "transpose": 0.0}
         for op in desc["ops"]:
             if op["op"] == "gemm":
-                per[_gemm_form(op)] += 8.0 * op["nb"] * op["m"] * op["n"] * op["k"]
-            else:
+                per["micro" if op.get("micro") else _gemm_form(op)] += 8.0 * op["nb"] * op["m"] * op["n"] * op["k"]
+            elif not op.get("micro"):
                 per["transpose"] += 16.0 * (1 << len(desc["tensors"][op["src"]]["layout"]))
-        flops_step = (per["gemm_mfma"] + per["gemm_valu"] + per["gemm_skinny"] + per["gemm_dot"]) * chunks * n_bs / \
-            (1 << desc["m"])
+        flops_step = (per["gemm_mfma"] + per["gemm_valu"] + per["gemm_skinny"] + per["gemm_dot"] + per["micro"]) * \
+            chunks * n_bs / (1 << desc["m"])
         kind_work = {"gemm_mfma": (per["gemm_mfma"] * chunks, "mfma"),
                      "gemm_valu": (per["gemm_valu"] * chunks, "alu"),
                      "gemm_skinny": (per["gemm_skinny"] * chunks, "alu"),
                      "gemm_dot": (per["gemm_dot"] * chunks, "alu"),
+                     "micro": (per["micro"] * chunks, "alu"),
                      "transpose": (per["transpose"] * chunks, "hbm")}
     dom = max(prof, key=lambda kk: prof[kk][1])
     launches, total_ms = prof[dom]

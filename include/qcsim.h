@@ -157,13 +157,18 @@ qc_status qc_plan_describe(qc_plan *plan, int32_t log2_batch_slices, int32_t log
  * sum_k A B with A stored [nb][k][m] if a_km else [nb][m][k], B stored
  * [nb][n][k] if b_nk else [nb][k][n]).  Tensor ids match qc_plan_describe.
  * Writes min(cap, count) rows to out (out may be NULL when cap is 0) and
- * the count to *n; QC_ERR_RANGE if the batch sizes exceed the plan. */
+ * the count to *n; QC_ERR_RANGE if the batch sizes exceed the plan.
+ * micro = 1 marks the small steps (output and operands of at most 2^12
+ * entries, fed only by leaves and other small steps) that the stepwise form
+ * runs together in one kernel right after the leaves, and the transposes it
+ * therefore skips. */
 typedef struct {
     int32_t kind;
     int32_t a, b, c;                 /* b = -1 for a transpose */
     int64_t nb, m, n, k;
     int32_t a_km, b_nk;
     double flops;                    /* 8 nb m n k for a GEMM step, 0 for a transpose */
+    int32_t micro, reserved;
 } qc_step_t;
 qc_status qc_plan_export_steps(qc_plan *plan, int32_t log2_batch_slices, int32_t log2_batch_bs, qc_step_t *out,
                                int32_t cap, int32_t *n);
@@ -211,9 +216,9 @@ qc_status qc_tune(qc_plan *plan, int64_t chunk_slices, int32_t n_bs, qc_precisio
  * events on its stream around every kernel it launches.  qc_profile_read
  * waits for the recorded events, then reports per kernel kind the launch
  * count and the summed event-to-event milliseconds since the last read (and
- * clears them).  kinds: "fused", "leaves", "transpose", "gemm_mfma",
- * "gemm_split_bf16", "gemm_split_fp16", "gemm_skinny", "gemm_dot",
- * "gemm_valu", "reduce64".  Not
+ * clears them).  kinds: "fused", "leaves", "micro", "transpose",
+ * "gemm_mfma", "gemm_split_bf16", "gemm_split_fp16", "gemm_skinny",
+ * "gemm_dot", "gemm_valu", "reduce64".  Not
  * thread-safe across concurrent calls on one plan. */
 typedef struct {
     char kind[16];

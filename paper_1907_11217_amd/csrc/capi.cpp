@@ -157,6 +157,7 @@ extern "C" qc_status qc_plan_export_steps(qc_plan *plan, int32_t log2_batch_slic
             r.b_nk = g.b_nk;
             r.flops = 8.0 * double(g.nb) * double(g.m) * double(g.n) * double(g.k);
         }
+        r.micro = prog->op_micro.empty() ? 0 : prog->op_micro[i];
         out[i] = r;
     }
     return QC_OK;

@@ -129,6 +129,21 @@ constexpr int kFusedPairsOptions[] = {1, 2, 4};
 size_t fused_lds_bytes(int pairs, int pair_elems);
 void launch_fused_pairs(const FusedParams &p, int pairs, int pair_elems, int zero_slot, hipStream_t st);
 
+// One small GEMM step computed by the micro-step kernel straight from its
+// operands' layouts: output element o (bit p of o = bit p of C's layout,
+// least significant first) reads A at a + sum of sa[p] over set bits, B at
+// b + sum of sb[p]; contracted value j adds ka[q], kb[q] for set bits q.
+constexpr int kMicroRank = 12;
+struct MicroStep {
+    int64_t a, b, c;                         // element offsets in the tensor region
+    int32_t rc, rk, out0, amax_slot;         // out0: first flat output of this step in its level
+    int32_t sa[kMicroRank], sb[kMicroRank], ka[kMicroRank], kb[kMicroRank];
+};
+// Runs the levels of micro steps in order with one workgroup (a barrier
+// between levels); amax (or null) as for the GEMM epilogues.
+void launch_micro(const MicroStep *steps, const int32_t *level_start, const int32_t *level_outs, int n_levels,
+                  float2 *tensors, uint32_t *amax, hipStream_t st);
+
 // Device descriptor of one request of a fused batch (one bitstring).  Its
 // slice values go to partial[partial_off + (s - s_base)], s_base = s_begin
 // rounded down to a multiple of 64.

@@ -105,6 +105,64 @@ void launch_zero_u32(uint32_t *p, int64_t n, hipStream_t st) {
     hipLaunchKernelGGL(zero_u32_kernel, dim3((unsigned)grid), dim3(256), 0, st, p, n);
 }
 
+// -------------------------------------------------------------- micro steps
+// All small GEMM steps of a stepwise program in one launch: levels in order,
+// the outputs of a level spread over the workgroup (steps of a level read
+// only lower levels), the operands read in the layouts their producers wrote.
+__global__ void __launch_bounds__(1024) micro_kernel(const MicroStep *__restrict__ steps,
+                                                     const int32_t *__restrict__ level_start,
+                                                     const int32_t *__restrict__ level_outs, int n_levels,
+                                                     float2 *tensors, uint32_t *amax) {
+    // Per-step maxima of a level gather in LDS first (one global atomic per
+    // step); a level with more steps than fit uses global atomics directly.
+    constexpr int kSlots = 1024;
+    __shared__ uint32_t lmax[kSlots];
+    for (int lv = 0; lv < n_levels; ++lv) {
+        const int s0 = level_start[lv], s1 = level_start[lv + 1];
+        const bool local = amax && s1 - s0 <= kSlots;
+        if (local) {
+            for (int i = threadIdx.x; i < s1 - s0; i += blockDim.x) lmax[i] = 0u;
+            __syncthreads();
+        }
+        for (int f = threadIdx.x; f < level_outs[lv]; f += blockDim.x) {
+            int s = s0;
+            while (s + 1 < s1 && steps[s + 1].out0 <= f) ++s;
+            const MicroStep &M = steps[s];
+            const int o = f - M.out0;
+            int64_t oa = M.a, ob = M.b;
+            for (int p = 0; p < M.rc; ++p)
+                if ((o >> p) & 1) { oa += M.sa[p]; ob += M.sb[p]; }
+            float re = 0.f, im = 0.f;
+            for (int j = 0; j < (1 << M.rk); ++j) {
+                int64_t xa = oa, xb = ob;
+                for (int q = 0; q < M.rk; ++q)
+                    if ((j >> q) & 1) { xa += M.ka[q]; xb += M.kb[q]; }
+                const float2 x = tensors[xa], y = tensors[xb];
+                re = fmaf(x.x, y.x, re);
+                re = fmaf(-x.y, y.y, re);
+                im = fmaf(x.x, y.y, im);
+                im = fmaf(x.y, y.x, im);
+            }
+            tensors[M.c + o] = make_float2(re, im);
+            const uint32_t mx = __float_as_uint(fmaxf(fabsf(re), fabsf(im)));
+            if (local) atomicMax(&lmax[s - s0], mx);
+            else if (amax) atomicMax(amax + M.amax_slot, mx);
+        }
+        __syncthreads();
+        if (local) {
+            for (int i = threadIdx.x; i < s1 - s0; i += blockDim.x) atomicMax(amax + steps[s0 + i].amax_slot, lmax[i]);
+            __syncthreads();
+        }
+    }
+}
+
+void launch_micro(const MicroStep *steps, const int32_t *level_start, const int32_t *level_outs, int n_levels,
+                  float2 *tensors, uint32_t *amax, hipStream_t st) {
+    if (n_levels <= 0) return;
+    hipLaunchKernelGGL(micro_kernel, dim3(1), dim3(1024), 0, st, steps, level_start, level_outs, n_levels, tensors,
+                       amax);
+}
+
 // --------------------------------------------------------------- transpose
 // A tile of 2^n_tile elements is read in input order (coalesced along the
 // input's fastest bits), stored in LDS, then written in output order

@@ -265,6 +265,42 @@ static bool lower(const qc_plan *plan, int b, int m, Program &prog, std::string 
     }
     prog.tensor_elems = arena.end;
 
+    // Micro steps: GEMM steps whose output and (untransposed) operands have at
+    // most 2^kMicroMaxLog2 entries and whose operands are leaves or outputs of
+    // micro steps.  They run together in one kernel right after the leaves,
+    // reading their operands as produced, so the transposes that fed them are
+    // skipped.  Being computed before their turn, their outputs get a region
+    // of their own after the arena.
+    {
+        std::vector<char> avail(nt, 0);
+        std::vector<int> producer(nt, -1);
+        for (int t = 0; t < L; ++t) avail[t] = 1;
+        for (size_t i = 0; i < prog.ops.size(); ++i) {
+            const Op &op = prog.ops[i];
+            producer[op.kind == Op::TRANSPOSE ? prog.transposes[op.index].dst : prog.gemms[op.index].c] = (int)i;
+        }
+        prog.op_micro.assign(prog.ops.size(), 0);
+        prog.gemm_micro.assign(prog.gemms.size(), 0);
+        const int64_t cap = int64_t(1) << kMicroMaxLog2;
+        int64_t extra = 0;
+        for (size_t i = 0; i < prog.ops.size(); ++i) {
+            const Op &op = prog.ops[i];
+            if (op.kind != Op::GEMM) continue;
+            const GemmOp &g = prog.gemms[op.index];
+            if (!avail[g.a_src] || !avail[g.b_src] || prog.tensors[g.c].size() > cap ||
+                prog.tensors[g.a_src].size() > cap || prog.tensors[g.b_src].size() > cap)
+                continue;
+            prog.op_micro[i] = 1;
+            prog.gemm_micro[op.index] = 1;
+            avail[g.c] = 1;
+            if (g.a != g.a_src) prog.op_micro[producer[g.a]] = 1;
+            if (g.b != g.b_src) prog.op_micro[producer[g.b]] = 1;
+            prog.tensors[g.c].offset = arena.end + extra;
+            extra += (prog.tensors[g.c].size() + 31) & ~int64_t(31);
+        }
+        prog.tensor_elems = arena.end + extra;
+    }
+
     // Fused form: GEMM steps read their operands as produced (no transposes)
     // and run level by level (a step's level is one more than its operands'),
     // all steps of a level at once.  Offsets come from a separate arena sized
@@ -354,13 +390,15 @@ std::string describe_program(const qc_plan *plan, const Program &prog) {
         o << (i ? "," : "");
         if (op.kind == Op::TRANSPOSE) {
             const TransposeOp &t = prog.transposes[op.index];
-            o << "{\"op\":\"transpose\",\"src\":" << t.src << ",\"dst\":" << t.dst << '}';
+            o << "{\"op\":\"transpose\",\"src\":" << t.src << ",\"dst\":" << t.dst
+              << ",\"micro\":" << int(prog.op_micro.empty() ? 0 : prog.op_micro[i]) << '}';
         } else {
             const GemmOp &g = prog.gemms[op.index];
             o << "{\"op\":\"gemm\",\"a\":" << g.a << ",\"b\":" << g.b << ",\"a_src\":" << g.a_src
               << ",\"b_src\":" << g.b_src << ",\"c\":" << g.c << ",\"nb\":" << g.nb
               << ",\"m\":" << g.m << ",\"n\":" << g.n << ",\"k\":" << g.k << ",\"a_km\":" << (g.a_km ? 1 : 0)
-              << ",\"b_nk\":" << (g.b_nk ? 1 : 0) << '}';
+              << ",\"b_nk\":" << (g.b_nk ? 1 : 0) << ",\"micro\":" << int(prog.op_micro.empty() ? 0 : prog.op_micro[i])
+              << '}';
         }
     }
     o << "],\"fused_pairs\":" << prog.fused_pairs << ",\"fused_tuning\":[";

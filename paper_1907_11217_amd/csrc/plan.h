@@ -79,6 +79,7 @@ TreeCost tree_cost(const OrderProblem &p, const std::vector<Merge> &tree,
 // ------------------------------------------------------------ lowering
 // Index ids inside a program: segment ids, then kBsBase + i for bitstring bit i.
 constexpr int kBsBase = 1 << 20;
+constexpr int kMicroMaxLog2 = 12;  // micro steps: output and operands of at most 2^12 entries
 
 struct ProgTensor {
     std::vector<int> layout;   // major -> minor
@@ -117,6 +118,8 @@ struct Program {
     std::vector<TransposeOp> transposes;
     std::vector<GemmOp> gemms;
     std::vector<Op> ops;
+    std::vector<char> op_micro;           // per op: run by the micro-step kernel (GEMM) or skipped (its transpose)
+    std::vector<char> gemm_micro;         // per GEMM step: run by the micro-step kernel
     int root = -1;                        // tensor holding [slice bits][bs bits]
     int root_pre = -1;                    // the tree's last tensor (before any final transpose)
     int64_t tensor_elems = 0;             // tensor region size (complex64 elements)
@@ -130,6 +133,9 @@ struct Program {
     void *d_leaf_block = nullptr;
     void *d_base = nullptr;
     int n_leaf_blocks = 0;
+    void *d_micro = nullptr;              // micro-step table (stepwise form)
+    void *d_micro_levels = nullptr;       // step offsets of its levels
+    int n_micro_levels = 0;
     void *d_fused_image = nullptr;        // leaf values that do not depend on the (slice, bitstring) pair
     int n_image = 0;
     void *d_fused_elems = nullptr;        // run-time leaf elements: LDS slot, base index, dynamic bits

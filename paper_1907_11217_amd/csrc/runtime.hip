@@ -226,6 +226,59 @@ bool ensure_device(const qc_plan *plan, Program &prog, bool fused, std::string &
             !upload(&prog.d_leaf_desc, descs.data(), descs.size() * sizeof(LeafDesc), err))
             return false;
         prog.n_leaf_blocks = (int)blocks.size();
+        // Micro steps, grouped by level (leaves are level 0).
+        std::vector<int> lvl(prog.tensors.size(), 0);
+        std::vector<std::vector<MicroStep>> by_level;
+        for (size_t i = 0; i < prog.ops.size(); ++i) {
+            if (prog.op_micro.empty() || !prog.op_micro[i] || prog.ops[i].kind != Op::GEMM) continue;
+            const GemmOp &g = prog.gemms[prog.ops[i].index];
+            const auto &LA = prog.tensors[g.a_src].layout, &LB = prog.tensors[g.b_src].layout;
+            const auto &LC = prog.tensors[g.c].layout;
+            const int lv = 1 + std::max(lvl[g.a_src], lvl[g.b_src]);
+            lvl[g.c] = lv;
+            MicroStep M;
+            std::memset(&M, 0, sizeof(M));
+            M.a = prog.tensors[g.a_src].offset;
+            M.b = prog.tensors[g.b_src].offset;
+            M.c = prog.tensors[g.c].offset;
+            M.rc = (int)LC.size();
+            M.amax_slot = g.c;
+            if (M.rc > kMicroRank) { err = "micro step rank too large"; return false; }
+            for (int p = 0; p < M.rc; ++p) {
+                const int e = LC[M.rc - 1 - p];
+                M.sa[p] = stride_in(LA, e);
+                M.sb[p] = stride_in(LB, e);
+            }
+            std::vector<int> ks;  // summed indices: in A or B, not in C
+            for (const auto *Lx : {&LA, &LB})
+                for (int e : *Lx)
+                    if (std::find(LC.begin(), LC.end(), e) == LC.end() && std::find(ks.begin(), ks.end(), e) == ks.end())
+                        ks.push_back(e);
+            if ((int)ks.size() > kMicroRank) { err = "micro step contraction too large"; return false; }
+            M.rk = (int)ks.size();
+            for (int q = 0; q < M.rk; ++q) {
+                M.ka[q] = stride_in(LA, ks[q]);
+                M.kb[q] = stride_in(LB, ks[q]);
+            }
+            if ((int)by_level.size() < lv) by_level.resize(lv);
+            by_level[lv - 1].push_back(M);
+        }
+        std::vector<MicroStep> steps;
+        std::vector<int32_t> starts(1, 0), outs;
+        for (auto &v : by_level) {
+            int32_t o = 0;
+            for (MicroStep &M : v) { M.out0 = o; o += 1 << M.rc; steps.push_back(M); }
+            starts.push_back((int32_t)steps.size());
+            outs.push_back(o);
+        }
+        prog.n_micro_levels = (int)by_level.size();
+        if (prog.n_micro_levels > 0) {
+            std::vector<int32_t> lv_tab(starts);
+            lv_tab.insert(lv_tab.end(), outs.begin(), outs.end());  // starts (n+1) then outs (n)
+            if (!upload(&prog.d_micro, steps.data(), steps.size() * sizeof(MicroStep), err) ||
+                !upload(&prog.d_micro_levels, lv_tab.data(), lv_tab.size() * 4, err))
+                return false;
+        }
     }
     if (fused && !prog.d_fused_items) {
         std::vector<LeafDesc> descs;
@@ -516,7 +569,16 @@ bool launch_all(qc_plan *plan, const Exec &x, uint64_t s_begin, uint64_t s_end, 
                               prog.n_leaf_blocks, (const double2 *)prog.d_base, tensors, bits, nq, n_bs, cb, amax,
                               st);
                 prof.end("leaves");
-                for (const Op &op : prog.ops) {
+                if (prog.n_micro_levels > 0) {
+                    const int32_t *lt = (const int32_t *)prog.d_micro_levels;
+                    prof.begin();
+                    launch_micro((const MicroStep *)prog.d_micro, lt, lt + prog.n_micro_levels + 1,
+                                 prog.n_micro_levels, tensors, amax, st);
+                    prof.end("micro");
+                }
+                for (size_t oi = 0; oi < prog.ops.size(); ++oi) {
+                    const Op &op = prog.ops[oi];
+                    if (prog.op_micro[oi]) continue;
                     prof.begin();
                     if (op.kind == Op::TRANSPOSE) {
                         launch_transpose(make_transpose(prog, prog.transposes[op.index], tensors), st);
@@ -665,7 +727,8 @@ void free_program_device(Program &prog) {
     for (auto &g : prog.graphs) (void)hipGraphExecDestroy((hipGraphExec_t)g.second);
     prog.graphs.clear();
     for (void **p : {&prog.d_leaf_desc, &prog.d_leaf_block, &prog.d_base, &prog.d_fused_image, &prog.d_fused_elems,
-                     &prog.d_fused_pool, &prog.d_fused_items, &prog.d_fused_levels}) {
+                     &prog.d_fused_pool, &prog.d_fused_items, &prog.d_fused_levels, &prog.d_micro,
+                     &prog.d_micro_levels}) {
         if (*p) (void)hipFree(*p);
         *p = nullptr;
     }
@@ -1061,7 +1124,9 @@ extern "C" qc_status qc_tune(qc_plan *plan, int64_t chunk_slices, int32_t n_bs, 
         qc_status status = QC_OK;
         // Operands are the program's own workspace regions: their contents do
         // not matter for timing, and every access stays inside the tensors.
-        for (qc::GemmOp &g : prog.gemms) {
+        for (size_t gi = 0; gi < prog.gemms.size(); ++gi) {
+            qc::GemmOp &g = prog.gemms[gi];
+            if (prog.gemm_micro[gi]) continue;  // run by the micro-step kernel
             const qc::GemmDesc d = qc::make_gemm(prog, g, tensors, x.prec, amax, slot);
             const std::string key = qc::tune_key(arch, d, g.a_km, g.b_nk);
             auto it = qc::g_tune.find(key);

@@ -54,7 +54,8 @@ class qc_circuit(ctypes.Structure):
 class qc_step_t(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("a", ctypes.c_int32), ("b", ctypes.c_int32), ("c", ctypes.c_int32),
                 ("nb", ctypes.c_int64), ("m", ctypes.c_int64), ("n", ctypes.c_int64), ("k", ctypes.c_int64),
-                ("a_km", ctypes.c_int32), ("b_nk", ctypes.c_int32), ("flops", ctypes.c_double)]
+                ("a_km", ctypes.c_int32), ("b_nk", ctypes.c_int32), ("flops", ctypes.c_double),
+                ("micro", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class qc_request(ctypes.Structure):
