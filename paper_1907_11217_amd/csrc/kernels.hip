@@ -265,6 +265,7 @@ __global__ void __launch_bounds__(256) gemm_skinny_kernel(GemmDesc d) {
         float re[M], im[M];
 #pragma unroll
         for (int i = 0; i < M; ++i) { re[i] = 0.f; im[i] = 0.f; }
+#pragma unroll 4
         for (int64_t l = 0; l < d.k; ++l) {
             const float2 y = ok ? Bb[l * d.sBk] : make_float2(0.f, 0.f);
 #pragma unroll
@@ -891,8 +892,9 @@ const char *launch_gemm_variant(const GemmDesc &d, int v, hipStream_t st) {
             return "gemm_dot";
         }
         case kVarSkinny: {
-            const int64_t blocks = d.nb * ((d.n + 255) / 256);
-            const unsigned g = (unsigned)(blocks < 8192 ? blocks : 8192);
+            // Fewer workgroups when each folds a maximum into one slot.
+            const int64_t blocks = d.nb * ((d.n + 255) / 256), cap = d.amax_c ? 2048 : 8192;
+            const unsigned g = (unsigned)(blocks < cap ? blocks : cap);
             switch (d.m) {
                 case 1: hipLaunchKernelGGL(gemm_skinny_kernel<1>, dim3(g), dim3(256), 0, st, d); break;
                 case 2: hipLaunchKernelGGL(gemm_skinny_kernel<2>, dim3(g), dim3(256), 0, st, d); break;
@@ -1185,14 +1187,14 @@ void launch_fused_pairs(const FusedParams &p, int pairs, int pair_elems, int zer
 
 // --------------------------------------------------------------- reduce64
 
-// One workgroup per bitstring.  Its waves (one, or four when there are many
-// blocks) form the 64-slice block sums (fixed butterfly) of up to 256 blocks
+// One workgroup per bitstring.  Its waves (one, four or sixteen, by the number
+// of blocks) form the 64-slice block sums (fixed butterfly) of up to 256 blocks
 // at a time into LDS; then one thread adds them to the running total in
 // increasing block order, so the result is bitwise the same as adding the
 // blocks one after another.
-constexpr int kReduceBatch = 256;
+constexpr int kReduceBatch = 1024;
 
-__global__ void __launch_bounds__(256) reduce64_kernel(const float2 *__restrict__ partial, int m, int n_bs,
+__global__ void __launch_bounds__(1024) reduce64_kernel(const float2 *__restrict__ partial, int m, int n_bs,
                                                        uint64_t sc, int64_t n_blocks, uint64_t lo, uint64_t hi,
                                                        uint64_t s_begin, double *__restrict__ out,
                                                        double *__restrict__ per_slice) {
@@ -1240,7 +1242,7 @@ __global__ void __launch_bounds__(256) reduce64_kernel(const float2 *__restrict_
 
 void launch_reduce64(const float2 *partial, int m, int n_bs, uint64_t sc, int64_t n_blocks, uint64_t lo, uint64_t hi,
                      uint64_t s_begin, double *out, double *per_slice, hipStream_t st) {
-    const int threads = n_blocks >= 16 ? 256 : 64;
+    const int threads = n_blocks >= 64 ? 1024 : (n_blocks >= 16 ? 256 : 64);
     hipLaunchKernelGGL(reduce64_kernel, dim3(n_bs), dim3(threads), 0, st, partial, m, n_bs, sc, n_blocks, lo, hi,
                        s_begin, out, per_slice);
 }
