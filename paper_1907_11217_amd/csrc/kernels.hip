@@ -265,16 +265,23 @@ __global__ void __launch_bounds__(256) gemm_skinny_kernel(GemmDesc d) {
         float re[M], im[M];
 #pragma unroll
         for (int i = 0; i < M; ++i) { re[i] = 0.f; im[i] = 0.f; }
-#pragma unroll 4
-        for (int64_t l = 0; l < d.k; ++l) {
-            const float2 y = ok ? Bb[l * d.sBk] : make_float2(0.f, 0.f);
+        // Eight loads of B in flight before their arithmetic.
+        for (int64_t l0 = 0; l0 < d.k; l0 += 8) {
+            float2 y[8];
 #pragma unroll
-            for (int i = 0; i < M; ++i) {
-                const float2 x = Ab[i * d.sAm + l * d.sAk];
-                re[i] = fmaf(x.x, y.x, re[i]);
-                re[i] = fmaf(-x.y, y.y, re[i]);
-                im[i] = fmaf(x.x, y.y, im[i]);
-                im[i] = fmaf(x.y, y.x, im[i]);
+            for (int u = 0; u < 8; ++u)
+                y[u] = (ok && l0 + u < d.k) ? Bb[(l0 + u) * d.sBk] : make_float2(0.f, 0.f);
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                if (l0 + u >= d.k) break;
+#pragma unroll
+                for (int i = 0; i < M; ++i) {
+                    const float2 x = Ab[i * d.sAm + (l0 + u) * d.sAk];
+                    re[i] = fmaf(x.x, y[u].x, re[i]);
+                    re[i] = fmaf(-x.y, y[u].y, re[i]);
+                    im[i] = fmaf(x.x, y[u].y, im[i]);
+                    im[i] = fmaf(x.y, y[u].x, im[i]);
+                }
             }
         }
         if (ok) {
