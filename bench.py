@@ -152,6 +152,9 @@ def batch_leg(n_req=256, seed=501, cap=24, reps=3, n_oracle=6, trials=32, precs=
     return leg
 
 
+PLAN_TRIALS = {"c3": 8, "c4": 256}   # greedy restarts of the order search (plan build, untimed)
+
+
 def first_nonzero_slice(key, candidates):
     """The first candidate slice of the 70-qubit plan whose value is not exactly
     zero (found with one split-BF16 contraction each)."""
@@ -162,7 +165,7 @@ def first_nonzero_slice(key, candidates):
 
     lat, circ, bs, spec = synth.config(key)
     plan = qcsim.qc_plan_build(lat.n, circ, bs[0], log2_slices=spec["log2_slices"],
-                               log2_max_entries=spec.get("log2_cap", 0), greedy_trials=8, seed=1)
+                               log2_max_entries=spec.get("log2_cap", 0), greedy_trials=PLAN_TRIALS[key], seed=1)
     k = qcsim.qc_plan_info(plan)["log2_slices"]
     ws = torch.empty(qcsim.qc_workspace_bytes(plan, 1, 1, "split_bf16"), dtype=torch.uint8, device="cuda")
     out = torch.zeros(1, 2, dtype=torch.float64, device="cuda")
@@ -192,7 +195,7 @@ def big_leg(key, precs, reps, s_range, oracle_slices=(), tune=False):
     lat, circ, bs, spec = synth.config(key)
     t0 = time.perf_counter()
     plan = qcsim.qc_plan_build(lat.n, circ, bs[0], log2_slices=spec["log2_slices"],
-                               log2_max_entries=spec.get("log2_cap", 0), greedy_trials=8, seed=1)
+                               log2_max_entries=spec.get("log2_cap", 0), greedy_trials=PLAN_TRIALS[key], seed=1)
     plan_s = time.perf_counter() - t0
     info = qcsim.qc_plan_info(plan)
     k = info["log2_slices"]
@@ -334,7 +337,7 @@ def main():
     torch.cuda.set_device(0)
     t0 = time.perf_counter()
     plan = qcsim.qc_plan_build(lat.n, circ, bs[0], log2_slices=spec["log2_slices"],
-                               log2_max_entries=spec.get("log2_cap", 0), greedy_trials=8, seed=1)
+                               log2_max_entries=spec.get("log2_cap", 0), greedy_trials=PLAN_TRIALS[key], seed=1)
     plan_s = time.perf_counter() - t0
     qcsim.qc_plan_set_exec(plan, args.exec)
     info = qcsim.qc_plan_info(plan)

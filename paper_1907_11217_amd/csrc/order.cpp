@@ -441,9 +441,12 @@ bool search_plan(qc_plan *plan, const qc_slice_spec *spec, std::string &err) {
             r.total = tree_cost(p, r.tree, rm).flops * std::ldexp(1.0, (int)r.sl.size());
         }
     });
-    for (Trial &r : tr) {
+    std::vector<int> ok_trials;
+    for (int t = 0; t < trials; ++t) {
+        Trial &r = tr[t];
         last_ach = std::min(last_ach == 0 ? r.ach : last_ach, r.ach);
         if (!r.ok) { best_ach = std::min(best_ach, r.ach); continue; }
+        ok_trials.push_back(t);
         if (!have || r.sl.size() < best_sliced.size() || (r.sl.size() == best_sliced.size() && r.total < best_total)) {
             have = true; best_total = r.total; best_tree = r.tree; best_sliced = r.sl;
         }
@@ -459,41 +462,66 @@ bool search_plan(qc_plan *plan, const qc_slice_spec *spec, std::string &err) {
                   std::to_string(best_ach);
         return false;
     }
-    // Re-search the order on the sliced network; keep it if it is cheaper
-    // and still within the cap.
-    std::vector<char> rm(p.n_index, 0);
-    for (int e : best_sliced) rm[e] = 1;
-    TreeCost bc = tree_cost(p, best_tree, rm);
-    std::vector<std::pair<std::vector<Merge>, TreeCost>> re(trials);
-    parallel_trials(trials, [&](int t) {
-        re[t].first = greedy_order(p, rm, seed + 0x9000 + 0x1000 * t, t == 0 ? 0.0 : 0.1 + 0.05 * (t % 8));
-        re[t].second = tree_cost(p, re[t].first, rm);
+    // The first-stage cost (unfolded flops of the first order) ranks
+    // candidates only roughly: the best few slice sets with the fewest slices
+    // each go through the re-search of the order on the sliced network and
+    // the constant-first orders, and the one with the least per-slice device
+    // work wins (ties: first in trial order).
+    std::stable_sort(ok_trials.begin(), ok_trials.end(), [&](int x, int y) {
+        if (tr[x].sl.size() != tr[y].sl.size()) return tr[x].sl.size() < tr[y].sl.size();
+        return tr[x].total < tr[y].total;
     });
-    for (auto &r : re)
-        if ((cap <= 0 || r.second.max_log2 <= cap) && r.second.flops < bc.flops) { bc = r.second; best_tree = r.first; }
-    const TreeCost c0 = tree_cost(p, best_tree, std::vector<char>(p.n_index, 0));
-    plan->info.flops_unsliced = c0.flops;
-
-    // Pair-invariant work: a leaf is dynamic if it holds a sliced or an output
-    // segment; every other subtree has the same value for all (slice,
-    // bitstring) pairs.  Try constant-first orders and keep the one with the
-    // least per-pair work, then fold its invariant subtrees on the host.
-    std::vector<char> dyn_leaf(p.leaf_idx.size(), 0);
-    for (size_t t = 0; t < p.leaf_idx.size(); ++t) {
-        for (int e : plan->net.leaves[t].idx)
-            if (plan->net.out_qubit[e] >= 0 || rm[e]) dyn_leaf[t] = 1;
+    const size_t n_cand = std::min<size_t>(ok_trials.size(), 8);
+    double best_score = -1;
+    std::vector<char> best_dyn;
+    for (size_t ci = 0; ci < n_cand; ++ci) {
+        const Trial &cand = tr[ok_trials[ci]];
+        if (cand.sl.size() != tr[ok_trials[0]].sl.size()) break;
+        std::vector<Merge> tree = cand.tree;
+        std::vector<char> rm(p.n_index, 0);
+        for (int e : cand.sl) rm[e] = 1;
+        // Re-search the order on the sliced network; keep it if cheaper and
+        // still within the cap.
+        TreeCost bc = tree_cost(p, tree, rm);
+        std::vector<std::pair<std::vector<Merge>, TreeCost>> re(trials);
+        parallel_trials(trials, [&](int t) {
+            re[t].first = greedy_order(p, rm, seed + 0x9000 + 0x1000 * t + 0x100000 * ci,
+                                       t == 0 ? 0.0 : 0.1 + 0.05 * (t % 8));
+            re[t].second = tree_cost(p, re[t].first, rm);
+        });
+        for (auto &r : re)
+            if ((cap <= 0 || r.second.max_log2 <= cap) && r.second.flops < bc.flops) { bc = r.second; tree = r.first; }
+        // Pair-invariant work: a leaf is dynamic if it holds a sliced or an
+        // output segment; every other subtree has the same value for all
+        // (slice, bitstring) pairs.  Constant-first orders, keeping the one
+        // with the least per-pair work.
+        std::vector<char> dyn_leaf(p.leaf_idx.size(), 0);
+        for (size_t t = 0; t < p.leaf_idx.size(); ++t)
+            for (int e : plan->net.leaves[t].idx)
+                if (plan->net.out_qubit[e] >= 0 || rm[e]) dyn_leaf[t] = 1;
+        double dev = per_pair_flops(p, tree, rm, dyn_leaf);
+        const int const_cap = std::max(4, (int)bc.max_log2);
+        std::vector<std::pair<std::vector<Merge>, double>> ph(trials);
+        parallel_trials(trials, [&](int t) {
+            ph[t].first = greedy_order_phased(p, rm, seed + 0x5000 + 0x1000 * t + 0x100000 * ci,
+                                              t == 0 ? 0.0 : 0.1 + 0.05 * (t % 8), &dyn_leaf, const_cap);
+            const TreeCost c = tree_cost(p, ph[t].first, rm);
+            ph[t].second = (cap > 0 && c.max_log2 > cap) ? -1.0 : per_pair_flops(p, ph[t].first, rm, dyn_leaf);
+        });
+        for (auto &r : ph)
+            if (r.second >= 0 && r.second < dev) { dev = r.second; tree = r.first; }
+        if (best_score < 0 || dev < best_score) {
+            best_score = dev;
+            best_tree = tree;
+            best_sliced = cand.sl;
+            best_dyn = dyn_leaf;
+        }
     }
-    double best_dev = per_pair_flops(p, best_tree, rm, dyn_leaf);
-    const int const_cap = std::max(4, (int)bc.max_log2);
-    std::vector<std::pair<std::vector<Merge>, double>> ph(trials);
-    parallel_trials(trials, [&](int t) {
-        ph[t].first = greedy_order_phased(p, rm, seed + 0x5000 + 0x1000 * t, t == 0 ? 0.0 : 0.1 + 0.05 * (t % 8),
-                                          &dyn_leaf, const_cap);
-        const TreeCost c = tree_cost(p, ph[t].first, rm);
-        ph[t].second = (cap > 0 && c.max_log2 > cap) ? -1.0 : per_pair_flops(p, ph[t].first, rm, dyn_leaf);
-    });
-    for (auto &r : ph)
-        if (r.second >= 0 && r.second < best_dev) { best_dev = r.second; best_tree = r.first; }
+    std::vector<char> dyn_leaf = best_dyn;
+    {
+        const TreeCost c0 = tree_cost(p, best_tree, std::vector<char>(p.n_index, 0));
+        plan->info.flops_unsliced = c0.flops;
+    }
     plan->tree = best_tree;
     plan->sliced = best_sliced;
     fold_invariant_subtrees(plan, dyn_leaf);
