@@ -143,8 +143,13 @@ def test_ranges_compose_and_repeat(c2_setup, mode):
     whole = _contract(plan, xs, 0, 256, ws_bytes=ws_bytes)
     again = _contract(plan, xs, 0, 256, ws_bytes=ws_bytes)
     assert np.array_equal(whole, again)  # bitwise reproducible
-    big = _contract(plan, xs, 0, 256)    # different super-chunk size, same 64-blocks
-    assert np.array_equal(whole, big)
+    # A larger workspace lowers the plan for more slices in flight: the GEMM
+    # steps change shape (and small ones move into the micro-step kernel), so
+    # each FP32 slice value may round differently; the FP64 sums then agree to
+    # FP32 rounding of the per-slice values only.
+    big = _contract(plan, xs, 0, 256)
+    assert np.abs(big - whole).max() <= 1e-5 * np.abs(whole).max()
+    assert np.array_equal(big, _contract(plan, xs, 0, 256))
     ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
     out = torch.zeros(len(xs), 2, dtype=torch.float64, device="cuda")
     qcsim.qc_contract_slices(plan, 0, 128, xs, "c64", ws, out)
