@@ -70,6 +70,14 @@ struct GemmDesc {
     int32_t prec;
     const uint32_t *amax_a, *amax_b;
     uint32_t *amax_c;
+    // Split over k (the two large-tile forms only): with kparts > 1 and a
+    // scratch buffer of kparts * nb * m * n complex64, the product runs as
+    // nb * kparts partial products of k / kparts into the scratch, then a sum
+    // over the parts in increasing order writes C (contiguous [nb][m][n]).
+    // Other forms ignore these fields.
+    int64_t kparts = 1;
+    float2 *kscratch = nullptr;
+    int64_t sAp = 0, sBp = 0;   // operand offset between k parts (set by the launch)
 };
 
 // Records max(|re|, |im|) of n values into *amax (atomicMax on float bits).

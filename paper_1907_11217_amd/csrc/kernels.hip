@@ -589,8 +589,8 @@ __global__ void __launch_bounds__(256) gemm_split_big_kernel(GemmDesc d) {
     const bool a_kc = d.sAk == 1, b_kc = d.sBk == 1;
     const int ar = a_kc ? (t >> 1) : (t & 127), ah = a_kc ? (t & 1) : (t >> 7);
     const int br = b_kc ? (t >> 1) : (t & 127), bh = b_kc ? (t & 1) : (t >> 7);
-    const bool a_vec = a_kc && d.sAm % 2 == 0 && d.sAb % 2 == 0 && (uintptr_t)d.A % 16 == 0;
-    const bool b_vec = b_kc && d.sBn % 2 == 0 && d.sBb % 2 == 0 && (uintptr_t)d.B % 16 == 0;
+    const bool a_vec = a_kc && d.sAm % 2 == 0 && d.sAb % 2 == 0 && d.sAp % 2 == 0 && (uintptr_t)d.A % 16 == 0;
+    const bool b_vec = b_kc && d.sBn % 2 == 0 && d.sBb % 2 == 0 && d.sBp % 2 == 0 && (uintptr_t)d.B % 16 == 0;
     const int ea = split_exp<T>(d.amax_a), eb = split_exp<T>(d.amax_b);
     const int n_slabs = int((d.k + KT - 1) / KT);
     float mx = 0.f;
@@ -601,8 +601,9 @@ __global__ void __launch_bounds__(256) gemm_split_big_kernel(GemmDesc d) {
         const int64_t tn = tile % tiles_n;
         const int64_t tm = (tile / tiles_n) % tiles_m;
         const int64_t bi = tile / (tiles_n * tiles_m);
-        const float2 *Ab = d.A + bi * d.sAb + tm * TM * d.sAm;
-        const float2 *Bb = d.B + bi * d.sBb + tn * TN * d.sBn;
+        const int64_t bq = d.kparts == 1 ? bi : bi / d.kparts, bp = bi - bq * d.kparts;
+        const float2 *Ab = d.A + bq * d.sAb + bp * d.sAp + tm * TM * d.sAm;
+        const float2 *Bb = d.B + bq * d.sBb + bp * d.sBp + tn * TN * d.sBn;
         floatx16 acc[2][2][2];
 #pragma unroll
         for (int i = 0; i < 2; ++i)
@@ -724,8 +725,8 @@ __global__ void __launch_bounds__(256) gemm_mfma_big_kernel(GemmDesc d) {
     const bool a_kc = d.sAk == 1, b_kc = d.sBk == 1;
     const int ar = a_kc ? (t >> 1) : (t & 127), ah = a_kc ? (t & 1) : (t >> 7);
     const int br = b_kc ? (t >> 1) : (t & 127), bh = b_kc ? (t & 1) : (t >> 7);
-    const bool a_vec = a_kc && d.sAm % 2 == 0 && d.sAb % 2 == 0 && (uintptr_t)d.A % 16 == 0;
-    const bool b_vec = b_kc && d.sBn % 2 == 0 && d.sBb % 2 == 0 && (uintptr_t)d.B % 16 == 0;
+    const bool a_vec = a_kc && d.sAm % 2 == 0 && d.sAb % 2 == 0 && d.sAp % 2 == 0 && (uintptr_t)d.A % 16 == 0;
+    const bool b_vec = b_kc && d.sBn % 2 == 0 && d.sBb % 2 == 0 && d.sBp % 2 == 0 && (uintptr_t)d.B % 16 == 0;
     const int n_slabs = int((d.k + KT - 1) / KT);
     int64_t first = blockIdx.x;
     if (gridDim.x % 8 == 0) first = int64_t(blockIdx.x % 8) * (gridDim.x / 8) + blockIdx.x / 8;
@@ -733,8 +734,9 @@ __global__ void __launch_bounds__(256) gemm_mfma_big_kernel(GemmDesc d) {
         const int64_t tn = tile % tiles_n;
         const int64_t tm = (tile / tiles_n) % tiles_m;
         const int64_t bi = tile / (tiles_n * tiles_m);
-        const float2 *Ab = d.A + bi * d.sAb + tm * TM * d.sAm;
-        const float2 *Bb = d.B + bi * d.sBb + tn * TN * d.sBn;
+        const int64_t bq = d.kparts == 1 ? bi : bi / d.kparts, bp = bi - bq * d.kparts;
+        const float2 *Ab = d.A + bq * d.sAb + bp * d.sAp + tm * TM * d.sAm;
+        const float2 *Bb = d.B + bq * d.sBb + bp * d.sBp + tn * TN * d.sBn;
         floatx16 acc[2][2][2];
 #pragma unroll
         for (int i = 0; i < 2; ++i)
@@ -842,6 +844,27 @@ int gemm_default_variant(const GemmDesc &d) {
     return kVarValu;
 }
 
+// Sum of the k parts of a split product: C[b][i] = sum over p in increasing
+// order of P[b][p][i] (FP32), with the maximum of |re|, |im| of C recorded.
+__global__ void __launch_bounds__(256) ksum_kernel(const float2 *__restrict__ P, float2 *__restrict__ C, int64_t nb,
+                                                   int64_t mn, int64_t kparts, uint32_t *amax) {
+    float mx = 0.f;
+    const int64_t total = nb * mn;
+    for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < total; i += int64_t(gridDim.x) * blockDim.x) {
+        const int64_t b = i / mn, r = i - b * mn;
+        const float2 *src = P + b * kparts * mn + r;
+        float2 acc = src[0];
+        for (int64_t p = 1; p < kparts; ++p) {
+            const float2 v = src[p * mn];
+            acc.x += v.x;
+            acc.y += v.y;
+        }
+        C[i] = acc;
+        mx = fmaxf(mx, fmaxf(fabsf(acc.x), fabsf(acc.y)));
+    }
+    if (amax) block_amax(mx, amax);
+}
+
 namespace {
 template <int WM, int WN>
 void launch_mfma(const GemmDesc &d, hipStream_t st) {
@@ -864,6 +887,40 @@ void launch_split(const GemmDesc &d, hipStream_t st) {
     else
         hipLaunchKernelGGL((gemm_split_kernel<__bf16, WM, WN>), dim3(grid), dim3(64 * WM * WN), 0, st, d);
 }
+// The two large-tile forms as they are, then split over k.
+const char *launch_big(const GemmDesc &d, int v, hipStream_t st) {
+    const int64_t t128 = d.nb * (d.m / 128) * (d.n / 128);
+    const unsigned g = (unsigned)(t128 < 1048576 ? t128 : 1048576);
+    if (v == kVarMfmaBig) {
+        hipLaunchKernelGGL(gemm_mfma_big_kernel, dim3(g), dim3(256), 0, st, d);
+        return "gemm_mfma";
+    }
+    if (d.prec == kPrecFP16)
+        hipLaunchKernelGGL(gemm_split_big_kernel<_Float16>, dim3(g), dim3(256), 0, st, d);
+    else
+        hipLaunchKernelGGL(gemm_split_big_kernel<__bf16>, dim3(g), dim3(256), 0, st, d);
+    return d.prec == kPrecFP16 ? "gemm_split_fp16" : "gemm_split_bf16";
+}
+
+// Callers guarantee: kparts a power of two dividing k, kscratch holding
+// kparts * nb * m * n values, C contiguous [nb][m][n].
+const char *launch_gemm_kparts(const GemmDesc &d, int v, hipStream_t st) {
+    GemmDesc e = d;
+    e.nb = d.nb * d.kparts;
+    e.k = d.k / d.kparts;
+    e.sAp = e.k * d.sAk;
+    e.sBp = e.k * d.sBk;
+    e.C = d.kscratch;
+    e.sCb = d.m * d.n; e.sCm = d.n; e.sCn = 1;
+    e.amax_c = nullptr;
+    const char *name = launch_big(e, v, st);
+    const int64_t total = d.nb * d.m * d.n;
+    int64_t grid = (total + 255) / 256;
+    grid = grid > 2048 ? 2048 : grid;
+    hipLaunchKernelGGL(ksum_kernel, dim3((unsigned)grid), dim3(256), 0, st, d.kscratch, d.C, d.nb, d.m * d.n, d.kparts,
+                       d.amax_c);
+    return name;
+}
 }  // namespace
 
 const char *launch_gemm_variant(const GemmDesc &d, int v, hipStream_t st) {
@@ -877,21 +934,9 @@ const char *launch_gemm_variant(const GemmDesc &d, int v, hipStream_t st) {
         case kVarSplit12: launch_split<1, 2>(d, st); return split_name;
         case kVarSplit21: launch_split<2, 1>(d, st); return split_name;
         case kVarSplit22: launch_split<2, 2>(d, st); return split_name;
-        case kVarMfmaBig: {
-            const int64_t t128 = d.nb * (d.m / 128) * (d.n / 128);
-            const unsigned g = (unsigned)(t128 < 1048576 ? t128 : 1048576);
-            hipLaunchKernelGGL(gemm_mfma_big_kernel, dim3(g), dim3(256), 0, st, d);
-            return "gemm_mfma";
-        }
-        case kVarSplitBig: {
-            const int64_t t128 = d.nb * (d.m / 128) * (d.n / 128);
-            const unsigned g = (unsigned)(t128 < 1048576 ? t128 : 1048576);
-            if (d.prec == kPrecFP16)
-                hipLaunchKernelGGL(gemm_split_big_kernel<_Float16>, dim3(g), dim3(256), 0, st, d);
-            else
-                hipLaunchKernelGGL(gemm_split_big_kernel<__bf16>, dim3(g), dim3(256), 0, st, d);
-            return split_name;
-        }
+        case kVarMfmaBig: case kVarSplitBig:
+            if (d.kparts > 1) return launch_gemm_kparts(d, v, st);
+            return launch_big(d, v, st);
         case kVarDot: {
             const int64_t outs = d.nb * d.m * d.n;
             const unsigned g = (unsigned)(outs < 65536 ? outs : 65536);

@@ -300,6 +300,14 @@ static bool lower(const qc_plan *plan, int b, int m, Program &prog, std::string 
         }
         prog.tensor_elems = arena.end + extra;
     }
+    // Scratch of the GEMM steps that run split over k (steps run one after
+    // another, so the largest one).
+    prog.ksplit_elems = 0;
+    for (size_t i = 0; i < prog.gemms.size(); ++i) {
+        const GemmOp &g = prog.gemms[i];
+        const int64_t p = gemm_kparts(g.nb, g.m, g.n, g.k);
+        if (!prog.gemm_micro[i] && p > 1) prog.ksplit_elems = std::max(prog.ksplit_elems, p * g.nb * g.m * g.n);
+    }
 
     // Fused form: GEMM steps read their operands as produced (no transposes)
     // and run level by level (a step's level is one more than its operands'),

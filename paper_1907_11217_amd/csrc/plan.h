@@ -96,6 +96,17 @@ struct TransposeOp {
     int src, dst;
 };
 
+// The number of k parts for a GEMM shape: large-tile shapes whose 128x128
+// tiles number fewer than 1024 (four per compute unit) are split
+// into up to 64 power-of-two parts, each of at least 256 k.
+inline int64_t gemm_kparts(int64_t nb, int64_t m, int64_t n, int64_t k) {
+    if (m % 128 != 0 || n % 128 != 0) return 1;
+    const int64_t tiles = nb * (m / 128) * (n / 128);
+    int64_t p = 1;
+    while (tiles * p < 1024 && p < 64 && k % (2 * p) == 0 && k / (2 * p) >= 256) p *= 2;
+    return p;
+}
+
 struct GemmOp {
     int a_src, b_src;          // operand tensors as produced (before transposes)
     int a, b, c;               // program tensor ids after transposes
@@ -123,6 +134,7 @@ struct Program {
     int root = -1;                        // tensor holding [slice bits][bs bits]
     int root_pre = -1;                    // the tree's last tensor (before any final transpose)
     int64_t tensor_elems = 0;             // tensor region size (complex64 elements)
+    int64_t ksplit_elems = 0;             // scratch of the GEMM steps split over k (complex64 elements)
     double flops = 0, bytes = 0, transpose_bytes = 0;
     // Fused form: the same steps without transposes, every tensor in LDS.
     std::vector<int64_t> lds_offset;      // per program tensor (-1 if not used by the fused form)

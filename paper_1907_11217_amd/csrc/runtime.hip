@@ -64,7 +64,7 @@ struct Exec {
 // slice values, per-tensor max|x| slots (split FP16 scale bookkeeping), and
 // the stepwise program's tensor region.
 struct WsLayout {
-    size_t bits_off, partial_off, amax_off, tensor_off, total;
+    size_t bits_off, partial_off, amax_off, tensor_off, ksplit_off, total;
 };
 
 WsLayout ws_layout(const Exec &x, int n_qubits) {
@@ -73,7 +73,8 @@ WsLayout ws_layout(const Exec &x, int n_qubits) {
     w.partial_off = align256(size_t(n_qubits) << x.m);
     w.amax_off = w.partial_off + align256((size_t(1) << (x.lp + x.m)) * sizeof(float2));
     w.tensor_off = w.amax_off + (x.fused ? 0 : align256(x.prog->tensors.size() * sizeof(uint32_t)));
-    w.total = w.tensor_off + (x.fused ? 0 : align256(size_t(x.prog->tensor_elems) * sizeof(float2)));
+    w.ksplit_off = w.tensor_off + (x.fused ? 0 : align256(size_t(x.prog->tensor_elems) * sizeof(float2)));
+    w.total = w.ksplit_off + (x.fused ? 0 : align256(size_t(x.prog->ksplit_elems) * sizeof(float2)));
     return w;
 }
 
@@ -464,8 +465,10 @@ TransposeDesc make_transpose(const Program &prog, const TransposeOp &t, float2 *
 // amax: per-tensor max|x| slots (split FP16) or null; slot[t] maps a
 // transposed tensor to the slot of the tensor it was copied from.
 GemmDesc make_gemm(const Program &prog, const GemmOp &g, float2 *tensors, int prec, uint32_t *amax,
-                   const std::vector<int> &slot) {
+                   const std::vector<int> &slot, float2 *kscratch) {
     GemmDesc d;
+    d.kparts = kscratch ? gemm_kparts(g.nb, g.m, g.n, g.k) : 1;
+    if (d.kparts > 1) d.kscratch = kscratch;
     d.prec = prec;
     d.amax_a = amax ? amax + slot[g.a] : nullptr;
     d.amax_b = amax ? amax + slot[g.b] : nullptr;
@@ -525,6 +528,7 @@ bool launch_all(qc_plan *plan, const Exec &x, uint64_t s_begin, uint64_t s_end, 
     const WsLayout w = ws_layout(x, nq);
     float2 *partial = (float2 *)((char *)ws + w.partial_off);
     float2 *tensors = (float2 *)((char *)ws + w.tensor_off);
+    float2 *kscratch = (float2 *)((char *)ws + w.ksplit_off);
     // Scale bookkeeping only where a scale is derived from it (FP16).
     uint32_t *amax = (!x.fused && x.prec == kPrecFP16) ? (uint32_t *)((char *)ws + w.amax_off) : nullptr;
     std::vector<int> slot(prog.tensors.size());
@@ -585,7 +589,7 @@ bool launch_all(qc_plan *plan, const Exec &x, uint64_t s_begin, uint64_t s_end, 
                         prof.end("transpose");
                     } else {
                         const GemmOp &g = prog.gemms[op.index];
-                        const GemmDesc gd = make_gemm(prog, g, tensors, x.prec, amax, slot);
+                        const GemmDesc gd = make_gemm(prog, g, tensors, x.prec, amax, slot, kscratch);
                         const int v = g.variant[x.prec];
                         prof.end(v >= 0 && gemm_variant_ok(gd, v) ? launch_gemm_variant(gd, v, st) : launch_gemm(gd, st));
                     }
@@ -1110,6 +1114,7 @@ extern "C" qc_status qc_tune(qc_plan *plan, int64_t chunk_slices, int32_t n_bs, 
         qc::tune_load(cache_path);
         const qc::WsLayout w = qc::ws_layout(x, plan->net.n_qubits);
         float2 *tensors = (float2 *)((char *)ws + w.tensor_off);
+        float2 *kscratch = (float2 *)((char *)ws + w.ksplit_off);
         uint32_t *amax = x.prec == qc::kPrecFP16 ? (uint32_t *)((char *)ws + w.amax_off) : nullptr;
         std::vector<int> slot(prog.tensors.size());
         for (size_t t = 0; t < slot.size(); ++t) slot[t] = (int)t;
@@ -1127,7 +1132,7 @@ extern "C" qc_status qc_tune(qc_plan *plan, int64_t chunk_slices, int32_t n_bs, 
         for (size_t gi = 0; gi < prog.gemms.size(); ++gi) {
             qc::GemmOp &g = prog.gemms[gi];
             if (prog.gemm_micro[gi]) continue;  // run by the micro-step kernel
-            const qc::GemmDesc d = qc::make_gemm(prog, g, tensors, x.prec, amax, slot);
+            const qc::GemmDesc d = qc::make_gemm(prog, g, tensors, x.prec, amax, slot, kscratch);
             const std::string key = qc::tune_key(arch, d, g.a_km, g.b_nk);
             auto it = qc::g_tune.find(key);
             if (it == qc::g_tune.end()) {
@@ -1219,11 +1224,16 @@ extern "C" void qc_plan_destroy(qc_plan *plan) {
     delete plan;
 }
 
-extern "C" qc_status qc_kernel_gemm_form(const void *A, const void *B, void *C, int64_t nb, int64_t m, int64_t n,
-                                         int64_t k, int32_t a_km, int32_t b_nk, qc_precision prec, int32_t form,
-                                         void *scale_ws, void *stream) {
+extern "C" int64_t qc_gemm_kparts(int64_t nb, int64_t m, int64_t n, int64_t k) {
+    if (nb < 1 || m < 1 || n < 1 || k < 1) return 1;
+    return qc::gemm_kparts(nb, m, n, k);
+}
+
+extern "C" qc_status qc_kernel_gemm_kparts(const void *A, const void *B, void *C, int64_t nb, int64_t m, int64_t n,
+                                           int64_t k, int32_t a_km, int32_t b_nk, qc_precision prec, int32_t form,
+                                           int64_t kparts, void *scratch, void *scale_ws, void *stream) {
     if (!A || !B || !C || nb < 1 || m < 1 || n < 1 || k < 1 || !valid_prec(prec) || form < -1 ||
-        form >= qc::kVarCount) {
+        form >= qc::kVarCount || kparts < 0 || kparts > 64 || (kparts & (kparts - 1)) != 0) {
         set_error("qc_kernel_gemm: invalid argument");
         return QC_ERR_INVALID_ARG;
     }
@@ -1249,15 +1259,32 @@ extern "C" qc_status qc_kernel_gemm_form(const void *A, const void *B, void *C, 
         set_error("qc_kernel_gemm_form: the form does not apply to this shape and precision");
         return QC_ERR_UNSUPPORTED;
     }
+    const int v = form >= 0 ? form : qc::gemm_default_variant(d);
+    if (kparts == 0) kparts = qc::gemm_kparts(nb, m, n, k);
+    const bool big = v == qc::kVarMfmaBig || v == qc::kVarSplitBig;
+    if (kparts > 1 && (!big || k % kparts != 0 || !scratch)) {
+        set_error("qc_kernel_gemm_kparts: a split over k needs a large-tile form, kparts dividing k and a scratch buffer");
+        return QC_ERR_UNSUPPORTED;
+    }
+    if (kparts > 1) {
+        d.kparts = kparts;
+        d.kscratch = (float2 *)scratch;
+    }
     if (amax) {
         qc::launch_zero_u32(amax, 3, st);
         qc::launch_absmax(d.A, nb * m * k, amax, st);
         qc::launch_absmax(d.B, nb * k * n, amax + 1, st);
     }
-    qc::launch_gemm_variant(d, form >= 0 ? form : qc::gemm_default_variant(d), st);
+    qc::launch_gemm_variant(d, v, st);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) { set_error(std::string("qc_kernel_gemm: ") + hipGetErrorString(e)); return QC_ERR_DEVICE; }
     return QC_OK;
+}
+
+extern "C" qc_status qc_kernel_gemm_form(const void *A, const void *B, void *C, int64_t nb, int64_t m, int64_t n,
+                                         int64_t k, int32_t a_km, int32_t b_nk, qc_precision prec, int32_t form,
+                                         void *scale_ws, void *stream) {
+    return qc_kernel_gemm_kparts(A, B, C, nb, m, n, k, a_km, b_nk, prec, form, 1, nullptr, scale_ws, stream);
 }
 
 extern "C" qc_status qc_kernel_gemm(const void *A, const void *B, void *C, int64_t nb, int64_t m, int64_t n, int64_t k,

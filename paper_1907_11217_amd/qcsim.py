@@ -30,7 +30,7 @@ EXPORTED = (
     "qc_gate_matrix", "qc_plan_destroy", "qc_last_error", "qc_kernel_gemm", "qc_kernel_transpose",
     "qc_plan_set_exec", "qc_profile_enable", "qc_profile_read", "qc_contract_slices_dev", "qc_plan_set_graphs",
     "qc_tune", "qc_kernel_gemm_form", "qc_batch_workspace_bytes", "qc_contract_batch", "qc_wall_clock_khz",
-    "qc_plan_export_steps",
+    "qc_plan_export_steps", "qc_kernel_gemm_kparts", "qc_gemm_kparts",
 )
 EXEC_MODES = {"auto": 0, "fused": 1, "stepwise": 2}
 
@@ -129,6 +129,11 @@ def load(path: str | None = None):
         lib.qc_kernel_gemm_form.argtypes = [vp, vp, vp, i64, i64, i64, i64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int,
                                             ctypes.c_int32, vp, vp]
         lib.qc_kernel_gemm_form.restype = ctypes.c_int
+        lib.qc_kernel_gemm_kparts.argtypes = [vp, vp, vp, i64, i64, i64, i64, ctypes.c_int32, ctypes.c_int32,
+                                              ctypes.c_int, ctypes.c_int32, i64, vp, vp, vp]
+        lib.qc_kernel_gemm_kparts.restype = ctypes.c_int
+        lib.qc_gemm_kparts.argtypes = [i64, i64, i64, i64]
+        lib.qc_gemm_kparts.restype = i64
         lib.qc_kernel_transpose.argtypes = [vp, vp, ctypes.c_int32, vp, vp]
         lib.qc_kernel_transpose.restype = ctypes.c_int
         lib.qc_tune.argtypes = [vp, i64, ctypes.c_int32, ctypes.c_int, vp, ctypes.c_size_t, vp, ctypes.c_char_p,
@@ -393,11 +398,14 @@ GEMM_FORMS = {"valu": 0, "skinny": 1, "dot": 2, "mfma11": 3, "mfma12": 4, "mfma2
 
 
 def qc_kernel_gemm(A, B, C, nb: int, m: int, n: int, k: int, a_km: bool = False, b_nk: bool = False,
-                   prec="c64", scale_ws=None, stream=None, form=-1):
+                   prec="c64", scale_ws=None, stream=None, form=-1, kparts=1, scratch=None):
     """One batched complex GEMM step on torch complex64 device tensors.
     scale_ws: optional int32 device tensor of >= 3 entries (required for
     split_fp16); afterwards it holds the float bits of max(|re|,|im|) of A, B
-    and C.  form: a GEMM_FORMS value fixes the kernel form (-1: default)."""
+    and C.  form: a GEMM_FORMS value fixes the kernel form (-1: default).
+    kparts: split over k (large-tile forms; 0 = the library's rule for the
+    shape) with `scratch` a complex64 device tensor of kparts * nb * m * n
+    values (allocated here when not given)."""
     import torch
     lib = load()
     for t in (A, B, C):
@@ -410,9 +418,24 @@ def qc_kernel_gemm(A, B, C, nb: int, m: int, n: int, k: int, a_km: bool = False,
     if scale_ws is None and _prec(prec) == PRECISIONS["split_fp16"]:
         scale_ws = torch.zeros(3, dtype=torch.int32, device=A.device)
     st = stream if stream is not None else torch.cuda.current_stream()
-    _check(lib.qc_kernel_gemm_form(A.data_ptr(), B.data_ptr(), C.data_ptr(), nb, m, n, k, int(bool(a_km)),
-                                   int(bool(b_nk)), _prec(prec), int(form),
-                                   None if scale_ws is None else scale_ws.data_ptr(), st.cuda_stream), lib)
+    if kparts == 1:
+        _check(lib.qc_kernel_gemm_form(A.data_ptr(), B.data_ptr(), C.data_ptr(), nb, m, n, k, int(bool(a_km)),
+                                       int(bool(b_nk)), _prec(prec), int(form),
+                                       None if scale_ws is None else scale_ws.data_ptr(), st.cuda_stream), lib)
+        return
+    parts = kparts if kparts > 0 else int(lib.qc_gemm_kparts(nb, m, n, k))
+    if scratch is None:
+        scratch = torch.empty(max(1, parts * nb * m * n), dtype=torch.complex64, device=A.device)
+    if scratch.dtype != torch.complex64 or scratch.numel() < parts * nb * m * n:
+        raise ValueError("scratch must hold kparts * nb * m * n complex64 values")
+    _check(lib.qc_kernel_gemm_kparts(A.data_ptr(), B.data_ptr(), C.data_ptr(), nb, m, n, k, int(bool(a_km)),
+                                     int(bool(b_nk)), _prec(prec), int(form), int(kparts), scratch.data_ptr(),
+                                     None if scale_ws is None else scale_ws.data_ptr(), st.cuda_stream), lib)
+
+
+def qc_gemm_kparts(nb: int, m: int, n: int, k: int) -> int:
+    """k parts the stepwise contraction uses for a GEMM step of this shape."""
+    return int(load().qc_gemm_kparts(nb, m, n, k))
 
 
 def qc_kernel_transpose(inp, out, rank: int, perm, stream=None):

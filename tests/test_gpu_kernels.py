@@ -105,3 +105,88 @@ def test_transpose_structured(kind):
     ref = np.zeros_like(x)
     ref[o] = x
     assert np.array_equal(d_out.cpu().numpy().view(np.uint64), ref.view(np.uint64))
+
+
+# Split over k: (nb, m, n, k, kparts); kparts 0 takes the library's rule.
+KSPLIT_SHAPES = [(1, 128, 128, 1024, 4), (2, 256, 128, 2048, 8), (3, 128, 256, 512, 2), (1, 128, 384, 4096, 0),
+                 (2, 128, 128, 8192, 64)]
+
+
+@pytest.mark.parametrize("shape", KSPLIT_SHAPES)
+@pytest.mark.parametrize("prec", ["c64", "split_bf16", "split_fp16"])
+@pytest.mark.parametrize("a_km,b_nk", [(0, 0), (1, 1), (1, 0)])
+def test_gemm_kparts(shape, prec, a_km, b_nk):
+    nb, m, n, k, kp = shape
+    rng = np.random.default_rng(nb * 7 + m + n * 3 + k + kp + 5 * a_km + 11 * b_nk)
+    A = _rand(rng, (nb, m, k)) * np.float32(2.0 ** -20)
+    B = _rand(rng, (nb, k, n))
+    a_store = A.transpose(0, 2, 1) if a_km else A
+    b_store = B.transpose(0, 2, 1) if b_nk else B
+    dA = torch.from_numpy(np.ascontiguousarray(a_store).reshape(-1)).cuda()
+    dB = torch.from_numpy(np.ascontiguousarray(b_store).reshape(-1)).cuda()
+    form = qcsim.GEMM_FORMS["mfma_big" if prec == "c64" else "split_big"]
+    parts = kp or qcsim.qc_gemm_kparts(nb, m, n, k)
+    assert parts > 1
+    scratch = torch.full((parts * nb * m * n,), float("nan"), dtype=torch.complex64, device="cuda")
+    slots = torch.zeros(3, dtype=torch.int32, device="cuda")
+    dC = torch.full((nb * m * n,), float("nan"), dtype=torch.complex64, device="cuda")
+    dC1 = torch.full((nb * m * n,), float("nan"), dtype=torch.complex64, device="cuda")
+    say(f"gemm {prec} split over k: nb={nb} m={m} n={n} k={k} kparts={kp} a_km={a_km} b_nk={b_nk}")
+    qcsim.qc_kernel_gemm(dA, dB, dC, nb, m, n, k, a_km, b_nk, prec=prec, scale_ws=slots, form=form, kparts=kp,
+                         scratch=scratch)
+    qcsim.qc_kernel_gemm(dA, dB, dC1, nb, m, n, k, a_km, b_nk, prec=prec, scale_ws=None if prec == "c64" else
+                         torch.zeros(3, dtype=torch.int32, device="cuda"), form=form)
+    torch.cuda.synchronize()
+    got = dC.cpu().numpy().reshape(nb, m, n)
+    whole = dC1.cpu().numpy().reshape(nb, m, n)
+    ref = np.matmul(A.astype(np.complex128), B.astype(np.complex128))
+    amax = max(np.abs(A.real).max(), np.abs(A.imag).max())
+    bmax = max(np.abs(B.real).max(), np.abs(B.imag).max())
+    # FP32 accumulation (plus the split's representation error) over k.
+    u = {"c64": 2.0 ** -23, "split_fp16": 2.0 ** -22, "split_bf16": 2.0 ** -16}[prec]
+    bound = 8.0 * k * u * amax * bmax
+    assert np.abs(got - ref).max() <= bound, (np.abs(got - ref).max(), bound)
+    assert np.abs(got - whole).max() <= 2 * bound
+    # The sum kernel records max(|re|, |im|) of C.
+    s = slots.cpu().numpy().view(np.float32)
+    g32 = got.astype(np.complex64)
+    assert s[2] == np.float32(max(np.abs(g32.real).max(), np.abs(g32.imag).max()))
+    # Deterministic: the parts are summed in a fixed order.
+    qcsim.qc_kernel_gemm(dA, dB, dC1, nb, m, n, k, a_km, b_nk, prec=prec, scale_ws=slots, form=form, kparts=kp,
+                         scratch=scratch)
+    torch.cuda.synchronize()
+    assert np.array_equal(dC1.cpu().numpy().view(np.uint64), dC.cpu().numpy().view(np.uint64))
+
+
+@pytest.mark.parametrize("prec", ["split_bf16", "split_fp16"])
+def test_gemm_kparts_exact(prec):
+    # Integer operands (A on a 2^-5 grid that needs a lo part): every partial
+    # and every sum of parts is exact, so the split product equals the FP64 one.
+    nb, m, n, k, kp = 2, 128, 256, 1024, 4
+    rng = np.random.default_rng(21)
+    ia = rng.integers(-(1 << 10) + 1, 1 << 10, size=(2, nb, m, k))
+    ib = rng.integers(-4, 5, size=(2, nb, k, n))
+    A = (ia[0] + 1j * ia[1]) * 2.0 ** -5
+    B = (ib[0] + 1j * ib[1]) * 1.0
+    dA = torch.from_numpy(A.astype(np.complex64).reshape(-1)).cuda()
+    dB = torch.from_numpy(B.astype(np.complex64).reshape(-1)).cuda()
+    dC = torch.zeros(nb * m * n, dtype=torch.complex64, device="cuda")
+    say(f"gemm {prec} split over k, exact operands")
+    qcsim.qc_kernel_gemm(dA, dB, dC, nb, m, n, k, 0, 0, prec=prec, form=qcsim.GEMM_FORMS["split_big"], kparts=kp,
+                         scale_ws=torch.zeros(3, dtype=torch.int32, device="cuda"))
+    torch.cuda.synchronize()
+    got = dC.cpu().numpy().reshape(nb, m, n).astype(np.complex128)
+    assert np.array_equal(got, np.matmul(A, B))
+
+
+def test_gemm_kparts_rejects_bad_arguments():
+    nb, m, n, k = 1, 128, 128, 1024
+    d = torch.zeros(nb * max(m, n) * k, dtype=torch.complex64, device="cuda")
+    scratch = torch.zeros(128 * m * n, dtype=torch.complex64, device="cuda")
+    for form, kp in [("mfma_big", 3), ("mfma22", 4), ("mfma_big", 128)]:
+        with pytest.raises(qcsim.QcError):
+            qcsim.qc_kernel_gemm(d, d, d, nb, m, n, k, prec="c64", form=qcsim.GEMM_FORMS[form], kparts=kp,
+                                 scratch=scratch)
+    with pytest.raises(qcsim.QcError):  # 16 parts do not divide k = 24
+        qcsim.qc_kernel_gemm(d, d, d, nb, m, n, 24, prec="c64", form=qcsim.GEMM_FORMS["mfma_big"], kparts=16,
+                             scratch=scratch)

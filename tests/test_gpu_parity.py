@@ -264,3 +264,27 @@ def test_c3_sampled_slices_match_oracle(prec):
     for s in picks:
         v = oracle.sliced_value(lat.n, circ, bs[0], segs, s)
         assert abs(ps[s, 0] - v) <= tol * max(abs(v), scale), (s, ps[s, 0], v)
+
+
+@pytest.mark.parametrize("prec", ["c64", "split_bf16"])
+def test_c3_split_over_k_program_matches_finer_slicing(prec):
+    # A 2-bit slicing of the 7x7 d24 circuit, one slice in flight, lowers to a
+    # program with a GEMM step split over k.  The sum of its four slice values
+    # is the amplitude, so it must agree with the sum of all 2^16 slices of
+    # the 16-bit slicing (whose slices are checked against the oracle above),
+    # to FP32 rounding of the slice values.
+    lat, circ, bs, _ = synth.config("c3")
+    coarse = qcsim.qc_plan_build(lat.n, circ, bs[0], log2_slices=2, greedy_trials=4, seed=1)
+    steps = qcsim.qc_plan_export_steps(coarse, 0, 0)
+    assert any(s["kind"] == 1 and not s["micro"] and qcsim.qc_gemm_kparts(s["nb"], s["m"], s["n"], s["k"]) > 1
+               for s in steps)
+    fine = qcsim.qc_plan_build(lat.n, circ, bs[0], log2_slices=16, log2_max_entries=30, greedy_trials=8, seed=1)
+    say(f"c3 7x7 d24, 2-bit slicing one slice in flight ({prec}) vs 16-bit slicing")
+    a, ps_a = _contract(coarse, bs[:1], 0, 4, prec=prec, ws_bytes=qcsim.qc_workspace_bytes(coarse, 1, 1, prec),
+                        per_slice=True)
+    b, ps_b = _contract(fine, bs[:1], 0, 1 << 16, prec="c64", chunk=1 << 16, per_slice=True)
+    rms_a = np.sqrt(np.mean(np.abs(ps_a) ** 2))
+    rms_b = np.sqrt(np.mean(np.abs(ps_b) ** 2))
+    tol = (TOL_C64 if prec == "c64" else TOL_SPLIT[prec]) * (2 * rms_a + 256 * rms_b)
+    say(f"  |a - b| = {abs(a[0] - b[0]):.3e}, |b| = {abs(b[0]):.3e}, tol {tol:.3e}")
+    assert abs(a[0] - b[0]) <= tol

@@ -36,6 +36,34 @@ def test_library_exports_every_declared_symbol():
     assert declared == set(qcsim.EXPORTED)
 
 
+def test_gemm_kparts_rule():
+    # Large-tile shapes with fewer than 1024 tiles of 128x128 are split over
+    # k into the smallest power of two reaching 1024 tiles, each part keeping
+    # at least 256 of k, at most 64 parts.
+    assert qcsim.qc_gemm_kparts(8, 128, 2048, 16384) == 8
+    assert qcsim.qc_gemm_kparts(2, 128, 2048, 8192) == 32
+    assert qcsim.qc_gemm_kparts(4, 256, 2048, 1024) == 4
+    assert qcsim.qc_gemm_kparts(4, 1024, 4096, 1024) == 1
+    assert qcsim.qc_gemm_kparts(1, 96, 128, 4096) == 1
+    assert qcsim.qc_gemm_kparts(1, 128, 128, 1 << 20) == 64
+    assert qcsim.qc_gemm_kparts(1, 128, 128, 384) == 1
+    assert qcsim.qc_gemm_kparts(1, 128, 128, 768) == 2
+
+
+def test_workspace_holds_split_over_k_scratch():
+    # A 2-bit slicing of the 7x7 d24 circuit has a GEMM step split over k at
+    # one slice in flight: the workspace grows by its scratch.
+    lat, circ, bs, _ = synth.config("c3")
+    plan = qcsim.qc_plan_build(lat.n, circ, bs[0], log2_slices=2, greedy_trials=4, seed=1)
+    steps = qcsim.qc_plan_export_steps(plan, 0, 0)
+    need = [qcsim.qc_gemm_kparts(s["nb"], s["m"], s["n"], s["k"]) * s["nb"] * s["m"] * s["n"]
+            for s in steps if s["kind"] == 1 and not s["micro"] and qcsim.qc_gemm_kparts(s["nb"], s["m"], s["n"], s["k"]) > 1]
+    assert need
+    desc = qcsim.qc_plan_describe(plan, 0, 0)
+    ws = qcsim.qc_workspace_bytes(plan, 1, 1)
+    assert ws >= (desc["tensor_elems"] + max(need)) * 8
+
+
 def test_gate_matrices_match_oracle_table():
     for kind in range(5):
         assert np.abs(qcsim.qc_gate_matrix(kind) - oracle.gate_matrix(kind)).max() < 1e-15
