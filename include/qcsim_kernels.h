@@ -54,25 +54,27 @@ qc_status qc_kernel_gemm_form(const void *A, const void *B, void *C, int64_t nb,
                               void *stream);
 
 /* qc_kernel_gemm_form split over k, as the stepwise contraction runs its
- * GEMM steps with few output tiles: the large-tile forms (7 and 12) compute
- * kparts partial products, part p over l in [p k/kparts, (p+1) k/kparts),
- * into `scratch`, then C = the parts summed in increasing p, in FP32 (so the
- * result is deterministic).  scratch: caller-owned device buffer of kparts *
- * nb * m * n complex64, contents afterwards unspecified.  kparts: a power of
- * two dividing k, at most 64; 0 takes qc_gemm_kparts(nb, m, n, k); 1 is
- * qc_kernel_gemm_form (scratch may then be NULL).  QC_ERR_UNSUPPORTED when
- * kparts > 1 and the form (given, or the default) is not a large-tile one,
- * kparts does not divide k, or scratch is NULL. */
+ * GEMM steps with few outputs: the large-tile forms (7, 12) and the dot form
+ * (2) compute kparts partial products, part p over l in [p k/kparts,
+ * (p+1) k/kparts), into `scratch`, then C = the parts summed in increasing p,
+ * in FP32 (so the result is deterministic).  scratch: caller-owned device
+ * buffer of kparts * nb * m * n complex64, contents afterwards unspecified.
+ * kparts: a power of two dividing k, at most 1024; 0 takes
+ * qc_gemm_kparts(nb, m, n, k); 1 is qc_kernel_gemm_form (scratch may then be
+ * NULL).  QC_ERR_UNSUPPORTED when kparts > 1 and the form (given, or the
+ * default) is none of these three, kparts does not divide k, or scratch is
+ * NULL. */
 qc_status qc_kernel_gemm_kparts(const void *A, const void *B, void *C, int64_t nb, int64_t m, int64_t n, int64_t k,
                                 int32_t a_km, int32_t b_nk, qc_precision prec, int32_t form, int64_t kparts,
                                 void *scratch, void *scale_ws, void *stream);
 
 /* The number of k parts the stepwise contraction uses for a GEMM step of this
- * shape when it runs a large-tile form: 1 unless m and n are multiples of 128
- * and the step has fewer than 1024 tiles of 128x128; then the smallest power
- * of two p <= 64 with at least 1024 tiles times p, while each part keeps at
- * least 256 of k.  The scratch for the largest such step is part of
- * qc_workspace_bytes. */
+ * shape when it runs a form that splits: for m and n multiples of 128 with
+ * fewer than 1024 tiles of 128x128, the smallest power of two p <= 64 with at
+ * least 1024 tiles times p, while each part keeps at least 256 of k; for at
+ * most 4096 outputs and k >= 8192, the smallest power of two p with at least
+ * 1024 outputs times p, while each part keeps at least 4096 of k; else 1.
+ * The scratch for the largest such step is part of qc_workspace_bytes. */
 int64_t qc_gemm_kparts(int64_t nb, int64_t m, int64_t n, int64_t k);
 
 /* Bit-permuting transpose of a rank-r tensor (2^r complex64 values): the

@@ -70,7 +70,7 @@ struct GemmDesc {
     int32_t prec;
     const uint32_t *amax_a, *amax_b;
     uint32_t *amax_c;
-    // Split over k (the two large-tile forms only): with kparts > 1 and a
+    // Split over k (the large-tile and dot forms only): with kparts > 1 and a
     // scratch buffer of kparts * nb * m * n complex64, the product runs as
     // nb * kparts partial products of k / kparts into the scratch, then a sum
     // over the parts in increasing order writes C (contiguous [nb][m][n]).
@@ -147,10 +147,14 @@ struct MicroStep {
     int32_t rc, rk, out0, amax_slot;         // out0: first flat output of this step in its level
     int32_t sa[kMicroRank], sb[kMicroRank], ka[kMicroRank], kb[kMicroRank];
 };
-// Runs the levels of micro steps in order with one workgroup (a barrier
-// between levels); amax (or null) as for the GEMM epilogues.
-void launch_micro(const MicroStep *steps, const int32_t *level_start, const int32_t *level_outs, int n_levels,
-                  float2 *tensors, uint32_t *amax, hipStream_t st);
+// Micro steps in groups of independent subtrees, one workgroup per group:
+// group g runs levels [group_start[g], group_start[g + 1]) in order (a
+// barrier between levels), level l holds steps [level_start[l],
+// level_start[l + 1]) with level_outs[l] outputs in all; amax (or null) as
+// for the GEMM epilogues.
+constexpr int kMicroGroups = 1024;
+void launch_micro(const MicroStep *steps, const int32_t *group_start, const int32_t *level_start,
+                  const int32_t *level_outs, int n_groups, float2 *tensors, uint32_t *amax, hipStream_t st);
 
 // Device descriptor of one request of a fused batch (one bitstring).  Its
 // slice values go to partial[partial_off + (s - s_base)], s_base = s_begin

@@ -106,18 +106,22 @@ void launch_zero_u32(uint32_t *p, int64_t n, hipStream_t st) {
 }
 
 // -------------------------------------------------------------- micro steps
-// All small GEMM steps of a stepwise program in one launch: levels in order,
-// the outputs of a level spread over the workgroup (steps of a level read
-// only lower levels), the operands read in the layouts their producers wrote.
+// All small GEMM steps of a stepwise program in one launch: each workgroup
+// runs one group of independent subtrees, its levels in order, the outputs of
+// a level spread over the workgroup (steps of a level read only lower levels
+// of the same subtree), the operands read in the layouts their producers
+// wrote.  Every output is computed by one thread in a fixed order, so the
+// result does not depend on the grouping.
 __global__ void __launch_bounds__(1024) micro_kernel(const MicroStep *__restrict__ steps,
+                                                     const int32_t *__restrict__ group_start,
                                                      const int32_t *__restrict__ level_start,
-                                                     const int32_t *__restrict__ level_outs, int n_levels,
-                                                     float2 *tensors, uint32_t *amax) {
+                                                     const int32_t *__restrict__ level_outs, float2 *tensors,
+                                                     uint32_t *amax) {
     // Per-step maxima of a level gather in LDS first (one global atomic per
     // step); a level with more steps than fit uses global atomics directly.
     constexpr int kSlots = 1024;
     __shared__ uint32_t lmax[kSlots];
-    for (int lv = 0; lv < n_levels; ++lv) {
+    for (int lv = group_start[blockIdx.x]; lv < group_start[blockIdx.x + 1]; ++lv) {
         const int s0 = level_start[lv], s1 = level_start[lv + 1];
         const bool local = amax && s1 - s0 <= kSlots;
         if (local) {
@@ -156,11 +160,11 @@ __global__ void __launch_bounds__(1024) micro_kernel(const MicroStep *__restrict
     }
 }
 
-void launch_micro(const MicroStep *steps, const int32_t *level_start, const int32_t *level_outs, int n_levels,
-                  float2 *tensors, uint32_t *amax, hipStream_t st) {
-    if (n_levels <= 0) return;
-    hipLaunchKernelGGL(micro_kernel, dim3(1), dim3(1024), 0, st, steps, level_start, level_outs, n_levels, tensors,
-                       amax);
+void launch_micro(const MicroStep *steps, const int32_t *group_start, const int32_t *level_start,
+                  const int32_t *level_outs, int n_groups, float2 *tensors, uint32_t *amax, hipStream_t st) {
+    if (n_groups <= 0) return;
+    hipLaunchKernelGGL(micro_kernel, dim3(n_groups), dim3(1024), 0, st, steps, group_start, level_start, level_outs,
+                       tensors, amax);
 }
 
 // --------------------------------------------------------------- transpose
@@ -299,15 +303,17 @@ __global__ void __launch_bounds__(256) gemm_skinny_kernel(GemmDesc d) {
 // Dot form for a few outputs with a long k (the last steps of a tree often
 // contract two large tensors to a handful of values): one workgroup of 1024
 // threads per output, k strided over the threads (coalesced), then a fixed
-// LDS tree, so the result does not depend on the launch.
+// LDS tree, so the result does not depend on the launch.  Split over k, each
+// workgroup takes one part of one output.
 __global__ void __launch_bounds__(1024) gemm_dot_kernel(GemmDesc d) {
     __shared__ float2 part[1024];
     const int64_t total = d.nb * d.m * d.n;
     float mx = 0.f;
     for (int64_t o = blockIdx.x; o < total; o += gridDim.x) {
         const int64_t j = o % d.n, i = (o / d.n) % d.m, bi = o / (d.n * d.m);
-        const float2 *a = d.A + bi * d.sAb + i * d.sAm;
-        const float2 *b = d.B + bi * d.sBb + j * d.sBn;
+        const int64_t bq = d.kparts == 1 ? bi : bi / d.kparts, bp = bi - bq * d.kparts;
+        const float2 *a = d.A + bq * d.sAb + bp * d.sAp + i * d.sAm;
+        const float2 *b = d.B + bq * d.sBb + bp * d.sBp + j * d.sBn;
         float re = 0.f, im = 0.f;
         for (int64_t l = threadIdx.x; l < d.k; l += blockDim.x) {
             const float2 x = a[l * d.sAk], y = b[l * d.sBk];
@@ -887,8 +893,19 @@ void launch_split(const GemmDesc &d, hipStream_t st) {
     else
         hipLaunchKernelGGL((gemm_split_kernel<__bf16, WM, WN>), dim3(grid), dim3(64 * WM * WN), 0, st, d);
 }
-// The two large-tile forms as they are, then split over k.
+void launch_dot(const GemmDesc &d, hipStream_t st) {
+    const int64_t outs = d.nb * d.m * d.n;
+    const unsigned g = (unsigned)(outs < 65536 ? outs : 65536);
+    hipLaunchKernelGGL(gemm_dot_kernel, dim3(g), dim3(1024), 0, st, d);
+}
+
+// The forms that can run split over k (large-tile and dot) as they are, then
+// split over k.
 const char *launch_big(const GemmDesc &d, int v, hipStream_t st) {
+    if (v == kVarDot) {
+        launch_dot(d, st);
+        return "gemm_dot";
+    }
     const int64_t t128 = d.nb * (d.m / 128) * (d.n / 128);
     const unsigned g = (unsigned)(t128 < 1048576 ? t128 : 1048576);
     if (v == kVarMfmaBig) {
@@ -937,12 +954,10 @@ const char *launch_gemm_variant(const GemmDesc &d, int v, hipStream_t st) {
         case kVarMfmaBig: case kVarSplitBig:
             if (d.kparts > 1) return launch_gemm_kparts(d, v, st);
             return launch_big(d, v, st);
-        case kVarDot: {
-            const int64_t outs = d.nb * d.m * d.n;
-            const unsigned g = (unsigned)(outs < 65536 ? outs : 65536);
-            hipLaunchKernelGGL(gemm_dot_kernel, dim3(g), dim3(1024), 0, st, d);
+        case kVarDot:
+            if (d.kparts > 1) return launch_gemm_kparts(d, v, st);
+            launch_dot(d, st);
             return "gemm_dot";
-        }
         case kVarSkinny: {
             // Fewer workgroups when each folds a maximum into one slot.
             const int64_t blocks = d.nb * ((d.n + 255) / 256), cap = d.amax_c ? 2048 : 8192;

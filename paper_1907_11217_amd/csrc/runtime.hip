@@ -227,9 +227,20 @@ bool ensure_device(const qc_plan *plan, Program &prog, bool fused, std::string &
             !upload(&prog.d_leaf_desc, descs.data(), descs.size() * sizeof(LeafDesc), err))
             return false;
         prog.n_leaf_blocks = (int)blocks.size();
-        // Micro steps, grouped by level (leaves are level 0).
-        std::vector<int> lvl(prog.tensors.size(), 0);
-        std::vector<std::vector<MicroStep>> by_level;
+        // Micro steps.  They form independent subtrees (a micro step reads
+        // leaves and outputs of micro steps only); each subtree runs in a
+        // workgroup of its own, level by level (leaves are level 0).  With
+        // more subtrees than kMicroGroups, subtrees are dealt to groups by
+        // decreasing work, each to the least loaded group.
+        std::vector<int> lvl(prog.tensors.size(), 0), comp_of(prog.tensors.size(), -1);
+        std::vector<int> parent;  // union-find over subtrees
+        auto find = [&](int x) {
+            while (parent[x] != x) x = parent[x] = parent[parent[x]];
+            return x;
+        };
+        std::vector<MicroStep> all;
+        std::vector<int> all_lv, all_comp;
+        std::vector<double> all_work;
         for (size_t i = 0; i < prog.ops.size(); ++i) {
             if (prog.op_micro.empty() || !prog.op_micro[i] || prog.ops[i].kind != Op::GEMM) continue;
             const GemmOp &g = prog.gemms[prog.ops[i].index];
@@ -237,6 +248,18 @@ bool ensure_device(const qc_plan *plan, Program &prog, bool fused, std::string &
             const auto &LC = prog.tensors[g.c].layout;
             const int lv = 1 + std::max(lvl[g.a_src], lvl[g.b_src]);
             lvl[g.c] = lv;
+            int c = -1;
+            for (int src : {g.a_src, g.b_src}) {
+                if (comp_of[src] < 0) continue;
+                const int r = find(comp_of[src]);
+                if (c < 0) c = r;
+                else if (r != c) parent[r] = c;
+            }
+            if (c < 0) {
+                c = (int)parent.size();
+                parent.push_back(c);
+            }
+            comp_of[g.c] = c;
             MicroStep M;
             std::memset(&M, 0, sizeof(M));
             M.a = prog.tensors[g.a_src].offset;
@@ -261,21 +284,69 @@ bool ensure_device(const qc_plan *plan, Program &prog, bool fused, std::string &
                 M.ka[q] = stride_in(LA, ks[q]);
                 M.kb[q] = stride_in(LB, ks[q]);
             }
-            if ((int)by_level.size() < lv) by_level.resize(lv);
-            by_level[lv - 1].push_back(M);
+            all.push_back(M);
+            all_lv.push_back(lv);
+            all_comp.push_back(c);
+            all_work.push_back(std::ldexp(1.0, M.rc + M.rk));
         }
+        // Subtree -> group.
+        std::vector<int> root_id(parent.size(), -1);
+        std::vector<double> comp_work;
+        for (size_t i = 0; i < all.size(); ++i) {
+            int &r = root_id[find(all_comp[i])];
+            if (r < 0) { r = (int)comp_work.size(); comp_work.push_back(0.0); }
+            comp_work[r] += all_work[i];
+        }
+        const int n_comp = (int)comp_work.size();
+        const int n_groups = std::min(n_comp, kMicroGroups);
+        std::vector<int> group_of_comp(n_comp);
+        {
+            std::vector<int> order(n_comp);
+            for (int i = 0; i < n_comp; ++i) order[i] = i;
+            std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return comp_work[x] > comp_work[y]; });
+            std::vector<double> load(n_groups, 0.0);
+            for (int c : order) {
+                const int gi = int(std::min_element(load.begin(), load.end()) - load.begin());
+                group_of_comp[c] = gi;
+                load[gi] += comp_work[c];
+            }
+        }
+        // Steps ordered by (group, level, program order); one level entry per
+        // (group, level) pair.
+        std::vector<int> idx(all.size());
+        for (size_t i = 0; i < idx.size(); ++i) idx[i] = (int)i;
+        auto grp = [&](int i) { return group_of_comp[root_id[find(all_comp[i])]]; };
+        std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) {
+            return grp(x) != grp(y) ? grp(x) < grp(y) : all_lv[x] < all_lv[y];
+        });
         std::vector<MicroStep> steps;
-        std::vector<int32_t> starts(1, 0), outs;
-        for (auto &v : by_level) {
-            int32_t o = 0;
-            for (MicroStep &M : v) { M.out0 = o; o += 1 << M.rc; steps.push_back(M); }
-            starts.push_back((int32_t)steps.size());
-            outs.push_back(o);
+        std::vector<int32_t> group_start(1, 0), starts(1, 0), outs;
+        for (size_t j = 0; j < idx.size(); ++j) {
+            const int i = idx[j];
+            const bool new_group = j == 0 || grp(i) != grp(idx[j - 1]);
+            const bool new_level = new_group || all_lv[i] != all_lv[idx[j - 1]];
+            if (j > 0 && new_level) {
+                starts.push_back((int32_t)steps.size());
+                if (new_group) group_start.push_back((int32_t)outs.size());
+            }
+            if (new_level) outs.push_back(0);
+            MicroStep M = all[i];
+            M.out0 = outs.back();
+            outs.back() += 1 << M.rc;
+            steps.push_back(M);
         }
-        prog.n_micro_levels = (int)by_level.size();
+        if (!steps.empty()) {
+            starts.push_back((int32_t)steps.size());
+            group_start.push_back((int32_t)outs.size());
+        }
+        prog.n_micro_levels = (int)outs.size();
+        prog.n_micro_groups = (int)group_start.size() - 1;
         if (prog.n_micro_levels > 0) {
-            std::vector<int32_t> lv_tab(starts);
-            lv_tab.insert(lv_tab.end(), outs.begin(), outs.end());  // starts (n+1) then outs (n)
+            // Table: group starts (G + 1 level entries), level starts (L + 1
+            // steps), outputs per level (L).
+            std::vector<int32_t> lv_tab(group_start);
+            lv_tab.insert(lv_tab.end(), starts.begin(), starts.end());
+            lv_tab.insert(lv_tab.end(), outs.begin(), outs.end());
             if (!upload(&prog.d_micro, steps.data(), steps.size() * sizeof(MicroStep), err) ||
                 !upload(&prog.d_micro_levels, lv_tab.data(), lv_tab.size() * 4, err))
                 return false;
@@ -576,8 +647,9 @@ bool launch_all(qc_plan *plan, const Exec &x, uint64_t s_begin, uint64_t s_end, 
                 if (prog.n_micro_levels > 0) {
                     const int32_t *lt = (const int32_t *)prog.d_micro_levels;
                     prof.begin();
-                    launch_micro((const MicroStep *)prog.d_micro, lt, lt + prog.n_micro_levels + 1,
-                                 prog.n_micro_levels, tensors, amax, st);
+                    const int32_t *ls = lt + prog.n_micro_groups + 1;
+                    launch_micro((const MicroStep *)prog.d_micro, lt, ls, ls + prog.n_micro_levels + 1,
+                                 prog.n_micro_groups, tensors, amax, st);
                     prof.end("micro");
                 }
                 for (size_t oi = 0; oi < prog.ops.size(); ++oi) {
@@ -1233,7 +1305,7 @@ extern "C" qc_status qc_kernel_gemm_kparts(const void *A, const void *B, void *C
                                            int64_t k, int32_t a_km, int32_t b_nk, qc_precision prec, int32_t form,
                                            int64_t kparts, void *scratch, void *scale_ws, void *stream) {
     if (!A || !B || !C || nb < 1 || m < 1 || n < 1 || k < 1 || !valid_prec(prec) || form < -1 ||
-        form >= qc::kVarCount || kparts < 0 || kparts > 64 || (kparts & (kparts - 1)) != 0) {
+        form >= qc::kVarCount || kparts < 0 || kparts > 1024 || (kparts & (kparts - 1)) != 0) {
         set_error("qc_kernel_gemm: invalid argument");
         return QC_ERR_INVALID_ARG;
     }
@@ -1261,9 +1333,10 @@ extern "C" qc_status qc_kernel_gemm_kparts(const void *A, const void *B, void *C
     }
     const int v = form >= 0 ? form : qc::gemm_default_variant(d);
     if (kparts == 0) kparts = qc::gemm_kparts(nb, m, n, k);
-    const bool big = v == qc::kVarMfmaBig || v == qc::kVarSplitBig;
-    if (kparts > 1 && (!big || k % kparts != 0 || !scratch)) {
-        set_error("qc_kernel_gemm_kparts: a split over k needs a large-tile form, kparts dividing k and a scratch buffer");
+    const bool splits = v == qc::kVarMfmaBig || v == qc::kVarSplitBig || v == qc::kVarDot;
+    if (kparts > 1 && (!splits || k % kparts != 0 || !scratch)) {
+        set_error("qc_kernel_gemm_kparts: a split over k needs a large-tile or dot form, kparts dividing k and a "
+                  "scratch buffer");
         return QC_ERR_UNSUPPORTED;
     }
     if (kparts > 1) {

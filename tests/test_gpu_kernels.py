@@ -183,10 +183,40 @@ def test_gemm_kparts_rejects_bad_arguments():
     nb, m, n, k = 1, 128, 128, 1024
     d = torch.zeros(nb * max(m, n) * k, dtype=torch.complex64, device="cuda")
     scratch = torch.zeros(128 * m * n, dtype=torch.complex64, device="cuda")
-    for form, kp in [("mfma_big", 3), ("mfma22", 4), ("mfma_big", 128)]:
+    for form, kp in [("mfma_big", 3), ("mfma22", 4), ("valu", 2)]:
         with pytest.raises(qcsim.QcError):
             qcsim.qc_kernel_gemm(d, d, d, nb, m, n, k, prec="c64", form=qcsim.GEMM_FORMS[form], kparts=kp,
                                  scratch=scratch)
     with pytest.raises(qcsim.QcError):  # 16 parts do not divide k = 24
         qcsim.qc_kernel_gemm(d, d, d, nb, m, n, 24, prec="c64", form=qcsim.GEMM_FORMS["mfma_big"], kparts=16,
                              scratch=scratch)
+
+
+@pytest.mark.parametrize("shape", [(1, 1, 1, 1 << 20, 0), (2, 2, 2, 65536, 0), (1, 1, 3, 16384, 4), (3, 1, 1, 8192, 2)])
+@pytest.mark.parametrize("a_km,b_nk", [(0, 0), (1, 1)])
+def test_gemm_dot_kparts(shape, a_km, b_nk):
+    nb, m, n, k, kp = shape
+    rng = np.random.default_rng(k + nb + 3 * m + 5 * n + kp + a_km)
+    A = _rand(rng, (nb, m, k))
+    B = _rand(rng, (nb, k, n))
+    a_store = A.transpose(0, 2, 1) if a_km else A
+    b_store = B.transpose(0, 2, 1) if b_nk else B
+    dA = torch.from_numpy(np.ascontiguousarray(a_store).reshape(-1)).cuda()
+    dB = torch.from_numpy(np.ascontiguousarray(b_store).reshape(-1)).cuda()
+    dC = torch.full((nb * m * n,), float("nan"), dtype=torch.complex64, device="cuda")
+    parts = kp or qcsim.qc_gemm_kparts(nb, m, n, k)
+    assert parts > 1
+    say(f"gemm dot split over k: nb={nb} m={m} n={n} k={k} kparts={parts} a_km={a_km} b_nk={b_nk}")
+    qcsim.qc_kernel_gemm(dA, dB, dC, nb, m, n, k, a_km, b_nk, form=qcsim.GEMM_FORMS["dot"], kparts=kp)
+    torch.cuda.synchronize()
+    got = dC.cpu().numpy().reshape(nb, m, n)
+    ref = np.matmul(A.astype(np.complex128), B.astype(np.complex128))
+    # FP32 sums of k unit-variance products: error ~ sqrt(k) u per part tree.
+    assert np.abs(got - ref).max() <= 64 * 2.0 ** -23 * k, np.abs(got - ref).max()
+
+
+def test_gemm_kparts_limit():
+    nb, m, n, k = 1, 1, 1, 1 << 22
+    d = torch.zeros(k, dtype=torch.complex64, device="cuda")
+    with pytest.raises((qcsim.QcError, ValueError)):  # at most 1024 parts
+        qcsim.qc_kernel_gemm(d, d, d, nb, m, n, k, form=qcsim.GEMM_FORMS["dot"], kparts=2048)

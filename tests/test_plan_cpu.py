@@ -48,6 +48,12 @@ def test_gemm_kparts_rule():
     assert qcsim.qc_gemm_kparts(1, 128, 128, 1 << 20) == 64
     assert qcsim.qc_gemm_kparts(1, 128, 128, 384) == 1
     assert qcsim.qc_gemm_kparts(1, 128, 128, 768) == 2
+    # Few outputs with a long k (the dot form): 1024 (output, part) pairs,
+    # each part at least 4096 of k.
+    assert qcsim.qc_gemm_kparts(1, 1, 1, 1 << 21) == 512
+    assert qcsim.qc_gemm_kparts(4, 8, 8, 16384) == 4
+    assert qcsim.qc_gemm_kparts(1, 1, 1, 4096) == 1
+    assert qcsim.qc_gemm_kparts(1, 64, 128, 1 << 20) == 1
 
 
 def test_workspace_holds_split_over_k_scratch():
