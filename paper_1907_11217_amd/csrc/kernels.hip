@@ -252,49 +252,84 @@ __global__ void __launch_bounds__(256) gemm_valu_kernel(GemmDesc d) {
 }
 
 // Skinny form for m <= 16 with a wide n (a small tensor applied to a large
-// one, HBM-bound): one thread per column j of C reads B[b][:, j] once
-// (coalesced when n is B's fast axis) and keeps all m outputs of the column
-// in registers; A's m x k values are the same for every thread of the block.
+// one, HBM-bound): each thread owns two adjacent columns of C and reads
+// B[b][:, j..j+1] once (16-byte loads, coalesced when n is B's fast axis),
+// keeping all m outputs of both columns in registers; A's m x k values are
+// staged in LDS as [k][m] (up to 32 KB per pass over k) and read as
+// broadcasts.  Sums run over k in increasing order.
 template <int M>
 __global__ void __launch_bounds__(256) gemm_skinny_kernel(GemmDesc d) {
-    const int64_t chunks = (d.n + 255) / 256;
+    constexpr int KC = 4096 / M;
+    __shared__ float2 As[KC * M];
+    const int64_t chunks = (d.n + 511) / 512;
     const int64_t total = d.nb * chunks;
+    const bool bvec = d.sBn == 1 && d.sBk % 2 == 0 && d.sBb % 2 == 0 && (uintptr_t)d.B % 16 == 0;
+    const bool cvec = d.sCn == 1 && d.sCm % 2 == 0 && d.sCb % 2 == 0 && (uintptr_t)d.C % 16 == 0;
     float mx = 0.f;
     for (int64_t blk = blockIdx.x; blk < total; blk += gridDim.x) {
         const int64_t bi = blk / chunks;
-        const int64_t j = (blk % chunks) * 256 + threadIdx.x;
-        const bool ok = j < d.n;
+        const int64_t j0 = (blk % chunks) * 512 + 2 * threadIdx.x;
+        const bool ok0 = j0 < d.n, ok1 = j0 + 1 < d.n;
         const float2 *Ab = d.A + bi * d.sAb;
-        const float2 *Bb = d.B + bi * d.sBb + (ok ? j : 0) * d.sBn;
-        float re[M], im[M];
+        const float2 *Bb = d.B + bi * d.sBb;
+        float re0[M], im0[M], re1[M], im1[M];
 #pragma unroll
-        for (int i = 0; i < M; ++i) { re[i] = 0.f; im[i] = 0.f; }
-        // Eight loads of B in flight before their arithmetic.
-        for (int64_t l0 = 0; l0 < d.k; l0 += 8) {
-            float2 y[8];
+        for (int i = 0; i < M; ++i) { re0[i] = 0.f; im0[i] = 0.f; re1[i] = 0.f; im1[i] = 0.f; }
+        for (int64_t k0 = 0; k0 < d.k; k0 += KC) {
+            const int kc = int(d.k - k0 < KC ? d.k - k0 : KC);
+            __syncthreads();
+            for (int e = threadIdx.x; e < kc * M; e += blockDim.x) {
+                const int l = e / M, i = e - l * M;
+                As[e] = Ab[i * d.sAm + (k0 + l) * d.sAk];
+            }
+            __syncthreads();
+            for (int l0 = 0; l0 < kc; l0 += 8) {
+                float2 y0[8], y1[8];
 #pragma unroll
-            for (int u = 0; u < 8; ++u)
-                y[u] = (ok && l0 + u < d.k) ? Bb[(l0 + u) * d.sBk] : make_float2(0.f, 0.f);
+                for (int u = 0; u < 8; ++u) {
+                    const int64_t l = k0 + l0 + u;
+                    y0[u] = make_float2(0.f, 0.f);
+                    y1[u] = make_float2(0.f, 0.f);
+                    if (l0 + u < kc) {
+                        if (bvec && ok1) {
+                            const float4 w = *(const float4 *)(Bb + l * d.sBk + j0);
+                            y0[u] = make_float2(w.x, w.y);
+                            y1[u] = make_float2(w.z, w.w);
+                        } else {
+                            if (ok0) y0[u] = Bb[l * d.sBk + j0 * d.sBn];
+                            if (ok1) y1[u] = Bb[l * d.sBk + (j0 + 1) * d.sBn];
+                        }
+                    }
+                }
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                if (l0 + u >= d.k) break;
+                for (int u = 0; u < 8; ++u) {
+                    if (l0 + u >= kc) break;
 #pragma unroll
-                for (int i = 0; i < M; ++i) {
-                    const float2 x = Ab[i * d.sAm + (l0 + u) * d.sAk];
-                    re[i] = fmaf(x.x, y[u].x, re[i]);
-                    re[i] = fmaf(-x.y, y[u].y, re[i]);
-                    im[i] = fmaf(x.x, y[u].y, im[i]);
-                    im[i] = fmaf(x.y, y[u].x, im[i]);
+                    for (int i = 0; i < M; ++i) {
+                        const float2 x = As[(l0 + u) * M + i];
+                        re0[i] = fmaf(x.x, y0[u].x, re0[i]);
+                        re0[i] = fmaf(-x.y, y0[u].y, re0[i]);
+                        im0[i] = fmaf(x.x, y0[u].y, im0[i]);
+                        im0[i] = fmaf(x.y, y0[u].x, im0[i]);
+                        re1[i] = fmaf(x.x, y1[u].x, re1[i]);
+                        re1[i] = fmaf(-x.y, y1[u].y, re1[i]);
+                        im1[i] = fmaf(x.x, y1[u].y, im1[i]);
+                        im1[i] = fmaf(x.y, y1[u].x, im1[i]);
+                    }
                 }
             }
         }
-        if (ok) {
-            float2 *Cb = d.C + bi * d.sCb + j * d.sCn;
+        float2 *Cb = d.C + bi * d.sCb;
 #pragma unroll
-            for (int i = 0; i < M; ++i) {
-                Cb[i * d.sCm] = make_float2(re[i], im[i]);
-                mx = fmaxf(mx, fmaxf(fabsf(re[i]), fabsf(im[i])));
+        for (int i = 0; i < M; ++i) {
+            if (cvec && ok1) {
+                *(float4 *)(Cb + i * d.sCm + j0) = make_float4(re0[i], im0[i], re1[i], im1[i]);
+            } else {
+                if (ok0) Cb[i * d.sCm + j0 * d.sCn] = make_float2(re0[i], im0[i]);
+                if (ok1) Cb[i * d.sCm + (j0 + 1) * d.sCn] = make_float2(re1[i], im1[i]);
             }
+            if (ok0) mx = fmaxf(mx, fmaxf(fabsf(re0[i]), fabsf(im0[i])));
+            if (ok1) mx = fmaxf(mx, fmaxf(fabsf(re1[i]), fabsf(im1[i])));
         }
     }
     if (d.amax_c) block_amax(mx, d.amax_c);
@@ -960,7 +995,7 @@ const char *launch_gemm_variant(const GemmDesc &d, int v, hipStream_t st) {
             return "gemm_dot";
         case kVarSkinny: {
             // Fewer workgroups when each folds a maximum into one slot.
-            const int64_t blocks = d.nb * ((d.n + 255) / 256), cap = d.amax_c ? 2048 : 8192;
+            const int64_t blocks = d.nb * ((d.n + 511) / 512), cap = d.amax_c ? 2048 : 8192;
             const unsigned g = (unsigned)(blocks < cap ? blocks : cap);
             switch (d.m) {
                 case 1: hipLaunchKernelGGL(gemm_skinny_kernel<1>, dim3(g), dim3(256), 0, st, d); break;
