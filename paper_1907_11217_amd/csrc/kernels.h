@@ -59,6 +59,7 @@ struct TransposeDesc {
 // kernel that wrote it); a kernel that writes C with amax_c set folds its
 // outputs in with atomicMax.
 enum GemmPrec { kPrecC64 = 0, kPrecBF16 = 1, kPrecFP16 = 2 };
+constexpr int kGemmMaxBits = 40;
 struct GemmDesc {
     const float2 *A;
     const float2 *B;
@@ -73,11 +74,18 @@ struct GemmDesc {
     // Split over k (the large-tile and dot forms only): with kparts > 1 and a
     // scratch buffer of kparts * nb * m * n complex64, the product runs as
     // nb * kparts partial products of k / kparts into the scratch, then a sum
-    // over the parts in increasing order writes C (contiguous [nb][m][n]).
+    // over the parts in increasing order writes C.
     // Other forms ignore these fields.
     int64_t kparts = 1;
     float2 *kscratch = nullptr;
     int64_t sAp = 0, sBp = 0;   // operand offset between k parts (set by the launch)
+    // Output scatter (cscatter = 1; nb, m, n powers of two): element (b, i, j)
+    // of C has the flat index f = (b m + i) n + j, whose bits (cbn bits of j
+    // least significant, then cbm of i, then cbb of b) go to bit positions
+    // cpos[t] of the element's offset in C.  The strides sC* are then unused.
+    int32_t cscatter = 0;
+    int32_t cbb = 0, cbm = 0, cbn = 0;
+    int8_t cpos[kGemmMaxBits] = {};
 };
 
 // Records max(|re|, |im|) of n values into *amax (atomicMax on float bits).

@@ -105,6 +105,57 @@ void launch_zero_u32(uint32_t *p, int64_t n, hipStream_t st) {
     hipLaunchKernelGGL(zero_u32_kernel, dim3((unsigned)grid), dim3(256), 0, st, p, n);
 }
 
+// ------------------------------------------------------ GEMM output address
+// Offset of the bits [first, first + nbits) of C's flat index, given as the
+// value v of that bit group, under the output scatter (uniform loop: the
+// positions are kernel arguments).
+__device__ __forceinline__ int64_t scat_bits(const GemmDesc &d, uint64_t v, int first, int nbits) {
+    int64_t o = 0;
+    for (int t = 0; t < nbits; ++t) o += int64_t((v >> t) & 1) << d.cpos[first + t];
+    return o;
+}
+
+// Offset of element (b, i, j) of C.
+__device__ __forceinline__ int64_t c_off(const GemmDesc &d, int64_t bi, int64_t i, int64_t j) {
+    if (!d.cscatter) return bi * d.sCb + i * d.sCm + j * d.sCn;
+    return scat_bits(d, uint64_t(j), 0, d.cbn) + scat_bits(d, uint64_t(i), d.cbn, d.cbm) +
+           scat_bits(d, uint64_t(bi), d.cbn + d.cbm, d.cbb);
+}
+
+// Addresses of a 32x32 MFMA output block with corner (row0, col0), both
+// multiples of 32: accumulator entry v of a lane is row row0 + (v >> 2) * 8 +
+// (lane >> 5) * 4 + (v & 3), column col0 + (lane & 31).  p is the lane's
+// address for v = 0; the offsets of row bits 0, 1, 3 and 4 give the rest.
+struct CBlock {
+    float2 *p;
+    int64_t r0, r1, r3, r4;
+};
+
+__device__ __forceinline__ CBlock c_block(const GemmDesc &d, int64_t bi, int64_t row0, int64_t col0, int lane) {
+    CBlock o;
+    if (!d.cscatter) {
+        o.p = d.C + bi * d.sCb + (row0 + (lane >> 5) * 4) * d.sCm + (col0 + (lane & 31)) * d.sCn;
+        o.r0 = d.sCm;
+        o.r1 = 2 * d.sCm;
+        o.r3 = 8 * d.sCm;
+        o.r4 = 16 * d.sCm;
+    } else {
+        const int fm = d.cbn, fb = d.cbn + d.cbm;
+        o.p = d.C + scat_bits(d, uint64_t(bi), fb, d.cbb) + scat_bits(d, uint64_t(row0), fm, d.cbm) +
+              scat_bits(d, uint64_t(col0), 0, d.cbn) + scat_bits(d, uint64_t(lane & 31), 0, 5) +
+              (int64_t(lane >> 5) << d.cpos[fm + 2]);
+        o.r0 = int64_t(1) << d.cpos[fm];
+        o.r1 = int64_t(1) << d.cpos[fm + 1];
+        o.r3 = int64_t(1) << d.cpos[fm + 3];
+        o.r4 = int64_t(1) << d.cpos[fm + 4];
+    }
+    return o;
+}
+
+__device__ __forceinline__ float2 *c_at(const CBlock &o, int v) {
+    return o.p + ((v & 1) ? o.r0 : 0) + ((v & 2) ? o.r1 : 0) + ((v & 4) ? o.r3 : 0) + ((v & 8) ? o.r4 : 0);
+}
+
 // -------------------------------------------------------------- micro steps
 // All small GEMM steps of a stepwise program in one launch: each workgroup
 // runs one group of independent subtrees, its levels in order, the outputs of
@@ -245,7 +296,7 @@ __global__ void __launch_bounds__(256) gemm_valu_kernel(GemmDesc d) {
             im = fmaf(x.x, y.y, im);
             im = fmaf(x.y, y.x, im);
         }
-        d.C[bi * d.sCb + mi * d.sCm + ni * d.sCn] = make_float2(re, im);
+        d.C[c_off(d, bi, mi, ni)] = make_float2(re, im);
         mx = fmaxf(mx, fmaxf(fabsf(re), fabsf(im)));
     }
     if (d.amax_c) block_amax(mx, d.amax_c);
@@ -264,7 +315,7 @@ __global__ void __launch_bounds__(256) gemm_skinny_kernel(GemmDesc d) {
     const int64_t chunks = (d.n + 511) / 512;
     const int64_t total = d.nb * chunks;
     const bool bvec = d.sBn == 1 && d.sBk % 2 == 0 && d.sBb % 2 == 0 && (uintptr_t)d.B % 16 == 0;
-    const bool cvec = d.sCn == 1 && d.sCm % 2 == 0 && d.sCb % 2 == 0 && (uintptr_t)d.C % 16 == 0;
+    const bool cvec = !d.cscatter && d.sCn == 1 && d.sCm % 2 == 0 && d.sCb % 2 == 0 && (uintptr_t)d.C % 16 == 0;
     float mx = 0.f;
     for (int64_t blk = blockIdx.x; blk < total; blk += gridDim.x) {
         const int64_t bi = blk / chunks;
@@ -320,13 +371,20 @@ __global__ void __launch_bounds__(256) gemm_skinny_kernel(GemmDesc d) {
             }
         }
         float2 *Cb = d.C + bi * d.sCb;
+        int64_t o0 = j0 * d.sCn, o1 = (j0 + 1) * d.sCn;
+        if (d.cscatter) {
+            Cb = d.C + scat_bits(d, uint64_t(bi), d.cbn + d.cbm, d.cbb);
+            o0 = scat_bits(d, uint64_t(j0), 0, d.cbn);
+            o1 = scat_bits(d, uint64_t(j0 + 1), 0, d.cbn);
+        }
 #pragma unroll
         for (int i = 0; i < M; ++i) {
             if (cvec && ok1) {
                 *(float4 *)(Cb + i * d.sCm + j0) = make_float4(re0[i], im0[i], re1[i], im1[i]);
             } else {
-                if (ok0) Cb[i * d.sCm + j0 * d.sCn] = make_float2(re0[i], im0[i]);
-                if (ok1) Cb[i * d.sCm + (j0 + 1) * d.sCn] = make_float2(re1[i], im1[i]);
+                const int64_t oi = d.cscatter ? scat_bits(d, uint64_t(i), d.cbn, d.cbm) : i * d.sCm;
+                if (ok0) Cb[oi + o0] = make_float2(re0[i], im0[i]);
+                if (ok1) Cb[oi + o1] = make_float2(re1[i], im1[i]);
             }
             if (ok0) mx = fmaxf(mx, fmaxf(fabsf(re0[i]), fabsf(im0[i])));
             if (ok1) mx = fmaxf(mx, fmaxf(fabsf(re1[i]), fabsf(im1[i])));
@@ -368,7 +426,7 @@ __global__ void __launch_bounds__(1024) gemm_dot_kernel(GemmDesc d) {
         }
         if (threadIdx.x == 0) {
             const float2 r = part[0];
-            d.C[bi * d.sCb + i * d.sCm + j * d.sCn] = r;
+            d.C[c_off(d, bi, i, j)] = r;
             mx = fmaxf(mx, fmaxf(fabsf(r.x), fabsf(r.y)));
         }
         __syncthreads();
@@ -435,13 +493,9 @@ __global__ void __launch_bounds__(64 * WM * WN) gemm_mfma_kernel(GemmDesc d) {
             }
             __syncthreads();
         }
-        float2 *Cb = d.C + bi * d.sCb + (tm * TM + wm * 32) * d.sCm + (tn * TN + wn * 32) * d.sCn;
+        const CBlock cb = c_block(d, bi, tm * TM + wm * 32, tn * TN + wn * 32, lane);
 #pragma unroll
-        for (int v = 0; v < 16; ++v) {
-            const int row = (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
-            const int col = lane & 31;
-            Cb[row * d.sCm + col * d.sCn] = make_float2(acc_re[v], acc_im[v]);
-        }
+        for (int v = 0; v < 16; ++v) *c_at(cb, v) = make_float2(acc_re[v], acc_im[v]);
     }
 }
 
@@ -550,13 +604,11 @@ __global__ void __launch_bounds__(64 * WM * WN) gemm_split_kernel(GemmDesc d) {
             acc_im = mfma16(ail, brh, acc_im);
             __syncthreads();
         }
-        float2 *Cb = d.C + bi * d.sCb + (tm * TM + wm * 32) * d.sCm + (tn * TN + wn * 32) * d.sCn;
+        const CBlock cb = c_block(d, bi, tm * TM + wm * 32, tn * TN + wn * 32, lane);
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
-            const int row = (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
-            const int col = lane & 31;
             const float re = ldexpf(acc_re[v], ea + eb), im = ldexpf(acc_im[v], ea + eb);
-            Cb[row * d.sCm + col * d.sCn] = make_float2(re, im);
+            *c_at(cb, v) = make_float2(re, im);
             mx = fmaxf(mx, fmaxf(fabsf(re), fabsf(im)));
         }
     }
@@ -730,13 +782,11 @@ __global__ void __launch_bounds__(256) gemm_split_big_kernel(GemmDesc d) {
         for (int i = 0; i < 2; ++i)
 #pragma unroll
             for (int j = 0; j < 2; ++j) {
-                float2 *Cb = d.C + bi * d.sCb + (tm * TM + wm * 64 + i * 32) * d.sCm + (tn * TN + wn * 64 + j * 32) * d.sCn;
+                const CBlock cb = c_block(d, bi, tm * TM + wm * 64 + i * 32, tn * TN + wn * 64 + j * 32, lane);
 #pragma unroll
                 for (int v = 0; v < 16; ++v) {
-                    const int row = (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
-                    const int col = lane & 31;
                     const float re = ldexpf(acc[i][j][0][v], ea + eb), im = ldexpf(acc[i][j][1][v], ea + eb);
-                    Cb[row * d.sCm + col * d.sCn] = make_float2(re, im);
+                    *c_at(cb, v) = make_float2(re, im);
                     mx = fmaxf(mx, fmaxf(fabsf(re), fabsf(im)));
                 }
             }
@@ -832,12 +882,9 @@ __global__ void __launch_bounds__(256) gemm_mfma_big_kernel(GemmDesc d) {
         for (int i = 0; i < 2; ++i)
 #pragma unroll
             for (int j = 0; j < 2; ++j) {
-                float2 *Cb = d.C + bi * d.sCb + (tm * TM + wm * 64 + i * 32) * d.sCm + (tn * TN + wn * 64 + j * 32) * d.sCn;
+                const CBlock cb = c_block(d, bi, tm * TM + wm * 64 + i * 32, tn * TN + wn * 64 + j * 32, lane);
 #pragma unroll
-                for (int v = 0; v < 16; ++v) {
-                    const int row = (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
-                    Cb[row * d.sCm + (lane & 31) * d.sCn] = make_float2(acc[i][j][0][v], acc[i][j][1][v]);
-                }
+                for (int v = 0; v < 16; ++v) *c_at(cb, v) = make_float2(acc[i][j][0][v], acc[i][j][1][v]);
             }
     }
 }
@@ -885,25 +932,26 @@ int gemm_default_variant(const GemmDesc &d) {
     return kVarValu;
 }
 
-// Sum of the k parts of a split product: C[b][i] = sum over p in increasing
-// order of P[b][p][i] (FP32), with the maximum of |re|, |im| of C recorded.
-__global__ void __launch_bounds__(256) ksum_kernel(const float2 *__restrict__ P, float2 *__restrict__ C, int64_t nb,
-                                                   int64_t mn, int64_t kparts, uint32_t *amax) {
+// Sum of the k parts of a split product: element (b, i, j) of C = sum over p
+// in increasing order of the parts' values (FP32), read from the scratch
+// P[b][p][i][j]; the maximum of |re|, |im| of C is recorded.
+__global__ void __launch_bounds__(256) ksum_kernel(GemmDesc d) {
     float mx = 0.f;
-    const int64_t total = nb * mn;
-    for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < total; i += int64_t(gridDim.x) * blockDim.x) {
-        const int64_t b = i / mn, r = i - b * mn;
-        const float2 *src = P + b * kparts * mn + r;
+    const int64_t mn = d.m * d.n, total = d.nb * mn;
+    for (int64_t f = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; f < total; f += int64_t(gridDim.x) * blockDim.x) {
+        const int64_t b = f / mn, r = f - b * mn;
+        const float2 *src = d.kscratch + b * d.kparts * mn + r;
         float2 acc = src[0];
-        for (int64_t p = 1; p < kparts; ++p) {
+        for (int64_t p = 1; p < d.kparts; ++p) {
             const float2 v = src[p * mn];
             acc.x += v.x;
             acc.y += v.y;
         }
-        C[i] = acc;
+        const int64_t i = r / d.n;
+        d.C[c_off(d, b, i, r - i * d.n)] = acc;
         mx = fmaxf(mx, fmaxf(fabsf(acc.x), fabsf(acc.y)));
     }
-    if (amax) block_amax(mx, amax);
+    if (d.amax_c) block_amax(mx, d.amax_c);
 }
 
 namespace {
@@ -955,7 +1003,7 @@ const char *launch_big(const GemmDesc &d, int v, hipStream_t st) {
 }
 
 // Callers guarantee: kparts a power of two dividing k, kscratch holding
-// kparts * nb * m * n values, C contiguous [nb][m][n].
+// kparts * nb * m * n values.
 const char *launch_gemm_kparts(const GemmDesc &d, int v, hipStream_t st) {
     GemmDesc e = d;
     e.nb = d.nb * d.kparts;
@@ -964,13 +1012,13 @@ const char *launch_gemm_kparts(const GemmDesc &d, int v, hipStream_t st) {
     e.sBp = e.k * d.sBk;
     e.C = d.kscratch;
     e.sCb = d.m * d.n; e.sCm = d.n; e.sCn = 1;
+    e.cscatter = 0;
     e.amax_c = nullptr;
     const char *name = launch_big(e, v, st);
     const int64_t total = d.nb * d.m * d.n;
     int64_t grid = (total + 255) / 256;
     grid = grid > 2048 ? 2048 : grid;
-    hipLaunchKernelGGL(ksum_kernel, dim3((unsigned)grid), dim3(256), 0, st, d.kscratch, d.C, d.nb, d.m * d.n, d.kparts,
-                       d.amax_c);
+    hipLaunchKernelGGL(ksum_kernel, dim3((unsigned)grid), dim3(256), 0, st, d);
     return name;
 }
 }  // namespace

@@ -196,23 +196,84 @@ static bool lower(const qc_plan *plan, int b, int m, Program &prog, std::string 
         int opA = ta, opB = tb;
         bool a_km = !a_mfirst, b_nk = !b_kfirst;
         const int64_t szA = int64_t(1) << LA.size(), szB = int64_t(1) << LB.size();
-        if (a_ok && b_ok && Ab == Bb && Ak == Bk) {
-            // no transposes
-        } else if (a_ok && (!b_ok || szA >= szB)) {
-            opB = emit_transpose(tb, cat({Ab, Ak, Bn}));
-            Bb = Ab; Bk = Ak; b_nk = false;
-        } else if (b_ok) {
-            opA = emit_transpose(ta, cat({Bb, Am, Bk}));
-            Ab = Bb; Ak = Bk; a_km = false;
-        } else {
-            opA = emit_transpose(ta, cat({Ab, Am, Ak}));
-            opB = emit_transpose(tb, cat({Ab, Ak, Bn}));
-            Bb = Ab; Bk = Ak; a_km = false; b_nk = false;
+        // A reordered operand is written by its producer straight into the
+        // new layout (see the folding below).  Its writes stay coalesced when
+        // the new layout's lowest bits are the producer's own lowest output
+        // bits in order, so among the valid layouts (batch outermost, the
+        // other two groups in either order, free indices in the producer's
+        // order) the one keeping the longest such run is taken; leaves and
+        // small tensors cost nothing.
+        auto by_nat = [](std::vector<int> v, const std::vector<int> &nat) {
+            std::stable_sort(v.begin(), v.end(), [&](int x, int y) {
+                return std::find(nat.begin(), nat.end(), x) < std::find(nat.begin(), nat.end(), y);
+            });
+            return v;
+        };
+        auto write_cost = [&](int t, const std::vector<int> &lay) {
+            const std::vector<int> &nat = layout[t];
+            if (t < L || nat.size() <= 12) return 0.0;
+            size_t q = 0;
+            while (q < nat.size() && lay[lay.size() - 1 - q] == nat[nat.size() - 1 - q]) ++q;
+            return std::ldexp(1.0, (int)nat.size()) * (q >= 4 ? 0.0 : (4.0 - double(q)) / 4.0);
+        };
+        if (!(a_ok && b_ok && Ab == Bb && Ak == Bk)) {
+            // Candidates: reorder B only (A as it is), A only, or both.
+            struct Cand {
+                int kind = -1;  // 0 B only, 1 A only, 2 both
+                double cost = 0;
+                std::vector<int> la, lb, b_, k_, m_, n_;
+                bool km = false, nk = false;
+            } best;
+            auto offer = [&](Cand c) {
+                if (best.kind < 0 || c.cost < best.cost) best = std::move(c);
+            };
+            const std::vector<int> m_ = by_nat(Am, LA), n_ = by_nat(Bn, LB);
+            if (a_ok) {
+                for (int nk = 0; nk < 2; ++nk) {
+                    Cand c;
+                    c.kind = 0;
+                    c.lb = nk ? cat({Ab, n_, Ak}) : cat({Ab, Ak, n_});
+                    c.cost = write_cost(tb, c.lb);
+                    c.b_ = Ab; c.k_ = Ak; c.m_ = Am; c.n_ = n_;
+                    c.km = a_km; c.nk = nk;
+                    offer(std::move(c));
+                }
+            }
+            if (b_ok) {
+                for (int km = 0; km < 2; ++km) {
+                    Cand c;
+                    c.kind = 1;
+                    c.la = km ? cat({Bb, Bk, m_}) : cat({Bb, m_, Bk});
+                    c.cost = write_cost(ta, c.la);
+                    c.b_ = Bb; c.k_ = Bk; c.m_ = m_; c.n_ = Bn;
+                    c.km = km; c.nk = b_nk;
+                    offer(std::move(c));
+                }
+            }
+            for (int bsel = 0; bsel < 2; ++bsel)
+                for (int ksel = 0; ksel < 2; ++ksel)
+                    for (int km = 0; km < 2; ++km)
+                        for (int nk = 0; nk < 2; ++nk) {
+                            Cand c;
+                            c.kind = 2;
+                            c.b_ = by_nat(Ab, bsel ? LB : LA);
+                            c.k_ = by_nat(Ak, ksel ? LB : LA);
+                            c.m_ = m_; c.n_ = n_;
+                            c.la = km ? cat({c.b_, c.k_, m_}) : cat({c.b_, m_, c.k_});
+                            c.lb = nk ? cat({c.b_, n_, c.k_}) : cat({c.b_, c.k_, n_});
+                            c.cost = write_cost(ta, c.la) + write_cost(tb, c.lb);
+                            c.km = km; c.nk = nk;
+                            offer(std::move(c));
+                        }
+            if (best.kind != 1) opB = emit_transpose(tb, best.lb);
+            if (best.kind != 0) opA = emit_transpose(ta, best.la);
+            Ab = Bb = best.b_; Ak = Bk = best.k_; Am = best.m_; Bn = best.n_;
+            a_km = best.km; b_nk = best.nk;
         }
         const int tc = new_tensor(cat({Ab, Am, Bn}));
         GemmOp g;
         g.a_src = ta; g.b_src = tb;
-        g.a = opA; g.b = opB; g.c = tc;
+        g.a = opA; g.b = opB; g.c = g.c_nat = tc;
         g.cls_b = (int)Ab.size(); g.cls_m = (int)Am.size(); g.cls_n = (int)Bn.size(); g.cls_k = (int)Ak.size();
         g.nb = int64_t(1) << g.cls_b; g.m = int64_t(1) << g.cls_m; g.n = int64_t(1) << g.cls_n; g.k = int64_t(1) << g.cls_k;
         g.a_km = a_km && g.m > 1 && g.k > 1;
@@ -242,6 +303,47 @@ static bool lower(const qc_plan *plan, int b, int m, Program &prog, std::string 
     }
     if (layout[root] != want) root = emit_transpose(root, want);
     prog.root = root;
+
+    // Every transpose is folded into the producer of its source (each tensor
+    // has exactly one consumer): a leaf is instantiated directly in the
+    // transposed layout, and a GEMM step writes its output in that layout
+    // (its natural [batch][m][n] order stays recorded as c_nat, and the
+    // kernels scatter the output bits accordingly).  Consumers then read the
+    // producer's tensor as is.
+    {
+        std::vector<int> producer(layout.size(), -1), rename(layout.size());
+        for (size_t i = 0; i < prog.gemms.size(); ++i) producer[prog.gemms[i].c] = (int)i;
+        for (size_t t = 0; t < rename.size(); ++t) rename[t] = (int)t;
+        for (const TransposeOp &t : prog.transposes) {
+            if (t.src < L) {
+                layout[t.src] = layout[t.dst];
+                rename[t.dst] = t.src;
+            } else {
+                GemmOp &g = prog.gemms[producer[t.src]];
+                std::vector<int> x = layout[t.src], y = layout[t.dst];
+                std::sort(x.begin(), x.end());
+                std::sort(y.begin(), y.end());
+                if (x != y || (int)x.size() != g.cls_b + g.cls_m + g.cls_n) {
+                    err = "internal: a folded transpose is not a permutation of its step's output";
+                    return false;
+                }
+                g.c = t.dst;
+                rename[t.src] = t.dst;
+            }
+        }
+        for (GemmOp &g : prog.gemms) {
+            g.a = g.a_src = rename[g.a];
+            g.b = g.b_src = rename[g.b];
+        }
+        prog.root = rename[prog.root];
+        std::vector<Op> ops;
+        for (const Op &op : prog.ops)
+            if (op.kind == Op::GEMM) ops.push_back(op);
+        prog.ops = std::move(ops);
+        prog.transposes.clear();
+        prog.transpose_bytes = 0;
+        prog.root_pre = prog.root;
+    }
 
     // Lifetimes and offsets.  Leaves are born before op 0; each op's output is
     // allocated before its inputs are released.
@@ -403,7 +505,7 @@ std::string describe_program(const qc_plan *plan, const Program &prog) {
         } else {
             const GemmOp &g = prog.gemms[op.index];
             o << "{\"op\":\"gemm\",\"a\":" << g.a << ",\"b\":" << g.b << ",\"a_src\":" << g.a_src
-              << ",\"b_src\":" << g.b_src << ",\"c\":" << g.c << ",\"nb\":" << g.nb
+              << ",\"b_src\":" << g.b_src << ",\"c\":" << g.c << ",\"c_nat\":" << g.c_nat << ",\"nb\":" << g.nb
               << ",\"m\":" << g.m << ",\"n\":" << g.n << ",\"k\":" << g.k << ",\"a_km\":" << (g.a_km ? 1 : 0)
               << ",\"b_nk\":" << (g.b_nk ? 1 : 0) << ",\"micro\":" << int(prog.op_micro.empty() ? 0 : prog.op_micro[i])
               << '}';

@@ -116,6 +116,7 @@ inline int64_t gemm_kparts(int64_t nb, int64_t m, int64_t n, int64_t k) {
 struct GemmOp {
     int a_src, b_src;          // operand tensors as produced (before transposes)
     int a, b, c;               // program tensor ids after transposes
+    int c_nat = -1;            // tensor holding C's natural [b][m][n] layout (c_nat != c: C is written scattered into c's layout)
     int64_t nb, m, n, k;       // C[b][m][n] = sum_k A . B
     bool a_km;                 // A stored [b][k][m] (else [b][m][k])
     bool b_nk;                 // B stored [b][n][k] (else [b][k][n])
@@ -138,7 +139,7 @@ struct Program {
     std::vector<char> op_micro;           // per op: run by the micro-step kernel (GEMM) or skipped (its transpose)
     std::vector<char> gemm_micro;         // per GEMM step: run by the micro-step kernel
     int root = -1;                        // tensor holding [slice bits][bs bits]
-    int root_pre = -1;                    // the tree's last tensor (before any final transpose)
+    int root_pre = -1;                    // the tree's last tensor
     int64_t tensor_elems = 0;             // tensor region size (complex64 elements)
     int64_t ksplit_elems = 0;             // scratch of the GEMM steps split over k (complex64 elements)
     double flops = 0, bytes = 0, transpose_bytes = 0;

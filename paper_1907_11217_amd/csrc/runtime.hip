@@ -553,6 +553,19 @@ GemmDesc make_gemm(const Program &prog, const GemmOp &g, float2 *tensors, int pr
     d.sBb = g.k * g.n;
     if (g.b_nk) { d.sBn = g.k; d.sBk = 1; } else { d.sBk = g.n; d.sBn = 1; }
     d.sCb = g.m * g.n; d.sCm = g.n; d.sCn = 1;
+    if (g.c_nat >= 0 && g.c_nat != g.c) {
+        // C goes straight into its consumer's layout: bit t of the natural
+        // flat index (least significant first) is index nat[r - 1 - t].
+        const auto &nat = prog.tensors[g.c_nat].layout, &lay = prog.tensors[g.c].layout;
+        const int r = (int)nat.size();
+        d.cscatter = 1;
+        d.cbb = g.cls_b; d.cbm = g.cls_m; d.cbn = g.cls_n;
+        for (int t = 0; t < r; ++t) {
+            const int e = nat[r - 1 - t];
+            const int at = int(std::find(lay.begin(), lay.end(), e) - lay.begin());
+            d.cpos[t] = (int8_t)(r - 1 - at);
+        }
+    }
     return d;
 }
 

@@ -2,7 +2,8 @@
 
 It runs the program's steps on the CPU exactly as the device executes them --
 each GEMM step reads its operands' flat storage as [nb][m][k] (or [nb][k][m])
-and [nb][k][n] (or [nb][n][k]) and writes [nb][m][n] -- so a planner or
+and [nb][k][n] (or [nb][n][k]) and writes [nb][m][n], scattered into its
+output tensor's layout when that differs (c_nat != c) -- so a planner or
 lowering mistake (a wrong index class, layout, transpose or stride flag)
 shows up on the CPU, separately from kernel bugs.  It also evaluates each
 step a second way, by einsum over index ids, as a check of the first.  It is
@@ -72,6 +73,12 @@ def run_program(desc, bitstrings, chunk_base=0, check_einsum=True):
             B = tensors[op["b"]].reshape(nb, n, k).transpose(0, 2, 1) if op["b_nk"] else \
                 tensors[op["b"]].reshape(nb, k, n)
             C = np.matmul(A, B).reshape(-1)
+            nat = op.get("c_nat", op["c"])
+            if nat != op["c"]:
+                # The step writes its natural [batch][m][n] order scattered
+                # into the layout of tensor c.
+                ln, lc = layouts[nat], layouts[op["c"]]
+                C = np.ascontiguousarray(np.transpose(C.reshape([2] * len(ln)), [ln.index(e) for e in lc])).reshape(-1)
             if check_einsum:
                 la, lb, lc = layouts[op["a"]], layouts[op["b"]], layouts[op["c"]]
                 ids = {}

@@ -70,6 +70,18 @@ def test_workspace_holds_split_over_k_scratch():
     assert ws >= (desc["tensor_elems"] + max(need)) * 8
 
 
+def test_programs_have_no_transposes():
+    # Every operand is produced in the layout its consumer reads: leaves are
+    # instantiated in it, GEMM steps scatter their output into it.
+    lat, circ, bs, _ = synth.config("c3")
+    plan = qcsim.qc_plan_build(lat.n, circ, bs[0], log2_slices=16, log2_max_entries=30, greedy_trials=8, seed=1)
+    for b, m in [(16, 0), (0, 0), (4, 2)]:
+        desc = qcsim.qc_plan_describe(plan, b, m)
+        assert all(op["op"] == "gemm" for op in desc["ops"])
+        assert desc["transpose_bytes"] == 0
+        assert any(op["c_nat"] != op["c"] for op in desc["ops"])
+
+
 def test_gate_matrices_match_oracle_table():
     for kind in range(5):
         assert np.abs(qcsim.qc_gate_matrix(kind) - oracle.gate_matrix(kind)).max() < 1e-15
