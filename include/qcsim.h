@@ -177,11 +177,13 @@ qc_status qc_plan_export_steps(qc_plan *plan, int32_t log2_batch_slices, int32_t
  *   QC_EXEC_AUTO (default): fused when one (slice, bitstring) contraction
  *     fits in LDS and prec is QC_C64, else stepwise;
  *   QC_EXEC_FUSED: one launch per super-chunk, each wavefront contracting a
- *     whole (slice, bitstring) program in LDS in complex FP32
+ *     whole program for a chunk of 2^b slices (b in-flight slice bits, see
+ *     qc_plan_set_fused_slice_bits) and one bitstring in LDS in complex FP32
  *     (QC_ERR_UNSUPPORTED later if it does not fit or prec is split);
- *   QC_EXEC_STEPWISE: per pairwise step, an LDS-staged transpose where the
- *     layout needs it and a batched complex GEMM, with slices and bitstrings
- *     in flight as batch indices in global memory.
+ *   QC_EXEC_STEPWISE: one batched complex GEMM per pairwise step, with
+ *     slices and bitstrings in flight as batch indices in global memory; each
+ *     step writes its output directly in the layout its consumer reads (no
+ *     separate transposes), and small steps run together in one launch.
  * Call before qc_workspace_bytes (the workspace depends on the mode). */
 enum { QC_EXEC_AUTO = 0, QC_EXEC_FUSED = 1, QC_EXEC_STEPWISE = 2 };
 qc_status qc_plan_set_exec(qc_plan *plan, int32_t mode);
@@ -196,6 +198,19 @@ qc_status qc_plan_set_exec(qc_plan *plan, int32_t mode);
  * launches per super-chunk), launch directly.  on = 0 launches every kernel
  * directly. */
 qc_status qc_plan_set_graphs(qc_plan *plan, int32_t on);
+
+/* In-flight slice bits b of the fused form: each work item contracts 2^b
+ * slices at once, sharing the work that does not depend on those slice bits
+ * (the program is lowered with them as open indices), at the price of 2^b
+ * times fewer work items.  b = -1 (default): the first fused call times every
+ * b in 0..4 whose program fits in LDS (with its best pairs per wavefront) on
+ * one super-chunk and keeps the fastest for the plan's lifetime; b in 0..4
+ * fixes it (for b > 0, QC_ERR_UNSUPPORTED if that program does not fit;
+ * QC_ERR_RANGE if b exceeds the plan's slice bits).  Slice values depend on b at the
+ * rounding level only; calls with the same b are bitwise reproducible.  The
+ * fused requests of qc_contract_batch always run b = 0.  The choice is
+ * reported as "fused_slice_bits" by qc_plan_describe. */
+qc_status qc_plan_set_fused_slice_bits(qc_plan *plan, int32_t b);
 
 /* Autotuning (untimed preparation, like qc_plan_build).  Lowers the plan
  * for chunk_slices slices and n_bs bitstrings in flight (as

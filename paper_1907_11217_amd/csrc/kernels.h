@@ -104,7 +104,10 @@ void launch_copy(float2 *dst, const float2 *src, int64_t n, hipStream_t st);
 //   x = out slot | nk << 16  (nk = number of contracted values)
 //   y = a0 | b0 << 16        (operand slots of the first contracted value)
 //   z = a1 | b1 << 16        (second value; the pair's zero slot when nk = 1)
-//   w = pool index of the remaining (nk - 2) slot pairs, or -1
+//   w = pool index of the values past the fourth (count, then nk - 4 slot
+//       pairs), or -1
+// with a companion int2 (a2 | b2 << 16, a3 | b3 << 16) holding the third and
+// fourth values when nk >= 4, read in the same round trip as the item.
 // Slots are offsets inside one pair's LDS region (below 2^16).
 constexpr int kFusedLdsBytes = 64 * 1024;
 
@@ -112,6 +115,7 @@ struct FusedParams {
     const int32_t *level_start;              // n_levels + 1 item offsets
     int32_t n_levels;
     const int4 *items;
+    const int2 *items2;                      // third and fourth operand slots per item
     const int32_t *pool;
     const float2 *leaf_image;                // LDS [0, n_image): leaf values that do not depend on the pair
     int32_t n_image;
@@ -122,8 +126,9 @@ struct FusedParams {
     int32_t n_qubits;
     int32_t n_bs;
     int32_t m;                               // log2 padded bitstrings (rows of partial)
-    int64_t first_slice, n_slices;           // slices relative to sc
+    int64_t first_slice, n_slices;           // chunks of 2^b slices, relative to sc
     uint64_t sc;                             // super-chunk base slice id
+    int32_t b;                               // log2 slices per work item
     int32_t root_off;
     float2 *partial;                         // [slice - sc][2^m]
     int32_t lds_elems;
@@ -134,8 +139,9 @@ struct FusedParams {
 // become scalar loads).
 struct FusedScalars {
     int32_t n_levels, n_image, n_elems, n_qubits, m, root_off, pair_elems, zero_slot;
-    int32_t n_bs, pad;                       // rows of bits; padded bitstrings reuse the last row
-    int64_t first_slice, n_slices;
+    int32_t n_bs;                            // rows of bits; padded bitstrings reuse the last row
+    int32_t b;                               // log2 slices per work item (in the program's layouts)
+    int64_t first_slice, n_slices;           // in chunks of 2^b slices, relative to sc
     uint64_t sc;
 };
 
@@ -170,6 +176,7 @@ void launch_micro(const MicroStep *steps, const int32_t *group_start, const int3
 struct BatchReq {
     const int32_t *level_start;
     const int4 *items;
+    const int2 *items2;                      // third and fourth operand slots per item
     const int32_t *pool;
     const float2 *image;
     const int4 *elems;

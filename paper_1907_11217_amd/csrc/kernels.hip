@@ -1067,11 +1067,12 @@ const char *launch_gemm_variant(const GemmDesc &d, int v, hipStream_t st) {
 const char *launch_gemm(const GemmDesc &d, hipStream_t st) { return launch_gemm_variant(d, gemm_default_variant(d), st); }
 
 // ------------------------------------------------------------------ fused
-// One work item = one (slice, bitstring) pair, one wavefront.  Leaves are
-// written into LDS from the base table (each element picks its base entry from
-// its own index plus at most two bits taken from the slice id or the
+// One work item = one chunk of 2^b slices (the program's in-flight slice bits,
+// b = 0 for one slice) with one bitstring, one wavefront.  Leaves are written
+// into LDS from the base table (each element picks its base entry from its
+// own index plus up to four bits taken from the chunk's slice id or the
 // bitstring), then every step computes its outputs from table-driven LDS
-// offsets, and lane 0 stores the rank-0 root.
+// offsets, and the lanes store the root's 2^b slice values.
 // A run-time bit of a leaf element, 16-bit code: base bit position in the low
 // 3 bits, source above it (slice bit j < 64, or 64 + qubit of the bitstring);
 // 0xffff = none.  Two codes per 32-bit word.
@@ -1087,6 +1088,26 @@ __device__ __forceinline__ int dyn_bits(int z, int w, uint64_t slice, const uint
            dyn_bit(uint32_t(w) & 0xffffu, slice, row) + dyn_bit(uint32_t(w) >> 16, slice, row);
 }
 
+// The same with the bitstring given as bit masks (qubit q is bit q & 63 of
+// qm[q >> 6]), uniform over the wavefront.
+__device__ __forceinline__ int dyn_bit_m(uint32_t code, uint64_t slice, const uint64_t (&qm)[4]) {
+    if (code == 0xffffu) return 0;
+    const int src = int(code >> 3);
+    uint64_t word = slice;
+    int sh = src;
+    if (src >= 64) {
+        const int q = src - 64;
+        word = q < 64 ? qm[0] : q < 128 ? qm[1] : q < 192 ? qm[2] : qm[3];
+        sh = q & 63;
+    }
+    return int((word >> sh) & 1) << (code & 7u);
+}
+
+__device__ __forceinline__ int dyn_bits_m(int z, int w, uint64_t slice, const uint64_t (&qm)[4]) {
+    return dyn_bit_m(uint32_t(z) & 0xffffu, slice, qm) + dyn_bit_m(uint32_t(z) >> 16, slice, qm) +
+           dyn_bit_m(uint32_t(w) & 0xffffu, slice, qm) + dyn_bit_m(uint32_t(w) >> 16, slice, qm);
+}
+
 // The fused kernel's workgroup is a single wavefront, whose LDS accesses are
 // performed in issue order.  Between levels it is therefore enough that the
 // compiler keeps LDS accesses on their side of the boundary (a wavefront-scope
@@ -1096,6 +1117,48 @@ __device__ __forceinline__ void wave_step_sync() {
     __builtin_amdgcn_wave_barrier();
 }
 
+// One output of a level: the sum over its contracted values of the products
+// of LDS operands, in table order (it: first two values; it2: the third and
+// fourth when there are four or more; pool: the rest, counted by pool[it.w]).
+__device__ __forceinline__ float2 item_value(const float2 *L, int4 it, int2 it2, const int32_t *__restrict__ pool) {
+    const uint32_t y = uint32_t(it.y), z = uint32_t(it.z);
+    const float2 x0 = L[y & 0xffffu], y0 = L[y >> 16];
+    const float2 x1 = L[z & 0xffffu], y1 = L[z >> 16];
+    float re = x0.x * y0.x;
+    re = fmaf(-x0.y, y0.y, re);
+    float im = x0.x * y0.y;
+    im = fmaf(x0.y, y0.x, im);
+    re = fmaf(x1.x, y1.x, re);
+    re = fmaf(-x1.y, y1.y, re);
+    im = fmaf(x1.x, y1.y, im);
+    im = fmaf(x1.y, y1.x, im);
+    if ((uint32_t(it.x) >> 16) > 2u) {
+        const uint32_t u = uint32_t(it2.x), v = uint32_t(it2.y);
+        const float2 x2 = L[u & 0xffffu], y2 = L[u >> 16];
+        const float2 x3 = L[v & 0xffffu], y3 = L[v >> 16];
+        re = fmaf(x2.x, y2.x, re);
+        re = fmaf(-x2.y, y2.y, re);
+        im = fmaf(x2.x, y2.y, im);
+        im = fmaf(x2.y, y2.x, im);
+        re = fmaf(x3.x, y3.x, re);
+        re = fmaf(-x3.y, y3.y, re);
+        im = fmaf(x3.x, y3.y, im);
+        im = fmaf(x3.y, y3.x, im);
+        if (it.w >= 0) {
+            const int extra = pool[it.w];
+            for (int j = 1; j <= extra; ++j) {
+                const uint32_t w = uint32_t(pool[it.w + j]);
+                const float2 xa = L[w & 0xffffu], yb = L[w >> 16];
+                re = fmaf(xa.x, yb.x, re);
+                re = fmaf(-xa.y, yb.y, re);
+                im = fmaf(xa.x, yb.y, im);
+                im = fmaf(xa.y, yb.x, im);
+            }
+        }
+    }
+    return make_float2(re, im);
+}
+
 // One wavefront runs PAIRS (slice, bitstring) pairs, each in its own LDS
 // region of pair_elems values (the last one, zero_slot, holds 0), level by
 // level: every item of a level reads only tensors of lower levels, so a level
@@ -1103,7 +1166,7 @@ __device__ __forceinline__ void wave_step_sync() {
 template <int PAIRS>
 __global__ void __launch_bounds__(64)
 fused_kernel(const int32_t *__restrict__ level_start, const int4 *__restrict__ items,
-             const int32_t *__restrict__ pool, const float2 *__restrict__ image, const int4 *__restrict__ elems,
+             const int2 *__restrict__ items2, const int32_t *__restrict__ pool, const float2 *__restrict__ image, const int4 *__restrict__ elems,
              const double2 *__restrict__ base, const uint8_t *__restrict__ bits, float2 *__restrict__ partial,
              FusedScalars S) {
     extern __shared__ float2 lds[];
@@ -1123,13 +1186,30 @@ fused_kernel(const int32_t *__restrict__ level_start, const int4 *__restrict__ i
         wave_step_sync();
         for (int p = 0; p < PAIRS; ++p) {
             const int64_t pair = min(g * PAIRS + p, n_pairs - 1);
-            const uint64_t slice = S.sc + uint64_t(S.first_slice + (pair >> S.m));
+            const uint64_t slice = S.sc + (uint64_t(S.first_slice + (pair >> S.m)) << S.b);
             const uint8_t *row = bits + int64_t(min(int(pair & (n_bs - 1)), S.n_bs - 1)) * S.n_qubits;
+            // The bitstring as four 64-bit masks (one load per lane and word).
+            uint64_t qm[4] = {0, 0, 0, 0};
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int q = j * 64 + lane;
+                qm[j] = __ballot(q < S.n_qubits && (row[q < S.n_qubits ? q : 0] & 1));
+            }
             float2 *L = lds + p * S.pair_elems;
-            for (int e = lane; e < S.n_elems; e += 64) {
-                const int4 t = elems[e];
-                const double2 v = base[t.y + dyn_bits(t.z, t.w, slice, row)];
-                L[t.x] = make_float2(float(v.x), float(v.y));
+            // Eight element descriptors per lane in flight, then their base
+            // values, then the stores.
+            for (int e0 = lane; e0 < S.n_elems; e0 += 8 * 64) {
+                int4 t[8];
+#pragma unroll
+                for (int j = 0; j < 8; ++j)
+                    if (e0 + j * 64 < S.n_elems) t[j] = elems[e0 + j * 64];
+                double2 v[8];
+#pragma unroll
+                for (int j = 0; j < 8; ++j)
+                    if (e0 + j * 64 < S.n_elems) v[j] = base[t[j].y + dyn_bits_m(t[j].z, t[j].w, slice, qm)];
+#pragma unroll
+                for (int j = 0; j < 8; ++j)
+                    if (e0 + j * 64 < S.n_elems) L[t[j].x] = make_float2(float(v[j].x), float(v[j].y));
             }
         }
         wave_step_sync();
@@ -1137,40 +1217,21 @@ fused_kernel(const int32_t *__restrict__ level_start, const int4 *__restrict__ i
             const int i0 = level_start[lv], i1 = level_start[lv + 1];
             for (int i = i0 + lane; i < i1; i += 64) {
                 const int4 it = items[i];
-                const uint32_t y = uint32_t(it.y), z = uint32_t(it.z);
+                const int2 it2 = items2[i];
 #pragma unroll
-                for (int p = 0; p < PAIRS; ++p) {
-                    const float2 *L = lds + p * S.pair_elems;
-                    const float2 x0 = L[y & 0xffffu], y0 = L[y >> 16];
-                    const float2 x1 = L[z & 0xffffu], y1 = L[z >> 16];
-                    float re = x0.x * y0.x;
-                    re = fmaf(-x0.y, y0.y, re);
-                    float im = x0.x * y0.y;
-                    im = fmaf(x0.y, y0.x, im);
-                    re = fmaf(x1.x, y1.x, re);
-                    re = fmaf(-x1.y, y1.y, re);
-                    im = fmaf(x1.x, y1.y, im);
-                    im = fmaf(x1.y, y1.x, im);
-                    if (it.w >= 0) {  // more than two contracted values
-                        const int extra = pool[it.w];
-                        for (int j = 1; j <= extra; ++j) {
-                            const uint32_t u = uint32_t(pool[it.w + j]);
-                            const float2 xa = L[u & 0xffffu], yb = L[u >> 16];
-                            re = fmaf(xa.x, yb.x, re);
-                            re = fmaf(-xa.y, yb.y, re);
-                            im = fmaf(xa.x, yb.y, im);
-                            im = fmaf(xa.y, yb.x, im);
-                        }
-                    }
-                    lds[p * S.pair_elems + (it.x & 0xffff)] = make_float2(re, im);
-                }
+                for (int p = 0; p < PAIRS; ++p)
+                    lds[p * S.pair_elems + (it.x & 0xffff)] = item_value(lds + p * S.pair_elems, it, it2, pool);
             }
             wave_step_sync();
         }
-        if (lane < PAIRS && g * PAIRS + lane < n_pairs) {
-            const int64_t pair = g * PAIRS + lane;
-            const int64_t s_rel = S.first_slice + (pair >> S.m);
-            partial[(s_rel << S.m) + (pair & (n_bs - 1))] = lds[lane * S.pair_elems + S.root_off];
+        // A work item's root holds its 2^b slice values in slice order.
+        for (int q = lane; q < (PAIRS << S.b); q += 64) {
+            const int p = q >> S.b, sl = q & ((1 << S.b) - 1);
+            const int64_t pair = g * PAIRS + p;
+            if (pair < n_pairs) {
+                const int64_t s_rel = ((S.first_slice + (pair >> S.m)) << S.b) + sl;
+                partial[(s_rel << S.m) + (pair & (n_bs - 1))] = lds[p * S.pair_elems + S.root_off + sl];
+            }
         }
         wave_step_sync();
     }
@@ -1218,29 +1279,8 @@ __global__ void __launch_bounds__(64) fused_batch_kernel(const BatchReq *__restr
             const int i0 = R.level_start[lv], i1 = R.level_start[lv + 1];
             for (int i = i0 + lane; i < i1; i += 64) {
                 const int4 it = R.items[i];
-                const uint32_t y = uint32_t(it.y), z = uint32_t(it.z);
-                const float2 x0 = lds[y & 0xffffu], y0 = lds[y >> 16];
-                const float2 x1 = lds[z & 0xffffu], y1 = lds[z >> 16];
-                float re = x0.x * y0.x;
-                re = fmaf(-x0.y, y0.y, re);
-                float im = x0.x * y0.y;
-                im = fmaf(x0.y, y0.x, im);
-                re = fmaf(x1.x, y1.x, re);
-                re = fmaf(-x1.y, y1.y, re);
-                im = fmaf(x1.x, y1.y, im);
-                im = fmaf(x1.y, y1.x, im);
-                if (it.w >= 0) {
-                    const int extra = R.pool[it.w];
-                    for (int j = 1; j <= extra; ++j) {
-                        const uint32_t u = uint32_t(R.pool[it.w + j]);
-                        const float2 xa = lds[u & 0xffffu], yb = lds[u >> 16];
-                        re = fmaf(xa.x, yb.x, re);
-                        re = fmaf(-xa.y, yb.y, re);
-                        im = fmaf(xa.x, yb.y, im);
-                        im = fmaf(xa.y, yb.x, im);
-                    }
-                }
-                lds[it.x & 0xffff] = make_float2(re, im);
+                const int2 it2 = R.items2[i];
+                lds[it.x & 0xffff] = item_value(lds, it, it2, R.pool);
             }
             wave_step_sync();
         }
@@ -1316,14 +1356,14 @@ void launch_fused_pairs(const FusedParams &p, int pairs, int pair_elems, int zer
     S.root_off = p.root_off;
     S.pair_elems = pair_elems;
     S.n_bs = p.n_bs;
-    S.pad = 0;
+    S.b = p.b;
     S.first_slice = p.first_slice;
     S.n_slices = p.n_slices;
     S.sc = p.sc;
     const size_t lds = fused_lds_bytes(pairs, pair_elems);
 #define QC_FUSED_CASE(N)                                                                                      \
     case N:                                                                                                   \
-        hipLaunchKernelGGL(fused_kernel<N>, dim3(grid), dim3(64), lds, st, p.level_start, p.items, p.pool,     \
+        hipLaunchKernelGGL(fused_kernel<N>, dim3(grid), dim3(64), lds, st, p.level_start, p.items, p.items2, p.pool,     \
                            p.leaf_image, p.elems, p.base, p.bits, p.partial, S);                              \
         break;
     switch (pairs) {

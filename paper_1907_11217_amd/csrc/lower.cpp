@@ -511,7 +511,7 @@ std::string describe_program(const qc_plan *plan, const Program &prog) {
               << '}';
         }
     }
-    o << "],\"fused_pairs\":" << prog.fused_pairs << ",\"fused_tuning\":[";
+    o << "],\"fused_pairs\":" << prog.fused_pairs << ",\"fused_slice_bits\":" << plan->fused_b << ",\"fused_tuning\":[";
     for (size_t i = 0; i < prog.fused_tuning.size(); ++i)
         o << (i ? "," : "") << '[' << prog.fused_tuning[i].first << ',' << prog.fused_tuning[i].second << ']';
     o << "],\"root\":" << prog.root << ",\"tensor_elems\":" << prog.tensor_elems << ",\"lds_elems\":" << prog.lds_elems

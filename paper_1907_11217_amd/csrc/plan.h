@@ -160,8 +160,9 @@ struct Program {
     int n_image = 0;
     void *d_fused_elems = nullptr;        // run-time leaf elements: LDS slot, base index, dynamic bits
     void *d_fused_items = nullptr;        // one item per output of every step, grouped by tree level
+    void *d_fused_items2 = nullptr;       // third and fourth operand slots of each item
     void *d_fused_levels = nullptr;       // item offsets of the levels
-    void *d_fused_pool = nullptr;         // operand slots of items with more than two contracted values
+    void *d_fused_pool = nullptr;         // operand slots of items with more than four contracted values
     int n_leaf_elems = 0;
     int n_levels = 0;
     int n_pool = 0;
@@ -192,6 +193,7 @@ struct qc_plan {
     // profiling events) is updated under dev_mu.
     std::mutex dev_mu;
     bool use_graphs = true;
+    int fused_b = -1;                     // slices in flight per fused work item (log2; -1: not timed yet)
     void *capture_stream = nullptr;       // hipStream_t used only to capture graphs
 };
 

@@ -78,20 +78,23 @@ WsLayout ws_layout(const Exec &x, int n_qubits) {
     return w;
 }
 
-// The fused form runs the (0 slices, 0 bitstring bits) program: every tensor
-// of one pair in LDS (offsets then fit in 16 bits) and a rank-0 root; each
-// leaf may take at most four bits from the slice id and the bitstring.
-// A pair's LDS region: the program's tensors, then one slot holding zero.
+// The fused form runs a (b slices, 0 bitstring bits) program, b <= 4: every
+// tensor of one work item in LDS (offsets then fit in 16 bits) and a root of
+// the b in-flight slice bits; each leaf may take at most four bits from the
+// chunk's slice id and the bitstring (of at most 256 qubits, held as masks).
+// b is chosen by timing per plan.
+constexpr int kFusedMaxSliceBits = 4;
+// A work item's LDS region: the program's tensors, then one slot holding zero.
 int64_t pair_elems64(const Program &prog) { return (prog.lds_elems + 2) & ~int64_t(1); }
 int zero_slot_of(const Program &prog) { return int(prog.lds_elems); }
 int pair_elems_of(const Program &prog) { return int(pair_elems64(prog)); }  // only once fused_fits holds
 
 bool fused_fits(const qc_plan *plan, const Program &p) {
-    if (p.b != 0 || p.m != 0) return false;
+    if (p.m != 0 || p.b > kFusedMaxSliceBits || plan->net.n_qubits > 256) return false;
     if (pair_elems64(p) * int64_t(sizeof(float2)) > kFusedLdsBytes) return false;
-    if (!p.tensors[p.root_pre].layout.empty()) return false;
-    std::vector<char> sliced(plan->net.n_index(), 0);
-    for (int e : plan->sliced) sliced[e] = 1;
+    if ((int)p.tensors[p.root].layout.size() != p.b) return false;
+    std::vector<char> sliced(plan->net.n_index(), 0);  // fixed per work item
+    for (size_t j = p.b; j < plan->sliced.size(); ++j) sliced[plan->sliced[j]] = 1;
     for (const LeafOp &lo : p.leaves) {
         int dyn = 0;
         for (int e : plan->net.leaves[lo.leaf].idx) dyn += sliced[e] || plan->net.out_qubit[e] >= 0;
@@ -392,6 +395,7 @@ bool ensure_device(const qc_plan *plan, Program &prog, bool fused, std::string &
             n_levels = std::max(n_levels, level[g.c]);
         }
         std::vector<std::vector<int4>> by_level(n_levels);
+        std::vector<std::vector<int2>> by_level2(n_levels);
         std::vector<int32_t> pool;
         auto pack = [](int64_t a, int64_t b) { return int32_t(uint32_t(a) | (uint32_t(b) << 16)); };
         for (const GemmOp &g : prog.gemms) {
@@ -425,18 +429,23 @@ bool ensure_device(const qc_plan *plan, Program &prog, bool fused, std::string &
                 it.y = pack(a, b);
                 it.z = nk > 1 ? pack(a + ka[1], b + kb[1]) : pack(zero, zero);
                 it.w = -1;
-                if (nk > 2) {
+                int2 it2 = make_int2(0, 0);
+                if (nk > 2) it2 = make_int2(pack(a + ka[2], b + kb[2]), pack(a + ka[3], b + kb[3]));
+                if (nk > 4) {
                     it.w = (int)pool.size();
-                    pool.push_back(int32_t(nk - 2));
-                    for (int64_t kk = 2; kk < nk; ++kk) pool.push_back(pack(a + ka[kk], b + kb[kk]));
+                    pool.push_back(int32_t(nk - 4));
+                    for (int64_t kk = 4; kk < nk; ++kk) pool.push_back(pack(a + ka[kk], b + kb[kk]));
                 }
                 by_level[level[g.c] - 1].push_back(it);
+                by_level2[level[g.c] - 1].push_back(it2);
             }
         }
         std::vector<int4> items;
+        std::vector<int2> items2;
         std::vector<int32_t> level_start(1, 0);
-        for (auto &lv : by_level) {
-            items.insert(items.end(), lv.begin(), lv.end());
+        for (int l = 0; l < n_levels; ++l) {
+            items.insert(items.end(), by_level[l].begin(), by_level[l].end());
+            items2.insert(items2.end(), by_level2[l].begin(), by_level2[l].end());
             level_start.push_back((int32_t)items.size());
         }
         if (!upload(&prog.d_fused_image, image.data(), image.size() * sizeof(float2), err) ||
@@ -444,6 +453,7 @@ bool ensure_device(const qc_plan *plan, Program &prog, bool fused, std::string &
             !upload(&prog.d_fused_pool, pool.data(), pool.size() * 4, err) ||
             (!prog.d_base && !upload(&prog.d_base, base.data(), base.size() * sizeof(double2), err)) ||
             !upload(&prog.d_fused_items, items.data(), items.size() * sizeof(int4), err) ||
+            !upload(&prog.d_fused_items2, items2.data(), items2.size() * sizeof(int2), err) ||
             !upload(&prog.d_fused_levels, level_start.data(), level_start.size() * 4, err))
             return false;
         prog.n_leaf_elems = (int)elems.size();
@@ -597,6 +607,35 @@ struct Prof {
     }
 };
 
+// Kernel parameters of the fused form for slices [lo, hi) of super-chunk sc.
+FusedParams fused_params(const qc_plan *plan, const Program &prog, const Exec &x, uint64_t sc, uint64_t lo,
+                         uint64_t hi, const uint8_t *bits, int n_bs, float2 *partial) {
+    FusedParams fp;
+    std::memset(&fp, 0, sizeof(fp));
+    fp.level_start = (const int32_t *)prog.d_fused_levels;
+    fp.n_levels = prog.n_levels;
+    fp.items = (const int4 *)prog.d_fused_items;
+    fp.items2 = (const int2 *)prog.d_fused_items2;
+    fp.pool = (const int32_t *)prog.d_fused_pool;
+    fp.leaf_image = (const float2 *)prog.d_fused_image;
+    fp.n_image = prog.n_image;
+    fp.elems = (const int4 *)prog.d_fused_elems;
+    fp.n_elems = prog.n_leaf_elems;
+    fp.base = (const double2 *)prog.d_base;
+    fp.bits = bits;
+    fp.n_qubits = plan->net.n_qubits;
+    fp.n_bs = n_bs;
+    fp.m = x.m;
+    fp.b = prog.b;
+    fp.first_slice = int64_t(lo - sc) >> prog.b;
+    fp.n_slices = ((int64_t(hi - sc) + (int64_t(1) << prog.b) - 1) >> prog.b) - fp.first_slice;
+    fp.sc = sc;
+    fp.root_off = (int32_t)prog.lds_offset[prog.root];
+    fp.partial = partial;
+    fp.lds_elems = (int32_t)prog.lds_elems;
+    return fp;
+}
+
 // The launches of one call, on stream st, bitstrings already in device
 // memory: for each super-chunk either the fused kernel or the stepwise
 // sequence (scale-slot reset, leaves, transposes and GEMMs per chunk, root
@@ -623,27 +662,7 @@ bool launch_all(qc_plan *plan, const Exec &x, uint64_t s_begin, uint64_t s_end, 
     for (uint64_t sc = s_begin & ~(P - 1); sc < s_end; sc += P) {
         const uint64_t lo = std::max(s_begin, sc), hi = std::min(s_end, sc + P);
         if (x.fused) {
-            FusedParams fp;
-            std::memset(&fp, 0, sizeof(fp));
-            fp.level_start = (const int32_t *)prog.d_fused_levels;
-            fp.n_levels = prog.n_levels;
-            fp.items = (const int4 *)prog.d_fused_items;
-            fp.pool = (const int32_t *)prog.d_fused_pool;
-            fp.leaf_image = (const float2 *)prog.d_fused_image;
-            fp.n_image = prog.n_image;
-            fp.elems = (const int4 *)prog.d_fused_elems;
-            fp.n_elems = prog.n_leaf_elems;
-            fp.base = (const double2 *)prog.d_base;
-            fp.bits = bits;
-            fp.n_qubits = nq;
-            fp.n_bs = n_bs;
-            fp.m = x.m;
-            fp.first_slice = int64_t(lo - sc);
-            fp.n_slices = int64_t(hi - lo);
-            fp.sc = sc;
-            fp.root_off = (int32_t)prog.lds_offset[prog.root_pre];
-            fp.partial = partial;
-            fp.lds_elems = (int32_t)prog.lds_elems;
+            const FusedParams fp = fused_params(plan, prog, x, sc, lo, hi, bits, n_bs, partial);
             if (prog.fused_pairs == 0 && !tune_fused(prog, fp, st, err)) { plan->profiling = saved; return false; }
             prof.begin();
             launch_fused_pairs(fp, prog.fused_pairs, pair_elems_of(prog), zero_slot_of(prog), st);
@@ -742,28 +761,67 @@ bool launch_graph(qc_plan *plan, const Exec &x, uint64_t s_begin, uint64_t s_end
     return true;
 }
 
+// Slices in flight per fused work item: a program with b in-flight slice bits
+// shares the work that does not depend on them among its 2^b slices, but has
+// 2^b times fewer work items.  Each b whose program fits is timed once per
+// plan (with its best pairs per wavefront) on a whole super-chunk starting at
+// the call's first one, with the call's bitstrings; the fastest is kept.
+// Only the super-chunk's slice values in the workspace are written.
+bool choose_fused_b(qc_plan *plan, const Exec &x, uint64_t s_begin, const uint8_t *bits, int n_bs, void *ws,
+                    hipStream_t st, std::string &err) {
+    const int k = (int)plan->sliced.size();
+    const uint64_t P = uint64_t(1) << x.lp;
+    const uint64_t sc = s_begin & ~(P - 1);
+    const uint64_t hi = std::min(sc + P, uint64_t(1) << k);
+    float2 *partial = (float2 *)((char *)ws + ws_layout(x, plan->net.n_qubits).partial_off);
+    int best_b = 0;
+    float best_ms = -1.f;
+    for (int b = 0; b <= std::min(k, kFusedMaxSliceBits); ++b) {
+        Program *p = get_program(plan, b, 0, err);
+        if (!p) return false;
+        if (!fused_fits(plan, *p) || (uint64_t(1) << b) > P) continue;
+        if (!ensure_device(plan, *p, true, err)) return false;
+        const FusedParams fp = fused_params(plan, *p, x, sc, sc, hi, bits, n_bs, partial);
+        if (p->fused_pairs == 0 && !tune_fused(*p, fp, st, err)) return false;
+        float ms = -1.f;
+        for (auto &t : p->fused_tuning)
+            if (ms < 0 || t.second < ms) ms = t.second;
+        if (best_ms < 0 || ms < best_ms) { best_ms = ms; best_b = b; }
+    }
+    plan->fused_b = best_b;
+    return true;
+}
+
 // bits_in: host bitstrings (copied into the workspace) or, with bits_on_device,
 // the caller's device array (read in place).
 bool enqueue(qc_plan *plan, const Exec &x, uint64_t s_begin, uint64_t s_end, const uint8_t *bits_in,
              bool bits_on_device, int n_bs, void *ws, hipStream_t st, double *out_dev, double *per_slice_dev,
              std::string &err) {
     std::lock_guard<std::mutex> lk(plan->dev_mu);
-    Program &prog = *x.prog;
-    if (!ensure_device(plan, prog, x.fused, err)) return false;
-    const WsLayout w = ws_layout(x, plan->net.n_qubits);
+    Exec y = x;
+    if (!ensure_device(plan, *y.prog, y.fused, err)) return false;
+    const WsLayout w = ws_layout(y, plan->net.n_qubits);
     const uint8_t *bits = bits_in;
     if (!bits_on_device) {
         uint8_t *dst = (uint8_t *)ws + w.bits_off;
         QC_HIP(hipMemcpyAsync(dst, bits_in, size_t(n_bs) * plan->net.n_qubits, hipMemcpyHostToDevice, st));
         bits = dst;
     }
+    if (y.fused) {
+        if (plan->fused_b < 0 && !choose_fused_b(plan, y, s_begin, bits, n_bs, ws, st, err)) return false;
+        if (plan->fused_b > 0) {
+            y.prog = get_program(plan, plan->fused_b, 0, err);
+            if (!y.prog || !ensure_device(plan, *y.prog, true, err)) return false;
+        }
+    }
+    const Exec &x2 = y;
     // Graphs pay off for the stepwise form's long launch sequences; the fused
     // form is two launches per super-chunk, which replay no faster.
-    if (plan->use_graphs && !plan->profiling && !x.fused) {
-        if (launch_graph(plan, x, s_begin, s_end, bits, n_bs, ws, st, out_dev, per_slice_dev, err)) return true;
+    if (plan->use_graphs && !plan->profiling && !x2.fused) {
+        if (launch_graph(plan, x2, s_begin, s_end, bits, n_bs, ws, st, out_dev, per_slice_dev, err)) return true;
         if (!err.empty()) return false;
     }
-    return launch_all(plan, x, s_begin, s_end, bits, n_bs, ws, st, out_dev, per_slice_dev, plan->profiling, err);
+    return launch_all(plan, x2, s_begin, s_end, bits, n_bs, ws, st, out_dev, per_slice_dev, plan->profiling, err);
 }
 
 // ------------------------------------------------------------------ tuning
@@ -816,7 +874,7 @@ void free_program_device(Program &prog) {
     for (auto &g : prog.graphs) (void)hipGraphExecDestroy((hipGraphExec_t)g.second);
     prog.graphs.clear();
     for (void **p : {&prog.d_leaf_desc, &prog.d_leaf_block, &prog.d_base, &prog.d_fused_image, &prog.d_fused_elems,
-                     &prog.d_fused_pool, &prog.d_fused_items, &prog.d_fused_levels, &prog.d_micro,
+                     &prog.d_fused_pool, &prog.d_fused_items, &prog.d_fused_items2, &prog.d_fused_levels, &prog.d_micro,
                      &prog.d_micro_levels}) {
         if (*p) (void)hipFree(*p);
         *p = nullptr;
@@ -1104,6 +1162,7 @@ extern "C" qc_status qc_contract_batch(const qc_request *reqs, int32_t n, qc_pre
             std::memset(&d, 0, sizeof(d));
             d.level_start = (const int32_t *)prog.d_fused_levels;
             d.items = (const int4 *)prog.d_fused_items;
+            d.items2 = (const int2 *)prog.d_fused_items2;
             d.pool = (const int32_t *)prog.d_fused_pool;
             d.image = (const float2 *)prog.d_fused_image;
             d.elems = (const int4 *)prog.d_fused_elems;
@@ -1164,6 +1223,29 @@ extern "C" qc_status qc_plan_set_graphs(qc_plan *plan, int32_t on) {
     if (!plan) { set_error("qc_plan_set_graphs: NULL plan"); return QC_ERR_INVALID_ARG; }
     std::lock_guard<std::mutex> lk(plan->dev_mu);
     plan->use_graphs = on != 0;
+    return QC_OK;
+}
+
+extern "C" qc_status qc_plan_set_fused_slice_bits(qc_plan *plan, int32_t b) {
+    if (!plan || b < -1 || b > qc::kFusedMaxSliceBits) {
+        set_error("qc_plan_set_fused_slice_bits: invalid argument");
+        return QC_ERR_INVALID_ARG;
+    }
+    if (b > (int)plan->sliced.size()) {
+        set_error("qc_plan_set_fused_slice_bits: more slice bits than the plan has");
+        return QC_ERR_RANGE;
+    }
+    std::string err;
+    if (b > 0) {
+        qc::Program *p = qc::get_program(plan, b, 0, err);
+        if (!p) { set_error("qc_plan_set_fused_slice_bits: " + err); return QC_ERR_UNSUPPORTED; }
+        if (!qc::fused_fits(plan, *p)) {
+            set_error("qc_plan_set_fused_slice_bits: the fused program with these slice bits does not fit in LDS");
+            return QC_ERR_UNSUPPORTED;
+        }
+    }
+    std::lock_guard<std::mutex> lk(plan->dev_mu);
+    plan->fused_b = b;
     return QC_OK;
 }
 

@@ -30,7 +30,7 @@ EXPORTED = (
     "qc_gate_matrix", "qc_plan_destroy", "qc_last_error", "qc_kernel_gemm", "qc_kernel_transpose",
     "qc_plan_set_exec", "qc_profile_enable", "qc_profile_read", "qc_contract_slices_dev", "qc_plan_set_graphs",
     "qc_tune", "qc_kernel_gemm_form", "qc_batch_workspace_bytes", "qc_contract_batch", "qc_wall_clock_khz",
-    "qc_plan_export_steps", "qc_kernel_gemm_kparts", "qc_gemm_kparts",
+    "qc_plan_export_steps", "qc_kernel_gemm_kparts", "qc_gemm_kparts", "qc_plan_set_fused_slice_bits",
 )
 EXEC_MODES = {"auto": 0, "fused": 1, "stepwise": 2}
 
@@ -151,6 +151,8 @@ def load(path: str | None = None):
         lib.qc_wall_clock_khz.restype = ctypes.c_int
         lib.qc_plan_set_graphs.argtypes = [vp, ctypes.c_int32]
         lib.qc_plan_set_graphs.restype = ctypes.c_int
+        lib.qc_plan_set_fused_slice_bits.argtypes = [vp, ctypes.c_int32]
+        lib.qc_plan_set_fused_slice_bits.restype = ctypes.c_int
         lib.qc_profile_enable.argtypes = [vp, ctypes.c_int32]
         lib.qc_profile_enable.restype = ctypes.c_int
         lib.qc_profile_read.argtypes = [vp, ctypes.POINTER(qc_kernel_stat_t), ctypes.c_int32,
@@ -322,6 +324,12 @@ def qc_wall_clock_khz() -> int:
 def qc_plan_set_graphs(plan: Plan, on: bool = True) -> None:
     """Replay captured HIP graphs for repeated call configurations (default on)."""
     _check(plan._lib.qc_plan_set_graphs(plan.handle, int(bool(on))), plan._lib)
+
+
+def qc_plan_set_fused_slice_bits(plan: Plan, b: int = -1) -> None:
+    """In-flight slice bits of the fused form (0..4), or -1 to time them on
+    the first fused call."""
+    _check(plan._lib.qc_plan_set_fused_slice_bits(plan.handle, int(b)), plan._lib)
 
 
 def qc_profile_enable(plan: Plan, on: bool = True) -> None:

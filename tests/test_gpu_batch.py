@@ -37,6 +37,9 @@ def test_batch_matches_single_requests(prec):
         # fused in complex FP32, one with a partial slice range.
         k = 3 if r["family"][0] == 6 else (2 if i % 2 else 0)
         plan = qcsim.qc_plan_build(lat.n, r["circuit"], r["bitstring"], log2_slices=k, greedy_trials=2, seed=1)
+        # Batches run fused requests one slice per work item; pin the single
+        # calls to the same so the two agree bit for bit.
+        qcsim.qc_plan_set_fused_slice_bits(plan, 0)
         s1 = 1 << qcsim.qc_plan_info(plan)["log2_slices"]
         s0 = 1 if (k == 2 and i == 1) else 0
         items.append((plan, r["bitstring"], s0, s1))

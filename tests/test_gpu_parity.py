@@ -130,6 +130,42 @@ def test_c2_per_slice_values_match_oracle(c2_setup, mode):
         assert abs(ps[s, j] - v) <= TOL_C64 * max(abs(v), scale), (s, j, ps[s, j], v)
 
 
+@pytest.mark.parametrize("fb", [0, 1, 2, 3, 4])
+def test_c2_fused_slice_bits_match_oracle(fb):
+    # The fused form with 2^fb slices per work item (the program lowered with
+    # fb open slice bits): amplitudes against the state vector, per-slice
+    # values against the oracle's sliced contraction, ranges that cut work
+    # items against whole ones.
+    lat, circ, bs, spec = synth.config("c2")
+    plan = qcsim.qc_plan_build(lat.n, circ, bs[0], log2_slices=6, greedy_trials=8, seed=1)
+    qcsim.qc_plan_set_exec(plan, "fused")
+    qcsim.qc_plan_set_fused_slice_bits(plan, fb)
+    assert qcsim.qc_plan_describe(plan, 0, 0)["fused_slice_bits"] == fb
+    psi = oracle.statevector(lat.n, circ)
+    ref = np.array([psi[oracle.index_of(x)] for x in bs])
+    say(f"c2 fused, {1 << fb} slices per work item, 64 bitstrings")
+    amps, ps = _contract(plan, bs, 0, 64, per_slice=True)
+    check_amplitudes(amps, ref, lat.n, TOL_C64)
+    segs = [tuple(int(v) for v in s) for s in qcsim.qc_plan_sliced_segments(plan)]
+    scale = np.sqrt(np.mean(np.abs(ps) ** 2))
+    for s, j in [(0, 0), (37, 1), (63, 7), (12, 3), (5, 60)]:
+        v = oracle.sliced_value(lat.n, circ, bs[j], segs, s)
+        assert abs(ps[s, j] - v) <= TOL_C64 * max(abs(v), scale), (s, j, ps[s, j], v)
+    # [3, 45) cuts work items at both ends; its slices equal the whole run's.
+    part, pps = _contract(plan, bs[:5], 3, 45, per_slice=True)
+    assert np.array_equal(pps, ps[3:45, :5])
+
+
+def test_fused_slice_bits_rejects_bad_values(c2_setup):
+    _lat, _circ, _bs, plan, _ref = c2_setup
+    with pytest.raises(qcsim.QcError):
+        qcsim.qc_plan_set_fused_slice_bits(plan, 5)
+    lat = synth.grid(2, 2)
+    small = qcsim.qc_plan_build(lat.n, synth.random_circuit(lat, 2, 1), None, log2_slices=0)
+    with pytest.raises(qcsim.QcError):
+        qcsim.qc_plan_set_fused_slice_bits(small, 1)
+
+
 @pytest.mark.parametrize("mode", MODES)
 def test_ranges_compose_and_repeat(c2_setup, mode):
     # Slices are summed in aligned blocks of 64; splits at multiples of 64
