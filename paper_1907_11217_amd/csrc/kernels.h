@@ -194,9 +194,9 @@ void launch_stamp(uint64_t *t, hipStream_t st);
 
 // out[bs] += sum of partial over in-range slices of the super-chunk, in
 // aligned blocks of 64 slices: a fixed butterfly within each block, blocks
-// added in increasing order.
+// added in increasing order.  bsum: scratch of n_blocks * n_bs double2.
 void launch_reduce64(const float2 *partial, int m, int n_bs, uint64_t sc, int64_t n_blocks, uint64_t lo, uint64_t hi,
-                     uint64_t s_begin, double *out, double *per_slice, hipStream_t st);
+                     uint64_t s_begin, double *out, double *per_slice, double2 *bsum, hipStream_t st);
 
 // amax: per program tensor slots (indexed by leaf tensor id), or null.
 void launch_leaves(const LeafDesc *descs, const int32_t *block_leaf, int n_blocks, const double2 *base,

@@ -1377,6 +1377,67 @@ void launch_fused_pairs(const FusedParams &p, int pairs, int pair_elems, int zer
 
 // --------------------------------------------------------------- reduce64
 
+// Two launches.  Block sums: one wavefront per (block of 64 slices,
+// bitstring) overlapping [lo, hi), the fixed butterfly over the block's
+// in-range slice values in FP64 (spread over the whole chip; a wavefront
+// sum's cross-lane moves go through each compute unit's LDS crossbar).
+__global__ void __launch_bounds__(1024) block_sum_kernel(const float2 *__restrict__ partial, int m, int n_bs,
+                                                         uint64_t sc, int64_t n_blocks, int64_t groups, uint64_t lo,
+                                                         uint64_t hi, uint64_t s_begin, double2 *__restrict__ bsum,
+                                                         double *__restrict__ per_slice) {
+    const int lane = threadIdx.x & 63;
+    const int bs = int(blockIdx.x / groups);
+    const int64_t j = (blockIdx.x % groups) * (blockDim.x / 64) + (threadIdx.x >> 6);
+    if (j >= n_blocks) return;
+    const uint64_t b0 = sc + uint64_t(j) * 64;
+    if (b0 + 64 <= lo || b0 >= hi) return;
+    const uint64_t s = b0 + lane;
+    double re = 0.0, im = 0.0;
+    if (s >= lo && s < hi) {
+        const float2 v = partial[(int64_t(s - sc) << m) + bs];
+        re = double(v.x);
+        im = double(v.y);
+        if (per_slice) {
+            double *p = per_slice + 2 * (int64_t(s - s_begin) * n_bs + bs);
+            p[0] = re;
+            p[1] = im;
+        }
+    }
+    re = wave_sum(re);
+    im = wave_sum(im);
+    if (lane == 0) bsum[int64_t(bs) * n_blocks + j] = make_double2(re, im);
+}
+
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+    const long long b = __double_as_longlong(v);
+    const int lo32 = __builtin_amdgcn_readlane(int(b & 0xffffffffll), l);
+    const int hi32 = __builtin_amdgcn_readlane(int(b >> 32), l);
+    return __longlong_as_double((long long)(uint32_t(lo32)) | ((long long)hi32 << 32));
+}
+
+// Then one wavefront per bitstring adds the block sums to out[bs] in
+// increasing block order: 64 at a time are loaded across the lanes and read
+// back one by one, so the result is bitwise the same as adding the blocks one
+// after another.
+__global__ void __launch_bounds__(64) block_add_kernel(const double2 *__restrict__ bsum, int64_t n_blocks, uint64_t sc,
+                                                       uint64_t lo, uint64_t hi, double *__restrict__ out) {
+    const int bs = blockIdx.x, lane = threadIdx.x;
+    double acc_re = out[2 * bs], acc_im = out[2 * bs + 1];
+    const int64_t j0 = int64_t(lo - sc) / 64, j1 = (int64_t(hi - sc) + 63) / 64;
+    for (int64_t c = j0; c < j1; c += 64) {
+        const double2 v = c + lane < j1 ? bsum[int64_t(bs) * n_blocks + c + lane] : make_double2(0.0, 0.0);
+        const int cnt = int(j1 - c < 64 ? j1 - c : 64);
+        for (int l = 0; l < cnt; ++l) {
+            acc_re += readlane_f64(v.x, l);
+            acc_im += readlane_f64(v.y, l);
+        }
+    }
+    if (lane == 0) {
+        out[2 * bs] = acc_re;
+        out[2 * bs + 1] = acc_im;
+    }
+}
+
 // One workgroup per bitstring.  Its waves (one, four or sixteen, by the number
 // of blocks) form the 64-slice block sums (fixed butterfly) of up to 256 blocks
 // at a time into LDS; then one thread adds them to the running total in
@@ -1430,11 +1491,22 @@ __global__ void __launch_bounds__(1024) reduce64_kernel(const float2 *__restrict
     }
 }
 
+// A few blocks per bitstring (up to 64): one launch, one workgroup per
+// bitstring forming the block sums and adding them.  More blocks: the two
+// launches above.  Both give the same bits.
 void launch_reduce64(const float2 *partial, int m, int n_bs, uint64_t sc, int64_t n_blocks, uint64_t lo, uint64_t hi,
-                     uint64_t s_begin, double *out, double *per_slice, hipStream_t st) {
-    const int threads = n_blocks >= 64 ? 1024 : (n_blocks >= 16 ? 256 : 64);
-    hipLaunchKernelGGL(reduce64_kernel, dim3(n_bs), dim3(threads), 0, st, partial, m, n_bs, sc, n_blocks, lo, hi,
-                       s_begin, out, per_slice);
+                     uint64_t s_begin, double *out, double *per_slice, double2 *bsum, hipStream_t st) {
+    if (n_blocks <= 64) {
+        const int threads = n_blocks >= 16 ? 1024 : (n_blocks >= 4 ? 256 : 64);
+        hipLaunchKernelGGL(reduce64_kernel, dim3(n_bs), dim3(threads), 0, st, partial, m, n_bs, sc, n_blocks, lo, hi,
+                           s_begin, out, per_slice);
+        return;
+    }
+    const int waves = n_blocks >= 16 ? 16 : int(n_blocks);
+    const int64_t groups = (n_blocks + waves - 1) / waves;
+    hipLaunchKernelGGL(block_sum_kernel, dim3((unsigned)(groups * n_bs)), dim3(64 * waves), 0, st, partial, m, n_bs, sc,
+                       n_blocks, groups, lo, hi, s_begin, bsum, per_slice);
+    hipLaunchKernelGGL(block_add_kernel, dim3(n_bs), dim3(64), 0, st, bsum, n_blocks, sc, lo, hi, out);
 }
 
 }  // namespace qc

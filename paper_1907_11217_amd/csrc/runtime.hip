@@ -61,17 +61,19 @@ struct Exec {
 };
 
 // Workspace: bitstrings (when handed over from the host), the super-chunk's
-// slice values, per-tensor max|x| slots (split FP16 scale bookkeeping), and
-// the stepwise program's tensor region.
+// slice values and their 64-slice block sums, per-tensor max|x| slots (split
+// FP16 scale bookkeeping), the stepwise program's tensor region, and the
+// scratch of GEMM steps split over k.
 struct WsLayout {
-    size_t bits_off, partial_off, amax_off, tensor_off, ksplit_off, total;
+    size_t bits_off, partial_off, bsum_off, amax_off, tensor_off, ksplit_off, total;
 };
 
 WsLayout ws_layout(const Exec &x, int n_qubits) {
     WsLayout w;
     w.bits_off = 0;
     w.partial_off = align256(size_t(n_qubits) << x.m);
-    w.amax_off = w.partial_off + align256((size_t(1) << (x.lp + x.m)) * sizeof(float2));
+    w.bsum_off = w.partial_off + align256((size_t(1) << (x.lp + x.m)) * sizeof(float2));
+    w.amax_off = w.bsum_off + align256((size_t(1) << (x.lp - 6 + x.m)) * sizeof(double2));
     w.tensor_off = w.amax_off + (x.fused ? 0 : align256(x.prog->tensors.size() * sizeof(uint32_t)));
     w.ksplit_off = w.tensor_off + (x.fused ? 0 : align256(size_t(x.prog->tensor_elems) * sizeof(float2)));
     w.total = w.ksplit_off + (x.fused ? 0 : align256(size_t(x.prog->ksplit_elems) * sizeof(float2)));
@@ -703,7 +705,8 @@ bool launch_all(qc_plan *plan, const Exec &x, uint64_t s_begin, uint64_t s_end, 
             }
         }
         prof.begin();
-        launch_reduce64(partial, x.m, n_bs, sc, int64_t(P / 64), lo, hi, s_begin, out_dev, per_slice_dev, st);
+        launch_reduce64(partial, x.m, n_bs, sc, int64_t(P / 64), lo, hi, s_begin, out_dev, per_slice_dev,
+                        (double2 *)((char *)ws + w.bsum_off), st);
         prof.end("reduce64");
     }
     plan->profiling = saved;

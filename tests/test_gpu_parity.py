@@ -324,3 +324,34 @@ def test_c3_split_over_k_program_matches_finer_slicing(prec):
     tol = (TOL_C64 if prec == "c64" else TOL_SPLIT[prec]) * (2 * rms_a + 256 * rms_b)
     say(f"  |a - b| = {abs(a[0] - b[0]):.3e}, |b| = {abs(b[0]):.3e}, tol {tol:.3e}")
     assert abs(a[0] - b[0]) <= tol
+
+
+def _butterfly_blocks(vals, lo, hi, base):
+    # The reduction's arithmetic on the host: each aligned block of 64
+    # slices summed by the xor butterfly (offsets 32, 16, ..., 1; lane 0's
+    # value), blocks added in increasing order.
+    acc = 0.0 + 0.0j
+    first = (lo - base) // 64 * 64 + base
+    for b0 in range(first, hi, 64):
+        lane = np.zeros(64, dtype=np.complex128)
+        for j in range(64):
+            s = b0 + j
+            if lo <= s < hi:
+                lane[j] = vals[s - lo]
+        for off in (32, 16, 8, 4, 2, 1):
+            lane = lane + lane[np.arange(64) ^ off]
+        acc += lane[0]
+    return acc
+
+
+@pytest.mark.parametrize("s0,s1,chunk", [(100, 9000, 1 << 13), (0, 64, 64), (3, 1000, 1 << 10)])
+def test_reduction_order_is_the_fixed_butterfly(s0, s1, chunk):
+    # The FP64 sum of slice values, bit for bit as the documented order (with
+    # more than 64 blocks per super-chunk the block sums and their ordered
+    # addition are separate launches).
+    lat, circ, bs, _ = synth.config("c3")
+    plan = qcsim.qc_plan_build(lat.n, circ, bs[0], log2_slices=16, log2_max_entries=30, greedy_trials=8, seed=1)
+    say(f"c3 slices [{s0}, {s1}), chunk {chunk}: reduction order")
+    amp, ps = _contract(plan, bs[:1], s0, s1, chunk=chunk, per_slice=True)
+    ref = _butterfly_blocks(ps[:, 0], s0, s1, s0 // chunk * chunk)
+    assert amp[0] == ref, (amp[0], ref)
