@@ -393,11 +393,18 @@ def main():
     fused = "fused" in prof
     result_extra = {}
     if fused:
-        desc = qcsim.qc_plan_describe(plan, 0, 0)
-        result_extra = {"fused_pairs_per_wave": desc["fused_pairs"], "fused_tuning_ms": desc["fused_tuning"]}
-        pairs_per_launch = n_slices * (1 << max(0, int(np.ceil(np.log2(n_bs)))))
-        flops_step = desc["flops"] * n_slices * n_bs
-        kind_work = {"fused": (desc["flops"] * pairs_per_launch, "alu")}
+        # A fused work item is a chunk of 2^fb slices (the slice bits the
+        # plan's first call chose by timing) with one bitstring; its work is
+        # the flops of the program lowered with those fb open slice bits.
+        fb = qcsim.qc_plan_describe(plan, 0, 0)["fused_slice_bits"]
+        fb = max(fb, 0)
+        desc = qcsim.qc_plan_describe(plan, fb, 0)
+        items_per_launch = ((n_slices + (1 << fb) - 1) >> fb) * (1 << max(0, int(np.ceil(np.log2(n_bs)))))
+        result_extra = {"fused_slice_bits": fb, "fused_pairs_per_wave": desc["fused_pairs"],
+                        "fused_tuning_ms": desc["fused_tuning"], "fused_flops_per_item": desc["flops"],
+                        "flops_per_pair_one_slice_program": qcsim.qc_plan_describe(plan, 0, 0)["flops"]}
+        flops_step = desc["flops"] * ((n_slices + (1 << fb) - 1) >> fb) * n_bs
+        kind_work = {"fused": (desc["flops"] * items_per_launch, "alu")}
     else:
         b = min(k, 12)
         desc = None

@@ -1213,16 +1213,50 @@ fused_kernel(const int32_t *__restrict__ level_start, const int4 *__restrict__ i
             }
         }
         wave_step_sync();
+        // Levels.  The level starts sit one per lane (read back with readlane,
+        // no memory round trip per level, up to 63 levels), and each lane's
+        // next item (the next 64-wide stretch of this level, or the first of
+        // the next level) is loaded before the current one is computed, so
+        // its latency overlaps that work.
+        const bool ls_in_lanes = S.n_levels < 64;
+        const int ls_lane = ls_in_lanes && lane <= S.n_levels ? level_start[lane] : 0;
+        auto lstart = [&](int l) { return ls_in_lanes ? __builtin_amdgcn_readlane(ls_lane, l) : level_start[l]; };
+        int a0 = 0, a1 = 0;
+        if (S.n_levels > 0) {
+            a0 = lstart(0);
+            a1 = lstart(1);
+        }
+        int4 cur = make_int4(0, 0, 0, -1);
+        int2 cur2 = make_int2(0, 0);
+        if (a0 + lane < a1) {
+            cur = items[a0 + lane];
+            cur2 = items2[a0 + lane];
+        }
         for (int lv = 0; lv < S.n_levels; ++lv) {
-            const int i0 = level_start[lv], i1 = level_start[lv + 1];
-            for (int i = i0 + lane; i < i1; i += 64) {
-                const int4 it = items[i];
-                const int2 it2 = items2[i];
+            const int i0 = a0, i1 = a1;
+            const int b1 = lv + 2 <= S.n_levels ? lstart(lv + 2) : i1;
+            const int n_it = (i1 - i0 + 63) >> 6;
+            for (int t = 0; t < n_it; ++t) {
+                const int i = i0 + t * 64 + lane;
+                const int nx = t + 1 < n_it ? i + 64 : i1 + lane;
+                const int nx_end = t + 1 < n_it ? i1 : b1;
+                int4 nxt = make_int4(0, 0, 0, -1);
+                int2 nxt2 = make_int2(0, 0);
+                if (nx < nx_end) {
+                    nxt = items[nx];
+                    nxt2 = items2[nx];
+                }
+                if (i < i1) {
 #pragma unroll
-                for (int p = 0; p < PAIRS; ++p)
-                    lds[p * S.pair_elems + (it.x & 0xffff)] = item_value(lds + p * S.pair_elems, it, it2, pool);
+                    for (int p = 0; p < PAIRS; ++p)
+                        lds[p * S.pair_elems + (cur.x & 0xffff)] = item_value(lds + p * S.pair_elems, cur, cur2, pool);
+                }
+                cur = nxt;
+                cur2 = nxt2;
             }
             wave_step_sync();
+            a0 = i1;
+            a1 = b1;
         }
         // A work item's root holds its 2^b slice values in slice order.
         for (int q = lane; q < (PAIRS << S.b); q += 64) {
