@@ -288,6 +288,8 @@ def main():
     ap.add_argument("--workload", default="grid5x5_d16", choices=sorted(WORKLOADS))
     ap.add_argument("--prec", default="c64", choices=["c64", "split_bf16", "split_fp16"])
     ap.add_argument("--exec", default="auto", choices=["auto", "fused", "stepwise"])
+    ap.add_argument("--fused-slice-bits", type=int, default=-1,
+                    help="slices per fused work item (log2); default: timed by the library on the first call")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-large", action="store_true",
                     help="skip the 7x7 depth-24, 70-qubit depth-32 and request-batch reports")
@@ -340,6 +342,8 @@ def main():
                                log2_max_entries=spec.get("log2_cap", 0), greedy_trials=PLAN_TRIALS[key], seed=1)
     plan_s = time.perf_counter() - t0
     qcsim.qc_plan_set_exec(plan, args.exec)
+    if args.fused_slice_bits >= 0:
+        qcsim.qc_plan_set_fused_slice_bits(plan, args.fused_slice_bits)
     info = qcsim.qc_plan_info(plan)
     k = info["log2_slices"]
     n_slices = 1 << k
