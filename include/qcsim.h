@@ -144,24 +144,26 @@ qc_status qc_plan_slice_assignment(const qc_plan *plan, uint64_t s, uint8_t *out
 
 /* JSON description of the program lowered for 2^log2_batch_slices slices and
  * 2^log2_batch_bs bitstrings in flight: leaves (indices, base values),
- * steps (operands, index classes, layouts, GEMM shapes, transposes) and
- * per-step algorithmic flops/bytes.  Writes at most cap bytes to buf (NUL
+ * steps (operands, layouts, GEMM shapes; c_nat names the tensor holding a
+ * step's natural [batch][m][n] order when it writes its output scattered
+ * into the layout of c) and per-step algorithmic flops/bytes.  Writes at most cap bytes to buf (NUL
  * terminated when it fits) and the full length to *len. */
 qc_status qc_plan_describe(qc_plan *plan, int32_t log2_batch_slices, int32_t log2_batch_bs,
                            qc_precision prec, char *buf, size_t cap, size_t *len);
 
 /* The same lowered program's operations as a table, in execution order.
- * kind 0 = bit-permuting transpose (a = source tensor, c = destination,
- * m = its number of complex64 elements); kind 1 = GEMM step (a, b = operand
- * tensors as stored after any transpose, c = result; C[nb][m][n] =
+ * kind 1 = GEMM step (a, b = operand tensors, c = result; C[nb][m][n] =
  * sum_k A B with A stored [nb][k][m] if a_km else [nb][m][k], B stored
- * [nb][n][k] if b_nk else [nb][k][n]).  Tensor ids match qc_plan_describe.
- * Writes min(cap, count) rows to out (out may be NULL when cap is 0) and
- * the count to *n; QC_ERR_RANGE if the batch sizes exceed the plan.
- * micro = 1 marks the small steps (output and operands of at most 2^12
- * entries, fed only by leaves and other small steps) that the stepwise form
- * runs together in one kernel right after the leaves, and the transposes it
- * therefore skips. */
+ * [nb][n][k] if b_nk else [nb][k][n]; C is written in c's layout, which may
+ * be a bit permutation of [nb][m][n]).  kind 0 = bit-permuting transpose
+ * (a = source, c = destination, m = its number of complex64 elements): the
+ * current lowering folds every transpose into the producer of its source
+ * and emits none.  Tensor ids match qc_plan_describe.  Writes min(cap,
+ * count) rows to out (out may be NULL when cap is 0) and the count to *n;
+ * QC_ERR_RANGE if the batch sizes exceed the plan.  micro = 1 marks the
+ * small steps (output and operands of at most 2^12 entries, fed only by
+ * leaves and other small steps) that the stepwise form runs together in one
+ * launch right after the leaves. */
 typedef struct {
     int32_t kind;
     int32_t a, b, c;                 /* b = -1 for a transpose */
@@ -233,7 +235,8 @@ qc_status qc_tune(qc_plan *plan, int64_t chunk_slices, int32_t n_bs, qc_precisio
  * count and the summed event-to-event milliseconds since the last read (and
  * clears them).  kinds: "fused", "leaves", "micro", "transpose",
  * "gemm_mfma", "gemm_split_bf16", "gemm_split_fp16", "gemm_skinny",
- * "gemm_dot", "gemm_valu", "reduce64".  Not
+ * "gemm_dot", "gemm_valu", "reduce64" (a GEMM step split over k counts its
+ * partial products and their sum under its form's kind).  Not
  * thread-safe across concurrent calls on one plan. */
 typedef struct {
     char kind[16];
