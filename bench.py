@@ -404,8 +404,9 @@ def main():
         fb = max(fb, 0)
         desc = qcsim.qc_plan_describe(plan, fb, 0)
         items_per_launch = ((n_slices + (1 << fb) - 1) >> fb) * (1 << max(0, int(np.ceil(np.log2(n_bs)))))
-        result_extra = {"fused_slice_bits": fb, "fused_pairs_per_wave": desc["fused_pairs"],
-                        "fused_tuning_ms": desc["fused_tuning"], "fused_flops_per_item": desc["flops"],
+        result_extra = {"fused_slice_bits": fb, "fused_items_per_workgroup": desc["fused_pairs"],
+                        "fused_waves_per_item": desc["fused_waves"],
+                        "fused_tuning_items_waves_ms": desc["fused_tuning"], "fused_flops_per_item": desc["flops"],
                         "flops_per_pair_one_slice_program": qcsim.qc_plan_describe(plan, 0, 0)["flops"]}
         flops_step = desc["flops"] * ((n_slices + (1 << fb) - 1) >> fb) * n_bs
         kind_work = {"fused": (desc["flops"] * items_per_launch, "alu")}

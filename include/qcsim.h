@@ -204,11 +204,15 @@ qc_status qc_plan_set_graphs(qc_plan *plan, int32_t on);
 /* In-flight slice bits b of the fused form: each work item contracts 2^b
  * slices at once, sharing the work that does not depend on those slice bits
  * (the program is lowered with them as open indices), at the price of 2^b
- * times fewer work items.  b = -1 (default): the first fused call times every
- * b in 0..4 whose program fits in LDS (with its best pairs per wavefront) on
- * one super-chunk and keeps the fastest for the plan's lifetime; b in 0..4
- * fixes it (for b > 0, QC_ERR_UNSUPPORTED if that program does not fit;
- * QC_ERR_RANGE if b exceeds the plan's slice bits).  Slice values depend on b at the
+ * times fewer work items (each run by 1 to 16 wavefronts, as timed).  With
+ * b = 6 a work item is one 64-slice block and, when a launch holds one block
+ * per bitstring, it adds its block sum to out_dev itself (no separate
+ * reduction launch; same bits).  b = -1 (default): the first fused call times
+ * every b in 0..6 whose program fits in LDS (with its best work-item shape,
+ * plus the reduction launch where one is needed) on one super-chunk and keeps
+ * the fastest for the plan's lifetime; b in 0..6 fixes it (for b > 0,
+ * QC_ERR_UNSUPPORTED if that program does not fit; QC_ERR_RANGE if b exceeds
+ * the plan's slice bits).  Slice values depend on b at the
  * rounding level only; calls with the same b are bitwise reproducible.  The
  * fused requests of qc_contract_batch always run b = 0.  The choice is
  * reported as "fused_slice_bits" by qc_plan_describe. */

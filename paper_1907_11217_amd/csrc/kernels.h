@@ -132,6 +132,13 @@ struct FusedParams {
     int32_t root_off;
     float2 *partial;                         // [slice - sc][2^m]
     int32_t lds_elems;
+    // Set when each work item is exactly one 64-slice block (b = 6) and the
+    // launch holds one block per bitstring: the kernel sums the block itself
+    // (the reduction's butterfly and order) into out[bs] (and per_slice), for
+    // slices in [lo, hi); partial is then not written.
+    double *out = nullptr;
+    double *per_slice = nullptr;
+    uint64_t lo = 0, hi = 0, s_begin = 0;
 };
 
 // The scalar part of FusedParams, passed by value next to the tables (which
@@ -143,13 +150,16 @@ struct FusedScalars {
     int32_t b;                               // log2 slices per work item (in the program's layouts)
     int64_t first_slice, n_slices;           // in chunks of 2^b slices, relative to sc
     uint64_t sc;
+    uint64_t lo, hi, s_begin;                // slice range (block sums in the kernel)
 };
 
-// Pairs per wavefront the fused kernel is built for; the runtime times them
-// on first use of a program and keeps the fastest.
-constexpr int kFusedPairsOptions[] = {1, 2, 4};
+// Work-item shapes the fused kernel is built for, (work items per workgroup,
+// wavefronts per work item): one wavefront running
+// 1, 2 or 4 work items, or 2, 4, 8 or 16 wavefronts sharing one work item's levels.
+// The runtime times them on first use of a program and keeps the fastest.
+constexpr int kFusedShapes[][2] = {{1, 1}, {2, 1}, {4, 1}, {1, 2}, {1, 4}, {1, 8}, {1, 16}};
 size_t fused_lds_bytes(int pairs, int pair_elems);
-void launch_fused_pairs(const FusedParams &p, int pairs, int pair_elems, int zero_slot, hipStream_t st);
+void launch_fused_pairs(const FusedParams &p, int pairs, int waves, int pair_elems, int zero_slot, hipStream_t st);
 
 // One small GEMM step computed by the micro-step kernel straight from its
 // operands' layouts: output element o (bit p of o = bit p of C's layout,

@@ -1117,6 +1117,11 @@ __device__ __forceinline__ void wave_step_sync() {
     __builtin_amdgcn_wave_barrier();
 }
 
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
 // One output of a level: the sum over its contracted values of the products
 // of LDS operands, in table order (it: first two values; it2: the third and
 // fourth when there are four or more; pool: the rest, counted by pool[it.w]).
@@ -1163,14 +1168,21 @@ __device__ __forceinline__ float2 item_value(const float2 *L, int4 it, int2 it2,
 // region of pair_elems values (the last one, zero_slot, holds 0), level by
 // level: every item of a level reads only tensors of lower levels, so a level
 // needs no synchronisation inside it.
-template <int PAIRS>
-__global__ void __launch_bounds__(64)
+template <int PAIRS, int W>
+__global__ void __launch_bounds__(64 * W)
 fused_kernel(const int32_t *__restrict__ level_start, const int4 *__restrict__ items,
              const int2 *__restrict__ items2, const int32_t *__restrict__ pool, const float2 *__restrict__ image, const int4 *__restrict__ elems,
              const double2 *__restrict__ base, const uint8_t *__restrict__ bits, float2 *__restrict__ partial,
-             FusedScalars S) {
+             double *__restrict__ out, double *__restrict__ per_slice, FusedScalars S) {
     extern __shared__ float2 lds[];
-    const int lane = threadIdx.x;
+    constexpr int NT = 64 * W;  // threads per work item
+    const int tid = threadIdx.x, lane = tid & 63;
+    // Between levels: a wavefront-scope fence for one wavefront, a barrier
+    // for several.
+    auto step_sync = [] {
+        if constexpr (W == 1) wave_step_sync();
+        else __syncthreads();
+    };
     const int n_bs = 1 << S.m;
     const int64_t n_pairs = S.n_slices << S.m;
     const int64_t n_groups = (n_pairs + PAIRS - 1) / PAIRS;
@@ -1180,10 +1192,10 @@ fused_kernel(const int32_t *__restrict__ level_start, const int4 *__restrict__ i
         // bitstring bits.  A group past the last pair repeats the last pair.
         for (int p = 0; p < PAIRS; ++p) {
             float2 *L = lds + p * S.pair_elems;
-            for (int e = lane; e < S.n_image; e += 64) L[e] = image[e];
-            if (lane == 0) L[S.zero_slot] = make_float2(0.f, 0.f);
+            for (int e = tid; e < S.n_image; e += NT) L[e] = image[e];
+            if (tid == 0) L[S.zero_slot] = make_float2(0.f, 0.f);
         }
-        wave_step_sync();
+        step_sync();
         for (int p = 0; p < PAIRS; ++p) {
             const int64_t pair = min(g * PAIRS + p, n_pairs - 1);
             const uint64_t slice = S.sc + (uint64_t(S.first_slice + (pair >> S.m)) << S.b);
@@ -1198,21 +1210,21 @@ fused_kernel(const int32_t *__restrict__ level_start, const int4 *__restrict__ i
             float2 *L = lds + p * S.pair_elems;
             // Eight element descriptors per lane in flight, then their base
             // values, then the stores.
-            for (int e0 = lane; e0 < S.n_elems; e0 += 8 * 64) {
+            for (int e0 = tid; e0 < S.n_elems; e0 += 8 * NT) {
                 int4 t[8];
 #pragma unroll
                 for (int j = 0; j < 8; ++j)
-                    if (e0 + j * 64 < S.n_elems) t[j] = elems[e0 + j * 64];
+                    if (e0 + j * NT < S.n_elems) t[j] = elems[e0 + j * NT];
                 double2 v[8];
 #pragma unroll
                 for (int j = 0; j < 8; ++j)
-                    if (e0 + j * 64 < S.n_elems) v[j] = base[t[j].y + dyn_bits_m(t[j].z, t[j].w, slice, qm)];
+                    if (e0 + j * NT < S.n_elems) v[j] = base[t[j].y + dyn_bits_m(t[j].z, t[j].w, slice, qm)];
 #pragma unroll
                 for (int j = 0; j < 8; ++j)
-                    if (e0 + j * 64 < S.n_elems) L[t[j].x] = make_float2(float(v[j].x), float(v[j].y));
+                    if (e0 + j * NT < S.n_elems) L[t[j].x] = make_float2(float(v[j].x), float(v[j].y));
             }
         }
-        wave_step_sync();
+        step_sync();
         // Levels.  The level starts sit one per lane (read back with readlane,
         // no memory round trip per level, up to 63 levels), and each lane's
         // next item (the next 64-wide stretch of this level, or the first of
@@ -1228,17 +1240,17 @@ fused_kernel(const int32_t *__restrict__ level_start, const int4 *__restrict__ i
         }
         int4 cur = make_int4(0, 0, 0, -1);
         int2 cur2 = make_int2(0, 0);
-        if (a0 + lane < a1) {
-            cur = items[a0 + lane];
-            cur2 = items2[a0 + lane];
+        if (a0 + tid < a1) {
+            cur = items[a0 + tid];
+            cur2 = items2[a0 + tid];
         }
         for (int lv = 0; lv < S.n_levels; ++lv) {
             const int i0 = a0, i1 = a1;
             const int b1 = lv + 2 <= S.n_levels ? lstart(lv + 2) : i1;
-            const int n_it = (i1 - i0 + 63) >> 6;
+            const int n_it = (i1 - i0 + NT - 1) / NT;
             for (int t = 0; t < n_it; ++t) {
-                const int i = i0 + t * 64 + lane;
-                const int nx = t + 1 < n_it ? i + 64 : i1 + lane;
+                const int i = i0 + t * NT + tid;
+                const int nx = t + 1 < n_it ? i + NT : i1 + tid;
                 const int nx_end = t + 1 < n_it ? i1 : b1;
                 int4 nxt = make_int4(0, 0, 0, -1);
                 int2 nxt2 = make_int2(0, 0);
@@ -1254,12 +1266,40 @@ fused_kernel(const int32_t *__restrict__ level_start, const int4 *__restrict__ i
                 cur = nxt;
                 cur2 = nxt2;
             }
-            wave_step_sync();
+            step_sync();
             a0 = i1;
             a1 = b1;
         }
+        if (out) {
+            // The work item is one 64-slice block: its in-range values summed
+            // by the reduction's fixed butterfly in FP64 and added to out.
+            if (tid < 64) {
+                const int64_t pair = g * PAIRS;
+                const int bsi = int(pair & (n_bs - 1));
+                const uint64_t s = S.sc + (uint64_t(S.first_slice + (pair >> S.m)) << S.b) + uint64_t(tid);
+                double re = 0.0, im = 0.0;
+                if (s >= S.lo && s < S.hi) {
+                    const float2 v = lds[S.root_off + tid];
+                    re = double(v.x);
+                    im = double(v.y);
+                    if (per_slice && bsi < S.n_bs) {
+                        double *ps = per_slice + 2 * (int64_t(s - S.s_begin) * S.n_bs + bsi);
+                        ps[0] = re;
+                        ps[1] = im;
+                    }
+                }
+                re = wave_sum(re);
+                im = wave_sum(im);
+                if (tid == 0 && bsi < S.n_bs) {
+                    out[2 * bsi] += re;
+                    out[2 * bsi + 1] += im;
+                }
+            }
+            step_sync();
+            continue;
+        }
         // A work item's root holds its 2^b slice values in slice order.
-        for (int q = lane; q < (PAIRS << S.b); q += 64) {
+        for (int q = tid; q < (PAIRS << S.b); q += NT) {
             const int p = q >> S.b, sl = q & ((1 << S.b) - 1);
             const int64_t pair = g * PAIRS + p;
             if (pair < n_pairs) {
@@ -1267,14 +1307,10 @@ fused_kernel(const int32_t *__restrict__ level_start, const int4 *__restrict__ i
                 partial[(s_rel << S.m) + (pair & (n_bs - 1))] = lds[p * S.pair_elems + S.root_off + sl];
             }
         }
-        wave_step_sync();
+        step_sync();
     }
 }
 
-__device__ __forceinline__ double wave_sum(double v) {
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
 
 // ---------------------------------------------------------- fused batches
 // Many independent requests (each its own plan and bitstring) in one
@@ -1375,7 +1411,7 @@ void launch_stamp(uint64_t *t, hipStream_t st) { hipLaunchKernelGGL(stamp_kernel
 
 size_t fused_lds_bytes(int pairs, int pair_elems) { return size_t(pairs) * pair_elems * sizeof(float2); }
 
-void launch_fused_pairs(const FusedParams &p, int pairs, int pair_elems, int zero_slot, hipStream_t st) {
+void launch_fused_pairs(const FusedParams &p, int pairs, int waves, int pair_elems, int zero_slot, hipStream_t st) {
     const int64_t n_pairs = p.n_slices << p.m;
     if (n_pairs <= 0) return;
     const int64_t groups = (n_pairs + pairs - 1) / pairs;
@@ -1394,16 +1430,24 @@ void launch_fused_pairs(const FusedParams &p, int pairs, int pair_elems, int zer
     S.first_slice = p.first_slice;
     S.n_slices = p.n_slices;
     S.sc = p.sc;
+    S.lo = p.lo;
+    S.hi = p.hi;
+    S.s_begin = p.s_begin;
     const size_t lds = fused_lds_bytes(pairs, pair_elems);
-#define QC_FUSED_CASE(N)                                                                                      \
-    case N:                                                                                                   \
-        hipLaunchKernelGGL(fused_kernel<N>, dim3(grid), dim3(64), lds, st, p.level_start, p.items, p.items2, p.pool,     \
-                           p.leaf_image, p.elems, p.base, p.bits, p.partial, S);                              \
+#define QC_FUSED_CASE(N, WV)                                                                                   \
+    case N * 16 + WV:                                                                                         \
+        hipLaunchKernelGGL((fused_kernel<N, WV>), dim3(grid), dim3(64 * WV), lds, st, p.level_start, p.items,  \
+                           p.items2, p.pool, p.leaf_image, p.elems, p.base, p.bits, p.partial, p.out,         \
+                           p.per_slice, S);                                                                    \
         break;
-    switch (pairs) {
-        QC_FUSED_CASE(1)
-        QC_FUSED_CASE(2)
-        QC_FUSED_CASE(4)
+    switch (pairs * 16 + waves) {
+        QC_FUSED_CASE(1, 1)
+        QC_FUSED_CASE(2, 1)
+        QC_FUSED_CASE(4, 1)
+        QC_FUSED_CASE(1, 2)
+        QC_FUSED_CASE(1, 4)
+        QC_FUSED_CASE(1, 8)
+        QC_FUSED_CASE(1, 16)
     default: break;
     }
 #undef QC_FUSED_CASE

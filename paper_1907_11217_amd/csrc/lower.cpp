@@ -511,9 +511,10 @@ std::string describe_program(const qc_plan *plan, const Program &prog) {
               << '}';
         }
     }
-    o << "],\"fused_pairs\":" << prog.fused_pairs << ",\"fused_slice_bits\":" << plan->fused_b << ",\"fused_tuning\":[";
+    o << "],\"fused_pairs\":" << prog.fused_pairs << ",\"fused_waves\":" << prog.fused_waves << ",\"fused_slice_bits\":" << plan->fused_b << ",\"fused_tuning\":[";
     for (size_t i = 0; i < prog.fused_tuning.size(); ++i)
-        o << (i ? "," : "") << '[' << prog.fused_tuning[i].first << ',' << prog.fused_tuning[i].second << ']';
+        o << (i ? "," : "") << '[' << prog.fused_tuning[i][0] << ',' << prog.fused_tuning[i][1] << ','
+          << prog.fused_tuning[i][2] << ']';
     o << "],\"root\":" << prog.root << ",\"tensor_elems\":" << prog.tensor_elems << ",\"lds_elems\":" << prog.lds_elems
       << ",\"flops\":" << prog.flops
       << ",\"bytes\":" << prog.bytes << ",\"transpose_bytes\":" << prog.transpose_bytes << '}';

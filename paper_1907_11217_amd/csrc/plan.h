@@ -8,6 +8,7 @@
 // they act on, so one index can join many tensors.
 #pragma once
 
+#include <array>
 #include <complex>
 #include <cstdint>
 #include <map>
@@ -166,8 +167,9 @@ struct Program {
     int n_leaf_elems = 0;
     int n_levels = 0;
     int n_pool = 0;
-    int fused_pairs = 0;                  // pairs per wavefront chosen by timing (0 = not tuned yet)
-    std::vector<std::pair<int, float>> fused_tuning;  // (pairs, ms) measured when tuning
+    int fused_pairs = 0;                  // work items per workgroup chosen by timing (0 = not tuned yet)
+    int fused_waves = 1;                  // wavefronts per work item chosen by timing
+    std::vector<std::array<float, 3>> fused_tuning;  // (work items, wavefronts, ms) measured when tuning
     // Launch sequences captured as HIP graphs, keyed by everything the
     // captured kernel arguments depend on (buffers, range, batch, precision).
     std::vector<std::pair<std::vector<uint64_t>, void *>> graphs;  // (key, hipGraphExec_t)

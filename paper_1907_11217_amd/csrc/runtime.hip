@@ -80,12 +80,12 @@ WsLayout ws_layout(const Exec &x, int n_qubits) {
     return w;
 }
 
-// The fused form runs a (b slices, 0 bitstring bits) program, b <= 4: every
+// The fused form runs a (b slices, 0 bitstring bits) program, b <= 6: every
 // tensor of one work item in LDS (offsets then fit in 16 bits) and a root of
 // the b in-flight slice bits; each leaf may take at most four bits from the
 // chunk's slice id and the bitstring (of at most 256 qubits, held as masks).
 // b is chosen by timing per plan.
-constexpr int kFusedMaxSliceBits = 4;
+constexpr int kFusedMaxSliceBits = 6;
 // A work item's LDS region: the program's tensors, then one slot holding zero.
 int64_t pair_elems64(const Program &prog) { return (prog.lds_elems + 2) & ~int64_t(1); }
 int zero_slot_of(const Program &prog) { return int(prog.lds_elems); }
@@ -475,17 +475,22 @@ bool tune_fused(Program &prog, const FusedParams &fp, hipStream_t st, std::strin
     QC_HIP(hipEventCreate(&e0));
     QC_HIP(hipEventCreate(&e1));
     float best = 0.f;
-    for (int pairs : kFusedPairsOptions) {
+    for (const auto &shape : kFusedShapes) {
+        const int pairs = shape[0], waves = shape[1];
         if (fused_lds_bytes(pairs, pe) > size_t(kFusedLdsBytes)) continue;
-        launch_fused_pairs(fp, pairs, pe, zero, st);  // warm-up
+        launch_fused_pairs(fp, pairs, waves, pe, zero, st);  // warm-up
         QC_HIP(hipEventRecord(e0, st));
-        for (int r = 0; r < 3; ++r) launch_fused_pairs(fp, pairs, pe, zero, st);
+        for (int r = 0; r < 3; ++r) launch_fused_pairs(fp, pairs, waves, pe, zero, st);
         QC_HIP(hipEventRecord(e1, st));
         QC_HIP(hipEventSynchronize(e1));
         float ms = 0.f;
         QC_HIP(hipEventElapsedTime(&ms, e0, e1));
-        prog.fused_tuning.push_back({pairs, ms / 3});
-        if (prog.fused_pairs == 0 || ms < best) { best = ms; prog.fused_pairs = pairs; }
+        prog.fused_tuning.push_back({float(pairs), float(waves), ms / 3});
+        if (prog.fused_pairs == 0 || ms < best) {
+            best = ms;
+            prog.fused_pairs = pairs;
+            prog.fused_waves = waves;
+        }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -609,6 +614,13 @@ struct Prof {
     }
 };
 
+// A fused launch whose work items are exactly 64-slice blocks, one item per
+// workgroup, with one block of [lo, hi) per bitstring, adds its block sums to
+// the output itself (same butterfly and order as the reduction launch).
+bool block_sums_in_fused(const Program &prog, uint64_t sc, uint64_t lo, uint64_t hi) {
+    return prog.b == 6 && prog.fused_pairs == 1 && ((lo - sc) >> 6) == ((hi - 1 - sc) >> 6);
+}
+
 // Kernel parameters of the fused form for slices [lo, hi) of super-chunk sc.
 FusedParams fused_params(const qc_plan *plan, const Program &prog, const Exec &x, uint64_t sc, uint64_t lo,
                          uint64_t hi, const uint8_t *bits, int n_bs, float2 *partial) {
@@ -663,11 +675,20 @@ bool launch_all(qc_plan *plan, const Exec &x, uint64_t s_begin, uint64_t s_end, 
     const uint64_t P = uint64_t(1) << x.lp;
     for (uint64_t sc = s_begin & ~(P - 1); sc < s_end; sc += P) {
         const uint64_t lo = std::max(s_begin, sc), hi = std::min(s_end, sc + P);
+        bool summed = false;  // block sums already added to out by the fused launch
         if (x.fused) {
-            const FusedParams fp = fused_params(plan, prog, x, sc, lo, hi, bits, n_bs, partial);
+            FusedParams fp = fused_params(plan, prog, x, sc, lo, hi, bits, n_bs, partial);
             if (prog.fused_pairs == 0 && !tune_fused(prog, fp, st, err)) { plan->profiling = saved; return false; }
+            summed = block_sums_in_fused(prog, sc, lo, hi);
+            if (summed) {
+                fp.out = out_dev;
+                fp.per_slice = per_slice_dev;
+                fp.lo = lo;
+                fp.hi = hi;
+                fp.s_begin = s_begin;
+            }
             prof.begin();
-            launch_fused_pairs(fp, prog.fused_pairs, pair_elems_of(prog), zero_slot_of(prog), st);
+            launch_fused_pairs(fp, prog.fused_pairs, prog.fused_waves, pair_elems_of(prog), zero_slot_of(prog), st);
             prof.end("fused");
         } else {
             const uint64_t chunk = uint64_t(1) << prog.b;
@@ -704,10 +725,12 @@ bool launch_all(qc_plan *plan, const Exec &x, uint64_t s_begin, uint64_t s_end, 
                             int64_t(1) << (prog.b + x.m), st);
             }
         }
-        prof.begin();
-        launch_reduce64(partial, x.m, n_bs, sc, int64_t(P / 64), lo, hi, s_begin, out_dev, per_slice_dev,
-                        (double2 *)((char *)ws + w.bsum_off), st);
-        prof.end("reduce64");
+        if (!summed) {
+            prof.begin();
+            launch_reduce64(partial, x.m, n_bs, sc, int64_t(P / 64), lo, hi, s_begin, out_dev, per_slice_dev,
+                            (double2 *)((char *)ws + w.bsum_off), st);
+            prof.end("reduce64");
+        }
     }
     plan->profiling = saved;
     const hipError_t e = hipGetLastError();
@@ -726,7 +749,7 @@ bool launch_graph(qc_plan *plan, const Exec &x, uint64_t s_begin, uint64_t s_end
     const std::vector<uint64_t> key = {uint64_t(x.fused), uint64_t(x.prec), uint64_t(x.lp), uint64_t(x.m),
                                        uint64_t(uintptr_t(ws)), uint64_t(uintptr_t(bits)), uint64_t(n_bs),
                                        uint64_t(uintptr_t(out_dev)), uint64_t(uintptr_t(per_slice_dev)), s_begin,
-                                       s_end, uint64_t(prog.fused_pairs)};
+                                       s_end, uint64_t(prog.fused_pairs), uint64_t(prog.fused_waves)};
     for (auto &g : prog.graphs)
         if (g.first == key) {
             QC_HIP(hipGraphLaunch((hipGraphExec_t)g.second, st));
@@ -777,6 +800,26 @@ bool choose_fused_b(qc_plan *plan, const Exec &x, uint64_t s_begin, const uint8_
     const uint64_t sc = s_begin & ~(P - 1);
     const uint64_t hi = std::min(sc + P, uint64_t(1) << k);
     float2 *partial = (float2 *)((char *)ws + ws_layout(x, plan->net.n_qubits).partial_off);
+    // The separate reduction launch, timed once on the super-chunk's slice
+    // values into scratch (the block-sum region), is added to every b whose
+    // launch does not sum the blocks itself.
+    const WsLayout w = ws_layout(x, plan->net.n_qubits);
+    float reduce_ms = 0.f;
+    {
+        hipEvent_t e0, e1;
+        QC_HIP(hipEventCreate(&e0));
+        QC_HIP(hipEventCreate(&e1));
+        double *scratch = (double *)((char *)ws + w.bsum_off);
+        QC_HIP(hipEventRecord(e0, st));
+        for (int r = 0; r < 3; ++r)
+            launch_reduce64(partial, x.m, n_bs, sc, int64_t(P / 64), sc, hi, sc, scratch, nullptr, (double2 *)scratch, st);
+        QC_HIP(hipEventRecord(e1, st));
+        QC_HIP(hipEventSynchronize(e1));
+        QC_HIP(hipEventElapsedTime(&reduce_ms, e0, e1));
+        reduce_ms /= 3;
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+    }
     int best_b = 0;
     float best_ms = -1.f;
     for (int b = 0; b <= std::min(k, kFusedMaxSliceBits); ++b) {
@@ -788,7 +831,8 @@ bool choose_fused_b(qc_plan *plan, const Exec &x, uint64_t s_begin, const uint8_
         if (p->fused_pairs == 0 && !tune_fused(*p, fp, st, err)) return false;
         float ms = -1.f;
         for (auto &t : p->fused_tuning)
-            if (ms < 0 || t.second < ms) ms = t.second;
+            if (ms < 0 || t[2] < ms) ms = t[2];
+        if (!block_sums_in_fused(*p, sc, sc, hi)) ms += reduce_ms;
         if (best_ms < 0 || ms < best_ms) { best_ms = ms; best_b = b; }
     }
     plan->fused_b = best_b;

@@ -327,7 +327,7 @@ def qc_plan_set_graphs(plan: Plan, on: bool = True) -> None:
 
 
 def qc_plan_set_fused_slice_bits(plan: Plan, b: int = -1) -> None:
-    """In-flight slice bits of the fused form (0..4), or -1 to time them on
+    """In-flight slice bits of the fused form (0..6), or -1 to time them on
     the first fused call."""
     _check(plan._lib.qc_plan_set_fused_slice_bits(plan.handle, int(b)), plan._lib)
 

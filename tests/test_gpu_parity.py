@@ -130,7 +130,7 @@ def test_c2_per_slice_values_match_oracle(c2_setup, mode):
         assert abs(ps[s, j] - v) <= TOL_C64 * max(abs(v), scale), (s, j, ps[s, j], v)
 
 
-@pytest.mark.parametrize("fb", [0, 1, 2, 3, 4])
+@pytest.mark.parametrize("fb", [0, 1, 2, 3, 4, 5, 6])
 def test_c2_fused_slice_bits_match_oracle(fb):
     # The fused form with 2^fb slices per work item (the program lowered with
     # fb open slice bits): amplitudes against the state vector, per-slice
@@ -159,7 +159,7 @@ def test_c2_fused_slice_bits_match_oracle(fb):
 def test_fused_slice_bits_rejects_bad_values(c2_setup):
     _lat, _circ, _bs, plan, _ref = c2_setup
     with pytest.raises(qcsim.QcError):
-        qcsim.qc_plan_set_fused_slice_bits(plan, 5)
+        qcsim.qc_plan_set_fused_slice_bits(plan, 7)
     lat = synth.grid(2, 2)
     small = qcsim.qc_plan_build(lat.n, synth.random_circuit(lat, 2, 1), None, log2_slices=0)
     with pytest.raises(qcsim.QcError):
