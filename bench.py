@@ -269,15 +269,61 @@ def big_leg(key, precs, reps, s_range, oracle_slices=(), tune=False):
         leg["projected_s_per_amplitude_c64"] = leg["per_prec"]["c64"]["ms_per_step"] * 1e-3 * (1 << k) / n_sl
     for p in precs[1:]:
         leg[f"speedup_{p}_over_c64"] = leg["per_prec"]["c64"]["ms_per_step"] / leg["per_prec"][p]["ms_per_step"]
+    leg["flops_unsliced"] = info["flops_unsliced"]
+    leg["slicing_overhead"] = info["flops_per_slice"] * float(1 << k) / max(info["flops_unsliced"], 1.0)
     if oracle_slices:
         import oracle
         segs = [tuple(int(v) for v in sg) for sg in qcsim.qc_plan_sliced_segments(plan)]
-        errs = []
+        errs, secs = [], []
         for s in oracle_slices:
+            t1 = time.perf_counter()
             v = oracle.sliced_value(lat.n, circ, x[0], segs, s0 + s)
+            secs.append(time.perf_counter() - t1)
             errs.append(abs(per_slice_ref[s] - v) / abs(v))
         leg["oracle_per_slice_rel_err_c64"] = {"slices": [s0 + s for s in oracle_slices], "max": float(max(errs))}
+        # The oracle beside the GPU: its per-slice time (NumPy FP64 pairwise
+        # contraction, the host's BLAS threads) projected to all 2^k slices.
+        med = sorted(secs)[len(secs) // 2]
+        leg["cpu_oracle"] = {"seconds_per_slice": med, "projected_s_per_amplitude": med * float(1 << k),
+                             "cores": len(os.sched_getaffinity(0)), "kind": "oracle",
+                             "sample": f"{len(secs)} sampled slice(s) of the same plan"}
     return leg
+
+
+def small_leg(reps=200):
+    """The 4x4 depth-10 workload: one amplitude (no slicing), latency per call
+    with the bitstring resident, against the oracle's state vector."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import synth
+    from paper_1907_11217_amd import qcsim
+
+    lat, circ, bs, spec = synth.config("c1")
+    plan = qcsim.qc_plan_build(lat.n, circ, bs[0], log2_slices=0, greedy_trials=PLAN_TRIALS["c1"], seed=1)
+    dbits = torch.from_numpy(np.ascontiguousarray(bs[:1], dtype=np.uint8)).cuda()
+    ws = torch.empty(qcsim.qc_workspace_bytes(plan, 1, 1), dtype=torch.uint8, device="cuda")
+    out = torch.zeros(1, 2, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def step():
+        qcsim.qc_contract_slices_dev(plan, 0, 1, dbits, "c64", ws, out, stream=stream)
+
+    ms = _events_ms(stream, step, reps)
+    out.zero_()
+    step()
+    torch.cuda.synchronize()
+    got = complex(*out.cpu().numpy()[0])
+    t1 = time.perf_counter()
+    ref = complex(oracle.amplitudes_sv(lat.n, circ, bs[:1])[0])
+    cpu_s = time.perf_counter() - t1
+    return {"workload": f"{spec['name']}: {lat.n} qubits, depth 1+{spec['depth']}+1, no slicing, 1 bitstring "
+                        f"(seeds {spec['seed']}/{spec['seed'] + 1})",
+            "us_per_amplitude": ms * 1e3, "amplitudes_per_s": 1.0 / (ms * 1e-3),
+            "abs_err": abs(got - ref), "abs_ref": abs(ref),
+            "cpu_oracle": {"seconds": cpu_s, "amplitudes_per_s": 1.0 / cpu_s, "kind": "oracle",
+                           "sample": "one state-vector run of the same circuit"}}
 
 
 def main():
@@ -484,6 +530,7 @@ def main():
     if not args.no_large:
         precs = ["c64", "split_fp16", "split_bf16"]
         # 7x7 depth 24: every slice of one amplitude per step.
+        result["grid4x4_d10"] = small_leg()
         result["grid7x7_d24"] = big_leg("c3", precs, 5, lambda k: (0, 1 << k), oracle_slices=(0,), tune=True)
         # 70 qubits depth 32: one slice per step; the amplitude is projected
         # as slice time x 2^k.  Many slices of this plan are exactly zero (a
