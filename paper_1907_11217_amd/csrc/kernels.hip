@@ -1150,14 +1150,22 @@ __device__ __forceinline__ float2 item_value(const float2 *L, int4 it, int2 it2,
         im = fmaf(x3.x, y3.y, im);
         im = fmaf(x3.y, y3.x, im);
         if (it.w >= 0) {
-            const int extra = pool[it.w];
-            for (int j = 1; j <= extra; ++j) {
-                const uint32_t w = uint32_t(pool[it.w + j]);
-                const float2 xa = L[w & 0xffffu], yb = L[w >> 16];
-                re = fmaf(xa.x, yb.x, re);
-                re = fmaf(-xa.y, yb.y, re);
-                im = fmaf(xa.x, yb.y, im);
-                im = fmaf(xa.y, yb.x, im);
+            // Values past the fourth: their count is nk - 4 (also stored at
+            // pool[it.w]); four slot pairs are loaded at a time, together.
+            const int extra = int(uint32_t(it.x) >> 16) - 4;
+            for (int j0 = 0; j0 < extra; j0 += 4) {
+                uint32_t w[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) w[j] = j0 + j < extra ? uint32_t(pool[it.w + 1 + j0 + j]) : 0u;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    if (j0 + j >= extra) break;
+                    const float2 xa = L[w[j] & 0xffffu], yb = L[w[j] >> 16];
+                    re = fmaf(xa.x, yb.x, re);
+                    re = fmaf(-xa.y, yb.y, re);
+                    im = fmaf(xa.x, yb.y, im);
+                    im = fmaf(xa.y, yb.x, im);
+                }
             }
         }
     }
@@ -1186,6 +1194,23 @@ fused_kernel(const int32_t *__restrict__ level_start, const int4 *__restrict__ i
     const int n_bs = 1 << S.m;
     const int64_t n_pairs = S.n_slices << S.m;
     const int64_t n_groups = (n_pairs + PAIRS - 1) / PAIRS;
+    // Before any work item: the level starts, one per lane (read back with
+    // readlane, no memory round trip per level, up to 63 levels), and each
+    // thread's first item, all work items being alike.
+    const bool ls_in_lanes = S.n_levels < 64;
+    const int ls_lane = ls_in_lanes && lane <= S.n_levels ? level_start[lane] : 0;
+    auto lstart = [&](int l) { return ls_in_lanes ? __builtin_amdgcn_readlane(ls_lane, l) : level_start[l]; };
+    int a0_first = 0, a1_first = 0;
+    if (S.n_levels > 0) {
+        a0_first = lstart(0);
+        a1_first = lstart(1);
+    }
+    int4 cur_first = make_int4(0, 0, 0, -1);
+    int2 cur2_first = make_int2(0, 0);
+    if (a0_first + tid < a1_first) {
+        cur_first = items[a0_first + tid];
+        cur2_first = items2[a0_first + tid];
+    }
     for (int64_t g = blockIdx.x; g < n_groups; g += gridDim.x) {
         // Leaves of every pair: the pair-independent values in one coalesced
         // copy, then the elements whose base entry depends on slice or
@@ -1225,25 +1250,12 @@ fused_kernel(const int32_t *__restrict__ level_start, const int4 *__restrict__ i
             }
         }
         step_sync();
-        // Levels.  The level starts sit one per lane (read back with readlane,
-        // no memory round trip per level, up to 63 levels), and each lane's
-        // next item (the next 64-wide stretch of this level, or the first of
-        // the next level) is loaded before the current one is computed, so
-        // its latency overlaps that work.
-        const bool ls_in_lanes = S.n_levels < 64;
-        const int ls_lane = ls_in_lanes && lane <= S.n_levels ? level_start[lane] : 0;
-        auto lstart = [&](int l) { return ls_in_lanes ? __builtin_amdgcn_readlane(ls_lane, l) : level_start[l]; };
-        int a0 = 0, a1 = 0;
-        if (S.n_levels > 0) {
-            a0 = lstart(0);
-            a1 = lstart(1);
-        }
-        int4 cur = make_int4(0, 0, 0, -1);
-        int2 cur2 = make_int2(0, 0);
-        if (a0 + tid < a1) {
-            cur = items[a0 + tid];
-            cur2 = items2[a0 + tid];
-        }
+        // Levels.  Each thread's next item (the next stretch of this level,
+        // or the first of the next level) is loaded before the current one is
+        // computed, so its latency overlaps that work.
+        int a0 = a0_first, a1 = a1_first;
+        int4 cur = cur_first;
+        int2 cur2 = cur2_first;
         for (int lv = 0; lv < S.n_levels; ++lv) {
             const int i0 = a0, i1 = a1;
             const int b1 = lv + 2 <= S.n_levels ? lstart(lv + 2) : i1;
