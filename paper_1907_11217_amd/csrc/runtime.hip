@@ -469,6 +469,8 @@ bool ensure_device(const qc_plan *plan, Program &prog, bool fused, std::string &
 // Times each pairs-per-wavefront option once on the caller's stream (the
 // launches write the same partial values the real launch then overwrites)
 // and keeps the fastest.  Runs once per program.
+constexpr int kFusedTuneReps = 10;  // timed launches per work-item shape
+
 bool tune_fused(Program &prog, const FusedParams &fp, hipStream_t st, std::string &err) {
     const int pe = pair_elems_of(prog), zero = zero_slot_of(prog);
     hipEvent_t e0, e1;
@@ -480,12 +482,12 @@ bool tune_fused(Program &prog, const FusedParams &fp, hipStream_t st, std::strin
         if (fused_lds_bytes(pairs, pe) > size_t(kFusedLdsBytes)) continue;
         launch_fused_pairs(fp, pairs, waves, pe, zero, st);  // warm-up
         QC_HIP(hipEventRecord(e0, st));
-        for (int r = 0; r < 3; ++r) launch_fused_pairs(fp, pairs, waves, pe, zero, st);
+        for (int r = 0; r < kFusedTuneReps; ++r) launch_fused_pairs(fp, pairs, waves, pe, zero, st);
         QC_HIP(hipEventRecord(e1, st));
         QC_HIP(hipEventSynchronize(e1));
         float ms = 0.f;
         QC_HIP(hipEventElapsedTime(&ms, e0, e1));
-        prog.fused_tuning.push_back({float(pairs), float(waves), ms / 3});
+        prog.fused_tuning.push_back({float(pairs), float(waves), ms / kFusedTuneReps});
         if (prog.fused_pairs == 0 || ms < best) {
             best = ms;
             prog.fused_pairs = pairs;
