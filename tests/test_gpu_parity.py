@@ -355,3 +355,34 @@ def test_reduction_order_is_the_fixed_butterfly(s0, s1, chunk):
     amp, ps = _contract(plan, bs[:1], s0, s1, chunk=chunk, per_slice=True)
     ref = _butterfly_blocks(ps[:, 0], s0, s1, s0 // chunk * chunk)
     assert amp[0] == ref, (amp[0], ref)
+
+
+def test_fused_block_sums_compose_across_super_chunks():
+    # 64-slice fused work items add their block sums to the output in the
+    # launch; a range of several blocks runs one launch per 64-slice
+    # super-chunk, so the blocks still arrive in increasing order: the result
+    # equals the two-launch reduction's bits (b = 0 with the same blocks is a
+    # different program, so that comparison is to rounding; the per-slice
+    # values of b = 6 are checked through the butterfly re-computation).
+    lat, circ, bs, _ = synth.config("c2")
+    plan = qcsim.qc_plan_build(lat.n, circ, bs[0], log2_slices=8, greedy_trials=2, seed=5)
+    qcsim.qc_plan_set_exec(plan, "fused")
+    qcsim.qc_plan_set_fused_slice_bits(plan, 6)
+    xs = bs[:8]
+    ws_bytes = qcsim.qc_workspace_bytes(plan, 64, len(xs))
+    say("c2 circuit, 256 slices, 64-slice fused work items, block sums in the launch")
+    whole, ps = _contract(plan, xs, 0, 256, ws_bytes=ws_bytes, per_slice=True)
+    for j in range(len(xs)):
+        assert whole[j] == _butterfly_blocks(ps[:, j], 0, 256, 0)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
+    out = torch.zeros(len(xs), 2, dtype=torch.float64, device="cuda")
+    qcsim.qc_contract_slices(plan, 0, 128, xs, "c64", ws, out)
+    qcsim.qc_contract_slices(plan, 128, 256, xs, "c64", ws, out)
+    torch.cuda.synchronize()
+    o = out.cpu().numpy()
+    assert np.array_equal(o[:, 0] + 1j * o[:, 1], whole)
+    plan0 = qcsim.qc_plan_build(lat.n, circ, bs[0], log2_slices=8, greedy_trials=2, seed=5)
+    qcsim.qc_plan_set_exec(plan0, "fused")
+    qcsim.qc_plan_set_fused_slice_bits(plan0, 0)
+    b0 = _contract(plan0, xs, 0, 256, ws_bytes=qcsim.qc_workspace_bytes(plan0, 64, len(xs)))
+    assert np.abs(b0 - whole).max() <= TOL_C64 * np.abs(whole).max()
