@@ -108,7 +108,8 @@ void launch_copy(float2 *dst, const float2 *src, int64_t n, hipStream_t st);
 //       pairs), or -1
 // with a companion int2 (a2 | b2 << 16, a3 | b3 << 16) holding the third and
 // fourth values when nk >= 4, read in the same round trip as the item.
-// Slots are offsets inside one pair's LDS region (below 2^16).
+// Slots are byte offsets inside one pair's LDS region (below 2^16, a region
+// being at most 64 KiB).
 constexpr int kFusedLdsBytes = 64 * 1024;
 
 struct FusedParams {

@@ -1125,47 +1125,52 @@ __device__ __forceinline__ double wave_sum(double v) {
 // One output of a level: the sum over its contracted values of the products
 // of LDS operands, in table order (it: first two values; it2: the third and
 // fourth when there are four or more; pool: the rest, counted by pool[it.w]).
-__device__ __forceinline__ float2 item_value(const float2 *L, int4 it, int2 it2, const int32_t *__restrict__ pool) {
-    const uint32_t y = uint32_t(it.y), z = uint32_t(it.z);
-    const float2 x0 = L[y & 0xffffu], y0 = L[y >> 16];
-    const float2 x1 = L[z & 0xffffu], y1 = L[z >> 16];
-    float re = x0.x * y0.x;
+// Slots are byte offsets from L.
+__device__ __forceinline__ const float2 &lds_at(const float2 *L, uint32_t byte_off) {
+    return *reinterpret_cast<const float2 *>(reinterpret_cast<const char *>(L) + byte_off);
+}
+
+__device__ __forceinline__ void item_acc(const float2 *L, uint32_t w, float &re, float &im) {
+    const float2 xa = lds_at(L, w & 0xffffu), yb = lds_at(L, w >> 16);
+    re = fmaf(xa.x, yb.x, re);
+    re = fmaf(-xa.y, yb.y, re);
+    im = fmaf(xa.x, yb.y, im);
+    im = fmaf(xa.y, yb.x, im);
+}
+
+// Operands of two values are read together, before the products.
+__device__ __forceinline__ void item_acc2(const float2 *L, uint32_t u, uint32_t v, float &re, float &im) {
+    const float2 x0 = lds_at(L, u & 0xffffu), y0 = lds_at(L, u >> 16);
+    const float2 x1 = lds_at(L, v & 0xffffu), y1 = lds_at(L, v >> 16);
+    re = fmaf(x0.x, y0.x, re);
     re = fmaf(-x0.y, y0.y, re);
-    float im = x0.x * y0.y;
+    im = fmaf(x0.x, y0.y, im);
     im = fmaf(x0.y, y0.x, im);
     re = fmaf(x1.x, y1.x, re);
     re = fmaf(-x1.y, y1.y, re);
     im = fmaf(x1.x, y1.y, im);
     im = fmaf(x1.y, y1.x, im);
+}
+
+__device__ __forceinline__ float2 item_value(const float2 *L, int4 it, int2 it2, const int32_t *__restrict__ pool) {
+    float re = 0.f, im = 0.f;
+    item_acc2(L, uint32_t(it.y), uint32_t(it.z), re, im);
     if ((uint32_t(it.x) >> 16) > 2u) {
-        const uint32_t u = uint32_t(it2.x), v = uint32_t(it2.y);
-        const float2 x2 = L[u & 0xffffu], y2 = L[u >> 16];
-        const float2 x3 = L[v & 0xffffu], y3 = L[v >> 16];
-        re = fmaf(x2.x, y2.x, re);
-        re = fmaf(-x2.y, y2.y, re);
-        im = fmaf(x2.x, y2.y, im);
-        im = fmaf(x2.y, y2.x, im);
-        re = fmaf(x3.x, y3.x, re);
-        re = fmaf(-x3.y, y3.y, re);
-        im = fmaf(x3.x, y3.y, im);
-        im = fmaf(x3.y, y3.x, im);
+        item_acc2(L, uint32_t(it2.x), uint32_t(it2.y), re, im);
         if (it.w >= 0) {
             // Values past the fourth: their count is nk - 4 (also stored at
             // pool[it.w]); four slot pairs are loaded at a time, together.
             const int extra = int(uint32_t(it.x) >> 16) - 4;
+            // Indexes past the last value repeat it (never used), so every
+            // load is issued and consumed on every path.
             for (int j0 = 0; j0 < extra; j0 += 4) {
                 uint32_t w[4];
 #pragma unroll
-                for (int j = 0; j < 4; ++j) w[j] = j0 + j < extra ? uint32_t(pool[it.w + 1 + j0 + j]) : 0u;
+                for (int j = 0; j < 4; ++j) w[j] = uint32_t(pool[it.w + 1 + min(j0 + j, extra - 1)]);
+                asm volatile("" ::"v"(w[0]), "v"(w[1]), "v"(w[2]), "v"(w[3]));
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    if (j0 + j >= extra) break;
-                    const float2 xa = L[w[j] & 0xffffu], yb = L[w[j] >> 16];
-                    re = fmaf(xa.x, yb.x, re);
-                    re = fmaf(-xa.y, yb.y, re);
-                    im = fmaf(xa.x, yb.y, im);
-                    im = fmaf(xa.y, yb.x, im);
-                }
+                for (int j = 0; j < 4; ++j)
+                    if (j0 + j < extra) item_acc(L, w[j], re, im);
             }
         }
     }
@@ -1194,24 +1199,82 @@ fused_kernel(const int32_t *__restrict__ level_start, const int4 *__restrict__ i
     const int n_bs = 1 << S.m;
     const int64_t n_pairs = S.n_slices << S.m;
     const int64_t n_groups = (n_pairs + PAIRS - 1) / PAIRS;
-    // Before any work item: the level starts, one per lane (read back with
-    // readlane, no memory round trip per level, up to 63 levels), and each
-    // thread's first item, all work items being alike.
+    // The level starts, one per lane (read back with readlane, no memory
+    // round trip per level, up to 63 levels).  The table has n_levels + 1 >= 1
+    // entries; lanes past its end repeat the last, and lane 0 is read here on
+    // every path, so the load is known to be complete before the loops.
     const bool ls_in_lanes = S.n_levels < 64;
-    const int ls_lane = ls_in_lanes && lane <= S.n_levels ? level_start[lane] : 0;
+    const int ls_lane = level_start[min(lane, S.n_levels)];
     auto lstart = [&](int l) { return ls_in_lanes ? __builtin_amdgcn_readlane(ls_lane, l) : level_start[l]; };
-    int a0_first = 0, a1_first = 0;
-    if (S.n_levels > 0) {
-        a0_first = lstart(0);
-        a1_first = lstart(1);
-    }
+    const int first_item = __builtin_amdgcn_readlane(ls_lane, 0);
+    // Sixteen wavefronts per work item rotate three register sets of
+    // prefetched items (below); fewer wavefronts, for which that bookkeeping
+    // costs more than it hides, load each thread's next item one pass ahead,
+    // starting with its first item, loaded here (all work items are alike).
+    constexpr bool kRotate = W >= 16;
+    int a1_first = 0;
     int4 cur_first = make_int4(0, 0, 0, -1);
     int2 cur2_first = make_int2(0, 0);
-    if (a0_first + tid < a1_first) {
-        cur_first = items[a0_first + tid];
-        cur2_first = items2[a0_first + tid];
+    if constexpr (!kRotate) {
+        if (S.n_levels > 0) a1_first = lstart(1);
+        if (first_item + tid < a1_first) {
+            cur_first = items[first_item + tid];
+            cur2_first = items2[first_item + tid];
+        }
     }
+    // The levels run as a sequence of passes of NT items each; a level's last
+    // pass ends with a synchronisation.  take() loads the next pass's items
+    // (cursor: level cl, first item cs) and run() computes a loaded pass.
+    struct Pass {
+        int4 it;
+        int2 it2;
+        int i, end;
+        bool last, valid;
+    };
+    int cl = 0, cs = 0;
+    // take() has no branch on the cursor: past the last level it loads the
+    // last item again and marks the pass invalid.  Levels are never empty, so
+    // a thread past its level's end loads the level's last item (unused).
+    // Plans without levels never load.
+    const bool has_levels = S.n_levels > 0;
+    auto take = [&](Pass &f) {
+        f.valid = cl < S.n_levels;
+        const int e = lstart(min(cl + 1, S.n_levels));
+        f.i = cs + tid;
+        f.end = e;
+        f.last = cs + NT >= e;
+        if (has_levels) {
+            const int ii = min(f.i, e - 1);
+            f.it = items[ii];
+            f.it2 = items2[ii];
+        }
+        cl = f.valid && f.last ? cl + 1 : cl;
+        cs = !f.valid ? cs : f.last ? e : cs + NT;
+    };
+    auto run = [&](const Pass &f) {
+        // An empty statement that reads the pass's registers on every path,
+        // so their loads are complete here even in a wavefront without an
+        // item in this pass (the next load into the same registers then has
+        // nothing of theirs to wait for).
+        asm volatile("" ::"v"(f.it.x), "v"(f.it.y), "v"(f.it.z), "v"(f.it.w), "v"(f.it2.x), "v"(f.it2.y));
+        if (f.i < f.end) {
+#pragma unroll
+            for (int p = 0; p < PAIRS; ++p)
+                const_cast<float2 &>(lds_at(lds + p * S.pair_elems, uint32_t(f.it.x) & 0xffffu)) =
+                    item_value(lds + p * S.pair_elems, f.it, f.it2, pool);
+        }
+        if (f.last) step_sync();
+    };
     for (int64_t g = blockIdx.x; g < n_groups; g += gridDim.x) {
+        // With rotation, the first two passes' items are loaded before the
+        // leaves, so that their latency overlaps them.
+        Pass A, B, C;
+        if constexpr (kRotate) {
+            cl = 0;
+            cs = first_item;
+            take(A);
+            take(B);
+        }
         // Leaves of every pair: the pair-independent values in one coalesced
         // copy, then the elements whose base entry depends on slice or
         // bitstring bits.  A group past the last pair repeats the last pair.
@@ -1250,37 +1313,54 @@ fused_kernel(const int32_t *__restrict__ level_start, const int4 *__restrict__ i
             }
         }
         step_sync();
-        // Levels.  Each thread's next item (the next stretch of this level,
-        // or the first of the next level) is loaded before the current one is
-        // computed, so its latency overlaps that work.
-        int a0 = a0_first, a1 = a1_first;
-        int4 cur = cur_first;
-        int2 cur2 = cur2_first;
-        for (int lv = 0; lv < S.n_levels; ++lv) {
-            const int i0 = a0, i1 = a1;
-            const int b1 = lv + 2 <= S.n_levels ? lstart(lv + 2) : i1;
-            const int n_it = (i1 - i0 + NT - 1) / NT;
-            for (int t = 0; t < n_it; ++t) {
-                const int i = i0 + t * NT + tid;
-                const int nx = t + 1 < n_it ? i + NT : i1 + tid;
-                const int nx_end = t + 1 < n_it ? i1 : b1;
-                int4 nxt = make_int4(0, 0, 0, -1);
-                int2 nxt2 = make_int2(0, 0);
-                if (nx < nx_end) {
-                    nxt = items[nx];
-                    nxt2 = items2[nx];
-                }
-                if (i < i1) {
-#pragma unroll
-                    for (int p = 0; p < PAIRS; ++p)
-                        lds[p * S.pair_elems + (cur.x & 0xffff)] = item_value(lds + p * S.pair_elems, cur, cur2, pool);
-                }
-                cur = nxt;
-                cur2 = nxt2;
+        // Levels.  With rotation, three passes rotate through the register
+        // sets A, B, C: a pass's items are loaded two passes before they are
+        // used and read where they were loaded, so their latency overlaps two
+        // passes and their synchronisations.
+        if constexpr (kRotate) {
+            while (true) {
+                if (!A.valid) break;
+                take(C);
+                run(A);
+                if (!B.valid) break;
+                take(A);
+                run(B);
+                if (!C.valid) break;
+                take(B);
+                run(C);
             }
-            step_sync();
-            a0 = i1;
-            a1 = b1;
+        } else {
+            // Each thread's next item (the next stretch of this level, or the
+            // first of the next level) is loaded before the current one is
+            // computed.  Levels are never empty, so the clamped index is in
+            // range; a thread past the end loads the level's last item.
+            int a0 = first_item, a1 = a1_first;
+            int4 cur = cur_first;
+            int2 cur2 = cur2_first;
+            for (int lv = 0; lv < S.n_levels; ++lv) {
+                const int i0 = a0, i1 = a1;
+                const int b1 = lv + 2 <= S.n_levels ? lstart(lv + 2) : i1;
+                const int n_it = (i1 - i0 + NT - 1) / NT;
+                for (int t = 0; t < n_it; ++t) {
+                    const int i = i0 + t * NT + tid;
+                    const int nx = t + 1 < n_it ? i + NT : i1 + tid;
+                    const int nx_end = t + 1 < n_it ? i1 : b1;
+                    const int nxc = min(nx, nx_end - 1);
+                    const int4 nxt = items[nxc];
+                    const int2 nxt2 = items2[nxc];
+                    if (i < i1) {
+#pragma unroll
+                        for (int p = 0; p < PAIRS; ++p)
+                            const_cast<float2 &>(lds_at(lds + p * S.pair_elems, uint32_t(cur.x) & 0xffffu)) =
+                                item_value(lds + p * S.pair_elems, cur, cur2, pool);
+                    }
+                    cur = nxt;
+                    cur2 = nxt2;
+                }
+                step_sync();
+                a0 = i1;
+                a1 = b1;
+            }
         }
         if (out) {
             // The work item is one 64-slice block: its in-range values summed
@@ -1362,7 +1442,7 @@ __global__ void __launch_bounds__(64) fused_batch_kernel(const BatchReq *__restr
             for (int i = i0 + lane; i < i1; i += 64) {
                 const int4 it = R.items[i];
                 const int2 it2 = R.items2[i];
-                lds[it.x & 0xffff] = item_value(lds, it, it2, R.pool);
+                const_cast<float2 &>(lds_at(lds, uint32_t(it.x) & 0xffffu)) = item_value(lds, it, it2, R.pool);
             }
             wave_step_sync();
         }

@@ -399,7 +399,11 @@ bool ensure_device(const qc_plan *plan, Program &prog, bool fused, std::string &
         std::vector<std::vector<int4>> by_level(n_levels);
         std::vector<std::vector<int2>> by_level2(n_levels);
         std::vector<int32_t> pool;
-        auto pack = [](int64_t a, int64_t b) { return int32_t(uint32_t(a) | (uint32_t(b) << 16)); };
+        // Operand and output slots are stored as LDS byte offsets inside a
+        // pair's region (below 2^16, the region being at most 64 KiB).
+        auto pack = [](int64_t a, int64_t b) {
+            return int32_t(uint32_t(a * int64_t(sizeof(float2))) | (uint32_t(b * int64_t(sizeof(float2))) << 16));
+        };
         for (const GemmOp &g : prog.gemms) {
             const auto &LA = prog.tensors[g.a_src].layout, &LB = prog.tensors[g.b_src].layout;
             const auto &LC = prog.tensors[g.c].layout;
@@ -427,7 +431,7 @@ bool ensure_device(const qc_plan *plan, Program &prog, bool fused, std::string &
                 for (int p = 0; p < rc; ++p)
                     if ((c >> p) & 1) { a += sA[p]; b += sB[p]; }
                 int4 it;
-                it.x = int(uint32_t(prog.lds_offset[g.c] + c) | (uint32_t(nk) << 16));
+                it.x = int(uint32_t((prog.lds_offset[g.c] + c) * int64_t(sizeof(float2))) | (uint32_t(nk) << 16));
                 it.y = pack(a, b);
                 it.z = nk > 1 ? pack(a + ka[1], b + kb[1]) : pack(zero, zero);
                 it.w = -1;
