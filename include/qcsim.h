@@ -146,7 +146,11 @@ qc_status qc_plan_slice_assignment(const qc_plan *plan, uint64_t s, uint8_t *out
  * 2^log2_batch_bs bitstrings in flight: leaves (indices, base values),
  * steps (operands, layouts, GEMM shapes; c_nat names the tensor holding a
  * step's natural [batch][m][n] order when it writes its output scattered
- * into the layout of c) and per-step algorithmic flops/bytes.  Writes at most cap bytes to buf (NUL
+ * into the layout of c) and per-step algorithmic flops/bytes, and the fused
+ * form's state: fused_pairs and fused_waves (the timed work-item shape, 0
+ * before the first fused call), fused_slice_bits, fused_shape_set (the shape
+ * set by qc_plan_set_fused_shape, [0,0] if none) and fused_tuning (items,
+ * wavefronts, ms per timed shape).  Writes at most cap bytes to buf (NUL
  * terminated when it fits) and the full length to *len. */
 qc_status qc_plan_describe(qc_plan *plan, int32_t log2_batch_slices, int32_t log2_batch_bs,
                            qc_precision prec, char *buf, size_t cap, size_t *len);
@@ -217,6 +221,18 @@ qc_status qc_plan_set_graphs(qc_plan *plan, int32_t on);
  * fused requests of qc_contract_batch always run b = 0.  The choice is
  * reported as "fused_slice_bits" by qc_plan_describe. */
 qc_status qc_plan_set_fused_slice_bits(qc_plan *plan, int32_t b);
+
+/* Work-item shape of the fused form: items_per_workgroup work items, each
+ * run by waves_per_item wavefronts, one of (1,1), (2,1), (4,1), (1,2),
+ * (1,4), (1,8), (1,16); (0,0) (default) uses the shape timed on first use
+ * for each lowered program.  The shape changes the kernel's schedule, not
+ * what it computes (same bits), and is used by every later fused launch of
+ * the plan; a launch whose shape does not fit in LDS (more items per
+ * workgroup than the program's LDS region allows) fails with QC_ERR_DEVICE
+ * and a message.  QC_ERR_INVALID_ARG for any other pair.  The in-launch
+ * block sums of b = 6 need one item per workgroup.  The requests of
+ * qc_contract_batch are not affected. */
+qc_status qc_plan_set_fused_shape(qc_plan *plan, int32_t items_per_workgroup, int32_t waves_per_item);
 
 /* Autotuning (untimed preparation, like qc_plan_build).  Lowers the plan
  * for chunk_slices slices and n_bs bitstrings in flight (as

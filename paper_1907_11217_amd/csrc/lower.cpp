@@ -511,7 +511,9 @@ std::string describe_program(const qc_plan *plan, const Program &prog) {
               << '}';
         }
     }
-    o << "],\"fused_pairs\":" << prog.fused_pairs << ",\"fused_waves\":" << prog.fused_waves << ",\"fused_slice_bits\":" << plan->fused_b << ",\"fused_tuning\":[";
+    o << "],\"fused_pairs\":" << prog.fused_pairs << ",\"fused_waves\":" << prog.fused_waves << ",\"fused_slice_bits\":" << plan->fused_b
+      << ",\"fused_shape_set\":[" << plan->fused_force_pairs << ',' << plan->fused_force_waves << ']'
+      << ",\"fused_tuning\":[";
     for (size_t i = 0; i < prog.fused_tuning.size(); ++i)
         o << (i ? "," : "") << '[' << prog.fused_tuning[i][0] << ',' << prog.fused_tuning[i][1] << ','
           << prog.fused_tuning[i][2] << ']';

@@ -196,6 +196,8 @@ struct qc_plan {
     std::mutex dev_mu;
     bool use_graphs = true;
     int fused_b = -1;                     // slices in flight per fused work item (log2; -1: not timed yet)
+    int fused_force_pairs = 0;            // work-item shape set by the caller (0: the timed one)
+    int fused_force_waves = 0;
     void *capture_stream = nullptr;       // hipStream_t used only to capture graphs
 };
 

@@ -623,8 +623,17 @@ struct Prof {
 // A fused launch whose work items are exactly 64-slice blocks, one item per
 // workgroup, with one block of [lo, hi) per bitstring, adds its block sums to
 // the output itself (same butterfly and order as the reduction launch).
-bool block_sums_in_fused(const Program &prog, uint64_t sc, uint64_t lo, uint64_t hi) {
-    return prog.b == 6 && prog.fused_pairs == 1 && ((lo - sc) >> 6) == ((hi - 1 - sc) >> 6);
+bool block_sums_in_fused(const Program &prog, int pairs, uint64_t sc, uint64_t lo, uint64_t hi) {
+    return prog.b == 6 && pairs == 1 && ((lo - sc) >> 6) == ((hi - 1 - sc) >> 6);
+}
+
+// The work-item shape a fused launch of prog uses: the caller's, if set, else
+// the timed one.
+int fused_pairs_of(const qc_plan *plan, const Program &prog) {
+    return plan->fused_force_pairs > 0 ? plan->fused_force_pairs : prog.fused_pairs;
+}
+int fused_waves_of(const qc_plan *plan, const Program &prog) {
+    return plan->fused_force_pairs > 0 ? plan->fused_force_waves : prog.fused_waves;
 }
 
 // Kernel parameters of the fused form for slices [lo, hi) of super-chunk sc.
@@ -685,7 +694,13 @@ bool launch_all(qc_plan *plan, const Exec &x, uint64_t s_begin, uint64_t s_end, 
         if (x.fused) {
             FusedParams fp = fused_params(plan, prog, x, sc, lo, hi, bits, n_bs, partial);
             if (prog.fused_pairs == 0 && !tune_fused(prog, fp, st, err)) { plan->profiling = saved; return false; }
-            summed = block_sums_in_fused(prog, sc, lo, hi);
+            const int pairs = fused_pairs_of(plan, prog), waves = fused_waves_of(plan, prog);
+            if (fused_lds_bytes(pairs, pair_elems_of(prog)) > size_t(kFusedLdsBytes)) {
+                err = "the fused work-item shape set for this plan does not fit in LDS";
+                plan->profiling = saved;
+                return false;
+            }
+            summed = block_sums_in_fused(prog, pairs, sc, lo, hi);
             if (summed) {
                 fp.out = out_dev;
                 fp.per_slice = per_slice_dev;
@@ -694,7 +709,7 @@ bool launch_all(qc_plan *plan, const Exec &x, uint64_t s_begin, uint64_t s_end, 
                 fp.s_begin = s_begin;
             }
             prof.begin();
-            launch_fused_pairs(fp, prog.fused_pairs, prog.fused_waves, pair_elems_of(prog), zero_slot_of(prog), st);
+            launch_fused_pairs(fp, pairs, waves, pair_elems_of(prog), zero_slot_of(prog), st);
             prof.end("fused");
         } else {
             const uint64_t chunk = uint64_t(1) << prog.b;
@@ -838,7 +853,7 @@ bool choose_fused_b(qc_plan *plan, const Exec &x, uint64_t s_begin, const uint8_
         float ms = -1.f;
         for (auto &t : p->fused_tuning)
             if (ms < 0 || t[2] < ms) ms = t[2];
-        if (!block_sums_in_fused(*p, sc, sc, hi)) ms += reduce_ms;
+        if (!block_sums_in_fused(*p, fused_pairs_of(plan, *p), sc, sc, hi)) ms += reduce_ms;
         if (best_ms < 0 || ms < best_ms) { best_ms = ms; best_b = b; }
     }
     plan->fused_b = best_b;
@@ -1299,6 +1314,20 @@ extern "C" qc_status qc_plan_set_fused_slice_bits(qc_plan *plan, int32_t b) {
     }
     std::lock_guard<std::mutex> lk(plan->dev_mu);
     plan->fused_b = b;
+    return QC_OK;
+}
+
+extern "C" qc_status qc_plan_set_fused_shape(qc_plan *plan, int32_t items_per_workgroup, int32_t waves_per_item) {
+    bool ok = items_per_workgroup == 0 && waves_per_item == 0;
+    for (const auto &shape : qc::kFusedShapes)
+        ok = ok || (shape[0] == items_per_workgroup && shape[1] == waves_per_item);
+    if (!plan || !ok) {
+        set_error("qc_plan_set_fused_shape: invalid argument");
+        return QC_ERR_INVALID_ARG;
+    }
+    std::lock_guard<std::mutex> lk(plan->dev_mu);
+    plan->fused_force_pairs = items_per_workgroup;
+    plan->fused_force_waves = waves_per_item;
     return QC_OK;
 }
 

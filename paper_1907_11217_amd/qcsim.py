@@ -31,6 +31,7 @@ EXPORTED = (
     "qc_plan_set_exec", "qc_profile_enable", "qc_profile_read", "qc_contract_slices_dev", "qc_plan_set_graphs",
     "qc_tune", "qc_kernel_gemm_form", "qc_batch_workspace_bytes", "qc_contract_batch", "qc_wall_clock_khz",
     "qc_plan_export_steps", "qc_kernel_gemm_kparts", "qc_gemm_kparts", "qc_plan_set_fused_slice_bits",
+    "qc_plan_set_fused_shape",
 )
 EXEC_MODES = {"auto": 0, "fused": 1, "stepwise": 2}
 
@@ -153,6 +154,8 @@ def load(path: str | None = None):
         lib.qc_plan_set_graphs.restype = ctypes.c_int
         lib.qc_plan_set_fused_slice_bits.argtypes = [vp, ctypes.c_int32]
         lib.qc_plan_set_fused_slice_bits.restype = ctypes.c_int
+        lib.qc_plan_set_fused_shape.argtypes = [vp, ctypes.c_int32, ctypes.c_int32]
+        lib.qc_plan_set_fused_shape.restype = ctypes.c_int
         lib.qc_profile_enable.argtypes = [vp, ctypes.c_int32]
         lib.qc_profile_enable.restype = ctypes.c_int
         lib.qc_profile_read.argtypes = [vp, ctypes.POINTER(qc_kernel_stat_t), ctypes.c_int32,
@@ -330,6 +333,14 @@ def qc_plan_set_fused_slice_bits(plan: Plan, b: int = -1) -> None:
     """In-flight slice bits of the fused form (0..6), or -1 to time them on
     the first fused call."""
     _check(plan._lib.qc_plan_set_fused_slice_bits(plan.handle, int(b)), plan._lib)
+
+
+def qc_plan_set_fused_shape(plan: Plan, items_per_workgroup: int = 0, waves_per_item: int = 0) -> None:
+    """Work-item shape of the fused form: (items per workgroup, wavefronts
+    per item), one of (1,1), (2,1), (4,1), (1,2), (1,4), (1,8), (1,16);
+    (0, 0) returns to the shape timed on first use."""
+    _check(plan._lib.qc_plan_set_fused_shape(plan.handle, int(items_per_workgroup), int(waves_per_item)),
+           plan._lib)
 
 
 def qc_profile_enable(plan: Plan, on: bool = True) -> None:

@@ -156,6 +156,47 @@ def test_c2_fused_slice_bits_match_oracle(fb):
     assert np.array_equal(pps, ps[3:45, :5])
 
 
+FUSED_SHAPES = [(1, 1), (2, 1), (4, 1), (1, 2), (1, 4), (1, 8), (1, 16)]
+
+
+@pytest.mark.parametrize("fb", [0, 6])
+def test_c2_every_fused_shape_matches_oracle_with_the_same_bits(c2_setup, fb):
+    # Each work-item shape (items per workgroup x wavefronts per item) runs the
+    # same per-item arithmetic on another schedule (sixteen wavefronts rotate
+    # three register sets of prefetched items, fewer load one pass ahead), so
+    # every shape that fits in LDS gives the same bits, and they match the
+    # state vector and the oracle's sliced values; a shape that does not fit
+    # fails with an error before any launch.
+    lat, circ, bs, _plan, ref = c2_setup
+    plan = qcsim.qc_plan_build(lat.n, circ, bs[0], log2_slices=6, greedy_trials=8, seed=1)
+    qcsim.qc_plan_set_exec(plan, "fused")
+    qcsim.qc_plan_set_fused_slice_bits(plan, fb)
+    pair_elems = (qcsim.qc_plan_describe(plan, fb, 0)["lds_elems"] + 2) & ~1
+    segs = [tuple(int(v) for v in s) for s in qcsim.qc_plan_sliced_segments(plan)]
+    first = None
+    for shape in FUSED_SHAPES:
+        qcsim.qc_plan_set_fused_shape(plan, *shape)
+        assert qcsim.qc_plan_describe(plan, fb, 0)["fused_shape_set"] == list(shape)
+        if shape[0] * pair_elems * 8 > 64 * 1024:
+            say(f"c2 fused, {1 << fb} slices per work item, shape {shape}: does not fit, expect an error")
+            with pytest.raises(qcsim.QcError):
+                _contract(plan, bs[:4], 0, 64)
+            continue
+        say(f"c2 fused, {1 << fb} slices per work item, shape {shape}")
+        amps, ps = _contract(plan, bs, 0, 64, per_slice=True)
+        if first is None:
+            first = (shape, amps, ps)
+            check_amplitudes(amps, ref, lat.n, TOL_C64)
+            scale = np.sqrt(np.mean(np.abs(ps) ** 2))
+            for s, j in [(0, 0), (63, 7), (21, 40)]:
+                v = oracle.sliced_value(lat.n, circ, bs[j], segs, s)
+                assert abs(ps[s, j] - v) <= TOL_C64 * max(abs(v), scale), (s, j, ps[s, j], v)
+        else:
+            assert np.array_equal(ps, first[2]), (shape, first[0])
+            assert np.array_equal(amps, first[1]), (shape, first[0])
+    assert first is not None
+
+
 def test_fused_slice_bits_rejects_bad_values(c2_setup):
     _lat, _circ, _bs, plan, _ref = c2_setup
     with pytest.raises(qcsim.QcError):

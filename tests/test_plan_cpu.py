@@ -267,3 +267,17 @@ def test_export_steps_matches_description():
                 assert st["kind"] == 0 and (st["a"], st["c"]) == (op["src"], op["dst"]) and st["b"] == -1
     with pytest.raises(qcsim.QcError):
         qcsim.qc_plan_export_steps(plan, 7, 0)
+
+
+def test_fused_shape_setter_validates_and_is_described():
+    # The seven work-item shapes and (0, 0) are accepted and reported by
+    # qc_plan_describe; anything else is rejected and leaves the setting.
+    lat = synth.grid(2, 2)
+    plan = qcsim.qc_plan_build(lat.n, synth.random_circuit(lat, 2, 1), None, log2_slices=0)
+    for shape in [(1, 1), (2, 1), (4, 1), (1, 2), (1, 4), (1, 8), (1, 16), (0, 0), (1, 16)]:
+        qcsim.qc_plan_set_fused_shape(plan, *shape)
+        assert qcsim.qc_plan_describe(plan, 0, 0)["fused_shape_set"] == list(shape)
+    for bad in [(3, 1), (2, 2), (1, 32), (0, 1), (1, 0), (-1, 1), (8, 1), (2, 16)]:
+        with pytest.raises(qcsim.QcError):
+            qcsim.qc_plan_set_fused_shape(plan, *bad)
+    assert qcsim.qc_plan_describe(plan, 0, 0)["fused_shape_set"] == [1, 16]
