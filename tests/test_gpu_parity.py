@@ -156,6 +156,25 @@ def test_c2_fused_slice_bits_match_oracle(fb):
     assert np.array_equal(pps, ps[3:45, :5])
 
 
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("shape,depth,seed,k", [((4, 4), 12, 31, 2), ((4, 5), 14, 33, 3), ((5, 5), 16, 32, 4)])
+def test_paper_rule_circuits_match_state_vector(shape, depth, seed, k, mode):
+    # Circuits drawn with the paper's own single-qubit rule (a sqrt X or sqrt Y
+    # after a CZ, a T after a sqrt X, sqrt Y or H, nothing otherwise) through
+    # the same plan and entry points, with k sliced segments.
+    lat = synth.grid(*shape)
+    circ = synth.random_circuit(lat, depth, seed, rule="paper")
+    bs = synth.random_bitstrings(lat.n, 16, seed + 1)
+    plan = qcsim.qc_plan_build(lat.n, circ, bs[0], log2_slices=k, greedy_trials=8, seed=1)
+    assert qcsim.qc_plan_info(plan)["log2_slices"] == k
+    qcsim.qc_plan_set_exec(plan, mode)
+    say(f"paper-rule {shape[0]}x{shape[1]} d{depth} seed {seed}, 2^{k} slices x 16 bitstrings, {mode}")
+    amps = _contract(plan, bs, 0, 1 << k)
+    psi = oracle.statevector(lat.n, circ)
+    ref = np.array([psi[oracle.index_of(x)] for x in bs])
+    check_amplitudes(amps, ref, lat.n, TOL_C64)
+
+
 FUSED_SHAPES = [(1, 1), (2, 1), (4, 1), (1, 2), (1, 4), (1, 8), (1, 16)]
 
 
