@@ -1176,7 +1176,9 @@ extern "C" qc_status qc_contract_batch(const qc_request *reqs, int32_t n, qc_pre
     }
     const hipStream_t st = (hipStream_t)stream;
     char *w = (char *)ws;
+    hipEvent_t fork = nullptr;
     auto fail = [&](const std::string &m) {
+        if (fork) (void)hipEventDestroy(fork);
         set_error("qc_contract_batch: " + m);
         return QC_ERR_DEVICE;
     };
@@ -1184,35 +1186,22 @@ extern "C" qc_status qc_contract_batch(const qc_request *reqs, int32_t n, qc_pre
     qc::launch_stamp(t_done_dev + n, st);
     for (int32_t r = 0; r < n; ++r)
         if (reqs[r].s_begin == reqs[r].s_end) qc::launch_stamp(t_done_dev + r, st);
-    // Stepwise requests: round-robin over internal streams (each with its own
-    // workspace part) that start after the caller's prior work and that the
-    // caller's stream waits for at the end.
+    // Stepwise requests run on internal streams (each with its own workspace
+    // part) that start after the caller's prior work, marked here, before the
+    // fused launch, which they therefore do not wait for; the caller's stream
+    // waits for them at the end.
     std::vector<hipStream_t> streams;
     std::vector<hipEvent_t> events;
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return fail("no device");
     if (!L.stepwise.empty()) {
         if (!qc::batch_streams(dev, streams, err)) return fail(err);
-        hipEvent_t fork = nullptr;
         if (hipEventCreateWithFlags(&fork, hipEventDisableTiming) != hipSuccess || hipEventRecord(fork, st) != hipSuccess)
             return fail("event");
-        const int used = std::min<int>(qc::kBatchStreams, (int)L.stepwise.size());
-        for (int i = 0; i < used; ++i)
-            if (hipStreamWaitEvent(streams[i], fork, 0) != hipSuccess) return fail("stream wait");
-        (void)hipEventDestroy(fork);
-        for (size_t j = 0; j < L.stepwise.size(); ++j) {
-            const int r = L.stepwise[j];
-            const int i = int(j % used);
-            void *part = w + L.steps_off + size_t(i) * qc::align256(L.part_bytes);
-            qc::Exec x;
-            if (!qc::choose_exec(reqs[r].plan, 0, L.want[r], qc::prec_code(prec), L.part_bytes, x, err)) return fail(err);
-            if (!qc::enqueue(reqs[r].plan, x, reqs[r].s_begin, reqs[r].s_end, reqs[r].bitstring, false, 1, part,
-                             streams[i], out_dev + 2 * r, nullptr, err))
-                return fail(err);
-            qc::launch_stamp(t_done_dev + r, streams[i]);
-        }
     }
-    // Fused requests: one launch over every (request, slice) pair.
+    // Fused requests: one launch over every (request, slice) pair, enqueued
+    // before the stepwise requests so that the device starts these short
+    // requests first instead of queueing them behind long ones.
     if (!L.fused.empty()) {
         std::vector<qc::BatchReq> desc(L.fused.size());
         std::vector<uint8_t> bits(L.fused.size() * size_t(L.bits_stride), 0);
@@ -1261,8 +1250,37 @@ extern "C" qc_status qc_contract_batch(const qc_request *reqs, int32_t n, qc_pre
                                L.max_pair_elems, partial, done, t_done_dev, st);
         qc::launch_reduce_batch((const qc::BatchReq *)(w + L.desc_off), (int)L.fused.size(), partial, out_dev, st);
     }
+    if (!L.stepwise.empty()) {
+        const int used = std::min<int>(qc::kBatchStreams, (int)L.stepwise.size());
+        for (int i = 0; i < used; ++i)
+            if (hipStreamWaitEvent(streams[i], fork, 0) != hipSuccess) return fail("stream wait");
+        (void)hipEventDestroy(fork);
+        fork = nullptr;
+        // Dealt round-robin in order of increasing work (the lowered program's
+        // flops times its chunks), so that light requests do not wait behind
+        // heavy ones on the same stream.
+        std::vector<std::pair<double, int>> order;
+        for (const int r : L.stepwise) {
+            const int b = L.exec[r].prog->b;
+            const double chunks = double(((reqs[r].s_end - reqs[r].s_begin) + (uint64_t(1) << b) - 1) >> b);
+            order.push_back({L.exec[r].prog->flops * chunks, r});
+        }
+        std::stable_sort(order.begin(), order.end(),
+                         [](const std::pair<double, int> &x, const std::pair<double, int> &y) { return x.first < y.first; });
+        for (size_t j = 0; j < order.size(); ++j) {
+            const int r = order[j].second;
+            const int i = int(j % used);
+            void *part = w + L.steps_off + size_t(i) * qc::align256(L.part_bytes);
+            qc::Exec x;
+            if (!qc::choose_exec(reqs[r].plan, 0, L.want[r], qc::prec_code(prec), L.part_bytes, x, err)) return fail(err);
+            if (!qc::enqueue(reqs[r].plan, x, reqs[r].s_begin, reqs[r].s_end, reqs[r].bitstring, false, 1, part,
+                             streams[i], out_dev + 2 * r, nullptr, err))
+                return fail(err);
+            qc::launch_stamp(t_done_dev + r, streams[i]);
+        }
+    }
     // The caller's stream waits for the internal streams (after its own
-    // fused work, which thus overlaps them).
+    // fused work, which overlaps them).
     const int used = std::min<int>(qc::kBatchStreams, (int)L.stepwise.size());
     for (int i = 0; i < used; ++i) {
         hipEvent_t join = nullptr;
