@@ -54,16 +54,16 @@ qc_status qc_kernel_gemm_form(const void *A, const void *B, void *C, int64_t nb,
                               void *stream);
 
 /* qc_kernel_gemm_form split over k, as the stepwise contraction runs its
- * GEMM steps with few outputs: the large-tile forms (7, 12) and the dot form
- * (2) compute kparts partial products, part p over l in [p k/kparts,
+ * GEMM steps with few outputs: every MFMA form (3-12) and the dot form (2)
+ * compute kparts partial products, part p over l in [p k/kparts,
  * (p+1) k/kparts), into `scratch`, then C = the parts summed in increasing p,
  * in FP32 (so the result is deterministic).  scratch: caller-owned device
  * buffer of kparts * nb * m * n complex64, contents afterwards unspecified.
  * kparts: a power of two dividing k, at most 1024; 0 takes
  * qc_gemm_kparts(nb, m, n, k); 1 is qc_kernel_gemm_form (scratch may then be
  * NULL).  QC_ERR_UNSUPPORTED when kparts > 1 and the form (given, or the
- * default) is none of these three, kparts does not divide k, or scratch is
- * NULL. */
+ * default) is none of these, kparts does not divide k, the form does not
+ * apply to a part (k / kparts values of k), or scratch is NULL. */
 qc_status qc_kernel_gemm_kparts(const void *A, const void *B, void *C, int64_t nb, int64_t m, int64_t n, int64_t k,
                                 int32_t a_km, int32_t b_nk, qc_precision prec, int32_t form, int64_t kparts,
                                 void *scratch, void *scale_ws, void *stream);
@@ -71,9 +71,12 @@ qc_status qc_kernel_gemm_kparts(const void *A, const void *B, void *C, int64_t n
 /* The number of k parts the stepwise contraction uses for a GEMM step of this
  * shape when it runs a form that splits: for m and n multiples of 128 with
  * fewer than 1024 tiles of 128x128, the smallest power of two p <= 64 with at
- * least 1024 tiles times p, while each part keeps at least 256 of k; for at
- * most 4096 outputs and k >= 8192, the smallest power of two p with at least
- * 1024 outputs times p, while each part keeps at least 4096 of k; else 1.
+ * least 1024 tiles times p, while each part keeps at least 256 of k; else for
+ * m and n multiples of 32 with fewer than 4096 tiles of 32x32, the smallest
+ * power of two p <= 64 with at least 4096 tiles times p, while each part keeps
+ * at least 256 of k; else for at most 4096 outputs and k >= 8192, the
+ * smallest power of two p with at least 1024 outputs times p, while each part
+ * keeps at least 4096 of k; else 1.
  * The scratch for the largest such step is part of qc_workspace_bytes. */
 int64_t qc_gemm_kparts(int64_t nb, int64_t m, int64_t n, int64_t k);
 

@@ -459,8 +459,10 @@ __global__ void __launch_bounds__(64 * WM * WN) gemm_mfma_kernel(GemmDesc d) {
         const int64_t tn = tile % tiles_n;
         const int64_t tm = (tile / tiles_n) % tiles_m;
         const int64_t bi = tile / (tiles_n * tiles_m);
-        const float2 *Ab = d.A + bi * d.sAb + tm * TM * d.sAm;
-        const float2 *Bb = d.B + bi * d.sBb + tn * TN * d.sBn;
+        // With a split over k, batch entry bi is part bp of entry bq.
+        const int64_t bq = d.kparts == 1 ? bi : bi / d.kparts, bp = bi - bq * d.kparts;
+        const float2 *Ab = d.A + bq * d.sAb + bp * d.sAp + tm * TM * d.sAm;
+        const float2 *Bb = d.B + bq * d.sBb + bp * d.sBp + tn * TN * d.sBn;
         floatx16 acc_re, acc_im;
         for (int v = 0; v < 16; ++v) { acc_re[v] = 0.f; acc_im[v] = 0.f; }
         for (int64_t k0 = 0; k0 < d.k; k0 += KT) {
@@ -554,8 +556,10 @@ __global__ void __launch_bounds__(64 * WM * WN) gemm_split_kernel(GemmDesc d) {
         const int64_t tn = tile % tiles_n;
         const int64_t tm = (tile / tiles_n) % tiles_m;
         const int64_t bi = tile / (tiles_n * tiles_m);
-        const float2 *Ab = d.A + bi * d.sAb + tm * TM * d.sAm;
-        const float2 *Bb = d.B + bi * d.sBb + tn * TN * d.sBn;
+        // With a split over k, batch entry bi is part bp of entry bq.
+        const int64_t bq = d.kparts == 1 ? bi : bi / d.kparts, bp = bi - bq * d.kparts;
+        const float2 *Ab = d.A + bq * d.sAb + bp * d.sAp + tm * TM * d.sAm;
+        const float2 *Bb = d.B + bq * d.sBb + bp * d.sBp + tn * TN * d.sBn;
         floatx16 acc_re, acc_im;
         for (int v = 0; v < 16; ++v) { acc_re[v] = 0.f; acc_im[v] = 0.f; }
         for (int64_t k0 = 0; k0 < d.k; k0 += KT) {
@@ -1014,7 +1018,19 @@ const char *launch_gemm_kparts(const GemmDesc &d, int v, hipStream_t st) {
     e.sCb = d.m * d.n; e.sCm = d.n; e.sCn = 1;
     e.cscatter = 0;
     e.amax_c = nullptr;
-    const char *name = launch_big(e, v, st);
+    const char *split_name = d.prec == kPrecFP16 ? "gemm_split_fp16" : "gemm_split_bf16";
+    const char *name = "gemm_mfma";
+    switch (v) {
+        case kVarMfma11: launch_mfma<1, 1>(e, st); break;
+        case kVarMfma12: launch_mfma<1, 2>(e, st); break;
+        case kVarMfma21: launch_mfma<2, 1>(e, st); break;
+        case kVarMfma22: launch_mfma<2, 2>(e, st); break;
+        case kVarSplit11: launch_split<1, 1>(e, st); name = split_name; break;
+        case kVarSplit12: launch_split<1, 2>(e, st); name = split_name; break;
+        case kVarSplit21: launch_split<2, 1>(e, st); name = split_name; break;
+        case kVarSplit22: launch_split<2, 2>(e, st); name = split_name; break;
+        default: name = launch_big(e, v, st); break;
+    }
     const int64_t total = d.nb * d.m * d.n;
     int64_t grid = (total + 255) / 256;
     grid = grid > 2048 ? 2048 : grid;
@@ -1026,14 +1042,19 @@ const char *launch_gemm_kparts(const GemmDesc &d, int v, hipStream_t st) {
 const char *launch_gemm_variant(const GemmDesc &d, int v, hipStream_t st) {
     const char *split_name = d.prec == kPrecFP16 ? "gemm_split_fp16" : "gemm_split_bf16";
     switch (v) {
-        case kVarMfma11: launch_mfma<1, 1>(d, st); return "gemm_mfma";
-        case kVarMfma12: launch_mfma<1, 2>(d, st); return "gemm_mfma";
-        case kVarMfma21: launch_mfma<2, 1>(d, st); return "gemm_mfma";
-        case kVarMfma22: launch_mfma<2, 2>(d, st); return "gemm_mfma";
-        case kVarSplit11: launch_split<1, 1>(d, st); return split_name;
-        case kVarSplit12: launch_split<1, 2>(d, st); return split_name;
-        case kVarSplit21: launch_split<2, 1>(d, st); return split_name;
-        case kVarSplit22: launch_split<2, 2>(d, st); return split_name;
+        case kVarMfma11: case kVarMfma12: case kVarMfma21: case kVarMfma22:
+        case kVarSplit11: case kVarSplit12: case kVarSplit21: case kVarSplit22:
+            if (d.kparts > 1) return launch_gemm_kparts(d, v, st);
+            switch (v) {
+                case kVarMfma11: launch_mfma<1, 1>(d, st); return "gemm_mfma";
+                case kVarMfma12: launch_mfma<1, 2>(d, st); return "gemm_mfma";
+                case kVarMfma21: launch_mfma<2, 1>(d, st); return "gemm_mfma";
+                case kVarMfma22: launch_mfma<2, 2>(d, st); return "gemm_mfma";
+                case kVarSplit11: launch_split<1, 1>(d, st); return split_name;
+                case kVarSplit12: launch_split<1, 2>(d, st); return split_name;
+                case kVarSplit21: launch_split<2, 1>(d, st); return split_name;
+                default: launch_split<2, 2>(d, st); return split_name;
+            }
         case kVarMfmaBig: case kVarSplitBig:
             if (d.kparts > 1) return launch_gemm_kparts(d, v, st);
             return launch_big(d, v, st);

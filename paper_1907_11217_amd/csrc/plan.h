@@ -99,14 +99,19 @@ struct TransposeOp {
 
 // The number of k parts for a GEMM shape: large-tile shapes whose 128x128
 // tiles number fewer than 1024 (four per compute unit) are split into up to
-// 64 power-of-two parts, each of at least 256 k; shapes of at most 4096
-// outputs with k >= 8192 (the dot form's) into the smallest power of two
-// giving 1024 (output, part) workgroups, each part keeping at least 4096 k.
+// 64 power-of-two parts, each of at least 256 k; other shapes with m and n
+// multiples of 32 (the 32- and 64-wide MFMA forms) likewise while their
+// 32x32 tiles number fewer than 4096; shapes of at most 4096 outputs with
+// k >= 8192 (the dot form's) into the smallest power of two giving 1024
+// (output, part) workgroups, each part keeping at least 4096 k.
 inline int64_t gemm_kparts(int64_t nb, int64_t m, int64_t n, int64_t k) {
     int64_t p = 1;
     if (m % 128 == 0 && n % 128 == 0) {
         const int64_t tiles = nb * (m / 128) * (n / 128);
         while (tiles * p < 1024 && p < 64 && k % (2 * p) == 0 && k / (2 * p) >= 256) p *= 2;
+    } else if (m % 32 == 0 && n % 32 == 0) {
+        const int64_t tiles = nb * (m / 32) * (n / 32);
+        while (tiles * p < 4096 && p < 64 && k % (2 * p) == 0 && k / (2 * p) >= 256) p *= 2;
     } else if (nb * m * n <= 4096 && k >= 8192) {
         const int64_t outs = nb * m * n;
         while (outs * p < 1024 && k % (2 * p) == 0 && k / (2 * p) >= 4096) p *= 2;

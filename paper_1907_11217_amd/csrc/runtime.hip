@@ -1528,10 +1528,14 @@ extern "C" qc_status qc_kernel_gemm_kparts(const void *A, const void *B, void *C
     }
     const int v = form >= 0 ? form : qc::gemm_default_variant(d);
     if (kparts == 0) kparts = qc::gemm_kparts(nb, m, n, k);
-    const bool splits = v == qc::kVarMfmaBig || v == qc::kVarSplitBig || v == qc::kVarDot;
-    if (kparts > 1 && (!splits || k % kparts != 0 || !scratch)) {
-        set_error("qc_kernel_gemm_kparts: a split over k needs a large-tile or dot form, kparts dividing k and a "
-                  "scratch buffer");
+    // Every MFMA form and the dot form split over k; each part must itself
+    // be a product the form applies to.
+    const bool splits = v != qc::kVarValu && v != qc::kVarSkinny;
+    qc::GemmDesc part = d;
+    if (kparts > 1) part.k = k / kparts;
+    if (kparts > 1 && (!splits || k % kparts != 0 || !scratch || !qc::gemm_variant_ok(part, v))) {
+        set_error("qc_kernel_gemm_kparts: a split over k needs an MFMA or dot form, kparts dividing k with each "
+                  "part a product the form applies to, and a scratch buffer");
         return QC_ERR_UNSUPPORTED;
     }
     if (kparts > 1) {

@@ -422,7 +422,7 @@ def qc_kernel_gemm(A, B, C, nb: int, m: int, n: int, k: int, a_km: bool = False,
     scale_ws: optional int32 device tensor of >= 3 entries (required for
     split_fp16); afterwards it holds the float bits of max(|re|,|im|) of A, B
     and C.  form: a GEMM_FORMS value fixes the kernel form (-1: default).
-    kparts: split over k (large-tile forms; 0 = the library's rule for the
+    kparts: split over k (MFMA and dot forms; 0 = the library's rule for the
     shape) with `scratch` a complex64 device tensor of kparts * nb * m * n
     values (allocated here when not given)."""
     import torch

@@ -116,6 +116,24 @@ KSPLIT_SHAPES = [(1, 128, 128, 1024, 4), (2, 256, 128, 2048, 8), (3, 128, 256, 5
 @pytest.mark.parametrize("prec", ["c64", "split_bf16", "split_fp16"])
 @pytest.mark.parametrize("a_km,b_nk", [(0, 0), (1, 1), (1, 0)])
 def test_gemm_kparts(shape, prec, a_km, b_nk):
+    _check_kparts(shape, prec, a_km, b_nk, "mfma_big" if prec == "c64" else "split_big")
+
+
+# The 32- and 64-wide MFMA forms split over k: (nb, m, n, k, kparts, tile),
+# tile = the form's 32-multiples in m and n.
+KSPLIT_SMALL = [(1, 32, 64, 4096, 8, "12"), (2, 64, 64, 2048, 0, "22"), (3, 32, 32, 1024, 4, "11"),
+                (1, 64, 32, 8192, 16, "21")]
+
+
+@pytest.mark.parametrize("shape", KSPLIT_SMALL)
+@pytest.mark.parametrize("prec", ["c64", "split_bf16", "split_fp16"])
+@pytest.mark.parametrize("a_km,b_nk", [(0, 0), (1, 1), (1, 0)])
+def test_gemm_kparts_small_forms(shape, prec, a_km, b_nk):
+    *dims, tile = shape
+    _check_kparts(tuple(dims), prec, a_km, b_nk, ("mfma" if prec == "c64" else "split") + tile)
+
+
+def _check_kparts(shape, prec, a_km, b_nk, form_name):
     nb, m, n, k, kp = shape
     rng = np.random.default_rng(nb * 7 + m + n * 3 + k + kp + 5 * a_km + 11 * b_nk)
     A = _rand(rng, (nb, m, k)) * np.float32(2.0 ** -20)
@@ -124,14 +142,14 @@ def test_gemm_kparts(shape, prec, a_km, b_nk):
     b_store = B.transpose(0, 2, 1) if b_nk else B
     dA = torch.from_numpy(np.ascontiguousarray(a_store).reshape(-1)).cuda()
     dB = torch.from_numpy(np.ascontiguousarray(b_store).reshape(-1)).cuda()
-    form = qcsim.GEMM_FORMS["mfma_big" if prec == "c64" else "split_big"]
+    form = qcsim.GEMM_FORMS[form_name]
     parts = kp or qcsim.qc_gemm_kparts(nb, m, n, k)
     assert parts > 1
     scratch = torch.full((parts * nb * m * n,), float("nan"), dtype=torch.complex64, device="cuda")
     slots = torch.zeros(3, dtype=torch.int32, device="cuda")
     dC = torch.full((nb * m * n,), float("nan"), dtype=torch.complex64, device="cuda")
     dC1 = torch.full((nb * m * n,), float("nan"), dtype=torch.complex64, device="cuda")
-    say(f"gemm {prec} split over k: nb={nb} m={m} n={n} k={k} kparts={kp} a_km={a_km} b_nk={b_nk}")
+    say(f"gemm {prec} {form_name} split over k: nb={nb} m={m} n={n} k={k} kparts={kp} a_km={a_km} b_nk={b_nk}")
     qcsim.qc_kernel_gemm(dA, dB, dC, nb, m, n, k, a_km, b_nk, prec=prec, scale_ws=slots, form=form, kparts=kp,
                          scratch=scratch)
     qcsim.qc_kernel_gemm(dA, dB, dC1, nb, m, n, k, a_km, b_nk, prec=prec, scale_ws=None if prec == "c64" else
@@ -183,9 +201,11 @@ def test_gemm_kparts_rejects_bad_arguments():
     nb, m, n, k = 1, 128, 128, 1024
     d = torch.zeros(nb * max(m, n) * k, dtype=torch.complex64, device="cuda")
     scratch = torch.zeros(128 * m * n, dtype=torch.complex64, device="cuda")
-    for form, kp in [("mfma_big", 3), ("mfma22", 4), ("valu", 2)]:
+    # Not a power of two; parts of one k value, which the form does not take;
+    # a form without a split over k.
+    for form, kp, kk in [("mfma_big", 3, k), ("mfma22", 64, 64), ("valu", 2, k)]:
         with pytest.raises(qcsim.QcError):
-            qcsim.qc_kernel_gemm(d, d, d, nb, m, n, k, prec="c64", form=qcsim.GEMM_FORMS[form], kparts=kp,
+            qcsim.qc_kernel_gemm(d, d, d, nb, m, n, kk, prec="c64", form=qcsim.GEMM_FORMS[form], kparts=kp,
                                  scratch=scratch)
     with pytest.raises(qcsim.QcError):  # 16 parts do not divide k = 24
         qcsim.qc_kernel_gemm(d, d, d, nb, m, n, 24, prec="c64", form=qcsim.GEMM_FORMS["mfma_big"], kparts=16,

@@ -44,7 +44,6 @@ def test_gemm_kparts_rule():
     assert qcsim.qc_gemm_kparts(2, 128, 2048, 8192) == 32
     assert qcsim.qc_gemm_kparts(4, 256, 2048, 1024) == 4
     assert qcsim.qc_gemm_kparts(4, 1024, 4096, 1024) == 1
-    assert qcsim.qc_gemm_kparts(1, 96, 128, 4096) == 1
     assert qcsim.qc_gemm_kparts(1, 128, 128, 1 << 20) == 64
     assert qcsim.qc_gemm_kparts(1, 128, 128, 384) == 1
     assert qcsim.qc_gemm_kparts(1, 128, 128, 768) == 2
@@ -53,7 +52,17 @@ def test_gemm_kparts_rule():
     assert qcsim.qc_gemm_kparts(1, 1, 1, 1 << 21) == 512
     assert qcsim.qc_gemm_kparts(4, 8, 8, 16384) == 4
     assert qcsim.qc_gemm_kparts(1, 1, 1, 4096) == 1
-    assert qcsim.qc_gemm_kparts(1, 64, 128, 1 << 20) == 1
+    # Shapes of the 32- and 64-wide MFMA forms: fewer than 4096 tiles of
+    # 32x32, parts of at least 256 k, at most 64 parts; 32-aligned shapes
+    # take this rule even with few outputs.
+    assert qcsim.qc_gemm_kparts(1, 96, 128, 4096) == 16
+    assert qcsim.qc_gemm_kparts(1, 64, 128, 1 << 20) == 64
+    assert qcsim.qc_gemm_kparts(4, 32, 256, 16384) == 64
+    assert qcsim.qc_gemm_kparts(4, 64, 32768, 32) == 1
+    assert qcsim.qc_gemm_kparts(64, 64, 64, 1024) == 4
+    assert qcsim.qc_gemm_kparts(64, 64, 64, 256) == 1
+    assert qcsim.qc_gemm_kparts(16, 64, 64, 512) == 2
+    assert qcsim.qc_gemm_kparts(1, 32, 32, 16384) == 64
 
 
 def test_workspace_holds_split_over_k_scratch():
