@@ -8,6 +8,7 @@
 // they act on, so one index can join many tensors.
 #pragma once
 
+#include <atomic>
 #include <array>
 #include <complex>
 #include <cstdint>
@@ -152,6 +153,7 @@ struct Program {
     // Fused form: the same steps without transposes, every tensor in LDS.
     std::vector<int64_t> lds_offset;      // per program tensor (-1 if not used by the fused form)
     int64_t lds_elems = 0;
+    mutable std::atomic<int> fused_fit{-1};  // whether the fused form fits (-1: not known yet)
     // Device constants, created lazily on the device current at first use.
     int device = -1;
     void *d_leaf_desc = nullptr;
@@ -174,6 +176,7 @@ struct Program {
     int n_pool = 0;
     int fused_pairs = 0;                  // work items per workgroup chosen by timing (0 = not tuned yet)
     int fused_waves = 1;                  // wavefronts per work item chosen by timing
+    int fused_best = 0;                   // entry of fused_tuning chosen
     std::vector<std::array<float, 3>> fused_tuning;  // (work items, wavefronts, ms) measured when tuning
     // Launch sequences captured as HIP graphs, keyed by everything the
     // captured kernel arguments depend on (buffers, range, batch, precision).
