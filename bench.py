@@ -83,7 +83,9 @@ def _events_ms(stream, fn, reps):
 def batch_leg(n_req=256, seed=501, cap=24, reps=3, n_oracle=6, trials=32, precs=("c64", "split_fp16")):
     """Uneven batch of requests (4x4 d12, 5x5 d16, 6x6 d20, 7x7 d24 drawn
     uniformly), each with its own plan (the smallest slice count meeting a
-    2^cap-entry cap) and bitstring, in one qc_contract_batch call per step."""
+    2^cap-entry cap) and bitstring, in one qc_contract_batch call per step; the
+    stepwise requests' GEMM forms are tuned beforehand (untimed, like the plan
+    build)."""
     import numpy as np
     import torch
 
@@ -111,6 +113,17 @@ def batch_leg(n_req=256, seed=501, cap=24, reps=3, n_oracle=6, trials=32, precs=
                        for f in sorted(set(fam_of))}
     ref = None
     for prec in precs:
+        # Untimed preparation, like the plan build: the GEMM forms of each
+        # stepwise request's program are timed (qc_tune keeps its choices per
+        # shape for the process, so a shape met again is not timed again).
+        t1 = time.perf_counter()
+        chunk = [1 << min(k, 12) for k in ks]
+        tws = torch.empty(max(qcsim.qc_workspace_bytes(p, c, 1, prec) for (p, _), c in zip(items, chunk)),
+                          dtype=torch.uint8, device="cuda")
+        n_timed = sum(qcsim.qc_tune(p, c, 1, prec, tws, stream=stream) for (p, _), c in zip(items, chunk))
+        torch.cuda.synchronize()
+        del tws
+        tune_s = time.perf_counter() - t1
         ws = torch.empty(qcsim.qc_batch_workspace_bytes(batch, prec), dtype=torch.uint8, device="cuda")
         out = torch.zeros(n_req, 2, dtype=torch.float64, device="cuda")
         tdone = torch.zeros(n_req + 1, dtype=torch.int64, device="cuda")
@@ -127,7 +140,8 @@ def batch_leg(n_req=256, seed=501, cap=24, reps=3, n_oracle=6, trials=32, precs=
         torch.cuda.synchronize()
         t = tdone.cpu().numpy()
         done_ms = (t[:-1] - t[-1]) / khz
-        r = {"ms_per_batch": ms, "amplitudes_per_s": n_req / (ms * 1e-3),
+        r = {"ms_per_batch": ms, "amplitudes_per_s": n_req / (ms * 1e-3), "tune_seconds": tune_s,
+             "shapes_timed": n_timed,
              "completion_ms": {"p50": float(np.percentile(done_ms, 50)), "p99": float(np.percentile(done_ms, 99)),
                                "max": float(done_ms.max())},
              "family_max_completion_ms": {f: float(max(d for g, d in zip(fam_of, done_ms) if g == f))
