@@ -179,6 +179,31 @@ typedef struct {
 qc_status qc_plan_export_steps(qc_plan *plan, int32_t log2_batch_slices, int32_t log2_batch_bs, qc_step_t *out,
                                int32_t cap, int32_t *n);
 
+/* The plan's pairwise contraction tree in the circuit's own terms, so that
+ * it can be followed by code that shares nothing with this library (the
+ * tree is data: any valid tree gives the same value, up to rounding, since
+ * the value of a network does not depend on the order of its pairwise
+ * contractions).  The circuit's tensors are numbered t < n_qubits for qubit
+ * t's input state <0| ... |0> factor and n_qubits + g for gate g of the
+ * circuit as given to qc_plan_build (H, sqrt X, sqrt Y: U[new][old] between
+ * consecutive segments; T: a vector on its segment; CZ: a 2x2 tensor on two
+ * segments).  Output segments are fixed to x[q] and sliced segments to the
+ * slice's bits; they are not tensors here.
+ *   *n_leaves: L, the number of simplified tensors the order was chosen on;
+ *   *n_tensors: n_qubits + number of gates;
+ *   origin_offsets (optional, L + 1 int32) and origin_ids (optional,
+ *     *n_tensors int32): leaf l consists of the circuit tensors
+ *     origin_ids[origin_offsets[l] .. origin_offsets[l + 1]) (every circuit
+ *     tensor in exactly one leaf);
+ *   merges (optional, 2 (L - 1) int32): merge i combines nodes merges[2 i]
+ *     and merges[2 i + 1], where nodes < L are leaves and node L + i is the
+ *     result of merge i; the last merge yields the slice value.
+ * This is the tree before the plan evaluates its pair-invariant subtrees on
+ * the host (those subtrees are part of it).  Call with NULL arrays first to
+ * learn the sizes.  Host only; QC_ERR_INVALID_ARG on NULL plan or counts. */
+qc_status qc_plan_export_tree(const qc_plan *plan, int32_t *n_leaves, int32_t *n_tensors,
+                              int32_t *origin_offsets, int32_t *origin_ids, int32_t *merges);
+
 /* How qc_contract_slices runs the program:
  *   QC_EXEC_AUTO (default): fused when one (slice, bitstring) contraction
  *     fits in LDS and prec is QC_C64, else stepwise;

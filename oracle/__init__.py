@@ -28,6 +28,7 @@ against closed forms, brute force and invariants; see the test docstrings.
 from .gates import gate_matrix, ORACLE_GATES
 from .statevector import statevector, amplitudes_sv, index_of
 from .pathsum import pathsum_amplitude
+from .hyper import hyper_network, hyper_value, contract_tree, contract_greedy, validate_tree
 from .tn import (
     build_plain_network, contract_network, tn_amplitude, sliced_value,
     segment_counts,
@@ -36,5 +37,6 @@ from .tn import (
 __all__ = [
     "gate_matrix", "ORACLE_GATES", "statevector", "amplitudes_sv", "index_of",
     "pathsum_amplitude", "build_plain_network", "contract_network",
-    "tn_amplitude", "sliced_value", "segment_counts",
+    "tn_amplitude", "sliced_value", "segment_counts", "hyper_network", "hyper_value",
+    "contract_tree", "contract_greedy", "validate_tree",
 ]

@@ -163,6 +163,28 @@ extern "C" qc_status qc_plan_export_steps(qc_plan *plan, int32_t log2_batch_slic
     return QC_OK;
 }
 
+extern "C" qc_status qc_plan_export_tree(const qc_plan *plan, int32_t *n_leaves, int32_t *n_tensors,
+                                         int32_t *origin_offsets, int32_t *origin_ids, int32_t *merges) {
+    if (!plan || !n_leaves || !n_tensors) { set_error("qc_plan_export_tree: NULL argument"); return QC_ERR_INVALID_ARG; }
+    const int L = (int)plan->origin_full.size();
+    *n_leaves = L;
+    *n_tensors = plan->net.n_orig;
+    if (origin_offsets && origin_ids) {
+        int32_t off = 0;
+        for (int t = 0; t < L; ++t) {
+            origin_offsets[t] = off;
+            for (int g : plan->origin_full[t]) origin_ids[off++] = g;
+        }
+        origin_offsets[L] = off;
+    }
+    if (merges)
+        for (size_t i = 0; i < plan->tree_full.size(); ++i) {
+            merges[2 * i] = plan->tree_full[i].a;
+            merges[2 * i + 1] = plan->tree_full[i].b;
+        }
+    return QC_OK;
+}
+
 extern "C" qc_status qc_plan_set_exec(qc_plan *plan, int32_t mode) {
     if (!plan || mode < QC_EXEC_AUTO || mode > QC_EXEC_STEPWISE) {
         set_error("qc_plan_set_exec: invalid argument");

@@ -50,6 +50,7 @@ bool build_network(const qc_circuit &c, Network &net, std::string &err) {
     for (int q = 0; q < n; ++q) {
         cur[q] = new_index(q, 0);
         net.leaves.push_back(Tensor{{cur[q]}, {cplx(1), cplx(0)}});
+        net.origin.push_back({q});
     }
     for (int g = 0; g < c.n_gates; ++g) {
         const qc_gate &gt = c.gates[g];
@@ -81,7 +82,9 @@ bool build_network(const qc_circuit &c, Network &net, std::string &err) {
             err = "gate " + std::to_string(g) + ": unknown kind " + std::to_string(gt.kind);
             return false;
         }
+        net.origin.push_back({n + g});
     }
+    net.n_orig = n + c.n_gates;
     for (int q = 0; q < n; ++q) net.out_qubit[cur[q]] = q;
     return true;
 }
@@ -161,6 +164,8 @@ void simplify_network(Network &net, const std::vector<int> &keep) {
                     for (int f : T[b].idx) holders[f].erase(b);
                     alive[b] = 0;
                     T[a] = std::move(C);
+                    net.origin[a].insert(net.origin[a].end(), net.origin[b].begin(), net.origin[b].end());
+                    net.origin[b].clear();
                     for (int f : T[a].idx) holders[f].insert((int)a);
                     merged = changed = true;
                     break;
@@ -171,9 +176,15 @@ void simplify_network(Network &net, const std::vector<int> &keep) {
         }
     }
     std::vector<Tensor> out;
+    std::vector<std::vector<int>> origin;
     for (size_t t = 0; t < T.size(); ++t)
-        if (alive[t]) out.push_back(std::move(T[t]));
+        if (alive[t]) {
+            out.push_back(std::move(T[t]));
+            std::sort(net.origin[t].begin(), net.origin[t].end());
+            origin.push_back(std::move(net.origin[t]));
+        }
     T = std::move(out);
+    net.origin = std::move(origin);
 }
 
 }  // namespace qc

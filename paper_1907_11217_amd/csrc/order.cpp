@@ -343,20 +343,30 @@ static void fold_invariant_subtrees(qc_plan *plan, const std::vector<char> &dyn_
         val[a] = Tensor();
         val[b] = Tensor();
     }
+    // Circuit tensors under every node (for the folded leaves' origin).
+    std::vector<std::vector<int>> under(L + M);
+    for (int t = 0; t < L; ++t) under[t] = plan->net.origin[t];
+    for (int i = 0; i < M; ++i) {
+        under[L + i] = under[plan->tree[i].a];
+        under[L + i].insert(under[L + i].end(), under[plan->tree[i].b].begin(), under[plan->tree[i].b].end());
+    }
     std::vector<Tensor> leaves;
-    std::vector<std::vector<int>> leaf_idx;
+    std::vector<std::vector<int>> leaf_idx, origin;
     std::vector<int> new_id(L + M, -1);
     for (int t = 0; t < L; ++t)
         if (!inside[t]) {
             new_id[t] = (int)leaves.size();
             leaves.push_back(plan->net.leaves[t]);
             leaf_idx.push_back(p.leaf_idx[t]);
+            origin.push_back(plan->net.origin[t]);
         }
     for (int n = L; n < L + M; ++n)
         if (top[n]) {
             new_id[n] = (int)leaves.size();
             leaves.push_back(std::move(val[n]));
             leaf_idx.push_back(sets[n]);
+            std::sort(under[n].begin(), under[n].end());
+            origin.push_back(under[n]);
         }
     const int L2 = (int)leaves.size();
     std::vector<Merge> tree;
@@ -368,6 +378,7 @@ static void fold_invariant_subtrees(qc_plan *plan, const std::vector<char> &dyn_
     }
     plan->info.n_folded_steps = M - (int)tree.size();
     plan->net.leaves = std::move(leaves);
+    plan->net.origin = std::move(origin);
     p.leaf_idx = std::move(leaf_idx);
     plan->tree = std::move(tree);
 }
@@ -524,6 +535,8 @@ bool search_plan(qc_plan *plan, const qc_slice_spec *spec, std::string &err) {
     }
     plan->tree = best_tree;
     plan->sliced = best_sliced;
+    plan->tree_full = best_tree;
+    plan->origin_full = plan->net.origin;
     fold_invariant_subtrees(plan, dyn_leaf);
     std::vector<char> rm2(plan->prob.n_index, 0);
     for (int e : plan->sliced) rm2[e] = 1;

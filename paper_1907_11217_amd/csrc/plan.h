@@ -41,6 +41,10 @@ struct Network {
     std::vector<int> out_qubit;         // per index: q if it is q's output segment, else -1
     std::vector<int> n_cut;             // per qubit: non-diagonal gate count
     std::vector<Tensor> leaves;         // simplified tensors
+    // Per leaf: the circuit's tensors merged into it, numbered t < n_qubits for
+    // qubit t's input state and n_qubits + g for gate g.
+    std::vector<std::vector<int>> origin;
+    int n_orig = 0;                     // n_qubits + number of gates
     int n_index() const { return (int)seg_q.size(); }
     int find_segment(int q, int ord) const;
 };
@@ -190,6 +194,10 @@ struct qc_plan {
     qc::OrderProblem prob;
     std::vector<qc::Merge> tree;
     std::vector<int> sliced;              // index ids in slice-bit order
+    // The chosen tree before host folding of pair-invariant subtrees, over the
+    // simplified leaves it was searched on (qc_plan_export_tree).
+    std::vector<qc::Merge> tree_full;
+    std::vector<std::vector<int>> origin_full;
     std::vector<uint8_t> default_bitstring;
     qc_plan_info_t info{};
     int exec_mode = QC_EXEC_AUTO;

@@ -31,7 +31,7 @@ EXPORTED = (
     "qc_plan_set_exec", "qc_profile_enable", "qc_profile_read", "qc_contract_slices_dev", "qc_plan_set_graphs",
     "qc_tune", "qc_kernel_gemm_form", "qc_batch_workspace_bytes", "qc_contract_batch", "qc_wall_clock_khz",
     "qc_plan_export_steps", "qc_kernel_gemm_kparts", "qc_gemm_kparts", "qc_plan_set_fused_slice_bits",
-    "qc_plan_set_fused_shape",
+    "qc_plan_set_fused_shape", "qc_plan_export_tree",
 )
 EXEC_MODES = {"auto": 0, "fused": 1, "stepwise": 2}
 
@@ -148,6 +148,9 @@ def load(path: str | None = None):
         lib.qc_plan_export_steps.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(qc_step_t),
                                              ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
         lib.qc_plan_export_steps.restype = ctypes.c_int
+        pi32 = ctypes.POINTER(ctypes.c_int32)
+        lib.qc_plan_export_tree.argtypes = [vp, pi32, pi32, pi32, pi32, pi32]
+        lib.qc_plan_export_tree.restype = ctypes.c_int
         lib.qc_wall_clock_khz.argtypes = [ctypes.POINTER(ctypes.c_int32)]
         lib.qc_wall_clock_khz.restype = ctypes.c_int
         lib.qc_plan_set_graphs.argtypes = [vp, ctypes.c_int32]
@@ -315,6 +318,23 @@ def qc_plan_export_steps(plan: Plan, log2_batch_slices: int = 0, log2_batch_bs: 
     _check(plan._lib.qc_plan_export_steps(plan.handle, log2_batch_slices, log2_batch_bs, rows, n.value,
                                           ctypes.byref(n)), plan._lib)
     return [{f: getattr(rows[i], f) for f, _ in qc_step_t._fields_} for i in range(n.value)]
+
+
+def qc_plan_export_tree(plan: Plan):
+    """The plan's contraction tree in circuit terms: (groups, merges), groups[l]
+    the circuit tensor ids of leaf l (t < n_qubits: input of qubit t; n_qubits
+    + g: gate g), merges an int32 [L - 1, 2] array of node ids (leaves first,
+    then merge results)."""
+    L, T = ctypes.c_int32(0), ctypes.c_int32(0)
+    _check(plan._lib.qc_plan_export_tree(plan.handle, ctypes.byref(L), ctypes.byref(T), None, None, None), plan._lib)
+    offs = np.zeros(L.value + 1, dtype=np.int32)
+    ids = np.zeros(max(1, T.value), dtype=np.int32)
+    merges = np.zeros((max(1, L.value - 1), 2), dtype=np.int32)
+    i32p = ctypes.POINTER(ctypes.c_int32)
+    _check(plan._lib.qc_plan_export_tree(plan.handle, ctypes.byref(L), ctypes.byref(T), offs.ctypes.data_as(i32p),
+                                         ids.ctypes.data_as(i32p), merges.ctypes.data_as(i32p)), plan._lib)
+    groups = [ids[offs[i]:offs[i + 1]].tolist() for i in range(L.value)]
+    return groups, merges[:max(0, L.value - 1)]
 
 
 def qc_wall_clock_khz() -> int:
