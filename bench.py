@@ -82,8 +82,8 @@ def _events_ms(stream, fn, reps):
 
 def batch_leg(n_req=256, seed=501, cap=24, reps=3, n_oracle=6, trials=32, precs=("c64", "split_fp16")):
     """Uneven batch of requests (4x4 d12, 5x5 d16, 6x6 d20, 7x7 d24 drawn
-    uniformly), each with its own plan (the smallest slice count meeting a
-    2^cap-entry cap) and bitstring, in one qc_contract_batch call per step; the
+    uniformly), each with its own plan (its drawn slice count 2^0..2^12, more
+    where the 2^cap-entry cap needs it) and bitstring, in one qc_contract_batch call per step; the
     stepwise requests' GEMM forms are tuned beforehand (untimed, like the plan
     build)."""
     import numpy as np
@@ -97,8 +97,8 @@ def batch_leg(n_req=256, seed=501, cap=24, reps=3, n_oracle=6, trials=32, precs=
     items, ks = [], []
     for r in reqs:
         lat = r["lattice"]
-        plan = qcsim.qc_plan_build(lat.n, r["circuit"], r["bitstring"], log2_slices=-1, log2_max_entries=cap,
-                                   greedy_trials=trials, seed=1)
+        plan = qcsim.qc_plan_build(lat.n, r["circuit"], r["bitstring"], log2_slices=r["log2_slices"],
+                                   log2_max_entries=cap, greedy_trials=trials, seed=1)
         ks.append(qcsim.qc_plan_info(plan)["log2_slices"])
         items.append((plan, r["bitstring"]))
     plan_s = time.perf_counter() - t0
@@ -106,7 +106,8 @@ def batch_leg(n_req=256, seed=501, cap=24, reps=3, n_oracle=6, trials=32, precs=
     stream = torch.cuda.current_stream()
     khz = qcsim.qc_wall_clock_khz()
     leg = {"workload": (f"{n_req} requests drawn uniformly from 4x4 d12 / 5x5 d16 / 6x6 d20 / 7x7 d24 "
-                        f"(seed {seed}), one bitstring each, plans capped at 2^{cap} entries"),
+                        f"(seed {seed}), one bitstring each, 2^0..2^12 slices each (drawn), plans capped at 2^{cap} "
+                        f"entries"),
            "plan_seconds": plan_s, "per_prec": {}}
     fam_of = ["%dx%d_d%d" % r["family"] for r in reqs]
     leg["families"] = {f: {"count": fam_of.count(f), "k": sorted({k for g, k in zip(fam_of, ks) if g == f})}
@@ -166,7 +167,12 @@ def batch_leg(n_req=256, seed=501, cap=24, reps=3, n_oracle=6, trials=32, precs=
     return leg
 
 
-PLAN_TRIALS = {"c1": 8, "c2": 8, "c3": 8, "c4": 256}   # greedy restarts of the order search (untimed)
+def _plan_trials():
+    import synth
+    return {k: v["trials"] for k, v in synth.CONFIGS.items()}
+
+
+PLAN_TRIALS = _plan_trials()   # greedy restarts of the order search (untimed)
 
 
 def first_nonzero_slice(key, candidates):

@@ -277,16 +277,22 @@ qc_status qc_tune(qc_plan *plan, int64_t chunk_slices, int32_t n_bs, qc_precisio
 /* Kernel timing.  While enabled, qc_contract_slices records a pair of HIP
  * events on its stream around every kernel it launches.  qc_profile_read
  * waits for the recorded events, then reports per kernel kind the launch
- * count and the summed event-to-event milliseconds since the last read (and
- * clears them).  kinds: "fused", "leaves", "micro", "transpose",
+ * count, the summed event-to-event milliseconds and the summed algorithmic
+ * flops of those launches (8 nb m n k per GEMM step, the micro launch's
+ * steps likewise; 0 for kinds that do no GEMM work) since the last read,
+ * and clears them.  kinds: "fused", "leaves", "micro", "transpose",
  * "gemm_mfma", "gemm_split_bf16", "gemm_split_fp16", "gemm_skinny",
  * "gemm_dot", "gemm_valu", "reduce64" (a GEMM step split over k counts its
- * partial products and their sum under its form's kind).  Not
- * thread-safe across concurrent calls on one plan. */
+ * partial products and their sum under its form's kind), so the kinds show
+ * which form -- and for split precisions whether a split MFMA form or a
+ * complex FP32 one -- ran each step.  Launches replayed from a graph are not
+ * timed (calls with timing on launch directly).  Not thread-safe across
+ * concurrent calls on one plan. */
 typedef struct {
     char kind[16];
     int64_t launches;
     double total_ms;
+    double flops;
 } qc_kernel_stat_t;
 qc_status qc_profile_enable(qc_plan *plan, int32_t on);
 qc_status qc_profile_read(qc_plan *plan, qc_kernel_stat_t *out, int32_t cap, int32_t *n);

@@ -30,8 +30,9 @@ it; the result does not depend on the order of the pairwise products (up to
 rounding).  The order is an input here -- a partition of the tensors into
 leaves and a list of pairwise merges, as a plan exports it -- and is treated
 as data only: it is validated, then followed.  Each product is computed in
-complex128 by permuting both operands to [batch, free, summed] and calling
-numpy's matmul (einsum for tiny matrices); nothing is blocked or fused.
+complex128 with plain PyTorch CPU operations (multi-threaded): both operands
+permuted to [batch, free, summed] and one batched matrix product; nothing is
+blocked or fused.
 Without a given tree, ``contract_greedy`` picks its own order (the pair
 whose product is smallest, ties by id).
 
@@ -42,6 +43,7 @@ different trees; rejection of invalid trees.
 """
 
 import numpy as np
+import torch
 
 from .gates import GATE_CZ, GATE_T, gate_matrix
 
@@ -68,25 +70,31 @@ def hyper_network(n_qubits: int, circuit):
 
 
 def fix_pieces(tensors, fixed: dict):
-    """Sub-block of every tensor with each index in ``fixed`` set to its value."""
+    """Sub-block of every tensor with each index in ``fixed`` set to its value
+    (as complex128 torch CPU tensors)."""
     out = []
     for arr, idx in tensors:
         sel = tuple(int(fixed[e]) if e in fixed else slice(None) for e in idx)
-        out.append((np.array(arr[sel], dtype=np.complex128), [e for e in idx if e not in fixed]))
+        sub = np.array(np.asarray(arr)[sel], dtype=np.complex128)
+        out.append((torch.from_numpy(sub), [e for e in idx if e not in fixed]))
     return out
 
 
-def _product(A, ia, B, ib, keep):
-    """A * B over their common indices; an index in neither ``keep`` (held by
-    another remaining tensor) is summed.  Result indices: batch, A-free, B-free."""
+def _product(operands, ia, ib, keep):
+    """A * B over their common indices, (A, B) = operands (the list is emptied
+    so that the operands can be freed once permuted); an index in neither
+    ``keep`` (held by another remaining tensor) is summed.  Result indices:
+    batch, A-free, B-free."""
+    A, B = operands
+    operands.clear()
     sa, sb = set(ia), set(ib)
     only_a = [e for e in ia if e not in sb and e not in keep]
     only_b = [e for e in ib if e not in sa and e not in keep]
     if only_a:
-        A = A.sum(axis=tuple(ia.index(e) for e in only_a))
+        A = A.sum(dim=tuple(ia.index(e) for e in only_a))
         ia = [e for e in ia if e not in only_a]
     if only_b:
-        B = B.sum(axis=tuple(ib.index(e) for e in only_b))
+        B = B.sum(dim=tuple(ib.index(e) for e in only_b))
         ib = [e for e in ib if e not in only_b]
     sb = set(ib)
     batch = [e for e in ia if e in sb and e in keep]
@@ -94,12 +102,10 @@ def _product(A, ia, B, ib, keep):
     free_a = [e for e in ia if e not in sb]
     free_b = [e for e in ib if e not in set(ia)]
     nb, na, nk, nf = (1 << len(batch)), (1 << len(free_a)), (1 << len(summed)), (1 << len(free_b))
-    At = np.ascontiguousarray(np.transpose(A, [ia.index(e) for e in batch + free_a + summed])).reshape(nb, na, nk)
-    Bt = np.ascontiguousarray(np.transpose(B, [ib.index(e) for e in batch + summed + free_b])).reshape(nb, nk, nf)
-    if na * nk * nf <= 512:
-        C = np.einsum("bmk,bkn->bmn", At, Bt)
-    else:
-        C = np.matmul(At, Bt)
+    At = A.permute([ia.index(e) for e in batch + free_a + summed]).reshape(nb, na, nk)
+    Bt = B.permute([ib.index(e) for e in batch + summed + free_b]).reshape(nb, nk, nf)
+    del A, B
+    C = torch.bmm(At, Bt)
     out_idx = batch + free_a + free_b
     return C.reshape([2] * len(out_idx)), out_idx
 
@@ -115,16 +121,16 @@ class _Live:
                 self.count[e] = self.count.get(e, 0) + 1
 
     def merge(self, ka, kb, knew):
-        A, ia = self.t.pop(ka)
-        B, ib = self.t.pop(kb)
+        ia, ib = self.t[ka][1], self.t[kb][1]
         for e in ia + ib:
             self.count[e] -= 1
         keep = {e for e in set(ia) | set(ib) if self.count[e] > 0}
-        C, ic = _product(A, ia, B, ib, keep)
+        operands = [self.t.pop(ka)[0], self.t.pop(kb)[0]]
+        C, ic = _product(operands, ia, ib, keep)
         for e in ic:
             self.count[e] += 1
         self.t[knew] = (C, ic)
-        return C.size
+        return C.numel()
 
 
 def _greedy_pairs(live, keys, next_key):
@@ -155,7 +161,7 @@ def _greedy_pairs(live, keys, next_key):
 def _scalar(arr, idx):
     if idx:
         raise AssertionError(f"indices left open after the contraction: {idx}")
-    return complex(np.asarray(arr).reshape(()))
+    return complex(arr.reshape(()).item())
 
 
 def validate_tree(n_tensors: int, groups, merges):

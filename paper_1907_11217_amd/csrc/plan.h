@@ -203,7 +203,12 @@ struct qc_plan {
     int exec_mode = QC_EXEC_AUTO;
     // Kernel timing (qc_profile_enable): pending event pairs and their kind.
     bool profiling = false;
-    std::vector<std::pair<std::string, std::pair<void *, void *>>> prof_pending;
+    struct ProfEntry {
+        std::string kind;
+        void *e0, *e1;
+        double flops;             // algorithmic flops of the launch (GEMM and micro steps; 0 otherwise)
+    };
+    std::vector<ProfEntry> prof_pending;
     std::vector<void *> prof_pool;
     std::mutex mu;
     std::map<std::pair<int, int>, std::unique_ptr<qc::Program>> programs;

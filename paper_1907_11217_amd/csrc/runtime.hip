@@ -612,6 +612,9 @@ GemmDesc make_gemm(const Program &prog, const GemmOp &g, float2 *tensors, int pr
     return d;
 }
 
+// Algorithmic real flops of a GEMM step (8 per complex multiply-add).
+double gemm_flops(const GemmOp &g) { return 8.0 * double(g.nb) * double(g.m) * double(g.n) * double(g.k); }
+
 // Event pair around each launch while the plan's kernel timing is on.
 struct Prof {
     qc_plan *plan;
@@ -632,11 +635,11 @@ struct Prof {
         e0 = event();
         hipEventRecord((hipEvent_t)e0, st);
     }
-    void end(const char *kind) {
+    void end(const char *kind, double flops = 0) {
         if (!plan->profiling) return;
         void *e1 = event();
         hipEventRecord((hipEvent_t)e1, st);
-        plan->prof_pending.push_back({kind, {e0, e1}});
+        plan->prof_pending.push_back({kind, e0, e1, flops});
     }
 };
 
@@ -751,7 +754,11 @@ bool launch_all(qc_plan *plan, const Exec &x, uint64_t s_begin, uint64_t s_end, 
                     const int32_t *ls = lt + prog.n_micro_groups + 1;
                     launch_micro((const MicroStep *)prog.d_micro, lt, ls, ls + prog.n_micro_levels + 1,
                                  prog.n_micro_groups, tensors, amax, st);
-                    prof.end("micro");
+                    double mf = 0;
+                    if (plan->profiling)
+                        for (size_t gi = 0; gi < prog.gemms.size(); ++gi)
+                            if (prog.gemm_micro[gi]) mf += gemm_flops(prog.gemms[gi]);
+                    prof.end("micro", mf);
                 }
                 for (size_t oi = 0; oi < prog.ops.size(); ++oi) {
                     const Op &op = prog.ops[oi];
@@ -764,7 +771,8 @@ bool launch_all(qc_plan *plan, const Exec &x, uint64_t s_begin, uint64_t s_end, 
                         const GemmOp &g = prog.gemms[op.index];
                         const GemmDesc gd = make_gemm(prog, g, tensors, x.prec, amax, slot, kscratch);
                         const int v = g.variant[x.prec];
-                        prof.end(v >= 0 && gemm_variant_ok(gd, v) ? launch_gemm_variant(gd, v, st) : launch_gemm(gd, st));
+                        prof.end(v >= 0 && gemm_variant_ok(gd, v) ? launch_gemm_variant(gd, v, st) : launch_gemm(gd, st),
+                                 gemm_flops(g));
                     }
                 }
                 launch_copy(partial + ((cb - sc) << x.m), tensors + prog.tensors[prog.root].offset,
@@ -1482,23 +1490,24 @@ extern "C" qc_status qc_profile_read(qc_plan *plan, qc_kernel_stat_t *out, int32
     qc_status st = QC_OK;
     for (auto &pe : plan->prof_pending) {
         float ms = 0.f;
-        if (hipEventSynchronize((hipEvent_t)pe.second.second) != hipSuccess ||
-            hipEventElapsedTime(&ms, (hipEvent_t)pe.second.first, (hipEvent_t)pe.second.second) != hipSuccess) {
+        if (hipEventSynchronize((hipEvent_t)pe.e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, (hipEvent_t)pe.e0, (hipEvent_t)pe.e1) != hipSuccess) {
             set_error("qc_profile_read: event query failed");
             st = QC_ERR_DEVICE;
         }
         qc_kernel_stat_t *s = nullptr;
         for (auto &x : stats)
-            if (pe.first == x.kind) s = &x;
+            if (pe.kind == x.kind) s = &x;
         if (!s) {
             stats.push_back(qc_kernel_stat_t{});
             s = &stats.back();
-            std::strncpy(s->kind, pe.first.c_str(), sizeof(s->kind) - 1);
+            std::strncpy(s->kind, pe.kind.c_str(), sizeof(s->kind) - 1);
         }
         s->launches += 1;
         s->total_ms += ms;
-        plan->prof_pool.push_back(pe.second.first);
-        plan->prof_pool.push_back(pe.second.second);
+        s->flops += pe.flops;
+        plan->prof_pool.push_back(pe.e0);
+        plan->prof_pool.push_back(pe.e1);
     }
     plan->prof_pending.clear();
     *n = (int32_t)stats.size();
@@ -1508,7 +1517,7 @@ extern "C" qc_status qc_profile_read(qc_plan *plan, qc_kernel_stat_t *out, int32
 
 extern "C" void qc_plan_destroy(qc_plan *plan) {
     if (!plan) return;
-    for (auto &pe : plan->prof_pending) plan->prof_pool.push_back(pe.second.first), plan->prof_pool.push_back(pe.second.second);
+    for (auto &pe : plan->prof_pending) plan->prof_pool.push_back(pe.e0), plan->prof_pool.push_back(pe.e1);
     for (void *e : plan->prof_pool) hipEventDestroy((hipEvent_t)e);
     for (auto &kv : plan->programs) qc::free_program_device(*kv.second);
     if (plan->capture_stream) (void)hipStreamDestroy((hipStream_t)plan->capture_stream);

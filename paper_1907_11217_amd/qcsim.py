@@ -83,7 +83,8 @@ class qc_plan_info_t(ctypes.Structure):
 
 
 class qc_kernel_stat_t(ctypes.Structure):
-    _fields_ = [("kind", ctypes.c_char * 16), ("launches", ctypes.c_int64), ("total_ms", ctypes.c_double)]
+    _fields_ = [("kind", ctypes.c_char * 16), ("launches", ctypes.c_int64), ("total_ms", ctypes.c_double),
+                ("flops", ctypes.c_double)]
 
 
 _lib = None
@@ -368,11 +369,13 @@ def qc_profile_enable(plan: Plan, on: bool = True) -> None:
 
 
 def qc_profile_read(plan: Plan) -> dict:
-    """{kind: (launches, total_ms)} since the last read (waits for the events)."""
+    """{kind: (launches, total_ms, algorithmic flops)} since the last read
+    (waits for the events)."""
     stats = (qc_kernel_stat_t * 32)()
     n = ctypes.c_int32()
     _check(plan._lib.qc_profile_read(plan.handle, stats, 32, ctypes.byref(n)), plan._lib)
-    return {stats[i].kind.decode(): (int(stats[i].launches), float(stats[i].total_ms)) for i in range(n.value)}
+    return {stats[i].kind.decode(): (int(stats[i].launches), float(stats[i].total_ms), float(stats[i].flops))
+            for i in range(n.value)}
 
 
 def qc_gate_matrix(kind: int, lib=None) -> np.ndarray:

@@ -149,16 +149,19 @@ def random_slices(log2_slices: int, count: int, seed: int) -> np.ndarray:
 
 
 # Workloads.  Seeds: circuit = seed, bitstrings = seed + 1, sampled slices =
-# seed + 2, request mix = seed + 3.
+# seed + 2, request mix = seed + 3 (per-request slice counts: seed + 4).
+# trials / plan_seed: restarts and seed of the order search that every
+# measurement and parity test of the workload uses; chunk: slices in flight
+# per call where the workload is timed on a slice range.
 CONFIGS = {
     "c1": dict(name="grid4x4_d10", lattice=(4, 4), depth=10, seed=101,
-               n_bitstrings=1, log2_slices=0),
+               n_bitstrings=1, log2_slices=0, trials=8, plan_seed=1),
     "c2": dict(name="grid5x5_d16", lattice=(5, 5), depth=16, seed=201,
-               n_bitstrings=64, log2_slices=6),
+               n_bitstrings=64, log2_slices=6, trials=8, plan_seed=1),
     "c3": dict(name="grid7x7_d24", lattice=(7, 7), depth=24, seed=301,
-               n_bitstrings=1, log2_slices=16, log2_cap=30, n_sampled=32),
+               n_bitstrings=1, log2_slices=16, log2_cap=30, n_sampled=32, trials=8, plan_seed=1),
     "c4": dict(name="diamond70_d32", lattice="diamond70", depth=32, seed=401,
-               n_bitstrings=1, log2_slices=20, log2_cap=30),
+               n_bitstrings=1, log2_slices=20, log2_cap=30, trials=256, plan_seed=1, chunk=8),
 }
 
 
@@ -174,17 +177,25 @@ def config(key: str):
 REQUEST_FAMILIES = ((4, 4, 12), (5, 5, 16), (6, 6, 20), (7, 7, 24))
 
 
+REQUEST_MAX_LOG2_SLICES = 12
+
+
 def request_mix(count: int = 256, seed: int = 501):
     """Uneven batch of amplitude requests: for each request a family drawn
     uniformly (floor(4u) on stream seed + 3), then a 32-bit circuit seed from
-    the same stream; the request's bitstring comes from circuit seed + 1."""
+    the same stream; the request's bitstring comes from circuit seed + 1.
+    Each request also asks for 2^k slices, k drawn uniformly from
+    0..REQUEST_MAX_LOG2_SLICES (floor(13u) on stream seed + 4), the planner
+    slicing further where a size cap demands it."""
     rng = SplitMix64(seed + 3)
+    rng_k = SplitMix64(seed + 4)
     reqs = []
     for _ in range(count):
         fam = REQUEST_FAMILIES[int(len(REQUEST_FAMILIES) * rng.uniform())]
         cseed = rng.next() & 0xFFFFFFFF
+        k = int((REQUEST_MAX_LOG2_SLICES + 1) * rng_k.uniform())
         lat = grid(fam[0], fam[1])
         circ = random_circuit(lat, fam[2], cseed)
         bs = random_bitstrings(lat.n, 1, cseed + 1)
-        reqs.append(dict(family=fam, seed=cseed, lattice=lat, circuit=circ, bitstring=bs[0]))
+        reqs.append(dict(family=fam, seed=cseed, lattice=lat, circuit=circ, bitstring=bs[0], log2_slices=k))
     return reqs

@@ -303,30 +303,79 @@ def test_device_resident_bitstrings_match_host(c2_setup, mode):
 
 
 # Split precisions: relative error <= 1e-4 for split FP16; split BF16 has no
-# target of its own and is held to 1e-3.  They always run stepwise.
+# target of its own and is held to 1e-3.  They always run stepwise, and only
+# GEMM steps with m and n multiples of 32 run on a split MFMA form.
 TOL_SPLIT = {"split_fp16": 1e-4, "split_bf16": 1e-3}
+SPLIT_KIND = {"split_fp16": "gemm_split_fp16", "split_bf16": "gemm_split_bf16"}
+
+
+def _split_eligible_flops(plan, b, m):
+    steps = qcsim.qc_plan_export_steps(plan, b, m)
+    gemm = [s for s in steps if s["kind"] == 1]
+    total = sum(s["flops"] for s in gemm)
+    elig = sum(s["flops"] for s in gemm if not s["micro"] and s["m"] % 32 == 0 and s["n"] % 32 == 0)
+    return elig, total
 
 
 @pytest.mark.parametrize("prec", sorted(TOL_SPLIT))
-def test_p6_unitarity_split(prec):
-    lat = synth.grid(3, 3)
-    circ = synth.random_circuit(lat, 8, 3)
-    xs = np.array(list(np.ndindex(*([2] * lat.n))), dtype=np.uint8)
-    plan = qcsim.qc_plan_build(lat.n, circ, None, log2_slices=2, greedy_trials=2)
-    say(f"P6 unitarity 3x3 d8 {prec}")
-    got = _contract(plan, xs, 0, 4, prec=prec)
-    assert abs(np.sum(np.abs(got) ** 2) - 1) <= TOL_SPLIT[prec]
-    check_amplitudes(got, oracle.statevector(lat.n, circ), lat.n, TOL_SPLIT[prec])
-
-
-@pytest.mark.parametrize("prec", sorted(TOL_SPLIT))
-def test_c2_amplitudes_split(c2_setup, prec):
+def test_c2_split_request_runs_complex_fp32_steps(c2_setup, prec):
+    # The 5x5 depth-16 program (2^6 slices, 64 bitstrings in flight) has no
+    # GEMM step with m and n multiples of 32, so a split precision runs every
+    # step in complex FP32: the result is bit for bit the stepwise complex
+    # FP32 one, and no split kernel launches.  Split MFMA parity against the
+    # state vector is the 5x5 depth-24 test below.
     lat, circ, bs, plan, ref = c2_setup
-    qcsim.qc_plan_set_exec(plan, "auto")
-    say(f"c2 5x5 d16, 64 bitstrings x 64 slices, {prec}")
-    got = _contract(plan, bs, 0, 64, prec=prec)
-    info = check_amplitudes(got, ref, lat.n, TOL_SPLIT[prec])
-    print("c2", prec, info)
+    qcsim.qc_plan_set_exec(plan, "stepwise")
+    try:
+        assert _split_eligible_flops(plan, 6, 6)[0] == 0
+        say(f"c2 5x5 d16, 64 bitstrings x 64 slices, stepwise c64 vs {prec}")
+        a = _contract(plan, bs, 0, 64, prec="c64")
+        qcsim.qc_profile_read(plan)
+        qcsim.qc_profile_enable(plan, True)
+        b = _contract(plan, bs, 0, 64, prec=prec)
+        qcsim.qc_profile_enable(plan, False)
+        prof = qcsim.qc_profile_read(plan)
+        assert SPLIT_KIND[prec] not in prof
+        assert np.array_equal(a, b)
+        check_amplitudes(b, ref, lat.n, TOL_C64)
+    finally:
+        qcsim.qc_plan_set_exec(plan, "auto")
+
+
+@pytest.fixture(scope="module")
+def deep5x5():
+    # 5x5 grid at depth 1+24+1 (circuit seed 201, the 5x5 workload's seed):
+    # about 90% of its program's flops sit in GEMM steps that a split MFMA
+    # form runs, and its 2^25-entry state vector is still at hand.
+    lat = synth.grid(5, 5)
+    circ = synth.random_circuit(lat, 24, 201)
+    xs = synth.random_bitstrings(lat.n, 16, 205)
+    plan = qcsim.qc_plan_build(lat.n, circ, xs[0], log2_slices=2, greedy_trials=8, seed=1)
+    qcsim.qc_plan_set_exec(plan, "stepwise")
+    psi = oracle.statevector(lat.n, circ)
+    ref = np.array([psi[oracle.index_of(x)] for x in xs])
+    return lat, xs, plan, ref
+
+
+@pytest.mark.parametrize("prec", ["c64", "split_fp16", "split_bf16"])
+def test_deep5x5_split_mfma_matches_statevector(deep5x5, prec):
+    lat, xs, plan, ref = deep5x5
+    elig, total = _split_eligible_flops(plan, 2, 4)
+    assert elig >= 0.5 * total, (elig, total)
+    say(f"5x5 d24, 16 bitstrings x 4 slices, stepwise {prec}")
+    qcsim.qc_profile_read(plan)
+    qcsim.qc_profile_enable(plan, True)
+    got = _contract(plan, xs, 0, 4, prec=prec)
+    qcsim.qc_profile_enable(plan, False)
+    prof = qcsim.qc_profile_read(plan)
+    gemm_flops = sum(v[2] for kk, v in prof.items())
+    if prec != "c64":
+        kind = SPLIT_KIND[prec]
+        assert kind in prof and prof[kind][0] > 0, prof
+        # Most of the work ran on the split MFMA form.
+        assert prof[kind][2] >= 0.5 * gemm_flops, prof
+    info = check_amplitudes(got, ref, lat.n, TOL_C64 if prec == "c64" else TOL_SPLIT[prec])
+    print("5x5 d24", prec, info, {kk: v[0] for kk, v in prof.items()})
 
 
 def test_split_needs_stepwise(c2_setup):
