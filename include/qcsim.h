@@ -332,6 +332,35 @@ qc_status qc_contract_slices_dev(qc_plan *plan, uint64_t s_begin, uint64_t s_end
                                  void *ws, size_t ws_bytes, void *stream,
                                  double *out_dev, double *per_slice_dev);
 
+/* qc_contract_slices_dev for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): it calls no hipMalloc, hipFree or allocating library routine.
+ * Instead of a caller workspace it uses the library's own scratch, a static
+ * device array of 64 MiB that each GPU the library runs on holds until the
+ * process ends: the lowered program's constants are copied into it on
+ * `stream` (hipMemcpyAsync from plan-owned host memory) and the rest serves as
+ * the workspace.  Same arguments, semantics and errors as
+ * qc_contract_slices_dev otherwise (out_dev accumulates; per_slice_dev
+ * optional), with these differences:
+ *   - QC_ERR_NOMEM if the program's constants plus the workspace for one
+ *     slice (or one 64-slice block of the fused form) in flight exceed the
+ *     64 MiB; the message says so.  Fewer slices are kept in flight than a
+ *     larger caller workspace would allow, so results may differ from
+ *     qc_contract_slices_dev in rounding (the FP64 sum's chunking, and for
+ *     the fused form the slice bits per work item), never beyond the
+ *     precision's tolerance.
+ *   - Nothing is timed and no graph is captured: the fused form uses the
+ *     plan's in-flight slice bits and work-item shape if an earlier call
+ *     timed them, else b = 0 and one work item on four wavefronts; kernel
+ *     timing (qc_profile_enable) is ignored.
+ *   - Every call on one GPU shares that GPU's scratch, which keeps the last
+ *     call's contents: calls that overlap on one GPU (different streams or
+ *     threads without ordering between them) race and give wrong results.
+ *     Calls ordered on one stream are safe. */
+qc_status qc_contract_slices_noalloc(qc_plan *plan, uint64_t s_begin, uint64_t s_end,
+                                     const uint8_t *bitstrings_dev, int32_t n_bs, qc_precision prec,
+                                     void *stream, double *out_dev, double *per_slice_dev);
+
 /* All slices of one amplitude, synchronously; allocates and frees its own
  * workspace on the current device.  out_host[0..1] = (re, im). */
 qc_status qc_amplitude(qc_plan *plan, const uint8_t *bitstring, qc_precision prec,

@@ -135,6 +135,26 @@ struct GemmOp {
     int variant[3] = {-1, -1, -1};   // GEMM kernel form per precision chosen by qc_tune (-1: default rules)
 };
 
+// Device constants of a lowered program, by id.
+enum ConstId {
+    kCLeafDesc,      // leaf descriptors (stepwise form)
+    kCLeafBlock,     // leaf blocks (stepwise form)
+    kCBase,          // leaf base values, complex double (both forms)
+    kCMicro,         // micro-step table (stepwise form)
+    kCMicroLevels,   // group and level starts of the micro-step table
+    kCFusedImage,    // leaf values that do not depend on the (slice, bitstring) pair
+    kCFusedElems,    // run-time leaf elements: LDS slot, base index, dynamic bits
+    kCFusedPool,     // operand slots of items with more than four contracted values
+    kCFusedItems,    // one item per output of every step, grouped by tree level
+    kCFusedItems2,   // third and fourth operand slots of each item
+    kCFusedLevels,   // item offsets of the levels
+    kNumConst
+};
+
+struct DevConsts {
+    void *p[kNumConst] = {};
+};
+
 struct Op {
     enum Kind { TRANSPOSE, GEMM } kind;
     int index;                 // into transposes / gemms
@@ -158,23 +178,18 @@ struct Program {
     std::vector<int64_t> lds_offset;      // per program tensor (-1 if not used by the fused form)
     int64_t lds_elems = 0;
     mutable std::atomic<int> fused_fit{-1};  // whether the fused form fits (-1: not known yet)
-    // Device constants, created lazily on the device current at first use.
+    // Device constants.  Their host images are built once (build_consts);
+    // dc holds the plan-owned device copies, created lazily on the device
+    // current at first use (a call that may not allocate copies the images
+    // into the library's static scratch instead).
     int device = -1;
-    void *d_leaf_desc = nullptr;
-    void *d_leaf_block = nullptr;
-    void *d_base = nullptr;
+    bool built_stepwise = false, built_fused = false;
+    std::vector<char> const_host[kNumConst];
+    DevConsts dc;
     int n_leaf_blocks = 0;
-    void *d_micro = nullptr;              // micro-step table (stepwise form)
-    void *d_micro_levels = nullptr;       // step offsets of its levels
     int n_micro_levels = 0;
     int n_micro_groups = 0;               // workgroups of the micro-step launch
-    void *d_fused_image = nullptr;        // leaf values that do not depend on the (slice, bitstring) pair
     int n_image = 0;
-    void *d_fused_elems = nullptr;        // run-time leaf elements: LDS slot, base index, dynamic bits
-    void *d_fused_items = nullptr;        // one item per output of every step, grouped by tree level
-    void *d_fused_items2 = nullptr;       // third and fourth operand slots of each item
-    void *d_fused_levels = nullptr;       // item offsets of the levels
-    void *d_fused_pool = nullptr;         // operand slots of items with more than four contracted values
     int n_leaf_elems = 0;
     int n_levels = 0;
     int n_pool = 0;

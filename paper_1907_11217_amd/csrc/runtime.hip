@@ -58,6 +58,8 @@ struct Exec {
     int m = 0;          // log2 bitstrings (padded)
     int lp = 6;         // log2 super-chunk slices
     int prec = kPrecC64;
+    const DevConsts *dc = nullptr;  // device constants (nullptr: the program's own)
+    int pairs = 0, waves = 0;       // fused work-item shape (0: the plan's, timed on first use)
 };
 
 // Workspace: bitstrings (when handed over from the host), the super-chunk's
@@ -154,10 +156,18 @@ bool choose_exec(qc_plan *plan, int m, int want_lp, int prec, size_t ws_bytes, E
     return false;
 }
 
-bool upload(void **dst, const void *src, size_t bytes, std::string &err) {
-    QC_HIP(hipMalloc(dst, std::max<size_t>(bytes, 16)));
-    if (bytes) QC_HIP(hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice));
+// Keeps the host image of device constant `id` of a program.
+bool stage(Program &prog, int id, const void *src, size_t bytes) {
+    prog.const_host[id].assign((const char *)src, (const char *)src + bytes);
     return true;
+}
+
+// The constants each form reads.
+bool const_needed(const Program &prog, bool fused, int id) {
+    if (id == kCBase) return true;
+    if (fused) return id >= kCFusedImage;
+    if (id == kCMicro || id == kCMicroLevels) return prog.n_micro_levels > 0;
+    return id == kCLeafDesc || id == kCLeafBlock;
 }
 
 // Leaf table of a program; lds = true gives LDS offsets (fused form).
@@ -225,21 +235,17 @@ int32_t stride_in(const std::vector<int> &layout, int e) {
 }
 
 // Uploads the program's constants to the current device (once).
-bool ensure_device(const qc_plan *plan, Program &prog, bool fused, std::string &err) {
-    int dev = 0;
-    QC_HIP(hipGetDevice(&dev));
-    if (prog.device >= 0 && prog.device != dev) { err = "plan was first used on another device"; return false; }
-    prog.device = dev;
-    if (!fused && !prog.d_leaf_desc) {
+// Host images of the device constants of one form (built once; host work only).
+bool build_consts(const qc_plan *plan, Program &prog, bool fused, std::string &err) {
+    if (!fused && !prog.built_stepwise) {
         std::vector<LeafDesc> descs;
         std::vector<int32_t> blocks;
         std::vector<double2> base;
         leaf_table(plan, prog, false, descs, blocks, base, err);
         if (!err.empty()) return false;
-        if (!upload(&prog.d_leaf_block, blocks.data(), blocks.size() * 4, err) ||
-            (!prog.d_base && !upload(&prog.d_base, base.data(), base.size() * sizeof(double2), err)) ||
-            !upload(&prog.d_leaf_desc, descs.data(), descs.size() * sizeof(LeafDesc), err))
-            return false;
+        stage(prog, kCLeafBlock, blocks.data(), blocks.size() * 4);
+        stage(prog, kCBase, base.data(), base.size() * sizeof(double2));
+        stage(prog, kCLeafDesc, descs.data(), descs.size() * sizeof(LeafDesc));
         prog.n_leaf_blocks = (int)blocks.size();
         // Micro steps.  They form independent subtrees (a micro step reads
         // leaves and outputs of micro steps only); each subtree runs in a
@@ -361,12 +367,12 @@ bool ensure_device(const qc_plan *plan, Program &prog, bool fused, std::string &
             std::vector<int32_t> lv_tab(group_start);
             lv_tab.insert(lv_tab.end(), starts.begin(), starts.end());
             lv_tab.insert(lv_tab.end(), outs.begin(), outs.end());
-            if (!upload(&prog.d_micro, steps.data(), steps.size() * sizeof(MicroStep), err) ||
-                !upload(&prog.d_micro_levels, lv_tab.data(), lv_tab.size() * 4, err))
-                return false;
+            stage(prog, kCMicro, steps.data(), steps.size() * sizeof(MicroStep));
+            stage(prog, kCMicroLevels, lv_tab.data(), lv_tab.size() * 4);
         }
+        prog.built_stepwise = true;
     }
-    if (fused && !prog.d_fused_items) {
+    if (fused && !prog.built_fused) {
         std::vector<LeafDesc> descs;
         std::vector<int32_t> unused;
         std::vector<double2> base;
@@ -463,18 +469,57 @@ bool ensure_device(const qc_plan *plan, Program &prog, bool fused, std::string &
             items2.insert(items2.end(), by_level2[l].begin(), by_level2[l].end());
             level_start.push_back((int32_t)items.size());
         }
-        if (!upload(&prog.d_fused_image, image.data(), image.size() * sizeof(float2), err) ||
-            !upload(&prog.d_fused_elems, elems.data(), elems.size() * sizeof(int4), err) ||
-            !upload(&prog.d_fused_pool, pool.data(), pool.size() * 4, err) ||
-            (!prog.d_base && !upload(&prog.d_base, base.data(), base.size() * sizeof(double2), err)) ||
-            !upload(&prog.d_fused_items, items.data(), items.size() * sizeof(int4), err) ||
-            !upload(&prog.d_fused_items2, items2.data(), items2.size() * sizeof(int2), err) ||
-            !upload(&prog.d_fused_levels, level_start.data(), level_start.size() * 4, err))
-            return false;
+        stage(prog, kCFusedImage, image.data(), image.size() * sizeof(float2));
+        stage(prog, kCFusedElems, elems.data(), elems.size() * sizeof(int4));
+        stage(prog, kCFusedPool, pool.data(), pool.size() * 4);
+        stage(prog, kCBase, base.data(), base.size() * sizeof(double2));
+        stage(prog, kCFusedItems, items.data(), items.size() * sizeof(int4));
+        stage(prog, kCFusedItems2, items2.data(), items2.size() * sizeof(int2));
+        stage(prog, kCFusedLevels, level_start.data(), level_start.size() * 4);
         prog.n_leaf_elems = (int)elems.size();
         prog.n_image = (int)image.size();
         prog.n_pool = (int)pool.size();
         prog.n_levels = n_levels;
+        prog.built_fused = true;
+    }
+    return true;
+}
+
+// Device constants of one form in plan-owned buffers on the current device
+// (allocated and copied on first use).
+bool ensure_device(const qc_plan *plan, Program &prog, bool fused, std::string &err) {
+    int dev = 0;
+    QC_HIP(hipGetDevice(&dev));
+    if (prog.device >= 0 && prog.device != dev) { err = "plan was first used on another device"; return false; }
+    if (!build_consts(plan, prog, fused, err)) return false;
+    prog.device = dev;
+    for (int id = 0; id < kNumConst; ++id) {
+        if (!const_needed(prog, fused, id) || prog.dc.p[id]) continue;
+        const std::vector<char> &h = prog.const_host[id];
+        QC_HIP(hipMalloc(&prog.dc.p[id], std::max<size_t>(h.size(), 16)));
+        if (!h.empty()) QC_HIP(hipMemcpy(prog.dc.p[id], h.data(), h.size(), hipMemcpyHostToDevice));
+    }
+    return true;
+}
+
+// Bytes the constants of one form take when packed at 256-byte boundaries.
+size_t packed_const_bytes(const Program &prog, bool fused) {
+    size_t total = 0;
+    for (int id = 0; id < kNumConst; ++id)
+        if (const_needed(prog, fused, id)) total += (std::max<size_t>(prog.const_host[id].size(), 16) + 255) & ~size_t(255);
+    return total;
+}
+
+// Copies the constants of one form into dst (device memory of at least
+// packed_const_bytes) on stream st, and points dc at the copies.
+bool place_consts(const Program &prog, bool fused, char *dst, hipStream_t st, DevConsts &dc, std::string &err) {
+    size_t off = 0;
+    for (int id = 0; id < kNumConst; ++id) {
+        if (!const_needed(prog, fused, id)) continue;
+        const std::vector<char> &h = prog.const_host[id];
+        dc.p[id] = dst + off;
+        if (!h.empty()) QC_HIP(hipMemcpyAsync(dst + off, h.data(), h.size(), hipMemcpyHostToDevice, st));
+        off += (std::max<size_t>(h.size(), 16) + 255) & ~size_t(255);
     }
     return true;
 }
@@ -664,16 +709,17 @@ FusedParams fused_params(const qc_plan *plan, const Program &prog, const Exec &x
                          uint64_t hi, const uint8_t *bits, int n_bs, float2 *partial) {
     FusedParams fp;
     std::memset(&fp, 0, sizeof(fp));
-    fp.level_start = (const int32_t *)prog.d_fused_levels;
+    const DevConsts &dc = x.dc ? *x.dc : prog.dc;
+    fp.level_start = (const int32_t *)dc.p[kCFusedLevels];
     fp.n_levels = prog.n_levels;
-    fp.items = (const int4 *)prog.d_fused_items;
-    fp.items2 = (const int2 *)prog.d_fused_items2;
-    fp.pool = (const int32_t *)prog.d_fused_pool;
-    fp.leaf_image = (const float2 *)prog.d_fused_image;
+    fp.items = (const int4 *)dc.p[kCFusedItems];
+    fp.items2 = (const int2 *)dc.p[kCFusedItems2];
+    fp.pool = (const int32_t *)dc.p[kCFusedPool];
+    fp.leaf_image = (const float2 *)dc.p[kCFusedImage];
     fp.n_image = prog.n_image;
-    fp.elems = (const int4 *)prog.d_fused_elems;
+    fp.elems = (const int4 *)dc.p[kCFusedElems];
     fp.n_elems = prog.n_leaf_elems;
-    fp.base = (const double2 *)prog.d_base;
+    fp.base = (const double2 *)dc.p[kCBase];
     fp.bits = bits;
     fp.n_qubits = plan->net.n_qubits;
     fp.n_bs = n_bs;
@@ -696,6 +742,7 @@ FusedParams fused_params(const qc_plan *plan, const Program &prog, const Exec &x
 bool launch_all(qc_plan *plan, const Exec &x, uint64_t s_begin, uint64_t s_end, const uint8_t *bits, int n_bs,
                 void *ws, hipStream_t st, double *out_dev, double *per_slice_dev, bool profile, std::string &err) {
     Program &prog = *x.prog;
+    const DevConsts &dc = x.dc ? *x.dc : prog.dc;
     Prof prof{plan, st};
     const bool saved = plan->profiling;
     plan->profiling = profile;
@@ -721,8 +768,12 @@ bool launch_all(qc_plan *plan, const Exec &x, uint64_t s_begin, uint64_t s_end, 
         bool summed = false;  // block sums already added to out by the fused launch
         if (x.fused) {
             FusedParams fp = fused_params(plan, prog, x, sc, lo, hi, bits, n_bs, partial);
-            if (prog.fused_pairs == 0 && !tune_fused(prog, fp, st, err)) { plan->profiling = saved; return false; }
-            const int pairs = fused_pairs_of(plan, prog), waves = fused_waves_of(plan, prog);
+            if (x.pairs == 0 && prog.fused_pairs == 0 && !tune_fused(prog, fp, st, err)) {
+                plan->profiling = saved;
+                return false;
+            }
+            const int pairs = x.pairs > 0 ? x.pairs : fused_pairs_of(plan, prog);
+            const int waves = x.pairs > 0 ? x.waves : fused_waves_of(plan, prog);
             if (fused_lds_bytes(pairs, pair_elems_of(prog)) > size_t(kFusedLdsBytes)) {
                 err = "the fused work-item shape set for this plan does not fit in LDS";
                 plan->profiling = saved;
@@ -744,15 +795,15 @@ bool launch_all(qc_plan *plan, const Exec &x, uint64_t s_begin, uint64_t s_end, 
             for (uint64_t cb = lo & ~(chunk - 1); cb < hi; cb += chunk) {
                 prof.begin();
                 if (amax) launch_zero_u32(amax, (int64_t)slot.size(), st);
-                launch_leaves((const LeafDesc *)prog.d_leaf_desc, (const int32_t *)prog.d_leaf_block,
-                              prog.n_leaf_blocks, (const double2 *)prog.d_base, tensors, bits, nq, n_bs, cb, amax,
+                launch_leaves((const LeafDesc *)dc.p[kCLeafDesc], (const int32_t *)dc.p[kCLeafBlock],
+                              prog.n_leaf_blocks, (const double2 *)dc.p[kCBase], tensors, bits, nq, n_bs, cb, amax,
                               st);
                 prof.end("leaves");
                 if (prog.n_micro_levels > 0) {
-                    const int32_t *lt = (const int32_t *)prog.d_micro_levels;
+                    const int32_t *lt = (const int32_t *)dc.p[kCMicroLevels];
                     prof.begin();
                     const int32_t *ls = lt + prog.n_micro_groups + 1;
-                    launch_micro((const MicroStep *)prog.d_micro, lt, ls, ls + prog.n_micro_levels + 1,
+                    launch_micro((const MicroStep *)dc.p[kCMicro], lt, ls, ls + prog.n_micro_levels + 1,
                                  prog.n_micro_groups, tensors, amax, st);
                     double mf = 0;
                     if (plan->profiling)
@@ -974,11 +1025,9 @@ void free_program_device(Program &prog) {
     (void)hipSetDevice(prog.device);
     for (auto &g : prog.graphs) (void)hipGraphExecDestroy((hipGraphExec_t)g.second);
     prog.graphs.clear();
-    for (void **p : {&prog.d_leaf_desc, &prog.d_leaf_block, &prog.d_base, &prog.d_fused_image, &prog.d_fused_elems,
-                     &prog.d_fused_pool, &prog.d_fused_items, &prog.d_fused_items2, &prog.d_fused_levels, &prog.d_micro,
-                     &prog.d_micro_levels}) {
-        if (*p) (void)hipFree(*p);
-        *p = nullptr;
+    for (void *&p : prog.dc.p) {
+        if (p) (void)hipFree(p);
+        p = nullptr;
     }
     (void)hipSetDevice(cur);
 }
@@ -1055,6 +1104,100 @@ extern "C" qc_status qc_contract_slices_dev(qc_plan *plan, uint64_t s_begin, uin
                                             size_t ws_bytes, void *stream, double *out_dev, double *per_slice_dev) {
     return contract_common("qc_contract_slices_dev", plan, s_begin, s_end, bitstrings_dev, true, n_bs, prec, ws,
                            ws_bytes, stream, out_dev, per_slice_dev);
+}
+
+// ------------------------------------------------------------------ no allocation
+// Scratch of qc_contract_slices_noalloc: the lowered program's constants
+// followed by its workspace.  Each device holds its own copy until the
+// process ends; every call on a device shares it.
+namespace qc {
+constexpr size_t kNoAllocBytes = size_t(64) << 20;
+}  // namespace qc
+
+static __device__ __align__(256) unsigned char scratch[qc::kNoAllocBytes];
+
+// Device address of `scratch` on the current device, looked up once per
+// device (the array's host-side name is not a device address).
+static bool scratch_address(int dev, char **out, std::string &err) {
+    static std::mutex mu;
+    static std::map<int, char *> addr;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = addr.find(dev);
+    if (it == addr.end()) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            err = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+            return false;
+        }
+        it = addr.emplace(dev, (char *)ptr).first;
+    }
+    *out = it->second;
+    return true;
+}
+
+extern "C" qc_status qc_contract_slices_noalloc(qc_plan *plan, uint64_t s_begin, uint64_t s_end,
+                                                const uint8_t *bitstrings_dev, int32_t n_bs, qc_precision prec,
+                                                void *stream, double *out_dev, double *per_slice_dev) {
+    const std::string fn = "qc_contract_slices_noalloc";
+    if (!plan || !bitstrings_dev || !out_dev) { set_error(fn + ": NULL argument"); return QC_ERR_INVALID_ARG; }
+    if (!valid_prec(prec)) { set_error(fn + ": invalid precision"); return QC_ERR_INVALID_ARG; }
+    if (n_bs < 1 || n_bs > (1 << qc::kMaxBsBits)) { set_error(fn + ": n_bs out of range"); return QC_ERR_RANGE; }
+    const int k = (int)plan->sliced.size();
+    const uint64_t n_slices = k >= 64 ? ~uint64_t(0) : (uint64_t(1) << k);
+    if (s_begin > s_end || s_end > n_slices) { set_error(fn + ": slice range out of bounds"); return QC_ERR_RANGE; }
+    if (s_begin == s_end) return QC_OK;
+    std::string err;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) { set_error(fn + ": no current device"); return QC_ERR_DEVICE; }
+    char *base = nullptr;
+    if (!scratch_address(dev, &base, err)) { set_error(fn + ": " + err); return QC_ERR_DEVICE; }
+    std::lock_guard<std::mutex> lk(plan->dev_mu);
+    // The form and program qc_contract_slices_dev would choose with a
+    // workspace of what the constants leave of the scratch.
+    const int want = std::min(k, qc::ceil_log2((int64_t)(s_end - s_begin)));
+    const int m = qc::ceil_log2(n_bs);
+    const int pc = qc::prec_code(prec);
+    qc::Exec x;
+    size_t cap = qc::kNoAllocBytes, cbytes = 0;
+    bool ok = false;
+    for (int iter = 0; iter < 8 && !ok; ++iter) {
+        if (!qc::choose_exec(plan, m, want, pc, cap, x, err)) {
+            set_error(fn + ": " + err + " (the scratch of this entry point holds " +
+                      std::to_string(qc::kNoAllocBytes >> 20) + " MiB)");
+            return err.find("workspace") != std::string::npos ? QC_ERR_NOMEM : QC_ERR_UNSUPPORTED;
+        }
+        if (x.fused) {
+            // The plan's slice bits and shape if timed before, else b = 0 and
+            // one work item on four wavefronts (nothing is timed here).
+            const int fb = plan->fused_b > 0 ? plan->fused_b : 0;
+            if (fb > 0 && !(x.prog = qc::get_program(plan, fb, 0, err))) { set_error(fn + ": " + err); return QC_ERR_DEVICE; }
+            if (plan->fused_force_pairs > 0) { x.pairs = plan->fused_force_pairs; x.waves = plan->fused_force_waves; }
+            else if (x.prog->fused_pairs > 0) { x.pairs = x.prog->fused_pairs; x.waves = x.prog->fused_waves; }
+            else { x.pairs = 1; x.waves = 4; }
+        }
+        if (!qc::build_consts(plan, *x.prog, x.fused, err)) { set_error(fn + ": " + err); return QC_ERR_DEVICE; }
+        cbytes = qc::packed_const_bytes(*x.prog, x.fused);
+        const size_t need = cbytes + qc::ws_layout(x, plan->net.n_qubits).total;
+        if (need <= qc::kNoAllocBytes) { ok = true; break; }
+        if (cbytes >= qc::kNoAllocBytes || cap <= qc::kNoAllocBytes - cbytes) break;
+        cap = qc::kNoAllocBytes - cbytes;
+    }
+    if (!ok) {
+        set_error(fn + ": the program's constants and workspace need more than the " +
+                  std::to_string(qc::kNoAllocBytes >> 20) + " MiB of this entry point's scratch");
+        return QC_ERR_NOMEM;
+    }
+    qc::DevConsts dc;
+    hipStream_t st = (hipStream_t)stream;
+    if (!qc::place_consts(*x.prog, x.fused, base, st, dc, err)) { set_error(fn + ": " + err); return QC_ERR_DEVICE; }
+    x.dc = &dc;
+    if (!qc::launch_all(plan, x, s_begin, s_end, bitstrings_dev, n_bs, base + cbytes, st, out_dev, per_slice_dev,
+                        false, err)) {
+        set_error(fn + ": " + err);
+        return QC_ERR_DEVICE;
+    }
+    return QC_OK;
 }
 
 extern "C" qc_status qc_amplitude(qc_plan *plan, const uint8_t *bitstring, qc_precision prec, double out_host[2]) {
@@ -1249,13 +1392,13 @@ extern "C" qc_status qc_contract_batch(const qc_request *reqs, int32_t n, qc_pre
             std::memcpy(bits.data() + j * L.bits_stride, q.bitstring, q.plan->net.n_qubits);
             qc::BatchReq &d = desc[j];
             std::memset(&d, 0, sizeof(d));
-            d.level_start = (const int32_t *)prog.d_fused_levels;
-            d.items = (const int4 *)prog.d_fused_items;
-            d.items2 = (const int2 *)prog.d_fused_items2;
-            d.pool = (const int32_t *)prog.d_fused_pool;
-            d.image = (const float2 *)prog.d_fused_image;
-            d.elems = (const int4 *)prog.d_fused_elems;
-            d.base = (const double2 *)prog.d_base;
+            d.level_start = (const int32_t *)prog.dc.p[qc::kCFusedLevels];
+            d.items = (const int4 *)prog.dc.p[qc::kCFusedItems];
+            d.items2 = (const int2 *)prog.dc.p[qc::kCFusedItems2];
+            d.pool = (const int32_t *)prog.dc.p[qc::kCFusedPool];
+            d.image = (const float2 *)prog.dc.p[qc::kCFusedImage];
+            d.elems = (const int4 *)prog.dc.p[qc::kCFusedElems];
+            d.base = (const double2 *)prog.dc.p[qc::kCBase];
             d.bits = (const uint8_t *)(w + L.bits_off) + j * L.bits_stride;
             d.n_levels = prog.n_levels;
             d.n_image = prog.n_image;

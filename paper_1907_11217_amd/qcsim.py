@@ -31,7 +31,7 @@ EXPORTED = (
     "qc_plan_set_exec", "qc_profile_enable", "qc_profile_read", "qc_contract_slices_dev", "qc_plan_set_graphs",
     "qc_tune", "qc_kernel_gemm_form", "qc_batch_workspace_bytes", "qc_contract_batch", "qc_wall_clock_khz",
     "qc_plan_export_steps", "qc_kernel_gemm_kparts", "qc_gemm_kparts", "qc_plan_set_fused_slice_bits",
-    "qc_plan_set_fused_shape", "qc_plan_export_tree",
+    "qc_plan_set_fused_shape", "qc_plan_export_tree", "qc_contract_slices_noalloc",
 )
 EXEC_MODES = {"auto": 0, "fused": 1, "stepwise": 2}
 
@@ -149,6 +149,9 @@ def load(path: str | None = None):
         lib.qc_plan_export_steps.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(qc_step_t),
                                              ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
         lib.qc_plan_export_steps.restype = ctypes.c_int
+        lib.qc_contract_slices_noalloc.argtypes = [vp, ctypes.c_uint64, ctypes.c_uint64, vp, ctypes.c_int32,
+                                                   ctypes.c_int, vp, vp, vp]
+        lib.qc_contract_slices_noalloc.restype = ctypes.c_int
         pi32 = ctypes.POINTER(ctypes.c_int32)
         lib.qc_plan_export_tree.argtypes = [vp, pi32, pi32, pi32, pi32, pi32]
         lib.qc_plan_export_tree.restype = ctypes.c_int
@@ -432,6 +435,27 @@ def qc_contract_slices_dev(plan: Plan, s_begin: int, s_end: int, bits_dev, prec,
     _check(plan._lib.qc_contract_slices_dev(
         plan.handle, ctypes.c_uint64(int(s_begin)), ctypes.c_uint64(int(s_end)), bits_dev.data_ptr(), n_bs,
         _prec(prec), ws.data_ptr(), ws.numel() * ws.element_size(), st.cuda_stream, out_dev.data_ptr(),
+        per_slice_dev.data_ptr() if per_slice_dev is not None else None), plan._lib)
+
+
+def qc_contract_slices_noalloc(plan: Plan, s_begin: int, s_end: int, bits_dev, prec, out_dev, per_slice_dev=None,
+                               stream=None):
+    """As qc_contract_slices_dev without a workspace: the library's static
+    device scratch (64 MiB per GPU) serves instead, and nothing is allocated."""
+    import torch
+    if bits_dev.dtype != torch.uint8 or bits_dev.dim() != 2 or bits_dev.shape[1] != plan.n_qubits \
+            or not bits_dev.is_contiguous() or not bits_dev.is_cuda:
+        raise ValueError("bits_dev must be a contiguous uint8 device tensor [n_bs, n_qubits]")
+    n_bs = bits_dev.shape[0]
+    if out_dev.dtype != torch.float64 or out_dev.numel() < 2 * n_bs or not out_dev.is_contiguous():
+        raise ValueError("out_dev must be a contiguous float64 device tensor of n_bs x 2")
+    if per_slice_dev is not None and (per_slice_dev.dtype != torch.float64 or
+                                      per_slice_dev.numel() < 2 * n_bs * (s_end - s_begin)):
+        raise ValueError("per_slice_dev must be float64 with (s_end - s_begin) x n_bs x 2 entries")
+    st = stream if stream is not None else torch.cuda.current_stream()
+    _check(plan._lib.qc_contract_slices_noalloc(
+        plan.handle, ctypes.c_uint64(int(s_begin)), ctypes.c_uint64(int(s_end)), bits_dev.data_ptr(), n_bs,
+        _prec(prec), st.cuda_stream, out_dev.data_ptr(),
         per_slice_dev.data_ptr() if per_slice_dev is not None else None), plan._lib)
 
 
