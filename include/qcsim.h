@@ -119,6 +119,7 @@ typedef struct {
                                    computed once in qc_plan_build (not counted in n_steps or
                                    flops_per_slice) */
     int32_t reserved;
+    double flops_folded;        /* algorithmic flops of those steps (FP64 on the host, once per plan) */
 } qc_plan_info_t;
 
 /* circuit + bitstring + slice set -> contraction plan (host only).

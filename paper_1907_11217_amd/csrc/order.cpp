@@ -327,6 +327,7 @@ static void fold_invariant_subtrees(qc_plan *plan, const std::vector<char> &dyn_
     for (int n = L; n < L + M; ++n) any |= top[n];
     if (!any) return;
     // Host values of the folded nodes (post-order).
+    double folded_flops = 0;
     std::vector<Tensor> val(L + M);
     std::vector<char> have(L + M, 0);
     for (int t = 0; t < L; ++t)
@@ -339,6 +340,7 @@ static void fold_invariant_subtrees(qc_plan *plan, const std::vector<char> &dyn_
         for (int e : unions[i])
             if (!std::binary_search(sets[n].begin(), sets[n].end(), e)) contracted.push_back(e);
         val[n] = contract_host(val[a], val[b], sets[n], contracted);
+        folded_flops += 8.0 * std::ldexp(1.0, (int)unions[i].size());
         have[n] = 1;
         val[a] = Tensor();
         val[b] = Tensor();
@@ -377,6 +379,7 @@ static void fold_invariant_subtrees(qc_plan *plan, const std::vector<char> &dyn_
         new_id[n] = L2 + (int)tree.size() - 1;
     }
     plan->info.n_folded_steps = M - (int)tree.size();
+    plan->info.flops_folded = folded_flops;
     plan->net.leaves = std::move(leaves);
     plan->net.origin = std::move(origin);
     p.leaf_idx = std::move(leaf_idx);

@@ -76,7 +76,7 @@ class qc_plan_info_t(ctypes.Structure):
                 ("log2_max_entries", ctypes.c_double), ("flops_per_slice", ctypes.c_double),
                 ("bytes_per_slice", ctypes.c_double), ("flops_unsliced", ctypes.c_double),
                 ("peak_live_bytes", ctypes.c_double), ("plan_seconds", ctypes.c_double),
-                ("n_folded_steps", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("n_folded_steps", ctypes.c_int32), ("reserved", ctypes.c_int32), ("flops_folded", ctypes.c_double)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
