@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <atomic>
 #include <cmath>
+#include <functional>
 #include <queue>
 #include <thread>
 
@@ -234,10 +235,10 @@ TreeCost tree_cost(const OrderProblem &p, const std::vector<Merge> &tree,
 // met.  `sliced` may hold explicit choices on entry.
 static bool choose_slices(const OrderProblem &p, const std::vector<Merge> &tree, int k_target,
                           double cap_log2, std::vector<int> &sliced, const std::vector<char> &sliceable,
-                          double &achieved_log2) {
+                          double &achieved_log2, int max_add = 1 << 30) {
     std::vector<char> removed(p.n_index, 0);
     for (int e : sliced) removed[e] = 1;
-    for (;;) {
+    for (int added = 0;; ++added) {
         std::vector<std::vector<int>> sets, unions;
         node_sets(p, tree, removed, sets, unions);
         int maxr = 0;
@@ -245,18 +246,28 @@ static bool choose_slices(const OrderProblem &p, const std::vector<Merge> &tree,
         achieved_log2 = maxr;
         const bool cap_ok = cap_log2 <= 0 || maxr <= cap_log2;
         if (cap_ok && (int)sliced.size() >= k_target) return true;
-        // Candidates: indices of the largest nodes.
+        if (added == max_add) return false;
+        // While the cap is not met, candidates are the indices of the largest
+        // nodes and the one leaving the smallest largest node wins (then the
+        // fewest flops per slice); once it is met, more slices are wanted only
+        // for k, and any sliceable index may be taken: the one leaving the
+        // fewest flops per slice (the least total work over all slices).
         std::vector<char> cand(p.n_index, 0);
-        for (auto &s : sets)
-            if ((int)s.size() == maxr)
-                for (int e : s) cand[e] = sliceable[e] && !removed[e];
+        if (cap_ok) {
+            for (int e = 0; e < p.n_index; ++e) cand[e] = sliceable[e] && !removed[e];
+        } else {
+            for (auto &s : sets)
+                if ((int)s.size() == maxr)
+                    for (int e : s) cand[e] = sliceable[e] && !removed[e];
+        }
         int best = -1;
         int best_max = 1 << 30;
         double best_flops = 0;
         for (int e = 0; e < p.n_index; ++e) {
             if (!cand[e]) continue;
             int m = 0;
-            for (auto &s : sets) m = std::max(m, (int)s.size() - (int)std::binary_search(s.begin(), s.end(), e));
+            if (!cap_ok)
+                for (auto &s : sets) m = std::max(m, (int)s.size() - (int)std::binary_search(s.begin(), s.end(), e));
             double f = 0;
             for (auto &u : unions)
                 f += std::ldexp(1.0, (int)u.size() - (int)std::binary_search(u.begin(), u.end(), e));
@@ -288,6 +299,253 @@ static double per_pair_flops(const OrderProblem &p, const std::vector<Merge> &tr
         if (d || (int)sets[L + i].size() > kFoldMaxLog2) f += 8.0 * std::ldexp(1.0, (int)unions[i].size());
     }
     return f;
+}
+
+// ------------------------------------------------- subtree reconfiguration
+// Improves a tree locally: for a node r, its subtree is cut at a frontier F of
+// up to kReconfFrontier nodes (grown from r's children by opening the most
+// expensive internal frontier node first), and the order in which F's tensors
+// are contracted into r is replaced by the cheapest one, found by dynamic
+// programming over the subsets of F.  An index is open at a subset S of F
+// when some leaf under S holds it and some leaf outside S does, so every
+// subset has a fixed index set and the cost of a merge A + B is 2^|open(A)
+// U open(B)|.  Merges of tensors free of dynamic leaves that stay within the
+// host-folding limits cost nothing (they are evaluated once on the host).
+// A new tree is kept only if its per-(slice, bitstring) work -- the objective
+// of the search -- goes down and no intermediate exceeds the cap.
+constexpr int kReconfFrontier = 10;
+constexpr int kReconfMaxIdx = 128;
+constexpr int kReconfSweeps = 6;
+
+namespace {
+
+struct TreeShape {
+    int L = 0;
+    std::vector<int> a, b;        // children of node L + i
+    int root = -1;
+};
+
+TreeShape shape_of(int L, const std::vector<Merge> &tree) {
+    TreeShape t;
+    t.L = L;
+    for (const Merge &m : tree) { t.a.push_back(m.a); t.b.push_back(m.b); }
+    t.root = tree.empty() ? 0 : L + (int)tree.size() - 1;
+    return t;
+}
+
+// The merges of a shape in post-order from its root (children before parents).
+std::vector<Merge> merges_of(const TreeShape &t) {
+    std::vector<Merge> out;
+    std::vector<int> id(t.L + t.a.size(), -1);
+    for (int l = 0; l < t.L; ++l) id[l] = l;
+    std::vector<std::pair<int, int>> st{{t.root, 0}};
+    while (!st.empty()) {
+        auto &[n, state] = st.back();
+        if (n < t.L) { st.pop_back(); continue; }
+        const int i = n - t.L;
+        if (state == 0) { state = 1; st.push_back({t.a[i], 0}); continue; }
+        if (state == 1) { state = 2; st.push_back({t.b[i], 0}); continue; }
+        out.push_back(Merge{id[t.a[i]], id[t.b[i]]});
+        id[n] = t.L + (int)out.size() - 1;
+        st.pop_back();
+    }
+    return out;
+}
+
+struct Bits {
+    uint64_t w[2] = {0, 0};
+    void set(int i) { w[i >> 6] |= uint64_t(1) << (i & 63); }
+    int count() const { return __builtin_popcountll(w[0]) + __builtin_popcountll(w[1]); }
+    Bits operator|(const Bits &o) const { Bits r; r.w[0] = w[0] | o.w[0]; r.w[1] = w[1] | o.w[1]; return r; }
+};
+
+}  // namespace
+
+// Open index sets and merge unions of every node of a shape (node ids as in
+// the shape: leaves, then L + i for the node whose children are a[i], b[i]).
+static void shape_sets(const OrderProblem &p, const TreeShape &t, const std::vector<char> &removed,
+                       const std::vector<int> &total, std::vector<std::vector<int>> &sets,
+                       std::vector<std::vector<int>> &unions) {
+    const int N = t.L + (int)t.a.size();
+    std::vector<std::vector<std::pair<int, int>>> cnt(N);
+    sets.assign(N, {});
+    unions.assign(N, {});
+    for (int l = 0; l < t.L; ++l) {
+        for (int e : p.leaf_idx[l])
+            if (!removed[e]) cnt[l].push_back({e, 1});
+        std::sort(cnt[l].begin(), cnt[l].end());
+        for (auto &v : cnt[l]) sets[l].push_back(v.first);
+    }
+    std::vector<std::pair<int, int>> st{{t.root, 0}};
+    while (!st.empty()) {
+        auto &[n, state] = st.back();
+        if (n < t.L) { st.pop_back(); continue; }
+        const int i = n - t.L;
+        if (state == 0) { state = 1; st.push_back({t.a[i], 0}); continue; }
+        if (state == 1) { state = 2; st.push_back({t.b[i], 0}); continue; }
+        const auto &ca = cnt[t.a[i]], &cb = cnt[t.b[i]];
+        size_t x = 0, y = 0;
+        while (x < ca.size() || y < cb.size()) {
+            std::pair<int, int> v;
+            if (y == cb.size() || (x < ca.size() && ca[x].first < cb[y].first)) v = ca[x++];
+            else if (x == ca.size() || cb[y].first < ca[x].first) v = cb[y++];
+            else { v = {ca[x].first, ca[x].second + cb[y].second}; ++x; ++y; }
+            unions[n].push_back(v.first);
+            if (v.second < total[v.first]) { cnt[n].push_back(v); sets[n].push_back(v.first); }
+        }
+        st.pop_back();
+    }
+}
+
+static double reconfigure(const OrderProblem &p, std::vector<Merge> &tree, const std::vector<char> &removed,
+                          const std::vector<char> &dyn_leaf, double cap, uint64_t seed, int sweeps) {
+    const int L = (int)p.leaf_idx.size();
+    if (tree.size() < 2) return per_pair_flops(p, tree, removed, dyn_leaf);
+    std::vector<int> total(p.n_index, 0);
+    for (int t = 0; t < L; ++t)
+        for (int e : p.leaf_idx[t])
+            if (!removed[e]) ++total[e];
+    double best = per_pair_flops(p, tree, removed, dyn_leaf);
+    Rng rng{seed};
+    TreeShape t = shape_of(L, tree);
+    const int N = L + (int)t.a.size();
+    std::vector<std::vector<int>> sets, unions;
+    std::vector<char> dyn(N, 0);
+    auto refresh = [&]() {
+        shape_sets(p, t, removed, total, sets, unions);
+        for (int l = 0; l < L; ++l) dyn[l] = dyn_leaf[l];
+        // dyn of internal nodes, children first (post-order of the shape).
+        std::vector<std::pair<int, int>> st{{t.root, 0}};
+        while (!st.empty()) {
+            auto &[n, state] = st.back();
+            if (n < L) { st.pop_back(); continue; }
+            const int i = n - L;
+            if (state == 0) { state = 1; st.push_back({t.a[i], 0}); continue; }
+            if (state == 1) { state = 2; st.push_back({t.b[i], 0}); continue; }
+            dyn[n] = dyn[t.a[i]] || dyn[t.b[i]];
+            st.pop_back();
+        }
+    };
+    refresh();
+    for (int sweep = 0; sweep < sweeps; ++sweep) {
+        bool improved = false;
+        // Visit internal nodes from the most expensive merge down (ties random).
+        std::vector<std::pair<double, int>> order;
+        for (int n = L; n < N; ++n) order.push_back({-(double)unions[n].size() - 0.5 * rng.uniform(), n});
+        std::sort(order.begin(), order.end());
+        for (auto &oi : order) {
+            const int r = oi.second;
+            // Frontier: open the most expensive internal node first.
+            std::vector<int> F{t.a[r - L], t.b[r - L]};
+            std::vector<int> inner{r};
+            while ((int)F.size() < kReconfFrontier) {
+                int pick = -1;
+                for (int j = 0; j < (int)F.size(); ++j)
+                    if (F[j] >= L && (pick < 0 || unions[F[j]].size() > unions[F[pick]].size())) pick = j;
+                if (pick < 0) break;
+                const int n = F[pick];
+                inner.push_back(n);
+                F[pick] = t.a[n - L];
+                F.push_back(t.b[n - L]);
+            }
+            const int f = (int)F.size();
+            if (f < 3) continue;
+            // Index universe of the frontier and per-frontier leaf counts.
+            std::vector<int> E;
+            for (int x : F) E.insert(E.end(), sets[x].begin(), sets[x].end());
+            std::sort(E.begin(), E.end());
+            E.erase(std::unique(E.begin(), E.end()), E.end());
+            if ((int)E.size() > kReconfMaxIdx) continue;
+            std::vector<std::vector<int>> cnt(f, std::vector<int>(E.size(), 0));
+            for (int x = 0; x < f; ++x) {
+                std::vector<int> st{F[x]};
+                while (!st.empty()) {
+                    const int n = st.back();
+                    st.pop_back();
+                    if (n >= L) { st.push_back(t.a[n - L]); st.push_back(t.b[n - L]); continue; }
+                    for (int e : p.leaf_idx[n]) {
+                        if (removed[e]) continue;
+                        auto it = std::lower_bound(E.begin(), E.end(), e);
+                        if (it != E.end() && *it == e) ++cnt[x][it - E.begin()];
+                    }
+                }
+            }
+            const int S_all = (1 << f) - 1;
+            std::vector<Bits> open(S_all + 1);
+            std::vector<char> cst(S_all + 1, 1);
+            std::vector<int> c(E.size());
+            for (int S = 1; S <= S_all; ++S) {
+                std::fill(c.begin(), c.end(), 0);
+                bool cs = true;
+                for (int x = 0; x < f; ++x)
+                    if ((S >> x) & 1) {
+                        cs = cs && !dyn[F[x]];
+                        for (size_t j = 0; j < E.size(); ++j) c[j] += cnt[x][j];
+                    }
+                Bits bm;
+                for (size_t j = 0; j < E.size(); ++j)
+                    if (c[j] > 0 && c[j] < total[E[j]]) bm.set((int)j);
+                open[S] = bm;
+                cst[S] = cs;
+            }
+            const double INF = 1e300;
+            std::vector<double> cost(S_all + 1, INF);
+            std::vector<int> split(S_all + 1, 0);
+            for (int x = 0; x < f; ++x) cost[1 << x] = 0;
+            for (int S = 1; S <= S_all; ++S) {
+                if (__builtin_popcount(S) < 2) continue;
+                const int sz = open[S].count();
+                if (cap > 0 && sz > cap) continue;
+                const int low = S & -S;
+                // A holds the lowest member of S; B = S \ A is nonempty.
+                for (int A = (S - 1) & S; A > 0; A = (A - 1) & S) {
+                    if (!(A & low)) continue;
+                    const int B = S ^ A;
+                    if (cost[A] >= INF || cost[B] >= INF) continue;
+                    const int u = (open[A] | open[B]).count();
+                    const bool folds = cst[S] && sz <= kFoldMaxLog2 && u <= kFoldMaxLog2 + 4;
+                    const double v = cost[A] + cost[B] + (folds ? 0.0 : std::ldexp(1.0, u));
+                    if (v < cost[S]) { cost[S] = v; split[S] = A; }
+                }
+            }
+            if (cost[S_all] >= INF) continue;
+            // Current cost of the subtree's merges under the same rule.
+            double cur = 0;
+            for (int n : inner) {
+                const bool folds = !dyn[n] && (int)sets[n].size() <= kFoldMaxLog2 &&
+                                   (int)unions[n].size() <= kFoldMaxLog2 + 4;
+                cur += folds ? 0.0 : std::ldexp(1.0, (int)unions[n].size());
+            }
+            if (cost[S_all] >= cur * (1 - 1e-9)) continue;
+            // Rebuild the subtree reusing the inner nodes' ids (r keeps its id).
+            TreeShape t2 = t;
+            std::vector<int> free_ids(inner.begin() + 1, inner.end());
+            std::function<int(int, bool)> build = [&](int S, bool is_root) -> int {
+                if (__builtin_popcount(S) == 1) return F[__builtin_ctz(S)];
+                const int A = split[S], B = S ^ A;
+                const int na = build(A, false), nb = build(B, false);
+                const int id = is_root ? r : free_ids.back();
+                if (!is_root) free_ids.pop_back();
+                t2.a[id - L] = na;
+                t2.b[id - L] = nb;
+                return id;
+            };
+            build(S_all, true);
+            std::vector<Merge> cand = merges_of(t2);
+            const TreeCost tc = tree_cost(p, cand, removed);
+            if (cap > 0 && tc.max_log2 > cap) continue;
+            const double v = per_pair_flops(p, cand, removed, dyn_leaf);
+            if (v < best * (1 - 1e-12)) {
+                best = v;
+                t = std::move(t2);
+                tree = std::move(cand);
+                refresh();
+                improved = true;
+            }
+        }
+        if (!improved) break;
+    }
+    return best;
 }
 
 // Replaces every maximal pair-invariant subtree (no dynamic leaf, result of
@@ -444,9 +702,16 @@ bool search_plan(qc_plan *plan, const qc_slice_spec *spec, std::string &err) {
         bool ok = false;
     };
     std::vector<Trial> tr(trials);
+    // Leaves holding an output segment (or a caller-chosen slice) differ per
+    // (slice, bitstring); the rest can be folded.
+    std::vector<char> dyn0(p.leaf_idx.size(), 0);
+    for (size_t t = 0; t < p.leaf_idx.size(); ++t)
+        for (int e : plan->net.leaves[t].idx)
+            if (plan->net.out_qubit[e] >= 0 || none[e]) dyn0[t] = 1;
     parallel_trials(trials, [&](int t) {
         Trial &r = tr[t];
         r.tree = greedy_order(p, none, seed + 0x1000 * t, t == 0 ? 0.0 : 0.1 + 0.05 * (t % 8));
+        reconfigure(p, r.tree, none, dyn0, 0, seed + 0x3000 + t, 2);
         r.sl = explicit_s;
         r.ok = choose_slices(p, r.tree, kt, cap, r.sl, sliceable, r.ach);
         if (r.ok) {
@@ -486,14 +751,66 @@ bool search_plan(qc_plan *plan, const qc_slice_spec *spec, std::string &err) {
         return tr[x].total < tr[y].total;
     });
     const size_t n_cand = std::min<size_t>(ok_trials.size(), 8);
-    double best_score = -1;
-    std::vector<char> best_dyn;
-    for (size_t ci = 0; ci < n_cand; ++ci) {
+    std::vector<std::vector<int>> slices_of_cand(n_cand);
+    for (size_t ci = 0; ci < n_cand; ++ci) slices_of_cand[ci] = tr[ok_trials[ci]].sl;
+    // The candidates are refined in parallel, each into its own slot, and
+    // compared in candidate order afterwards (so the plan does not depend on
+    // the thread count).
+    struct Refined {
+        bool ok = false;
+        double dev = 0;
+        std::vector<Merge> tree;
+        std::vector<char> dyn;
+    };
+    std::vector<Refined> refined(n_cand);
+    parallel_trials((int)n_cand, [&](int cii) {
+        const size_t ci = (size_t)cii;
         const Trial &cand = tr[ok_trials[ci]];
-        if (cand.sl.size() != tr[ok_trials[0]].sl.size()) break;
+        if (cand.sl.size() != tr[ok_trials[0]].sl.size()) return;
         std::vector<Merge> tree = cand.tree;
         std::vector<char> rm(p.n_index, 0);
         for (int e : cand.sl) rm[e] = 1;
+        // A second slice set for this tree: one index at a time, the tree
+        // reconfigured for the sliced network after each, so that it can
+        // gather its expensive merges on the sliced indices.  Kept if its
+        // per-slice work beats the first set's once both are reconfigured.
+        {
+            std::vector<Merge> t2 = cand.tree;
+            std::vector<int> sl2 = explicit_s;
+            std::vector<char> rm2(p.n_index, 0);
+            for (int e : sl2) rm2[e] = 1;
+            double ach = 0;
+            bool done = false;
+            for (int step = 0; step < 64 && !done; ++step) {
+                done = choose_slices(p, t2, kt, cap, sl2, sliceable, ach, 1);
+                std::fill(rm2.begin(), rm2.end(), 0);
+                for (int e : sl2) rm2[e] = 1;
+                std::vector<char> dyn2(p.leaf_idx.size(), 0);
+                for (size_t t = 0; t < p.leaf_idx.size(); ++t)
+                    for (int e : plan->net.leaves[t].idx)
+                        if (plan->net.out_qubit[e] >= 0 || rm2[e]) dyn2[t] = 1;
+                reconfigure(p, t2, rm2, dyn2, 0, seed + 0xB000 + 0x100 * ci + step, 2);
+            }
+            if (done && (int)sl2.size() == (int)cand.sl.size()) {
+                std::vector<char> dyn2(p.leaf_idx.size(), 0), dyn1(p.leaf_idx.size(), 0);
+                for (size_t t = 0; t < p.leaf_idx.size(); ++t)
+                    for (int e : plan->net.leaves[t].idx) {
+                        if (plan->net.out_qubit[e] >= 0 || rm2[e]) dyn2[t] = 1;
+                        if (plan->net.out_qubit[e] >= 0 || rm[e]) dyn1[t] = 1;
+                    }
+                std::vector<Merge> t1 = tree;
+                const double f2 = reconfigure(p, t2, rm2, dyn2, cap, seed + 0xC000 + ci, 2);
+                const double f1 = reconfigure(p, t1, rm, dyn1, cap, seed + 0xD000 + ci, 2);
+                const TreeCost c2 = tree_cost(p, t2, rm2);
+                if (f2 < f1 && (cap <= 0 || c2.max_log2 <= cap)) {
+                    tree = t2;
+                    rm = rm2;
+                    slices_of_cand[ci] = sl2;
+                } else {
+                    tree = t1;
+                }
+            }
+        }
         // Re-search the order on the sliced network; keep it if cheaper and
         // still within the cap.
         TreeCost bc = tree_cost(p, tree, rm);
@@ -524,11 +841,22 @@ bool search_plan(qc_plan *plan, const qc_slice_spec *spec, std::string &err) {
         });
         for (auto &r : ph)
             if (r.second >= 0 && r.second < dev) { dev = r.second; tree = r.first; }
-        if (best_score < 0 || dev < best_score) {
-            best_score = dev;
-            best_tree = tree;
-            best_sliced = cand.sl;
-            best_dyn = dyn_leaf;
+        // Local optimisation of the chosen tree for this slice set.
+        dev = reconfigure(p, tree, rm, dyn_leaf, cap, seed + 0x7000 + ci, kReconfSweeps);
+        refined[ci].ok = true;
+        refined[ci].dev = dev;
+        refined[ci].tree = std::move(tree);
+        refined[ci].dyn = std::move(dyn_leaf);
+    });
+    double best_score = -1;
+    std::vector<char> best_dyn;
+    for (size_t ci = 0; ci < n_cand; ++ci) {
+        if (!refined[ci].ok) continue;
+        if (best_score < 0 || refined[ci].dev < best_score) {
+            best_score = refined[ci].dev;
+            best_tree = refined[ci].tree;
+            best_sliced = slices_of_cand[ci];
+            best_dyn = refined[ci].dyn;
         }
     }
     std::vector<char> dyn_leaf = best_dyn;
