@@ -286,7 +286,21 @@ constexpr int kFoldMaxLog2 = 14;
 
 // Per-(slice, bitstring) flops of a tree once its foldable pair-invariant
 // subtrees are precomputed.
-static double per_pair_flops(const OrderProblem &p, const std::vector<Merge> &tree,
+// Estimated device cost of one pairwise step, in complex multiply-adds: the
+// larger of its multiply-adds and kMovePerMac times the elements it reads and
+// writes (a roofline with ~100 TFLOP/s of complex FP32 arithmetic against
+// ~5 TB/s of memory traffic), so that steps moving large tensors for little
+// arithmetic are charged for their traffic.
+constexpr double kMovePerMac = 20.0;
+inline double step_cost(int union_bits, int a_bits, int b_bits, int c_bits) {
+    const double macs = std::ldexp(1.0, union_bits);
+    const double moved = std::ldexp(1.0, a_bits) + std::ldexp(1.0, b_bits) + std::ldexp(1.0, c_bits);
+    return std::max(macs, kMovePerMac * moved);
+}
+
+// Per-(slice, bitstring) device cost of a tree once its foldable
+// pair-invariant subtrees are precomputed: the objective of the search.
+static double per_pair_cost(const OrderProblem &p, const std::vector<Merge> &tree,
                              const std::vector<char> &removed, const std::vector<char> &dyn_leaf) {
     std::vector<std::vector<int>> sets, unions;
     node_sets(p, tree, removed, sets, unions);
@@ -296,7 +310,9 @@ static double per_pair_flops(const OrderProblem &p, const std::vector<Merge> &tr
     for (size_t i = 0; i < tree.size(); ++i) {
         const bool d = dyn[tree[i].a] || dyn[tree[i].b];
         dyn.push_back(d);
-        if (d || (int)sets[L + i].size() > kFoldMaxLog2) f += 8.0 * std::ldexp(1.0, (int)unions[i].size());
+        if (d || (int)sets[L + i].size() > kFoldMaxLog2)
+            f += step_cost((int)unions[i].size(), (int)sets[tree[i].a].size(), (int)sets[tree[i].b].size(),
+                           (int)sets[L + i].size());
     }
     return f;
 }
@@ -400,12 +416,12 @@ static void shape_sets(const OrderProblem &p, const TreeShape &t, const std::vec
 static double reconfigure(const OrderProblem &p, std::vector<Merge> &tree, const std::vector<char> &removed,
                           const std::vector<char> &dyn_leaf, double cap, uint64_t seed, int sweeps) {
     const int L = (int)p.leaf_idx.size();
-    if (tree.size() < 2) return per_pair_flops(p, tree, removed, dyn_leaf);
+    if (tree.size() < 2) return per_pair_cost(p, tree, removed, dyn_leaf);
     std::vector<int> total(p.n_index, 0);
     for (int t = 0; t < L; ++t)
         for (int e : p.leaf_idx[t])
             if (!removed[e]) ++total[e];
-    double best = per_pair_flops(p, tree, removed, dyn_leaf);
+    double best = per_pair_cost(p, tree, removed, dyn_leaf);
     Rng rng{seed};
     TreeShape t = shape_of(L, tree);
     const int N = L + (int)t.a.size();
@@ -504,7 +520,8 @@ static double reconfigure(const OrderProblem &p, std::vector<Merge> &tree, const
                     if (cost[A] >= INF || cost[B] >= INF) continue;
                     const int u = (open[A] | open[B]).count();
                     const bool folds = cst[S] && sz <= kFoldMaxLog2 && u <= kFoldMaxLog2 + 4;
-                    const double v = cost[A] + cost[B] + (folds ? 0.0 : std::ldexp(1.0, u));
+                    const double v = cost[A] + cost[B] +
+                                     (folds ? 0.0 : step_cost(u, open[A].count(), open[B].count(), sz));
                     if (v < cost[S]) { cost[S] = v; split[S] = A; }
                 }
             }
@@ -514,7 +531,8 @@ static double reconfigure(const OrderProblem &p, std::vector<Merge> &tree, const
             for (int n : inner) {
                 const bool folds = !dyn[n] && (int)sets[n].size() <= kFoldMaxLog2 &&
                                    (int)unions[n].size() <= kFoldMaxLog2 + 4;
-                cur += folds ? 0.0 : std::ldexp(1.0, (int)unions[n].size());
+                cur += folds ? 0.0 : step_cost((int)unions[n].size(), (int)sets[t.a[n - L]].size(),
+                                               (int)sets[t.b[n - L]].size(), (int)sets[n].size());
             }
             if (cost[S_all] >= cur * (1 - 1e-9)) continue;
             // Rebuild the subtree reusing the inner nodes' ids (r keeps its id).
@@ -534,7 +552,7 @@ static double reconfigure(const OrderProblem &p, std::vector<Merge> &tree, const
             std::vector<Merge> cand = merges_of(t2);
             const TreeCost tc = tree_cost(p, cand, removed);
             if (cap > 0 && tc.max_log2 > cap) continue;
-            const double v = per_pair_flops(p, cand, removed, dyn_leaf);
+            const double v = per_pair_cost(p, cand, removed, dyn_leaf);
             if (v < best * (1 - 1e-12)) {
                 best = v;
                 t = std::move(t2);
@@ -830,14 +848,14 @@ bool search_plan(qc_plan *plan, const qc_slice_spec *spec, std::string &err) {
         for (size_t t = 0; t < p.leaf_idx.size(); ++t)
             for (int e : plan->net.leaves[t].idx)
                 if (plan->net.out_qubit[e] >= 0 || rm[e]) dyn_leaf[t] = 1;
-        double dev = per_pair_flops(p, tree, rm, dyn_leaf);
+        double dev = per_pair_cost(p, tree, rm, dyn_leaf);
         const int const_cap = std::max(4, (int)bc.max_log2);
         std::vector<std::pair<std::vector<Merge>, double>> ph(trials);
         parallel_trials(trials, [&](int t) {
             ph[t].first = greedy_order_phased(p, rm, seed + 0x5000 + 0x1000 * t + 0x100000 * ci,
                                               t == 0 ? 0.0 : 0.1 + 0.05 * (t % 8), &dyn_leaf, const_cap);
             const TreeCost c = tree_cost(p, ph[t].first, rm);
-            ph[t].second = (cap > 0 && c.max_log2 > cap) ? -1.0 : per_pair_flops(p, ph[t].first, rm, dyn_leaf);
+            ph[t].second = (cap > 0 && c.max_log2 > cap) ? -1.0 : per_pair_cost(p, ph[t].first, rm, dyn_leaf);
         });
         for (auto &r : ph)
             if (r.second >= 0 && r.second < dev) { dev = r.second; tree = r.first; }
