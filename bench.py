@@ -3,7 +3,7 @@
 
 Headline workload: the 70-qubit diamond lattice at depth 1+32+1 (seed 401,
 one bitstring), sliced into 2^20 slices of at most 2^30 entries.  One step =
-one qc_contract_slices_dev call over a chunk of consecutive slices (8 in
+one qc_contract_slices_dev call over a chunk of consecutive slices (64 in
 flight): leaf instantiation, every pairwise contraction step, the FP64
 cross-slice sum, inputs resident on the device.  A whole amplitude is 2^20
 such slices; as in the paper's own extrapolation from subtask times, the
@@ -77,28 +77,37 @@ def _traffic(kind, workload, prec):
 
 
 def _roofline(prof, prec, workload):
-    """The dominant kernel kind (most time) of a profiled loop: its achieved
-    rate from the algorithmic flops the library counts per launch and the
-    summed launch time (HIP events on the call's stream)."""
+    """The dominant kernel kind (most time) of a profiled loop: its algorithmic
+    flops and bytes as the library counts them per launch, over the summed
+    launch time (HIP events on the call's stream).  It is MFMA-bound when its
+    flops at the dtype's MFMA peak take longer than its bytes at the HBM
+    peak, else HBM-bound; `frac` is the achieved rate over that peak."""
     dom = max(prof, key=lambda kk: prof[kk][1])
-    launches, total_ms, flops = prof[dom]
-    if dom in MFMA_KINDS:
-        # Split forms: three 16-bit MFMA products per algorithmic product.
-        achieved = flops * HW_PER_ALG[prec] / (total_ms * 1e-3) / 1e12
-        peak, bound = PEAK_MFMA_TFLOPS[prec], "mfma"
+    launches, total_ms, flops, nbytes = prof[dom]
+    hw = HW_PER_ALG[prec] if dom in MFMA_KINDS else 1.0
+    peak_f = PEAK_MFMA_TFLOPS[prec] if dom in MFMA_KINDS else PEAK_FP32_TFLOPS
+    t_f = flops * hw / (peak_f * 1e12)
+    t_b = nbytes / (PEAK_HBM_GBS * 1e9)
+    sec = total_ms * 1e-3
+    if t_f >= t_b:
+        r = {"bound": "mfma" if dom in MFMA_KINDS else "alu", "achieved": flops * hw / sec / 1e12, "peak": peak_f,
+             "unit": "TFLOP/s"}
     else:
-        achieved = flops / (total_ms * 1e-3) / 1e12
-        peak, bound = PEAK_FP32_TFLOPS, "alu"
-    return {"bound": bound, "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-            "traffic": _traffic(dom, workload, prec), "kernel": dom, "launches": launches,
-            "avg_launch_ms": total_ms / launches, "flops_per_launch": flops / launches,
-            "flops_counted": "hardware (3 per algorithmic) for split forms" if prec != "c64" and dom in MFMA_KINDS
-            else "algorithmic (8 per complex multiply-add)"}
+        r = {"bound": "hbm", "achieved": nbytes / sec / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s"}
+    r["frac"] = r["achieved"] / r["peak"]
+    r.update({"traffic": _traffic(dom, workload, prec), "kernel": dom, "launches": launches,
+              "avg_launch_ms": total_ms / launches, "flops_per_launch": flops / launches,
+              "bytes_per_launch": nbytes / launches, "tflops_alg": flops / sec / 1e12, "gbs_alg": nbytes / sec / 1e9,
+              "roofline_time_frac": max(t_f, t_b) / sec,
+              "flops_counted": "hardware (3 per algorithmic) for split forms" if hw > 1
+              else "algorithmic (8 per complex multiply-add)"})
+    return r
 
 
 def _kernel_table(prof, steps):
     return {kk: {"launches_per_step": v[0] / steps, "ms_per_step": v[1] / steps,
-                 "tflops_alg": (v[2] / (v[1] * 1e-3) / 1e12) if v[1] > 0 and v[2] > 0 else None}
+                 "tflops_alg": (v[2] / (v[1] * 1e-3) / 1e12) if v[1] > 0 and v[2] > 0 else None,
+                 "gbs_alg": (v[3] / (v[1] * 1e-3) / 1e9) if v[1] > 0 and v[3] > 0 else None}
             for kk, v in prof.items()}
 
 
@@ -129,7 +138,7 @@ def _slice_errors(got, ref, tol):
 
 
 # ---------------------------------------------------------------- headline
-def diamond_leg(steps, warmup, precs, chunk=None, cpu=True):
+def diamond_leg(steps, warmup, precs, chunk=None, cpu=True, tune_cache=None):
     """The 70-qubit depth 1+32+1 workload: a chunk of consecutive slices per
     step, each precision timed over `steps` steps after `warmup` (the first
     call of a configuration captures its graph), then `min(steps, 5)` steps
@@ -185,7 +194,7 @@ def diamond_leg(steps, warmup, precs, chunk=None, cpu=True):
     for prec in precs:
         ws = torch.empty(qcsim.qc_workspace_bytes(plan, chunk, 1, prec), dtype=torch.uint8, device="cuda")
         t1 = time.perf_counter()
-        n_timed = qcsim.qc_tune(plan, chunk, 1, prec, ws, stream=stream)   # untimed preparation
+        n_timed = qcsim.qc_tune(plan, chunk, 1, prec, ws, cache_path=tune_cache, stream=stream)   # untimed
         torch.cuda.synchronize()
         tune_s = time.perf_counter() - t1
 
@@ -287,7 +296,7 @@ def fused_leg(steps=50, warmup=10, cpu=True):
            "fused_waves_per_item": item["fused_waves"], "fused_flops_per_item": item["flops"],
            "kernels": {kk: {"launches_per_step": v[0] / n_prof, "avg_ms": v[1] / v[0]} for kk, v in prof.items()}}
     if "fused" in prof:
-        launches, total_ms, _ = prof["fused"]
+        launches, total_ms = prof["fused"][:2]
         items_per_launch = (n_slices >> fb) * n_bs
         ach = item["flops"] * items_per_launch / (total_ms / launches * 1e-3) / 1e12
         leg["fused_roofline"] = {"bound": "alu", "achieved": ach, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
@@ -507,7 +516,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--prec", default="c64", choices=["c64", "split_fp16", "split_bf16"],
                     help="precision of the headline value (the others are reported beside it)")
-    ap.add_argument("--chunk", type=int, default=0, help="slices per step of the 70-qubit workload (default 8)")
+    ap.add_argument("--chunk", type=int, default=0, help="slices per step of the 70-qubit workload (default 64)")
+    ap.add_argument("--tune-cache", default=None,
+                    help="text file of GEMM form choices read before and written after tuning the 70-qubit "
+                         "workload (a profiling run then times no forms)")
     ap.add_argument("--only-prec", action="store_true", help="time only --prec on the 70-qubit workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the 4x4, 5x5, 7x7 and request-batch legs")
@@ -541,7 +553,8 @@ def main():
 
     precs = [args.prec] if args.only_prec else \
         [args.prec] + [p for p in ("c64", "split_fp16", "split_bf16") if p != args.prec]
-    head = diamond_leg(args.steps, args.warmup, precs, chunk=args.chunk or None, cpu=not args.no_cpu_baseline)
+    head = diamond_leg(args.steps, args.warmup, precs, chunk=args.chunk or None, cpu=not args.no_cpu_baseline,
+                       tune_cache=args.tune_cache)
     main_prec = head["per_prec"][args.prec]
     result = {
         "metric": METRIC,

@@ -279,11 +279,12 @@ qc_status qc_tune(qc_plan *plan, int64_t chunk_slices, int32_t n_bs, qc_precisio
  * events on its stream around every kernel it launches.  qc_profile_read
  * waits for the recorded events, then reports per kernel kind the launch
  * count, the summed event-to-event milliseconds and the summed algorithmic
- * flops of those launches (8 nb m n k per GEMM step, the micro launch's
- * steps likewise; 0 for kinds that do no GEMM work) since the last read,
- * and clears them.  kinds: "fused", "leaves", "micro", "transpose",
- * "gemm_mfma", "gemm_split_bf16", "gemm_split_fp16", "gemm_skinny",
- * "gemm_dot", "gemm_valu", "reduce64" (a GEMM step split over k counts its
+ * flops and bytes of those launches (8 nb m n k flops and 8 nb (m k + k n +
+ * m n) bytes per GEMM step, the micro launch's steps likewise; 0 for kinds
+ * that do no GEMM work) since the last read, and clears them.  kinds:
+ * "fused", "leaves", "micro", "transpose", "gemm_mfma", "gemm_split_bf16",
+ * "gemm_split_fp16", "gemm_skinny", "gemm_skinny_t", "gemm_rows", "gemm_dot",
+ * "gemm_dot_tile", "gemm_valu", "reduce64" (a GEMM step split over k counts its
  * partial products and their sum under its form's kind), so the kinds show
  * which form -- and for split precisions whether a split MFMA form or a
  * complex FP32 one -- ran each step.  Launches replayed from a graph are not
@@ -294,6 +295,7 @@ typedef struct {
     int64_t launches;
     double total_ms;
     double flops;
+    double bytes;      /* algorithmic bytes of those launches: 8 nb (m k + k n + m n) per GEMM step */
 } qc_kernel_stat_t;
 qc_status qc_profile_enable(qc_plan *plan, int32_t on);
 qc_status qc_profile_read(qc_plan *plan, qc_kernel_stat_t *out, int32_t cap, int32_t *n);

@@ -46,15 +46,19 @@ qc_status qc_kernel_gemm(const void *A, const void *B, void *C, int64_t nb, int6
  *   tiles 32x32, 32x64, 64x32, 64x64 (QC_C64; k in {2,4,8} or a multiple of
  *   16), 7 split 128x128, 8..11 split 32x32, 32x64, 64x32, 64x64 (split
  *   precisions, k >= 2), 12 complex FP32 MFMA 128x128 (QC_C64, k >= 2, m and n
- *   multiples of 128); form -1 is the default choice.  Forms 0..2 compute
- *   in FP32 for every precision.  QC_ERR_UNSUPPORTED if the form does not
- *   apply to the shape and precision. */
+ *   multiples of 128), 13 skinny on the transposed product (n in
+ *   {1,2,4,8,16}, m >= 64), 14 dot tile (m n <= 256, k >= 64: one workgroup
+ *   per batch entry's whole tile, k staged through LDS), 15 rows (n in
+ *   {1,2,4,8,16}, m >= 64: one row of C per thread, B in LDS); form -1 is the
+ *   default choice.  Forms 0..2 and 13..15 compute in FP32 for every
+ *   precision.  QC_ERR_UNSUPPORTED if the form does not apply to the shape and
+ *   precision. */
 qc_status qc_kernel_gemm_form(const void *A, const void *B, void *C, int64_t nb, int64_t m, int64_t n, int64_t k,
                               int32_t a_km, int32_t b_nk, qc_precision prec, int32_t form, void *scale_ws,
                               void *stream);
 
 /* qc_kernel_gemm_form split over k, as the stepwise contraction runs its
- * GEMM steps with few outputs: every MFMA form (3-12) and the dot form (2)
+ * GEMM steps with few outputs: every MFMA form (3-12) and the dot forms (2, 14)
  * compute kparts partial products, part p over l in [p k/kparts,
  * (p+1) k/kparts), into `scratch`, then C = the parts summed in increasing p,
  * in FP32 (so the result is deterministic).  scratch: caller-owned device
@@ -74,9 +78,11 @@ qc_status qc_kernel_gemm_kparts(const void *A, const void *B, void *C, int64_t n
  * least 1024 tiles times p, while each part keeps at least 256 of k; else for
  * m and n multiples of 32 with fewer than 4096 tiles of 32x32, the smallest
  * power of two p <= 64 with at least 4096 tiles times p, while each part keeps
- * at least 256 of k; else for at most 4096 outputs and k >= 8192, the
- * smallest power of two p with at least 1024 outputs times p, while each part
- * keeps at least 4096 of k; else 1.
+ * at least 256 of k; else for m n <= 256 and k >= 1024, the smallest power
+ * of two p <= 1024 with nb p >= 1024, while each part keeps at least 256 of
+ * k; else for at most 4096 outputs and k >= 8192, the smallest power of two p
+ * with at least 1024 outputs times p, while each part keeps at least 4096 of
+ * k; else 1.
  * The scratch for the largest such step is part of qc_workspace_bytes. */
 int64_t qc_gemm_kparts(int64_t nb, int64_t m, int64_t n, int64_t k);
 

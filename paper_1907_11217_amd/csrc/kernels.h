@@ -221,7 +221,11 @@ const char *launch_gemm(const GemmDesc &d, hipStream_t st);  // returns the form
 // the 128 x 128 tiles; Skinny: m <= 16; Dot: few outputs, long k; Valu: any.
 enum GemmVariant {
     kVarValu = 0, kVarSkinny, kVarDot, kVarMfma11, kVarMfma12, kVarMfma21, kVarMfma22,
-    kVarSplitBig, kVarSplit11, kVarSplit12, kVarSplit21, kVarSplit22, kVarMfmaBig, kVarCount
+    kVarSplitBig, kVarSplit11, kVarSplit12, kVarSplit21, kVarSplit22, kVarMfmaBig,
+    kVarSkinnyT,   // the skinny form on the transposed problem (C^T = B^T A^T): n <= 16, wide m
+    kVarDotTile,   // small output tile (m n <= 256 per batch), long k: A and B k-chunks through LDS
+    kVarRows,      // n <= 16, tall m: B in LDS, one row of C per thread, A rows read once
+    kVarCount
 };
 bool gemm_variant_ok(const GemmDesc &d, int v);
 int gemm_default_variant(const GemmDesc &d);

@@ -434,6 +434,142 @@ __global__ void __launch_bounds__(1024) gemm_dot_kernel(GemmDesc d) {
     if (d.amax_c) block_amax(mx, d.amax_c);
 }
 
+// Rows form for a small n (<= 16) with a tall m: B's k x n values are staged
+// in LDS ([k][n], up to 2048 per pass, read as broadcasts) and each thread
+// owns one row of C, keeping its n outputs in registers while it reads the
+// row of A once -- with 16-byte loads along k when A is stored [m][k], or
+// coalesced across the threads' rows when it is stored [k][m].  Sums run
+// over k in increasing order.
+template <int N>
+__global__ void __launch_bounds__(256) gemm_rows_kernel(GemmDesc d) {
+    constexpr int KC = 2048 / N;
+    __shared__ float2 Bs[KC * N];
+    const bool avec = d.sAk == 1 && d.sAm % 2 == 0 && d.sAb % 2 == 0 && (uintptr_t)d.A % 16 == 0;
+    const int64_t chunks = (d.m + 255) / 256;
+    const int64_t total = d.nb * chunks;
+    // Column offsets of C (its n bits), per column.
+    int64_t coff[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) coff[j] = d.cscatter ? scat_bits(d, uint64_t(j), 0, d.cbn) : j * d.sCn;
+    float mx = 0.f;
+    for (int64_t blk = blockIdx.x; blk < total; blk += gridDim.x) {
+        const int64_t bi = blk / chunks;
+        const int64_t i = (blk % chunks) * 256 + threadIdx.x;
+        const bool ok = i < d.m;
+        const float2 *Ar = d.A + bi * d.sAb + (ok ? i : 0) * d.sAm;
+        const float2 *Bb = d.B + bi * d.sBb;
+        float re[N], im[N];
+#pragma unroll
+        for (int j = 0; j < N; ++j) { re[j] = 0.f; im[j] = 0.f; }
+        for (int64_t k0 = 0; k0 < d.k; k0 += KC) {
+            const int kc = int(d.k - k0 < KC ? d.k - k0 : KC);
+            __syncthreads();
+            for (int e = threadIdx.x; e < kc * N; e += blockDim.x) {
+                const int l = e / N, j = e - l * N;
+                Bs[e] = Bb[(k0 + l) * d.sBk + j * d.sBn];
+            }
+            __syncthreads();
+            if (ok) {
+                int l = 0;
+                if (avec) {
+                    for (; l + 1 < kc; l += 2) {
+                        const float4 w = *(const float4 *)(Ar + k0 + l);
+#pragma unroll
+                        for (int j = 0; j < N; ++j) {
+                            const float2 y0 = Bs[l * N + j], y1 = Bs[(l + 1) * N + j];
+                            re[j] = fmaf(w.x, y0.x, re[j]);
+                            re[j] = fmaf(-w.y, y0.y, re[j]);
+                            im[j] = fmaf(w.x, y0.y, im[j]);
+                            im[j] = fmaf(w.y, y0.x, im[j]);
+                            re[j] = fmaf(w.z, y1.x, re[j]);
+                            re[j] = fmaf(-w.w, y1.y, re[j]);
+                            im[j] = fmaf(w.z, y1.y, im[j]);
+                            im[j] = fmaf(w.w, y1.x, im[j]);
+                        }
+                    }
+                }
+                for (; l < kc; ++l) {
+                    const float2 x = Ar[(k0 + l) * d.sAk];
+#pragma unroll
+                    for (int j = 0; j < N; ++j) {
+                        const float2 y = Bs[l * N + j];
+                        re[j] = fmaf(x.x, y.x, re[j]);
+                        re[j] = fmaf(-x.y, y.y, re[j]);
+                        im[j] = fmaf(x.x, y.y, im[j]);
+                        im[j] = fmaf(x.y, y.x, im[j]);
+                    }
+                }
+            }
+        }
+        if (ok) {
+            const int64_t ro = d.cscatter ? scat_bits(d, uint64_t(bi), d.cbn + d.cbm, d.cbb) +
+                                                scat_bits(d, uint64_t(i), d.cbn, d.cbm)
+                                          : bi * d.sCb + i * d.sCm;
+#pragma unroll
+            for (int j = 0; j < N; ++j) {
+                d.C[ro + coff[j]] = make_float2(re[j], im[j]);
+                mx = fmaxf(mx, fmaxf(fabsf(re[j]), fabsf(im[j])));
+            }
+        }
+    }
+    if (d.amax_c) block_amax(mx, d.amax_c);
+}
+
+// Dot-tile form for a small output tile (m n <= 256 per batch) with a long k:
+// a workgroup owns one batch entry's whole m x n tile, thread t < m n one
+// output (t / n, t % n); k runs in chunks whose A (m x kc) and B (kc x n)
+// values are staged in LDS with loads coalesced along whichever index is
+// contiguous, so every operand value is read from memory once per
+// workgroup.  Sums run over k in increasing order.  Split over k, each
+// workgroup takes one part of one batch entry.
+__global__ void __launch_bounds__(256) gemm_dot_tile_kernel(GemmDesc d) {
+    __shared__ float2 sm[4096];
+    const int m = int(d.m), n = int(d.n), mn = m * n;
+    int kc = 4096 / (m + n);
+    kc = kc >= 64 ? 64 : kc;
+    float2 *As = sm, *Bs = sm + m * kc;
+    const bool a_k_fast = d.sAk == 1, b_k_fast = d.sBk == 1;
+    const int t = threadIdx.x;
+    const int oi = t / n, oj = t - (t / n) * n;
+    float mx = 0.f;
+    for (int64_t bi = blockIdx.x; bi < d.nb; bi += gridDim.x) {
+        const int64_t bq = d.kparts == 1 ? bi : bi / d.kparts, bp = bi - bq * d.kparts;
+        const float2 *a = d.A + bq * d.sAb + bp * d.sAp;
+        const float2 *b = d.B + bq * d.sBb + bp * d.sBp;
+        float re = 0.f, im = 0.f;
+        for (int64_t l0 = 0; l0 < d.k; l0 += kc) {
+            const int c = int(d.k - l0 < kc ? d.k - l0 : kc);
+            __syncthreads();
+            for (int e = t; e < m * c; e += blockDim.x) {
+                int i, l;
+                if (a_k_fast) { i = e / c; l = e - i * c; } else { l = e / m; i = e - l * m; }
+                As[i * kc + l] = a[i * d.sAm + (l0 + l) * d.sAk];
+            }
+            for (int e = t; e < n * c; e += blockDim.x) {
+                int j, l;
+                if (b_k_fast) { j = e / c; l = e - j * c; } else { l = e / n; j = e - l * n; }
+                Bs[l * n + j] = b[(l0 + l) * d.sBk + j * d.sBn];
+            }
+            __syncthreads();
+            if (t < mn) {
+                const float2 *ar = As + oi * kc;
+                for (int l = 0; l < c; ++l) {
+                    const float2 x = ar[l], y = Bs[l * n + oj];
+                    re = fmaf(x.x, y.x, re);
+                    re = fmaf(-x.y, y.y, re);
+                    im = fmaf(x.x, y.y, im);
+                    im = fmaf(x.y, y.x, im);
+                }
+            }
+        }
+        if (t < mn) {
+            d.C[c_off(d, bi, oi, oj)] = make_float2(re, im);
+            mx = fmaxf(mx, fmaxf(fabsf(re), fabsf(im)));
+        }
+    }
+    if (d.amax_c) block_amax(mx, d.amax_c);
+}
+
 // -------------------------------------------------------------- MFMA GEMM
 // Complex FP32 GEMM in the 4M form on v_mfma_f32_32x32x2_f32: each wave owns
 // a 32x32 output tile with separate real and imaginary accumulators,
@@ -905,6 +1041,9 @@ bool gemm_variant_ok(const GemmDesc &d, int v) {
     switch (v) {
         case kVarValu: return true;
         case kVarSkinny: return d.n >= 64 && m_pow2_16;
+        case kVarSkinnyT: return d.m >= 64 && (d.n == 1 || d.n == 2 || d.n == 4 || d.n == 8 || d.n == 16);
+        case kVarDotTile: return d.m * d.n <= 256 && d.k >= 64;
+        case kVarRows: return d.m >= 64 && (d.n == 1 || d.n == 2 || d.n == 4 || d.n == 8 || d.n == 16);
         case kVarDot: return d.k >= 256 && d.nb * d.m * d.n <= 65536;
         case kVarMfma11: case kVarMfma12: case kVarMfma21: case kVarMfma22: {
             const int wm = (v == kVarMfma21 || v == kVarMfma22) ? 2 : 1, wn = (v == kVarMfma12 || v == kVarMfma22) ? 2 : 1;
@@ -931,8 +1070,10 @@ int gemm_default_variant(const GemmDesc &d) {
         const int v = wm == 2 ? (wn == 2 ? kVarMfma22 : kVarMfma21) : (wn == 2 ? kVarMfma12 : kVarMfma11);
         if (gemm_variant_ok(d, v)) return v;
     }
+    if (d.k >= 1024 && gemm_variant_ok(d, kVarDotTile)) return kVarDotTile;
     if (d.k >= 4096 && d.nb * d.m * d.n <= 4096) return kVarDot;
     if (d.n >= 256 && gemm_variant_ok(d, kVarSkinny)) return kVarSkinny;
+    if (d.m >= 256 && gemm_variant_ok(d, kVarRows)) return kVarRows;
     return kVarValu;
 }
 
@@ -980,6 +1121,40 @@ void launch_split(const GemmDesc &d, hipStream_t st) {
     else
         hipLaunchKernelGGL((gemm_split_kernel<__bf16, WM, WN>), dim3(grid), dim3(64 * WM * WN), 0, st, d);
 }
+void launch_skinny(const GemmDesc &d, hipStream_t st) {
+    // Fewer workgroups when each folds a maximum into one slot.
+    const int64_t blocks = d.nb * ((d.n + 511) / 512), cap = d.amax_c ? 2048 : 8192;
+    const unsigned g = (unsigned)(blocks < cap ? blocks : cap);
+    switch (d.m) {
+        case 1: hipLaunchKernelGGL(gemm_skinny_kernel<1>, dim3(g), dim3(256), 0, st, d); break;
+        case 2: hipLaunchKernelGGL(gemm_skinny_kernel<2>, dim3(g), dim3(256), 0, st, d); break;
+        case 4: hipLaunchKernelGGL(gemm_skinny_kernel<4>, dim3(g), dim3(256), 0, st, d); break;
+        case 8: hipLaunchKernelGGL(gemm_skinny_kernel<8>, dim3(g), dim3(256), 0, st, d); break;
+        default: hipLaunchKernelGGL(gemm_skinny_kernel<16>, dim3(g), dim3(256), 0, st, d); break;
+    }
+}
+
+// The same product as C^T = B^T A^T: operands swapped and transposed through
+// their strides, C's index roles swapped (strides, or the scatter positions
+// of its row and column bits).
+GemmDesc transposed(const GemmDesc &d) {
+    GemmDesc t = d;
+    t.A = d.B; t.B = d.A;
+    t.m = d.n; t.n = d.m;
+    t.sAb = d.sBb; t.sAm = d.sBn; t.sAk = d.sBk;
+    t.sBb = d.sAb; t.sBk = d.sAk; t.sBn = d.sAm;
+    t.sCb = d.sCb; t.sCm = d.sCn; t.sCn = d.sCm;
+    t.sAp = d.sBp; t.sBp = d.sAp;
+    t.amax_a = d.amax_b; t.amax_b = d.amax_a;
+    if (d.cscatter) {
+        t.cbm = d.cbn;
+        t.cbn = d.cbm;
+        for (int q = 0; q < d.cbm; ++q) t.cpos[q] = d.cpos[d.cbn + q];
+        for (int q = 0; q < d.cbn; ++q) t.cpos[d.cbm + q] = d.cpos[q];
+    }
+    return t;
+}
+
 void launch_dot(const GemmDesc &d, hipStream_t st) {
     const int64_t outs = d.nb * d.m * d.n;
     const unsigned g = (unsigned)(outs < 65536 ? outs : 65536);
@@ -992,6 +1167,11 @@ const char *launch_big(const GemmDesc &d, int v, hipStream_t st) {
     if (v == kVarDot) {
         launch_dot(d, st);
         return "gemm_dot";
+    }
+    if (v == kVarDotTile) {
+        const unsigned g = (unsigned)(d.nb < 65536 ? d.nb : 65536);
+        hipLaunchKernelGGL(gemm_dot_tile_kernel, dim3(g), dim3(256), 0, st, d);
+        return "gemm_dot_tile";
     }
     const int64_t t128 = d.nb * (d.m / 128) * (d.n / 128);
     const unsigned g = (unsigned)(t128 < 1048576 ? t128 : 1048576);
@@ -1058,22 +1238,26 @@ const char *launch_gemm_variant(const GemmDesc &d, int v, hipStream_t st) {
         case kVarMfmaBig: case kVarSplitBig:
             if (d.kparts > 1) return launch_gemm_kparts(d, v, st);
             return launch_big(d, v, st);
-        case kVarDot:
+        case kVarDot: case kVarDotTile:
             if (d.kparts > 1) return launch_gemm_kparts(d, v, st);
-            launch_dot(d, st);
-            return "gemm_dot";
-        case kVarSkinny: {
-            // Fewer workgroups when each folds a maximum into one slot.
-            const int64_t blocks = d.nb * ((d.n + 511) / 512), cap = d.amax_c ? 2048 : 8192;
-            const unsigned g = (unsigned)(blocks < cap ? blocks : cap);
-            switch (d.m) {
-                case 1: hipLaunchKernelGGL(gemm_skinny_kernel<1>, dim3(g), dim3(256), 0, st, d); break;
-                case 2: hipLaunchKernelGGL(gemm_skinny_kernel<2>, dim3(g), dim3(256), 0, st, d); break;
-                case 4: hipLaunchKernelGGL(gemm_skinny_kernel<4>, dim3(g), dim3(256), 0, st, d); break;
-                case 8: hipLaunchKernelGGL(gemm_skinny_kernel<8>, dim3(g), dim3(256), 0, st, d); break;
-                default: hipLaunchKernelGGL(gemm_skinny_kernel<16>, dim3(g), dim3(256), 0, st, d); break;
-            }
+            return launch_big(d, v, st);
+        case kVarSkinny:
+            launch_skinny(d, st);
             return "gemm_skinny";
+        case kVarSkinnyT:
+            launch_skinny(transposed(d), st);
+            return "gemm_skinny_t";
+        case kVarRows: {
+            const int64_t blocks = d.nb * ((d.m + 255) / 256), cap = d.amax_c ? 2048 : 65536;
+            const unsigned g = (unsigned)(blocks < cap ? blocks : cap);
+            switch (d.n) {
+                case 1: hipLaunchKernelGGL(gemm_rows_kernel<1>, dim3(g), dim3(256), 0, st, d); break;
+                case 2: hipLaunchKernelGGL(gemm_rows_kernel<2>, dim3(g), dim3(256), 0, st, d); break;
+                case 4: hipLaunchKernelGGL(gemm_rows_kernel<4>, dim3(g), dim3(256), 0, st, d); break;
+                case 8: hipLaunchKernelGGL(gemm_rows_kernel<8>, dim3(g), dim3(256), 0, st, d); break;
+                default: hipLaunchKernelGGL(gemm_rows_kernel<16>, dim3(g), dim3(256), 0, st, d); break;
+            }
+            return "gemm_rows";
         }
         default: {
             const int64_t total = d.nb * d.m * d.n;

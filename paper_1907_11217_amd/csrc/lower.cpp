@@ -304,17 +304,24 @@ static bool lower(const qc_plan *plan, int b, int m, Program &prog, std::string 
     if (layout[root] != want) root = emit_transpose(root, want);
     prog.root = root;
 
-    // Every transpose is folded into the producer of its source (each tensor
+    // Transposes are folded into the producer of their source (each tensor
     // has exactly one consumer): a leaf is instantiated directly in the
     // transposed layout, and a GEMM step writes its output in that layout
     // (its natural [batch][m][n] order stays recorded as c_nat, and the
     // kernels scatter the output bits accordingly).  Consumers then read the
-    // producer's tensor as is.
+    // producer's tensor as is.  Exception: a large GEMM output whose new
+    // layout keeps fewer than kMinWriteRun of its natural lowest bits lowest
+    // would be written in scattered 8- or 16-byte pieces; it is written in
+    // natural order and moved by the LDS-staged transpose kernel instead
+    // (coalesced on both sides, two more passes over the tensor, cheaper
+    // than writes a sixteenth or an eighth as efficient).
     {
         std::vector<int> producer(layout.size(), -1), rename(layout.size());
         for (size_t i = 0; i < prog.gemms.size(); ++i) producer[prog.gemms[i].c] = (int)i;
         for (size_t t = 0; t < rename.size(); ++t) rename[t] = (int)t;
-        for (const TransposeOp &t : prog.transposes) {
+        std::vector<char> keep(prog.transposes.size(), 0);
+        for (size_t ti = 0; ti < prog.transposes.size(); ++ti) {
+            const TransposeOp &t = prog.transposes[ti];
             if (t.src < L) {
                 layout[t.src] = layout[t.dst];
                 rename[t.dst] = t.src;
@@ -327,6 +334,13 @@ static bool lower(const qc_plan *plan, int b, int m, Program &prog, std::string 
                     err = "internal: a folded transpose is not a permutation of its step's output";
                     return false;
                 }
+                const std::vector<int> &nat = layout[t.src], &lay = layout[t.dst];
+                size_t q = 0;
+                while (q < nat.size() && lay[lay.size() - 1 - q] == nat[nat.size() - 1 - q]) ++q;
+                if ((int)nat.size() >= kTransposeMinLog2 && (int)q < kMinWriteRun) {
+                    keep[ti] = 1;
+                    continue;
+                }
                 g.c = t.dst;
                 rename[t.src] = t.dst;
             }
@@ -337,11 +351,19 @@ static bool lower(const qc_plan *plan, int b, int m, Program &prog, std::string 
         }
         prog.root = rename[prog.root];
         std::vector<Op> ops;
-        for (const Op &op : prog.ops)
-            if (op.kind == Op::GEMM) ops.push_back(op);
-        prog.ops = std::move(ops);
-        prog.transposes.clear();
+        std::vector<TransposeOp> kept;
         prog.transpose_bytes = 0;
+        for (const Op &op : prog.ops) {
+            if (op.kind == Op::GEMM) {
+                ops.push_back(op);
+            } else if (keep[op.index]) {
+                kept.push_back(prog.transposes[op.index]);
+                ops.push_back(Op{Op::TRANSPOSE, (int)kept.size() - 1});
+                prog.transpose_bytes += 16.0 * std::ldexp(1.0, (int)layout[kept.back().src].size());
+            }
+        }
+        prog.ops = std::move(ops);
+        prog.transposes = std::move(kept);
         prog.root_pre = prog.root;
     }
 

@@ -86,6 +86,8 @@ TreeCost tree_cost(const OrderProblem &p, const std::vector<Merge> &tree,
 // Index ids inside a program: segment ids, then kBsBase + i for bitstring bit i.
 constexpr int kBsBase = 1 << 20;
 constexpr int kMicroMaxLog2 = 12;  // micro steps: output and operands of at most 2^12 entries
+constexpr int kTransposeMinLog2 = 20;  // GEMM outputs from 2^20 entries may keep an explicit transpose
+constexpr int kMinWriteRun = 2;        // ... when fewer natural lowest bits than this stay lowest
 
 struct ProgTensor {
     std::vector<int> layout;   // major -> minor
@@ -106,9 +108,12 @@ struct TransposeOp {
 // tiles number fewer than 1024 (four per compute unit) are split into up to
 // 64 power-of-two parts, each of at least 256 k; other shapes with m and n
 // multiples of 32 (the 32- and 64-wide MFMA forms) likewise while their
-// 32x32 tiles number fewer than 4096; shapes of at most 4096 outputs with
-// k >= 8192 (the dot form's) into the smallest power of two giving 1024
-// (output, part) workgroups, each part keeping at least 4096 k.
+// 32x32 tiles number fewer than 4096; shapes with small output tiles (m n
+// <= 256, the dot-tile form's) and k >= 1024 into the smallest power of two
+// giving 1024 (batch, part) workgroups, each part keeping at least 256 k;
+// other shapes of at most 4096 outputs with k >= 8192 (the dot form's) into
+// the smallest power of two giving 1024 (output, part) workgroups, each part
+// keeping at least 4096 k.
 inline int64_t gemm_kparts(int64_t nb, int64_t m, int64_t n, int64_t k) {
     int64_t p = 1;
     if (m % 128 == 0 && n % 128 == 0) {
@@ -117,6 +122,8 @@ inline int64_t gemm_kparts(int64_t nb, int64_t m, int64_t n, int64_t k) {
     } else if (m % 32 == 0 && n % 32 == 0) {
         const int64_t tiles = nb * (m / 32) * (n / 32);
         while (tiles * p < 4096 && p < 64 && k % (2 * p) == 0 && k / (2 * p) >= 256) p *= 2;
+    } else if (m * n <= 256 && k >= 1024) {
+        while (nb * p < 1024 && p < 1024 && k % (2 * p) == 0 && k / (2 * p) >= 256) p *= 2;
     } else if (nb * m * n <= 4096 && k >= 8192) {
         const int64_t outs = nb * m * n;
         while (outs * p < 1024 && k % (2 * p) == 0 && k / (2 * p) >= 4096) p *= 2;
@@ -222,6 +229,7 @@ struct qc_plan {
         std::string kind;
         void *e0, *e1;
         double flops;             // algorithmic flops of the launch (GEMM and micro steps; 0 otherwise)
+        double bytes;             // algorithmic bytes: complex64 operands read and written once
     };
     std::vector<ProfEntry> prof_pending;
     std::vector<void *> prof_pool;

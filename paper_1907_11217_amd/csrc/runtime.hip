@@ -657,8 +657,12 @@ GemmDesc make_gemm(const Program &prog, const GemmOp &g, float2 *tensors, int pr
     return d;
 }
 
-// Algorithmic real flops of a GEMM step (8 per complex multiply-add).
+// Algorithmic real flops of a GEMM step (8 per complex multiply-add) and its
+// algorithmic bytes (complex64 operands read and the result written once).
 double gemm_flops(const GemmOp &g) { return 8.0 * double(g.nb) * double(g.m) * double(g.n) * double(g.k); }
+double gemm_bytes(const GemmOp &g) {
+    return 8.0 * double(g.nb) * (double(g.m) * double(g.k) + double(g.k) * double(g.n) + double(g.m) * double(g.n));
+}
 
 // Event pair around each launch while the plan's kernel timing is on.
 struct Prof {
@@ -680,11 +684,11 @@ struct Prof {
         e0 = event();
         hipEventRecord((hipEvent_t)e0, st);
     }
-    void end(const char *kind, double flops = 0) {
+    void end(const char *kind, double flops = 0, double bytes = 0) {
         if (!plan->profiling) return;
         void *e1 = event();
         hipEventRecord((hipEvent_t)e1, st);
-        plan->prof_pending.push_back({kind, e0, e1, flops});
+        plan->prof_pending.push_back({kind, e0, e1, flops, bytes});
     }
 };
 
@@ -805,11 +809,14 @@ bool launch_all(qc_plan *plan, const Exec &x, uint64_t s_begin, uint64_t s_end, 
                     const int32_t *ls = lt + prog.n_micro_groups + 1;
                     launch_micro((const MicroStep *)dc.p[kCMicro], lt, ls, ls + prog.n_micro_levels + 1,
                                  prog.n_micro_groups, tensors, amax, st);
-                    double mf = 0;
+                    double mf = 0, mb = 0;
                     if (plan->profiling)
                         for (size_t gi = 0; gi < prog.gemms.size(); ++gi)
-                            if (prog.gemm_micro[gi]) mf += gemm_flops(prog.gemms[gi]);
-                    prof.end("micro", mf);
+                            if (prog.gemm_micro[gi]) {
+                                mf += gemm_flops(prog.gemms[gi]);
+                                mb += gemm_bytes(prog.gemms[gi]);
+                            }
+                    prof.end("micro", mf, mb);
                 }
                 for (size_t oi = 0; oi < prog.ops.size(); ++oi) {
                     const Op &op = prog.ops[oi];
@@ -823,7 +830,7 @@ bool launch_all(qc_plan *plan, const Exec &x, uint64_t s_begin, uint64_t s_end, 
                         const GemmDesc gd = make_gemm(prog, g, tensors, x.prec, amax, slot, kscratch);
                         const int v = g.variant[x.prec];
                         prof.end(v >= 0 && gemm_variant_ok(gd, v) ? launch_gemm_variant(gd, v, st) : launch_gemm(gd, st),
-                                 gemm_flops(g));
+                                 gemm_flops(g), gemm_bytes(g));
                     }
                 }
                 launch_copy(partial + ((cb - sc) << x.m), tensors + prog.tensors[prog.root].offset,
@@ -1649,6 +1656,7 @@ extern "C" qc_status qc_profile_read(qc_plan *plan, qc_kernel_stat_t *out, int32
         s->launches += 1;
         s->total_ms += ms;
         s->flops += pe.flops;
+        s->bytes += pe.bytes;
         plan->prof_pool.push_back(pe.e0);
         plan->prof_pool.push_back(pe.e1);
     }
@@ -1706,7 +1714,7 @@ extern "C" qc_status qc_kernel_gemm_kparts(const void *A, const void *B, void *C
     if (kparts == 0) kparts = qc::gemm_kparts(nb, m, n, k);
     // Every MFMA form and the dot form split over k; each part must itself
     // be a product the form applies to.
-    const bool splits = v != qc::kVarValu && v != qc::kVarSkinny;
+    const bool splits = v != qc::kVarValu && v != qc::kVarSkinny && v != qc::kVarSkinnyT && v != qc::kVarRows;
     qc::GemmDesc part = d;
     if (kparts > 1) part.k = k / kparts;
     if (kparts > 1 && (!splits || k % kparts != 0 || !scratch || !qc::gemm_variant_ok(part, v))) {

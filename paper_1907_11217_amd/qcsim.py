@@ -84,7 +84,7 @@ class qc_plan_info_t(ctypes.Structure):
 
 class qc_kernel_stat_t(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_char * 16), ("launches", ctypes.c_int64), ("total_ms", ctypes.c_double),
-                ("flops", ctypes.c_double)]
+                ("flops", ctypes.c_double), ("bytes", ctypes.c_double)]
 
 
 _lib = None
@@ -372,12 +372,13 @@ def qc_profile_enable(plan: Plan, on: bool = True) -> None:
 
 
 def qc_profile_read(plan: Plan) -> dict:
-    """{kind: (launches, total_ms, algorithmic flops)} since the last read
-    (waits for the events)."""
+    """{kind: (launches, total_ms, algorithmic flops, algorithmic bytes)} since
+    the last read (waits for the events)."""
     stats = (qc_kernel_stat_t * 32)()
     n = ctypes.c_int32()
     _check(plan._lib.qc_profile_read(plan.handle, stats, 32, ctypes.byref(n)), plan._lib)
-    return {stats[i].kind.decode(): (int(stats[i].launches), float(stats[i].total_ms), float(stats[i].flops))
+    return {stats[i].kind.decode(): (int(stats[i].launches), float(stats[i].total_ms), float(stats[i].flops),
+                                     float(stats[i].bytes))
             for i in range(n.value)}
 
 
@@ -460,7 +461,8 @@ def qc_contract_slices_noalloc(plan: Plan, s_begin: int, s_end: int, bits_dev, p
 
 
 GEMM_FORMS = {"valu": 0, "skinny": 1, "dot": 2, "mfma11": 3, "mfma12": 4, "mfma21": 5, "mfma22": 6,
-              "split_big": 7, "split11": 8, "split12": 9, "split21": 10, "split22": 11, "mfma_big": 12}
+              "split_big": 7, "split11": 8, "split12": 9, "split21": 10, "split22": 11, "mfma_big": 12,
+              "skinny_t": 13, "dot_tile": 14, "rows": 15}
 
 
 def qc_kernel_gemm(A, B, C, nb: int, m: int, n: int, k: int, a_km: bool = False, b_nk: bool = False,

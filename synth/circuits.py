@@ -161,7 +161,7 @@ CONFIGS = {
     "c3": dict(name="grid7x7_d24", lattice=(7, 7), depth=24, seed=301,
                n_bitstrings=1, log2_slices=16, log2_cap=30, n_sampled=32, trials=8, plan_seed=1),
     "c4": dict(name="diamond70_d32", lattice="diamond70", depth=32, seed=401,
-               n_bitstrings=1, log2_slices=20, log2_cap=30, trials=256, plan_seed=1, chunk=8),
+               n_bitstrings=1, log2_slices=20, log2_cap=30, trials=256, plan_seed=1, chunk=64),
 }
 
 

@@ -240,3 +240,46 @@ def test_gemm_kparts_limit():
     d = torch.zeros(k, dtype=torch.complex64, device="cuda")
     with pytest.raises((qcsim.QcError, ValueError)):  # at most 1024 parts
         qcsim.qc_kernel_gemm(d, d, d, nb, m, n, k, form=qcsim.GEMM_FORMS["dot"], kparts=2048)
+
+
+# Every complex FP32 form on integer operands small enough that every
+# product and partial sum is an integer below 2^24: the result must equal the
+# FP64 product bit for bit, so a dropped, repeated or misplaced term fails at
+# any k (the random-operand tests above can only bound rounding).
+# (form, nb, m, n, k, kparts); kparts 0 takes the library's rule.
+EXACT_FORMS = [
+    ("valu", 2, 3, 5, 7, 1), ("valu", 1, 1, 1, 1024, 1),
+    ("skinny", 2, 4, 512, 33, 1), ("skinny", 1, 16, 300, 7, 1),
+    ("skinny_t", 2, 512, 4, 33, 1), ("skinny_t", 3, 300, 16, 7, 1), ("skinny_t", 1, 256, 8, 64, 1),
+    ("rows", 2, 512, 4, 33, 1), ("rows", 3, 300, 16, 7, 1), ("rows", 1, 256, 8, 4100, 1), ("rows", 2, 64, 1, 2, 1),
+    ("dot", 2, 2, 2, 5000, 1), ("dot", 1, 1, 1, 1 << 20, 0),
+    ("dot_tile", 4, 16, 16, 4096, 1), ("dot_tile", 2, 32, 8, 2048, 1), ("dot_tile", 1, 1, 256, 300, 1),
+    ("dot_tile", 3, 5, 7, 1000, 1), ("dot_tile", 2, 32, 8, 1 << 16, 0), ("dot_tile", 32, 16, 16, 16384, 0),
+    ("mfma11", 2, 64, 64, 48, 1), ("mfma12", 1, 32, 64, 16, 1), ("mfma21", 3, 64, 32, 8, 1),
+    ("mfma22", 1, 128, 64, 4, 1), ("mfma11", 1, 32, 32, 4096, 8),
+    ("mfma_big", 1, 128, 256, 64, 1), ("mfma_big", 2, 128, 128, 2, 1), ("mfma_big", 1, 128, 128, 1024, 4),
+]
+
+
+@pytest.mark.parametrize("case", EXACT_FORMS, ids=lambda c: "-".join(str(v) for v in c))
+@pytest.mark.parametrize("a_km,b_nk", [(0, 0), (1, 1), (1, 0), (0, 1)])
+def test_fp32_forms_exact_on_integer_operands(case, a_km, b_nk):
+    form, nb, m, n, k, kp = case
+    r = max(1, int(np.sqrt((2.0 ** 23 - 1) / k)))
+    rng = np.random.default_rng(nb + 7 * m + 13 * n + 17 * k + 3 * a_km + 5 * b_nk)
+    ia = rng.integers(-r, r + 1, size=(2, nb, m, k))
+    ib = rng.integers(-r, r + 1, size=(2, nb, k, n))
+    A = (ia[0] + 1j * ia[1]).astype(np.complex64)
+    B = (ib[0] + 1j * ib[1]).astype(np.complex64)
+    a_store = A.transpose(0, 2, 1) if a_km else A
+    b_store = B.transpose(0, 2, 1) if b_nk else B
+    dA = torch.from_numpy(np.ascontiguousarray(a_store).reshape(-1)).cuda()
+    dB = torch.from_numpy(np.ascontiguousarray(b_store).reshape(-1)).cuda()
+    dC = torch.full((nb * m * n,), float("nan"), dtype=torch.complex64, device="cuda")
+    say(f"gemm {form} exact: nb={nb} m={m} n={n} k={k} kparts={kp} a_km={a_km} b_nk={b_nk}")
+    qcsim.qc_kernel_gemm(dA, dB, dC, nb, m, n, k, a_km, b_nk, form=qcsim.GEMM_FORMS[form], kparts=kp)
+    torch.cuda.synchronize()
+    got = dC.cpu().numpy().reshape(nb, m, n).astype(np.complex128)
+    ref = np.matmul(A.astype(np.complex128), B.astype(np.complex128))
+    assert np.abs(ref.real).max() < 2 ** 24 and np.abs(ref.imag).max() < 2 ** 24
+    assert np.array_equal(got, ref), np.abs(got - ref).max()

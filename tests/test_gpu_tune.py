@@ -20,7 +20,8 @@ from paper_1907_11217_amd import qcsim  # noqa: E402
 
 U = {"c64": 2.0 ** -24, "split_fp16": 2.0 ** -22, "split_bf16": 2.0 ** -16}
 FORM_SHAPES = [(1, 1, 256, 512), (2, 8, 64, 33), (1, 16, 128, 16), (3, 32, 32, 16), (1, 64, 128, 64),
-               (2, 128, 128, 48), (1, 256, 384, 32), (4, 2, 2, 4096)]
+               (2, 128, 128, 48), (1, 256, 384, 32), (4, 2, 2, 4096), (2, 512, 8, 64), (4, 16, 16, 2048),
+               (1, 300, 16, 5)]
 
 
 @pytest.mark.parametrize("prec", ["c64", "split_fp16", "split_bf16"])

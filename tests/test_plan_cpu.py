@@ -47,11 +47,18 @@ def test_gemm_kparts_rule():
     assert qcsim.qc_gemm_kparts(1, 128, 128, 1 << 20) == 64
     assert qcsim.qc_gemm_kparts(1, 128, 128, 384) == 1
     assert qcsim.qc_gemm_kparts(1, 128, 128, 768) == 2
-    # Few outputs with a long k (the dot form): 1024 (output, part) pairs,
-    # each part at least 4096 of k.
-    assert qcsim.qc_gemm_kparts(1, 1, 1, 1 << 21) == 512
-    assert qcsim.qc_gemm_kparts(4, 8, 8, 16384) == 4
-    assert qcsim.qc_gemm_kparts(1, 1, 1, 4096) == 1
+    # Small output tiles (m n <= 256) with k >= 1024 (the dot-tile form): the
+    # smallest power of two p <= 1024 with nb p >= 1024, each part at least
+    # 256 of k.
+    assert qcsim.qc_gemm_kparts(1, 1, 1, 1 << 21) == 1024
+    assert qcsim.qc_gemm_kparts(4, 8, 8, 16384) == 64
+    assert qcsim.qc_gemm_kparts(1, 1, 1, 4096) == 16
+    assert qcsim.qc_gemm_kparts(256, 16, 16, 16384) == 4
+    assert qcsim.qc_gemm_kparts(2, 16, 16, 512) == 1
+    # Other few-output shapes with a long k (the dot form): 1024 (output,
+    # part) pairs, each part at least 4096 of k.
+    assert qcsim.qc_gemm_kparts(1, 16, 32, 1 << 16) == 2
+    assert qcsim.qc_gemm_kparts(2, 16, 64, 1 << 14) == 1
     # Shapes of the 32- and 64-wide MFMA forms: fewer than 4096 tiles of
     # 32x32, parts of at least 256 k, at most 64 parts; 32-aligned shapes
     # take this rule even with few outputs.
@@ -79,16 +86,46 @@ def test_workspace_holds_split_over_k_scratch():
     assert ws >= (desc["tensor_elems"] + max(need)) * 8
 
 
-def test_programs_have_no_transposes():
-    # Every operand is produced in the layout its consumer reads: leaves are
-    # instantiated in it, GEMM steps scatter their output into it.
+def test_transposes_only_for_large_scattered_outputs():
+    # Operands are produced in the layout their consumer reads: leaves are
+    # instantiated in it, GEMM steps scatter their output into it -- except a
+    # GEMM output of at least 2^20 entries whose consumer layout keeps fewer
+    # than two of its natural lowest bits lowest, which is written in natural
+    # order and moved by an explicit transpose.
     lat, circ, bs, _ = synth.config("c3")
     plan = qcsim.qc_plan_build(lat.n, circ, bs[0], log2_slices=16, log2_max_entries=30, greedy_trials=8, seed=1)
-    for b, m in [(16, 0), (0, 0), (4, 2)]:
+    seen = 0
+    for b, m in [(16, 0), (0, 0), (4, 2), (12, 0)]:
         desc = qcsim.qc_plan_describe(plan, b, m)
-        assert all(op["op"] == "gemm" for op in desc["ops"])
-        assert desc["transpose_bytes"] == 0
-        assert any(op["c_nat"] != op["c"] for op in desc["ops"])
+        T = desc["tensors"]
+        produced_by = {op["c"]: op for op in desc["ops"] if op["op"] == "gemm"}
+        for op in desc["ops"]:
+            if op["op"] != "transpose":
+                continue
+            seen += 1
+            nat, lay = T[op["src"]]["layout"], T[op["dst"]]["layout"]
+            assert op["src"] in produced_by and sorted(nat) == sorted(lay) and len(nat) >= 20
+            q = 0
+            while q < len(nat) and lay[-1 - q] == nat[-1 - q]:
+                q += 1
+            assert q < 2
+        assert any(op["op"] == "gemm" and op["c_nat"] != op["c"] for op in desc["ops"])
+    assert seen > 0
+
+
+def test_program_with_transposes_matches_statevector():
+    # 5x5 at depth 1+28+1 with four bitstrings in flight: a program holding
+    # explicit transposes, interpreted on the CPU, against the state vector.
+    lat = synth.grid(5, 5)
+    circ = synth.random_circuit(lat, 28, 201)
+    xs = synth.random_bitstrings(lat.n, 4, 206)
+    plan = qcsim.qc_plan_build(lat.n, circ, None, log2_slices=0, greedy_trials=8, seed=1)
+    desc = qcsim.qc_plan_describe(plan, 0, 2)
+    assert any(op["op"] == "transpose" for op in desc["ops"])
+    got = run_program(desc, xs)[0]
+    psi = oracle.statevector(lat.n, circ)
+    ref = np.array([psi[oracle.index_of(x)] for x in xs])
+    assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
 
 
 def test_gate_matrices_match_oracle_table():
