@@ -220,15 +220,17 @@ qc_status qc_plan_export_tree(const qc_plan *plan, int32_t *n_leaves, int32_t *n
 enum { QC_EXEC_AUTO = 0, QC_EXEC_FUSED = 1, QC_EXEC_STEPWISE = 2 };
 qc_status qc_plan_set_exec(qc_plan *plan, int32_t mode);
 
-/* Graph replay of the stepwise form (on by default).  The first
- * qc_contract_slices call with a given configuration (precision, workspace,
- * bitstring and output buffers, slice range, batch size) captures its launch
- * sequence as a HIP graph on a private stream, and every call with the same
- * configuration replays it on the caller's stream; graphs hold no memset
- * nodes.  Up to 8 graphs are kept per lowered program; evicting one waits for
- * the device to drain.  Calls with kernel timing on, and the fused form (two
- * launches per super-chunk), launch directly.  on = 0 launches every kernel
- * directly. */
+/* Graph replay of the stepwise form (on by default).  The launches of one
+ * chunk that do not depend on its position (the micro-step launch and every
+ * GEMM or transpose step) are captured once per configuration (precision,
+ * slices and bitstrings in flight, workspace) as a HIP graph on a private
+ * stream, with no memset nodes; every chunk of every call with that
+ * configuration replays it on the caller's stream, between the chunk's leaf
+ * launch and its slice-value copy, whatever the slice range -- so a call over
+ * any number of chunks holds one graph.  Up to 8 graphs are kept per lowered
+ * program; evicting one waits for the device to drain.  Calls with kernel
+ * timing on, and the fused form, launch directly.  on = 0 launches every
+ * kernel directly. */
 qc_status qc_plan_set_graphs(qc_plan *plan, int32_t on);
 
 /* In-flight slice bits b of the fused form: each work item contracts 2^b

@@ -491,6 +491,7 @@ std::string describe_program(const qc_plan *plan, const Program &prog) {
     std::ostringstream o;
     o.precision(17);
     o << "{\"b\":" << prog.b << ",\"m\":" << prog.m << ",\"bs_base\":" << kBsBase;
+    o << ",\"n_graphs\":" << prog.graphs.size();
     o << ",\"n_qubits\":" << net.n_qubits;
     o << ",\"segments\":[";
     for (int e = 0; e < net.n_index(); ++e)

@@ -60,6 +60,7 @@ struct Exec {
     int prec = kPrecC64;
     const DevConsts *dc = nullptr;  // device constants (nullptr: the program's own)
     int pairs = 0, waves = 0;       // fused work-item shape (0: the plan's, timed on first use)
+    void *steps_graph = nullptr;    // hipGraphExec_t of the chunk's step sequence (stepwise form), or null
 };
 
 // Workspace: bitstrings (when handed over from the host), the super-chunk's
@@ -692,6 +693,54 @@ struct Prof {
     }
 };
 
+// The scale slot of each tensor of a stepwise program (a transpose's output
+// shares its input's).
+std::vector<int> scale_slots(const Program &prog) {
+    std::vector<int> slot(prog.tensors.size());
+    for (size_t t = 0; t < slot.size(); ++t) slot[t] = (int)t;
+    for (const Op &op : prog.ops)
+        if (op.kind == Op::TRANSPOSE) slot[prog.transposes[op.index].dst] = slot[prog.transposes[op.index].src];
+    return slot;
+}
+
+// The launches of one chunk of the stepwise form that do not depend on the
+// chunk's position: the micro-step launch, then every GEMM and transpose op on
+// the chunk's tensors.  This sequence is what a graph captures.
+void launch_steps(qc_plan *plan, const Exec &x, const DevConsts &dc, float2 *tensors, float2 *kscratch,
+                  uint32_t *amax, const std::vector<int> &slot, hipStream_t st, Prof &prof) {
+    const Program &prog = *x.prog;
+    if (prog.n_micro_levels > 0) {
+        const int32_t *lt = (const int32_t *)dc.p[kCMicroLevels];
+        prof.begin();
+        const int32_t *ls = lt + prog.n_micro_groups + 1;
+        launch_micro((const MicroStep *)dc.p[kCMicro], lt, ls, ls + prog.n_micro_levels + 1, prog.n_micro_groups,
+                     tensors, amax, st);
+        double mf = 0, mb = 0;
+        if (plan->profiling)
+            for (size_t gi = 0; gi < prog.gemms.size(); ++gi)
+                if (prog.gemm_micro[gi]) {
+                    mf += gemm_flops(prog.gemms[gi]);
+                    mb += gemm_bytes(prog.gemms[gi]);
+                }
+        prof.end("micro", mf, mb);
+    }
+    for (size_t oi = 0; oi < prog.ops.size(); ++oi) {
+        const Op &op = prog.ops[oi];
+        if (prog.op_micro[oi]) continue;
+        prof.begin();
+        if (op.kind == Op::TRANSPOSE) {
+            launch_transpose(make_transpose(prog, prog.transposes[op.index], tensors), st);
+            prof.end("transpose");
+        } else {
+            const GemmOp &g = prog.gemms[op.index];
+            const GemmDesc gd = make_gemm(prog, g, tensors, x.prec, amax, slot, kscratch);
+            const int v = g.variant[x.prec];
+            prof.end(v >= 0 && gemm_variant_ok(gd, v) ? launch_gemm_variant(gd, v, st) : launch_gemm(gd, st),
+                     gemm_flops(g), gemm_bytes(g));
+        }
+    }
+}
+
 // A fused launch whose work items are exactly 64-slice blocks, one item per
 // workgroup, with one block of [lo, hi) per bitstring, adds its block sums to
 // the output itself (same butterfly and order as the reduction launch).
@@ -757,15 +806,7 @@ bool launch_all(qc_plan *plan, const Exec &x, uint64_t s_begin, uint64_t s_end, 
     float2 *kscratch = (float2 *)((char *)ws + w.ksplit_off);
     // Scale bookkeeping only where a scale is derived from it (FP16).
     uint32_t *amax = (!x.fused && x.prec == kPrecFP16) ? (uint32_t *)((char *)ws + w.amax_off) : nullptr;
-    // Stepwise form: the scale slot of each tensor (a transpose's output
-    // shares its input's).
-    std::vector<int> slot;
-    if (!x.fused) {
-        slot.resize(prog.tensors.size());
-        for (size_t t = 0; t < slot.size(); ++t) slot[t] = (int)t;
-        for (const Op &op : prog.ops)
-            if (op.kind == Op::TRANSPOSE) slot[prog.transposes[op.index].dst] = slot[prog.transposes[op.index].src];
-    }
+    const std::vector<int> slot = x.fused ? std::vector<int>() : scale_slots(prog);
     const uint64_t P = uint64_t(1) << x.lp;
     for (uint64_t sc = s_begin & ~(P - 1); sc < s_end; sc += P) {
         const uint64_t lo = std::max(s_begin, sc), hi = std::min(s_end, sc + P);
@@ -803,35 +844,12 @@ bool launch_all(qc_plan *plan, const Exec &x, uint64_t s_begin, uint64_t s_end, 
                               prog.n_leaf_blocks, (const double2 *)dc.p[kCBase], tensors, bits, nq, n_bs, cb, amax,
                               st);
                 prof.end("leaves");
-                if (prog.n_micro_levels > 0) {
-                    const int32_t *lt = (const int32_t *)dc.p[kCMicroLevels];
-                    prof.begin();
-                    const int32_t *ls = lt + prog.n_micro_groups + 1;
-                    launch_micro((const MicroStep *)dc.p[kCMicro], lt, ls, ls + prog.n_micro_levels + 1,
-                                 prog.n_micro_groups, tensors, amax, st);
-                    double mf = 0, mb = 0;
-                    if (plan->profiling)
-                        for (size_t gi = 0; gi < prog.gemms.size(); ++gi)
-                            if (prog.gemm_micro[gi]) {
-                                mf += gemm_flops(prog.gemms[gi]);
-                                mb += gemm_bytes(prog.gemms[gi]);
-                            }
-                    prof.end("micro", mf, mb);
-                }
-                for (size_t oi = 0; oi < prog.ops.size(); ++oi) {
-                    const Op &op = prog.ops[oi];
-                    if (prog.op_micro[oi]) continue;
-                    prof.begin();
-                    if (op.kind == Op::TRANSPOSE) {
-                        launch_transpose(make_transpose(prog, prog.transposes[op.index], tensors), st);
-                        prof.end("transpose");
-                    } else {
-                        const GemmOp &g = prog.gemms[op.index];
-                        const GemmDesc gd = make_gemm(prog, g, tensors, x.prec, amax, slot, kscratch);
-                        const int v = g.variant[x.prec];
-                        prof.end(v >= 0 && gemm_variant_ok(gd, v) ? launch_gemm_variant(gd, v, st) : launch_gemm(gd, st),
-                                 gemm_flops(g), gemm_bytes(g));
-                    }
+                if (!x.steps_graph) {
+                    launch_steps(plan, x, dc, tensors, kscratch, amax, slot, st, prof);
+                } else if (hipGraphLaunch((hipGraphExec_t)x.steps_graph, st) != hipSuccess) {
+                    err = std::string("hipGraphLaunch: ") + hipGetErrorString(hipGetLastError());
+                    plan->profiling = saved;
+                    return false;
                 }
                 launch_copy(partial + ((cb - sc) << x.m), tensors + prog.tensors[prog.root].offset,
                             int64_t(1) << (prog.b + x.m), st);
@@ -850,53 +868,62 @@ bool launch_all(qc_plan *plan, const Exec &x, uint64_t s_begin, uint64_t s_end, 
     return true;
 }
 
-// Replays the cached graph of this exact call configuration, or captures the
-// launch sequence on the plan's capture stream, instantiates it and replays
-// it (at most 8 graphs per program; the oldest is dropped after the device
-// has drained).  Returns false with err empty if capture is not possible, so
-// the caller launches directly.
-bool launch_graph(qc_plan *plan, const Exec &x, uint64_t s_begin, uint64_t s_end, const uint8_t *bits, int n_bs,
-                  void *ws, hipStream_t st, double *out_dev, double *per_slice_dev, std::string &err) {
+// The graph of a stepwise program's per-chunk step sequence for one
+// configuration (precision, slices and bitstrings in flight, workspace):
+// captured once on the plan's capture stream and kept (at most 8 per program;
+// dropping one waits for the device to drain).  Every chunk of every call with
+// that configuration replays it, whatever the slice range, so host memory and
+// capture work stay bounded however many chunks a call holds.  Returns null
+// with err empty if capture is not possible (the caller then launches
+// directly).
+void *steps_graph(qc_plan *plan, const Exec &x, void *ws, std::string &err) {
     Program &prog = *x.prog;
-    const std::vector<uint64_t> key = {uint64_t(x.fused), uint64_t(x.prec), uint64_t(x.lp), uint64_t(x.m),
-                                       uint64_t(uintptr_t(ws)), uint64_t(uintptr_t(bits)), uint64_t(n_bs),
-                                       uint64_t(uintptr_t(out_dev)), uint64_t(uintptr_t(per_slice_dev)), s_begin,
-                                       s_end, uint64_t(prog.fused_pairs), uint64_t(prog.fused_waves)};
+    const std::vector<uint64_t> key = {uint64_t(x.prec), uint64_t(x.lp), uint64_t(x.m), uint64_t(prog.b),
+                                       uint64_t(uintptr_t(ws))};
     for (auto &g : prog.graphs)
-        if (g.first == key) {
-            QC_HIP(hipGraphLaunch((hipGraphExec_t)g.second, st));
-            return true;
-        }
+        if (g.first == key) return g.second;
     if (!plan->capture_stream) {
         hipStream_t cs = nullptr;
-        QC_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+        if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) {
+            err = "hipStreamCreateWithFlags failed";
+            return nullptr;
+        }
         plan->capture_stream = (void *)cs;
     }
     hipStream_t cs = (hipStream_t)plan->capture_stream;
     if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
         (void)hipGetLastError();
-        return false;
+        return nullptr;
     }
-    std::string lerr;
-    const bool ok = launch_all(plan, x, s_begin, s_end, bits, n_bs, ws, cs, out_dev, per_slice_dev, false, lerr);
+    const WsLayout w = ws_layout(x, plan->net.n_qubits);
+    float2 *tensors = (float2 *)((char *)ws + w.tensor_off);
+    float2 *kscratch = (float2 *)((char *)ws + w.ksplit_off);
+    uint32_t *amax = x.prec == kPrecFP16 ? (uint32_t *)((char *)ws + w.amax_off) : nullptr;
+    Prof none{plan, cs};
+    const bool saved = plan->profiling;
+    plan->profiling = false;
+    launch_steps(plan, x, prog.dc, tensors, kscratch, amax, scale_slots(prog), cs, none);
+    plan->profiling = saved;
     hipGraph_t graph = nullptr;
     const hipError_t ec = hipStreamEndCapture(cs, &graph);
     hipGraphExec_t exec = nullptr;
-    const bool inst = ok && ec == hipSuccess && graph &&
-                      hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess;
+    const bool inst = ec == hipSuccess && graph && hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess;
     if (graph) (void)hipGraphDestroy(graph);
     if (!inst) {
         (void)hipGetLastError();
-        return false;
+        return nullptr;
     }
     if (prog.graphs.size() >= 8) {
-        QC_HIP(hipDeviceSynchronize());
+        if (hipDeviceSynchronize() != hipSuccess) {
+            err = "hipDeviceSynchronize failed";
+            (void)hipGraphExecDestroy(exec);
+            return nullptr;
+        }
         (void)hipGraphExecDestroy((hipGraphExec_t)prog.graphs.front().second);
         prog.graphs.erase(prog.graphs.begin());
     }
     prog.graphs.push_back({key, (void *)exec});
-    QC_HIP(hipGraphLaunch(exec, st));
-    return true;
+    return (void *)exec;
 }
 
 // Slices in flight per fused work item: a program with b in-flight slice bits
@@ -973,14 +1000,13 @@ bool enqueue(qc_plan *plan, const Exec &x, uint64_t s_begin, uint64_t s_end, con
             if (!y.prog || !ensure_device(plan, *y.prog, true, err)) return false;
         }
     }
-    const Exec &x2 = y;
     // Graphs pay off for the stepwise form's long launch sequences; the fused
     // form is two launches per super-chunk, which replay no faster.
-    if (plan->use_graphs && !plan->profiling && !x2.fused) {
-        if (launch_graph(plan, x2, s_begin, s_end, bits, n_bs, ws, st, out_dev, per_slice_dev, err)) return true;
-        if (!err.empty()) return false;
+    if (plan->use_graphs && !plan->profiling && !y.fused) {
+        y.steps_graph = steps_graph(plan, y, ws, err);
+        if (!y.steps_graph && !err.empty()) return false;
     }
-    return launch_all(plan, x2, s_begin, s_end, bits, n_bs, ws, st, out_dev, per_slice_dev, plan->profiling, err);
+    return launch_all(plan, y, s_begin, s_end, bits, n_bs, ws, st, out_dev, per_slice_dev, plan->profiling, err);
 }
 
 // ------------------------------------------------------------------ tuning

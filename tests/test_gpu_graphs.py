@@ -62,3 +62,54 @@ def test_graph_large_program_7x7():
     say("graphs c3 3 replays")
     for o, p in _calls(plan, bs[:1], 4096, 8192, "c64", True, 3):
         assert np.array_equal(o, direct[0]) and np.array_equal(p, direct[1])
+
+
+def test_multi_chunk_call_replays_one_graph():
+    # The 7x7 depth-24 plan with a workspace for 4096 slices: one call over
+    # all 2^16 slices runs 16 chunks, each replaying the same step graph
+    # (one graph for the program however many chunks); it equals the direct
+    # launches and 16 calls of one chunk each bit for bit (chunk boundaries
+    # are multiples of 64, where the FP64 sums compose exactly).
+    lat, circ, bs, spec = synth.config("c3")
+    plan = qcsim.qc_plan_build(lat.n, circ, bs[0], log2_slices=16, log2_max_entries=30, greedy_trials=8, seed=1)
+    ws = torch.empty(qcsim.qc_workspace_bytes(plan, 4096, 1), dtype=torch.uint8, device="cuda")
+    outs = []
+    for graphs in (True, False):
+        qcsim.qc_plan_set_graphs(plan, graphs)
+        out = torch.zeros(1, 2, dtype=torch.float64, device="cuda")
+        say(f"c3 one call over 16 chunks of 4096, graphs={graphs}")
+        qcsim.qc_contract_slices(plan, 0, 1 << 16, bs[:1], "c64", ws, out)
+        torch.cuda.synchronize()
+        outs.append(out.cpu().numpy().copy())
+    assert np.array_equal(outs[0], outs[1])
+    qcsim.qc_plan_set_graphs(plan, True)
+    out = torch.zeros(1, 2, dtype=torch.float64, device="cuda")
+    say("c3 16 calls of one chunk each")
+    for c in range(16):
+        qcsim.qc_contract_slices(plan, c * 4096, (c + 1) * 4096, bs[:1], "c64", ws, out)
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy(), outs[0])
+    assert qcsim.qc_plan_describe(plan, 12, 0)["n_graphs"] == 1
+
+
+def test_multi_chunk_70_qubit_range():
+    # 32 chunks of 64 slices of the 70-qubit plan in one call: one graph,
+    # equal to the direct launches bit for bit, and to the per-chunk calls.
+    lat, circ, bs, spec = synth.config("c4")
+    plan = qcsim.qc_plan_build(lat.n, circ, bs[0], log2_slices=spec["log2_slices"], log2_max_entries=spec["log2_cap"],
+                               greedy_trials=spec["trials"], seed=spec["plan_seed"])
+    chunk = spec["chunk"]
+    ws = torch.empty(qcsim.qc_workspace_bytes(plan, chunk, 1), dtype=torch.uint8, device="cuda")
+    s0, s1 = 5 * chunk, 37 * chunk
+    res = []
+    for graphs in (True, False):
+        qcsim.qc_plan_set_graphs(plan, graphs)
+        out = torch.zeros(1, 2, dtype=torch.float64, device="cuda")
+        ps = torch.zeros(s1 - s0, 1, 2, dtype=torch.float64, device="cuda")
+        say(f"c4 slices [{s0}, {s1}) in one call, graphs={graphs}")
+        qcsim.qc_contract_slices(plan, s0, s1, bs[:1], "c64", ws, out, ps)
+        torch.cuda.synchronize()
+        res.append((out.cpu().numpy().copy(), ps.cpu().numpy().copy()))
+    assert np.array_equal(res[0][0], res[1][0]) and np.array_equal(res[0][1], res[1][1])
+    b = (chunk - 1).bit_length()
+    assert qcsim.qc_plan_describe(plan, b, 0)["n_graphs"] == 1
