@@ -123,6 +123,11 @@ typedef struct {
 } qc_plan_info_t;
 
 /* circuit + bitstring + slice set -> contraction plan (host only).
+ * The paper's preprocessing (Section "Benchmarking and the Experimental
+ * Setup", preprocessing paragraph): the network of the amplitude is refactored
+ * into a hypergraph (refactoring paragraph: nodes hold tensors, hyper-edges are
+ * running indices) and split into subtasks of equal cost that share no data;
+ * it is done once and not counted in the running time.
  *   bitstring: optional default bitstring (n_qubits bytes) or NULL.
  *   spec: slicing request (NULL = no slicing, one greedy trial).
  * Builds the hypergraph network (diagonal gates share the wire's index),
@@ -133,10 +138,13 @@ typedef struct {
 qc_status qc_plan_build(const qc_circuit *circuit, const uint8_t *bitstring,
                         const qc_slice_spec *spec, qc_plan **out);
 
+/* The plan's sizes and costs (the quantities of the paper's prediction from
+ * subtask cost, Section "Benchmarking Results", prediction paragraph). */
 qc_status qc_plan_info(const qc_plan *plan, qc_plan_info_t *info);
 
 /* The k sliced segments as (q, ordinal) pairs in slice-bit order: out_pairs
- * must hold 2k int32. */
+ * must hold 2k int32.  (The split into subtasks of the preprocessing
+ * paragraph; which indices are fixed is this library's choice.) */
 qc_status qc_plan_sliced_segments(const qc_plan *plan, int32_t *out_pairs);
 
 /* Bit values of slice s: out[j] = (s >> j) & 1 for j < k; QC_ERR_RANGE if
@@ -308,6 +316,11 @@ qc_status qc_profile_read(qc_plan *plan, qc_kernel_stat_t *out, int32_t cap, int
 size_t qc_workspace_bytes(qc_plan *plan, int64_t chunk_slices, int32_t n_bs, qc_precision prec);
 
 /* plan + slice range -> partial amplitudes, asynchronously on `stream`
+ * The subtasks of the paper (Section "Benchmarking Results", subtask
+ * paragraph: equal cost, no shared data, any share of them per worker) are the
+ * slices; their results add up to the amplitude (Section "Benchmarking and the
+ * Experimental Setup", preprocessing paragraph), so a range's partial sum is
+ * added to out_dev and ranges compose.
  * (a hipStream_t, or NULL for the null stream) of the current device.
  *   bitstrings: host uint8 [n_bs][n_qubits], 1 <= n_bs <= 65536; copied.
  *   ws, ws_bytes: device workspace owned by the caller; the largest
@@ -367,12 +380,16 @@ qc_status qc_contract_slices_noalloc(qc_plan *plan, uint64_t s_begin, uint64_t s
                                      void *stream, double *out_dev, double *per_slice_dev);
 
 /* All slices of one amplitude, synchronously; allocates and frees its own
- * workspace on the current device.  out_host[0..1] = (re, im). */
+ * workspace on the current device.  out_host[0..1] = (re, im).  The
+ * amplitude <x|C|0^n> is the sum of all subtask results (Section
+ * "Benchmarking and the Experimental Setup", preprocessing paragraph). */
 qc_status qc_amplitude(qc_plan *plan, const uint8_t *bitstring, qc_precision prec,
                        double out_host[2]);
 
 /* Many amplitude requests, each with its own plan, bitstring and slice
- * range, in one call (asynchronous on `stream`).  Requests whose plan runs
+ * range, in one call (asynchronous on `stream`): the paper's many-amplitude
+ * batches (Section "Benchmarking Results", N_a paragraph: time per amplitude
+ * falls as more amplitudes share the machine).  Requests whose plan runs
  * fused (complex FP32, the program fits in LDS) share one launch whose
  * wavefronts take (request, slice) pairs in turn; the others run stepwise on
  * eight internal streams (default priority) that start after the caller's
