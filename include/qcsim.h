@@ -99,6 +99,9 @@ typedef struct {
     const int32_t *explicit_segments;/* n_explicit (q, ordinal) pairs, host pointer, or NULL */
     uint64_t seed;                   /* seed of the randomised greedy restarts */
     int32_t greedy_trials;           /* restarts of the order search (>= 1) */
+    int32_t quick;                   /* 0: full search (greedy restarts refined by subtree
+                                        reconfiguration); 1: greedy restarts and slicing only,
+                                        much faster, for many small plans */
 } qc_slice_spec;
 
 typedef struct qc_plan qc_plan;
@@ -118,7 +121,7 @@ typedef struct {
     int32_t n_folded_steps;     /* steps whose value is the same for every slice and bitstring,
                                    computed once in qc_plan_build (not counted in n_steps or
                                    flops_per_slice) */
-    int32_t reserved;
+    int32_t n_open;             /* output qubits left open (qc_plan_build_open); 0 otherwise */
     double flops_folded;        /* algorithmic flops of those steps (FP64 on the host, once per plan) */
 } qc_plan_info_t;
 
@@ -137,6 +140,29 @@ typedef struct {
  * with the requested k (the message states the achievable size). */
 qc_status qc_plan_build(const qc_circuit *circuit, const uint8_t *bitstring,
                         const qc_slice_spec *spec, qc_plan **out);
+
+/* Largest number of open output qubits (2^20 amplitudes per bitstring). */
+#define QC_MAX_OPEN_QUBITS 20
+
+/* qc_plan_build with the output segments of the qubits open_qubits[0 ..
+ * n_open - 1] left open: those indices are never fixed to a bitstring bit nor
+ * summed, the order search keeps them to the end, and every contraction of the
+ * plan yields, per bitstring x, the 2^n_open amplitudes <y|C|0^n> of the
+ * bitstrings y that equal x outside the open qubits -- many amplitudes from one
+ * contraction, the regime where the paper computes many amplitudes of one
+ * circuit (Section "Benchmarking Results", N_a paragraph; Porter-Thomas
+ * paragraph).  The bits x[q] of the open qubits are ignored.  Result entry o in
+ * [0, 2^n_open) sets open qubit open_qubits_sorted[i] to bit (n_open - 1 - i)
+ * of o: the open qubits in increasing order, the first one the most
+ * significant, as in the bitstring index of the state vector.
+ *   n_open: 0 .. QC_MAX_OPEN_QUBITS; open_qubits: distinct qubits (any order,
+ *   host pointer, copied), or NULL when n_open = 0.
+ * Plans with open outputs always run stepwise and are not accepted by
+ * qc_contract_batch (QC_ERR_UNSUPPORTED); every output buffer of the
+ * contraction calls has 2^n_open entries per bitstring (below).  Errors as
+ * qc_plan_build; QC_ERR_INVALID_ARG for a bad open qubit list. */
+qc_status qc_plan_build_open(const qc_circuit *circuit, const uint8_t *bitstring, const qc_slice_spec *spec,
+                             int32_t n_open, const int32_t *open_qubits, qc_plan **out);
 
 /* The plan's sizes and costs (the quantities of the paper's prediction from
  * subtask cost, Section "Benchmarking Results", prediction paragraph). */
@@ -312,7 +338,12 @@ qc_status qc_profile_read(qc_plan *plan, qc_kernel_stat_t *out, int32_t cap, int
 
 /* Device workspace (bytes) that qc_contract_slices needs to keep
  * chunk_slices slices (rounded up to a power of two) and n_bs bitstrings in
- * flight.  0 on invalid arguments. */
+ * flight.  0 on invalid arguments.
+ *
+ * Open outputs: for a plan with n_open > 0, every per-bitstring output below
+ * holds A = 2^n_open amplitudes (entry o as in qc_plan_build_open): out_dev is
+ * double [n_bs][A][2], per_slice_dev [s_end - s_begin][n_bs][A][2], out_host
+ * of qc_amplitude [A][2].  n_bs * A must not exceed 2^20. */
 size_t qc_workspace_bytes(qc_plan *plan, int64_t chunk_slices, int32_t n_bs, qc_precision prec);
 
 /* plan + slice range -> partial amplitudes, asynchronously on `stream`

@@ -1,6 +1,7 @@
 // C ABI: plan construction and inspection (host only).  The device entry
 // points (qc_workspace_bytes, qc_contract_slices, qc_amplitude) live in
 // runtime.hip.
+#include <algorithm>
 #include <chrono>
 #include <cstring>
 #include <new>
@@ -20,7 +21,24 @@ extern "C" const char *qc_last_error(void) { return qc::g_last_error.c_str(); }
 
 extern "C" qc_status qc_plan_build(const qc_circuit *circuit, const uint8_t *bitstring,
                                    const qc_slice_spec *spec, qc_plan **out) {
+    return qc_plan_build_open(circuit, bitstring, spec, 0, nullptr, out);
+}
+
+extern "C" qc_status qc_plan_build_open(const qc_circuit *circuit, const uint8_t *bitstring,
+                                        const qc_slice_spec *spec, int32_t n_open, const int32_t *open_qubits,
+                                        qc_plan **out) {
     if (!circuit || !out) { set_error("qc_plan_build: NULL argument"); return QC_ERR_INVALID_ARG; }
+    if (n_open < 0 || n_open > QC_MAX_OPEN_QUBITS || (n_open > 0 && !open_qubits)) {
+        set_error("qc_plan_build: n_open must be in [0, " + std::to_string(QC_MAX_OPEN_QUBITS) + "]");
+        return QC_ERR_INVALID_ARG;
+    }
+    std::vector<int> open(open_qubits, open_qubits + n_open);
+    std::sort(open.begin(), open.end());
+    for (size_t i = 0; i < open.size(); ++i)
+        if (open[i] < 0 || open[i] >= circuit->n_qubits || (i > 0 && open[i] == open[i - 1])) {
+            set_error("qc_plan_build: open qubits must be distinct qubits of the circuit");
+            return QC_ERR_INVALID_ARG;
+        }
     if (circuit->n_qubits < 1 || circuit->n_qubits > 4096 || circuit->n_gates < 0 ||
         (circuit->n_gates > 0 && !circuit->gates)) {
         set_error("qc_plan_build: invalid circuit");
@@ -39,7 +57,8 @@ extern "C" qc_status qc_plan_build(const qc_circuit *circuit, const uint8_t *bit
     if (!plan) { set_error("qc_plan_build: out of host memory"); return QC_ERR_NOMEM; }
     std::string err;
     try {
-        if (!qc::build_network(*circuit, plan->net, err)) {
+        plan->open_qubits = open;
+        if (!qc::build_network(*circuit, open, plan->net, err)) {
             delete plan;
             set_error("qc_plan_build: " + err);
             return QC_ERR_INVALID_ARG;
@@ -55,9 +74,10 @@ extern "C" qc_status qc_plan_build(const qc_circuit *circuit, const uint8_t *bit
         for (const auto &T : plan->net.leaves) {
             std::vector<int> s;
             for (int e : T.idx)
-                if (plan->net.out_qubit[e] < 0) s.push_back(e);
+                if (!plan->net.fixed_out(e)) s.push_back(e);
             plan->prob.leaf_idx.push_back(s);
         }
+        if (!open.empty()) plan->prob.keep = plan->net.open_out;
         if (!qc::search_plan(plan, spec, err)) {
             delete plan;
             set_error("qc_plan_build: " + err);
@@ -71,12 +91,14 @@ extern "C" qc_status qc_plan_build(const qc_circuit *circuit, const uint8_t *bit
     if (bitstring) plan->default_bitstring.assign(bitstring, bitstring + circuit->n_qubits);
     int n_sum = 0;
     for (int e = 0; e < plan->net.n_index(); ++e) {
+        if (plan->prob.kept(e)) continue;
         bool used = false;
         for (const auto &li : plan->prob.leaf_idx)
             for (int f : li) used |= f == e;
         n_sum += used;
     }
     plan->info.n_qubits = circuit->n_qubits;
+    plan->info.n_open = (int32_t)open.size();
     plan->info.n_indices = n_sum;
     plan->info.n_leaves = (int)plan->net.leaves.size();
     plan->info.n_steps = (int)plan->tree.size();

@@ -3,7 +3,8 @@
 //
 // In-flight slice bits are the first b sliced segments left open (never
 // summed); bitstring bits are extra open indices carried by every leaf that
-// touches an output segment.  Both then behave like hyper-edges: in a step
+// touches a fixed output segment; the output segments of open output qubits
+// are open indices of their own.  All of them behave like hyper-edges: in a step
 // where both operands hold them they are batch indices, otherwise free
 // indices.  Each step C = A (x) B is classified per index as batch (in both,
 // still needed later), contracted (in both, needed nowhere else), free-A or
@@ -116,6 +117,8 @@ static bool lower(const qc_plan *plan, int b, int m, Program &prog, std::string 
     if (m < 0 || m > kMaxBsBits) { err = "in-flight bitstring bits out of range"; return false; }
     std::vector<char> fixed(n_idx, 0), open(n_idx, 0);
     for (int j = 0; j < k; ++j) (j < b ? open : fixed)[plan->sliced[j]] = 1;
+    for (int e = 0; e < n_idx; ++e)
+        if (net.open_out[e]) open[e] = 1;   // open outputs: indices of the result
 
     std::vector<int> bs_bits;  // major -> minor
     for (int i = m - 1; i >= 0; --i) bs_bits.push_back(kBsBase + i);
@@ -128,7 +131,7 @@ static bool lower(const qc_plan *plan, int b, int m, Program &prog, std::string 
         bool has_out = false;
         std::vector<int> lay;
         for (int e : T.idx) {
-            if (net.out_qubit[e] >= 0) has_out = true;
+            if (net.fixed_out(e)) has_out = true;
             else if (!fixed[e]) { lay.push_back(e); ++total[e]; }
         }
         if (has_out) lay.insert(lay.begin(), bs_bits.begin(), bs_bits.end());
@@ -292,9 +295,12 @@ static bool lower(const qc_plan *plan, int b, int m, Program &prog, std::string 
     }
     int root = tensor_of.back();
     prog.root_pre = root;
-    std::vector<int> want;
+    std::vector<int> want;  // [slice bits][bitstring bits][open outputs, first qubit most significant]
     for (int j = b - 1; j >= 0; --j) want.push_back(plan->sliced[j]);
     want.insert(want.end(), bs_bits.begin(), bs_bits.end());
+    for (int q : plan->open_qubits)
+        for (int e = 0; e < n_idx; ++e)
+            if (net.open_out[e] && net.out_qubit[e] == q) want.push_back(e);
     {
         std::vector<int> a = layout[root], w = want;
         std::sort(a.begin(), a.end());
@@ -498,6 +504,8 @@ std::string describe_program(const qc_plan *plan, const Program &prog) {
         o << (e ? "," : "") << '[' << net.seg_q[e] << ',' << net.seg_ord[e] << ',' << net.out_qubit[e] << ']';
     o << "],\"sliced\":";
     json_ints(o, plan->sliced);
+    o << ",\"open_qubits\":";
+    json_ints(o, plan->open_qubits);
     o << ",\"leaves\":[";
     for (size_t t = 0; t < net.leaves.size(); ++t) {
         const Tensor &T = net.leaves[t];

@@ -8,7 +8,9 @@
 // makes the running indices hyper-edges (the paper's refactored network:
 // nodes hold tensors, hyper-edges are running indices).  The input segment of
 // every qubit carries the vector e_0 = (1, 0); the output segment is left as
-// an index, fixed to x[q] when the leaves are instantiated for a bitstring.
+// an index, fixed to x[q] when the leaves are instantiated for a bitstring --
+// or, for the qubits the caller leaves open, kept as an index of the result,
+// so that one contraction gives the amplitudes of all 2^m settings of them.
 #include <algorithm>
 #include <cmath>
 #include <set>
@@ -35,7 +37,7 @@ static void gate_2x2(int kind, cplx u[2][2]) {
     }
 }
 
-bool build_network(const qc_circuit &c, Network &net, std::string &err) {
+bool build_network(const qc_circuit &c, const std::vector<int> &open, Network &net, std::string &err) {
     const int n = c.n_qubits;
     net = Network();
     net.n_qubits = n;
@@ -45,6 +47,7 @@ bool build_network(const qc_circuit &c, Network &net, std::string &err) {
         net.seg_q.push_back(q);
         net.seg_ord.push_back(ord);
         net.out_qubit.push_back(-1);
+        net.open_out.push_back(0);
         return (int)net.seg_q.size() - 1;
     };
     for (int q = 0; q < n; ++q) {
@@ -86,6 +89,10 @@ bool build_network(const qc_circuit &c, Network &net, std::string &err) {
     }
     net.n_orig = n + c.n_gates;
     for (int q = 0; q < n; ++q) net.out_qubit[cur[q]] = q;
+    for (int q : open) {
+        if (q < 0 || q >= n) { err = "open output qubit out of range"; return false; }
+        net.open_out[cur[q]] = 1;
+    }
     return true;
 }
 
@@ -123,13 +130,13 @@ Tensor contract_host(const Tensor &A, const Tensor &B, const std::vector<int> &c
 // than the larger of the two (this absorbs vectors, collapses chains of 2x2
 // tensors and folds tensors whose indices are a subset of a neighbour's).
 // Output segments and the indices in `keep` (caller-chosen slices) are never
-// summed here.  Sizes are counted without output segments, which are fixed per
-// bitstring when leaves are instantiated; a merged tensor keeps at most
-// kMaxLeafBase indices in all.  Exact in FP64.
+// summed here.  Sizes are counted without the fixed output segments, which
+// are fixed per bitstring when leaves are instantiated (open ones count); a
+// merged tensor keeps at most kMaxLeafBase indices in all.  Exact in FP64.
 void simplify_network(Network &net, const std::vector<int> &keep) {
     auto eff = [&](const std::vector<int> &idx) {
         int r = 0;
-        for (int f : idx) r += net.out_qubit[f] < 0;
+        for (int f : idx) r += !net.fixed_out(f);
         return r;
     };
     std::vector<Tensor> &T = net.leaves;

@@ -84,8 +84,8 @@ std::vector<Merge> greedy_order_phased(const OrderProblem &p, const std::vector<
         while (i < A.size() || j < B.size()) {
             if (j == B.size() || (i < A.size() && A[i] < B[j])) { ++r; ++i; }
             else if (i == A.size() || B[j] < A[i]) { ++r; ++j; }
-            else {  // shared: stays if another live tensor holds it
-                if (holders[A[i]].size() > 2) ++r;
+            else {  // shared: stays if another live tensor holds it (or it is never summed)
+                if (holders[A[i]].size() > 2 || p.kept(A[i])) ++r;
                 ++i; ++j;
             }
         }
@@ -119,7 +119,7 @@ std::vector<Merge> greedy_order_phased(const OrderProblem &p, const std::vector<
         for (int e : u) {
             const bool both = std::binary_search(sets[a].begin(), sets[a].end(), e) &&
                               std::binary_search(sets[b].begin(), sets[b].end(), e);
-            if (!(both && holders[e].size() == 2)) c.push_back(e);
+            if (!(both && holders[e].size() == 2 && !p.kept(e))) c.push_back(e);
         }
         const int id = (int)sets.size();
         for (int e : u) {
@@ -186,6 +186,7 @@ static void node_sets(const OrderProblem &p, const std::vector<Merge> &tree,
         cnt.push_back(std::move(c));
         sets.push_back(std::move(s));
     }
+    for (int e = 0; e < p.n_index; ++e) total[e] += p.kept(e);  // open outputs are never closed
     for (size_t i = 0; i < tree.size(); ++i) {
         const auto &ca = cnt[tree[i].a], &cb = cnt[tree[i].b];
         std::vector<std::pair<int, int>> cc;
@@ -421,6 +422,7 @@ static double reconfigure(const OrderProblem &p, std::vector<Merge> &tree, const
     for (int t = 0; t < L; ++t)
         for (int e : p.leaf_idx[t])
             if (!removed[e]) ++total[e];
+    for (int e = 0; e < p.n_index; ++e) total[e] += p.kept(e);
     double best = per_pair_cost(p, tree, removed, dyn_leaf);
     Rng rng{seed};
     TreeShape t = shape_of(L, tree);
@@ -688,9 +690,10 @@ bool search_plan(qc_plan *plan, const qc_slice_spec *spec, std::string &err) {
     const double cap = spec ? spec->log2_max_entries : 0;
     const int trials = spec ? std::max(1, spec->greedy_trials) : 1;
     const uint64_t seed = spec ? spec->seed : 0;
+    const bool quick = spec && spec->quick;   // no subtree reconfiguration
     std::vector<char> sliceable(p.n_index, 0);
     for (const auto &li : p.leaf_idx)
-        for (int e : li) sliceable[e] = 1;   // summed indices only (outputs are not in leaf_idx)
+        for (int e : li) sliceable[e] = !p.kept(e);   // summed indices only (fixed outputs are not in leaf_idx)
     std::vector<int> explicit_s;
     if (spec && spec->n_explicit > 0) {
         for (int i = 0; i < spec->n_explicit; ++i) {
@@ -729,7 +732,7 @@ bool search_plan(qc_plan *plan, const qc_slice_spec *spec, std::string &err) {
     parallel_trials(trials, [&](int t) {
         Trial &r = tr[t];
         r.tree = greedy_order(p, none, seed + 0x1000 * t, t == 0 ? 0.0 : 0.1 + 0.05 * (t % 8));
-        reconfigure(p, r.tree, none, dyn0, 0, seed + 0x3000 + t, 2);
+        if (!quick) reconfigure(p, r.tree, none, dyn0, 0, seed + 0x3000 + t, 2);
         r.sl = explicit_s;
         r.ok = choose_slices(p, r.tree, kt, cap, r.sl, sliceable, r.ach);
         if (r.ok) {
@@ -792,7 +795,7 @@ bool search_plan(qc_plan *plan, const qc_slice_spec *spec, std::string &err) {
         // reconfigured for the sliced network after each, so that it can
         // gather its expensive merges on the sliced indices.  Kept if its
         // per-slice work beats the first set's once both are reconfigured.
-        {
+        if (!quick) {
             std::vector<Merge> t2 = cand.tree;
             std::vector<int> sl2 = explicit_s;
             std::vector<char> rm2(p.n_index, 0);
@@ -860,7 +863,7 @@ bool search_plan(qc_plan *plan, const qc_slice_spec *spec, std::string &err) {
         for (auto &r : ph)
             if (r.second >= 0 && r.second < dev) { dev = r.second; tree = r.first; }
         // Local optimisation of the chosen tree for this slice set.
-        dev = reconfigure(p, tree, rm, dyn_leaf, cap, seed + 0x7000 + ci, kReconfSweeps);
+        if (!quick) dev = reconfigure(p, tree, rm, dyn_leaf, cap, seed + 0x7000 + ci, kReconfSweeps);
         refined[ci].ok = true;
         refined[ci].dev = dev;
         refined[ci].tree = std::move(tree);

@@ -39,6 +39,7 @@ struct Network {
     int n_qubits = 0;
     std::vector<int> seg_q, seg_ord;    // per index: its segment (q, ordinal)
     std::vector<int> out_qubit;         // per index: q if it is q's output segment, else -1
+    std::vector<char> open_out;         // per index: an output segment left open (never fixed or summed)
     std::vector<int> n_cut;             // per qubit: non-diagonal gate count
     std::vector<Tensor> leaves;         // simplified tensors
     // Per leaf: the circuit's tensors merged into it, numbered t < n_qubits for
@@ -47,11 +48,14 @@ struct Network {
     int n_orig = 0;                     // n_qubits + number of gates
     int n_index() const { return (int)seg_q.size(); }
     int find_segment(int q, int ord) const;
+    // An output segment fixed to the bitstring's bit (not an open one).
+    bool fixed_out(int e) const { return out_qubit[e] >= 0 && !open_out[e]; }
 };
 
 // Builds the hypergraph network of <x|C|0^n> with output segments left as
-// indices (fixed per bitstring at instantiation) and input segments fixed to 0.
-bool build_network(const qc_circuit &c, Network &net, std::string &err);
+// indices (fixed per bitstring at instantiation, except those of the qubits in
+// `open`, which stay open to the end) and input segments fixed to 0.
+bool build_network(const qc_circuit &c, const std::vector<int> &open, Network &net, std::string &err);
 void simplify_network(Network &net, const std::vector<int> &keep);
 // C = sum over `contracted` of A * B, with C's indices in the order c_idx (FP64, host).
 Tensor contract_host(const Tensor &A, const Tensor &B, const std::vector<int> &c_idx,
@@ -72,7 +76,9 @@ struct TreeCost {
 // order search and slicing.
 struct OrderProblem {
     int n_index = 0;
-    std::vector<std::vector<int>> leaf_idx;   // summed (non-output) indices per leaf
+    std::vector<std::vector<int>> leaf_idx;   // summed and open-output indices per leaf (not fixed outputs)
+    std::vector<char> keep;                   // per index: never summed (open outputs); empty = none
+    bool kept(int e) const { return !keep.empty() && keep[e]; }
 };
 
 std::vector<Merge> greedy_order(const OrderProblem &p, const std::vector<char> &removed,
@@ -216,6 +222,7 @@ struct qc_plan {
     qc::OrderProblem prob;
     std::vector<qc::Merge> tree;
     std::vector<int> sliced;              // index ids in slice-bit order
+    std::vector<int> open_qubits;         // qubits whose output segment stays open (ascending)
     // The chosen tree before host folding of pair-invariant subtrees, over the
     // simplified leaves it was searched on (qc_plan_export_tree).
     std::vector<qc::Merge> tree_full;

@@ -56,6 +56,7 @@ struct Exec {
     Program *prog = nullptr;
     bool fused = false;
     int m = 0;          // log2 bitstrings (padded)
+    int mo = 0;         // open output qubits: 2^mo values per (slice, bitstring)
     int lp = 6;         // log2 super-chunk slices
     int prec = kPrecC64;
     const DevConsts *dc = nullptr;  // device constants (nullptr: the program's own)
@@ -75,8 +76,8 @@ WsLayout ws_layout(const Exec &x, int n_qubits) {
     WsLayout w;
     w.bits_off = 0;
     w.partial_off = align256(size_t(n_qubits) << x.m);
-    w.bsum_off = w.partial_off + align256((size_t(1) << (x.lp + x.m)) * sizeof(float2));
-    w.amax_off = w.bsum_off + align256((size_t(1) << (x.lp - 6 + x.m)) * sizeof(double2));
+    w.bsum_off = w.partial_off + align256((size_t(1) << (x.lp + x.m + x.mo)) * sizeof(float2));
+    w.amax_off = w.bsum_off + align256((size_t(1) << (x.lp - 6 + x.m + x.mo)) * sizeof(double2));
     w.tensor_off = w.amax_off + (x.fused ? 0 : align256(x.prog->tensors.size() * sizeof(uint32_t)));
     w.ksplit_off = w.tensor_off + (x.fused ? 0 : align256(size_t(x.prog->tensor_elems) * sizeof(float2)));
     w.total = w.ksplit_off + (x.fused ? 0 : align256(size_t(x.prog->ksplit_elems) * sizeof(float2)));
@@ -96,6 +97,7 @@ int pair_elems_of(const Program &prog) { return int(pair_elems64(prog)); }  // o
 
 bool fused_fits_uncached(const qc_plan *plan, const Program &p) {
     if (p.m != 0 || p.b > kFusedMaxSliceBits || plan->net.n_qubits > 256) return false;
+    if (!plan->open_qubits.empty()) return false;  // a work item yields one value per slice
     if (pair_elems64(p) * int64_t(sizeof(float2)) > kFusedLdsBytes) return false;
     if ((int)p.tensors[p.root].layout.size() != p.b) return false;
     std::vector<char> sliced(plan->net.n_index(), 0);  // fixed per work item
@@ -126,6 +128,7 @@ bool choose_exec(qc_plan *plan, int m, int want_lp, int prec, size_t ws_bytes, E
     const int k = (int)plan->sliced.size();
     const int nq = plan->net.n_qubits;
     x.m = m;
+    x.mo = (int)plan->open_qubits.size();
     x.prec = prec;
     Program *pf = get_program(plan, 0, 0, err);
     if (!pf) return false;
@@ -204,7 +207,7 @@ void leaf_table(const qc_plan *plan, const Program &prog, bool lds, std::vector<
         }
         for (int j = 0; j < rb; ++j) {
             const int e = T.idx[j];
-            if (net.out_qubit[e] >= 0) {
+            if (net.fixed_out(e)) {
                 d.oq_pos[d.n_oq] = (int8_t)(rb - 1 - j);
                 d.oq_q[d.n_oq] = (int16_t)net.out_qubit[e];
                 ++d.n_oq;
@@ -851,14 +854,16 @@ bool launch_all(qc_plan *plan, const Exec &x, uint64_t s_begin, uint64_t s_end, 
                     plan->profiling = saved;
                     return false;
                 }
-                launch_copy(partial + ((cb - sc) << x.m), tensors + prog.tensors[prog.root].offset,
-                            int64_t(1) << (prog.b + x.m), st);
+                launch_copy(partial + ((cb - sc) << (x.m + x.mo)), tensors + prog.tensors[prog.root].offset,
+                            int64_t(1) << (prog.b + x.m + x.mo), st);
             }
         }
         if (!summed) {
             prof.begin();
-            launch_reduce64(partial, x.m, n_bs, sc, int64_t(P / 64), lo, hi, s_begin, out_dev, per_slice_dev,
-                            (double2 *)((char *)ws + w.bsum_off), st);
+            // Open outputs: the root holds [bitstring][open bits], so the sums
+            // run over n_bs << mo values per slice in the same layout.
+            launch_reduce64(partial, x.m + x.mo, n_bs << x.mo, sc, int64_t(P / 64), lo, hi, s_begin, out_dev,
+                            per_slice_dev, (double2 *)((char *)ws + w.bsum_off), st);
             prof.end("reduce64");
         }
     }
@@ -1101,7 +1106,10 @@ static qc_status contract_common(const char *fn, qc_plan *plan, uint64_t s_begin
                                  void *ws, size_t ws_bytes, void *stream, double *out_dev, double *per_slice_dev) {
     if (!plan || !bitstrings || !ws || !out_dev) { set_error(std::string(fn) + ": NULL argument"); return QC_ERR_INVALID_ARG; }
     if (!valid_prec(prec)) { set_error(std::string(fn) + ": invalid precision"); return QC_ERR_INVALID_ARG; }
-    if (n_bs < 1 || n_bs > (1 << qc::kMaxBsBits)) { set_error(std::string(fn) + ": n_bs out of range"); return QC_ERR_RANGE; }
+    if (n_bs < 1 || n_bs > (1 << qc::kMaxBsBits) || (int64_t(n_bs) << plan->open_qubits.size()) > (int64_t(1) << 20)) {
+        set_error(std::string(fn) + ": n_bs out of range");
+        return QC_ERR_RANGE;
+    }
     const int k = (int)plan->sliced.size();
     const uint64_t n_slices = k >= 64 ? ~uint64_t(0) : (uint64_t(1) << k);
     if (s_begin > s_end || s_end > n_slices) { set_error(std::string(fn) + ": slice range out of bounds"); return QC_ERR_RANGE; }
@@ -1175,7 +1183,10 @@ extern "C" qc_status qc_contract_slices_noalloc(qc_plan *plan, uint64_t s_begin,
     const std::string fn = "qc_contract_slices_noalloc";
     if (!plan || !bitstrings_dev || !out_dev) { set_error(fn + ": NULL argument"); return QC_ERR_INVALID_ARG; }
     if (!valid_prec(prec)) { set_error(fn + ": invalid precision"); return QC_ERR_INVALID_ARG; }
-    if (n_bs < 1 || n_bs > (1 << qc::kMaxBsBits)) { set_error(fn + ": n_bs out of range"); return QC_ERR_RANGE; }
+    if (n_bs < 1 || n_bs > (1 << qc::kMaxBsBits) || (int64_t(n_bs) << plan->open_qubits.size()) > (int64_t(1) << 20)) {
+        set_error(fn + ": n_bs out of range");
+        return QC_ERR_RANGE;
+    }
     const int k = (int)plan->sliced.size();
     const uint64_t n_slices = k >= 64 ? ~uint64_t(0) : (uint64_t(1) << k);
     if (s_begin > s_end || s_end > n_slices) { set_error(fn + ": slice range out of bounds"); return QC_ERR_RANGE; }
@@ -1247,26 +1258,28 @@ extern "C" qc_status qc_amplitude(qc_plan *plan, const uint8_t *bitstring, qc_pr
         if (need <= cap) break;
     }
     if (b < 0) need = qc_workspace_bytes(plan, 1, 1, prec);
+    // 2^n_open amplitudes for a plan with open outputs.
+    const size_t n_out = size_t(2) << plan->open_qubits.size();
     void *ws = nullptr, *out = nullptr;
     if (hipMalloc(&ws, need) != hipSuccess) { set_error("qc_amplitude: workspace allocation failed"); return QC_ERR_NOMEM; }
-    if (hipMalloc(&out, 2 * sizeof(double)) != hipSuccess) { hipFree(ws); set_error("qc_amplitude: allocation failed"); return QC_ERR_NOMEM; }
+    if (hipMalloc(&out, n_out * sizeof(double)) != hipSuccess) { hipFree(ws); set_error("qc_amplitude: allocation failed"); return QC_ERR_NOMEM; }
     qc_status st = QC_OK;
-    double res[2] = {0, 0};
-    if (hipMemset(out, 0, 2 * sizeof(double)) != hipSuccess) st = QC_ERR_DEVICE;
+    std::vector<double> res(n_out, 0.0);
+    if (hipMemset(out, 0, n_out * sizeof(double)) != hipSuccess) st = QC_ERR_DEVICE;
     if (st == QC_OK) {
         const uint64_t n_slices = uint64_t(1) << k;
         st = qc_contract_slices(plan, 0, n_slices, bits, 1, prec, ws, need, nullptr, (double *)out, nullptr);
     }
     if (st == QC_OK) {
         if (hipDeviceSynchronize() != hipSuccess ||
-            hipMemcpy(res, out, sizeof(res), hipMemcpyDeviceToHost) != hipSuccess) {
+            hipMemcpy(res.data(), out, n_out * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess) {
             set_error(std::string("qc_amplitude: ") + hipGetErrorString(hipGetLastError()));
             st = QC_ERR_DEVICE;
         }
     }
     hipFree(ws);
     hipFree(out);
-    if (st == QC_OK) { out_host[0] = res[0]; out_host[1] = res[1]; }
+    if (st == QC_OK) std::copy(res.begin(), res.end(), out_host);
     return st;
 }
 
@@ -1346,6 +1359,10 @@ static qc_status check_requests(const char *fn, const qc_request *reqs, int32_t 
     for (int32_t r = 0; r < n; ++r) {
         const qc_request &q = reqs[r];
         if (!q.plan || !q.bitstring) { set_error(f + ": request with NULL plan or bitstring"); return QC_ERR_INVALID_ARG; }
+        if (!q.plan->open_qubits.empty()) {
+            set_error(f + ": plans with open output qubits are not accepted in a batch");
+            return QC_ERR_UNSUPPORTED;
+        }
         const int k = (int)q.plan->sliced.size();
         const uint64_t n_slices = k >= 64 ? ~uint64_t(0) : (uint64_t(1) << k);
         if (q.s_begin > q.s_end || q.s_end > n_slices) {

@@ -31,7 +31,7 @@ EXPORTED = (
     "qc_plan_set_exec", "qc_profile_enable", "qc_profile_read", "qc_contract_slices_dev", "qc_plan_set_graphs",
     "qc_tune", "qc_kernel_gemm_form", "qc_batch_workspace_bytes", "qc_contract_batch", "qc_wall_clock_khz",
     "qc_plan_export_steps", "qc_kernel_gemm_kparts", "qc_gemm_kparts", "qc_plan_set_fused_slice_bits",
-    "qc_plan_set_fused_shape", "qc_plan_export_tree", "qc_contract_slices_noalloc",
+    "qc_plan_set_fused_shape", "qc_plan_export_tree", "qc_contract_slices_noalloc", "qc_plan_build_open",
 )
 EXEC_MODES = {"auto": 0, "fused": 1, "stepwise": 2}
 
@@ -67,7 +67,7 @@ class qc_request(ctypes.Structure):
 class qc_slice_spec(ctypes.Structure):
     _fields_ = [("log2_slices", ctypes.c_int32), ("log2_max_entries", ctypes.c_double),
                 ("n_explicit", ctypes.c_int32), ("explicit_segments", ctypes.POINTER(ctypes.c_int32)),
-                ("seed", ctypes.c_uint64), ("greedy_trials", ctypes.c_int32)]
+                ("seed", ctypes.c_uint64), ("greedy_trials", ctypes.c_int32), ("quick", ctypes.c_int32)]
 
 
 class qc_plan_info_t(ctypes.Structure):
@@ -76,7 +76,7 @@ class qc_plan_info_t(ctypes.Structure):
                 ("log2_max_entries", ctypes.c_double), ("flops_per_slice", ctypes.c_double),
                 ("bytes_per_slice", ctypes.c_double), ("flops_unsliced", ctypes.c_double),
                 ("peak_live_bytes", ctypes.c_double), ("plan_seconds", ctypes.c_double),
-                ("n_folded_steps", ctypes.c_int32), ("reserved", ctypes.c_int32), ("flops_folded", ctypes.c_double)]
+                ("n_folded_steps", ctypes.c_int32), ("n_open", ctypes.c_int32), ("flops_folded", ctypes.c_double)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -101,6 +101,9 @@ def load(path: str | None = None):
     lib = ctypes.CDLL(p)
     vp, sz = ctypes.c_void_p, ctypes.c_size_t
     lib.qc_plan_build.argtypes = [ctypes.POINTER(qc_circuit), vp, ctypes.POINTER(qc_slice_spec), ctypes.POINTER(vp)]
+    lib.qc_plan_build_open.argtypes = [ctypes.POINTER(qc_circuit), vp, ctypes.POINTER(qc_slice_spec), ctypes.c_int32,
+                                       vp, ctypes.POINTER(vp)]
+    lib.qc_plan_build_open.restype = ctypes.c_int
     lib.qc_plan_info.argtypes = [vp, ctypes.POINTER(qc_plan_info_t)]
     lib.qc_plan_sliced_segments.argtypes = [vp, vp]
     lib.qc_plan_slice_assignment.argtypes = [vp, ctypes.c_uint64, vp]
@@ -189,10 +192,15 @@ def _prec(p) -> int:
 class Plan:
     """Owns a qc_plan*; freed by qc_plan_destroy when garbage collected."""
 
-    def __init__(self, handle, lib, n_qubits):
+    def __init__(self, handle, lib, n_qubits, n_open=0):
         self._h = handle
         self._lib = lib
         self.n_qubits = n_qubits
+        self.n_open = n_open            # open output qubits: 2^n_open amplitudes per bitstring
+
+    @property
+    def n_amp(self):
+        return 1 << self.n_open
 
     @property
     def handle(self):
@@ -206,7 +214,10 @@ class Plan:
 
 def qc_plan_build(n_qubits: int, circuit, bitstring=None, log2_slices: int = 0,
                   log2_max_entries: float = 0.0, explicit_segments=None, seed: int = 0,
-                  greedy_trials: int = 1, lib=None) -> Plan:
+                  greedy_trials: int = 1, open_qubits=None, quick: bool = False, lib=None) -> Plan:
+    """Calls qc_plan_build, or qc_plan_build_open when ``open_qubits`` (a
+    list of qubits whose outputs stay open) is given and not empty; ``quick``
+    skips the subtree reconfiguration of the order search."""
     lib = lib or load()
     circ = np.ascontiguousarray(np.asarray(circuit, dtype=np.int32).reshape(-1, 4))
     gates = (qc_gate * max(1, len(circ)))()
@@ -220,12 +231,17 @@ def qc_plan_build(n_qubits: int, circuit, bitstring=None, log2_slices: int = 0,
         ex = (ctypes.c_int32 * (2 * n_ex))(*ex_arr.reshape(-1).tolist())
     spec = qc_slice_spec(int(log2_slices), float(log2_max_entries), n_ex,
                          ctypes.cast(ex, ctypes.POINTER(ctypes.c_int32)) if ex is not None else None,
-                         int(seed), int(greedy_trials))
+                         int(seed), int(greedy_trials), int(bool(quick)))
     bsp = None
     if bitstring is not None:
         bs = np.ascontiguousarray(np.asarray(bitstring, dtype=np.uint8).reshape(-1))
         bsp = bs.ctypes.data
     h = ctypes.c_void_p()
+    if open_qubits is not None and len(open_qubits):
+        oq = np.ascontiguousarray(np.asarray(open_qubits, dtype=np.int32).reshape(-1))
+        _check(lib.qc_plan_build_open(ctypes.byref(c), bsp, ctypes.byref(spec), len(oq), oq.ctypes.data,
+                                      ctypes.byref(h)), lib)
+        return Plan(h, lib, int(n_qubits), len(oq))
     _check(lib.qc_plan_build(ctypes.byref(c), bsp, ctypes.byref(spec), ctypes.byref(h)), lib)
     return Plan(h, lib, int(n_qubits))
 
@@ -397,6 +413,17 @@ def qc_workspace_bytes(plan: Plan, chunk_slices: int, n_bs: int, prec="c64") -> 
     return n
 
 
+def _check_outputs(plan: Plan, n_bs: int, n_range: int, out_dev, per_slice_dev):
+    import torch
+    a = plan.n_amp
+    if out_dev.dtype != torch.float64 or out_dev.numel() < 2 * n_bs * a or not out_dev.is_contiguous():
+        raise ValueError("out_dev must be a contiguous float64 device tensor of n_bs x 2^n_open x 2")
+    if per_slice_dev is not None and (per_slice_dev.dtype != torch.float64 or not per_slice_dev.is_contiguous() or
+                                      per_slice_dev.numel() < 2 * n_bs * a * n_range):
+        raise ValueError("per_slice_dev must be contiguous float64 with (s_end - s_begin) x n_bs x 2^n_open x 2 "
+                         "entries")
+
+
 def qc_contract_slices(plan: Plan, s_begin: int, s_end: int, bitstrings, prec, ws, out_dev,
                        per_slice_dev=None, stream=None):
     """Enqueues the slice range on ``stream`` (default: torch's current
@@ -406,11 +433,7 @@ def qc_contract_slices(plan: Plan, s_begin: int, s_end: int, bitstrings, prec, w
     bs = np.ascontiguousarray(np.atleast_2d(np.asarray(bitstrings, dtype=np.uint8)))
     if bs.shape[1] != plan.n_qubits:
         raise ValueError("bitstrings must be [n_bs, n_qubits]")
-    if out_dev.dtype != torch.float64 or out_dev.numel() < 2 * bs.shape[0] or not out_dev.is_contiguous():
-        raise ValueError("out_dev must be a contiguous float64 device tensor of n_bs x 2")
-    if per_slice_dev is not None and (per_slice_dev.dtype != torch.float64 or
-                                      per_slice_dev.numel() < 2 * bs.shape[0] * (s_end - s_begin)):
-        raise ValueError("per_slice_dev must be float64 with (s_end - s_begin) x n_bs x 2 entries")
+    _check_outputs(plan, bs.shape[0], s_end - s_begin, out_dev, per_slice_dev)
     st = stream if stream is not None else torch.cuda.current_stream()
     _check(plan._lib.qc_contract_slices(
         plan.handle, ctypes.c_uint64(int(s_begin)), ctypes.c_uint64(int(s_end)), bs.ctypes.data, bs.shape[0],
@@ -427,11 +450,7 @@ def qc_contract_slices_dev(plan: Plan, s_begin: int, s_end: int, bits_dev, prec,
             or not bits_dev.is_contiguous() or not bits_dev.is_cuda:
         raise ValueError("bits_dev must be a contiguous uint8 device tensor [n_bs, n_qubits]")
     n_bs = bits_dev.shape[0]
-    if out_dev.dtype != torch.float64 or out_dev.numel() < 2 * n_bs or not out_dev.is_contiguous():
-        raise ValueError("out_dev must be a contiguous float64 device tensor of n_bs x 2")
-    if per_slice_dev is not None and (per_slice_dev.dtype != torch.float64 or
-                                      per_slice_dev.numel() < 2 * n_bs * (s_end - s_begin)):
-        raise ValueError("per_slice_dev must be float64 with (s_end - s_begin) x n_bs x 2 entries")
+    _check_outputs(plan, n_bs, s_end - s_begin, out_dev, per_slice_dev)
     st = stream if stream is not None else torch.cuda.current_stream()
     _check(plan._lib.qc_contract_slices_dev(
         plan.handle, ctypes.c_uint64(int(s_begin)), ctypes.c_uint64(int(s_end)), bits_dev.data_ptr(), n_bs,
@@ -448,11 +467,7 @@ def qc_contract_slices_noalloc(plan: Plan, s_begin: int, s_end: int, bits_dev, p
             or not bits_dev.is_contiguous() or not bits_dev.is_cuda:
         raise ValueError("bits_dev must be a contiguous uint8 device tensor [n_bs, n_qubits]")
     n_bs = bits_dev.shape[0]
-    if out_dev.dtype != torch.float64 or out_dev.numel() < 2 * n_bs or not out_dev.is_contiguous():
-        raise ValueError("out_dev must be a contiguous float64 device tensor of n_bs x 2")
-    if per_slice_dev is not None and (per_slice_dev.dtype != torch.float64 or
-                                      per_slice_dev.numel() < 2 * n_bs * (s_end - s_begin)):
-        raise ValueError("per_slice_dev must be float64 with (s_end - s_begin) x n_bs x 2 entries")
+    _check_outputs(plan, n_bs, s_end - s_begin, out_dev, per_slice_dev)
     st = stream if stream is not None else torch.cuda.current_stream()
     _check(plan._lib.qc_contract_slices_noalloc(
         plan.handle, ctypes.c_uint64(int(s_begin)), ctypes.c_uint64(int(s_end)), bits_dev.data_ptr(), n_bs,
@@ -518,8 +533,12 @@ def qc_kernel_transpose(inp, out, rank: int, perm, stream=None):
     _check(lib.qc_kernel_transpose(inp.data_ptr(), out.data_ptr(), int(rank), p.ctypes.data, st.cuda_stream), lib)
 
 
-def qc_amplitude(plan: Plan, bitstring, prec="c64") -> complex:
+def qc_amplitude(plan: Plan, bitstring, prec="c64"):
+    """The amplitude (complex), or for a plan with open outputs the 2^n_open
+    amplitudes (complex128 array, entry o as in qc_plan_build_open)."""
     bs = np.ascontiguousarray(np.asarray(bitstring, dtype=np.uint8).reshape(-1))
-    out = np.zeros(2, dtype=np.float64)
+    out = np.zeros(2 * plan.n_amp, dtype=np.float64)
     _check(plan._lib.qc_amplitude(plan.handle, bs.ctypes.data, _prec(prec), out.ctypes.data), plan._lib)
-    return complex(out[0], out[1])
+    if plan.n_open == 0:
+        return complex(out[0], out[1])
+    return out[0::2] + 1j * out[1::2]

@@ -12,7 +12,7 @@ import pytest
 import oracle
 import synth
 from paper_1907_11217_amd import qcsim
-from tests.plan_interp import run_program, sliced_amplitudes
+from tests.plan_interp import check_liveness, run_program, sliced_amplitudes
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
@@ -327,3 +327,165 @@ def test_fused_shape_setter_validates_and_is_described():
         with pytest.raises(qcsim.QcError):
             qcsim.qc_plan_set_fused_shape(plan, *bad)
     assert qcsim.qc_plan_describe(plan, 0, 0)["fused_shape_set"] == [1, 16]
+
+
+# ------------------------------------------------ open output qubits
+def _sv_block(psi, n, x, open_qubits):
+    """State-vector amplitudes of the 2^m bitstrings equal to x outside the
+    open qubits; entry o sets the i-th open qubit (ascending) to bit m-1-i."""
+    oq = sorted(open_qubits)
+    m = len(oq)
+    out = np.zeros(1 << m, dtype=np.complex128)
+    for o in range(1 << m):
+        y = np.array(x, dtype=np.uint8).copy()
+        for i, q in enumerate(oq):
+            y[q] = (o >> (m - 1 - i)) & 1
+        out[o] = psi[oracle.index_of(y)]
+    return out
+
+
+@pytest.mark.parametrize("b,m", [(0, 0), (2, 1), (4, 2)])
+def test_open_outputs_c1_match_statevector(b, m):
+    # 4x4 depth 1+10+1 with three open output qubits (given unsorted) and 16
+    # slices: every one of the 8 amplitudes per bitstring against the state
+    # vector, the program run in one NaN-poisoned buffer in device order.
+    lat, circ, _bs, _ = synth.config("c1")
+    oq = [12, 3, 7]
+    plan = qcsim.qc_plan_build(lat.n, circ, None, log2_slices=4, greedy_trials=2, seed=3, open_qubits=oq)
+    info = qcsim.qc_plan_info(plan)
+    assert info["n_open"] == 3 and info["log2_slices"] == 4 and plan.n_amp == 8
+    desc = qcsim.qc_plan_describe(plan, b, m)
+    assert desc["open_qubits"] == sorted(oq)
+    xs = synth.random_bitstrings(lat.n, max(1, (1 << m) - 1), 41)
+    total, per_slice = sliced_amplitudes(desc, xs, 16, flat=True)
+    psi = oracle.statevector(lat.n, circ)
+    for i, x in enumerate(xs):
+        assert np.abs(total[i] - _sv_block(psi, lat.n, x, oq)).max() < 1e-14
+    # The bits of the open qubits in the bitstring are ignored.
+    x2 = xs[:1].copy()
+    x2[0, oq] ^= 1
+    t2, _ = sliced_amplitudes(desc, x2, 16)
+    assert np.abs(t2[0] - total[0]).max() < 1e-15
+
+
+def test_all_outputs_open_give_the_state_vector():
+    # Every output open: one contraction gives all 2^9 amplitudes of a 3x3
+    # depth-8 circuit, which must be the state vector (and have norm 1).
+    lat = synth.grid(3, 3)
+    circ = synth.random_circuit(lat, 8, 17)
+    plan = qcsim.qc_plan_build(lat.n, circ, None, log2_slices=2, greedy_trials=2, seed=1,
+                               open_qubits=list(range(lat.n)))
+    desc = qcsim.qc_plan_describe(plan, 1, 0)
+    total, _ = sliced_amplitudes(desc, np.zeros((1, lat.n), np.uint8), 4, flat=True)
+    psi = oracle.statevector(lat.n, circ)
+    assert np.abs(total[0] - psi).max() < 1e-14
+    assert abs(np.sum(np.abs(total[0]) ** 2) - 1.0) < 1e-12
+
+
+def test_open_outputs_c2_program():
+    # 5x5 depth 1+16+1, six open qubits, 2^6 slices: 64 amplitudes per
+    # bitstring from one sliced contraction, against the state vector.
+    lat, circ, bs, _ = synth.config("c2")
+    oq = [0, 6, 12, 18, 20, 24]
+    plan = qcsim.qc_plan_build(lat.n, circ, None, log2_slices=6, greedy_trials=4, seed=1, open_qubits=oq)
+    desc = qcsim.qc_plan_describe(plan, 6, 1)
+    total, _ = sliced_amplitudes(desc, bs[:2], 64, flat=True)
+    psi = oracle.statevector(lat.n, circ)
+    for i in range(2):
+        ref = _sv_block(psi, lat.n, bs[i], oq)
+        assert np.abs(total[i] - ref).max() < 1e-13 * np.abs(ref).max()
+    check_liveness(desc)
+
+
+def test_open_output_arguments_rejected():
+    lat, circ, _bs, _ = synth.config("c1")
+    for bad in ([3, 3], [16], [-1], list(range(16)) + [0]):
+        with pytest.raises(qcsim.QcError) as e:
+            qcsim.qc_plan_build(lat.n, circ, None, open_qubits=bad)
+        assert e.value.status == 1, bad
+    big = synth.grid(5, 5)
+    c2 = synth.random_circuit(big, 4, 3)
+    with pytest.raises(qcsim.QcError) as e:
+        qcsim.qc_plan_build(big.n, c2, None, open_qubits=list(range(21)))
+    assert e.value.status == 1
+
+
+# ------------------------------------------------ buffer offsets (aliasing)
+@pytest.mark.parametrize("key,b,m", [("c1", 0, 4), ("c2", 6, 2), ("c2", 3, 0)])
+def test_flat_buffer_programs(key, b, m):
+    # The programs run in one buffer at the offsets the device uses, in the
+    # device's order, give the oracle's values (an aliasing mistake would
+    # change them or leave NaN).
+    lat, circ, bs, plan = _plan(key, log2_slices=4 if key == "c1" else 6, greedy_trials=4, seed=1)
+    desc = qcsim.qc_plan_describe(plan, b, m)
+    check_liveness(desc)
+    xs = synth.random_bitstrings(lat.n, max(1, (1 << m) - 1), 7)
+    n = 1 << qcsim.qc_plan_info(plan)["log2_slices"]
+    total, _ = sliced_amplitudes(desc, xs, n, flat=True)
+    psi = oracle.statevector(lat.n, circ)
+    ref = np.array([psi[oracle.index_of(x)] for x in xs])
+    assert np.abs(total - ref).max() < 1e-13 * np.abs(ref).max()
+
+
+def test_flat_buffer_program_with_transposes():
+    lat = synth.grid(5, 5)
+    circ = synth.random_circuit(lat, 28, 201)
+    xs = synth.random_bitstrings(lat.n, 4, 206)
+    plan = qcsim.qc_plan_build(lat.n, circ, None, log2_slices=0, greedy_trials=8, seed=1)
+    desc = qcsim.qc_plan_describe(plan, 0, 2)
+    assert any(op["op"] == "transpose" for op in desc["ops"])
+    check_liveness(desc)
+    got = run_program(desc, xs, flat=True)[0]
+    psi = oracle.statevector(lat.n, circ)
+    ref = np.array([psi[oracle.index_of(x)] for x in xs])
+    assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_diamond70_programs_liveness_and_sampled_slices():
+    # The measured 70-qubit depth 1+32+1 plan (2^20 slices, cap 2^30): its
+    # 64-slice program's buffer offsets checked statically in device order
+    # (every step and kept transpose).  On the same lattice at depth 1+24+1
+    # (per-slice tensors small enough for the CPU, 2^10 slices of at most 2^20
+    # entries): eight slices of the 4-slice program run in one NaN-poisoned
+    # buffer against O4, the oracle's own contraction of the circuit's network
+    # along the plan's tree.  Some slices are exact zeros that both sides
+    # reach only up to FP64 rounding of the leaf values, hence the rule
+    # |v - v_ref| <= tol max(|v_ref|, rms) of the GPU slice tests.
+    lat, circ, bs, spec = synth.config("c4")
+    plan = qcsim.qc_plan_build(lat.n, circ, bs[0], log2_slices=spec["log2_slices"],
+                               log2_max_entries=spec["log2_cap"], greedy_trials=spec["trials"],
+                               seed=spec["plan_seed"])
+    desc = qcsim.qc_plan_describe(plan, 6, 0)
+    assert check_liveness(desc) > 20
+    assert any(op["op"] == "transpose" for op in desc["ops"])
+    circ24 = synth.random_circuit(lat, 24, spec["seed"])
+    small = qcsim.qc_plan_build(lat.n, circ24, bs[0], log2_slices=10, log2_max_entries=20, greedy_trials=8, seed=2)
+    k = qcsim.qc_plan_info(small)["log2_slices"]
+    d2 = qcsim.qc_plan_describe(small, 2, 0)
+    check_liveness(d2)
+    tree = qcsim.qc_plan_export_tree(small)
+    segs = qcsim.qc_plan_sliced_segments(small)
+    got, ref = [], []
+    for s in (int(v) for v in synth.random_slices(k, 8, spec["seed"] + 2)):
+        got.append(run_program(d2, bs[:1], s & ~3, check_einsum=False, flat=True)[s & 3, 0])
+        ref.append(oracle.hyper_value(lat.n, circ24, bs[0], segs, s, tree))
+    got, ref = np.array(got), np.array(ref)
+    rms = np.sqrt(np.mean(np.abs(ref) ** 2))
+    assert (np.abs(ref) > 1e-6 * rms).sum() >= 2
+    assert (np.abs(got - ref) <= 1e-12 * np.maximum(np.abs(ref), rms)).all(), (got, ref)
+
+
+def test_quick_search_plan_matches_statevector():
+    # The quick search (greedy restarts and slicing, no reconfiguration)
+    # gives another valid tree: same amplitudes.
+    lat, circ, bs, _ = synth.config("c2")
+    full = qcsim.qc_plan_build(lat.n, circ, None, log2_slices=6, greedy_trials=4, seed=1)
+    quick = qcsim.qc_plan_build(lat.n, circ, None, log2_slices=6, greedy_trials=4, seed=1, quick=True)
+    assert qcsim.qc_plan_info(quick)["log2_slices"] == 6
+    assert qcsim.qc_plan_info(quick)["plan_seconds"] < qcsim.qc_plan_info(full)["plan_seconds"]
+    desc = qcsim.qc_plan_describe(quick, 6, 1)
+    check_liveness(desc)
+    total, _ = sliced_amplitudes(desc, bs[:2], 64, flat=True)
+    psi = oracle.statevector(lat.n, circ)
+    ref = np.array([psi[oracle.index_of(x)] for x in bs[:2]])
+    assert np.abs(total - ref).max() < 1e-13 * np.abs(ref).max()
