@@ -114,4 +114,10 @@ def test_open_plan_rejected_by_batch():
     batch = qcsim.Batch([(plan, bs[0])])
     with pytest.raises(qcsim.QcError) as e:
         qcsim.qc_batch_workspace_bytes(batch)
+    assert "open output" in str(e.value)
+    ws = torch.empty(1 << 20, dtype=torch.uint8, device="cuda")
+    out = torch.zeros(1, 2, dtype=torch.float64, device="cuda")
+    tdone = torch.zeros(2, dtype=torch.int64, device="cuda")
+    with pytest.raises(qcsim.QcError) as e:
+        qcsim.qc_contract_batch(batch, "c64", ws, out, tdone)
     assert e.value.status == 5
