@@ -252,6 +252,109 @@ def diamond_leg(steps, warmup, precs, chunk=None, cpu=True, tune_cache=None):
 
 
 # ------------------------------------------------------------ extra legs
+def open_leg(steps=3, warmup=1, precs=("c64", "split_fp16"), cpu=True):
+    """The 70-qubit depth 1+32+1 circuit with its last 16 output qubits left
+    open (qc_plan_build_open): every slice contraction yields 2^16 amplitude
+    contributions, so one pass over the 2^20 slices gives 65536 amplitudes
+    (the bitstrings that differ from the drawn one only in those qubits).
+    One step = one call over a chunk of consecutive slices; amplitudes/s is
+    projected as 2^16 x slices/s / 2^20.  Checked against O4 on the two
+    largest entries of the chunk's first nonzero slice (the oracle fixes the
+    open qubits to those entries' bits)."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1907_11217_amd import qcsim
+
+    lat, circ, bs, spec = synth.config("c4o")
+    oq, chunk, m = spec["open_qubits"], spec["chunk"], spec["n_open"]
+    t0 = time.perf_counter()
+    plan = qcsim.qc_plan_build(lat.n, circ, bs[0], log2_slices=spec["log2_slices"], log2_max_entries=spec["log2_cap"],
+                               greedy_trials=spec["trials"], seed=spec["plan_seed"], open_qubits=oq)
+    plan_s = time.perf_counter() - t0
+    info = qcsim.qc_plan_info(plan)
+    k = info["log2_slices"]
+    _say(f"70-qubit open: 2^{k} slices, {info['flops_per_slice']:.3e} flops per slice ({plan_s:.1f} s)")
+    stream = torch.cuda.current_stream()
+    bits = torch.from_numpy(np.ascontiguousarray(bs[:1])).cuda()
+    A = 1 << m
+    out = torch.zeros(1, A, 2, dtype=torch.float64, device="cuda")
+    ps = torch.zeros(chunk, 1, A, 2, dtype=torch.float64, device="cuda")
+    s0 = int(synth.random_slices(k, 1, spec["seed"] + 2)[0])
+    c0 = s0 - s0 % chunk
+    leg = {"workload": (f"{spec['name']}: the 70-qubit diamond at depth 1+{spec['depth']}+1 (seed {spec['seed']}, "
+                        f"bitstring seed {spec['seed'] + 1}) with the outputs of qubits {oq[0]}..{oq[-1]} open; "
+                        f"2^{k} slices (cap 2^{spec['log2_cap']}), {chunk} slices [{c0}, {c0 + chunk}) per step, "
+                        f"2^{m} amplitudes per contraction"),
+           "open_qubits": len(oq), "log2_slices": k, "slices_per_step": chunk, "plan_seconds": plan_s,
+           "log2_max_entries": info["log2_max_entries"], "flops_per_slice": info["flops_per_slice"],
+           "flops_per_amplitude": info["flops_per_slice"] * float(1 << k) / A, "per_prec": {}}
+    vals = {}
+    for prec in precs:
+        ws = torch.empty(qcsim.qc_workspace_bytes(plan, chunk, 1, prec), dtype=torch.uint8, device="cuda")
+        qcsim.qc_tune(plan, chunk, 1, prec, ws, stream=stream)   # untimed
+
+        def step():
+            qcsim.qc_contract_slices_dev(plan, c0, c0 + chunk, bits, prec, ws, out, stream=stream)
+
+        for _ in range(max(1, warmup)):
+            step()
+        ms = _events_ms(stream, step, steps)
+        qcsim.qc_profile_read(plan)
+        qcsim.qc_profile_enable(plan, True)
+        ms_prof = _events_ms(stream, step, 1)
+        qcsim.qc_profile_enable(plan, False)
+        prof = qcsim.qc_profile_read(plan)
+        out.zero_()
+        qcsim.qc_contract_slices_dev(plan, c0, c0 + chunk, bits, prec, ws, out, ps, stream=stream)
+        torch.cuda.synchronize()
+        p = ps.cpu().numpy()[:, 0]
+        vals[prec] = p[..., 0] + 1j * p[..., 1]
+        leg["per_prec"][prec] = {
+            "ms_per_step": ms, "slices_per_s": chunk / (ms * 1e-3),
+            "projected_amplitudes_per_s": A * chunk / (ms * 1e-3) / float(1 << k),
+            "projected_s_per_amplitude": ms * 1e-3 * float(1 << k) / chunk / A,
+            "tflops_alg": info["flops_per_slice"] * chunk / (ms * 1e-3) / 1e12, "ms_per_step_profiled": ms_prof,
+            "kernels": _kernel_table(prof, 1), "roofline": _roofline(prof, prec, "diamond70_d32_open16")}
+        _say(f"70-qubit open {prec}: {ms:.1f} ms per {chunk} slices")
+        del ws
+    c64 = leg["per_prec"].get("c64")
+    for prec in precs:
+        if prec != "c64" and c64:
+            leg["per_prec"][prec]["speedup_over_c64"] = c64["ms_per_step"] / leg["per_prec"][prec]["ms_per_step"]
+            leg["per_prec"][prec]["slice_diff_vs_c64"] = _slice_errors(vals[prec].reshape(-1),
+                                                                       vals["c64"].reshape(-1), TOL[prec])
+    if cpu:
+        import oracle
+        v = vals[precs[0]]
+        nz = [j for j in range(chunk) if np.abs(v[j]).max() > 0]
+        if nz:
+            j = nz[0]
+            top = np.argsort(-np.abs(v[j]))[:2]
+            tree = qcsim.qc_plan_export_tree(plan)
+            segs = qcsim.qc_plan_sliced_segments(plan)
+            ref, secs = [], []
+            for o in top:
+                y = bs[0].copy()
+                for i, q in enumerate(oq):
+                    y[q] = (int(o) >> (m - 1 - i)) & 1
+                t1 = time.perf_counter()
+                ref.append(oracle.hyper_value(lat.n, circ, y, segs, c0 + j, tree))
+                secs.append(time.perf_counter() - t1)
+            rms = float(np.sqrt(np.mean(np.abs(v[j]) ** 2)))
+            for prec in precs:
+                got = vals[prec][j][top]
+                leg["per_prec"][prec]["err_vs_oracle"] = {
+                    "max_rel": float(np.max(np.abs(got - np.array(ref)) / np.abs(np.array(ref)))),
+                    "values": 2, "slice": c0 + j, "tol": TOL[prec], "slice_rms": rms}
+            med = float(np.median(secs))
+            _say(f"70-qubit open oracle: {med:.1f} s per value")
+            leg["cpu_oracle"] = dict(seconds_per_value=med, projected_s_per_amplitude=med * float(1 << k),
+                                     **_cpu_info(), sample="O4 on 2 entries of one slice (one open setting each)")
+    return leg
+
+
 def fused_leg(steps=50, warmup=10, cpu=True):
     """The 5x5 depth 1+16+1 workload: every one of its 2^6 slices for all 64
     bitstrings per step, fused form (one launch per call plus the sums)."""
@@ -537,7 +640,7 @@ def main():
     ap.add_argument("--only-prec", action="store_true", help="time only --prec on the 70-qubit workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the 4x4, 5x5, 7x7 and request-batch legs")
-    ap.add_argument("--leg", choices=["grid5x5_d16", "grid7x7_d24", "request_batch"],
+    ap.add_argument("--leg", choices=["grid5x5_d16", "grid7x7_d24", "request_batch", "diamond70_d32_open16"],
                     help="run only this leg and print its JSON (for profiling runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 256 MiB device to device 5 times (the plain-copy reference of the "
@@ -561,7 +664,8 @@ def main():
     if args.leg:
         leg = {"grid5x5_d16": lambda: fused_leg(cpu=False),
                "grid7x7_d24": lambda: grid7_leg(["c64", "split_fp16", "split_bf16"], cpu=False),
-               "request_batch": batch_leg}[args.leg]()
+               "request_batch": batch_leg,
+               "diamond70_d32_open16": lambda: open_leg(cpu=False)}[args.leg]()
         print(json.dumps(leg), flush=True)
         return
 
@@ -613,6 +717,8 @@ def main():
         _say("7x7 done")
         result["request_batch"] = batch_leg()
         _say("request batch done")
+        result["diamond70_d32_open16"] = open_leg(cpu=not args.no_cpu_baseline)
+        _say("70-qubit open outputs done")
     print(json.dumps(result), flush=True)
 
 

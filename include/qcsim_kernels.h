@@ -49,8 +49,12 @@ qc_status qc_kernel_gemm(const void *A, const void *B, void *C, int64_t nb, int6
  *   multiples of 128), 13 skinny on the transposed product (n in
  *   {1,2,4,8,16}, m >= 64), 14 dot tile (m n <= 256, k >= 64: one workgroup
  *   per batch entry's whole tile, k staged through LDS), 15 rows (n in
- *   {1,2,4,8,16}, m >= 64: one row of C per thread, B in LDS); form -1 is the
- *   default choice.  Forms 0..2 and 13..15 compute in FP32 for every
+ *   {1,2,4,8,16}, m >= 64: one row of C per thread, B in LDS), 16..21
+ *   complex FP32 MFMA with tall or wide tiles 256x64, 64x256, 32x256, 256x32,
+ *   128x64, 64x128 (QC_C64, k >= 2, m and n multiples of the tile: the
+ *   128x128 form's double-buffered slabs for shapes with one short output
+ *   dimension); form -1 is the default choice.  Forms 0..2 and 13..15
+ *   compute in FP32 for every
  *   precision.  QC_ERR_UNSUPPORTED if the form does not apply to the shape and
  *   precision. */
 qc_status qc_kernel_gemm_form(const void *A, const void *B, void *C, int64_t nb, int64_t m, int64_t n, int64_t k,
@@ -58,7 +62,7 @@ qc_status qc_kernel_gemm_form(const void *A, const void *B, void *C, int64_t nb,
                               void *stream);
 
 /* qc_kernel_gemm_form split over k, as the stepwise contraction runs its
- * GEMM steps with few outputs: every MFMA form (3-12) and the dot forms (2, 14)
+ * GEMM steps with few outputs: every MFMA form (3-12, 16-21) and the dot forms (2, 14)
  * compute kparts partial products, part p over l in [p k/kparts,
  * (p+1) k/kparts), into `scratch`, then C = the parts summed in increasing p,
  * in FP32 (so the result is deterministic).  scratch: caller-owned device

@@ -225,6 +225,8 @@ enum GemmVariant {
     kVarSkinnyT,   // the skinny form on the transposed problem (C^T = B^T A^T): n <= 16, wide m
     kVarDotTile,   // small output tile (m n <= 256 per batch), long k: A and B k-chunks through LDS
     kVarRows,      // n <= 16, tall m: B in LDS, one row of C per thread, A rows read once
+    // Tall and wide tiles of the complex FP32 MFMA product (TM x TN):
+    kVarT256x64, kVarT64x256, kVarT32x256, kVarT256x32, kVarT128x64, kVarT64x128,
     kVarCount
 };
 bool gemm_variant_ok(const GemmDesc &d, int v);

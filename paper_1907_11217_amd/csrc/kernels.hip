@@ -1029,10 +1029,158 @@ __global__ void __launch_bounds__(256) gemm_mfma_big_kernel(GemmDesc d) {
     }
 }
 
+// Tall and wide tile forms of the complex FP32 MFMA product: the large-tile
+// form's structure (four waves, K slabs of 16 double buffered in LDS as
+// (re, im) pairs [k][row], the next slab prefetched in registers while the
+// current one is multiplied, XCD-contiguous tile order) with a tile of
+// TM x TN = (32 BM WGM) x (32 BN WGN): the waves in a WGM x WGN grid, each
+// holding BM x BN output blocks of 32 x 32.  Shapes with one long and one
+// short output dimension and a short k (a long panel streamed past a small
+// operand) fill the chip with these tiles where 128 x 128 tiles do not fit.
+// Each thread stages up to PA (PB) groups of 8 consecutive k of one row.
+template <int BM, int BN, int WGM, int WGN>
+__global__ void __launch_bounds__(256) gemm_mfma_tile_kernel(GemmDesc d) {
+    static_assert(WGM * WGN == 4, "four waves");
+    constexpr int TM = 32 * BM * WGM, TN = 32 * BN * WGN, KT = 16;
+    constexpr int PA = (2 * TM + 255) / 256, PB = (2 * TN + 255) / 256;
+    __shared__ __attribute__((aligned(16))) float2 As[2][KT][TM];
+    __shared__ __attribute__((aligned(16))) float2 Bs[2][KT][TN];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int wm = wave / WGN, wn = wave % WGN;
+    const int64_t tiles_m = d.m / TM, tiles_n = d.n / TN;
+    const int64_t n_tiles = d.nb * tiles_m * tiles_n;
+    const bool a_kc = d.sAk == 1, b_kc = d.sBk == 1;
+    const bool a_vec = a_kc && d.sAm % 2 == 0 && d.sAb % 2 == 0 && d.sAp % 2 == 0 && (uintptr_t)d.A % 16 == 0;
+    const bool b_vec = b_kc && d.sBn % 2 == 0 && d.sBb % 2 == 0 && d.sBp % 2 == 0 && (uintptr_t)d.B % 16 == 0;
+    // Staging pairs (row, half of the slab): along k when k is the fast axis
+    // (two threads per row), else along the row (coalesced across lanes).
+    int ar[PA], ah[PA], br[PB], bh[PB];
+    bool a_on[PA], b_on[PB];
+#pragma unroll
+    for (int p = 0; p < PA; ++p) {
+        const int q = t + 256 * p;
+        a_on[p] = q < 2 * TM;
+        ar[p] = a_kc ? (q >> 1) % TM : q % TM;
+        ah[p] = a_kc ? (q & 1) : (q / TM) & 1;
+    }
+#pragma unroll
+    for (int p = 0; p < PB; ++p) {
+        const int q = t + 256 * p;
+        b_on[p] = q < 2 * TN;
+        br[p] = b_kc ? (q >> 1) % TN : q % TN;
+        bh[p] = b_kc ? (q & 1) : (q / TN) & 1;
+    }
+    const int n_slabs = int((d.k + KT - 1) / KT);
+    int64_t first = blockIdx.x;
+    if (gridDim.x % 8 == 0) first = int64_t(blockIdx.x % 8) * (gridDim.x / 8) + blockIdx.x / 8;
+    for (int64_t tile = first; tile < n_tiles; tile += gridDim.x) {
+        const int64_t tn = tile % tiles_n;
+        const int64_t tm = (tile / tiles_n) % tiles_m;
+        const int64_t bi = tile / (tiles_n * tiles_m);
+        const int64_t bq = d.kparts == 1 ? bi : bi / d.kparts, bp = bi - bq * d.kparts;
+        const float2 *Ab = d.A + bq * d.sAb + bp * d.sAp + tm * TM * d.sAm;
+        const float2 *Bb = d.B + bq * d.sBb + bp * d.sBp + tn * TN * d.sBn;
+        floatx16 acc[BM][BN][2];
+#pragma unroll
+        for (int i = 0; i < BM; ++i)
+#pragma unroll
+            for (int j = 0; j < BN; ++j)
+#pragma unroll
+                for (int v = 0; v < 16; ++v) { acc[i][j][0][v] = 0.f; acc[i][j][1][v] = 0.f; }
+        float2 ra[PA][8], rb[PB][8];
+#pragma unroll
+        for (int p = 0; p < PA; ++p)
+            if (a_on[p]) load8(ra[p], Ab, d.sAm, d.sAk, a_vec, ar[p], 8 * ah[p], d.k);
+#pragma unroll
+        for (int p = 0; p < PB; ++p)
+            if (b_on[p]) load8(rb[p], Bb, d.sBn, d.sBk, b_vec, br[p], 8 * bh[p], d.k);
+#pragma unroll
+        for (int p = 0; p < PA; ++p)
+            if (a_on[p])
+#pragma unroll
+                for (int q = 0; q < 8; ++q) As[0][8 * ah[p] + q][ar[p]] = ra[p][q];
+#pragma unroll
+        for (int p = 0; p < PB; ++p)
+            if (b_on[p])
+#pragma unroll
+                for (int q = 0; q < 8; ++q) Bs[0][8 * bh[p] + q][br[p]] = rb[p][q];
+        __syncthreads();
+        for (int s = 0; s < n_slabs; ++s) {
+            const int buf = s & 1;
+            const bool more = s + 1 < n_slabs;
+            if (more) {
+                const int64_t k1 = int64_t(s + 1) * KT;
+#pragma unroll
+                for (int p = 0; p < PA; ++p)
+                    if (a_on[p]) load8(ra[p], Ab, d.sAm, d.sAk, a_vec, ar[p], k1 + 8 * ah[p], d.k);
+#pragma unroll
+                for (int p = 0; p < PB; ++p)
+                    if (b_on[p]) load8(rb[p], Bb, d.sBn, d.sBk, b_vec, br[p], k1 + 8 * bh[p], d.k);
+            }
+#pragma unroll
+            for (int kk = 0; kk < KT; kk += 2) {
+                const int kr = kk + (lane >> 5);
+                float2 a[BM], b[BN];
+#pragma unroll
+                for (int i = 0; i < BM; ++i) a[i] = As[buf][kr][wm * 32 * BM + i * 32 + (lane & 31)];
+#pragma unroll
+                for (int j = 0; j < BN; ++j) b[j] = Bs[buf][kr][wn * 32 * BN + j * 32 + (lane & 31)];
+#pragma unroll
+                for (int i = 0; i < BM; ++i)
+#pragma unroll
+                    for (int j = 0; j < BN; ++j) {
+                        acc[i][j][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i].x, b[j].x, acc[i][j][0], 0, 0, 0);
+                        acc[i][j][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i].x, b[j].y, acc[i][j][1], 0, 0, 0);
+                    }
+#pragma unroll
+                for (int i = 0; i < BM; ++i)
+#pragma unroll
+                    for (int j = 0; j < BN; ++j) {
+                        acc[i][j][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(-a[i].y, b[j].y, acc[i][j][0], 0, 0, 0);
+                        acc[i][j][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i].y, b[j].x, acc[i][j][1], 0, 0, 0);
+                    }
+            }
+            if (more) {
+#pragma unroll
+                for (int p = 0; p < PA; ++p)
+                    if (a_on[p])
+#pragma unroll
+                        for (int q = 0; q < 8; ++q) As[buf ^ 1][8 * ah[p] + q][ar[p]] = ra[p][q];
+#pragma unroll
+                for (int p = 0; p < PB; ++p)
+                    if (b_on[p])
+#pragma unroll
+                        for (int q = 0; q < 8; ++q) Bs[buf ^ 1][8 * bh[p] + q][br[p]] = rb[p][q];
+            }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int i = 0; i < BM; ++i)
+#pragma unroll
+            for (int j = 0; j < BN; ++j) {
+                const CBlock cb = c_block(d, bi, tm * TM + wm * 32 * BM + i * 32, tn * TN + wn * 32 * BN + j * 32, lane);
+#pragma unroll
+                for (int v = 0; v < 16; ++v) *c_at(cb, v) = make_float2(acc[i][j][0][v], acc[i][j][1][v]);
+            }
+    }
+}
+
 // ----------------------------------------------------------- GEMM variants
 // Every kernel form a GEMM step can run as.  gemm_variant_ok says whether a
 // form applies to a shape (tile divisibility, k, precision); the default
 // choice follows fixed rules, the autotuner may pick another applicable one.
+// Tile of a tall or wide FP32 MFMA form.
+static void tile_dims(int v, int &tm, int &tn) {
+    switch (v) {
+        case kVarT256x64: tm = 256; tn = 64; break;
+        case kVarT64x256: tm = 64; tn = 256; break;
+        case kVarT32x256: tm = 32; tn = 256; break;
+        case kVarT256x32: tm = 256; tn = 32; break;
+        case kVarT128x64: tm = 128; tn = 64; break;
+        default: tm = 64; tn = 128; break;
+    }
+}
+
 bool gemm_variant_ok(const GemmDesc &d, int v) {
     const bool split = d.prec != kPrecC64;
     const int64_t kt = d.k >= 16 ? 16 : d.k;
@@ -1051,6 +1199,11 @@ bool gemm_variant_ok(const GemmDesc &d, int v) {
         }
         case kVarSplitBig: return split && d.k >= 2 && d.m % 128 == 0 && d.n % 128 == 0;
         case kVarMfmaBig: return !split && d.k >= 2 && d.m % 128 == 0 && d.n % 128 == 0;
+        case kVarT256x64: case kVarT64x256: case kVarT32x256: case kVarT256x32: case kVarT128x64: case kVarT64x128: {
+            int tm = 0, tn = 0;
+            tile_dims(v, tm, tn);
+            return !split && d.k >= 2 && d.m % tm == 0 && d.n % tn == 0;
+        }
         case kVarSplit11: case kVarSplit12: case kVarSplit21: case kVarSplit22: {
             const int wm = (v == kVarSplit21 || v == kVarSplit22) ? 2 : 1, wn = (v == kVarSplit12 || v == kVarSplit22) ? 2 : 1;
             return split && d.k >= 2 && d.m % (32 * wm) == 0 && d.n % (32 * wn) == 0;
@@ -1173,6 +1326,21 @@ const char *launch_big(const GemmDesc &d, int v, hipStream_t st) {
         hipLaunchKernelGGL(gemm_dot_tile_kernel, dim3(g), dim3(256), 0, st, d);
         return "gemm_dot_tile";
     }
+    if (v >= kVarT256x64 && v <= kVarT64x128) {
+        int tm = 0, tn = 0;
+        tile_dims(v, tm, tn);
+        const int64_t tiles = d.nb * (d.m / tm) * (d.n / tn);
+        const unsigned gt = (unsigned)(tiles < 1048576 ? tiles : 1048576);
+        switch (v) {
+            case kVarT256x64: hipLaunchKernelGGL((gemm_mfma_tile_kernel<2, 2, 4, 1>), dim3(gt), dim3(256), 0, st, d); break;
+            case kVarT64x256: hipLaunchKernelGGL((gemm_mfma_tile_kernel<2, 2, 1, 4>), dim3(gt), dim3(256), 0, st, d); break;
+            case kVarT32x256: hipLaunchKernelGGL((gemm_mfma_tile_kernel<1, 2, 1, 4>), dim3(gt), dim3(256), 0, st, d); break;
+            case kVarT256x32: hipLaunchKernelGGL((gemm_mfma_tile_kernel<2, 1, 4, 1>), dim3(gt), dim3(256), 0, st, d); break;
+            case kVarT128x64: hipLaunchKernelGGL((gemm_mfma_tile_kernel<2, 1, 2, 2>), dim3(gt), dim3(256), 0, st, d); break;
+            default: hipLaunchKernelGGL((gemm_mfma_tile_kernel<1, 2, 2, 2>), dim3(gt), dim3(256), 0, st, d); break;
+        }
+        return "gemm_mfma";
+    }
     const int64_t t128 = d.nb * (d.m / 128) * (d.n / 128);
     const unsigned g = (unsigned)(t128 < 1048576 ? t128 : 1048576);
     if (v == kVarMfmaBig) {
@@ -1236,6 +1404,7 @@ const char *launch_gemm_variant(const GemmDesc &d, int v, hipStream_t st) {
                 default: launch_split<2, 2>(d, st); return split_name;
             }
         case kVarMfmaBig: case kVarSplitBig:
+        case kVarT256x64: case kVarT64x256: case kVarT32x256: case kVarT256x32: case kVarT128x64: case kVarT64x128:
             if (d.kparts > 1) return launch_gemm_kparts(d, v, st);
             return launch_big(d, v, st);
         case kVarDot: case kVarDotTile:

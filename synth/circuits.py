@@ -162,13 +162,21 @@ CONFIGS = {
                n_bitstrings=1, log2_slices=16, log2_cap=30, n_sampled=32, trials=8, plan_seed=1),
     "c4": dict(name="diamond70_d32", lattice="diamond70", depth=32, seed=401,
                n_bitstrings=1, log2_slices=20, log2_cap=30, trials=256, plan_seed=1, chunk=64),
+    # The same circuit with the outputs of its last n_open qubits left open:
+    # each contraction gives the 2^n_open amplitudes of the bitstrings that
+    # differ from the drawn one only there.
+    "c4o": dict(name="diamond70_d32_open16", lattice="diamond70", depth=32, seed=401,
+                n_bitstrings=1, log2_slices=20, log2_cap=30, trials=256, plan_seed=1, chunk=32, n_open=16),
 }
 
 
 def config(key: str):
-    """(lattice, circuit, bitstrings, spec dict) for a named workload."""
+    """(lattice, circuit, bitstrings, spec dict) for a named workload; a
+    workload with open outputs also gets spec["open_qubits"]."""
     spec = dict(CONFIGS[key])
     lat = diamond70() if spec["lattice"] == "diamond70" else grid(*spec["lattice"])
+    if spec.get("n_open"):
+        spec["open_qubits"] = list(range(lat.n - spec["n_open"], lat.n))
     circ = random_circuit(lat, spec["depth"], spec["seed"])
     bs = random_bitstrings(lat.n, spec["n_bitstrings"], spec["seed"] + 1)
     return lat, circ, bs, spec

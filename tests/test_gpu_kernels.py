@@ -258,6 +258,9 @@ EXACT_FORMS = [
     ("mfma11", 2, 64, 64, 48, 1), ("mfma12", 1, 32, 64, 16, 1), ("mfma21", 3, 64, 32, 8, 1),
     ("mfma22", 1, 128, 64, 4, 1), ("mfma11", 1, 32, 32, 4096, 8),
     ("mfma_big", 1, 128, 256, 64, 1), ("mfma_big", 2, 128, 128, 2, 1), ("mfma_big", 1, 128, 128, 1024, 4),
+    ("tile256x64", 2, 512, 64, 40, 1), ("tile64x256", 1, 64, 512, 16, 1), ("tile32x256", 3, 32, 256, 7, 1),
+    ("tile256x32", 1, 256, 96, 64, 1), ("tile128x64", 2, 256, 64, 2, 1), ("tile64x128", 1, 128, 128, 512, 4),
+    ("tile32x256", 1, 64, 512, 256, 8),
 ]
 
 

@@ -121,3 +121,43 @@ def test_open_plan_rejected_by_batch():
     with pytest.raises(qcsim.QcError) as e:
         qcsim.qc_contract_batch(batch, "c64", ws, out, tdone)
     assert e.value.status == 5
+
+
+def test_diamond70_open_outputs_vs_o4():
+    # The 70-qubit depth 1+32+1 circuit with its last 12 outputs open (2^20
+    # slices, cap 2^30): the per-slice values of one 16-slice chunk, complex
+    # FP32 and split FP16, against O4 (the oracle's contraction of the
+    # circuit's network along the plan's tree, the open qubits fixed to the
+    # entry's bits) on the three largest entries and one drawn entry of the
+    # chunk's first nonzero slice.
+    lat, circ, bs, spec = synth.config("c4")
+    oq = list(range(lat.n - 12, lat.n))
+    plan = qcsim.qc_plan_build(lat.n, circ, bs[0], log2_slices=20, log2_max_entries=30, greedy_trials=64, seed=1,
+                               open_qubits=oq)
+    k = qcsim.qc_plan_info(plan)["log2_slices"]
+    s0 = int(synth.random_slices(k, 1, spec["seed"] + 2)[0])
+    c0 = s0 - s0 % 16
+    vals = {}
+    for prec in ("c64", "split_fp16"):
+        say(f"70-qubit, 12 open outputs, slices [{c0}, {c0 + 16}) {prec}")
+        _, vals[prec] = _contract(plan, bs[:1], c0, c0 + 16, prec, chunk=16, per_slice=True)
+    v = vals["c64"][:, 0]
+    nz = [j for j in range(16) if np.abs(v[j]).max() > 0]
+    assert nz, "every slice of the chunk is zero"
+    j = nz[0]
+    picks = list(np.argsort(-np.abs(v[j]))[:3]) + [int(synth.random_slices(12, 1, 7)[0])]
+    tree = qcsim.qc_plan_export_tree(plan)
+    segs = qcsim.qc_plan_sliced_segments(plan)
+    ref = []
+    for o in picks:
+        y = bs[0].copy()
+        for i, q in enumerate(oq):
+            y[q] = (int(o) >> (11 - i)) & 1
+        ref.append(oracle.hyper_value(lat.n, circ, y, segs, c0 + j, tree))
+    ref = np.array(ref)
+    rms = np.sqrt(np.mean(np.abs(v[j]) ** 2))
+    for prec, tol in (("c64", 1e-5), ("split_fp16", 1e-4)):
+        got = vals[prec][j, 0][picks]
+        err = np.abs(got - ref) / np.maximum(np.abs(ref), rms)
+        say(f"  {prec}: max err {err.max():.2e}")
+        assert (err <= tol).all(), (prec, got, ref)
