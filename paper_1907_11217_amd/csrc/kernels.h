@@ -29,7 +29,8 @@ struct LeafDesc {
 // Bit permutation out[perm(i)] = in[i] of a rank-r complex64 tensor, staged
 // through LDS one tile at a time.  Tile bits = the input's lowest bits plus the
 // output's lowest bits; the remaining bits enumerate tiles.
-constexpr int kTransMaxTile = 10;
+constexpr int kTransMaxTile = 12;    // tile bits of tensors of rank >= 12 (16-byte accesses)
+constexpr int kTransSmallTile = 10;  // tile bits of smaller tensors (all of them up to rank 10)
 struct TransposeDesc {
     const float2 *in;
     float2 *out;

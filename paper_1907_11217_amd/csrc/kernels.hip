@@ -229,9 +229,9 @@ void launch_micro(const MicroStep *steps, const int32_t *group_start, const int3
 __device__ __forceinline__ int lds_pad(int t) { return t + (t >> 5); }
 
 __global__ void __launch_bounds__(256) transpose_kernel(TransposeDesc d) {
-    __shared__ float2 tile[(1 << kTransMaxTile) + (1 << kTransMaxTile) / 32];
+    __shared__ float2 tile[(1 << kTransSmallTile) + (1 << kTransSmallTile) / 32];
     const int tsize = 1 << d.n_tile;
-    constexpr int E = 4;  // (1 << kTransMaxTile) / 256, and 128 / 64 for the small form
+    constexpr int E = 4;  // (1 << kTransSmallTile) / 256, and 128 / 64 for the small form
     int64_t ioff[E], ooff[E];
     int ilds[E], olds[E];
 #pragma unroll
@@ -264,8 +264,66 @@ __global__ void __launch_bounds__(256) transpose_kernel(TransposeDesc d) {
     }
 }
 
+// Tiles of 2^12 elements (tensors of rank >= 12): both phases move pairs of
+// elements with 16-byte accesses -- phase 1 pairs consecutive input elements
+// (the tile holds input bit 0), phase 2 pairs consecutive output elements
+// (the tile holds the input bit that becomes output bit 0) -- and each
+// thread moves eight pairs per tile.  Pair j of thread t is element e = 2 t +
+// 512 j of the tile in input order (phase 1) or output order (phase 2), so
+// its offsets split into a per-thread part (bits 1..8) and a part shared by
+// all threads (bits 9..11).
+__global__ void __launch_bounds__(256) transpose_wide_kernel(TransposeDesc d) {
+    constexpr int NT = 1 << kTransMaxTile, J = NT / 512;
+    __shared__ float2 tile[NT + NT / 32];
+    const int t = threadIdx.x;
+    int64_t ilo = 0, olo = 0;
+    int llo = 0;
+#pragma unroll
+    for (int i = 1; i < 9; ++i)
+        if (((2 * t) >> i) & 1) { ilo += d.tin_in[i]; olo += d.tout_out[i]; llo += d.tout_lds[i]; }
+    int64_t ihi[J], ohi[J];
+    int lhi[J];
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+        ihi[j] = 0; ohi[j] = 0; lhi[j] = 0;
+#pragma unroll
+        for (int i = 9; i < kTransMaxTile; ++i)
+            if (((512 * j) >> i) & 1) { ihi[j] += d.tin_in[i]; ohi[j] += d.tout_out[i]; lhi[j] += d.tout_lds[i]; }
+    }
+    const int l1 = d.tout_lds[0];  // input-order distance of the two elements of an output pair
+    for (int64_t t_id = blockIdx.x; t_id < d.n_tiles; t_id += gridDim.x) {
+        int64_t in_base = 0, out_base = 0;
+        for (uint64_t rest = uint64_t(t_id); rest; rest &= rest - 1) {
+            const int j = __builtin_ctzll(rest);
+            in_base += d.rest_in[j];
+            out_base += d.rest_out[j];
+        }
+        float4 v[J];
+#pragma unroll
+        for (int j = 0; j < J; ++j) v[j] = *(const float4 *)(d.in + in_base + ilo + ihi[j]);
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            const int e = 2 * t + 512 * j;
+            tile[lds_pad(e)] = make_float2(v[j].x, v[j].y);
+            tile[lds_pad(e + 1)] = make_float2(v[j].z, v[j].w);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            const int l = llo + lhi[j];
+            const float2 a = tile[lds_pad(l)], b = tile[lds_pad(l + l1)];
+            *(float4 *)(d.out + out_base + olo + ohi[j]) = make_float4(a.x, a.y, b.x, b.y);
+        }
+        __syncthreads();
+    }
+}
+
 void launch_transpose(const TransposeDesc &d, hipStream_t st) {
     const int64_t grid = d.n_tiles < 65536 ? d.n_tiles : 65536;
+    if (d.n_tile == kTransMaxTile) {
+        hipLaunchKernelGGL(transpose_wide_kernel, dim3((unsigned)grid), dim3(256), 0, st, d);
+        return;
+    }
     // 256 threads for tiles of 256..1024 elements, 64 for smaller ones (at
     // most four elements per thread either way).
     const int threads = d.n_tile >= 8 ? 256 : 64;
@@ -788,22 +846,30 @@ __device__ __forceinline__ void split_store(T (*plane)[128][16], int row, int ha
 }
 
 // 8 consecutive k (from k0 + 8 half) of row `row` of an operand whose element
-// (row, kk) sits at base[row * s_row + kk * s_k]; zero beyond k.  vec: k is
-// the fast axis and every row start is 16-byte aligned (16-byte loads).
+// (row, kk) sits at base[row * s_row + kk * s_k]; zero beyond k, which the
+// forms using this require to be a multiple of 8 (a group is then entirely
+// inside k or entirely past it: no per-element predicates, which would hold
+// eight addresses live).  vec: k is the fast axis and every row start is
+// 16-byte aligned (16-byte loads).
 __device__ __forceinline__ void load8(float2 (&v)[8], const float2 *base, int64_t s_row, int64_t s_k, bool vec,
                                       int row, int64_t kk0, int64_t k) {
     const float2 *p = base + row * s_row + kk0 * s_k;
-    if (vec && kk0 + 8 <= k) {
-        const float4 *p4 = (const float4 *)p;
+    if (kk0 < k) {
+        if (vec) {
+            const float4 *p4 = (const float4 *)p;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const float4 w = p4[q];
-            v[2 * q] = make_float2(w.x, w.y);
-            v[2 * q + 1] = make_float2(w.z, w.w);
+            for (int q = 0; q < 4; ++q) {
+                const float4 w = p4[q];
+                v[2 * q] = make_float2(w.x, w.y);
+                v[2 * q + 1] = make_float2(w.z, w.w);
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < 8; ++q) v[q] = p[q * s_k];
         }
     } else {
 #pragma unroll
-        for (int q = 0; q < 8; ++q) v[q] = kk0 + q < k ? p[q * s_k] : make_float2(0.f, 0.f);
+        for (int q = 0; q < 8; ++q) v[q] = make_float2(0.f, 0.f);
     }
 }
 
@@ -1071,15 +1137,49 @@ __global__ void __launch_bounds__(256) gemm_mfma_tile_kernel(GemmDesc d) {
         bh[p] = b_kc ? (q & 1) : (q / TN) & 1;
     }
     const int n_slabs = int((d.k + KT - 1) / KT);
-    int64_t first = blockIdx.x;
-    if (gridDim.x % 8 == 0) first = int64_t(blockIdx.x % 8) * (gridDim.x / 8) + blockIdx.x / 8;
-    for (int64_t tile = first; tile < n_tiles; tile += gridDim.x) {
-        const int64_t tn = tile % tiles_n;
-        const int64_t tm = (tile / tiles_n) % tiles_m;
-        const int64_t bi = tile / (tiles_n * tiles_m);
+    // Operand panels of a tile (batch entry, rows, columns).
+    auto panels = [&](int64_t tile, const float2 *&Ab, const float2 *&Bb, int64_t &bi, int64_t &tm, int64_t &tn) {
+        tn = tile % tiles_n;
+        tm = (tile / tiles_n) % tiles_m;
+        bi = tile / (tiles_n * tiles_m);
         const int64_t bq = d.kparts == 1 ? bi : bi / d.kparts, bp = bi - bq * d.kparts;
-        const float2 *Ab = d.A + bq * d.sAb + bp * d.sAp + tm * TM * d.sAm;
-        const float2 *Bb = d.B + bq * d.sBb + bp * d.sBp + tn * TN * d.sBn;
+        Ab = d.A + bq * d.sAb + bp * d.sAp + tm * TM * d.sAm;
+        Bb = d.B + bq * d.sBb + bp * d.sBp + tn * TN * d.sBn;
+    };
+    float2 ra[PA][8], rb[PB][8];
+    auto load_slab = [&](const float2 *Ab, const float2 *Bb, int64_t k0) {
+#pragma unroll
+        for (int p = 0; p < PA; ++p)
+            if (a_on[p]) load8(ra[p], Ab, d.sAm, d.sAk, a_vec, ar[p], k0 + 8 * ah[p], d.k);
+#pragma unroll
+        for (int p = 0; p < PB; ++p)
+            if (b_on[p]) load8(rb[p], Bb, d.sBn, d.sBk, b_vec, br[p], k0 + 8 * bh[p], d.k);
+    };
+    auto store_slab = [&](int buf) {
+#pragma unroll
+        for (int p = 0; p < PA; ++p)
+            if (a_on[p])
+#pragma unroll
+                for (int q = 0; q < 8; ++q) As[buf][8 * ah[p] + q][ar[p]] = ra[p][q];
+#pragma unroll
+        for (int p = 0; p < PB; ++p)
+            if (b_on[p])
+#pragma unroll
+                for (int q = 0; q < 8; ++q) Bs[buf][8 * bh[p] + q][br[p]] = rb[p][q];
+    };
+    // Persistent: a block takes tiles first, first + G, ... (G = grid size);
+    // the first slab of its next tile is loaded while the last slab of the
+    // current one is multiplied, so the loads overlap the MFMAs and the
+    // output stores of the tile before.
+    int64_t tile = blockIdx.x;
+    if (gridDim.x % 8 == 0) tile = int64_t(blockIdx.x % 8) * (gridDim.x / 8) + blockIdx.x / 8;
+    if (tile >= n_tiles) return;
+    const float2 *Ab, *Bb;
+    int64_t bi, tm, tn;
+    panels(tile, Ab, Bb, bi, tm, tn);
+    load_slab(Ab, Bb, 0);
+    for (;;) {
+        const int64_t next = tile + gridDim.x;
         floatx16 acc[BM][BN][2];
 #pragma unroll
         for (int i = 0; i < BM; ++i)
@@ -1087,35 +1187,19 @@ __global__ void __launch_bounds__(256) gemm_mfma_tile_kernel(GemmDesc d) {
             for (int j = 0; j < BN; ++j)
 #pragma unroll
                 for (int v = 0; v < 16; ++v) { acc[i][j][0][v] = 0.f; acc[i][j][1][v] = 0.f; }
-        float2 ra[PA][8], rb[PB][8];
-#pragma unroll
-        for (int p = 0; p < PA; ++p)
-            if (a_on[p]) load8(ra[p], Ab, d.sAm, d.sAk, a_vec, ar[p], 8 * ah[p], d.k);
-#pragma unroll
-        for (int p = 0; p < PB; ++p)
-            if (b_on[p]) load8(rb[p], Bb, d.sBn, d.sBk, b_vec, br[p], 8 * bh[p], d.k);
-#pragma unroll
-        for (int p = 0; p < PA; ++p)
-            if (a_on[p])
-#pragma unroll
-                for (int q = 0; q < 8; ++q) As[0][8 * ah[p] + q][ar[p]] = ra[p][q];
-#pragma unroll
-        for (int p = 0; p < PB; ++p)
-            if (b_on[p])
-#pragma unroll
-                for (int q = 0; q < 8; ++q) Bs[0][8 * bh[p] + q][br[p]] = rb[p][q];
+        store_slab(0);
         __syncthreads();
         for (int s = 0; s < n_slabs; ++s) {
             const int buf = s & 1;
             const bool more = s + 1 < n_slabs;
             if (more) {
-                const int64_t k1 = int64_t(s + 1) * KT;
-#pragma unroll
-                for (int p = 0; p < PA; ++p)
-                    if (a_on[p]) load8(ra[p], Ab, d.sAm, d.sAk, a_vec, ar[p], k1 + 8 * ah[p], d.k);
-#pragma unroll
-                for (int p = 0; p < PB; ++p)
-                    if (b_on[p]) load8(rb[p], Bb, d.sBn, d.sBk, b_vec, br[p], k1 + 8 * bh[p], d.k);
+                load_slab(Ab, Bb, int64_t(s + 1) * KT);
+            } else if (next < n_tiles) {
+                // The next tile's panels (its indices are recomputed after
+                // this tile's output is written).
+                int64_t x0, x1, x2;
+                panels(next, Ab, Bb, x0, x1, x2);
+                load_slab(Ab, Bb, 0);
             }
 #pragma unroll
             for (int kk = 0; kk < KT; kk += 2) {
@@ -1140,18 +1224,7 @@ __global__ void __launch_bounds__(256) gemm_mfma_tile_kernel(GemmDesc d) {
                         acc[i][j][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i].y, b[j].x, acc[i][j][1], 0, 0, 0);
                     }
             }
-            if (more) {
-#pragma unroll
-                for (int p = 0; p < PA; ++p)
-                    if (a_on[p])
-#pragma unroll
-                        for (int q = 0; q < 8; ++q) As[buf ^ 1][8 * ah[p] + q][ar[p]] = ra[p][q];
-#pragma unroll
-                for (int p = 0; p < PB; ++p)
-                    if (b_on[p])
-#pragma unroll
-                        for (int q = 0; q < 8; ++q) Bs[buf ^ 1][8 * bh[p] + q][br[p]] = rb[p][q];
-            }
+            if (more) store_slab(buf ^ 1);
             __syncthreads();
         }
 #pragma unroll
@@ -1162,6 +1235,11 @@ __global__ void __launch_bounds__(256) gemm_mfma_tile_kernel(GemmDesc d) {
 #pragma unroll
                 for (int v = 0; v < 16; ++v) *c_at(cb, v) = make_float2(acc[i][j][0][v], acc[i][j][1][v]);
             }
+        if (next >= n_tiles) break;
+        tile = next;
+        tn = tile % tiles_n;
+        tm = (tile / tiles_n) % tiles_m;
+        bi = tile / (tiles_n * tiles_m);
     }
 }
 
@@ -1169,6 +1247,19 @@ __global__ void __launch_bounds__(256) gemm_mfma_tile_kernel(GemmDesc d) {
 // Every kernel form a GEMM step can run as.  gemm_variant_ok says whether a
 // form applies to a shape (tile divisibility, k, precision); the default
 // choice follows fixed rules, the autotuner may pick another applicable one.
+// Compute units of the current device (looked up once per device).
+static int device_cus() {
+    static int cus[64] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    if (cus[dev] == 0) {
+        int n = 0;
+        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
+        cus[dev] = n;
+    }
+    return cus[dev];
+}
+
 // Tile of a tall or wide FP32 MFMA form.
 static void tile_dims(int v, int &tm, int &tn) {
     switch (v) {
@@ -1197,12 +1288,13 @@ bool gemm_variant_ok(const GemmDesc &d, int v) {
             const int wm = (v == kVarMfma21 || v == kVarMfma22) ? 2 : 1, wn = (v == kVarMfma12 || v == kVarMfma22) ? 2 : 1;
             return !split && k_fp32 && d.m % (32 * wm) == 0 && d.n % (32 * wn) == 0;
         }
-        case kVarSplitBig: return split && d.k >= 2 && d.m % 128 == 0 && d.n % 128 == 0;
-        case kVarMfmaBig: return !split && d.k >= 2 && d.m % 128 == 0 && d.n % 128 == 0;
+        // The large-tile and tile forms stage k in groups of 8 (load8).
+        case kVarSplitBig: return split && d.k % 8 == 0 && d.m % 128 == 0 && d.n % 128 == 0;
+        case kVarMfmaBig: return !split && d.k % 8 == 0 && d.m % 128 == 0 && d.n % 128 == 0;
         case kVarT256x64: case kVarT64x256: case kVarT32x256: case kVarT256x32: case kVarT128x64: case kVarT64x128: {
             int tm = 0, tn = 0;
             tile_dims(v, tm, tn);
-            return !split && d.k >= 2 && d.m % tm == 0 && d.n % tn == 0;
+            return !split && d.k % 8 == 0 && d.m % tm == 0 && d.n % tn == 0;
         }
         case kVarSplit11: case kVarSplit12: case kVarSplit21: case kVarSplit22: {
             const int wm = (v == kVarSplit21 || v == kVarSplit22) ? 2 : 1, wn = (v == kVarSplit12 || v == kVarSplit22) ? 2 : 1;
@@ -1329,8 +1421,9 @@ const char *launch_big(const GemmDesc &d, int v, hipStream_t st) {
     if (v >= kVarT256x64 && v <= kVarT64x128) {
         int tm = 0, tn = 0;
         tile_dims(v, tm, tn);
-        const int64_t tiles = d.nb * (d.m / tm) * (d.n / tn);
-        const unsigned gt = (unsigned)(tiles < 1048576 ? tiles : 1048576);
+        // Persistent blocks, two per compute unit.
+        const int64_t tiles = d.nb * (d.m / tm) * (d.n / tn), cap = 2 * int64_t(device_cus());
+        const unsigned gt = (unsigned)(tiles < cap ? tiles : cap);
         switch (v) {
             case kVarT256x64: hipLaunchKernelGGL((gemm_mfma_tile_kernel<2, 2, 4, 1>), dim3(gt), dim3(256), 0, st, d); break;
             case kVarT64x256: hipLaunchKernelGGL((gemm_mfma_tile_kernel<2, 2, 1, 4>), dim3(gt), dim3(256), 0, st, d); break;

@@ -581,14 +581,18 @@ TransposeDesc make_transpose_desc(const float2 *in, float2 *out, int r, const st
     d.in = in;
     d.out = out;
     // Tile bits: the input's lowest bits and the output's lowest bits, taken
-    // alternately until the tile has kTransMaxTile bits (all bits of a small
-    // tensor), so reads and writes both run along contiguous stretches.
-    std::vector<char> in_tile(r, r <= kTransMaxTile ? 1 : 0);
-    if (r > kTransMaxTile) {
+    // alternately until the tile has kTransMaxTile bits (rank >= 12: the
+    // 16-byte form, whose pairs need input bit 0 and the input bit of output
+    // bit 0, the first two taken) or kTransSmallTile bits (all bits of a
+    // tensor of rank <= 10), so reads and writes both run along contiguous
+    // stretches.
+    const int nt = r >= kTransMaxTile ? kTransMaxTile : kTransSmallTile;
+    std::vector<char> in_tile(r, r <= nt ? 1 : 0);
+    if (r > nt) {
         std::vector<int> inv(r);
         for (int p = 0; p < r; ++p) inv[perm[p]] = p;
         int a = 0, c = 0, n = 0;
-        while (n < kTransMaxTile) {
+        while (n < nt) {
             const int p = a <= c ? a++ : inv[c++];
             if (!in_tile[p]) { in_tile[p] = 1; ++n; }
         }
