@@ -227,7 +227,9 @@ enum GemmVariant {
     kVarDotTile,   // small output tile (m n <= 256 per batch), long k: A and B k-chunks through LDS
     kVarRows,      // n <= 16, tall m: B in LDS, one row of C per thread, A rows read once
     // Tall and wide tiles of the complex FP32 MFMA product (TM x TN):
-    kVarT256x64, kVarT64x256, kVarT32x256, kVarT256x32, kVarT128x64, kVarT64x128,
+    kVarT256x64, kVarT64x256, kVarT32x256, kVarT256x32, kVarT128x64, kVarT64x128, kVarT128x32, kVarT32x128,
+    kVarMfma16,    // one 16x16 tile per wave on v_mfma_f32_16x16x4_f32 (n = 8 or n % 16 = 0), operands in registers
+    kVarMfma16T,   // the same on the transposed product (m = 8 or m % 16 = 0)
     kVarCount
 };
 bool gemm_variant_ok(const GemmDesc &d, int v);

@@ -1243,6 +1243,92 @@ __global__ void __launch_bounds__(256) gemm_mfma_tile_kernel(GemmDesc d) {
     }
 }
 
+// 16-wide MFMA form for a short output dimension (n = 8 or a multiple of 16)
+// with a long m -- through the transposed product also the reverse -- and
+// for 16 x 16 tiles with a long k split into parts.  Each wave owns one
+// 16 x 16 output tile and reads its operands straight into registers in the
+// v_mfma_f32_16x16x4_f32 layout: lane l holds row (of A) and column (of B)
+// l mod 16 and, of every chunk of 16 k, the four consecutive k from
+// 4 (l / 16) -- 32 contiguous bytes per lane where k is the fast axis,
+// 16-lane runs along the row or column otherwise -- and the chunk's four
+// products pair A's and B's k lane group by lane group (4M complex form, 16
+// MFMAs per chunk).  The next chunk is loaded while the current one is
+// multiplied.  Tiles are dealt to the grid's waves in turn; with n = 8 the
+// upper eight columns are zeros that are not stored.  No LDS, no barriers.
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+template <int NC>
+__global__ void __launch_bounds__(256) gemm_mfma16_kernel(GemmDesc d) {
+    const int lane = threadIdx.x & 63;
+    const int g = lane >> 4, c = lane & 15;
+    const bool bcol = NC == 16 || c < NC;
+    const int64_t tiles_m = d.m / 16, tiles_n = NC == 16 ? d.n / 16 : 1;
+    const int64_t n_tiles = d.nb * tiles_m * tiles_n;
+    const int64_t waves = int64_t(gridDim.x) * (blockDim.x >> 6);
+    const int n_chunks = int((d.k + 15) / 16);
+    const bool a_vec = d.sAk == 1 && d.sAm % 2 == 0 && d.sAb % 2 == 0 && d.sAp % 2 == 0 && (uintptr_t)d.A % 16 == 0;
+    const bool b_vec = d.sBk == 1 && d.sBn % 2 == 0 && d.sBb % 2 == 0 && d.sBp % 2 == 0 && (uintptr_t)d.B % 16 == 0;
+    float mx = 0.f;
+    for (int64_t tile = int64_t(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6); tile < n_tiles; tile += waves) {
+        const int64_t tn = tile % tiles_n, tm = (tile / tiles_n) % tiles_m, bi = tile / (tiles_n * tiles_m);
+        const int64_t bq = d.kparts == 1 ? bi : bi / d.kparts, bp = bi - bq * d.kparts;
+        const float2 *Ar = d.A + bq * d.sAb + bp * d.sAp + (tm * 16 + c) * d.sAm;
+        const float2 *Bc = d.B + bq * d.sBb + bp * d.sBp + (tn * 16 + (bcol ? c : 0)) * d.sBn;
+        // Four consecutive k from 4 g of chunk ch (zero past k or past n).
+        auto load = [&](int ch, float2 (&x)[4], float2 (&y)[4]) {
+            const int64_t k0 = int64_t(ch) * 16 + 4 * g;
+            if (k0 < d.k) {
+                if (a_vec) {
+                    const float4 u = *(const float4 *)(Ar + k0), w = *(const float4 *)(Ar + k0 + 2);
+                    x[0] = make_float2(u.x, u.y); x[1] = make_float2(u.z, u.w);
+                    x[2] = make_float2(w.x, w.y); x[3] = make_float2(w.z, w.w);
+                } else {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) x[q] = Ar[(k0 + q) * d.sAk];
+                }
+                if (!bcol) {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) y[q] = make_float2(0.f, 0.f);
+                } else if (b_vec) {
+                    const float4 u = *(const float4 *)(Bc + k0), w = *(const float4 *)(Bc + k0 + 2);
+                    y[0] = make_float2(u.x, u.y); y[1] = make_float2(u.z, u.w);
+                    y[2] = make_float2(w.x, w.y); y[3] = make_float2(w.z, w.w);
+                } else {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) y[q] = Bc[(k0 + q) * d.sBk];
+                }
+            } else {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) { x[q] = make_float2(0.f, 0.f); y[q] = make_float2(0.f, 0.f); }
+            }
+        };
+        floatx4 re = {0.f, 0.f, 0.f, 0.f}, im = {0.f, 0.f, 0.f, 0.f};
+        float2 a[4], b[4], an[4], bn[4];
+        load(0, a, b);
+        for (int ch = 0; ch < n_chunks; ++ch) {
+            if (ch + 1 < n_chunks) load(ch + 1, an, bn);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                re = __builtin_amdgcn_mfma_f32_16x16x4f32(a[j].x, b[j].x, re, 0, 0, 0);
+                im = __builtin_amdgcn_mfma_f32_16x16x4f32(a[j].x, b[j].y, im, 0, 0, 0);
+                re = __builtin_amdgcn_mfma_f32_16x16x4f32(-a[j].y, b[j].y, re, 0, 0, 0);
+                im = __builtin_amdgcn_mfma_f32_16x16x4f32(a[j].y, b[j].x, im, 0, 0, 0);
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) { a[q] = an[q]; b[q] = bn[q]; }
+        }
+        // Lane l holds rows 4 (l / 16) + v, column l mod 16.
+        if (bcol) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                d.C[c_off(d, bi, tm * 16 + 4 * g + v, tn * 16 + c)] = make_float2(re[v], im[v]);
+                mx = fmaxf(mx, fmaxf(fabsf(re[v]), fabsf(im[v])));
+            }
+        }
+    }
+    if (d.amax_c) block_amax(mx, d.amax_c);
+}
+
 // ----------------------------------------------------------- GEMM variants
 // Every kernel form a GEMM step can run as.  gemm_variant_ok says whether a
 // form applies to a shape (tile divisibility, k, precision); the default
@@ -1268,7 +1354,9 @@ static void tile_dims(int v, int &tm, int &tn) {
         case kVarT32x256: tm = 32; tn = 256; break;
         case kVarT256x32: tm = 256; tn = 32; break;
         case kVarT128x64: tm = 128; tn = 64; break;
-        default: tm = 64; tn = 128; break;
+        case kVarT64x128: tm = 64; tn = 128; break;
+        case kVarT128x32: tm = 128; tn = 32; break;
+        default: tm = 32; tn = 128; break;
     }
 }
 
@@ -1283,6 +1371,9 @@ bool gemm_variant_ok(const GemmDesc &d, int v) {
         case kVarSkinnyT: return d.m >= 64 && (d.n == 1 || d.n == 2 || d.n == 4 || d.n == 8 || d.n == 16);
         case kVarDotTile: return d.m * d.n <= 256 && d.k >= 64;
         case kVarRows: return d.m >= 64 && (d.n == 1 || d.n == 2 || d.n == 4 || d.n == 8 || d.n == 16);
+        // 16-wide MFMA (FP32 for every precision, like the other small-shape forms).
+        case kVarMfma16: return (d.n % 16 == 0 || d.n == 8) && d.m % 16 == 0 && d.k % 4 == 0 && d.k >= 4;
+        case kVarMfma16T: return (d.m % 16 == 0 || d.m == 8) && d.n % 16 == 0 && d.k % 4 == 0 && d.k >= 4;
         case kVarDot: return d.k >= 256 && d.nb * d.m * d.n <= 65536;
         case kVarMfma11: case kVarMfma12: case kVarMfma21: case kVarMfma22: {
             const int wm = (v == kVarMfma21 || v == kVarMfma22) ? 2 : 1, wn = (v == kVarMfma12 || v == kVarMfma22) ? 2 : 1;
@@ -1291,7 +1382,8 @@ bool gemm_variant_ok(const GemmDesc &d, int v) {
         // The large-tile and tile forms stage k in groups of 8 (load8).
         case kVarSplitBig: return split && d.k % 8 == 0 && d.m % 128 == 0 && d.n % 128 == 0;
         case kVarMfmaBig: return !split && d.k % 8 == 0 && d.m % 128 == 0 && d.n % 128 == 0;
-        case kVarT256x64: case kVarT64x256: case kVarT32x256: case kVarT256x32: case kVarT128x64: case kVarT64x128: {
+        case kVarT256x64: case kVarT64x256: case kVarT32x256: case kVarT256x32: case kVarT128x64: case kVarT64x128:
+        case kVarT128x32: case kVarT32x128: {
             int tm = 0, tn = 0;
             tile_dims(v, tm, tn);
             return !split && d.k % 8 == 0 && d.m % tm == 0 && d.n % tn == 0;
@@ -1307,6 +1399,16 @@ bool gemm_variant_ok(const GemmDesc &d, int v) {
 int gemm_default_variant(const GemmDesc &d) {
     if (d.prec != kPrecC64 && gemm_variant_ok(d, kVarSplitBig)) return kVarSplitBig;
     if (d.prec == kPrecC64 && gemm_variant_ok(d, kVarMfmaBig)) return kVarMfmaBig;
+    // Tall or wide shapes with a 32- or 64-wide side (measured fastest on
+    // such steps of the 70-qubit workload).
+    if (d.prec == kPrecC64 && d.m >= 1024) {
+        if (d.n == 64 && gemm_variant_ok(d, kVarT128x64)) return kVarT128x64;
+        if (d.n == 32 && gemm_variant_ok(d, kVarT128x32)) return kVarT128x32;
+    }
+    if (d.prec == kPrecC64 && d.n >= 1024 && d.m == 32 && gemm_variant_ok(d, kVarT32x128)) return kVarT32x128;
+    // A 16-wide side with a long other one: one 16x16 MFMA tile per wave.
+    if (d.n == 16 && d.m >= 256 && gemm_variant_ok(d, kVarMfma16)) return kVarMfma16;
+    if (d.m == 16 && d.n >= 256 && gemm_variant_ok(d, kVarMfma16T)) return kVarMfma16T;
     const int wm = d.m % 64 == 0 ? 2 : 1, wn = d.n % 64 == 0 ? 2 : 1;
     if (d.prec != kPrecC64) {
         const int v = wm == 2 ? (wn == 2 ? kVarSplit22 : kVarSplit21) : (wn == 2 ? kVarSplit12 : kVarSplit11);
@@ -1418,7 +1520,18 @@ const char *launch_big(const GemmDesc &d, int v, hipStream_t st) {
         hipLaunchKernelGGL(gemm_dot_tile_kernel, dim3(g), dim3(256), 0, st, d);
         return "gemm_dot_tile";
     }
-    if (v >= kVarT256x64 && v <= kVarT64x128) {
+    if (v == kVarMfma16 || v == kVarMfma16T) {
+        const GemmDesc e = v == kVarMfma16T ? transposed(d) : d;
+        const int64_t tiles = e.nb * (e.m / 16) * (e.n % 16 == 0 ? e.n / 16 : 1);
+        const int64_t blocks = (tiles + 3) / 4, cap = 8 * int64_t(device_cus());
+        const unsigned gb = (unsigned)(blocks < cap ? blocks : cap);
+        if (e.n % 16 == 0)
+            hipLaunchKernelGGL(gemm_mfma16_kernel<16>, dim3(gb), dim3(256), 0, st, e);
+        else
+            hipLaunchKernelGGL(gemm_mfma16_kernel<8>, dim3(gb), dim3(256), 0, st, e);
+        return "gemm_mfma";
+    }
+    if (v >= kVarT256x64 && v <= kVarT32x128) {
         int tm = 0, tn = 0;
         tile_dims(v, tm, tn);
         // Persistent blocks, two per compute unit.
@@ -1430,7 +1543,9 @@ const char *launch_big(const GemmDesc &d, int v, hipStream_t st) {
             case kVarT32x256: hipLaunchKernelGGL((gemm_mfma_tile_kernel<1, 2, 1, 4>), dim3(gt), dim3(256), 0, st, d); break;
             case kVarT256x32: hipLaunchKernelGGL((gemm_mfma_tile_kernel<2, 1, 4, 1>), dim3(gt), dim3(256), 0, st, d); break;
             case kVarT128x64: hipLaunchKernelGGL((gemm_mfma_tile_kernel<2, 1, 2, 2>), dim3(gt), dim3(256), 0, st, d); break;
-            default: hipLaunchKernelGGL((gemm_mfma_tile_kernel<1, 2, 2, 2>), dim3(gt), dim3(256), 0, st, d); break;
+            case kVarT64x128: hipLaunchKernelGGL((gemm_mfma_tile_kernel<1, 2, 2, 2>), dim3(gt), dim3(256), 0, st, d); break;
+            case kVarT128x32: hipLaunchKernelGGL((gemm_mfma_tile_kernel<1, 1, 4, 1>), dim3(gt), dim3(256), 0, st, d); break;
+            default: hipLaunchKernelGGL((gemm_mfma_tile_kernel<1, 1, 1, 4>), dim3(gt), dim3(256), 0, st, d); break;
         }
         return "gemm_mfma";
     }
@@ -1498,6 +1613,7 @@ const char *launch_gemm_variant(const GemmDesc &d, int v, hipStream_t st) {
             }
         case kVarMfmaBig: case kVarSplitBig:
         case kVarT256x64: case kVarT64x256: case kVarT32x256: case kVarT256x32: case kVarT128x64: case kVarT64x128:
+        case kVarT128x32: case kVarT32x128: case kVarMfma16: case kVarMfma16T:
             if (d.kparts > 1) return launch_gemm_kparts(d, v, st);
             return launch_big(d, v, st);
         case kVarDot: case kVarDotTile:

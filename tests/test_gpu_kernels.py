@@ -260,7 +260,11 @@ EXACT_FORMS = [
     ("mfma_big", 1, 128, 256, 64, 1), ("mfma_big", 2, 128, 128, 8, 1), ("mfma_big", 1, 128, 128, 1024, 4),
     ("tile256x64", 2, 512, 64, 40, 1), ("tile64x256", 1, 64, 512, 16, 1), ("tile32x256", 3, 32, 256, 24, 1),
     ("tile256x32", 1, 256, 96, 64, 1), ("tile128x64", 2, 256, 64, 8, 1), ("tile64x128", 1, 128, 128, 512, 4),
-    ("tile32x256", 1, 64, 512, 256, 8),
+    ("tile32x256", 1, 64, 512, 256, 8), ("tile128x32", 2, 256, 96, 32, 1), ("tile32x128", 1, 96, 256, 8, 1),
+    ("tile128x32", 1, 128, 32, 2048, 4),
+    ("mfma16", 2, 64, 16, 64, 1), ("mfma16", 1, 32, 8, 20, 1), ("mfma16", 3, 48, 32, 12, 1), ("mfma16", 1, 16, 16, 8, 1),
+    ("mfma16", 4, 16, 16, 4096, 4), ("mfma16_t", 2, 16, 256, 64, 1), ("mfma16_t", 1, 8, 64, 36, 1),
+    ("mfma16_t", 2, 32, 48, 4, 1),
 ]
 
 

@@ -135,15 +135,21 @@ def test_diamond70_open_outputs_vs_o4():
     plan = qcsim.qc_plan_build(lat.n, circ, bs[0], log2_slices=20, log2_max_entries=30, greedy_trials=64, seed=1,
                                open_qubits=oq)
     k = qcsim.qc_plan_info(plan)["log2_slices"]
-    s0 = int(synth.random_slices(k, 1, spec["seed"] + 2)[0])
-    c0 = s0 - s0 % 16
+    # Most slices of this plan are exactly zero: chunks around slices drawn
+    # from the seed + 2 stream are tried in order until one holds a nonzero
+    # slice.
     vals = {}
-    for prec in ("c64", "split_fp16"):
-        say(f"70-qubit, 12 open outputs, slices [{c0}, {c0 + 16}) {prec}")
-        _, vals[prec] = _contract(plan, bs[:1], c0, c0 + 16, prec, chunk=16, per_slice=True)
-    v = vals["c64"][:, 0]
-    nz = [j for j in range(16) if np.abs(v[j]).max() > 0]
-    assert nz, "every slice of the chunk is zero"
+    for s0 in (int(s) for s in synth.random_slices(k, 64, spec["seed"] + 2)):
+        c0 = s0 - s0 % 16
+        say(f"70-qubit, 12 open outputs, slices [{c0}, {c0 + 16}) c64")
+        _, vals["c64"] = _contract(plan, bs[:1], c0, c0 + 16, "c64", chunk=16, per_slice=True)
+        v = vals["c64"][:, 0]
+        nz = [j for j in range(16) if np.abs(v[j]).max() > 0]
+        if nz:
+            break
+    assert nz, "every drawn chunk is zero"
+    say(f"70-qubit, 12 open outputs, slices [{c0}, {c0 + 16}) split_fp16")
+    _, vals["split_fp16"] = _contract(plan, bs[:1], c0, c0 + 16, "split_fp16", chunk=16, per_slice=True)
     j = nz[0]
     picks = list(np.argsort(-np.abs(v[j]))[:3]) + [int(synth.random_slices(12, 1, 7)[0])]
     tree = qcsim.qc_plan_export_tree(plan)
