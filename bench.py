@@ -246,8 +246,21 @@ def diamond_leg(steps, warmup, precs, chunk=None, cpu=True, tune_cache=None):
             leg["per_prec"][prec]["slice_err_vs_oracle"] = _slice_errors(vals[prec], ref, TOL[prec])
         med = float(np.median(secs))
         _say(f"70-qubit oracle: {med:.2f} s per slice")
+        # One host thread, for a per-core figure (the paper quotes per-vCPU
+        # work): two slices of the same chunk.
+        n_threads = torch.get_num_threads()
+        torch.set_num_threads(1)
+        t1 = time.perf_counter()
+        for s in range(c0, c0 + 2):
+            oracle.hyper_value(lat.n, circ, bs[0], segs, s, tree)
+        one = (time.perf_counter() - t1) / 2
+        torch.set_num_threads(n_threads)
+        _say(f"70-qubit oracle, one thread: {one:.2f} s per slice")
         leg["cpu_oracle"] = dict(seconds_per_slice=med, projected_s_per_amplitude=med * float(1 << k), **_cpu_info(),
-                                 sample=f"O4 on the {chunk} slices of the timed chunk ({sum(secs):.1f} s)")
+                                 seconds_per_slice_one_thread=one,
+                                 projected_core_s_per_amplitude=one * float(1 << k),
+                                 sample=f"O4 on the {chunk} slices of the timed chunk ({sum(secs):.1f} s); one "
+                                        f"thread: 2 of them")
     return leg
 
 
@@ -700,6 +713,7 @@ def main():
         c = head["cpu_oracle"]
         result["cpu_baseline"] = {"value": 1.0 / c["projected_s_per_amplitude"], "unit": "amplitudes/s",
                                   "cores": c["cores"], "kind": "oracle", "cpu_model": c["cpu_model"],
+                                  "one_thread_value": 1.0 / (c["seconds_per_slice_one_thread"] * float(1 << head["log2_slices"])),
                                   "sample": c["sample"] + f", median {c['seconds_per_slice']:.2f} s per slice x "
                                                           f"2^{head['log2_slices']} slices (projection)"}
     for prec, r in head["per_prec"].items():

@@ -1634,14 +1634,14 @@ extern "C" qc_status qc_tune(qc_plan *plan, int64_t chunk_slices, int32_t n_bs, 
             if (it == qc::g_tune.end()) {
                 int best = -1;
                 float best_ms = 0.f;
-                // Forms without matrix cores are not timed on large steps that
-                // an MFMA form can take.
+                // The one-thread-per-output vector form is not timed on large
+                // steps that an MFMA form can take (it is far slower there).
                 bool mfma_ok = false;
                 for (int v = qc::kVarMfma11; v < qc::kVarCount; ++v) mfma_ok |= qc::gemm_variant_ok(d, v);
                 const double flops = 8.0 * double(d.nb) * double(d.m) * double(d.n) * double(d.k);
                 for (int v = 0; v < qc::kVarCount; ++v) {
                     if (!qc::gemm_variant_ok(d, v)) continue;
-                    if (mfma_ok && flops > 1e8 && v < qc::kVarMfma11) continue;
+                    if (mfma_ok && flops > 1e8 && v == qc::kVarValu) continue;
                     qc::launch_gemm_variant(d, v, st);  // warm-up
                     float ms = 0.f;
                     if (hipEventRecord(e0, st) != hipSuccess) { status = QC_ERR_DEVICE; break; }

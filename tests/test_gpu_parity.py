@@ -505,3 +505,29 @@ def test_fused_block_sums_compose_across_super_chunks():
     qcsim.qc_plan_set_fused_slice_bits(plan0, 0)
     b0 = _contract(plan0, xs, 0, 256, ws_bytes=qcsim.qc_workspace_bytes(plan0, 64, len(xs)))
     assert np.abs(b0 - whole).max() <= TOL_C64 * np.abs(whole).max()
+
+
+def test_fused_program_with_many_levels():
+    # A 1x220 chain at depth 1+10+1: the plan's tree is 69 levels deep, so
+    # the fused kernel reads its level starts from memory (programs of 64
+    # levels or more) instead of from lanes.  32 bitstrings in the fused
+    # form against O4 (the oracle's network along the plan's tree).
+    lat = synth.grid(1, 220)
+    circ = synth.random_circuit(lat, 10, 5)
+    plan = qcsim.qc_plan_build(lat.n, circ, None, log2_slices=2, greedy_trials=1, seed=1)
+    desc = qcsim.qc_plan_describe(plan, 0, 0)
+    lvl, deepest = {leaf["tensor"]: 0 for leaf in desc["leaves"]}, 0
+    for op in desc["ops"]:
+        if op["op"] == "gemm":
+            lvl[op["c"]] = 1 + max(lvl[op["a_src"]], lvl[op["b_src"]])
+            deepest = max(deepest, lvl[op["c"]])
+    assert deepest >= 64
+    qcsim.qc_plan_set_exec(plan, "fused")
+    xs = synth.random_bitstrings(lat.n, 32, 6)
+    say(f"fused program with {deepest} levels, 1x220 d10, 32 bitstrings")
+    got = _contract(plan, xs, 0, 4)
+    tree = qcsim.qc_plan_export_tree(plan)
+    segs = qcsim.qc_plan_sliced_segments(plan)
+    ref = np.array([sum(oracle.hyper_value(lat.n, circ, x, segs, s, tree) for s in range(4)) for x in xs])
+    assert (np.abs(ref) > 0).sum() >= 8
+    check_amplitudes(got, ref, lat.n, TOL_C64)
