@@ -111,6 +111,15 @@ def _kernel_table(prof, steps):
             for kk, v in prof.items()}
 
 
+def _split_share(prof):
+    """Share of the GEMM steps' algorithmic flops that ran on 16-bit MFMA
+    (split kinds); the rest ran in complex FP32 (smaller steps, and steps the
+    tuner measured faster in FP32)."""
+    gemm = sum(v[2] for kk, v in prof.items() if kk.startswith("gemm") or kk == "micro")
+    split = sum(v[2] for kk, v in prof.items() if kk.startswith("gemm_split"))
+    return split / gemm if gemm > 0 else None
+
+
 def _cpu_info():
     import torch
     model = ""
@@ -222,6 +231,7 @@ def diamond_leg(steps, warmup, precs, chunk=None, cpu=True, tune_cache=None):
             "projected_s_per_amplitude": ms * 1e-3 * float(1 << k) / chunk,
             "tflops_alg": flops_step / (ms * 1e-3) / 1e12, "ms_per_step_profiled": ms_prof,
             "kernels": _kernel_table(prof, n_prof), "roofline": _roofline(prof, prec, "diamond70_d32"),
+            "gemm_flop_share_16bit": _split_share(prof),
             "tune_seconds": tune_s, "shapes_timed": n_timed}
         _say(f"70-qubit {prec}: {ms:.2f} ms per {chunk} slices")
         del ws
@@ -294,8 +304,20 @@ def open_leg(steps=3, warmup=1, precs=("c64", "split_fp16"), cpu=True):
     A = 1 << m
     out = torch.zeros(1, A, 2, dtype=torch.float64, device="cuda")
     ps = torch.zeros(chunk, 1, A, 2, dtype=torch.float64, device="cuda")
-    s0 = int(synth.random_slices(k, 1, spec["seed"] + 2)[0])
-    c0 = s0 - s0 % chunk
+    # The timed chunk: the first chunk around a slice drawn from the seed + 2
+    # stream that holds a nonzero slice (most slices of this plan are exact
+    # zeros; the time does not depend on the values).
+    ws = torch.empty(qcsim.qc_workspace_bytes(plan, chunk, 1, "c64"), dtype=torch.uint8, device="cuda")
+    c0 = None
+    for s in synth.random_slices(k, 16, spec["seed"] + 2):
+        c = int(s) - int(s) % chunk
+        qcsim.qc_contract_slices_dev(plan, c, c + chunk, bits, "c64", ws, out, ps, stream=stream)
+        torch.cuda.synchronize()
+        c0 = c if c0 is None else c0
+        if ps.abs().max().item() > 0:
+            c0 = c
+            break
+    del ws
     leg = {"workload": (f"{spec['name']}: the 70-qubit diamond at depth 1+{spec['depth']}+1 (seed {spec['seed']}, "
                         f"bitstring seed {spec['seed'] + 1}) with the outputs of qubits {oq[0]}..{oq[-1]} open; "
                         f"2^{k} slices (cap 2^{spec['log2_cap']}), {chunk} slices [{c0}, {c0 + chunk}) per step, "
@@ -329,7 +351,8 @@ def open_leg(steps=3, warmup=1, precs=("c64", "split_fp16"), cpu=True):
             "projected_amplitudes_per_s": A * chunk / (ms * 1e-3) / float(1 << k),
             "projected_s_per_amplitude": ms * 1e-3 * float(1 << k) / chunk / A,
             "tflops_alg": info["flops_per_slice"] * chunk / (ms * 1e-3) / 1e12, "ms_per_step_profiled": ms_prof,
-            "kernels": _kernel_table(prof, 1), "roofline": _roofline(prof, prec, "diamond70_d32_open16")}
+            "kernels": _kernel_table(prof, 1), "roofline": _roofline(prof, prec, "diamond70_d32_open16"),
+            "gemm_flop_share_16bit": _split_share(prof)}
         _say(f"70-qubit open {prec}: {ms:.1f} ms per {chunk} slices")
         del ws
     c64 = leg["per_prec"].get("c64")
@@ -639,6 +662,86 @@ def batch_leg(n_req=256, seed=501, cap=24, reps=3, n_oracle=6, trials=32, precs=
     return leg
 
 
+def _headline_program(prec):
+    """The 70-qubit plan and its 64-slice program's step list (host only)."""
+    import synth
+    from paper_1907_11217_amd import qcsim
+
+    lat, circ, bs, spec = synth.config("c4")
+    plan = qcsim.qc_plan_build(lat.n, circ, bs[0], log2_slices=spec["log2_slices"], log2_max_entries=spec["log2_cap"],
+                               greedy_trials=spec["trials"], seed=spec["plan_seed"])
+    b = spec["chunk"].bit_length() - 1
+    return qcsim.qc_plan_export_steps(plan, b, 0), qcsim.qc_plan_describe(plan, b, 0, prec)
+
+
+def trace_summary(path, prec):
+    """Per-step table of the last complete 64-slice call in a rocprofv3
+    kernel trace (CSV) of the 70-qubit workload: each launch matched to its
+    step in program order, with the step's shape, kernel, time and the time
+    its algorithmic flops and bytes take at the chip's peaks."""
+    import csv
+    rows = sorted(csv.DictReader(open(path)), key=lambda r: int(r["Start_Timestamp"]))
+    names = [r["Kernel_Name"] for r in rows]
+    i0 = max(i for i, nm in enumerate(names) if "leaf_kernel" in nm)
+    if i0 > 0 and "zero_u32" in names[i0 - 1]:
+        i0 -= 1
+    i1 = next(i for i in range(i0, len(names)) if "reduce64" in names[i] or "block_add" in names[i])
+    call = rows[i0:i1 + 1]
+    steps, desc = _headline_program(prec)
+    peak_f = PEAK_MFMA_TFLOPS[prec] * 1e12
+    dur = lambda r: (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3
+    k = next(i for i, r in enumerate(call) if "micro_kernel" in r["Kernel_Name"]) + 1
+    lines, tot, roof_tot = [], 0.0, 0.0
+    for i, st in enumerate(steps):
+        if st["micro"]:
+            continue
+        r = call[k]
+        k += 1
+        t = dur(r)
+        if k < len(call) and "ksum" in call[k]["Kernel_Name"]:
+            t += dur(call[k])
+            k += 1
+        if st["kind"] == 0:
+            by = 16.0 * st["m"]
+            roof = by / (PEAK_HBM_GBS * 1e9) * 1e6
+            shape = f"transpose 2^{st['m'].bit_length() - 1}"
+        else:
+            nb, m, n, kk = st["nb"], st["m"], st["n"], st["k"]
+            f = 8.0 * nb * m * n * kk
+            by = 8.0 * nb * (m * kk + kk * n + m * n)
+            hw = HW_PER_ALG[prec] if "split" in r["Kernel_Name"] else 1.0
+            pf = peak_f if "split" in r["Kernel_Name"] or prec == "c64" else PEAK_FP32_TFLOPS * 1e12
+            roof = max(f * hw / pf, by / (PEAK_HBM_GBS * 1e9)) * 1e6
+            op = desc["ops"][i]
+            shape = f"{nb}x{m}x{n}x{kk}{' scat' if op['c_nat'] != op['c'] else ''}"
+        name = r["Kernel_Name"].replace("void ", "").replace("qc::", "").split("(")[0]
+        lines.append(f"  {i:4d} {shape:32s} {name[:44]:44s} {t:9.1f} us  roof {roof:8.1f} us  {roof / t:6.1%}")
+        tot += t
+        roof_tot += roof
+    span = (int(call[-1]["End_Timestamp"]) - int(call[0]["Start_Timestamp"])) * 1e-3
+    print(f"  step shape (nb x m x n x k)               kernel                                        time        "
+          f"roofline (peaks: {PEAK_MFMA_TFLOPS[prec]:.1f} TFLOP/s, {PEAK_HBM_GBS / 1e3:.0f} TB/s)")
+    print("\n".join(lines))
+    print(f"  steps {tot / 1e3:.2f} ms, their roofline {roof_tot / 1e3:.2f} ms ({roof_tot / tot:.1%}); "
+          f"whole call {span / 1e3:.2f} ms")
+
+
+def pmc_summary(path, calls):
+    """Per-kernel sums of every counter in a rocprofv3 counter-collection CSV,
+    divided by the number of contraction calls in the traced process."""
+    import csv
+    from collections import defaultdict
+    agg = defaultdict(lambda: defaultdict(float))
+    n = defaultdict(set)
+    for r in csv.DictReader(open(path)):
+        name = r["Kernel_Name"].replace("void ", "").replace("qc::", "").split("(")[0]
+        agg[name][r["Counter_Name"]] += float(r["Counter_Value"])
+        n[name].add(r["Dispatch_Id"])
+    for name in sorted(agg, key=lambda x: -len(n[x])):
+        vals = ", ".join(f"{c} {v / calls:.6g}" for c, v in sorted(agg[name].items()))
+        print(f"  {name[:48]:48s} dispatches/call {len(n[name]) / calls:7.2f}  per call: {vals}")
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -655,10 +758,23 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="skip the 4x4, 5x5, 7x7 and request-batch legs")
     ap.add_argument("--leg", choices=["grid5x5_d16", "grid7x7_d24", "request_batch", "diamond70_d32_open16"],
                     help="run only this leg and print its JSON (for profiling runs)")
+    ap.add_argument("--trace-summary", metavar="CSV",
+                    help="print the per-step table of a rocprofv3 kernel trace of the 70-qubit workload "
+                         "(host only: rebuilds the plan to match launches to steps) and exit")
+    ap.add_argument("--pmc-summary", metavar="CSV",
+                    help="print per-kernel counter sums of a rocprofv3 counter-collection CSV, divided by "
+                         "--calls, and exit")
+    ap.add_argument("--calls", type=int, default=1, help="contraction calls in the traced process (--pmc-summary)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 256 MiB device to device 5 times (the plain-copy reference of the "
                          "FETCH_SIZE / WRITE_SIZE counter runs)")
     args = ap.parse_args()
+    if args.trace_summary:
+        trace_summary(args.trace_summary, args.prec)
+        return
+    if args.pmc_summary:
+        pmc_summary(args.pmc_summary, args.calls)
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}): it measures one "

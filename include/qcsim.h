@@ -80,7 +80,9 @@ typedef struct {
  * nearest even) and accumulate hi*hi + hi*lo + lo*hi in FP32 on MFMA; the
  * power-of-two scale d is 0 for BF16 and, for FP16, floor(log2 max|x|) - 14
  * over the tensor instance of the current chunk, with max|x| recorded by the
- * kernel that wrote the tensor.  Smaller steps stay complex FP32.  The split
+ * kernel that wrote the tensor.  Smaller steps stay complex FP32, and after
+ * qc_tune any step may run in complex FP32 where that form measured faster
+ * (never less accurate; the kernel statistics name each launch's form).  The split
  * forms always run stepwise (see qc_plan_set_exec).  The cross-slice sum is
  * FP64 in every case. */
 typedef enum {

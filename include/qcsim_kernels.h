@@ -43,23 +43,24 @@ qc_status qc_kernel_gemm(const void *A, const void *B, void *C, int64_t nb, int6
 /* qc_kernel_gemm with the kernel form fixed (the choices qc_tune times):
  *   0 vector ALU (any shape), 1 skinny (m in {1,2,4,8,16}, n >= 64),
  *   2 dot (k >= 256, nb m n <= 65536), 3..6 complex FP32 MFMA with block
- *   tiles 32x32, 32x64, 64x32, 64x64 (QC_C64; k in {2,4,8} or a multiple of
- *   16), 7 split 128x128 (k a multiple of 8), 8..11 split 32x32, 32x64, 64x32, 64x64 (split
- *   precisions, k >= 2), 12 complex FP32 MFMA 128x128 (QC_C64, k a multiple of 8, m and n
- *   multiples of 128), 13 skinny on the transposed product (n in
+ *   tiles 32x32, 32x64, 64x32, 64x64 (k in {2,4,8} or a multiple of 16),
+ *   7 split 128x128 (split precisions, k a multiple of 8), 8..11 split 32x32,
+ *   32x64, 64x32, 64x64 (split precisions, k >= 2), 12 complex FP32 MFMA
+ *   128x128 (k a multiple of 8, m and n multiples of 128), 13 skinny on the
+ *   transposed product (n in
  *   {1,2,4,8,16}, m >= 64), 14 dot tile (m n <= 256, k >= 64: one workgroup
  *   per batch entry's whole tile, k staged through LDS), 15 rows (n in
  *   {1,2,4,8,16}, m >= 64: one row of C per thread, B in LDS), 16..23
  *   complex FP32 MFMA with tall or wide tiles 256x64, 64x256, 32x256, 256x32,
- *   128x64, 64x128, 128x32, 32x128 (QC_C64, k a multiple of 8, m and n
- *   multiples of the tile: the
+ *   128x64, 64x128, 128x32, 32x128 (k a multiple of 8, m and n multiples of
+ *   the tile: the
  *   128x128 form's double-buffered slabs for shapes with one short output
  *   dimension), 24 16-wide MFMA (n = 8 or a multiple of 16, m a multiple of
  *   16, k a multiple of 4: one 16x16 tile per wave on
  *   v_mfma_f32_16x16x4_f32, operands read straight into registers), 25 the
  *   same on the transposed product (m = 8 or a multiple of 16, n a multiple
- *   of 16); form -1 is the default choice.  Forms 0..2, 13..15, 24 and 25
- *   compute in FP32 for every
+ *   of 16); form -1 is the default choice.  Every form but 7..11 computes
+ *   in complex FP32 for every
  *   precision.  QC_ERR_UNSUPPORTED if the form does not apply to the shape and
  *   precision. */
 qc_status qc_kernel_gemm_form(const void *A, const void *B, void *C, int64_t nb, int64_t m, int64_t n, int64_t k,

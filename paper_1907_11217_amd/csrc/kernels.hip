@@ -649,6 +649,7 @@ __global__ void __launch_bounds__(64 * WM * WN) gemm_mfma_kernel(GemmDesc d) {
     const int64_t n_tiles = d.nb * tiles_m * tiles_n;
     const bool a_k_fast = d.sAk == 1;
     const bool b_n_fast = d.sBn == 1;
+    float mx = 0.f;  // max(|re|, |im|) written, folded into amax_c when the program tracks it
     for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
         const int64_t tn = tile % tiles_n;
         const int64_t tm = (tile / tiles_n) % tiles_m;
@@ -691,8 +692,12 @@ __global__ void __launch_bounds__(64 * WM * WN) gemm_mfma_kernel(GemmDesc d) {
         }
         const CBlock cb = c_block(d, bi, tm * TM + wm * 32, tn * TN + wn * 32, lane);
 #pragma unroll
-        for (int v = 0; v < 16; ++v) *c_at(cb, v) = make_float2(acc_re[v], acc_im[v]);
+        for (int v = 0; v < 16; ++v) {
+            *c_at(cb, v) = make_float2(acc_re[v], acc_im[v]);
+            mx = fmaxf(mx, fmaxf(fabsf(acc_re[v]), fabsf(acc_im[v])));
+        }
     }
+    if (d.amax_c) block_amax(mx, d.amax_c);
 }
 
 // ------------------------------------------------ split-precision MFMA GEMM
@@ -1011,6 +1016,10 @@ __device__ __forceinline__ void store8_kmajor(float2 (*plane)[128], int row, int
     for (int q = 0; q < 8; ++q) plane[8 * half + q][row] = v[q];
 }
 
+// AMAX: also fold max(|re|, |im|) of the output into amax_c (split FP16
+// programs, whose later steps derive scales from it; a separate instance, as
+// the extra epilogue work costs the plain form its second wave per SIMD).
+template <bool AMAX>
 __global__ void __launch_bounds__(256) gemm_mfma_big_kernel(GemmDesc d) {
     constexpr int TM = 128, TN = 128, KT = 16;
     __shared__ __attribute__((aligned(16))) float2 As[2][KT][TM];
@@ -1025,6 +1034,7 @@ __global__ void __launch_bounds__(256) gemm_mfma_big_kernel(GemmDesc d) {
     const bool a_vec = a_kc && d.sAm % 2 == 0 && d.sAb % 2 == 0 && d.sAp % 2 == 0 && (uintptr_t)d.A % 16 == 0;
     const bool b_vec = b_kc && d.sBn % 2 == 0 && d.sBb % 2 == 0 && d.sBp % 2 == 0 && (uintptr_t)d.B % 16 == 0;
     const int n_slabs = int((d.k + KT - 1) / KT);
+    float mx = 0.f;  // max(|re|, |im|) written, folded into amax_c when the program tracks it
     int64_t first = blockIdx.x;
     if (gridDim.x % 8 == 0) first = int64_t(blockIdx.x % 8) * (gridDim.x / 8) + blockIdx.x / 8;
     for (int64_t tile = first; tile < n_tiles; tile += gridDim.x) {
@@ -1090,9 +1100,13 @@ __global__ void __launch_bounds__(256) gemm_mfma_big_kernel(GemmDesc d) {
             for (int j = 0; j < 2; ++j) {
                 const CBlock cb = c_block(d, bi, tm * TM + wm * 64 + i * 32, tn * TN + wn * 64 + j * 32, lane);
 #pragma unroll
-                for (int v = 0; v < 16; ++v) *c_at(cb, v) = make_float2(acc[i][j][0][v], acc[i][j][1][v]);
+                for (int v = 0; v < 16; ++v) {
+                    *c_at(cb, v) = make_float2(acc[i][j][0][v], acc[i][j][1][v]);
+                    if (AMAX) mx = fmaxf(mx, fmaxf(fabsf(acc[i][j][0][v]), fabsf(acc[i][j][1][v])));
+                }
             }
     }
+    if (AMAX && d.amax_c) block_amax(mx, d.amax_c);
 }
 
 // Tall and wide tile forms of the complex FP32 MFMA product: the large-tile
@@ -1104,7 +1118,7 @@ __global__ void __launch_bounds__(256) gemm_mfma_big_kernel(GemmDesc d) {
 // short output dimension and a short k (a long panel streamed past a small
 // operand) fill the chip with these tiles where 128 x 128 tiles do not fit.
 // Each thread stages up to PA (PB) groups of 8 consecutive k of one row.
-template <int BM, int BN, int WGM, int WGN>
+template <int BM, int BN, int WGM, int WGN, bool AMAX>
 __global__ void __launch_bounds__(256) gemm_mfma_tile_kernel(GemmDesc d) {
     static_assert(WGM * WGN == 4, "four waves");
     constexpr int TM = 32 * BM * WGM, TN = 32 * BN * WGN, KT = 16;
@@ -1137,6 +1151,7 @@ __global__ void __launch_bounds__(256) gemm_mfma_tile_kernel(GemmDesc d) {
         bh[p] = b_kc ? (q & 1) : (q / TN) & 1;
     }
     const int n_slabs = int((d.k + KT - 1) / KT);
+    float mx = 0.f;  // max(|re|, |im|) written, folded into amax_c when the program tracks it
     // Operand panels of a tile (batch entry, rows, columns).
     auto panels = [&](int64_t tile, const float2 *&Ab, const float2 *&Bb, int64_t &bi, int64_t &tm, int64_t &tn) {
         tn = tile % tiles_n;
@@ -1233,7 +1248,10 @@ __global__ void __launch_bounds__(256) gemm_mfma_tile_kernel(GemmDesc d) {
             for (int j = 0; j < BN; ++j) {
                 const CBlock cb = c_block(d, bi, tm * TM + wm * 32 * BM + i * 32, tn * TN + wn * 32 * BN + j * 32, lane);
 #pragma unroll
-                for (int v = 0; v < 16; ++v) *c_at(cb, v) = make_float2(acc[i][j][0][v], acc[i][j][1][v]);
+                for (int v = 0; v < 16; ++v) {
+                    *c_at(cb, v) = make_float2(acc[i][j][0][v], acc[i][j][1][v]);
+                    if (AMAX) mx = fmaxf(mx, fmaxf(fabsf(acc[i][j][0][v]), fabsf(acc[i][j][1][v])));
+                }
             }
         if (next >= n_tiles) break;
         tile = next;
@@ -1241,6 +1259,7 @@ __global__ void __launch_bounds__(256) gemm_mfma_tile_kernel(GemmDesc d) {
         tm = (tile / tiles_n) % tiles_m;
         bi = tile / (tiles_n * tiles_m);
     }
+    if (AMAX && d.amax_c) block_amax(mx, d.amax_c);
 }
 
 // 16-wide MFMA form for a short output dimension (n = 8 or a multiple of 16)
@@ -1375,18 +1394,20 @@ bool gemm_variant_ok(const GemmDesc &d, int v) {
         case kVarMfma16: return (d.n % 16 == 0 || d.n == 8) && d.m % 16 == 0 && d.k % 4 == 0 && d.k >= 4;
         case kVarMfma16T: return (d.m % 16 == 0 || d.m == 8) && d.n % 16 == 0 && d.k % 4 == 0 && d.k >= 4;
         case kVarDot: return d.k >= 256 && d.nb * d.m * d.n <= 65536;
+        // Complex FP32 MFMA forms (any precision: a split program's step may
+        // run in FP32 where the tuner measured it faster).
         case kVarMfma11: case kVarMfma12: case kVarMfma21: case kVarMfma22: {
             const int wm = (v == kVarMfma21 || v == kVarMfma22) ? 2 : 1, wn = (v == kVarMfma12 || v == kVarMfma22) ? 2 : 1;
-            return !split && k_fp32 && d.m % (32 * wm) == 0 && d.n % (32 * wn) == 0;
+            return k_fp32 && d.m % (32 * wm) == 0 && d.n % (32 * wn) == 0;
         }
         // The large-tile and tile forms stage k in groups of 8 (load8).
         case kVarSplitBig: return split && d.k % 8 == 0 && d.m % 128 == 0 && d.n % 128 == 0;
-        case kVarMfmaBig: return !split && d.k % 8 == 0 && d.m % 128 == 0 && d.n % 128 == 0;
+        case kVarMfmaBig: return d.k % 8 == 0 && d.m % 128 == 0 && d.n % 128 == 0;
         case kVarT256x64: case kVarT64x256: case kVarT32x256: case kVarT256x32: case kVarT128x64: case kVarT64x128:
         case kVarT128x32: case kVarT32x128: {
             int tm = 0, tn = 0;
             tile_dims(v, tm, tn);
-            return !split && d.k % 8 == 0 && d.m % tm == 0 && d.n % tn == 0;
+            return d.k % 8 == 0 && d.m % tm == 0 && d.n % tn == 0;
         }
         case kVarSplit11: case kVarSplit12: case kVarSplit21: case kVarSplit22: {
             const int wm = (v == kVarSplit21 || v == kVarSplit22) ? 2 : 1, wn = (v == kVarSplit12 || v == kVarSplit22) ? 2 : 1;
@@ -1537,22 +1558,33 @@ const char *launch_big(const GemmDesc &d, int v, hipStream_t st) {
         // Persistent blocks, two per compute unit.
         const int64_t tiles = d.nb * (d.m / tm) * (d.n / tn), cap = 2 * int64_t(device_cus());
         const unsigned gt = (unsigned)(tiles < cap ? tiles : cap);
+#define QC_TILE(BM, BN, WGM, WGN)                                                                          \
+    do {                                                                                                   \
+        if (d.amax_c)                                                                                      \
+            hipLaunchKernelGGL((gemm_mfma_tile_kernel<BM, BN, WGM, WGN, true>), dim3(gt), dim3(256), 0, st, d);  \
+        else                                                                                               \
+            hipLaunchKernelGGL((gemm_mfma_tile_kernel<BM, BN, WGM, WGN, false>), dim3(gt), dim3(256), 0, st, d); \
+    } while (0)
         switch (v) {
-            case kVarT256x64: hipLaunchKernelGGL((gemm_mfma_tile_kernel<2, 2, 4, 1>), dim3(gt), dim3(256), 0, st, d); break;
-            case kVarT64x256: hipLaunchKernelGGL((gemm_mfma_tile_kernel<2, 2, 1, 4>), dim3(gt), dim3(256), 0, st, d); break;
-            case kVarT32x256: hipLaunchKernelGGL((gemm_mfma_tile_kernel<1, 2, 1, 4>), dim3(gt), dim3(256), 0, st, d); break;
-            case kVarT256x32: hipLaunchKernelGGL((gemm_mfma_tile_kernel<2, 1, 4, 1>), dim3(gt), dim3(256), 0, st, d); break;
-            case kVarT128x64: hipLaunchKernelGGL((gemm_mfma_tile_kernel<2, 1, 2, 2>), dim3(gt), dim3(256), 0, st, d); break;
-            case kVarT64x128: hipLaunchKernelGGL((gemm_mfma_tile_kernel<1, 2, 2, 2>), dim3(gt), dim3(256), 0, st, d); break;
-            case kVarT128x32: hipLaunchKernelGGL((gemm_mfma_tile_kernel<1, 1, 4, 1>), dim3(gt), dim3(256), 0, st, d); break;
-            default: hipLaunchKernelGGL((gemm_mfma_tile_kernel<1, 1, 1, 4>), dim3(gt), dim3(256), 0, st, d); break;
+            case kVarT256x64: QC_TILE(2, 2, 4, 1); break;
+            case kVarT64x256: QC_TILE(2, 2, 1, 4); break;
+            case kVarT32x256: QC_TILE(1, 2, 1, 4); break;
+            case kVarT256x32: QC_TILE(2, 1, 4, 1); break;
+            case kVarT128x64: QC_TILE(2, 1, 2, 2); break;
+            case kVarT64x128: QC_TILE(1, 2, 2, 2); break;
+            case kVarT128x32: QC_TILE(1, 1, 4, 1); break;
+            default: QC_TILE(1, 1, 1, 4); break;
         }
+#undef QC_TILE
         return "gemm_mfma";
     }
     const int64_t t128 = d.nb * (d.m / 128) * (d.n / 128);
     const unsigned g = (unsigned)(t128 < 1048576 ? t128 : 1048576);
     if (v == kVarMfmaBig) {
-        hipLaunchKernelGGL(gemm_mfma_big_kernel, dim3(g), dim3(256), 0, st, d);
+        if (d.amax_c)
+            hipLaunchKernelGGL(gemm_mfma_big_kernel<true>, dim3(g), dim3(256), 0, st, d);
+        else
+            hipLaunchKernelGGL(gemm_mfma_big_kernel<false>, dim3(g), dim3(256), 0, st, d);
         return "gemm_mfma";
     }
     if (d.prec == kPrecFP16)
