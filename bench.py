@@ -403,7 +403,7 @@ def fused_leg(steps=50, warmup=10, cpu=True):
     lat, circ, bs, spec = synth.config("c2")
     n_bs = len(bs)
     plan = qcsim.qc_plan_build(lat.n, circ, bs[0], log2_slices=spec["log2_slices"], greedy_trials=spec["trials"],
-                               seed=spec["plan_seed"])
+                               seed=spec["plan_seed"], quick=spec.get("quick", False))
     n_slices = 1 << qcsim.qc_plan_info(plan)["log2_slices"]
     ws = torch.empty(qcsim.qc_workspace_bytes(plan, n_slices, n_bs), dtype=torch.uint8, device="cuda")
     out = torch.zeros(n_bs, 2, dtype=torch.float64, device="cuda")

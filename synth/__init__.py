@@ -9,13 +9,13 @@ of the method's arithmetic.
 from .rng import SplitMix64
 from .circuits import (
     GATE_H, GATE_SQRT_X, GATE_SQRT_Y, GATE_T, GATE_CZ, GATE_NAMES,
-    Lattice, grid, diamond70, cz_patterns, random_circuit, random_bitstrings,
+    Lattice, grid, diamond70, diamond72, cz_patterns, random_circuit, random_bitstrings,
     random_slices, config, request_mix, CONFIGS,
 )
 
 __all__ = [
     "SplitMix64", "GATE_H", "GATE_SQRT_X", "GATE_SQRT_Y", "GATE_T", "GATE_CZ",
-    "GATE_NAMES", "Lattice", "grid", "diamond70", "cz_patterns",
+    "GATE_NAMES", "Lattice", "grid", "diamond70", "diamond72", "cz_patterns",
     "random_circuit", "random_bitstrings", "random_slices", "config",
     "request_mix", "CONFIGS",
 ]

@@ -193,3 +193,24 @@ def test_batch_large_requests_match_o4():
             bound = TOL[prec] * max(abs(refs[i]), 2.0 ** (-n / 2))
             assert abs(got - refs[i]) <= bound, (i, r["family"], got, refs[i])
         del ws
+
+
+# ------------------------------------------------ 72 qubits with degree-1 qubits
+@pytest.mark.parametrize("prec", ["c64", "split_fp16"])
+def test_diamond72_slices_vs_o4(prec):
+    # The 72-qubit lattice whose corner qubits have one neighbour each, depth
+    # 1+24+1, 2^12 slices of at most 2^20 entries: the 64-slice chunk around
+    # a slice drawn from stream 413, every slice against O4.
+    lat = synth.diamond72()
+    circ = synth.random_circuit(lat, 24, 411)
+    bs = synth.random_bitstrings(lat.n, 1, 412)
+    plan = qcsim.qc_plan_build(lat.n, circ, bs[0], log2_slices=10, log2_max_entries=20, greedy_trials=8, seed=2)
+    k = qcsim.qc_plan_info(plan)["log2_slices"]
+    s0 = int(synth.random_slices(k, 1, 413)[0])
+    c0 = s0 - s0 % 64
+    say(f"72-qubit d24 slices [{c0}, {c0 + 64}) {prec}")
+    got, _ = _slice_values(plan, bs[0], c0, c0 + 64, prec, 64)
+    tree = qcsim.qc_plan_export_tree(plan)
+    segs = qcsim.qc_plan_sliced_segments(plan)
+    ref = [oracle.hyper_value(lat.n, circ, bs[0], segs, s, tree) for s in range(c0, c0 + 64)]
+    _check_slices(got, ref, TOL[prec], f"72-qubit d24 {prec}")

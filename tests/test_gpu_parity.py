@@ -97,8 +97,10 @@ def test_c1_qc_amplitude():
 
 @pytest.fixture(scope="module")
 def c2_setup():
+    # The benchmark's plan of this workload (quick search).
     lat, circ, bs, spec = synth.config("c2")
-    plan = qcsim.qc_plan_build(lat.n, circ, bs[0], log2_slices=spec["log2_slices"], greedy_trials=8, seed=1)
+    plan = qcsim.qc_plan_build(lat.n, circ, bs[0], log2_slices=spec["log2_slices"], greedy_trials=spec["trials"],
+                               seed=spec["plan_seed"], quick=spec["quick"])
     psi = oracle.statevector(lat.n, circ)
     ref = np.array([psi[oracle.index_of(x)] for x in bs])
     return lat, circ, bs, plan, ref

@@ -489,3 +489,35 @@ def test_quick_search_plan_matches_statevector():
     psi = oracle.statevector(lat.n, circ)
     ref = np.array([psi[oracle.index_of(x)] for x in bs[:2]])
     assert np.abs(total - ref).max() < 1e-13 * np.abs(ref).max()
+
+
+def test_diamond72_degree_one_qubits_program():
+    # The 72-qubit lattice with two degree-1 qubits (the 70-qubit lattice plus
+    # two qubits whose only neighbour is on it): 125 couplers, qubits 0 and 71
+    # with one coupler each.  At depth 1+24+1 (2^12 slices of at most 2^20
+    # entries) eight slices of the 4-slice program, run in one NaN-poisoned
+    # buffer, against O4 along the plan's tree.
+    lat = synth.diamond72()
+    pairs = {c for p in synth.cz_patterns(lat) for c in p}
+    assert lat.n == 72 and len(pairs) == 125
+    deg = np.zeros(lat.n, int)
+    for a, b in pairs:
+        deg[a] += 1
+        deg[b] += 1
+    assert sorted(np.flatnonzero(deg == 1).tolist()) == [0, 71] and deg.min() == 1
+    circ = synth.random_circuit(lat, 24, 411)
+    bs = synth.random_bitstrings(lat.n, 1, 412)
+    plan = qcsim.qc_plan_build(lat.n, circ, bs[0], log2_slices=10, log2_max_entries=20, greedy_trials=8, seed=2)
+    k = qcsim.qc_plan_info(plan)["log2_slices"]
+    desc = qcsim.qc_plan_describe(plan, 2, 0)
+    check_liveness(desc)
+    tree = qcsim.qc_plan_export_tree(plan)
+    segs = qcsim.qc_plan_sliced_segments(plan)
+    got, ref = [], []
+    for s in (int(v) for v in synth.random_slices(k, 8, 413)):
+        got.append(run_program(desc, bs[:1], s & ~3, check_einsum=False, flat=True)[s & 3, 0])
+        ref.append(oracle.hyper_value(lat.n, circ, bs[0], segs, s, tree))
+    got, ref = np.array(got), np.array(ref)
+    rms = np.sqrt(np.mean(np.abs(ref) ** 2))
+    assert (np.abs(ref) > 1e-6 * rms).sum() >= 2
+    assert (np.abs(got - ref) <= 1e-12 * np.maximum(np.abs(ref), rms)).all()
