@@ -726,6 +726,52 @@ def trace_summary(path, prec):
           f"whole call {span / 1e3:.2f} ms")
 
 
+def _kernel_name(raw):
+    """Readable kernel name: the trace's demangled form without the argument
+    list, or, for names the profiler left mangled (templates over the 16-bit
+    float types), the name with its template arguments spelled out."""
+    import re
+    m = re.match(r"_ZN2qc(\d+)", raw)
+    if not m:
+        return raw.replace("void ", "").replace("qc::", "").split("(")[0]
+    n = int(m.group(1))
+    name = raw[m.end():m.end() + n]
+    rest = raw[m.end() + n:]
+    args = []
+    if rest.startswith("I"):
+        for t in re.finditer(r"DF16_|DF16b|Li(\d+)E", rest):
+            args.append({"DF16_": "_Float16", "DF16b": "__bf16"}.get(t.group(0), t.group(1)))
+    return name + (f"<{', '.join(args)}>" if args else "")
+
+
+def trace_kernels(path):
+    """Per-kernel launches and time of the last complete contraction call in a
+    rocprofv3 kernel trace (CSV) of any workload: from its leaf launch to its
+    slice reduction."""
+    import csv
+    from collections import defaultdict
+    rows = sorted(csv.DictReader(open(path)), key=lambda r: int(r["Start_Timestamp"]))
+    names = [r["Kernel_Name"] for r in rows]
+    ends = [i for i, nm in enumerate(names) if "reduce64" in nm or "block_add" in nm]
+    i1 = ends[-1]
+    i0 = max(i for i in range(i1) if "leaf_kernel" in names[i])
+    if i0 > 0 and "zero_u32" in names[i0 - 1]:
+        i0 -= 1
+    call = rows[i0:i1 + 1]
+    agg = defaultdict(lambda: [0, 0.0])
+    for r in call:
+        nm = _kernel_name(r["Kernel_Name"])
+        agg[nm][0] += 1
+        agg[nm][1] += (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3
+    span = (int(call[-1]["End_Timestamp"]) - int(call[0]["Start_Timestamp"])) * 1e-3
+    busy = sum(v[1] for v in agg.values())
+    print(f"  last complete call: {len(call)} launches, {span / 1e3:.3f} ms from first start to last end, "
+          f"kernels busy {busy / 1e3:.3f} ms")
+    print(f"  {'kernel':52s} {'launches':>8s} {'total us':>11s} {'avg us':>9s} {'% busy':>7s}")
+    for nm, (n, t) in sorted(agg.items(), key=lambda kv: -kv[1][1]):
+        print(f"  {nm[:52]:52s} {n:8d} {t:11.1f} {t / n:9.1f} {t / busy:7.1%}")
+
+
 def pmc_summary(path, calls):
     """Per-kernel sums of every counter in a rocprofv3 counter-collection CSV,
     divided by the number of contraction calls in the traced process."""
@@ -761,6 +807,8 @@ def main():
     ap.add_argument("--trace-summary", metavar="CSV",
                     help="print the per-step table of a rocprofv3 kernel trace of the 70-qubit workload "
                          "(host only: rebuilds the plan to match launches to steps) and exit")
+    ap.add_argument("--trace-kernels", metavar="CSV",
+                    help="print per-kernel time of the last complete contraction call in a rocprofv3 kernel trace")
     ap.add_argument("--pmc-summary", metavar="CSV",
                     help="print per-kernel counter sums of a rocprofv3 counter-collection CSV, divided by "
                          "--calls, and exit")
@@ -771,6 +819,9 @@ def main():
     args = ap.parse_args()
     if args.trace_summary:
         trace_summary(args.trace_summary, args.prec)
+        return
+    if args.trace_kernels:
+        trace_kernels(args.trace_kernels)
         return
     if args.pmc_summary:
         pmc_summary(args.pmc_summary, args.calls)
