@@ -366,14 +366,81 @@ __global__ void __launch_bounds__(256) gemm_valu_kernel(GemmDesc d) {
 // keeping all m outputs of both columns in registers; A's m x k values are
 // staged in LDS as [k][m] (up to 32 KB per pass over k) and read as
 // broadcasts.  Sums run over k in increasing order.
+//
+// Output: run on the transposed product (or with a scattered C) a thread's
+// two columns are far from its neighbours', so for m <= 8, whole 512-column
+// chunks and C offsets that are sums of per-bit offsets, the chunk's m x 512
+// block is staged in LDS and written in the order of its offsets, as in the
+// rows form below (bits ranked by their position in C; thread t writes the
+// block's elements t, t + 256, ...).
 template <int M>
 __global__ void __launch_bounds__(256) gemm_skinny_kernel(GemmDesc d) {
     constexpr int KC = 4096 / M;
-    __shared__ float2 As[KC * M];
+    constexpr int MB = M == 1 ? 0 : M == 2 ? 1 : M == 4 ? 2 : M == 8 ? 3 : 4;  // log2 M
+    constexpr int RS = M + 1;                                                  // staged column stride (padded)
+    constexpr bool kStage = M <= 8;
+    constexpr int SM = kStage && 512 * RS > KC * M ? 512 * RS : KC * M;
+    constexpr int NJ = 2 * M;                                                  // elements per thread
+    __shared__ float2 sm[SM];
+    __shared__ int hi_row[NJ], hi_col[NJ];
+    __shared__ int64_t hi_off[NJ];
+    __shared__ int s_pos[9 + MB], s_rank[9 + MB], s_ok;
+    float2 *As = sm;
     const int64_t chunks = (d.n + 511) / 512;
     const int64_t total = d.nb * chunks;
     const bool bvec = d.sBn == 1 && d.sBk % 2 == 0 && d.sBb % 2 == 0 && (uintptr_t)d.B % 16 == 0;
     const bool cvec = !d.cscatter && d.sCn == 1 && d.sCm % 2 == 0 && d.sCb % 2 == 0 && (uintptr_t)d.C % 16 == 0;
+    // Bit positions in C of the block's bits (column bits 0..8 of the chunk,
+    // then the m row bits) and their ranks; a direct vector store (cvec) is
+    // already coalesced and stays.
+    const bool pow2 = d.sCn > 0 && d.sCm > 0 && (d.sCn & (d.sCn - 1)) == 0 && (d.sCm & (d.sCm - 1)) == 0;
+    const bool can = kStage && !cvec && d.n % 512 == 0 && d.m == M && (d.cscatter || pow2);
+    if (threadIdx.x == 0) s_ok = can;
+    if (can && threadIdx.x < 9 + MB) {
+        const int b = threadIdx.x;
+        if (d.cscatter)
+            s_pos[b] = b < 9 ? d.cpos[b] : d.cpos[d.cbn + b - 9];
+        else
+            s_pos[b] = b < 9 ? __builtin_ctzll(uint64_t(d.sCn)) + b : __builtin_ctzll(uint64_t(d.sCm)) + b - 9;
+    }
+    __syncthreads();
+    if (can && threadIdx.x < 9 + MB) {
+        const int b = threadIdx.x, p = s_pos[b];
+        int r = 0;
+        for (int c = 0; c < 9 + MB; ++c) {
+            r += s_pos[c] < p;
+            if (c != b && s_pos[c] == p) s_ok = 0;
+        }
+        s_rank[b] = r;
+    }
+    __syncthreads();
+    const bool staged = s_ok;
+    int lo_row = 0, lo_col = 0;
+    int64_t lo_off = 0;
+    if (staged) {
+        for (int b = 0; b < 9 + MB; ++b) {
+            const int r = s_rank[b];
+            if (r < 8 && ((threadIdx.x >> r) & 1)) {
+                if (b < 9) lo_col |= 1 << b; else lo_row |= 1 << (b - 9);
+                lo_off += int64_t(1) << s_pos[b];
+            }
+        }
+        if (threadIdx.x < NJ) {
+            int hr = 0, hc = 0;
+            int64_t ho = 0;
+            for (int b = 0; b < 9 + MB; ++b) {
+                const int r = s_rank[b];
+                if (r >= 8 && ((threadIdx.x >> (r - 8)) & 1)) {
+                    if (b < 9) hc |= 1 << b; else hr |= 1 << (b - 9);
+                    ho += int64_t(1) << s_pos[b];
+                }
+            }
+            hi_row[threadIdx.x] = hr;
+            hi_col[threadIdx.x] = hc;
+            hi_off[threadIdx.x] = ho;
+        }
+    }
+    __syncthreads();
     float mx = 0.f;
     for (int64_t blk = blockIdx.x; blk < total; blk += gridDim.x) {
         const int64_t bi = blk / chunks;
@@ -427,6 +494,25 @@ __global__ void __launch_bounds__(256) gemm_skinny_kernel(GemmDesc d) {
                     }
                 }
             }
+        }
+        if constexpr (kStage) if (staged) {
+            // The chunk's base: its batch entry and column bits 9 and up.
+            const int64_t jc = j0 - 2 * threadIdx.x;
+            const int64_t base = d.cscatter ? scat_bits(d, uint64_t(bi), d.cbn + d.cbm, d.cbb) +
+                                                  scat_bits(d, uint64_t(jc), 0, d.cbn)
+                                            : bi * d.sCb + jc * d.sCn;
+            __syncthreads();  // A's values are no longer read
+#pragma unroll
+            for (int i = 0; i < M; ++i) {
+                sm[(2 * threadIdx.x) * RS + i] = make_float2(re0[i], im0[i]);
+                sm[(2 * threadIdx.x + 1) * RS + i] = make_float2(re1[i], im1[i]);
+                mx = fmaxf(mx, fmaxf(fmaxf(fabsf(re0[i]), fabsf(im0[i])), fmaxf(fabsf(re1[i]), fabsf(im1[i]))));
+            }
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < NJ; ++j)
+                d.C[base + lo_off + hi_off[j]] = sm[(lo_col + hi_col[j]) * RS + lo_row + hi_row[j]];
+            continue;
         }
         float2 *Cb = d.C + bi * d.sCb;
         int64_t o0 = j0 * d.sCn, o1 = (j0 + 1) * d.sCn;
@@ -498,17 +584,84 @@ __global__ void __launch_bounds__(1024) gemm_dot_kernel(GemmDesc d) {
 // row of A once -- with 16-byte loads along k when A is stored [m][k], or
 // coalesced across the threads' rows when it is stored [k][m].  Sums run
 // over k in increasing order.
+//
+// Output: a thread's n values of one row go to n places that are usually far
+// from its neighbours' (rows are 8 n bytes apart or scattered), so direct
+// stores touch 64 cache lines per instruction.  When every 256-row chunk is
+// whole and C's element offset is a sum of per-bit offsets (a scattered
+// output, or power-of-two strides), the chunk's 256 x n block is staged in
+// LDS and written in the order of its offsets: the block's 8 + log2 n bits
+// are ranked by their bit position in C, element e of the block takes bit r
+// of e from the bit of rank r, and thread t writes elements t, t + 256, ...,
+// so consecutive lanes write consecutive addresses as far as C keeps the
+// block's bits together.
 template <int N>
 __global__ void __launch_bounds__(256) gemm_rows_kernel(GemmDesc d) {
     constexpr int KC = 2048 / N;
-    __shared__ float2 Bs[KC * N];
+    constexpr int NB = N == 1 ? 0 : N == 2 ? 1 : N == 4 ? 2 : N == 8 ? 3 : 4;  // log2 N
+    constexpr int RS = N + 1;                                                  // staged row stride (padded)
+    constexpr int SM = 256 * RS > KC * N ? 256 * RS : KC * N;
+    __shared__ float2 sm[SM];
+    __shared__ int hi_row[N], hi_col[N];
+    __shared__ int64_t hi_off[N];
+    float2 *Bs = sm;
     const bool avec = d.sAk == 1 && d.sAm % 2 == 0 && d.sAb % 2 == 0 && (uintptr_t)d.A % 16 == 0;
     const int64_t chunks = (d.m + 255) / 256;
     const int64_t total = d.nb * chunks;
-    // Column offsets of C (its n bits), per column.
-    int64_t coff[N];
-#pragma unroll
-    for (int j = 0; j < N; ++j) coff[j] = d.cscatter ? scat_bits(d, uint64_t(j), 0, d.cbn) : j * d.sCn;
+    // Bit positions in C of the block's bits (n bits 0..NB-1, then row bits
+    // 0..7 of the chunk) and their ranks, worked out once by the first
+    // NB + 8 threads; any two bits at one position leave the block unstaged.
+    __shared__ int s_pos[NB + 8], s_rank[NB + 8], s_ok;
+    const bool pow2 = d.sCn > 0 && d.sCm > 0 && (d.sCn & (d.sCn - 1)) == 0 && (d.sCm & (d.sCm - 1)) == 0;
+    const bool can = d.m % 256 == 0 && d.n == N && (d.cscatter || pow2);
+    if (threadIdx.x == 0) s_ok = can;
+    if (can && threadIdx.x < NB + 8) {
+        const int b = threadIdx.x;
+        if (d.cscatter)
+            s_pos[b] = b < NB ? d.cpos[b] : d.cpos[d.cbn + b - NB];
+        else
+            s_pos[b] = b < NB ? __builtin_ctzll(uint64_t(d.sCn)) + b : __builtin_ctzll(uint64_t(d.sCm)) + b - NB;
+    }
+    __syncthreads();
+    if (can && threadIdx.x < NB + 8) {
+        const int b = threadIdx.x, p = s_pos[b];
+        int r = 0;
+        for (int c = 0; c < NB + 8; ++c) {
+            r += s_pos[c] < p;
+            if (c != b && s_pos[c] == p) s_ok = 0;
+        }
+        s_rank[b] = r;
+    }
+    __syncthreads();
+    const bool staged = s_ok;
+    // This thread's element t: its row, column and offset from the bits of
+    // rank < 8; elements t + 256 j add the parts of the bits of rank >= 8.
+    int lo_row = 0, lo_col = 0;
+    int64_t lo_off = 0;
+    if (staged) {
+        for (int b = 0; b < NB + 8; ++b) {
+            const int r = s_rank[b];
+            if (r < 8 && ((threadIdx.x >> r) & 1)) {
+                if (b < NB) lo_col |= 1 << b; else lo_row |= 1 << (b - NB);
+                lo_off += int64_t(1) << s_pos[b];
+            }
+        }
+        if (threadIdx.x < N) {
+            int hr = 0, hc = 0;
+            int64_t ho = 0;
+            for (int b = 0; b < NB + 8; ++b) {
+                const int r = s_rank[b];
+                if (r >= 8 && ((threadIdx.x >> (r - 8)) & 1)) {
+                    if (b < NB) hc |= 1 << b; else hr |= 1 << (b - NB);
+                    ho += int64_t(1) << s_pos[b];
+                }
+            }
+            hi_row[threadIdx.x] = hr;
+            hi_col[threadIdx.x] = hc;
+            hi_off[threadIdx.x] = ho;
+        }
+    }
+    __syncthreads();
     float mx = 0.f;
     for (int64_t blk = blockIdx.x; blk < total; blk += gridDim.x) {
         const int64_t bi = blk / chunks;
@@ -559,13 +712,30 @@ __global__ void __launch_bounds__(256) gemm_rows_kernel(GemmDesc d) {
                 }
             }
         }
-        if (ok) {
+        if (staged) {
+            // The chunk's base: its batch entry and row bits 8 and up.
+            const int64_t i0 = i - threadIdx.x;
+            const int64_t base = d.cscatter ? scat_bits(d, uint64_t(bi), d.cbn + d.cbm, d.cbb) +
+                                                  scat_bits(d, uint64_t(i0), d.cbn, d.cbm)
+                                            : bi * d.sCb + i0 * d.sCm;
+            __syncthreads();  // B's values are no longer read
+#pragma unroll
+            for (int j = 0; j < N; ++j) {
+                sm[threadIdx.x * RS + j] = make_float2(re[j], im[j]);
+                mx = fmaxf(mx, fmaxf(fabsf(re[j]), fabsf(im[j])));
+            }
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < N; ++j)
+                d.C[base + lo_off + hi_off[j]] = sm[(lo_row + hi_row[j]) * RS + lo_col + hi_col[j]];
+        } else if (ok) {
             const int64_t ro = d.cscatter ? scat_bits(d, uint64_t(bi), d.cbn + d.cbm, d.cbb) +
                                                 scat_bits(d, uint64_t(i), d.cbn, d.cbm)
                                           : bi * d.sCb + i * d.sCm;
 #pragma unroll
             for (int j = 0; j < N; ++j) {
-                d.C[ro + coff[j]] = make_float2(re[j], im[j]);
+                const int64_t co = d.cscatter ? scat_bits(d, uint64_t(j), 0, d.cbn) : j * d.sCn;
+                d.C[ro + co] = make_float2(re[j], im[j]);
                 mx = fmaxf(mx, fmaxf(fabsf(re[j]), fabsf(im[j])));
             }
         }

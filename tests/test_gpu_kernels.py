@@ -251,7 +251,9 @@ EXACT_FORMS = [
     ("valu", 2, 3, 5, 7, 1), ("valu", 1, 1, 1, 1024, 1),
     ("skinny", 2, 4, 512, 33, 1), ("skinny", 1, 16, 300, 7, 1),
     ("skinny_t", 2, 512, 4, 33, 1), ("skinny_t", 3, 300, 16, 7, 1), ("skinny_t", 1, 256, 8, 64, 1),
+    ("skinny_t", 1, 2048, 8, 12, 1), ("skinny_t", 2, 1024, 1, 5, 1), ("skinny", 2, 2, 1536, 9, 1),
     ("rows", 2, 512, 4, 33, 1), ("rows", 3, 300, 16, 7, 1), ("rows", 1, 256, 8, 4100, 1), ("rows", 2, 64, 1, 2, 1),
+    ("rows", 1, 2048, 16, 24, 1), ("rows", 2, 768, 2, 9, 1),
     ("dot", 2, 2, 2, 5000, 1), ("dot", 1, 1, 1, 1 << 20, 0),
     ("dot_tile", 4, 16, 16, 4096, 1), ("dot_tile", 2, 32, 8, 2048, 1), ("dot_tile", 1, 1, 256, 300, 1),
     ("dot_tile", 3, 5, 7, 1000, 1), ("dot_tile", 2, 32, 8, 1 << 16, 0), ("dot_tile", 32, 16, 16, 16384, 0),
