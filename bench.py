@@ -84,8 +84,11 @@ def _roofline(prof, prec, workload):
     peak, else HBM-bound; `frac` is the achieved rate over that peak."""
     dom = max(prof, key=lambda kk: prof[kk][1])
     launches, total_ms, flops, nbytes = prof[dom]
-    hw = HW_PER_ALG[prec] if dom in MFMA_KINDS else 1.0
-    peak_f = PEAK_MFMA_TFLOPS[prec] if dom in MFMA_KINDS else PEAK_FP32_TFLOPS
+    # The 16-bit kinds multiply three hardware products per algorithmic one
+    # against the 16-bit peak; every other kind (the complex FP32 MFMA forms
+    # included, also inside a split program) computes in FP32.
+    hw = HW_PER_ALG[prec] if dom.startswith("gemm_split") else 1.0
+    peak_f = PEAK_MFMA_TFLOPS[prec] if dom.startswith("gemm_split") else PEAK_FP32_TFLOPS
     t_f = flops * hw / (peak_f * 1e12)
     t_b = nbytes / (PEAK_HBM_GBS * 1e9)
     sec = total_ms * 1e-3
@@ -102,6 +105,18 @@ def _roofline(prof, prec, workload):
               "flops_counted": "hardware (3 per algorithmic) for split forms" if hw > 1
               else "algorithmic (8 per complex multiply-add)"})
     return r
+
+
+def _hbm_kind(prof, kind):
+    """Achieved algorithmic HBM rate of one kernel kind (bytes each launch must
+    read and write, over its HIP-event time) against the 8 TB/s peak."""
+    if kind not in prof or prof[kind][1] <= 0 or prof[kind][3] <= 0:
+        return None
+    launches, total_ms, _, nbytes = prof[kind]
+    gbs = nbytes / (total_ms * 1e-3) / 1e9
+    return {"bound": "hbm", "kernel": kind, "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": gbs / PEAK_HBM_GBS, "launches": launches, "bytes_per_launch": nbytes / launches,
+            "avg_launch_ms": total_ms / launches}
 
 
 def _kernel_table(prof, steps):
@@ -231,7 +246,7 @@ def diamond_leg(steps, warmup, precs, chunk=None, cpu=True, tune_cache=None):
             "projected_s_per_amplitude": ms * 1e-3 * float(1 << k) / chunk,
             "tflops_alg": flops_step / (ms * 1e-3) / 1e12, "ms_per_step_profiled": ms_prof,
             "kernels": _kernel_table(prof, n_prof), "roofline": _roofline(prof, prec, "diamond70_d32"),
-            "gemm_flop_share_16bit": _split_share(prof),
+            "transpose_hbm": _hbm_kind(prof, "transpose"), "gemm_flop_share_16bit": _split_share(prof),
             "tune_seconds": tune_s, "shapes_timed": n_timed}
         _say(f"70-qubit {prec}: {ms:.2f} ms per {chunk} slices")
         del ws
@@ -874,6 +889,7 @@ def main():
         "projected_s_per_amplitude": main_prec["projected_s_per_amplitude"],
         "tflops": main_prec["tflops_alg"],
         "roofline": main_prec["roofline"],
+        "transpose_hbm": main_prec["transpose_hbm"],
         "diamond70_d32": head,
     }
     if "cpu_oracle" in head:

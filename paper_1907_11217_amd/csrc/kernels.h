@@ -234,6 +234,8 @@ enum GemmVariant {
 };
 bool gemm_variant_ok(const GemmDesc &d, int v);
 int gemm_default_variant(const GemmDesc &d);
+// Whether form v multiplies on 16-bit MFMA (and so reads its operands' recorded maxima).
+bool gemm_variant_16bit(int v);
 const char *launch_gemm_variant(const GemmDesc &d, int v, hipStream_t st);
 
 }  // namespace qc

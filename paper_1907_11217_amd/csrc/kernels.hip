@@ -1587,6 +1587,10 @@ bool gemm_variant_ok(const GemmDesc &d, int v) {
     }
 }
 
+bool gemm_variant_16bit(int v) {
+    return v == kVarSplitBig || v == kVarSplit11 || v == kVarSplit12 || v == kVarSplit21 || v == kVarSplit22;
+}
+
 int gemm_default_variant(const GemmDesc &d) {
     if (d.prec != kPrecC64 && gemm_variant_ok(d, kVarSplitBig)) return kVarSplitBig;
     if (d.prec == kPrecC64 && gemm_variant_ok(d, kVarMfmaBig)) return kVarMfmaBig;

@@ -630,16 +630,18 @@ TransposeDesc make_transpose(const Program &prog, const TransposeOp &t, float2 *
 }
 
 // amax: per-tensor max|x| slots (split FP16) or null; slot[t] maps a
-// transposed tensor to the slot of the tensor it was copied from.
+// transposed tensor to the slot of the tensor it was copied from; need_c, if
+// given, says which slots a later step reads (the output maximum is recorded
+// only for those).
 GemmDesc make_gemm(const Program &prog, const GemmOp &g, float2 *tensors, int prec, uint32_t *amax,
-                   const std::vector<int> &slot, float2 *kscratch) {
+                   const std::vector<int> &slot, float2 *kscratch, const std::vector<char> *need_c = nullptr) {
     GemmDesc d;
     d.kparts = kscratch ? gemm_kparts(g.nb, g.m, g.n, g.k) : 1;
     if (d.kparts > 1) d.kscratch = kscratch;
     d.prec = prec;
     d.amax_a = amax ? amax + slot[g.a] : nullptr;
     d.amax_b = amax ? amax + slot[g.b] : nullptr;
-    d.amax_c = amax ? amax + slot[g.c] : nullptr;
+    d.amax_c = amax && (!need_c || (*need_c)[slot[g.c]]) ? amax + slot[g.c] : nullptr;
     d.A = tensors + prog.tensors[g.a].offset;
     d.B = tensors + prog.tensors[g.b].offset;
     d.C = tensors + prog.tensors[g.c].offset;
@@ -716,6 +718,22 @@ std::vector<int> scale_slots(const Program &prog) {
 void launch_steps(qc_plan *plan, const Exec &x, const DevConsts &dc, float2 *tensors, float2 *kscratch,
                   uint32_t *amax, const std::vector<int> &slot, hipStream_t st, Prof &prof) {
     const Program &prog = *x.prog;
+    // Split FP16: a GEMM step records its output's maximum only where a step
+    // reading that tensor (directly or through a transpose) multiplies on a
+    // 16-bit form, which derives its operand scale from it; elsewhere the
+    // complex FP32 forms run their instances without the recording epilogue.
+    std::vector<char> need;
+    if (amax) {
+        need.assign(prog.tensors.size(), 0);
+        for (size_t gi = 0; gi < prog.gemms.size(); ++gi) {
+            if (prog.gemm_micro[gi]) continue;
+            const GemmOp &g = prog.gemms[gi];
+            const GemmDesc gd = make_gemm(prog, g, tensors, x.prec, amax, slot, kscratch);
+            const int v = g.variant[x.prec];
+            if (gemm_variant_16bit(v >= 0 && gemm_variant_ok(gd, v) ? v : gemm_default_variant(gd)))
+                need[slot[g.a]] = need[slot[g.b]] = 1;
+        }
+    }
     if (prog.n_micro_levels > 0) {
         const int32_t *lt = (const int32_t *)dc.p[kCMicroLevels];
         prof.begin();
@@ -736,11 +754,13 @@ void launch_steps(qc_plan *plan, const Exec &x, const DevConsts &dc, float2 *ten
         if (prog.op_micro[oi]) continue;
         prof.begin();
         if (op.kind == Op::TRANSPOSE) {
-            launch_transpose(make_transpose(prog, prog.transposes[op.index], tensors), st);
-            prof.end("transpose");
+            const TransposeOp &t = prog.transposes[op.index];
+            launch_transpose(make_transpose(prog, t, tensors), st);
+            // Algorithmic bytes: every element read once and written once.
+            prof.end("transpose", 0, 16.0 * double(int64_t(1) << prog.tensors[t.src].layout.size()));
         } else {
             const GemmOp &g = prog.gemms[op.index];
-            const GemmDesc gd = make_gemm(prog, g, tensors, x.prec, amax, slot, kscratch);
+            const GemmDesc gd = make_gemm(prog, g, tensors, x.prec, amax, slot, kscratch, amax ? &need : nullptr);
             const int v = g.variant[x.prec];
             prof.end(v >= 0 && gemm_variant_ok(gd, v) ? launch_gemm_variant(gd, v, st) : launch_gemm(gd, st),
                      gemm_flops(g), gemm_bytes(g));
