@@ -230,6 +230,8 @@ enum GemmVariant {
     kVarT256x64, kVarT64x256, kVarT32x256, kVarT256x32, kVarT128x64, kVarT64x128, kVarT128x32, kVarT32x128,
     kVarMfma16,    // one 16x16 tile per wave on v_mfma_f32_16x16x4_f32 (n = 8 or n % 16 = 0), operands in registers
     kVarMfma16T,   // the same on the transposed product (m = 8 or m % 16 = 0)
+    kVarStream,    // n = 32 or 64, k = 8, 16 or 32: B in registers, 32-row blocks of A streamed through MFMA
+    kVarStreamT,   // the same on the transposed product (m = 32 or 64)
     kVarCount
 };
 bool gemm_variant_ok(const GemmDesc &d, int v);

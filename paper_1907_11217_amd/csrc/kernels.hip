@@ -1518,6 +1518,126 @@ __global__ void __launch_bounds__(256) gemm_mfma16_kernel(GemmDesc d) {
     if (d.amax_c) block_amax(mx, d.amax_c);
 }
 
+// ------------------------------------------------ streaming MFMA form
+// Tall products whose B operand (k x n per batch entry) is small: n = 32 or
+// 64, k = 8, 16 or 32.  Each wave keeps its batch entry's whole B in
+// registers, in the v_mfma_f32_32x32x2_f32 operand layout, and streams 32-row
+// blocks of A straight from memory into registers, loading the next block
+// before multiplying the current one: no LDS and no barriers, so the output
+// stores of one block overlap the next block's loads and MFMAs.  Row blocks
+// are dealt to the waves in turn, so the waves in flight read and write
+// neighbouring rows (B is reloaded where a wave's next block lies in another
+// batch entry).  The k order inside an MFMA is free as long as
+// both operands follow it: step s of lane half h (lane / 32) takes
+// k = h (k / 2) + s, so a lane reads k / 2 consecutive values of its row of A
+// (16-byte loads when k is A's fast axis, AKF).
+template <int NB, int KK, bool AKF>
+__global__ void __launch_bounds__(256, 2) gemm_stream_kernel(GemmDesc d) {
+    constexpr int S = KK / 2;
+    const int lane = threadIdx.x & 63, h = lane >> 5, r = lane & 31;
+    const int64_t mb = d.m / 32, R = d.nb * mb;
+    const int64_t W = int64_t(gridDim.x) * 4, w = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+    float mx = 0.f;  // max(|re|, |im|) written, folded into amax_c when the program tracks it
+    float bre[S][NB], bim[S][NB];
+    float2 a[S], an[S];
+    auto load_a = [&](float2 (&x)[S], int64_t rb) {
+        const int64_t bi = rb / mb, tm = rb - bi * mb;
+        const float2 *p = d.A + bi * d.sAb + (tm * 32 + r) * d.sAm + int64_t(h * S) * d.sAk;
+        if constexpr (AKF) {
+#pragma unroll
+            for (int s = 0; s < S; s += 2) {
+                const float4 q = *(const float4 *)(p + s);
+                x[s] = make_float2(q.x, q.y);
+                x[s + 1] = make_float2(q.z, q.w);
+            }
+        } else {
+#pragma unroll
+            for (int s = 0; s < S; ++s) x[s] = p[s * d.sAk];
+        }
+    };
+    int64_t cur = -1;
+    if (w < R) load_a(a, w);
+    for (int64_t rb = w; rb < R; rb += W) {
+        const int64_t bi = rb / mb, tm = rb - bi * mb;
+        if (bi != cur) {
+            cur = bi;
+            const float2 *q = d.B + bi * d.sBb + int64_t(h * S) * d.sBk + r * d.sBn;
+#pragma unroll
+            for (int s = 0; s < S; ++s)
+#pragma unroll
+                for (int j = 0; j < NB; ++j) {
+                    const float2 v = q[s * d.sBk + j * 32 * d.sBn];
+                    bre[s][j] = v.x;
+                    bim[s][j] = v.y;
+                }
+        }
+        if (rb + W < R) load_a(an, rb + W);
+        floatx16 acc[NB][2];
+#pragma unroll
+        for (int j = 0; j < NB; ++j)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) { acc[j][0][v] = 0.f; acc[j][1][v] = 0.f; }
+#pragma unroll
+        for (int s = 0; s < S; ++s)
+#pragma unroll
+            for (int j = 0; j < NB; ++j) {
+                acc[j][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[s].x, bre[s][j], acc[j][0], 0, 0, 0);
+                acc[j][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(-a[s].y, bim[s][j], acc[j][0], 0, 0, 0);
+                acc[j][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[s].x, bim[s][j], acc[j][1], 0, 0, 0);
+                acc[j][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[s].y, bre[s][j], acc[j][1], 0, 0, 0);
+            }
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            const CBlock cb = c_block(d, bi, tm * 32, j * 32, lane);
+#pragma unroll
+            for (int v = 0; v < 16; ++v) *c_at(cb, v) = make_float2(acc[j][0][v], acc[j][1][v]);
+            if (d.amax_c)
+#pragma unroll
+                for (int v = 0; v < 16; ++v) mx = fmaxf(mx, fmaxf(fabsf(acc[j][0][v]), fabsf(acc[j][1][v])));
+        }
+#pragma unroll
+        for (int s = 0; s < S; ++s) a[s] = an[s];
+    }
+    if (d.amax_c) block_amax(mx, d.amax_c);
+}
+
+static int device_cus();
+namespace {
+GemmDesc transposed(const GemmDesc &d);
+}
+
+// Whether the streaming form applies to d as it is (n and k fixed by the
+// instances; no split over k).
+static bool stream_ok(const GemmDesc &d) {
+    return d.kparts == 1 && d.m % 32 == 0 && d.m >= 32 && (d.n == 32 || d.n == 64) &&
+           (d.k == 8 || d.k == 16 || d.k == 32);
+}
+
+static void launch_stream(const GemmDesc &d, hipStream_t st) {
+    // Workgroups per compute unit as the instance's registers allow.
+    const int per_cu = d.n == 32 ? (d.k <= 16 ? 4 : 3) : (d.k == 8 ? 3 : 2);
+    const int64_t blocks = (d.nb * (d.m / 32) + 3) / 4, cap = per_cu * int64_t(device_cus());
+    const unsigned g = (unsigned)(blocks < cap ? blocks : cap);
+    const bool akf = d.sAk == 1 && d.sAm % 2 == 0 && d.sAb % 2 == 0 && (uintptr_t)d.A % 16 == 0;
+#define QC_STREAM(NB, KK)                                                                                 \
+    do {                                                                                                  \
+        if (akf)                                                                                          \
+            hipLaunchKernelGGL((gemm_stream_kernel<NB, KK, true>), dim3(g), dim3(256), 0, st, d);         \
+        else                                                                                              \
+            hipLaunchKernelGGL((gemm_stream_kernel<NB, KK, false>), dim3(g), dim3(256), 0, st, d);        \
+    } while (0)
+    if (d.n == 32) {
+        if (d.k == 8) QC_STREAM(1, 8);
+        else if (d.k == 16) QC_STREAM(1, 16);
+        else QC_STREAM(1, 32);
+    } else {
+        if (d.k == 8) QC_STREAM(2, 8);
+        else if (d.k == 16) QC_STREAM(2, 16);
+        else QC_STREAM(2, 32);
+    }
+#undef QC_STREAM
+}
+
 // ----------------------------------------------------------- GEMM variants
 // Every kernel form a GEMM step can run as.  gemm_variant_ok says whether a
 // form applies to a shape (tile divisibility, k, precision); the default
@@ -1563,6 +1683,9 @@ bool gemm_variant_ok(const GemmDesc &d, int v) {
         // 16-wide MFMA (FP32 for every precision, like the other small-shape forms).
         case kVarMfma16: return (d.n % 16 == 0 || d.n == 8) && d.m % 16 == 0 && d.k % 4 == 0 && d.k >= 4;
         case kVarMfma16T: return (d.m % 16 == 0 || d.m == 8) && d.n % 16 == 0 && d.k % 4 == 0 && d.k >= 4;
+        // Streaming form (FP32 for every precision): B in registers, A streamed.
+        case kVarStream: return stream_ok(d);
+        case kVarStreamT: return stream_ok(transposed(d));
         case kVarDot: return d.k >= 256 && d.nb * d.m * d.n <= 65536;
         // Complex FP32 MFMA forms (any precision: a split program's step may
         // run in FP32 where the tuner measured it faster).
@@ -1831,6 +1954,12 @@ const char *launch_gemm_variant(const GemmDesc &d, int v, hipStream_t st) {
         case kVarSkinnyT:
             launch_skinny(transposed(d), st);
             return "gemm_skinny_t";
+        case kVarStream:
+            launch_stream(d, st);
+            return "gemm_mfma";
+        case kVarStreamT:
+            launch_stream(transposed(d), st);
+            return "gemm_mfma";
         case kVarRows: {
             const int64_t blocks = d.nb * ((d.m + 255) / 256), cap = d.amax_c ? 2048 : 65536;
             const unsigned g = (unsigned)(blocks < cap ? blocks : cap);

@@ -276,6 +276,12 @@ EXACT_FORMS = [
     ("mfma16", 2, 64, 16, 64, 1), ("mfma16", 1, 32, 8, 20, 1), ("mfma16", 3, 48, 32, 12, 1), ("mfma16", 1, 16, 16, 8, 1),
     ("mfma16", 4, 16, 16, 4096, 4), ("mfma16_t", 2, 16, 256, 64, 1), ("mfma16_t", 1, 8, 64, 36, 1),
     ("mfma16_t", 2, 32, 48, 4, 1),
+    # Streaming form: every (n, k) instance; ranges of row blocks that cross
+    # batch entries (B reloaded), and more row blocks than waves.
+    ("stream", 2, 64, 32, 8, 1), ("stream", 1, 96, 32, 16, 1), ("stream", 3, 32, 32, 32, 1),
+    ("stream", 2, 128, 64, 8, 1), ("stream", 5, 96, 64, 16, 1), ("stream", 1, 64, 64, 32, 1),
+    ("stream", 3, 22400, 64, 16, 1), ("stream", 2, 40000, 32, 32, 1),
+    ("stream_t", 2, 32, 64, 8, 1), ("stream_t", 3, 64, 96, 32, 1), ("stream_t", 2, 32, 30016, 16, 1),
 ]
 
 
@@ -301,3 +307,24 @@ def test_fp32_forms_exact_on_integer_operands(case, a_km, b_nk):
     ref = np.matmul(A.astype(np.complex128), B.astype(np.complex128))
     assert np.abs(ref.real).max() < 2 ** 24 and np.abs(ref.imag).max() < 2 ** 24
     assert np.array_equal(got, ref), np.abs(got - ref).max()
+
+
+def test_stream_records_output_max():
+    # In a split FP16 program the streaming form (FP32) records max(|re|, |im|)
+    # of its output for a later 16-bit step.
+    nb, m, n, k = 2, 4096, 64, 32
+    rng = np.random.default_rng(5)
+    A = _rand(rng, (nb, m, k))
+    B = _rand(rng, (nb, k, n))
+    dA = torch.from_numpy(A.reshape(-1)).cuda()
+    dB = torch.from_numpy(B.reshape(-1)).cuda()
+    dC = torch.full((nb * m * n,), float("nan"), dtype=torch.complex64, device="cuda")
+    slots = torch.zeros(3, dtype=torch.int32, device="cuda")
+    say("gemm stream split_fp16 output max")
+    qcsim.qc_kernel_gemm(dA, dB, dC, nb, m, n, k, prec="split_fp16", scale_ws=slots, form=qcsim.GEMM_FORMS["stream"])
+    torch.cuda.synchronize()
+    got = dC.cpu().numpy().reshape(nb, m, n)
+    ref = np.matmul(A.astype(np.complex128), B.astype(np.complex128))
+    assert np.abs(got - ref).max() <= fp32_sum_tol(k)
+    s = slots.cpu().numpy().view(np.float32)
+    assert s[2] == np.float32(max(np.abs(got.real).max(), np.abs(got.imag).max()))

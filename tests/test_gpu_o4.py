@@ -100,6 +100,27 @@ def test_c4_sampled_slices_match_o4(c4_full, prec):
     _check_slices(got, [ref[s] for s in picks], TOL[prec], f"c4 {prec}")
 
 
+@pytest.mark.parametrize("prec", ["c64", "split_fp16"])
+def test_c4_tuned_slices_match_o4(c4_full, prec):
+    # The same slices with the GEMM forms the tuner picks (the benchmark's
+    # configuration: streaming and tile forms, recorded maxima only where a
+    # 16-bit form reads them).
+    lat, bs, spec, plan, picks, ref = c4_full
+    chunk = spec["chunk"]
+    ws = torch.empty(qcsim.qc_workspace_bytes(plan, chunk, 1, prec), dtype=torch.uint8, device="cuda")
+    say(f"c4 70q d32 qc_tune {prec}")
+    qcsim.qc_tune(plan, chunk, 1, prec, ws)
+    torch.cuda.synchronize()
+    del ws
+    got = []
+    for s in picks:
+        s0 = s - s % chunk
+        say(f"c4 70q d32 tuned slices [{s0}, {s0 + chunk}) {prec}")
+        vals, total = _slice_values(plan, bs[0], s0, s0 + chunk, prec, chunk)
+        got.append(vals[s - s0])
+    _check_slices(got, [ref[s] for s in picks], TOL[prec], f"c4 tuned {prec}")
+
+
 @pytest.fixture(scope="module")
 def c4_fine():
     """The same circuit under a finer slicing (cap 2^22: 32 slice bits, a
