@@ -232,6 +232,7 @@ enum GemmVariant {
     kVarMfma16T,   // the same on the transposed product (m = 8 or m % 16 = 0)
     kVarStream,    // n = 32 or 64, k = 8, 16 or 32: B in registers, 32-row blocks of A streamed through MFMA
     kVarStreamT,   // the same on the transposed product (m = 32 or 64)
+    kVarStream16,  // n = 8 or 16, k <= 64: the same scheme on v_mfma_f32_16x16x4_f32
     kVarCount
 };
 bool gemm_variant_ok(const GemmDesc &d, int v);

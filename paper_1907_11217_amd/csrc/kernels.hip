@@ -1532,7 +1532,7 @@ __global__ void __launch_bounds__(256) gemm_mfma16_kernel(GemmDesc d) {
 // k = h (k / 2) + s, so a lane reads k / 2 consecutive values of its row of A
 // (16-byte loads when k is A's fast axis, AKF).
 template <int NB, int KK, bool AKF>
-__global__ void __launch_bounds__(256, 2) gemm_stream_kernel(GemmDesc d) {
+__global__ void __launch_bounds__(256, 2) gemm_mfma_stream_kernel(GemmDesc d) {
     constexpr int S = KK / 2;
     const int lane = threadIdx.x & 63, h = lane >> 5, r = lane & 31;
     const int64_t mb = d.m / 32, R = d.nb * mb;
@@ -1601,6 +1601,83 @@ __global__ void __launch_bounds__(256, 2) gemm_stream_kernel(GemmDesc d) {
     if (d.amax_c) block_amax(mx, d.amax_c);
 }
 
+// The same streaming scheme on v_mfma_f32_16x16x4_f32 for n = 8 or 16 and
+// k <= 64 (a multiple of 4): the batch entry's B (KC chunks of 16 k) in
+// registers, 16-row blocks of A dealt to the waves in turn, each block's
+// whole k loaded into registers one block ahead.  Operand layout as in the
+// 16-wide form above (lane l: row / column l mod 16, four consecutive k from
+// 4 (l / 16) of each 16-k chunk; groups past k are zeros).
+template <int NC, int KC, bool AV>
+__global__ void __launch_bounds__(256) gemm_mfma16_stream_kernel(GemmDesc d) {
+    const int lane = threadIdx.x & 63;
+    const int g = lane >> 4, c = lane & 15;
+    const bool bcol = NC == 16 || c < NC;
+    const int64_t mb = d.m / 16, R = d.nb * mb;
+    const int64_t W = int64_t(gridDim.x) * 4, w = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+    float mx = 0.f;  // max(|re|, |im|) written, folded into amax_c when the program tracks it
+    float2 b[KC][4], a[KC][4], an[KC][4];
+    auto load_a = [&](float2 (&x)[KC][4], int64_t rb) {
+        const int64_t bi = rb / mb, tm = rb - bi * mb;
+        const float2 *Ar = d.A + bi * d.sAb + (tm * 16 + c) * d.sAm;
+#pragma unroll
+        for (int ch = 0; ch < KC; ++ch) {
+            const int64_t k0 = int64_t(ch) * 16 + 4 * g;
+            if (k0 < d.k) {
+                if constexpr (AV) {
+                    const float4 u = *(const float4 *)(Ar + k0), v = *(const float4 *)(Ar + k0 + 2);
+                    x[ch][0] = make_float2(u.x, u.y); x[ch][1] = make_float2(u.z, u.w);
+                    x[ch][2] = make_float2(v.x, v.y); x[ch][3] = make_float2(v.z, v.w);
+                } else {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) x[ch][q] = Ar[(k0 + q) * d.sAk];
+                }
+            } else {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) x[ch][q] = make_float2(0.f, 0.f);
+            }
+        }
+    };
+    int64_t cur = -1;
+    if (w < R) load_a(a, w);
+    for (int64_t rb = w; rb < R; rb += W) {
+        const int64_t bi = rb / mb, tm = rb - bi * mb;
+        if (bi != cur) {
+            cur = bi;
+            const float2 *Bc = d.B + bi * d.sBb + (bcol ? c : 0) * d.sBn;
+#pragma unroll
+            for (int ch = 0; ch < KC; ++ch) {
+                const int64_t k0 = int64_t(ch) * 16 + 4 * g;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) b[ch][q] = (bcol && k0 < d.k) ? Bc[(k0 + q) * d.sBk] : make_float2(0.f, 0.f);
+            }
+        }
+        if (rb + W < R) load_a(an, rb + W);
+        floatx4 re = {0.f, 0.f, 0.f, 0.f}, im = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ch = 0; ch < KC; ++ch)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                re = __builtin_amdgcn_mfma_f32_16x16x4f32(a[ch][j].x, b[ch][j].x, re, 0, 0, 0);
+                im = __builtin_amdgcn_mfma_f32_16x16x4f32(a[ch][j].x, b[ch][j].y, im, 0, 0, 0);
+                re = __builtin_amdgcn_mfma_f32_16x16x4f32(-a[ch][j].y, b[ch][j].y, re, 0, 0, 0);
+                im = __builtin_amdgcn_mfma_f32_16x16x4f32(a[ch][j].y, b[ch][j].x, im, 0, 0, 0);
+            }
+        // Lane l holds rows 4 (l / 16) + v, column l mod 16.
+        if (bcol) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                d.C[c_off(d, bi, tm * 16 + 4 * g + v, c)] = make_float2(re[v], im[v]);
+                mx = fmaxf(mx, fmaxf(fabsf(re[v]), fabsf(im[v])));
+            }
+        }
+#pragma unroll
+        for (int ch = 0; ch < KC; ++ch)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) a[ch][q] = an[ch][q];
+    }
+    if (d.amax_c) block_amax(mx, d.amax_c);
+}
+
 static int device_cus();
 namespace {
 GemmDesc transposed(const GemmDesc &d);
@@ -1613,6 +1690,39 @@ static bool stream_ok(const GemmDesc &d) {
            (d.k == 8 || d.k == 16 || d.k == 32);
 }
 
+static bool stream16_ok(const GemmDesc &d) {
+    return d.kparts == 1 && d.m % 16 == 0 && d.m >= 16 && (d.n == 16 || d.n == 8) && d.k % 4 == 0 && d.k >= 4 &&
+           d.k <= 64;
+}
+
+static void launch_stream16(const GemmDesc &d, hipStream_t st) {
+    const int kc = int((d.k + 15) / 16);
+    // Workgroups per compute unit as the instance's registers allow.
+    const int per_cu = kc == 1 ? 6 : kc == 2 ? 4 : 3;
+    const int64_t blocks = (d.nb * (d.m / 16) + 3) / 4, cap = per_cu * int64_t(device_cus());
+    const unsigned g = (unsigned)(blocks < cap ? blocks : cap);
+    const bool av = d.sAk == 1 && d.sAm % 2 == 0 && d.sAb % 2 == 0 && (uintptr_t)d.A % 16 == 0;
+#define QC_S16(NC, KC)                                                                                    \
+    do {                                                                                                  \
+        if (av)                                                                                           \
+            hipLaunchKernelGGL((gemm_mfma16_stream_kernel<NC, KC, true>), dim3(g), dim3(256), 0, st, d);  \
+        else                                                                                              \
+            hipLaunchKernelGGL((gemm_mfma16_stream_kernel<NC, KC, false>), dim3(g), dim3(256), 0, st, d); \
+    } while (0)
+    if (d.n == 16) {
+        if (kc == 1) QC_S16(16, 1);
+        else if (kc == 2) QC_S16(16, 2);
+        else if (kc == 3) QC_S16(16, 3);
+        else QC_S16(16, 4);
+    } else {
+        if (kc == 1) QC_S16(8, 1);
+        else if (kc == 2) QC_S16(8, 2);
+        else if (kc == 3) QC_S16(8, 3);
+        else QC_S16(8, 4);
+    }
+#undef QC_S16
+}
+
 static void launch_stream(const GemmDesc &d, hipStream_t st) {
     // Workgroups per compute unit as the instance's registers allow.
     const int per_cu = d.n == 32 ? (d.k <= 16 ? 4 : 3) : (d.k == 8 ? 3 : 2);
@@ -1622,9 +1732,9 @@ static void launch_stream(const GemmDesc &d, hipStream_t st) {
 #define QC_STREAM(NB, KK)                                                                                 \
     do {                                                                                                  \
         if (akf)                                                                                          \
-            hipLaunchKernelGGL((gemm_stream_kernel<NB, KK, true>), dim3(g), dim3(256), 0, st, d);         \
+            hipLaunchKernelGGL((gemm_mfma_stream_kernel<NB, KK, true>), dim3(g), dim3(256), 0, st, d);         \
         else                                                                                              \
-            hipLaunchKernelGGL((gemm_stream_kernel<NB, KK, false>), dim3(g), dim3(256), 0, st, d);        \
+            hipLaunchKernelGGL((gemm_mfma_stream_kernel<NB, KK, false>), dim3(g), dim3(256), 0, st, d);        \
     } while (0)
     if (d.n == 32) {
         if (d.k == 8) QC_STREAM(1, 8);
@@ -1686,6 +1796,7 @@ bool gemm_variant_ok(const GemmDesc &d, int v) {
         // Streaming form (FP32 for every precision): B in registers, A streamed.
         case kVarStream: return stream_ok(d);
         case kVarStreamT: return stream_ok(transposed(d));
+        case kVarStream16: return stream16_ok(d);
         case kVarDot: return d.k >= 256 && d.nb * d.m * d.n <= 65536;
         // Complex FP32 MFMA forms (any precision: a split program's step may
         // run in FP32 where the tuner measured it faster).
@@ -1959,6 +2070,9 @@ const char *launch_gemm_variant(const GemmDesc &d, int v, hipStream_t st) {
             return "gemm_mfma";
         case kVarStreamT:
             launch_stream(transposed(d), st);
+            return "gemm_mfma";
+        case kVarStream16:
+            launch_stream16(d, st);
             return "gemm_mfma";
         case kVarRows: {
             const int64_t blocks = d.nb * ((d.m + 255) / 256), cap = d.amax_c ? 2048 : 65536;
