@@ -230,7 +230,7 @@ enum GemmVariant {
     kVarT256x64, kVarT64x256, kVarT32x256, kVarT256x32, kVarT128x64, kVarT64x128, kVarT128x32, kVarT32x128,
     kVarMfma16,    // one 16x16 tile per wave on v_mfma_f32_16x16x4_f32 (n = 8 or n % 16 = 0), operands in registers
     kVarMfma16T,   // the same on the transposed product (m = 8 or m % 16 = 0)
-    kVarStream,    // n = 32 or 64, k = 8, 16 or 32: B in registers, 32-row blocks of A streamed through MFMA
+    kVarStream,    // n = 32 or 64 with k = 8, 16 or 32, n = 32 with k = 64: B in registers, 32-row blocks of A streamed through MFMA
     kVarStreamT,   // the same on the transposed product (m = 32 or 64)
     kVarStream16,  // n = 8 or 16, k <= 64: the same scheme on v_mfma_f32_16x16x4_f32
     kVarCount

@@ -1520,7 +1520,7 @@ __global__ void __launch_bounds__(256) gemm_mfma16_kernel(GemmDesc d) {
 
 // ------------------------------------------------ streaming MFMA form
 // Tall products whose B operand (k x n per batch entry) is small: n = 32 or
-// 64, k = 8, 16 or 32.  Each wave keeps its batch entry's whole B in
+// 64 with k = 8, 16 or 32, or n = 32 with k = 64.  Each wave keeps its batch entry's whole B in
 // registers, in the v_mfma_f32_32x32x2_f32 operand layout, and streams 32-row
 // blocks of A straight from memory into registers, loading the next block
 // before multiplying the current one: no LDS and no barriers, so the output
@@ -1686,8 +1686,8 @@ GemmDesc transposed(const GemmDesc &d);
 // Whether the streaming form applies to d as it is (n and k fixed by the
 // instances; no split over k).
 static bool stream_ok(const GemmDesc &d) {
-    return d.kparts == 1 && d.m % 32 == 0 && d.m >= 32 && (d.n == 32 || d.n == 64) &&
-           (d.k == 8 || d.k == 16 || d.k == 32);
+    return d.kparts == 1 && d.m % 32 == 0 && d.m >= 32 &&
+           (((d.n == 32 || d.n == 64) && (d.k == 8 || d.k == 16 || d.k == 32)) || (d.n == 32 && d.k == 64));
 }
 
 static bool stream16_ok(const GemmDesc &d) {
@@ -1725,7 +1725,7 @@ static void launch_stream16(const GemmDesc &d, hipStream_t st) {
 
 static void launch_stream(const GemmDesc &d, hipStream_t st) {
     // Workgroups per compute unit as the instance's registers allow.
-    const int per_cu = d.n == 32 ? (d.k <= 16 ? 4 : 3) : (d.k == 8 ? 3 : 2);
+    const int per_cu = d.n == 32 ? (d.k <= 16 ? 4 : d.k == 32 ? 3 : 2) : (d.k == 8 ? 3 : 2);
     const int64_t blocks = (d.nb * (d.m / 32) + 3) / 4, cap = per_cu * int64_t(device_cus());
     const unsigned g = (unsigned)(blocks < cap ? blocks : cap);
     const bool akf = d.sAk == 1 && d.sAm % 2 == 0 && d.sAb % 2 == 0 && (uintptr_t)d.A % 16 == 0;
@@ -1739,7 +1739,8 @@ static void launch_stream(const GemmDesc &d, hipStream_t st) {
     if (d.n == 32) {
         if (d.k == 8) QC_STREAM(1, 8);
         else if (d.k == 16) QC_STREAM(1, 16);
-        else QC_STREAM(1, 32);
+        else if (d.k == 32) QC_STREAM(1, 32);
+        else QC_STREAM(1, 64);
     } else {
         if (d.k == 8) QC_STREAM(2, 8);
         else if (d.k == 16) QC_STREAM(2, 16);

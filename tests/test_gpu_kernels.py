@@ -280,7 +280,8 @@ EXACT_FORMS = [
     # batch entries (B reloaded), and more row blocks than waves.
     ("stream", 2, 64, 32, 8, 1), ("stream", 1, 96, 32, 16, 1), ("stream", 3, 32, 32, 32, 1),
     ("stream", 2, 128, 64, 8, 1), ("stream", 5, 96, 64, 16, 1), ("stream", 1, 64, 64, 32, 1),
-    ("stream", 3, 22400, 64, 16, 1), ("stream", 2, 40000, 32, 32, 1),
+    ("stream", 3, 22400, 64, 16, 1), ("stream", 2, 40000, 32, 32, 1), ("stream", 2, 96, 32, 64, 1),
+    ("stream", 3, 20000, 32, 64, 1), ("stream_t", 2, 32, 128, 64, 1),
     ("stream_t", 2, 32, 64, 8, 1), ("stream_t", 3, 64, 96, 32, 1), ("stream_t", 2, 32, 30016, 16, 1),
     ("stream16", 2, 64, 16, 64, 1), ("stream16", 1, 48, 8, 20, 1), ("stream16", 3, 32, 16, 12, 1),
     ("stream16", 1, 16, 8, 4, 1), ("stream16", 2, 96, 16, 44, 1), ("stream16", 3, 40000, 16, 32, 1),
