@@ -59,7 +59,12 @@ qc_status qc_kernel_gemm(const void *A, const void *B, void *C, int64_t nb, int6
  *   16, k a multiple of 4: one 16x16 tile per wave on
  *   v_mfma_f32_16x16x4_f32, operands read straight into registers), 25 the
  *   same on the transposed product (m = 8 or a multiple of 16, n a multiple
- *   of 16); form -1 is the default choice.  Every form but 7..11 computes
+ *   of 16), 26 streaming complex FP32 MFMA (n = 32 or 64 with k in {8,16,32},
+ *   or n = 32 with k = 64, m a multiple of 32: B held in registers, 32-row
+ *   blocks of A streamed into the MFMA operands), 27 the same on the
+ *   transposed product (m = 32 or 64), 28 streaming 16-wide MFMA (n = 8 or
+ *   16, k <= 64 a multiple of 4, m a multiple of 16); form -1 is the default
+ *   choice.  Every form but 7..11 computes
  *   in complex FP32 for every
  *   precision.  QC_ERR_UNSUPPORTED if the form does not apply to the shape and
  *   precision. */
@@ -68,7 +73,8 @@ qc_status qc_kernel_gemm_form(const void *A, const void *B, void *C, int64_t nb,
                               void *stream);
 
 /* qc_kernel_gemm_form split over k, as the stepwise contraction runs its
- * GEMM steps with few outputs: every MFMA form (3-12, 16-25) and the dot forms (2, 14)
+ * GEMM steps with few outputs: every MFMA form (3-12, 16-25; not the
+ * streaming forms 26-28) and the dot forms (2, 14)
  * compute kparts partial products, part p over l in [p k/kparts,
  * (p+1) k/kparts), into `scratch`, then C = the parts summed in increasing p,
  * in FP32 (so the result is deterministic).  scratch: caller-owned device

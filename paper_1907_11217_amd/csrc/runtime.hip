@@ -1779,9 +1779,10 @@ extern "C" qc_status qc_kernel_gemm_kparts(const void *A, const void *B, void *C
     }
     const int v = form >= 0 ? form : qc::gemm_default_variant(d);
     if (kparts == 0) kparts = qc::gemm_kparts(nb, m, n, k);
-    // Every MFMA form and the dot form split over k; each part must itself
-    // be a product the form applies to.
-    const bool splits = v != qc::kVarValu && v != qc::kVarSkinny && v != qc::kVarSkinnyT && v != qc::kVarRows;
+    // Every MFMA form but the streaming ones, and the dot form, split over
+    // k; each part must itself be a product the form applies to.
+    const bool splits = v != qc::kVarValu && v != qc::kVarSkinny && v != qc::kVarSkinnyT && v != qc::kVarRows &&
+                        v != qc::kVarStream && v != qc::kVarStreamT && v != qc::kVarStream16;
     qc::GemmDesc part = d;
     if (kparts > 1) part.k = k / kparts;
     if (kparts > 1 && (!splits || k % kparts != 0 || !scratch || !qc::gemm_variant_ok(part, v))) {

@@ -217,6 +217,12 @@ def test_gemm_kparts_rejects_bad_arguments():
         with pytest.raises(qcsim.QcError):
             qcsim.qc_kernel_gemm(d, d, d, nb, m, n, kk, prec="c64", form=qcsim.GEMM_FORMS[form], kparts=kp,
                                  scratch=scratch)
+    # The streaming forms do not split over k (n = 32, k = 64: the form and
+    # each part of k = 32 would both apply).
+    d32 = torch.zeros(128 * 64, dtype=torch.complex64, device="cuda")
+    with pytest.raises(qcsim.QcError):
+        qcsim.qc_kernel_gemm(d32, d32, d32, 1, 128, 32, 64, prec="c64", form=qcsim.GEMM_FORMS["stream"], kparts=2,
+                             scratch=scratch)
     with pytest.raises(qcsim.QcError):  # 16 parts do not divide k = 24
         qcsim.qc_kernel_gemm(d, d, d, nb, m, n, 24, prec="c64", form=qcsim.GEMM_FORMS["mfma_big"], kparts=16,
                              scratch=scratch)
