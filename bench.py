@@ -803,6 +803,29 @@ def pmc_summary(path, calls):
         print(f"  {name[:48]:48s} dispatches/call {len(n[name]) / calls:7.2f}  per call: {vals}")
 
 
+def gemm_form_probe(spec):
+    """Four launches of one GEMM kernel form on one shape (random complex64
+    operands, A stored [k][m] when AKM, B stored [n][k] when BNK); the split
+    FP16 form gets a scale workspace.  Returns the last launch's event time."""
+    import torch
+    from paper_1907_11217_amd import qcsim
+    form, prec, nb, m, n, k, akm, bnk = spec.split(":")
+    nb, m, n, k, akm, bnk = (int(v) for v in (nb, m, n, k, akm, bnk))
+    A = torch.randn(nb * m * k, dtype=torch.complex64, device="cuda")
+    B = torch.randn(nb * k * n, dtype=torch.complex64, device="cuda")
+    C = torch.empty(nb * m * n, dtype=torch.complex64, device="cuda")
+    slots = torch.zeros(3, dtype=torch.int32, device="cuda") if prec != "c64" else None
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for _ in range(4):
+        e0.record()
+        qcsim.qc_kernel_gemm(A, B, C, nb, m, n, k, akm, bnk, prec=prec, scale_ws=slots, form=qcsim.GEMM_FORMS[form])
+        e1.record()
+        torch.cuda.synchronize()
+    flops = 8.0 * nb * m * n * k
+    return {"form": form, "prec": prec, "shape": [nb, m, n, k], "a_km": akm, "b_nk": bnk,
+            "ms_last": e0.elapsed_time(e1), "tflops_alg": flops / (e0.elapsed_time(e1) * 1e-3) / 1e12}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -828,6 +851,9 @@ def main():
                     help="print per-kernel counter sums of a rocprofv3 counter-collection CSV, divided by "
                          "--calls, and exit")
     ap.add_argument("--calls", type=int, default=1, help="contraction calls in the traced process (--pmc-summary)")
+    ap.add_argument("--gemm", metavar="FORM:PREC:NB:M:N:K:AKM:BNK", action="append", default=[],
+                    help="only time GEMM kernel forms (qcsim.GEMM_FORMS names) on one shape each, four launches "
+                         "apiece (for counter runs on a single kernel), and print one JSON line per form")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 256 MiB device to device 5 times (the plain-copy reference of the "
                          "FETCH_SIZE / WRITE_SIZE counter runs)")
@@ -855,6 +881,10 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_per_launch": src.numel() * 4}), flush=True)
+        return
+    if args.gemm:
+        for spec in args.gemm:
+            print(json.dumps(gemm_form_probe(spec)), flush=True)
         return
     if args.leg:
         leg = {"grid5x5_d16": lambda: fused_leg(cpu=False),

@@ -233,6 +233,7 @@ enum GemmVariant {
     kVarStream,    // n = 32 or 64 with k = 8, 16 or 32, n = 32 with k = 64: B in registers, 32-row blocks of A streamed through MFMA
     kVarStreamT,   // the same on the transposed product (m = 32 or 64)
     kVarStream16,  // n = 8 or 16, k <= 64: the same scheme on v_mfma_f32_16x16x4_f32
+    kVarSplitBig64,  // split 16-bit MFMA with a 128x64 tile (two waves per SIMD), m % 128 = n % 64 = 0
     kVarCount
 };
 bool gemm_variant_ok(const GemmDesc &d, int v);

@@ -1000,8 +1000,8 @@ __global__ void __launch_bounds__(64 * WM * WN) gemm_split_kernel(GemmDesc d) {
 // one XCD share A panels in that XCD's L2.
 __device__ __forceinline__ int swz(int row, int half) { return (half ^ ((row >> 3) & 1)) * 8; }
 
-template <typename T>
-__device__ __forceinline__ void split_store(T (*plane)[128][16], int row, int half, const float2 (&v)[8], int e) {
+template <typename T, int ROWS>
+__device__ __forceinline__ void split_store(T (*plane)[ROWS][16], int row, int half, const float2 (&v)[8], int e) {
     typedef T V __attribute__((ext_vector_type(8)));
     V hr, hi, lr, li;
 #pragma unroll
@@ -1048,10 +1048,13 @@ __device__ __forceinline__ void load8(float2 (&v)[8], const float2 *base, int64_
     }
 }
 
-template <typename T>
-__global__ void __launch_bounds__(256) gemm_split_big_kernel(GemmDesc d) {
+// JN = 2: the 128x128 tile above (each wave 64x64); JN = 1: a 128x64 tile
+// (each wave 64x32, half the accumulators, two waves per SIMD), in which
+// only the first 128 threads stage B.
+template <typename T, int JN>
+__global__ void __launch_bounds__(256, JN == 1 ? 2 : 1) gemm_split_big_kernel(GemmDesc d) {
     typedef T V __attribute__((ext_vector_type(8)));
-    constexpr int TM = 128, TN = 128, KT = 16;
+    constexpr int TM = 128, TN = 64 * JN, KT = 16;
     __shared__ __attribute__((aligned(16))) T As[2][4][TM][KT];
     __shared__ __attribute__((aligned(16))) T Bs[2][4][TN][KT];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
@@ -1062,7 +1065,8 @@ __global__ void __launch_bounds__(256) gemm_split_big_kernel(GemmDesc d) {
     // thread), else along the row (coalesced across the wavefront).
     const bool a_kc = d.sAk == 1, b_kc = d.sBk == 1;
     const int ar = a_kc ? (t >> 1) : (t & 127), ah = a_kc ? (t & 1) : (t >> 7);
-    const int br = b_kc ? (t >> 1) : (t & 127), bh = b_kc ? (t & 1) : (t >> 7);
+    const int br = b_kc ? ((t >> 1) & (TN - 1)) : (t & (TN - 1)), bh = b_kc ? (t & 1) : ((t / TN) & 1);
+    const bool bst = JN == 2 || t < 2 * TN;  // this thread stages a row half of B
     const bool a_vec = a_kc && d.sAm % 2 == 0 && d.sAb % 2 == 0 && d.sAp % 2 == 0 && (uintptr_t)d.A % 16 == 0;
     const bool b_vec = b_kc && d.sBn % 2 == 0 && d.sBb % 2 == 0 && d.sBp % 2 == 0 && (uintptr_t)d.B % 16 == 0;
     const int ea = split_exp<T>(d.amax_a), eb = split_exp<T>(d.amax_b);
@@ -1078,32 +1082,32 @@ __global__ void __launch_bounds__(256) gemm_split_big_kernel(GemmDesc d) {
         const int64_t bq = d.kparts == 1 ? bi : bi / d.kparts, bp = bi - bq * d.kparts;
         const float2 *Ab = d.A + bq * d.sAb + bp * d.sAp + tm * TM * d.sAm;
         const float2 *Bb = d.B + bq * d.sBb + bp * d.sBp + tn * TN * d.sBn;
-        floatx16 acc[2][2][2];
+        floatx16 acc[2][JN][2];
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
-            for (int j = 0; j < 2; ++j)
+            for (int j = 0; j < JN; ++j)
 #pragma unroll
                 for (int v = 0; v < 16; ++v) { acc[i][j][0][v] = 0.f; acc[i][j][1][v] = 0.f; }
         float2 ra[8], rb[8];
         load8(ra, Ab, d.sAm, d.sAk, a_vec, ar, 8 * ah, d.k);
-        load8(rb, Bb, d.sBn, d.sBk, b_vec, br, 8 * bh, d.k);
-        split_store<T>(As[0], ar, ah, ra, ea);
-        split_store<T>(Bs[0], br, bh, rb, eb);
+        if (bst) load8(rb, Bb, d.sBn, d.sBk, b_vec, br, 8 * bh, d.k);
+        split_store<T, TM>(As[0], ar, ah, ra, ea);
+        if (bst) split_store<T, TN>(Bs[0], br, bh, rb, eb);
         __syncthreads();
         for (int s = 0; s < n_slabs; ++s) {
             const int buf = s & 1;
             // The next slab.  BF16 stages it unconditionally (zeros past the
             // end, into the buffer nobody reads again) so that the staging
             // shares the MFMAs' basic block and can be interleaved with them.
-            constexpr bool kInterleave = __is_same(T, __bf16);
+            constexpr bool kInterleave = __is_same(T, __bf16) && JN == 2;
             const bool more = kInterleave || s + 1 < n_slabs;
             if (more) {
                 const int64_t k1 = int64_t(s + 1) * KT;
                 load8(ra, Ab, d.sAm, d.sAk, a_vec, ar, k1 + 8 * ah, d.k);
-                load8(rb, Bb, d.sBn, d.sBk, b_vec, br, k1 + 8 * bh, d.k);
+                if (bst) load8(rb, Bb, d.sBn, d.sBk, b_vec, br, k1 + 8 * bh, d.k);
             }
-            V a[2][4], b[2][4], na[2][2];
+            V a[2][4], b[JN][4], na[2][2];
 #pragma unroll
             for (int i = 0; i < 2; ++i) {
                 const int row = wm * 64 + i * 32 + (lane & 31);
@@ -1114,8 +1118,8 @@ __global__ void __launch_bounds__(256) gemm_split_big_kernel(GemmDesc d) {
                 na[i][1] = negate16(a[i][3]);
             }
 #pragma unroll
-            for (int j = 0; j < 2; ++j) {
-                const int row = wn * 64 + j * 32 + (lane & 31);
+            for (int j = 0; j < JN; ++j) {
+                const int row = wn * 32 * JN + j * 32 + (lane & 31);
                 const int c = swz(row, lane >> 5);
 #pragma unroll
                 for (int p = 0; p < 4; ++p) b[j][p] = *(const V *)&Bs[buf][p][row][c];
@@ -1123,7 +1127,7 @@ __global__ void __launch_bounds__(256) gemm_split_big_kernel(GemmDesc d) {
             // Planes: 0 hi re, 1 hi im, 2 lo re, 3 lo im.  Consecutive MFMAs
             // go to different accumulators.
 #define QC_MFMA_ALL(ROW_A, COL_B, RI)                                                    \
-    _Pragma("unroll") for (int i = 0; i < 2; ++i) _Pragma("unroll") for (int j = 0; j < 2; ++j) \
+    _Pragma("unroll") for (int i = 0; i < 2; ++i) _Pragma("unroll") for (int j = 0; j < JN; ++j) \
         acc[i][j][RI] = mfma16(ROW_A, COL_B, acc[i][j][RI]);
             QC_MFMA_ALL(a[i][0], b[j][0], 0)
             QC_MFMA_ALL(a[i][0], b[j][1], 1)
@@ -1139,8 +1143,8 @@ __global__ void __launch_bounds__(256) gemm_split_big_kernel(GemmDesc d) {
             QC_MFMA_ALL(a[i][3], b[j][0], 1)
 #undef QC_MFMA_ALL
             if (more) {
-                split_store<T>(As[buf ^ 1], ar, ah, ra, ea);
-                split_store<T>(Bs[buf ^ 1], br, bh, rb, eb);
+                split_store<T, TM>(As[buf ^ 1], ar, ah, ra, ea);
+                if (bst) split_store<T, TN>(Bs[buf ^ 1], br, bh, rb, eb);
             }
             // BF16: the fragment reads, then each of the 48 MFMAs with four
             // VALU instructions of the next slab's conversion and an LDS write
@@ -1162,8 +1166,8 @@ __global__ void __launch_bounds__(256) gemm_split_big_kernel(GemmDesc d) {
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
-            for (int j = 0; j < 2; ++j) {
-                const CBlock cb = c_block(d, bi, tm * TM + wm * 64 + i * 32, tn * TN + wn * 64 + j * 32, lane);
+            for (int j = 0; j < JN; ++j) {
+                const CBlock cb = c_block(d, bi, tm * TM + wm * 64 + i * 32, tn * TN + wn * 32 * JN + j * 32, lane);
 #pragma unroll
                 for (int v = 0; v < 16; ++v) {
                     const float re = ldexpf(acc[i][j][0][v], ea + eb), im = ldexpf(acc[i][j][1][v], ea + eb);
@@ -1819,6 +1823,7 @@ bool gemm_variant_ok(const GemmDesc &d, int v) {
         }
         // The large-tile and tile forms stage k in groups of 8 (load8).
         case kVarSplitBig: return split && d.k % 8 == 0 && d.m % 128 == 0 && d.n % 128 == 0;
+        case kVarSplitBig64: return split && d.k % 8 == 0 && d.m % 128 == 0 && d.n % 64 == 0;
         case kVarMfmaBig: return d.k % 8 == 0 && d.m % 128 == 0 && d.n % 128 == 0;
         case kVarT256x64: case kVarT64x256: case kVarT32x256: case kVarT256x32: case kVarT128x64: case kVarT64x128:
         case kVarT128x32: case kVarT32x128: {
@@ -1835,7 +1840,8 @@ bool gemm_variant_ok(const GemmDesc &d, int v) {
 }
 
 bool gemm_variant_16bit(int v) {
-    return v == kVarSplitBig || v == kVarSplit11 || v == kVarSplit12 || v == kVarSplit21 || v == kVarSplit22;
+    return v == kVarSplitBig || v == kVarSplitBig64 || v == kVarSplit11 || v == kVarSplit12 || v == kVarSplit21 ||
+           v == kVarSplit22;
 }
 
 int gemm_default_variant(const GemmDesc &d) {
@@ -2008,10 +2014,19 @@ const char *launch_big(const GemmDesc &d, int v, hipStream_t st) {
             hipLaunchKernelGGL(gemm_mfma_big_kernel<false>, dim3(g), dim3(256), 0, st, d);
         return "gemm_mfma";
     }
+    if (v == kVarSplitBig64) {
+        const int64_t t64 = d.nb * (d.m / 128) * (d.n / 64);
+        const unsigned g64 = (unsigned)(t64 < 1048576 ? t64 : 1048576);
+        if (d.prec == kPrecFP16)
+            hipLaunchKernelGGL((gemm_split_big_kernel<_Float16, 1>), dim3(g64), dim3(256), 0, st, d);
+        else
+            hipLaunchKernelGGL((gemm_split_big_kernel<__bf16, 1>), dim3(g64), dim3(256), 0, st, d);
+        return d.prec == kPrecFP16 ? "gemm_split_fp16" : "gemm_split_bf16";
+    }
     if (d.prec == kPrecFP16)
-        hipLaunchKernelGGL(gemm_split_big_kernel<_Float16>, dim3(g), dim3(256), 0, st, d);
+        hipLaunchKernelGGL((gemm_split_big_kernel<_Float16, 2>), dim3(g), dim3(256), 0, st, d);
     else
-        hipLaunchKernelGGL(gemm_split_big_kernel<__bf16>, dim3(g), dim3(256), 0, st, d);
+        hipLaunchKernelGGL((gemm_split_big_kernel<__bf16, 2>), dim3(g), dim3(256), 0, st, d);
     return d.prec == kPrecFP16 ? "gemm_split_fp16" : "gemm_split_bf16";
 }
 
@@ -2064,7 +2079,7 @@ const char *launch_gemm_variant(const GemmDesc &d, int v, hipStream_t st) {
                 case kVarSplit21: launch_split<2, 1>(d, st); return split_name;
                 default: launch_split<2, 2>(d, st); return split_name;
             }
-        case kVarMfmaBig: case kVarSplitBig:
+        case kVarMfmaBig: case kVarSplitBig: case kVarSplitBig64:
         case kVarT256x64: case kVarT64x256: case kVarT32x256: case kVarT256x32: case kVarT128x64: case kVarT64x128:
         case kVarT128x32: case kVarT32x128: case kVarMfma16: case kVarMfma16T:
             if (d.kparts > 1) return launch_gemm_kparts(d, v, st);

@@ -479,7 +479,8 @@ GEMM_FORMS = {"valu": 0, "skinny": 1, "dot": 2, "mfma11": 3, "mfma12": 4, "mfma2
               "split_big": 7, "split11": 8, "split12": 9, "split21": 10, "split22": 11, "mfma_big": 12,
               "skinny_t": 13, "dot_tile": 14, "rows": 15, "tile256x64": 16, "tile64x256": 17, "tile32x256": 18,
               "tile256x32": 19, "tile128x64": 20, "tile64x128": 21, "tile128x32": 22, "tile32x128": 23, "mfma16": 24,
-              "mfma16_t": 25, "stream": 26, "stream_t": 27, "stream16": 28}
+              "mfma16_t": 25, "stream": 26, "stream_t": 27, "stream16": 28,
+              "split_big64": 29}
 
 
 def qc_kernel_gemm(A, B, C, nb: int, m: int, n: int, k: int, a_km: bool = False, b_nk: bool = False,

@@ -36,13 +36,15 @@ def _dev(x):
     return torch.from_numpy(np.ascontiguousarray(x).reshape(-1)).cuda()
 
 
-def _run(A, B, nb, m, n, k, a_km, b_nk, prec, scale_ws=None):
+def _run(A, B, nb, m, n, k, a_km, b_nk, prec, scale_ws=None, form=-1):
     a_store = A.transpose(0, 2, 1) if a_km else A
     b_store = B.transpose(0, 2, 1) if b_nk else B
     dA, dB = _dev(a_store.astype(np.complex64)), _dev(b_store.astype(np.complex64))
     dC = torch.full((nb * m * n,), float("nan"), dtype=torch.complex64, device="cuda")
-    say(f"gemm {prec} nb={nb} m={m} n={n} k={k} a_km={a_km} b_nk={b_nk}")
-    qcsim.qc_kernel_gemm(dA, dB, dC, nb, m, n, k, a_km, b_nk, prec=prec, scale_ws=scale_ws)
+    say(f"gemm {prec} nb={nb} m={m} n={n} k={k} a_km={a_km} b_nk={b_nk} form={form}")
+    if prec == "split_fp16" and scale_ws is None and form >= 0:
+        scale_ws = torch.zeros(3, dtype=torch.int32, device="cuda")
+    qcsim.qc_kernel_gemm(dA, dB, dC, nb, m, n, k, a_km, b_nk, prec=prec, scale_ws=scale_ws, form=form)
     torch.cuda.synchronize()
     return dC.cpu().numpy().reshape(nb, m, n)
 
@@ -74,6 +76,39 @@ def test_split_gemm_exact(prec, shape, a_km, b_nk, scale):
     got = _run(A, B, nb, m, n, k, a_km, b_nk, prec)
     ref = np.matmul(A, B)
     assert np.array_equal(got.astype(np.complex128), ref), np.abs(got - ref).max()
+
+
+# The 128x64-tile form (m % 128 = 0, n % 64 = 0, k % 8 = 0), every operand layout.
+BIG64_SHAPES = [(1, 128, 64, 16), (2, 256, 192, 40), (1, 128, 64, 256), (3, 384, 128, 8)]
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("shape", BIG64_SHAPES)
+@pytest.mark.parametrize("a_km,b_nk", [(0, 0), (1, 1), (1, 0), (0, 1)])
+@pytest.mark.parametrize("scale", [(1.0, 1.0), (2.0 ** -40, 2.0 ** -20)])
+def test_split_big64_exact(prec, shape, a_km, b_nk, scale):
+    nb, m, n, k = shape
+    rng = np.random.default_rng(m * 5 + n * 37 + k + nb * 19 + a_km + 2 * b_nk)
+    A, B = _exact_operands(rng, nb, m, n, k, *scale)
+    got = _run(A, B, nb, m, n, k, a_km, b_nk, prec, form=qcsim.GEMM_FORMS["split_big64"])
+    ref = np.matmul(A, B)
+    assert np.array_equal(got.astype(np.complex128), ref), np.abs(got - ref).max()
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("a_km,b_nk", [(0, 0), (1, 0)])
+def test_split_big64_error_bound(prec, a_km, b_nk):
+    nb, m, n, k = 2, 256, 192, 1000 - 1000 % 8
+    rng = np.random.default_rng(91 + a_km)
+    A = (rng.standard_normal((nb, m, k)) + 1j * rng.standard_normal((nb, m, k))) * 2.0 ** -30
+    B = (rng.standard_normal((nb, k, n)) + 1j * rng.standard_normal((nb, k, n))) * 2.0 ** 3
+    A = A.astype(np.complex64).astype(np.complex128)
+    B = B.astype(np.complex64).astype(np.complex128)
+    got = _run(A, B, nb, m, n, k, a_km, b_nk, prec, form=qcsim.GEMM_FORMS["split_big64"])
+    ref = np.matmul(A, B)
+    amax = max(np.abs(A.real).max(), np.abs(A.imag).max())
+    bmax = max(np.abs(B.real).max(), np.abs(B.imag).max())
+    assert np.abs(got - ref).max() <= C_BOUND * k * U[prec] * amax * bmax
 
 
 SHAPES = [(1, 32, 32, 16), (2, 64, 64, 128), (1, 128, 64, 1000), (8, 32, 32, 2), (1, 64, 128, 4096), (1, 256, 256, 1000),
