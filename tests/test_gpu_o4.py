@@ -100,7 +100,7 @@ def test_c4_sampled_slices_match_o4(c4_full, prec):
     _check_slices(got, [ref[s] for s in picks], TOL[prec], f"c4 {prec}")
 
 
-@pytest.mark.parametrize("prec", ["c64", "split_fp16"])
+@pytest.mark.parametrize("prec", ["c64", "split_fp16", "split_bf16"])
 def test_c4_tuned_slices_match_o4(c4_full, prec):
     # The same slices with the GEMM forms the tuner picks (the benchmark's
     # configuration: streaming and tile forms, recorded maxima only where a
