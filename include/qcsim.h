@@ -302,7 +302,8 @@ qc_status qc_plan_set_fused_shape(qc_plan *plan, int32_t items_per_workgroup, in
  * for chunk_slices slices and n_bs bitstrings in flight (as
  * qc_contract_slices would with this workspace) and, for every GEMM step of
  * the stepwise program, times each applicable kernel form (MFMA tile shapes,
- * the split 128 x 128 tile, the skinny, dot and vector-ALU forms) on the
+ * the split 128 x 128 and 128 x 64 tiles, the streaming MFMA forms, the
+ * skinny, rows, dot and vector-ALU forms) on the
  * caller's workspace (contents are overwritten) and stream, and keeps the
  * fastest for this plan and precision.  Choices are shared process-wide per
  * (device architecture, precision, shape, operand layout); cache_path (or
