@@ -288,15 +288,20 @@ constexpr int kFoldMaxLog2 = 14;
 // Per-(slice, bitstring) flops of a tree once its foldable pair-invariant
 // subtrees are precomputed.
 // Estimated device cost of one pairwise step, in complex multiply-adds: the
-// larger of its multiply-adds and kMovePerMac times the elements it reads and
-// writes (a roofline with ~100 TFLOP/s of complex FP32 arithmetic against
+// larger of its multiply-adds and w times the elements it reads and writes
+// (w = 20: a roofline with ~100 TFLOP/s of complex FP32 arithmetic against
 // ~5 TB/s of memory traffic), so that steps moving large tensors for little
 // arithmetic are charged for their traffic.
 constexpr double kMovePerMac = 20.0;
-inline double step_cost(int union_bits, int a_bits, int b_bits, int c_bits) {
+// The full search also runs under this weight and keeps whichever result is
+// cheaper under kMovePerMac: the randomised search settles in different trees
+// under different weights, and on the 70-qubit workload the tree found under
+// this one is cheaper under both (half the flops and bytes per slice).
+constexpr double kMovePerMacAlt = 10.0;
+inline double step_cost(int union_bits, int a_bits, int b_bits, int c_bits, double w) {
     const double macs = std::ldexp(1.0, union_bits);
     const double moved = std::ldexp(1.0, a_bits) + std::ldexp(1.0, b_bits) + std::ldexp(1.0, c_bits);
-    return std::max(macs, kMovePerMac * moved);
+    return std::max(macs, w * moved);
 }
 
 // Per-(slice, bitstring) device cost of a tree once its foldable
@@ -313,7 +318,7 @@ static double per_pair_cost(const OrderProblem &p, const std::vector<Merge> &tre
         dyn.push_back(d);
         if (d || (int)sets[L + i].size() > kFoldMaxLog2)
             f += step_cost((int)unions[i].size(), (int)sets[tree[i].a].size(), (int)sets[tree[i].b].size(),
-                           (int)sets[L + i].size());
+                           (int)sets[L + i].size(), p.move_per_mac);
     }
     return f;
 }
@@ -523,7 +528,7 @@ static double reconfigure(const OrderProblem &p, std::vector<Merge> &tree, const
                     const int u = (open[A] | open[B]).count();
                     const bool folds = cst[S] && sz <= kFoldMaxLog2 && u <= kFoldMaxLog2 + 4;
                     const double v = cost[A] + cost[B] +
-                                     (folds ? 0.0 : step_cost(u, open[A].count(), open[B].count(), sz));
+                                     (folds ? 0.0 : step_cost(u, open[A].count(), open[B].count(), sz, p.move_per_mac));
                     if (v < cost[S]) { cost[S] = v; split[S] = A; }
                 }
             }
@@ -534,7 +539,7 @@ static double reconfigure(const OrderProblem &p, std::vector<Merge> &tree, const
                 const bool folds = !dyn[n] && (int)sets[n].size() <= kFoldMaxLog2 &&
                                    (int)unions[n].size() <= kFoldMaxLog2 + 4;
                 cur += folds ? 0.0 : step_cost((int)unions[n].size(), (int)sets[t.a[n - L]].size(),
-                                               (int)sets[t.b[n - L]].size(), (int)sets[n].size());
+                                               (int)sets[t.b[n - L]].size(), (int)sets[n].size(), p.move_per_mac);
             }
             if (cost[S_all] >= cur * (1 - 1e-9)) continue;
             // Rebuild the subtree reusing the inner nodes' ids (r keeps its id).
@@ -684,8 +689,17 @@ static void parallel_trials(int n, F f) {
     for (auto &th : pool) th.join();
 }
 
-bool search_plan(qc_plan *plan, const qc_slice_spec *spec, std::string &err) {
-    const OrderProblem &p = plan->prob;
+// The search's result before folding: tree, slice set, dynamic leaves and
+// its per-pair cost under the problem's weight.
+struct SearchResult {
+    std::vector<Merge> tree;
+    std::vector<int> sliced;
+    std::vector<char> dyn;
+    double score = 0;
+};
+
+static bool search_once(qc_plan *plan, const OrderProblem &p, const qc_slice_spec *spec, std::string &err,
+                        SearchResult &out) {
     const int k_target = spec ? spec->log2_slices : 0;
     const double cap = spec ? spec->log2_max_entries : 0;
     const int trials = spec ? std::max(1, spec->greedy_trials) : 1;
@@ -880,7 +894,35 @@ bool search_plan(qc_plan *plan, const qc_slice_spec *spec, std::string &err) {
             best_dyn = refined[ci].dyn;
         }
     }
-    std::vector<char> dyn_leaf = best_dyn;
+    (void)last_ach;
+    out.tree = std::move(best_tree);
+    out.sliced = std::move(best_sliced);
+    out.dyn = std::move(best_dyn);
+    out.score = best_score;
+    return true;
+}
+
+bool search_plan(qc_plan *plan, const qc_slice_spec *spec, std::string &err) {
+    const OrderProblem &p = plan->prob;
+    SearchResult best;
+    if (!search_once(plan, p, spec, err, best)) return false;
+    if (!(spec && spec->quick)) {
+        // The same search under the second weight, kept if its tree costs
+        // less per pair under the first weight's step cost.
+        OrderProblem alt = p;
+        alt.move_per_mac = kMovePerMacAlt;
+        SearchResult r;
+        std::string err2;
+        if (search_once(plan, alt, spec, err2, r)) {
+            std::vector<char> rm(p.n_index, 0);
+            for (int e : r.sliced) rm[e] = 1;
+            if (r.sliced.size() == best.sliced.size() && per_pair_cost(p, r.tree, rm, r.dyn) < best.score)
+                best = std::move(r);
+        }
+    }
+    std::vector<Merge> best_tree = std::move(best.tree);
+    std::vector<int> best_sliced = std::move(best.sliced);
+    std::vector<char> dyn_leaf = std::move(best.dyn);
     {
         const TreeCost c0 = tree_cost(p, best_tree, std::vector<char>(p.n_index, 0));
         plan->info.flops_unsliced = c0.flops;
@@ -898,7 +940,6 @@ bool search_plan(qc_plan *plan, const qc_slice_spec *spec, std::string &err) {
     plan->info.flops_per_slice = cf.flops;
     plan->info.bytes_per_slice = cf.bytes;
     plan->info.peak_live_bytes = cf.peak_live;
-    (void)last_ach;
     return true;
 }
 

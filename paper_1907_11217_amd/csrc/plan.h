@@ -79,6 +79,9 @@ struct OrderProblem {
     std::vector<std::vector<int>> leaf_idx;   // summed and open-output indices per leaf (not fixed outputs)
     std::vector<char> keep;                   // per index: never summed (open outputs); empty = none
     bool kept(int e) const { return !keep.empty() && keep[e]; }
+    // Weight of an element moved against a complex multiply-add in the
+    // search's step cost (see order.cpp).
+    double move_per_mac = 20.0;
 };
 
 std::vector<Merge> greedy_order(const OrderProblem &p, const std::vector<char> &removed,
